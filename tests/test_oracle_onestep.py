@@ -1,0 +1,243 @@
+"""One-sweep predictions of the oracle chain from brute-force energies.
+
+For every colour pass the test recomputes, independently of the oracle:
+  * the energy change of each proposal from two full-lattice energies
+    (Eq. (1), Eq. (2), Eq. (3)), not from a local formula;
+  * the Metropolis rule of Algorithm 1 in its plain form: accept when
+    dE <= 0, else when the uniform W / 2^32 < exp(-beta dE);
+  * all sites of the colour at once, from the pass-start state (the
+    checkerboard argument), whereas the oracle updates them in place.
+The uniform W and the proposals follow the documented counter layout of the
+Philox streams (Philox itself is pinned in test_oracle_philox.py).
+A dropped term, a wrong sign, a transposed axis or a wrong colour order in
+the oracle changes at least one site here.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from exact import ising_energy, potts_energy
+
+MASK16 = 0xFFFF
+
+
+def _key(seed):
+    return [seed & 0xFFFFFFFF, seed >> 32]
+
+
+def _u(orc, a, p, rid, tag, seed):
+    return [int(v) for v in orc.philox4x32_10([a, p, rid, tag], _key(seed))]
+
+
+def _metropolis(W, dE, beta):
+    return dE <= 0 or W < math.ldexp(math.exp(-beta * dE), 32)
+
+
+def predict_ising(orc, s, Jx, Jy, h, beta, seed, rid, t):
+    s = s.astype(np.int8).copy()
+    Ly, Lx = s.shape
+    for c in (0, 1):
+        p = 2 * t + c
+        E0, _ = ising_energy(s, Jx, Jy, h)
+        new = s.copy()
+        for y in range(Ly):
+            for x in range(Lx):
+                if (x + y) % 2 != c:
+                    continue
+                k = y * (Lx // 2) + x // 2
+                w = _u(orc, k >> 3, p, rid, 0, seed)
+                hw = k & 7
+                ra = (w[hw >> 1] >> (16 * (hw & 1))) & MASK16
+                f = _u(orc, k, p, rid, 1, seed)
+                W = (ra << 16) | (f[0] & MASK16)
+                trial = s.copy()
+                trial[y, x] = -trial[y, x]
+                E1, _ = ising_energy(trial, Jx, Jy, h)
+                if _metropolis(W, E1 - E0, beta):
+                    new[y, x] = -s[y, x]
+        s = new
+    return s
+
+
+@pytest.mark.parametrize("shape,Jx,Jy,h,beta,seed,rid,t", [
+    ((6, 8), 1.0, 1.0, 0.0, 0.44, 1, 0, 0),
+    ((8, 6), 0.7, 1.3, 0.2, 0.6, 99, 5, 17),
+    ((4, 10), 1.1, 0.4, -0.3, 0.9, 2 ** 40 + 3, 1023, 123456),
+    ((10, 20), 0.5, 0.5, 0.05, 0.3, 7, 3, 2),
+])
+def test_ising_sweep_matches_bruteforce(orc, shape, Jx, Jy, h, beta, seed, rid, t):
+    rng = np.random.default_rng(seed % 1000)
+    s0 = (2 * rng.integers(0, 2, size=shape) - 1).astype(np.int8)
+    Jx, Jy, h = (float(np.float32(v)) for v in (Jx, Jy, h))
+    want = predict_ising(orc, s0, Jx, Jy, h, beta, seed, rid, t)
+    got, _ = orc.ising_run(s0, Jx, Jy, h, beta, seed, rid, t, 1)
+    assert np.array_equal(got, want)
+
+
+def test_ising_flip_frequencies_follow_metropolis(orc):
+    """From one fixed state, over many chain seeds, each site of colour 0
+    flips in its first pass with probability min(1, exp(-beta dE))."""
+    rng = np.random.default_rng(3)
+    s0 = (2 * rng.integers(0, 2, size=(4, 8)) - 1).astype(np.int8)
+    Jx, Jy, h, beta = 1.0, 0.5, 0.1, 0.5
+    E0, _ = ising_energy(s0, Jx, Jy, h)
+    n = 3000
+    flips = np.zeros(s0.shape)
+    for seed in range(n):
+        # half a sweep: run one sweep and look at colour-0 sites only, which
+        # colour 1 never changes
+        got, _ = orc.ising_run(s0, Jx, Jy, h, beta, seed + 1, 0, 0, 1)
+        flips += (got != s0)
+    for y in range(4):
+        for x in range(8):
+            if (x + y) % 2:
+                continue
+            trial = s0.copy()
+            trial[y, x] *= -1
+            dE = ising_energy(trial, Jx, Jy, h)[0] - E0
+            p = min(1.0, math.exp(-beta * dE))
+            sd = math.sqrt(max(p * (1 - p), 1e-12) / n)
+            assert abs(flips[y, x] / n - p) < 5 * sd + 1e-9
+
+
+def _potts_offset(rp, fb, m):
+    prod = rp * m
+    if (prod & MASK16) < (65536 % m):
+        return (fb * m) >> 32
+    return prod >> 16
+
+
+def predict_potts(orc, s, q, J, h, beta, seed, rid, t):
+    s = s.astype(np.uint8).copy()
+    Ly, Lx = s.shape
+    for c in (0, 1):
+        p = 2 * t + c
+        E0, _ = potts_energy(s, J, h)
+        new = s.copy()
+        for y in range(Ly):
+            for x in range(Lx):
+                if (x + y) % 2 != c:
+                    continue
+                k = y * (Lx // 2) + x // 2
+                word = _u(orc, k >> 2, p, rid, 0, seed)[k & 3]
+                f = _u(orc, k, p, rid, 1, seed)
+                W = ((word >> 16) << 16) | (f[0] & MASK16)
+                off = _potts_offset(word & MASK16, f[1], q - 1)
+                s2 = (int(s[y, x]) + 1 + off) % q
+                assert s2 != s[y, x]
+                trial = s.copy()
+                trial[y, x] = s2
+                E1, _ = potts_energy(trial, J, h)
+                if _metropolis(W, E1 - E0, beta):
+                    new[y, x] = s2
+        s = new
+    return s
+
+
+@pytest.mark.parametrize("shape,q,J,h,beta,seed,rid,t", [
+    ((6, 8), 3, 1.0, 0.0, 1.0, 1, 0, 0),
+    ((8, 6), 4, 1.0, 0.15, 1.2, 5, 9, 31),
+    ((4, 8), 8, 0.75, -0.1, 1.5, 123, 77, 4),
+    ((6, 6), 2, 1.0, 0.0, 0.8, 3, 1, 0),
+])
+def test_potts_sweep_matches_bruteforce(orc, shape, q, J, h, beta, seed, rid, t):
+    rng = np.random.default_rng(seed)
+    s0 = rng.integers(0, q, size=shape).astype(np.uint8)
+    J, h = float(np.float32(J)), float(np.float32(h))
+    want = predict_potts(orc, s0, q, J, h, beta, seed, rid, t)
+    got, _ = orc.potts_run(s0, q, J, h, beta, seed, rid, t, 1)
+    assert np.array_equal(got, want)
+
+
+def test_potts_proposal_offsets_exactly_uniform():
+    """Lemire's multiply-shift with rejection: over all 2^16 prefixes the
+    accepted ones give every offset in [0, m) equally often."""
+    for m in range(1, 12):
+        counts = np.zeros(m, np.int64)
+        rej = 0
+        for rp in range(65536):
+            prod = rp * m
+            if (prod & MASK16) < (65536 % m):
+                rej += 1
+                continue
+            counts[prod >> 16] += 1
+        assert rej == 65536 % m
+        assert np.all(counts == counts[0])
+
+
+# ------------------------------------------------------------------ CPM
+MOORE = [(-1, -1), (-1, 0), (-1, 1), (0, -1), (0, 1), (1, -1), (1, 0), (1, 1)]
+
+
+def cpm_energy(ids, J, ctype, A, lam, area):
+    """Eq. (3): adhesion over unordered Moore pairs between different ids,
+    plus lambda (a - A)^2 over cells (not the medium), with given areas."""
+    Ly, Lx = ids.shape
+    H = 0.0
+    for dy, dx in [(0, 1), (1, 0), (1, 1), (1, -1)]:
+        nb = np.roll(np.roll(ids, -dy, axis=0), -dx, axis=1)
+        diff = ids != nb
+        H += float(J[ctype[ids[diff]], ctype[nb[diff]]].astype(np.float64).sum())
+    cells = np.arange(1, len(A))
+    H += lam * float(((area[cells].astype(np.float64) - A[cells]) ** 2).sum())
+    return H
+
+
+def predict_cpm(orc, ids, J, ctype, A, lam, T, seed, rid, t):
+    ids = ids.copy()
+    Ly, Lx = ids.shape
+    for c in range(4):
+        p = 4 * t + c
+        snap = np.bincount(ids.reshape(-1), minlength=len(A))
+        E0 = cpm_energy(ids, J, ctype, A, lam, snap)
+        new = ids.copy()
+        for y in range(Ly):
+            for x in range(Lx):
+                if 2 * (y & 1) + (x & 1) != c:
+                    continue
+                k = (y >> 1) * (Lx // 2) + (x >> 1)
+                word = _u(orc, k >> 2, p, rid, 0, seed)[k & 3]
+                dy, dx = MOORE[word & 7]
+                s, tg = ids[y, x], ids[(y + dy) % Ly, (x + dx) % Lx]
+                if s == tg:
+                    continue
+                f = _u(orc, k, p, rid, 1, seed)
+                W = ((word >> 16) << 16) | (f[0] & MASK16)
+                trial = ids.copy()
+                trial[y, x] = tg
+                a1 = snap.copy()
+                a1[tg] += 1
+                a1[s] -= 1
+                dH = cpm_energy(trial, J, ctype, A, lam, a1) - E0
+                if dH <= 0 or W < math.ldexp(math.exp(-dH / T), 32):
+                    new[y, x] = tg
+        ids = new
+    return ids
+
+
+def _cpm_case(seed, L=(8, 10), n_cells=5):
+    rng = np.random.default_rng(seed)
+    Ly, Lx = L
+    ids = rng.integers(0, n_cells + 1, size=(Ly, Lx)).astype(np.int32)
+    ctype = np.concatenate([[0], rng.integers(1, 3, size=n_cells)]).astype(np.int8)
+    A = np.concatenate([[0], rng.integers(5, 15, size=n_cells)]).astype(np.int32)
+    return ids, ctype, A
+
+
+@pytest.mark.parametrize("seed,lam,T,Jset", [
+    (1, 1.0, 10.0, "sorting"),
+    (2, 0.5, 3.0, "halves"),
+    (3, 0.0, 1.0, "sorting"),
+    (4, 2.0, 25.0, "halves"),
+])
+def test_cpm_mcs_matches_bruteforce(orc, seed, lam, T, Jset):
+    ids, ctype, A = _cpm_case(seed)
+    if Jset == "sorting":
+        J = np.array([[0, 16, 16], [16, 2, 11], [16, 11, 16]], np.float32)
+    else:
+        J = np.array([[0, 3.5, 4.5], [3.5, 1.5, 2.0], [4.5, 2.0, 0.5]], np.float32)
+    want = predict_cpm(orc, ids, J, ctype, A, lam, T, seed, 2, 5)
+    got, area, _ = orc.cpm_run(ids, J, ctype, A, lam, T, seed, 2, 5, 1)
+    assert np.array_equal(got, want)
+    assert np.array_equal(area, np.bincount(got.reshape(-1), minlength=len(A)))
