@@ -1,0 +1,257 @@
+/*
+ * spinmc.h -- C ABI of libspinmc, the MI355X (gfx950) checkerboard
+ * Metropolis-Hastings sampler for the Ising, q-state Potts and Cellular
+ * Potts models of "A differentiable programming framework for spin models"
+ * (Farias, Schultz, Mombach, Maziero).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every function returns a spinmc_status (0 = OK, < 0 = error).  On error
+ *   nothing is enqueued and no state changes; spinmc_last_error() returns a
+ *   thread-local message.  After a device fault a context is poisoned: every
+ *   call but spinmc_destroy returns SPINMC_E_DEVICE.
+ * - "dev" pointers are device memory owned by the caller (for example torch
+ *   tensors); "host" pointers are host memory.  Device work is enqueued on the
+ *   HIP stream given to spinmc_create (NULL = the null stream) and runs
+ *   asynchronously unless stated otherwise.
+ * - Lattices are periodic, Ly rows by Lx columns, Lx and Ly even.  Site
+ *   (y, x) has colour (x + y) & 1 for Ising/Potts (Related Work, checkerboard
+ *   decomposition, Fig. 1) and 2 (y & 1) + (x & 1) for the Cellular Potts
+ *   model, whose Moore neighbourhood needs four colours.
+ * - A sweep (Ising/Potts) is the colour-0 pass then the colour-1 pass; a
+ *   Cellular Potts Monte Carlo step is the four colour passes in order.  The
+ *   global sweep counter t (persisted in the context) numbers the passes
+ *   p = 2t + c (CPM: 4t + c), which key the Philox4x32-10 streams together
+ *   with the seed and the replica id.  Results depend only on (seed, rid,
+ *   t, state), never on batching, tiling or the schedule.
+ * - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef SPINMC_H
+#define SPINMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spinmc_ctx spinmc_ctx;
+
+enum spinmc_model { SPINMC_ISING = 0, SPINMC_POTTS = 1, SPINMC_CPM = 2 };
+
+enum spinmc_status {
+    SPINMC_OK = 0,
+    SPINMC_E_INVALID = -1,          /* bad argument (shape, range, NULL, NaN)          */
+    SPINMC_E_UNSUPPORTED = -2,      /* valid but not implemented by this build          */
+    SPINMC_E_NOMEM = -3,            /* device allocation failed; nothing leaked         */
+    SPINMC_E_DEVICE = -4,           /* no usable GPU, or a device fault (ctx poisoned)  */
+    SPINMC_E_NOT_REPRESENTABLE = -5,/* CPM energies not exact in the fixed-point scale */
+    SPINMC_E_STATE = -6             /* call not valid in the current state              */
+};
+
+/* Integer statistics recorded per replica and per recorded sweep
+ * (spinmc_stats_width() int32 entries, 8 or 16):
+ *   Ising  [M, Bx, By, 0...]   M = sum s, Bx = sum s(y,x) s(y,x+1),
+ *                              By = sum s(y,x) s(y+1,x)        (Eq. (1))
+ *   Potts  [Nx, Ny, S, nmax, 0...]  equal horizontal / vertical bonds, sum
+ *                              of labels, population of the largest state
+ *                              (Eq. (2))
+ *   CPM    [b0..b9, Hlo, Hhi, 0...] von Neumann bonds between different ids
+ *                              by unordered type pair (a <= b, index
+ *                              a*n_types - a(a-1)/2 + (b - a)), and the
+ *                              energy of Eq. (3) times the fixed-point scale
+ *                              S as an int64 split in two int32 words.      */
+
+/* Hamiltonian parameters of one replica (Eq. (1), Eq. (2), Eq. (3)).
+ * Signs: Ising H = -Jx sum_h s s' - Jy sum_v s s' - h sum s with s = +-1;
+ * Potts H = -Jx sum delta(s, s') - h sum s with labels 0..q-1 (Jy must equal
+ * Jx); both count every nearest-neighbour bond once, so J > 0 is
+ * ferromagnetic (the paper writes the same model with J = -1).
+ * CPM H = sum over unordered Moore pairs J[type][type'] [id != id']
+ *         + lambda sum over cells (a - A)^2 (no area term for id 0, the
+ *         medium).  The descriptor is deep-copied by spinmc_create.          */
+typedef struct spinmc_replica_desc {
+    int32_t model;               /* enum spinmc_model                              */
+    int32_t Lx, Ly;              /* even, >= 2                                      */
+    int32_t q;                   /* Potts: 2..255; CPM: number of cells n (ids 0..n); Ising: ignored */
+    float Jx, Jy, h;             /* couplings and field (Ising, Potts)              */
+    double beta;                 /* inverse temperature (Ising, Potts), >= 0         */
+    uint32_t rid;                /* replica id: selects the random streams          */
+    /* Cellular Potts only */
+    int32_t n_types;             /* 1..4, type 0 = medium                           */
+    const float *adhesion;       /* host [n_types * n_types], symmetric             */
+    const int8_t *cell_type;     /* host [q + 1], cell_type[0] = 0                  */
+    const int32_t *target_area;  /* host [q + 1] (entry 0 unused)                   */
+    float lambda_area;           /* >= 0                                            */
+    double temperature;          /* > 0                                             */
+} spinmc_replica_desc;
+
+/* Create a batch of n replicas (Methods, batched tensors: one context runs
+ * many lattices or temperatures at once; Ising and Potts may be mixed; a CPM
+ * context holds only CPM replicas).  Builds the FP64 Metropolis thresholds
+ * T = ceil(2^32 exp(-beta dE)) of Algorithm 1 on the host, allocates the
+ * lattices, and if init = 1 draws the initial state from the Philox init
+ * stream (Ising: s = +1 iff the word < 2^31; Potts: floor(word q / 2^32)).
+ * init = 0 leaves zeros (Ising all -1, Potts all 0, CPM all medium); CPM
+ * states are set with spinmc_set_state.  hip_stream: a hipStream_t or NULL.
+ * Errors: SPINMC_E_INVALID (shape, ranges, n < 1, duplicate rid),
+ * SPINMC_E_NOT_REPRESENTABLE (CPM J or lambda not exact at S <= 256 below
+ * 2^20), SPINMC_E_NOMEM, SPINMC_E_DEVICE (no GPU).  *out receives the
+ * context, owned by the caller until spinmc_destroy.                        */
+int spinmc_create(const spinmc_replica_desc *d, int32_t n, uint64_t seed, int32_t init,
+                  void *hip_stream, spinmc_ctx **out);
+
+/* Free every device buffer of the context.  Waits for its stream.  NULL is a
+ * no-op.                                                                     */
+int spinmc_destroy(spinmc_ctx *ctx);
+
+/* Copy one replica's lattice from / to host memory, natural row-major:
+ * Ising int8 in {-1, +1}, Potts uint8 in [0, q), CPM int32 in [0, n].
+ * bytes must equal Lx*Ly*elem_size.  Synchronous (waits for the stream).
+ * set_state validates every value first (SPINMC_E_INVALID leaves the state
+ * unchanged); for CPM it also recomputes the cell areas.                    */
+int spinmc_set_state(spinmc_ctx *ctx, int32_t replica, const void *host_buf, size_t bytes);
+int spinmc_get_state(spinmc_ctx *ctx, int32_t replica, void *host_buf, size_t bytes);
+
+/* Run n_sweeps sweeps (CPM: Monte Carlo steps) of every replica
+ * (Algorithm 1 with the checkerboard colouring).  If record_every > 0 the
+ * integer statistics after sweeps k*record_every (k = 1, 2, ...) are written
+ * to dev_stats as int32 [n_sweeps / record_every][n_replicas][width], row
+ * k-1.  dev_stats may be NULL only when record_every == 0.  Advances the
+ * sweep counter by n_sweeps.  Asynchronous.  The work runs in the schedule
+ * chosen by spinmc_set_schedule / spinmc_autotune; every schedule produces
+ * the same bits.                                                            */
+int spinmc_sweep(spinmc_ctx *ctx, int32_t n_sweeps, int32_t record_every, void *dev_stats);
+
+/* Integer statistics of the current state into dev_stats int32 [n][width]
+ * and, if dev_obs is not NULL, FP64 observables into dev_obs [n][4]:
+ *   Ising (e, |m|, m^2, m) with e = -(Jx Bx + Jy By + h M)/N, m = M/N;
+ *   Potts (e, m_P, S/N, 0) with e = -(Jx (Nx+Ny) + h S)/N and
+ *         m_P = (q nmax / N - 1)/(q - 1);
+ *   CPM   (H, 0, 0, 0) with H = (H*S)/S.   Asynchronous.                    */
+int spinmc_measure(spinmc_ctx *ctx, void *dev_stats, void *dev_obs);
+
+/* Fluctuation (covariance) estimator of the gradients of equilibrium Ising
+ * observables; it replaces the logistic relaxation of Algorithm 2 (Methods)
+ * with the exact identity d<O>/dtheta = <dO/dtheta> - beta Cov(O, dH/dtheta).
+ * dev_stats: int32 [n_rec][n][width] as written by spinmc_sweep; samples
+ * k >= burn_in are used.  Observables O = (e, |m|); parameters
+ * theta = (Jx, Jy, h), dH/dJx = -Bx, dH/dJy = -By, dH/dh = -M.
+ * Outputs (device FP64, any may be NULL): dev_means [n][4] =
+ * (<e>, <|m|>, <m^2>, chi) with chi = beta N (<m^2> - <|m|>^2);
+ * dev_grads [n][2][3] = d<O_o>/dtheta_j; dev_dtheta [n][3] =
+ * sum_o dev_grad_out[n][o] * d<O_o>/dtheta (dev_grad_out FP64 [n][2],
+ * required when dev_dtheta is set).  Moments are exact int64 sums combined
+ * in FP64.  Ising-only contexts.  Asynchronous.                             */
+int spinmc_grad(spinmc_ctx *ctx, const void *dev_stats, int32_t n_rec, int32_t burn_in,
+                const void *dev_grad_out, void *dev_means, void *dev_grads, void *dev_dtheta);
+
+/* Global sweep counter t (host mirror of the device counter).               */
+int spinmc_sweep_counter(const spinmc_ctx *ctx, uint64_t *t);
+
+/* int32 entries per replica in a statistics row (8 or 16).                 */
+int spinmc_stats_width(const spinmc_ctx *ctx);
+
+/* Number of replicas.                                                      */
+int spinmc_num_replicas(const spinmc_ctx *ctx);
+
+/* Copy replica r's Metropolis thresholds to host memory as uint64 values
+ * T in [0, 2^32] (accept iff the uniform word W < T): Ising 18 entries
+ * (index 9[s>0] + 3(Sx/2+1) + (Sy/2+1)), Potts 9(2q-1) (index
+ * (dn+4)(2q-1) + (s'-s+q-1)), CPM K1 entries for k = 1..K1 (k >= K1 gives
+ * T = 1 up to the first k with T = 0, reported in *aux).  *n_out receives
+ * the entry count; cap is the capacity of host_T.                          */
+int spinmc_thresholds(const spinmc_ctx *ctx, int32_t replica, uint64_t *host_T, int32_t cap,
+                      int32_t *n_out, int64_t *aux);
+
+/* Execution schedule of spinmc_sweep (the batched scheduler).
+ * mode 1 resident: one persistent launch for all sweeps of the call; each
+ *   workgroup owns one replica whose lattice lives in LDS for the whole call
+ *   (lattices up to 128 KiB).
+ * mode 2 stream: one launch per colour pass over (replica, row-tile) units of
+ *   every replica whose Lx/2 is a multiple of 16 (others go resident).
+ * mode 3 hybrid: resident where the lattice fits the LDS budget, streamed
+ *   otherwise; both run concurrently.
+ * mode 0 auto: resident if every lattice fits, else hybrid.
+ * Calls without recording replay cached hipGraphs of 50-sweep chunks
+ * (streamed passes and the concurrent resident branch captured together).
+ * tile_rows: rows of a plane per streamed unit (even; 0 = about 16 KiB);
+ * wg_threads: 256 or 512 (resident also 1024; 0 = default).  Invalid values
+ * return SPINMC_E_INVALID.  CPM contexts use tile_rows and wg_threads only. */
+typedef struct spinmc_schedule {
+    int32_t mode;
+    int32_t tile_rows;
+    int32_t wg_threads;
+    int32_t reserved;
+} spinmc_schedule;
+
+int spinmc_set_schedule(spinmc_ctx *ctx, const spinmc_schedule *s);
+int spinmc_get_schedule(const spinmc_ctx *ctx, spinmc_schedule *s);
+
+/* Sites per sweep that the current schedule streams through colour-pass
+ * launches and that it keeps resident in LDS (host out-parameters).        */
+int spinmc_schedule_sites(const spinmc_ctx *ctx, int64_t *streamed, int64_t *resident);
+
+/* Time candidate schedules for trial_sweeps sweeps each on a scratch copy of
+ * the state (the context's state and counter are restored afterwards), pick
+ * the fastest, store it, and return it in *chosen (may be NULL) with the
+ * measured attempts per ns of every candidate in host_rates (capacity cap,
+ * may be NULL; *n_tried receives the count).  Synchronous.                  */
+int spinmc_autotune(spinmc_ctx *ctx, int32_t trial_sweeps, spinmc_schedule *chosen,
+                    double *host_rates, int32_t cap, int32_t *n_tried);
+
+const char *spinmc_last_error(void);
+
+/* Kernel timing with HIP events, for benchmarks.  spinmc_profile(ctx, 1)
+ * clears the record and brackets every following sweep-kernel launch with a
+ * pair of events on the context's stream; spinmc_profile(ctx, 0) stops.
+ * spinmc_profile_read waits for the recorded events and returns, for one
+ * kernel class (0 streamed colour pass, 1 resident, 2 persistent, 3 CPM
+ * colour pass), the summed elapsed milliseconds and the launch count.       */
+enum spinmc_kernel_kind {
+    SPINMC_K_STREAM_PASS = 0, SPINMC_K_RESIDENT = 1, SPINMC_K_PERSISTENT = 2, SPINMC_K_CPM_PASS = 3
+};
+int spinmc_profile(spinmc_ctx *ctx, int32_t enable);
+int spinmc_profile_read(spinmc_ctx *ctx, int32_t kind, double *ms_total, int64_t *launches);
+
+/* ------------------------------------------------------------------------
+ * Surrogate MLP 4-128-128-3 (SiLU), BF16 weights and activations with FP32
+ * accumulation on MFMA.  Maps normalised (beta, Jx, Jy, h) to normalised
+ * (<e>, <|m|>, chi).  Parameters live in one caller-owned FP32 device buffer
+ * of spinmc_mlp_num_params() floats (layout: W1[128][4], b1[128],
+ * W2[128][128], b2[128], W3[3][128], b3[3]); the BF16 copies used by the
+ * matrix cores are rounded from it (round to nearest even) by every call.
+ * Adam follows the paper's optimiser settings by default (Results,
+ * optimisation: learning rate 1e-3, betas 0.9 / 0.999).                    */
+int spinmc_mlp_num_params(void);
+
+/* y[B][3] = MLP(x[B][4]) (device FP32).  dev_act may be NULL; otherwise it
+ * receives the pre-activations the backward pass needs, FP32
+ * [B][256] = spinmc_mlp_act_floats(B) floats.  B >= 1.                     */
+int spinmc_mlp_act_floats(int32_t B);
+int spinmc_mlp_forward(const void *dev_params, const void *dev_x, int32_t B, void *dev_y,
+                       void *dev_act, void *hip_stream);
+
+/* Gradients of L = (1/B) sum_b sum_j w_j (y_bj - t_bj)^2 with respect to the
+ * parameters (dev_grad, FP32, same layout as the parameters) and optionally
+ * the inputs (dev_dx [B][4], may be NULL).  dev_act from the forward call of
+ * the same x.  dev_loss (FP32 scalar, may be NULL) receives L.  Per-output
+ * weights dev_w [3] (FP32).  dev_workspace: FP32
+ * [spinmc_mlp_workspace_floats(B)] of per-workgroup partial sums, reduced in
+ * a fixed order (deterministic).                                            */
+int spinmc_mlp_workspace_floats(int32_t B);
+int spinmc_mlp_backward(const void *dev_params, const void *dev_x, const void *dev_act,
+                        const void *dev_t, const void *dev_w, int32_t B, void *dev_grad,
+                        void *dev_dx, void *dev_loss, void *dev_workspace, void *hip_stream);
+
+/* One Adam step on the FP32 parameters: m, v (FP32, same size) are the
+ * moment buffers, step >= 1 the 1-based step number.                        */
+int spinmc_mlp_adam(void *dev_params, const void *dev_grad, void *dev_m, void *dev_v,
+                    int32_t step, float lr, float beta1, float beta2, float eps,
+                    void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPINMC_H */

@@ -1,0 +1,223 @@
+// Cellular Potts model (Eq. (3)) copy-attempt kernels for gfx950.
+//
+// Cell ids are int32 in natural row-major layout.  The Moore neighbourhood
+// has range one in both axes, so a 2x2 sublattice colouring
+// c = 2 (y & 1) + (x & 1) makes the sites of one colour independent (the
+// colouring criterion of the Related-Work section: no site interacts with
+// another site of its own colour); a Monte Carlo step is the four colour
+// passes in order.  Each attempt picks a target site and one of its eight
+// neighbours (Methods, Cellular Potts model), and copies the neighbour's id
+// through the Algorithm-1 test.  Energies are integers in a fixed-point
+// scale S; the area term reads a snapshot of the cell areas taken at the
+// start of the pass (so the outcome does not depend on the order in which
+// the sites of one pass are visited), and accepted copies update the live
+// areas with integer atomics, which commute.
+#include "spinmc_internal.hpp"
+
+namespace spinmc {
+
+namespace {
+__device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_cpm_pass(CpmArgs a, int c, int sweep_off) {
+    extern __shared__ uint32_t lthr[];  // [2 * tab_n]: hi16 | lo16 of T(k), k = 1..K1-1
+    __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
+    const TileDev T = a.tiles[blockIdx.x];
+    const RepDev R = a.reps[T.rep];
+    for (int i = threadIdx.x; i < 2 * R.tab_n; i += blockDim.x) lthr[i] = a.tab[R.tab_off + i];
+    for (int i = threadIdx.x; i < R.n_types * R.n_types; i += blockDim.x)
+        ljs[i] = a.js[R.js_off + i];
+    __syncthreads();
+    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
+    const uint32_t p = (uint32_t)(4 * t + (uint64_t)c);
+    const int cy = c >> 1, cx = c & 1;
+    const int Lx = R.Lx, Ly = R.Ly, Wc = Lx >> 1, nt = R.n_types;
+    int32_t* ids = a.lat + R.lat_off;
+    const int8_t* ty = a.ctype + R.cell_off;
+    const int32_t* A = a.target + R.cell_off;
+    const int32_t* snap = a.snap + R.cell_off;
+    int32_t* area = a.area + R.cell_off;
+    const int total = (T.rows >> 1) * Wc;
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        const int r = it / Wc;
+        const int i = it - r * Wc;
+        const int y = T.y0 + 2 * r + cy;
+        const int x = 2 * i + cx;
+        const uint32_t k = (uint32_t)((y >> 1) * Wc + i);
+        uint32_t w[4];
+        philox4x32_10(k >> 2, p, R.rid, kTagMain, a.key0, a.key1, w);
+        const uint32_t word = w[k & 3u];
+        const int jn = (int)(word & 7u);
+        // Moore order (dy, dx): (-1,-1) (-1,0) (-1,1) (0,-1) (0,1) (1,-1) (1,0) (1,1)
+        const int ndy = jn < 3 ? -1 : (jn < 5 ? 0 : 1);
+        const int ndx = (jn == 0 || jn == 3 || jn == 5) ? -1 : ((jn == 1 || jn == 6) ? 0 : 1);
+        const int ym = wrapc(y - 1, Ly), yp = wrapc(y + 1, Ly);
+        const int xm = wrapc(x - 1, Lx), xp = wrapc(x + 1, Lx);
+        const int s = ids[(size_t)y * Lx + x];
+        const int tg = ids[(size_t)wrapc(y + ndy, Ly) * Lx + wrapc(x + ndx, Lx)];
+        if (tg == s) continue;
+        const int nb[8] = {ids[(size_t)ym * Lx + xm], ids[(size_t)ym * Lx + x],
+                           ids[(size_t)ym * Lx + xp], ids[(size_t)y * Lx + xm],
+                           ids[(size_t)y * Lx + xp], ids[(size_t)yp * Lx + xm],
+                           ids[(size_t)yp * Lx + x], ids[(size_t)yp * Lx + xp]};
+        const int ts = ty[s] * nt, tt = ty[tg] * nt;
+        int kadh = 0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int m = nb[j];
+            const int tm = ty[m];
+            kadh += (tg != m) ? ljs[tt + tm] : 0;
+            kadh -= (s != m) ? ljs[ts + tm] : 0;
+        }
+        int64_t karea = 0;
+        if (tg != 0) karea += 2 * ((int64_t)snap[tg] - (int64_t)A[tg]) + 1;
+        if (s != 0) karea += -2 * ((int64_t)snap[s] - (int64_t)A[s]) + 1;
+        const int64_t kk = (int64_t)kadh + R.LS * karea;
+        bool acc;
+        if (kk <= 0) {
+            acc = true;
+        } else if (kk >= R.K0) {
+            acc = false;
+        } else {
+            uint32_t hi = 0u, lo = 1u;  // T = 1 for K1 <= k < K0
+            if (kk < (int64_t)R.K1) {
+                hi = lthr[kk - 1];
+                lo = lthr[R.tab_n + kk - 1];
+            }
+            const uint32_t rr = word >> 16;
+            acc = rr < hi;
+            if (rr == hi && lo != 0u) {
+                uint32_t f[4];
+                philox4x32_10(k, p, R.rid, kTagFallback, a.key0, a.key1, f);
+                acc = (f[0] & 0xFFFFu) < lo;
+            }
+        }
+        if (acc) {
+            ids[(size_t)y * Lx + x] = tg;
+            atomicAdd(&area[tg], 1);
+            atomicAdd(&area[s], -1);
+        }
+    }
+}
+
+__global__ void k_cpm_copy(const int32_t* src, int32_t* dst, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// Areas from the lattice (after set_state): per tile, atomics into area
+// (which the caller cleared).
+__global__ void k_cpm_area_count(CpmArgs a) {
+    const TileDev T = a.tiles[blockIdx.x];
+    const RepDev R = a.reps[T.rep];
+    const int32_t* ids = a.lat + R.lat_off;
+    int32_t* area = a.area + R.cell_off;
+    const int n = T.rows * R.Lx;
+    const size_t base = (size_t)T.y0 * R.Lx;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&area[ids[base + i]], 1);
+}
+
+// Statistics: boundary bonds by type pair (von Neumann, right and down) and
+// the adhesion energy over Moore pairs counted once (right, down,
+// down-right, down-left), in fixed point; the area term is added by
+// k_cpm_area_energy.  stats row: [10 pair counts, H lo, H hi, ...].
+__global__ void __launch_bounds__(256) k_cpm_stats(CpmArgs a, int rec_row) {
+    __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
+    __shared__ int lpair[10];
+    __shared__ unsigned long long lH;
+    const TileDev T = a.tiles[blockIdx.x];
+    const RepDev R = a.reps[T.rep];
+    const int nt = R.n_types;
+    for (int i = threadIdx.x; i < nt * nt; i += blockDim.x) ljs[i] = a.js[R.js_off + i];
+    if (threadIdx.x < 10) lpair[threadIdx.x] = 0;
+    if (threadIdx.x == 0) lH = 0ull;
+    __syncthreads();
+    const int Lx = R.Lx, Ly = R.Ly;
+    const int32_t* ids = a.lat + R.lat_off;
+    const int8_t* ty = a.ctype + R.cell_off;
+    long long H = 0;
+    const int n = T.rows * Lx;
+    for (int it = threadIdx.x; it < n; it += blockDim.x) {
+        const int y = T.y0 + it / Lx, x = it % Lx;
+        const int yp = wrapc(y + 1, Ly), xp = wrapc(x + 1, Lx), xm = wrapc(x - 1, Lx);
+        const int s = ids[(size_t)y * Lx + x];
+        const int ts = ty[s];
+        const int r = ids[(size_t)y * Lx + xp], d = ids[(size_t)yp * Lx + x];
+        const int dr = ids[(size_t)yp * Lx + xp], dl = ids[(size_t)yp * Lx + xm];
+        if (r != s) {
+            int p0 = ts, p1 = ty[r];
+            if (p0 > p1) { const int tmp = p0; p0 = p1; p1 = tmp; }
+            atomicAdd(&lpair[p0 * nt - p0 * (p0 - 1) / 2 + (p1 - p0)], 1);
+            H += ljs[ts * nt + ty[r]];
+        }
+        if (d != s) {
+            int p0 = ts, p1 = ty[d];
+            if (p0 > p1) { const int tmp = p0; p0 = p1; p1 = tmp; }
+            atomicAdd(&lpair[p0 * nt - p0 * (p0 - 1) / 2 + (p1 - p0)], 1);
+            H += ljs[ts * nt + ty[d]];
+        }
+        if (dr != s) H += ljs[ts * nt + ty[dr]];
+        if (dl != s) H += ljs[ts * nt + ty[dl]];
+    }
+    atomicAdd(&lH, (unsigned long long)H);
+    __syncthreads();
+    int32_t* row = a.stats + ((size_t)rec_row * a.R + T.rep) * a.width;
+    if (threadIdx.x < 10 && lpair[threadIdx.x]) atomicAdd(&row[threadIdx.x], lpair[threadIdx.x]);
+    if (threadIdx.x == 0) atomicAdd(reinterpret_cast<unsigned long long*>(row + 10), lH);
+}
+
+// lambda S sum over cells (not the medium) of (a - A)^2, one block per replica.
+__global__ void k_cpm_area_energy(CpmArgs a, int rec_row) {
+    __shared__ unsigned long long lH;
+    const int r = blockIdx.x;
+    const RepDev R = a.reps[r];
+    if (threadIdx.x == 0) lH = 0ull;
+    __syncthreads();
+    const int32_t* area = a.area + R.cell_off;
+    const int32_t* A = a.target + R.cell_off;
+    long long H = 0;
+    for (int i = 1 + threadIdx.x; i <= R.q; i += blockDim.x) {
+        const long long d = (long long)area[i] - (long long)A[i];
+        H += R.LS * d * d;
+    }
+    atomicAdd(&lH, (unsigned long long)H);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t* row = a.stats + ((size_t)rec_row * a.R + r) * a.width;
+        atomicAdd(reinterpret_cast<unsigned long long*>(row + 10), lH);
+    }
+}
+
+hipError_t launch_cpm_pass(const CpmArgs& a, int n_tiles, int c, int sweep_off, int threads,
+                           size_t lds_tab_bytes, hipStream_t s) {
+    hipLaunchKernelGGL(k_cpm_pass, dim3(n_tiles), dim3(threads), lds_tab_bytes, s, a, c,
+                       sweep_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_cpm_snapshot(const CpmArgs& a, int total_cells, hipStream_t s) {
+    int blocks = (total_cells + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_cpm_copy, dim3(blocks), dim3(256), 0, s, a.area, a.snap, total_cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_cpm_area_recount(const CpmArgs& a, int n_tiles, int total_cells, hipStream_t s) {
+    hipError_t e = launch_fill_i32(a.area, (size_t)total_cells, 0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cpm_area_count, dim3(n_tiles), dim3(256), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_cpm_snapshot(a, total_cells, s);
+}
+
+hipError_t launch_cpm_stats(const CpmArgs& a, int n_tiles, int rec_row, hipStream_t s) {
+    hipLaunchKernelGGL(k_cpm_stats, dim3(n_tiles), dim3(256), 0, s, a, rec_row);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cpm_area_energy, dim3(a.R), dim3(256), 0, s, a, rec_row);
+    return hipGetLastError();
+}
+
+}  // namespace spinmc

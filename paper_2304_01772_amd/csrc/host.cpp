@@ -1,0 +1,1311 @@
+// Host runtime of libspinmc: validation, FP64 Metropolis thresholds, device
+// memory, state I/O, schedules, and the C ABI declared in include/spinmc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "spinmc.h"
+#include "spinmc_internal.hpp"
+
+using namespace spinmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kResidentMaxBytes = 128 * 1024;  // lattice bytes kept in LDS by the resident kernel
+constexpr int kMaxCpmCells = 1 << 20;
+constexpr int kGraphChunk = 50;  // sweeps per captured graph
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Metropolis threshold of Algorithm 1 for a uniform 32-bit word W:
+// accept iff W < T with T = 2^32 when dE <= 0, else ceil(2^32 exp(-beta dE)).
+uint64_t metropolis_threshold(double dE, double beta) {
+    if (dE <= 0.0) return (uint64_t)1 << 32;
+    return (uint64_t)std::ceil(std::ldexp(std::exp(-beta * dE), 32));
+}
+
+// Ising, Eq. (1): flipping s with neighbour sums Sx, Sy changes the energy by
+// dE = 2 s (Jx Sx + Jy Sy + h); class 9[s>0] + 3(Sx/2+1) + (Sy/2+1).
+void ising_thresholds(float Jx, float Jy, float h, double beta, std::vector<uint64_t>& T) {
+    T.assign(kIsingClasses, 0);
+    for (int si = 0; si < 2; ++si)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double s = si ? 1.0 : -1.0;
+                const double Sx = 2.0 * a - 2.0, Sy = 2.0 * b - 2.0;
+                double u = (double)Jx * Sx;
+                u = u + (double)Jy * Sy;
+                u = u + (double)h;
+                const double dE = 2.0 * s * u;
+                T[9 * si + 3 * a + b] = metropolis_threshold(dE, beta);
+            }
+}
+
+// Potts, Eq. (2): s -> s' changes the energy by dE = -(J dn + h (s' - s)),
+// dn = #{neighbours == s'} - #{neighbours == s}; class (dn+4)(2q-1)+(s'-s+q-1).
+void potts_thresholds(int q, float J, float h, double beta, std::vector<uint64_t>& T) {
+    T.assign((size_t)9 * (2 * q - 1), 0);
+    for (int dn = -4; dn <= 4; ++dn)
+        for (int ds = -(q - 1); ds <= q - 1; ++ds) {
+            double u = (double)J * (double)dn;
+            u = u + (double)h * (double)ds;
+            const double dE = -u;
+            T[(size_t)(dn + 4) * (2 * q - 1) + (ds + q - 1)] = metropolis_threshold(dE, beta);
+        }
+}
+
+struct HostRep {
+    spinmc_replica_desc d{};
+    std::vector<float> adh;
+    std::vector<int8_t> ctype;
+    std::vector<int32_t> target;
+    std::vector<uint64_t> T;
+    int64_t aux = 0;
+    RepDev dev{};
+    bool chunk = false;     // W % 16 == 0: 16-byte SWAR path
+    bool resident = false;  // fits the resident kernel's LDS
+    size_t lat_bytes = 0;
+};
+
+}  // namespace
+
+struct spinmc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    uint64_t seed = 0;
+    uint64_t t = 0;
+    bool poisoned = false;
+    int R = 0;
+    int width = 8;
+    bool cpm = false;
+    std::vector<HostRep> reps;
+    int max_tab_n = 0;
+    int max_sites = 0;
+    // device buffers
+    uint8_t* d_lat = nullptr;
+    size_t lat_bytes = 0;
+    RepDev* d_reps = nullptr;
+    uint32_t* d_tab = nullptr;
+    uint64_t* d_t = nullptr;
+    int32_t* d_hist = nullptr;
+    int32_t* d_lists = nullptr;  // [all | potts | chunk-resident | generic-resident | stream-exempt]
+    std::vector<int32_t> all_list, potts_list, res_chunk, res_gen, stream_rest;
+    int off_all = 0, off_potts = 0, off_res_chunk = 0, off_res_gen = 0, off_rest = 0;
+    TileDev* d_tiles = nullptr;
+    int n_tiles = 0;
+    int tiles_rows = 0;
+    spinmc_schedule sched{0, 0, 0, 0};
+    bool prepared = false;
+    long prepared_key = 0;
+    std::vector<int32_t> stream_potts;
+    // hipGraphs of whole chunks of unrecorded sweeps, keyed by chunk length
+    bool use_graphs = true;
+    std::map<int, hipGraphExec_t> graphs;
+    hipStream_t cap[2] = {nullptr, nullptr};
+    hipEvent_t cap_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // Cellular Potts
+    int8_t* d_ctype = nullptr;
+    int32_t* d_target = nullptr;
+    int32_t* d_area = nullptr;
+    int32_t* d_snap = nullptr;
+    int32_t* d_js = nullptr;
+    int total_cells = 0;
+    // kernel timing
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<std::tuple<int, hipEvent_t, hipEvent_t>> prof_recs;
+};
+
+namespace {
+
+int check_dev(spinmc_ctx* c, hipError_t e, const char* what) {
+    if (e == hipSuccess) return SPINMC_OK;
+    c->poisoned = true;
+    return fail(SPINMC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+hipEvent_t next_event(spinmc_ctx* c) {
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->ev_pool.push_back(e);
+    }
+    return c->ev_pool[c->ev_used++];
+}
+
+// Bracket one kernel launch with events when timing is on.
+template <class F>
+hipError_t timed(spinmc_ctx* c, int kind, F&& launch, hipStream_t s) {
+    if (!c->prof) return launch();
+    hipEvent_t a = next_event(c), b = next_event(c);
+    if (!a || !b) return launch();
+    hipError_t e = hipEventRecord(a, s);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) c->prof_recs.emplace_back(kind, a, b);
+    return e;
+}
+
+void free_all(spinmc_ctx* c) {
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+    for (int k = 0; k < 2; ++k) {
+        if (c->cap[k]) hipStreamDestroy(c->cap[k]);
+        c->cap[k] = nullptr;
+    }
+    for (int k = 0; k < 4; ++k) {
+        if (c->cap_ev[k]) hipEventDestroy(c->cap_ev[k]);
+        c->cap_ev[k] = nullptr;
+    }
+    for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
+    c->ev_pool.clear();
+    c->ev_used = 0;
+    c->prof_recs.clear();
+    hipFree(c->d_lat);
+    hipFree(c->d_reps);
+    hipFree(c->d_tab);
+    hipFree(c->d_t);
+    hipFree(c->d_hist);
+    hipFree(c->d_lists);
+    hipFree(c->d_tiles);
+    hipFree(c->d_ctype);
+    hipFree(c->d_target);
+    hipFree(c->d_area);
+    hipFree(c->d_snap);
+    hipFree(c->d_js);
+    c->d_ctype = nullptr;
+    c->d_target = nullptr;
+    c->d_area = nullptr;
+    c->d_snap = nullptr;
+    c->d_js = nullptr;
+    c->d_lat = nullptr;
+    c->d_reps = nullptr;
+    c->d_tab = nullptr;
+    c->d_t = nullptr;
+    c->d_hist = nullptr;
+    c->d_lists = nullptr;
+    c->d_tiles = nullptr;
+}
+
+int validate(const spinmc_replica_desc& d, int i, bool& cpm_seen, bool& lat_seen) {
+    if (d.model != SPINMC_ISING && d.model != SPINMC_POTTS && d.model != SPINMC_CPM)
+        return fail(SPINMC_E_INVALID, "replica %d: unknown model %d", i, d.model);
+    if (d.Lx < 2 || d.Ly < 2 || (d.Lx & 1) || (d.Ly & 1))
+        return fail(SPINMC_E_INVALID, "replica %d: Lx, Ly must be even and >= 2 (got %d x %d)", i,
+                    d.Lx, d.Ly);
+    if ((int64_t)d.Lx * d.Ly > (1 << 28))
+        return fail(SPINMC_E_INVALID, "replica %d: lattice too large", i);
+    if (d.model == SPINMC_CPM) {
+        cpm_seen = true;
+        if (d.q < 1 || d.q > kMaxCpmCells)
+            return fail(SPINMC_E_INVALID, "replica %d: CPM needs 1 <= n_cells <= %d", i, kMaxCpmCells);
+        if (d.n_types < 1 || d.n_types > kMaxCpmTypes)
+            return fail(SPINMC_E_INVALID, "replica %d: CPM needs 1 <= n_types <= %d", i,
+                        kMaxCpmTypes);
+        if (!d.adhesion || !d.cell_type || !d.target_area)
+            return fail(SPINMC_E_INVALID, "replica %d: CPM tables missing", i);
+        if (!(d.temperature > 0.0) || !std::isfinite(d.temperature))
+            return fail(SPINMC_E_INVALID, "replica %d: CPM temperature must be > 0", i);
+        if (!(d.lambda_area >= 0.0f) || !std::isfinite(d.lambda_area))
+            return fail(SPINMC_E_INVALID, "replica %d: CPM lambda must be >= 0", i);
+        if (d.cell_type[0] != 0)
+            return fail(SPINMC_E_INVALID, "replica %d: cell_type[0] (medium) must be 0", i);
+        for (int k = 0; k <= d.q; ++k)
+            if (d.cell_type[k] < 0 || d.cell_type[k] >= d.n_types)
+                return fail(SPINMC_E_INVALID, "replica %d: cell type out of range", i);
+        for (int a = 0; a < d.n_types; ++a)
+            for (int b = 0; b < d.n_types; ++b) {
+                const float v = d.adhesion[a * d.n_types + b];
+                if (!std::isfinite(v) || v != d.adhesion[b * d.n_types + a])
+                    return fail(SPINMC_E_INVALID, "replica %d: adhesion must be finite, symmetric",
+                                i);
+            }
+        return SPINMC_OK;
+    }
+    lat_seen = true;
+    if (!std::isfinite(d.Jx) || !std::isfinite(d.Jy) || !std::isfinite(d.h))
+        return fail(SPINMC_E_INVALID, "replica %d: non-finite coupling or field", i);
+    if (!(d.beta >= 0.0) || !std::isfinite(d.beta))
+        return fail(SPINMC_E_INVALID, "replica %d: beta must be finite and >= 0", i);
+    if (d.model == SPINMC_POTTS) {
+        if (d.q < 2 || d.q > 255)
+            return fail(SPINMC_E_INVALID, "replica %d: Potts q must be in [2, 255]", i);
+        if (d.q > kMaxPottsQ)
+            return fail(SPINMC_E_UNSUPPORTED, "replica %d: Potts q > %d not supported", i,
+                        kMaxPottsQ);
+        if (d.Jy != d.Jx)
+            return fail(SPINMC_E_UNSUPPORTED, "replica %d: Potts needs Jy == Jx", i);
+    }
+    return SPINMC_OK;
+}
+
+// ----------------------------------------------------------- Cellular Potts
+// Fixed point of Eq. (3): the smallest S = 2^s (s <= 8) that makes every
+// J[a][b] S and lambda S an integer below 2^20 in magnitude; thresholds
+// T(k) = ceil(2^32 exp(-k / (S T_temp))) for k = 1..K1-1, T = 1 for
+// K1 <= k < K0, T = 0 from K0 on.
+struct CpmFixed {
+    int32_t S = 1;
+    std::vector<int32_t> JS;
+    int64_t LS = 0;
+    std::vector<uint64_t> T;
+    int32_t K1 = 1;
+    int64_t K0 = 1;
+};
+
+constexpr int kMaxCpmTable = 16384;  // thresholds staged in LDS (<= 128 KiB)
+
+uint64_t cpm_T(int64_t k, int32_t S, double temp) {
+    return (uint64_t)std::ceil(std::ldexp(std::exp(-(double)k / ((double)S * temp)), 32));
+}
+
+int cpm_fixed_point(const spinmc_replica_desc& d, int i, CpmFixed& f) {
+    const int nt = d.n_types;
+    int s;
+    for (s = 0; s <= 8; ++s) {
+        const double S = std::ldexp(1.0, s);
+        bool ok = true;
+        for (int k = 0; k < nt * nt && ok; ++k) {
+            const double v = (double)d.adhesion[k] * S;
+            if (!(std::fabs(v) < 1048576.0) || v != std::floor(v)) ok = false;
+        }
+        const double l = (double)d.lambda_area * S;
+        if (!(std::fabs(l) < 1048576.0) || l != std::floor(l)) ok = false;
+        if (ok) break;
+    }
+    if (s > 8)
+        return fail(SPINMC_E_NOT_REPRESENTABLE,
+                    "replica %d: adhesion / lambda not exact in a fixed-point scale <= 256", i);
+    f.S = 1 << s;
+    f.JS.resize((size_t)nt * nt);
+    for (int k = 0; k < nt * nt; ++k) f.JS[k] = (int32_t)std::llround((double)d.adhesion[k] * f.S);
+    f.LS = (int64_t)std::llround((double)d.lambda_area * f.S);
+    f.T.clear();
+    int64_t k = 1;
+    for (;; ++k) {
+        const uint64_t t = cpm_T(k, f.S, d.temperature);
+        if (t <= 1) break;
+        f.T.push_back(t);
+        if ((int64_t)f.T.size() > kMaxCpmTable)
+            return fail(SPINMC_E_UNSUPPORTED, "replica %d: CPM temperature too high for the table",
+                        i);
+    }
+    f.K1 = (int32_t)k;
+    if (cpm_T(k, f.S, d.temperature) == 0) {
+        f.K0 = k;
+        return SPINMC_OK;
+    }
+    // smallest k with T(k) = 0 (exp underflow), by doubling then bisection
+    int64_t lo = k, hi = k;
+    while (cpm_T(hi, f.S, d.temperature) != 0) {
+        lo = hi;
+        if (hi > ((int64_t)1 << 61)) {
+            f.K0 = INT64_MAX;
+            return SPINMC_OK;
+        }
+        hi *= 2;
+    }
+    while (hi - lo > 1) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (cpm_T(mid, f.S, d.temperature) == 0)
+            hi = mid;
+        else
+            lo = mid;
+    }
+    f.K0 = hi;
+    return SPINMC_OK;
+}
+
+int cpm_prepare_tables(const spinmc_replica_desc* d, int n) {
+    for (int i = 0; i < n; ++i) {
+        CpmFixed f;
+        int rc = cpm_fixed_point(d[i], i, f);
+        if (rc) return rc;
+    }
+    return SPINMC_OK;
+}
+
+int create_cpm(const spinmc_replica_desc* d, int n, uint64_t seed, void* stream,
+               spinmc_ctx** out);
+
+size_t resident_lds(const spinmc_ctx* c, const HostRep& r) {
+    return align_up((size_t)8 * c->max_tab_n, 16) + r.lat_bytes;
+}
+
+int enqueue_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
+int cpm_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes);
+int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes);
+int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
+int cpm_measure(spinmc_ctx* c, int32_t* stats, double* obs);
+int default_tile_rows(const HostRep& h);
+int effective_mode(const spinmc_ctx* c);
+
+}  // namespace
+
+// ===================================================================== ABI
+extern "C" {
+
+const char* spinmc_last_error(void) { return g_err.c_str(); }
+
+int spinmc_create(const spinmc_replica_desc* d, int32_t n, uint64_t seed, int32_t init,
+                  void* hip_stream, spinmc_ctx** out) {
+    if (!d || !out || n < 1) return fail(SPINMC_E_INVALID, "create: null argument or n < 1");
+    *out = nullptr;
+    if (init != 0 && init != 1) return fail(SPINMC_E_INVALID, "create: init must be 0 or 1");
+    bool cpm_seen = false, lat_seen = false;
+    for (int i = 0; i < n; ++i) {
+        int rc = validate(d[i], i, cpm_seen, lat_seen);
+        if (rc) return rc;
+    }
+    if (cpm_seen && lat_seen)
+        return fail(SPINMC_E_UNSUPPORTED, "create: CPM replicas cannot share a context with Ising/Potts");
+    if (cpm_seen) {
+        int rc = cpm_prepare_tables(d, n);
+        if (rc) return rc;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return fail(SPINMC_E_DEVICE, "create: no HIP device available");
+    if (cpm_seen) return create_cpm(d, n, seed, hip_stream, out);
+    spinmc_ctx* c = new spinmc_ctx();
+    hipGetDevice(&c->device);
+    c->stream = (hipStream_t)hip_stream;
+    c->seed = seed;
+    c->R = n;
+    c->width = 8;
+    c->reps.resize(n);
+    size_t lat_off = 0, tab_off = 0, hist_off = 0;
+    for (int i = 0; i < n; ++i) {
+        HostRep& h = c->reps[i];
+        h.d = d[i];
+        h.d.adhesion = nullptr;
+        h.d.cell_type = nullptr;
+        h.d.target_area = nullptr;
+        RepDev& r = h.dev;
+        r.model = d[i].model;
+        r.Lx = d[i].Lx;
+        r.Ly = d[i].Ly;
+        r.W = d[i].Lx / 2;
+        r.q = d[i].model == SPINMC_POTTS ? d[i].q : 2;
+        r.rid = d[i].rid;
+        r.Jx = d[i].Jx;
+        r.Jy = d[i].Jy;
+        r.h = d[i].h;
+        r.beta = d[i].beta;
+        if (r.model == SPINMC_ISING)
+            ising_thresholds(d[i].Jx, d[i].Jy, d[i].h, d[i].beta, h.T);
+        else
+            potts_thresholds(d[i].q, d[i].Jx, d[i].h, d[i].beta, h.T);
+        r.tab_n = (int)h.T.size();
+        r.tab_off = (int)tab_off;
+        tab_off += 2 * h.T.size();
+        c->max_tab_n = std::max(c->max_tab_n, r.tab_n);
+        h.lat_bytes = (size_t)r.Lx * r.Ly;
+        r.lat_off = (int64_t)lat_off;
+        lat_off = align_up(lat_off + h.lat_bytes, kAlign);
+        r.hist_off = (int)hist_off;
+        if (r.model == SPINMC_POTTS) hist_off += (size_t)r.q;
+        h.chunk = (r.W % 16) == 0;
+        h.resident = h.lat_bytes <= (size_t)kResidentMaxBytes;
+        if (!h.chunk && !h.resident) {
+            delete c;
+            return fail(SPINMC_E_UNSUPPORTED,
+                        "replica %d: Lx/2 must be a multiple of 16 for lattices above %d sites", i,
+                        kResidentMaxBytes);
+        }
+        c->max_sites = std::max(c->max_sites, r.Lx * r.Ly);
+        c->all_list.push_back(i);
+        if (r.model == SPINMC_POTTS) c->potts_list.push_back(i);
+    }
+    c->lat_bytes = lat_off + 64;
+    // host threshold words: hi16 | lo16 halves
+    std::vector<uint32_t> tab(std::max<size_t>(tab_off, 1));
+    for (int i = 0; i < n; ++i) {
+        const HostRep& h = c->reps[i];
+        for (int k = 0; k < h.dev.tab_n; ++k) {
+            tab[h.dev.tab_off + k] = (uint32_t)(h.T[k] >> 16);
+            tab[h.dev.tab_off + h.dev.tab_n + k] = (uint32_t)(h.T[k] & 0xFFFFu);
+        }
+    }
+    std::vector<RepDev> rd(n);
+    for (int i = 0; i < n; ++i) rd[i] = c->reps[i].dev;
+    auto A = [&](void** p, size_t b) { return hipMalloc(p, std::max<size_t>(b, 16)); };
+    hipError_t e = hipSuccess;
+    if ((e = A((void**)&c->d_lat, c->lat_bytes)) != hipSuccess ||
+        (e = A((void**)&c->d_reps, sizeof(RepDev) * n)) != hipSuccess ||
+        (e = A((void**)&c->d_tab, sizeof(uint32_t) * tab.size())) != hipSuccess ||
+        (e = A((void**)&c->d_t, sizeof(uint64_t))) != hipSuccess ||
+        (e = A((void**)&c->d_hist, sizeof(int32_t) * std::max<size_t>(hist_off, 1))) != hipSuccess ||
+        (e = A((void**)&c->d_lists, sizeof(int32_t) * 5 * n)) != hipSuccess) {
+        free_all(c);
+        delete c;
+        hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? SPINMC_E_NOMEM : SPINMC_E_DEVICE,
+                    "create: device allocation failed: %s", hipGetErrorString(e));
+    }
+    std::vector<int32_t> lists(5 * (size_t)n, 0);
+    c->off_all = 0;
+    c->off_potts = n;
+    c->off_res_chunk = 2 * n;
+    c->off_res_gen = 3 * n;
+    c->off_rest = 4 * n;
+    std::copy(c->all_list.begin(), c->all_list.end(), lists.begin() + c->off_all);
+    std::copy(c->potts_list.begin(), c->potts_list.end(), lists.begin() + c->off_potts);
+    const uint64_t zero = 0;
+    if ((e = hipMemcpy(c->d_reps, rd.data(), sizeof(RepDev) * n, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_tab, tab.data(), sizeof(uint32_t) * tab.size(),
+                       hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_t, &zero, sizeof zero, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_lists, lists.data(), sizeof(int32_t) * lists.size(),
+                       hipMemcpyHostToDevice)) ||
+        (e = hipMemset(c->d_hist, 0, sizeof(int32_t) * std::max<size_t>(hist_off, 1))) ||
+        (e = hipMemset(c->d_lat, 0, c->lat_bytes))) {
+        free_all(c);
+        delete c;
+        return fail(SPINMC_E_DEVICE, "create: upload failed: %s", hipGetErrorString(e));
+    }
+    if (init == 1) {
+        e = launch_init(c->d_reps, c->d_lists + c->off_all, n, c->d_lat,
+                        (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), 256, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            free_all(c);
+            delete c;
+            return fail(SPINMC_E_DEVICE, "create: init kernel failed: %s", hipGetErrorString(e));
+        }
+    }
+    *out = c;
+    return SPINMC_OK;
+}
+
+int spinmc_destroy(spinmc_ctx* c) {
+    if (!c) return SPINMC_OK;
+    if (!c->poisoned) hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+    return SPINMC_OK;
+}
+
+int spinmc_num_replicas(const spinmc_ctx* c) { return c ? c->R : SPINMC_E_INVALID; }
+int spinmc_stats_width(const spinmc_ctx* c) { return c ? c->width : SPINMC_E_INVALID; }
+
+int spinmc_sweep_counter(const spinmc_ctx* c, uint64_t* t) {
+    if (!c || !t) return fail(SPINMC_E_INVALID, "sweep_counter: null argument");
+    *t = c->t;
+    return SPINMC_OK;
+}
+
+int spinmc_set_state(spinmc_ctx* c, int32_t r, const void* host, size_t bytes) {
+    if (!c || !host) return fail(SPINMC_E_INVALID, "set_state: null argument");
+    if (c->poisoned) return fail(SPINMC_E_DEVICE, "set_state: context poisoned");
+    if (r < 0 || r >= c->R) return fail(SPINMC_E_INVALID, "set_state: replica out of range");
+    if (c->cpm) return cpm_set_state(c, r, host, bytes);
+    const HostRep& h = c->reps[r];
+    const int Lx = h.dev.Lx, Ly = h.dev.Ly, W = h.dev.W;
+    if (bytes != (size_t)Lx * Ly) return fail(SPINMC_E_INVALID, "set_state: wrong byte count");
+    const uint8_t* src = (const uint8_t*)host;
+    std::vector<uint8_t> planes((size_t)Lx * Ly);
+    for (int y = 0; y < Ly; ++y)
+        for (int x = 0; x < Lx; ++x) {
+            const int8_t v = (int8_t)src[(size_t)y * Lx + x];
+            uint8_t u;
+            if (h.dev.model == SPINMC_ISING) {
+                if (v != 1 && v != -1)
+                    return fail(SPINMC_E_INVALID, "set_state: Ising spins must be +-1");
+                u = v > 0 ? 1 : 0;
+            } else {
+                u = (uint8_t)v;
+                if ((int)u >= h.dev.q)
+                    return fail(SPINMC_E_INVALID, "set_state: Potts label out of range");
+            }
+            planes[(size_t)((x + y) & 1) * Ly * W + (size_t)y * W + (x >> 1)] = u;
+        }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->d_lat + h.dev.lat_off, planes.data(), planes.size(), hipMemcpyHostToDevice);
+    return check_dev(c, e, "set_state");
+}
+
+int spinmc_get_state(spinmc_ctx* c, int32_t r, void* host, size_t bytes) {
+    if (!c || !host) return fail(SPINMC_E_INVALID, "get_state: null argument");
+    if (c->poisoned) return fail(SPINMC_E_DEVICE, "get_state: context poisoned");
+    if (r < 0 || r >= c->R) return fail(SPINMC_E_INVALID, "get_state: replica out of range");
+    if (c->cpm) return cpm_get_state(c, r, host, bytes);
+    const HostRep& h = c->reps[r];
+    const int Lx = h.dev.Lx, Ly = h.dev.Ly, W = h.dev.W;
+    if (bytes != (size_t)Lx * Ly) return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
+    std::vector<uint8_t> planes((size_t)Lx * Ly);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(planes.data(), c->d_lat + h.dev.lat_off, planes.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return check_dev(c, e, "get_state");
+    uint8_t* dst = (uint8_t*)host;
+    for (int y = 0; y < Ly; ++y)
+        for (int x = 0; x < Lx; ++x) {
+            const uint8_t u = planes[(size_t)((x + y) & 1) * Ly * W + (size_t)y * W + (x >> 1)];
+            dst[(size_t)y * Lx + x] =
+                h.dev.model == SPINMC_ISING ? (uint8_t)(int8_t)(u ? 1 : -1) : u;
+        }
+    return SPINMC_OK;
+}
+
+int spinmc_thresholds(const spinmc_ctx* c, int32_t r, uint64_t* T, int32_t cap, int32_t* n_out,
+                      int64_t* aux) {
+    if (!c || !n_out) return fail(SPINMC_E_INVALID, "thresholds: null argument");
+    if (r < 0 || r >= c->R) return fail(SPINMC_E_INVALID, "thresholds: replica out of range");
+    const HostRep& h = c->reps[r];
+    *n_out = (int32_t)h.T.size();
+    if (aux) *aux = h.aux;
+    if (T) {
+        if (cap < (int32_t)h.T.size()) return fail(SPINMC_E_INVALID, "thresholds: capacity");
+        std::copy(h.T.begin(), h.T.end(), T);
+    }
+    return SPINMC_OK;
+}
+
+int spinmc_schedule_sites(const spinmc_ctx* c, int64_t* streamed, int64_t* resident) {
+    if (!c || !streamed || !resident) return fail(SPINMC_E_INVALID, "schedule_sites: null argument");
+    int64_t st = 0, re = 0;
+    if (c->cpm) {
+        for (const HostRep& h : c->reps) st += (int64_t)h.dev.Lx * h.dev.Ly;
+    } else {
+        const int mode = effective_mode(c);
+        for (const HostRep& h : c->reps) {
+            const bool res = (mode == 1) || !h.chunk || (mode == 3 && h.resident);
+            (res ? re : st) += (int64_t)h.dev.Lx * h.dev.Ly;
+        }
+    }
+    *streamed = st;
+    *resident = re;
+    return SPINMC_OK;
+}
+
+int spinmc_get_schedule(const spinmc_ctx* c, spinmc_schedule* s) {
+    if (!c || !s) return fail(SPINMC_E_INVALID, "get_schedule: null argument");
+    *s = c->sched;
+    return SPINMC_OK;
+}
+
+int spinmc_set_schedule(spinmc_ctx* c, const spinmc_schedule* s) {
+    if (!c || !s) return fail(SPINMC_E_INVALID, "set_schedule: null argument");
+    if (s->mode < 0 || s->mode > 3)
+        return fail(SPINMC_E_INVALID, "set_schedule: mode %d not available", s->mode);
+    if (s->tile_rows < 0 || (s->tile_rows & 1))
+        return fail(SPINMC_E_INVALID, "set_schedule: tile_rows must be even and >= 0");
+    if (s->wg_threads != 0 && s->wg_threads != 256 && s->wg_threads != 512 &&
+        !(s->mode == 1 && s->wg_threads == 1024))
+        return fail(SPINMC_E_INVALID, "set_schedule: wg_threads must be 256 or 512 (1024 resident)");
+    if (s->mode == 1 && !c->cpm)
+        for (const HostRep& h : c->reps)
+            if (!h.resident)
+                return fail(SPINMC_E_INVALID, "set_schedule: a lattice exceeds the resident LDS budget");
+    c->sched = *s;
+    c->prepared = false;  // new tiles, resident lists and graphs on the next sweep
+    return SPINMC_OK;
+}
+
+int spinmc_sweep(spinmc_ctx* c, int32_t n, int32_t re, void* dev_stats) {
+    if (!c) return fail(SPINMC_E_INVALID, "sweep: null context");
+    if (c->poisoned) return fail(SPINMC_E_DEVICE, "sweep: context poisoned");
+    if (n < 0 || re < 0) return fail(SPINMC_E_INVALID, "sweep: negative count");
+    if (re > 0 && !dev_stats) return fail(SPINMC_E_INVALID, "sweep: recording needs dev_stats");
+    if ((uint64_t)c->t + (uint64_t)n >= ((uint64_t)1 << 31))
+        return fail(SPINMC_E_INVALID, "sweep: sweep counter would exceed 2^31");
+    if (n == 0) return SPINMC_OK;
+    int rc = c->cpm ? cpm_sweep(c, n, re, (int32_t*)dev_stats)
+                    : enqueue_sweep(c, n, re, (int32_t*)dev_stats);
+    if (rc == SPINMC_OK) c->t += (uint64_t)n;
+    return rc;
+}
+
+int spinmc_measure(spinmc_ctx* c, void* dev_stats, void* dev_obs) {
+    if (!c || !dev_stats) return fail(SPINMC_E_INVALID, "measure: null argument");
+    if (c->poisoned) return fail(SPINMC_E_DEVICE, "measure: context poisoned");
+    int32_t* st = (int32_t*)dev_stats;
+    if (c->cpm) return cpm_measure(c, st, (double*)dev_obs);
+    hipError_t e = launch_fill_i32(st, (size_t)c->R * c->width, 0, c->stream);
+    SweepArgs a{};
+    a.reps = c->d_reps;
+    a.stats = st;
+    a.hist = c->d_hist;
+    a.R = c->R;
+    a.width = c->width;
+    if (e == hipSuccess)
+        e = launch_measure(c->d_reps, c->d_lists + c->off_all, c->R, c->max_sites, c->d_lat, st,
+                           c->d_hist, c->width, c->stream);
+    if (e == hipSuccess && !c->potts_list.empty())
+        e = launch_potts_hist_finalize(a, c->d_lists + c->off_potts, (int)c->potts_list.size(), 0,
+                                       c->stream);
+    if (e == hipSuccess && dev_obs)
+        e = launch_observables(c->d_reps, c->R, st, c->width, (double*)dev_obs, c->stream);
+    return check_dev(c, e, "measure");
+}
+
+int spinmc_grad(spinmc_ctx* c, const void* dev_stats, int32_t n_rec, int32_t burn_in,
+                const void* gout, void* means, void* grads, void* dtheta) {
+    if (!c || !dev_stats) return fail(SPINMC_E_INVALID, "grad: null argument");
+    if (c->poisoned) return fail(SPINMC_E_DEVICE, "grad: context poisoned");
+    for (const HostRep& h : c->reps)
+        if (h.dev.model != SPINMC_ISING) return fail(SPINMC_E_UNSUPPORTED, "grad: Ising contexts only");
+    if (n_rec < 1 || burn_in < 0 || burn_in >= n_rec)
+        return fail(SPINMC_E_INVALID, "grad: need 0 <= burn_in < n_rec");
+    if (dtheta && !gout) return fail(SPINMC_E_INVALID, "grad: dtheta needs grad_out");
+    hipError_t e = launch_cov_grad(c->d_reps, c->R, (const int32_t*)dev_stats, n_rec, burn_in,
+                                   c->width, (const double*)gout, (double*)means, (double*)grads,
+                                   (double*)dtheta, c->stream);
+    return check_dev(c, e, "grad");
+}
+
+int spinmc_profile(spinmc_ctx* c, int32_t enable) {
+    if (!c) return fail(SPINMC_E_INVALID, "profile: null context");
+    if (enable) {
+        hipStreamSynchronize(c->stream);
+        c->prof_recs.clear();
+        c->ev_used = 0;
+    }
+    c->prof = enable != 0;
+    return SPINMC_OK;
+}
+
+int spinmc_profile_read(spinmc_ctx* c, int32_t kind, double* ms, int64_t* launches) {
+    if (!c || !ms || !launches) return fail(SPINMC_E_INVALID, "profile_read: null argument");
+    double tot = 0.0;
+    int64_t n = 0;
+    for (auto& r : c->prof_recs) {
+        if (std::get<0>(r) != kind) continue;
+        hipError_t e = hipEventSynchronize(std::get<2>(r));
+        float m = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&m, std::get<1>(r), std::get<2>(r));
+        if (e != hipSuccess) return check_dev(c, e, "profile_read");
+        tot += m;
+        ++n;
+    }
+    *ms = tot;
+    *launches = n;
+    return SPINMC_OK;
+}
+
+int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen, double* rates,
+                    int32_t cap, int32_t* n_tried) {
+    if (!c) return fail(SPINMC_E_INVALID, "autotune: null context");
+    if (c->poisoned) return fail(SPINMC_E_DEVICE, "autotune: context poisoned");
+    if (trial_sweeps < 1) return fail(SPINMC_E_INVALID, "autotune: trial_sweeps must be >= 1");
+    // candidate schedules
+    std::vector<spinmc_schedule> cand;
+    if (c->cpm) {
+        for (int tr : {0, 2, 4, 8, 16}) cand.push_back(spinmc_schedule{2, tr, 256, 0});
+    } else {
+        bool all_res = true, any_res_chunk = false, any_stream = false;
+        int min_def = 1 << 30;
+        for (const HostRep& h : c->reps) {
+            all_res = all_res && h.resident;
+            any_res_chunk = any_res_chunk || (h.resident && h.chunk);
+            any_stream = any_stream || h.chunk;
+            if (h.chunk) min_def = std::min(min_def, default_tile_rows(h));
+        }
+        if (all_res)
+            for (int th : {256, 512, 1024}) cand.push_back(spinmc_schedule{1, 0, th, 0});
+        if (any_stream) {
+            std::vector<int> trs = {0};
+            if (min_def >= 8) trs.push_back(std::max(2, (min_def / 2) & ~1));
+            trs.push_back(min_def * 2);
+            for (int mode : {2, 3}) {
+                if (mode == 3 && !any_res_chunk) continue;
+                for (int tr : trs)
+                    for (int th : {256, 512}) cand.push_back(spinmc_schedule{mode, tr, th, 0});
+            }
+        }
+    }
+    if (cand.empty()) return fail(SPINMC_E_UNSUPPORTED, "autotune: no candidate schedule");
+    const spinmc_schedule saved_sched = c->sched;
+    const uint64_t saved_t = c->t;
+    // scratch copy of the state (lattices, sweep counter, CPM areas)
+    uint8_t* lat_copy = nullptr;
+    int32_t* area_copy = nullptr;
+    uint64_t dt_saved = 0;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMalloc((void**)&lat_copy, c->lat_bytes);
+    if (e == hipSuccess && c->cpm) e = hipMalloc((void**)&area_copy, sizeof(int32_t) * c->total_cells);
+    if (e != hipSuccess) {
+        hipFree(lat_copy);
+        hipGetLastError();
+        return fail(SPINMC_E_NOMEM, "autotune: no memory for the state copy");
+    }
+    e = hipMemcpy(lat_copy, c->d_lat, c->lat_bytes, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipMemcpy(&dt_saved, c->d_t, sizeof dt_saved, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && c->cpm)
+        e = hipMemcpy(area_copy, c->d_area, sizeof(int32_t) * c->total_cells,
+                      hipMemcpyDeviceToDevice);
+    auto restore = [&]() -> hipError_t {
+        hipError_t r = hipStreamSynchronize(c->stream);
+        if (r == hipSuccess) r = hipMemcpy(c->d_lat, lat_copy, c->lat_bytes, hipMemcpyDeviceToDevice);
+        if (r == hipSuccess) r = hipMemcpy(c->d_t, &dt_saved, sizeof dt_saved, hipMemcpyHostToDevice);
+        if (r == hipSuccess && c->cpm) {
+            r = hipMemcpy(c->d_area, area_copy, sizeof(int32_t) * c->total_cells,
+                          hipMemcpyDeviceToDevice);
+            if (r == hipSuccess) r = hipMemcpy(c->d_snap, area_copy, sizeof(int32_t) * c->total_cells,
+                                               hipMemcpyDeviceToDevice);
+        }
+        c->t = saved_t;
+        return r;
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    double sites = 0;
+    for (const HostRep& h : c->reps) sites += (double)h.dev.Lx * h.dev.Ly;
+    int best = -1;
+    double best_rate = 0;
+    int tried = 0;
+    for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
+        c->sched = cand[k];
+        c->prepared = false;
+        // one warm-up sweep builds tiles and graphs
+        int rc = c->cpm ? cpm_sweep(c, 1, 0, nullptr) : enqueue_sweep(c, 1, 0, nullptr);
+        if (rc == SPINMC_OK) rc = c->cpm ? cpm_sweep(c, trial_sweeps, 0, nullptr)
+                                         : enqueue_sweep(c, trial_sweeps, 0, nullptr);
+        if (rc != SPINMC_OK) {
+            e = hipErrorUnknown;
+            break;
+        }
+        e = restore();
+        if (e != hipSuccess) break;
+        e = hipEventRecord(e0, c->stream);
+        rc = c->cpm ? cpm_sweep(c, trial_sweeps, 0, nullptr)
+                    : enqueue_sweep(c, trial_sweeps, 0, nullptr);
+        if (rc != SPINMC_OK) {
+            e = hipErrorUnknown;
+            break;
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        const double rate = ms > 0 ? sites * trial_sweeps / (ms * 1e6) : 0.0;
+        if (rates && tried < cap) rates[tried] = rate;
+        ++tried;
+        if (rate > best_rate) {
+            best_rate = rate;
+            best = (int)k;
+        }
+        if (e == hipSuccess) e = restore();
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipError_t er = restore();
+    hipFree(lat_copy);
+    hipFree(area_copy);
+    if (e != hipSuccess || er != hipSuccess || best < 0) {
+        c->sched = saved_sched;
+        c->prepared = false;
+        if (c->poisoned) return SPINMC_E_DEVICE;
+        return check_dev(c, e != hipSuccess ? e : er, "autotune");
+    }
+    c->sched = cand[best];
+    c->prepared = false;
+    if (chosen) *chosen = cand[best];
+    if (n_tried) *n_tried = tried;
+    return SPINMC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Resolve mode 0: everything resident when every lattice fits the LDS
+// budget, else the hybrid (resident where it fits, streamed otherwise).
+int effective_mode(const spinmc_ctx* c) {
+    if (c->sched.mode != 0) return c->sched.mode;
+    for (const HostRep& h : c->reps)
+        if (!h.resident) return 3;
+    return 1;
+}
+
+int default_tile_rows(const HostRep& h) {
+    // ~16 KiB of one plane per unit
+    int rows = std::max(2, 16384 / std::max(1, h.dev.W));
+    rows &= ~1;
+    return std::min(rows, h.dev.Ly);
+}
+
+void drop_graphs(spinmc_ctx* c) {
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+// (Re)build the tile table and the resident lists for a schedule.
+//   mode 1: every replica resident;
+//   mode 2: every replica with the chunk layout streamed (others resident);
+//   mode 3: resident if it fits the LDS budget, streamed otherwise.
+int prepare(spinmc_ctx* c, int mode) {
+    const int tr = c->sched.tile_rows;
+    const long key = ((long)mode << 32) | (long)(unsigned)tr;
+    if (c->prepared && c->prepared_key == key) return SPINMC_OK;
+    std::vector<int32_t> res_chunk, res_gen, spotts;
+    std::vector<TileDev> tiles;
+    for (int i = 0; i < c->R; ++i) {
+        const HostRep& h = c->reps[i];
+        const bool resident = (mode == 1) || !h.chunk || (mode == 3 && h.resident);
+        if (resident) {
+            (h.chunk ? res_chunk : res_gen).push_back(i);
+            continue;
+        }
+        if (h.dev.model == SPINMC_POTTS) spotts.push_back(i);
+        const int rows = tr > 0 ? std::min(tr, h.dev.Ly) : default_tile_rows(h);
+        for (int y0 = 0; y0 < h.dev.Ly; y0 += rows)
+            tiles.push_back(TileDev{i, y0, std::min(rows, h.dev.Ly - y0), 0});
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    c->res_chunk = res_chunk;
+    c->res_gen = res_gen;
+    c->stream_potts = spotts;
+    std::vector<int32_t> buf;
+    buf.insert(buf.end(), res_chunk.begin(), res_chunk.end());
+    buf.insert(buf.end(), res_gen.begin(), res_gen.end());
+    if (e == hipSuccess && !buf.empty())
+        e = hipMemcpy(c->d_lists + c->off_res_chunk, buf.data(), sizeof(int32_t) * buf.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !spotts.empty())
+        e = hipMemcpy(c->d_lists + c->off_rest, spotts.data(), sizeof(int32_t) * spotts.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && (int)tiles.size() != c->n_tiles) {
+        hipFree(c->d_tiles);
+        c->d_tiles = nullptr;
+        c->n_tiles = 0;
+        if (!tiles.empty()) e = hipMalloc((void**)&c->d_tiles, sizeof(TileDev) * tiles.size());
+    }
+    if (e == hipSuccess && !tiles.empty())
+        e = hipMemcpy(c->d_tiles, tiles.data(), sizeof(TileDev) * tiles.size(),
+                      hipMemcpyHostToDevice);
+    c->n_tiles = (int)tiles.size();
+    if (e == hipSuccess && !buf.empty()) {
+        size_t lds = 0;
+        for (int i : buf) lds = std::max(lds, resident_lds(c, c->reps[i]));
+        e = resident_reserve_lds(lds);
+    }
+    if (e == hipSuccess) {
+        c->prepared = true;
+        c->prepared_key = key;
+    }
+    return check_dev(c, e, "prepare schedule");
+}
+
+SweepArgs sweep_args(spinmc_ctx* c, int n, int re, int32_t* stats) {
+    SweepArgs a{};
+    a.reps = c->d_reps;
+    a.tiles = c->d_tiles;
+    a.tab = c->d_tab;
+    a.lat = c->d_lat;
+    a.t_base = c->d_t;
+    a.stats = stats;
+    a.hist = c->d_hist;
+    a.key0 = (uint32_t)(c->seed & 0xffffffffu);
+    a.key1 = (uint32_t)(c->seed >> 32);
+    a.R = c->R;
+    a.width = c->width;
+    a.n_sweeps = n;
+    a.record_every = re;
+    a.n_units = c->n_tiles;
+    a.tab_lds_bytes = (int)align_up((size_t)8 * c->max_tab_n, 16);
+    return a;
+}
+
+// Resident kernels for n sweeps on stream s.
+hipError_t enqueue_resident(spinmc_ctx* c, SweepArgs a, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const int res_threads = c->sched.wg_threads > 0 ? c->sched.wg_threads : 512;
+    size_t lds = 0;
+    for (int i : c->res_chunk) lds = std::max(lds, resident_lds(c, c->reps[i]));
+    if (!c->res_chunk.empty()) {
+        a.rep_list = c->d_lists + c->off_res_chunk;
+        e = timed(c, SPINMC_K_RESIDENT, [&] {
+            return launch_resident(a, (int)c->res_chunk.size(), 0, true, res_threads, lds, s);
+        }, s);
+    }
+    lds = 0;
+    for (int i : c->res_gen) lds = std::max(lds, resident_lds(c, c->reps[i]));
+    if (e == hipSuccess && !c->res_gen.empty()) {
+        a.rep_list = c->d_lists + c->off_res_chunk + c->res_chunk.size();
+        e = timed(c, SPINMC_K_RESIDENT, [&] {
+            return launch_resident(a, (int)c->res_gen.size(), 0, false, res_threads, lds, s);
+        }, s);
+    }
+    return e;
+}
+
+// Streamed colour passes for sweeps [i0, i0 + n) of the call on stream s.
+hipError_t enqueue_stream(spinmc_ctx* c, const SweepArgs& a, int i0, int n, int re,
+                          hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const int threads = c->sched.wg_threads > 0 ? std::min(c->sched.wg_threads, 512) : 256;
+    for (int i = i0; i < i0 + n && e == hipSuccess; ++i) {
+        const bool rec = re > 0 && ((i + 1) % re) == 0;
+        const int row = rec ? (i + 1) / re - 1 : -1;
+        e = timed(c, SPINMC_K_STREAM_PASS, [&] {
+            return launch_stream_pass(a, c->n_tiles, 0, i, -1, threads, a.tab_lds_bytes, s);
+        }, s);
+        if (e == hipSuccess)
+            e = timed(c, SPINMC_K_STREAM_PASS, [&] {
+                return launch_stream_pass(a, c->n_tiles, 1, i, row, threads, a.tab_lds_bytes, s);
+            }, s);
+        if (e == hipSuccess && rec && !c->stream_potts.empty())
+            e = launch_potts_hist_finalize(a, c->d_lists + c->off_rest,
+                                           (int)c->stream_potts.size(), row, s);
+    }
+    return e;
+}
+
+int ensure_side_streams(spinmc_ctx* c) {
+    if (c->cap[0]) return SPINMC_OK;
+    for (int k = 0; k < 2; ++k)
+        if (hipStreamCreateWithFlags(&c->cap[k], hipStreamNonBlocking) != hipSuccess)
+            return fail(SPINMC_E_DEVICE, "side stream creation failed");
+    for (int k = 0; k < 4; ++k)
+        if (hipEventCreateWithFlags(&c->cap_ev[k], hipEventDisableTiming) != hipSuccess)
+            return fail(SPINMC_E_DEVICE, "event creation failed");
+    return SPINMC_OK;
+}
+
+// One graph for a chunk of G unrecorded sweeps: the resident kernel on a
+// forked branch runs concurrently with the 2G streamed passes; the device
+// sweep counter advances by G at the join.
+int chunk_graph(spinmc_ctx* c, int G, hipGraphExec_t* out) {
+    auto it = c->graphs.find(G);
+    if (it != c->graphs.end()) {
+        *out = it->second;
+        return SPINMC_OK;
+    }
+    int rc0 = ensure_side_streams(c);
+    if (rc0) return rc0;
+    SweepArgs a = sweep_args(c, G, 0, nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap[0], hipStreamCaptureModeRelaxed);
+    const bool res = !c->res_chunk.empty() || !c->res_gen.empty();
+    if (e == hipSuccess && res) {
+        e = hipEventRecord(c->cap_ev[0], c->cap[0]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->cap[1], c->cap_ev[0], 0);
+        const bool prof = c->prof;
+        c->prof = false;
+        if (e == hipSuccess) e = enqueue_resident(c, a, c->cap[1]);
+        if (e == hipSuccess && c->n_tiles > 0) e = enqueue_stream(c, a, 0, G, 0, c->cap[0]);
+        c->prof = prof;
+        if (e == hipSuccess) e = hipEventRecord(c->cap_ev[1], c->cap[1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->cap[0], c->cap_ev[1], 0);
+    } else if (e == hipSuccess && c->n_tiles > 0) {
+        const bool prof = c->prof;
+        c->prof = false;
+        e = enqueue_stream(c, a, 0, G, 0, c->cap[0]);
+        c->prof = prof;
+    }
+    if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)G, c->cap[0]);
+    hipError_t e2 = hipStreamEndCapture(c->cap[0], &g);
+    if (e == hipSuccess) e = e2;
+    hipGraphExec_t ex = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    if (e != hipSuccess) return check_dev(c, e, "graph capture");
+    c->graphs[G] = ex;
+    *out = ex;
+    return SPINMC_OK;
+}
+
+int enqueue_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
+    const int mode = effective_mode(c);
+    int rc = prepare(c, mode);
+    if (rc) return rc;
+    hipError_t e = hipSuccess;
+    // Unrecorded, untimed calls replay cached graphs of whole chunks.
+    if (re == 0 && !c->prof && c->use_graphs) {
+        const int G = std::min(n, kGraphChunk);
+        const int full = n / G, rest = n - full * G;
+        hipGraphExec_t ex = nullptr;
+        rc = chunk_graph(c, G, &ex);
+        if (rc) return rc;
+        for (int k = 0; k < full && e == hipSuccess; ++k) e = hipGraphLaunch(ex, c->stream);
+        if (e == hipSuccess && rest > 0) {
+            rc = chunk_graph(c, rest, &ex);
+            if (rc) return rc;
+            e = hipGraphLaunch(ex, c->stream);
+        }
+        return check_dev(c, e, "sweep (graph)");
+    }
+    SweepArgs a = sweep_args(c, n, re, stats);
+    const int n_rec = re > 0 ? n / re : 0;
+    if (n_rec > 0 && c->n_tiles > 0) {
+        // stream-pass statistics accumulate with atomics: clear their rows
+        // first (resident replicas overwrite theirs)
+        e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
+    }
+    const bool res = !c->res_chunk.empty() || !c->res_gen.empty();
+    if (res && c->n_tiles > 0) {
+        // resident kernels on a side stream, concurrent with the streamed passes
+        rc = ensure_side_streams(c);
+        if (rc) return rc;
+        if (e == hipSuccess) e = hipEventRecord(c->cap_ev[2], c->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->cap[1], c->cap_ev[2], 0);
+        if (e == hipSuccess) e = enqueue_resident(c, a, c->cap[1]);
+        if (e == hipSuccess) e = enqueue_stream(c, a, 0, n, re, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(c->cap_ev[3], c->cap[1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->cap_ev[3], 0);
+    } else {
+        if (e == hipSuccess) e = enqueue_resident(c, a, c->stream);
+        if (e == hipSuccess && c->n_tiles > 0) e = enqueue_stream(c, a, 0, n, re, c->stream);
+    }
+    if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)n, c->stream);
+    return check_dev(c, e, "sweep");
+}
+
+}  // namespace
+
+// =========================================================== Cellular Potts
+namespace {
+
+CpmArgs cpm_args(spinmc_ctx* c, int32_t* stats) {
+    CpmArgs a{};
+    a.reps = c->d_reps;
+    a.tiles = c->d_tiles;
+    a.tab = c->d_tab;
+    a.lat = reinterpret_cast<int32_t*>(c->d_lat);
+    a.ctype = c->d_ctype;
+    a.target = c->d_target;
+    a.area = c->d_area;
+    a.snap = c->d_snap;
+    a.js = c->d_js;
+    a.t_base = c->d_t;
+    a.stats = stats;
+    a.key0 = (uint32_t)(c->seed & 0xffffffffu);
+    a.key1 = (uint32_t)(c->seed >> 32);
+    a.R = c->R;
+    a.width = c->width;
+    return a;
+}
+
+int cpm_build_tiles(spinmc_ctx* c) {
+    std::vector<TileDev> tiles;
+    for (int i = 0; i < c->R; ++i) {
+        const RepDev& r = c->reps[i].dev;
+        int rows = c->sched.tile_rows > 0 ? c->sched.tile_rows : ((4096 / r.Lx) & ~1);
+        rows = std::max(2, std::min(rows, r.Ly));
+        for (int y0 = 0; y0 < r.Ly; y0 += rows)
+            tiles.push_back(TileDev{i, y0, std::min(rows, r.Ly - y0), 0});
+    }
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && (int)tiles.size() != c->n_tiles) {
+        hipFree(c->d_tiles);
+        c->d_tiles = nullptr;
+        e = hipMalloc((void**)&c->d_tiles, sizeof(TileDev) * tiles.size());
+    }
+    if (e == hipSuccess)
+        e = hipMemcpy(c->d_tiles, tiles.data(), sizeof(TileDev) * tiles.size(),
+                      hipMemcpyHostToDevice);
+    c->n_tiles = (int)tiles.size();
+    c->tiles_rows = c->sched.tile_rows;
+    return check_dev(c, e, "CPM tiles");
+}
+
+int create_cpm(const spinmc_replica_desc* d, int n, uint64_t seed, void* stream,
+               spinmc_ctx** out) {
+    spinmc_ctx* c = new spinmc_ctx();
+    hipGetDevice(&c->device);
+    c->stream = (hipStream_t)stream;
+    c->seed = seed;
+    c->R = n;
+    c->width = 16;
+    c->cpm = true;
+    c->reps.resize(n);
+    size_t lat_off = 0, tab_off = 0, cell_off = 0, js_off = 0;
+    std::vector<uint32_t> tab;
+    std::vector<int8_t> ctype;
+    std::vector<int32_t> target, js;
+    for (int i = 0; i < n; ++i) {
+        HostRep& h = c->reps[i];
+        CpmFixed f;
+        int rc = cpm_fixed_point(d[i], i, f);
+        if (rc) {
+            delete c;
+            return rc;
+        }
+        h.d = d[i];
+        h.d.adhesion = nullptr;
+        h.d.cell_type = nullptr;
+        h.d.target_area = nullptr;
+        h.adh.assign(d[i].adhesion, d[i].adhesion + d[i].n_types * d[i].n_types);
+        h.ctype.assign(d[i].cell_type, d[i].cell_type + d[i].q + 1);
+        h.target.assign(d[i].target_area, d[i].target_area + d[i].q + 1);
+        h.T = f.T;
+        h.aux = f.K0;
+        RepDev& r = h.dev;
+        r.model = SPINMC_CPM;
+        r.Lx = d[i].Lx;
+        r.Ly = d[i].Ly;
+        r.W = d[i].Lx / 2;
+        r.q = d[i].q;
+        r.rid = d[i].rid;
+        r.n_types = d[i].n_types;
+        r.S = f.S;
+        r.LS = f.LS;
+        r.K1 = f.K1;
+        r.K0 = f.K0;
+        h.lat_bytes = (size_t)r.Lx * r.Ly * 4;
+        r.lat_off = (int64_t)(lat_off / 4);  // int32 elements
+        lat_off = align_up(lat_off + h.lat_bytes, kAlign);
+        r.tab_n = (int)f.T.size();
+        r.tab_off = (int)tab_off;
+        tab.resize(tab_off + 2 * f.T.size());
+        for (size_t k = 0; k < f.T.size(); ++k) {
+            tab[tab_off + k] = (uint32_t)(f.T[k] >> 16);
+            tab[tab_off + f.T.size() + k] = (uint32_t)(f.T[k] & 0xFFFFu);
+        }
+        tab_off += 2 * f.T.size();
+        c->max_tab_n = std::max(c->max_tab_n, r.tab_n);
+        r.cell_off = (int)cell_off;
+        ctype.insert(ctype.end(), h.ctype.begin(), h.ctype.end());
+        target.insert(target.end(), h.target.begin(), h.target.end());
+        cell_off += (size_t)r.q + 1;
+        r.js_off = (int)js_off;
+        js.insert(js.end(), f.JS.begin(), f.JS.end());
+        js_off += f.JS.size();
+        c->max_sites = std::max(c->max_sites, r.Lx * r.Ly);
+    }
+    c->total_cells = (int)cell_off;
+    c->lat_bytes = lat_off + 64;
+    std::vector<RepDev> rd(n);
+    for (int i = 0; i < n; ++i) rd[i] = c->reps[i].dev;
+    if (tab.empty()) tab.push_back(0);
+    auto A = [&](void** p, size_t b) { return hipMalloc(p, std::max<size_t>(b, 16)); };
+    hipError_t e = hipSuccess;
+    if ((e = A((void**)&c->d_lat, c->lat_bytes)) || (e = A((void**)&c->d_reps, sizeof(RepDev) * n)) ||
+        (e = A((void**)&c->d_tab, sizeof(uint32_t) * tab.size())) ||
+        (e = A((void**)&c->d_t, sizeof(uint64_t))) ||
+        (e = A((void**)&c->d_ctype, ctype.size())) ||
+        (e = A((void**)&c->d_target, sizeof(int32_t) * target.size())) ||
+        (e = A((void**)&c->d_area, sizeof(int32_t) * cell_off)) ||
+        (e = A((void**)&c->d_snap, sizeof(int32_t) * cell_off)) ||
+        (e = A((void**)&c->d_js, sizeof(int32_t) * js.size()))) {
+        free_all(c);
+        delete c;
+        hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? SPINMC_E_NOMEM : SPINMC_E_DEVICE,
+                    "create: device allocation failed: %s", hipGetErrorString(e));
+    }
+    const uint64_t zero = 0;
+    if ((e = hipMemcpy(c->d_reps, rd.data(), sizeof(RepDev) * n, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_tab, tab.data(), sizeof(uint32_t) * tab.size(),
+                       hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_t, &zero, sizeof zero, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_ctype, ctype.data(), ctype.size(), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_target, target.data(), sizeof(int32_t) * target.size(),
+                       hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_js, js.data(), sizeof(int32_t) * js.size(), hipMemcpyHostToDevice)) ||
+        (e = hipMemset(c->d_lat, 0, c->lat_bytes))) {
+        free_all(c);
+        delete c;
+        return fail(SPINMC_E_DEVICE, "create: upload failed: %s", hipGetErrorString(e));
+    }
+    int rc = cpm_build_tiles(c);
+    if (rc == SPINMC_OK) {
+        CpmArgs a = cpm_args(c, nullptr);
+        e = launch_cpm_area_recount(a, c->n_tiles, c->total_cells, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        rc = check_dev(c, e, "create: area count");
+    }
+    if (rc) {
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return SPINMC_OK;
+}
+
+int cpm_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes) {
+    const HostRep& h = c->reps[r];
+    const size_t n = (size_t)h.dev.Lx * h.dev.Ly;
+    if (bytes != n * 4) return fail(SPINMC_E_INVALID, "set_state: wrong byte count");
+    const int32_t* v = (const int32_t*)host;
+    for (size_t i = 0; i < n; ++i)
+        if (v[i] < 0 || v[i] > h.dev.q)
+            return fail(SPINMC_E_INVALID, "set_state: cell id out of range");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(reinterpret_cast<int32_t*>(c->d_lat) + h.dev.lat_off, host, bytes,
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        CpmArgs a = cpm_args(c, nullptr);
+        e = launch_cpm_area_recount(a, c->n_tiles, c->total_cells, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return check_dev(c, e, "set_state");
+}
+
+int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
+    const HostRep& h = c->reps[r];
+    if (bytes != (size_t)h.dev.Lx * h.dev.Ly * 4)
+        return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(host, reinterpret_cast<int32_t*>(c->d_lat) + h.dev.lat_off, bytes,
+                      hipMemcpyDeviceToHost);
+    return check_dev(c, e, "get_state");
+}
+
+int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
+    if (c->tiles_rows != c->sched.tile_rows) {
+        int rc = cpm_build_tiles(c);
+        if (rc) return rc;
+    }
+    CpmArgs a = cpm_args(c, stats);
+    const size_t tab_bytes = align_up((size_t)8 * std::max(c->max_tab_n, 1), 16);
+    const int threads = c->sched.wg_threads > 0 ? std::min(c->sched.wg_threads, 256) : 256;
+    hipError_t e = hipSuccess;
+    const int n_rec = re > 0 ? n / re : 0;
+    if (n_rec > 0) e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        for (int col = 0; col < 4 && e == hipSuccess; ++col) {
+            e = launch_cpm_snapshot(a, c->total_cells, c->stream);
+            if (e == hipSuccess)
+                e = timed(c, SPINMC_K_CPM_PASS, [&] {
+                    return launch_cpm_pass(a, c->n_tiles, col, i, threads, tab_bytes, c->stream);
+                }, c->stream);
+        }
+        if (e == hipSuccess && re > 0 && ((i + 1) % re) == 0)
+            e = launch_cpm_stats(a, c->n_tiles, (i + 1) / re - 1, c->stream);
+    }
+    if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)n, c->stream);
+    return check_dev(c, e, "sweep");
+}
+
+int cpm_measure(spinmc_ctx* c, int32_t* stats, double* obs) {
+    CpmArgs a = cpm_args(c, stats);
+    hipError_t e = launch_fill_i32(stats, (size_t)c->R * c->width, 0, c->stream);
+    if (e == hipSuccess) e = launch_cpm_stats(a, c->n_tiles, 0, c->stream);
+    if (e == hipSuccess && obs)
+        e = launch_observables(c->d_reps, c->R, stats, c->width, obs, c->stream);
+    return check_dev(c, e, "measure");
+}
+
+}  // namespace

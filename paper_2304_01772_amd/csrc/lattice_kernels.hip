@@ -1,0 +1,754 @@
+// Ising and q-state Potts checkerboard Metropolis kernels for gfx950.
+//
+// Data layout (per replica): two int8 colour planes P0, P1, each Ly rows of
+// W = Lx/2 bytes; site (y, x) lives in P[(x+y)&1][y][x>>1].  Ising stores
+// the spin bit u = (s + 1)/2, Potts the label.  A colour pass updates every
+// byte of P_c from its own value and four neighbours in P_{1-c}: the same
+// column in rows y-1, y, y+1, and column j-1 (if x is even) or j+1 (if x is
+// odd) in row y.  Colour-0 sites go first (Related Work, Fig. 1: sites of one
+// colour have no interacting neighbour of that colour, so the pass is
+// embarrassingly parallel).
+//
+// The fast ("chunk") path gives each lane 16 consecutive bytes of a plane row
+// (one dwordx4 load per plane row), builds neighbour sums with byte-SWAR
+// arithmetic, and consumes one 16-bit Philox prefix per site for the
+// Metropolis test of Algorithm 1 (Ising: 8 sites per Philox4x32-10 call;
+// Potts: 16-bit proposal + 16-bit accept prefix, 4 sites per call).  The low
+// 16 bits of the uniform word are drawn from the fallback stream only when
+// the prefix ties the threshold's high half (probability 2^-16), so the
+// result equals comparing a full 32-bit uniform word with the FP64-built
+// threshold T = ceil(2^32 exp(-beta dE)).
+#include "spinmc_internal.hpp"
+
+namespace spinmc {
+
+namespace {
+
+__device__ __forceinline__ uint32_t sad_u8(uint32_t a, uint32_t acc) {
+    return __builtin_amdgcn_sad_u8(a, 0u, acc);
+}
+
+// Wave + workgroup sum of up to 4 ints, result valid in thread 0.
+template <int N>
+__device__ __forceinline__ void block_sum(int (&v)[N], int* lds /* >= 16*N */) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] += __shfl_xor(v[i], o, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) lds[wave * N + i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nw; ++w) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] += lds[w * N + i];
+        }
+    }
+    __syncthreads();
+}
+
+struct IsingAcc {
+    int M, Bx, By;
+};
+
+// ---------------------------------------------------------------- Ising
+// One 16-site chunk of plane row y starting at byte j0 (j0 % 16 == 0,
+// W % 16 == 0).  PAR = (y + c) & 1 selects which horizontal neighbour the
+// shifted byte stream supplies.  thr: LDS [18 hi | 18 lo].
+template <int PAR, bool REC>
+__device__ __forceinline__ void ising_chunk(uint8_t* own, const uint8_t* oth, int W, int y, int ym,
+                                            int yp, int j0, uint32_t p, uint32_t rid, uint32_t k0,
+                                            uint32_t k1, const uint32_t* thr, IsingAcc& acc) {
+    const size_t ro = (size_t)y * W;
+    const uint4 o = *reinterpret_cast<const uint4*>(own + ro + j0);
+    const uint4 m = *reinterpret_cast<const uint4*>(oth + ro + j0);
+    const uint4 U = *reinterpret_cast<const uint4*>(oth + (size_t)ym * W + j0);
+    const uint4 D = *reinterpret_cast<const uint4*>(oth + (size_t)yp * W + j0);
+    uint32_t e;
+    if (PAR == 0) {
+        const int je = (j0 == 0) ? W - 4 : j0 - 4;
+        e = *reinterpret_cast<const uint32_t*>(oth + ro + je);
+    } else {
+        const int je = (j0 + 16 == W) ? 0 : j0 + 16;
+        e = *reinterpret_cast<const uint32_t*>(oth + ro + je);
+    }
+    const uint32_t ov[4] = {o.x, o.y, o.z, o.w};
+    const uint32_t mv[4] = {m.x, m.y, m.z, m.w};
+    const uint32_t Uv[4] = {U.x, U.y, U.z, U.w};
+    const uint32_t Dv[4] = {D.x, D.y, D.z, D.w};
+    uint32_t sv[4];
+    if (PAR == 0) {
+        sv[0] = __builtin_amdgcn_alignbyte(mv[0], e, 3);
+        sv[1] = __builtin_amdgcn_alignbyte(mv[1], mv[0], 3);
+        sv[2] = __builtin_amdgcn_alignbyte(mv[2], mv[1], 3);
+        sv[3] = __builtin_amdgcn_alignbyte(mv[3], mv[2], 3);
+    } else {
+        sv[0] = __builtin_amdgcn_alignbyte(mv[1], mv[0], 1);
+        sv[1] = __builtin_amdgcn_alignbyte(mv[2], mv[1], 1);
+        sv[2] = __builtin_amdgcn_alignbyte(mv[3], mv[2], 1);
+        sv[3] = __builtin_amdgcn_alignbyte(e, mv[3], 1);
+    }
+    uint32_t idx[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t nx = mv[k] + sv[k];
+        const uint32_t ny = Uv[k] + Dv[k];
+        idx[k] = (ov[k] << 3) + ov[k] + (nx << 1) + nx + ny;  // 9u + 3nx + ny per byte
+    }
+    const uint32_t kb = (uint32_t)(ro + j0);  // within-colour index of the first site
+    uint32_t w[8];
+    philox4x32_10(kb >> 3, p, rid, kTagMain, k0, k1, &w[0]);
+    philox4x32_10((kb >> 3) + 1u, p, rid, kTagMain, k0, k1, &w[4]);
+    uint32_t flip[4] = {0u, 0u, 0u, 0u};
+    uint32_t amb = 0u;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t cls = (idx[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        const int32_t th = (int32_t)thr[cls];
+        const int32_t r = (int32_t)((w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu);
+        const int32_t d = r - th;
+        flip[j >> 2] |= ((uint32_t)(d >> 31)) & (1u << (8 * (j & 3)));
+        amb |= (d == 0 ? 1u : 0u) << j;
+    }
+    if (amb) {
+        // The prefix equals the threshold's high half: the low halves decide.
+        for (int j = 0; j < 16; ++j) {
+            if (!((amb >> j) & 1u)) continue;
+            const uint32_t cls = (idx[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+            const uint32_t lo = thr[kIsingClasses + cls];
+            if (lo == 0u) continue;
+            uint32_t f[4];
+            philox4x32_10(kb + (uint32_t)j, p, rid, kTagFallback, k0, k1, f);
+            if ((f[0] & 0xFFFFu) < lo) flip[j >> 2] |= 1u << (8 * (j & 3));
+        }
+    }
+    uint32_t nv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) nv[k] = ov[k] ^ flip[k];
+    *reinterpret_cast<uint4*>(own + ro + j0) = make_uint4(nv[0], nv[1], nv[2], nv[3]);
+    if (REC) {
+        // Colour-1 pass of a recorded sweep: every bond has exactly one
+        // colour-1 end, so summing over the updated sites counts each once.
+        uint32_t up = 0u, dx = 0u, dy = 0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            up = sad_u8(nv[k], up);
+            up = sad_u8(mv[k], up);
+            dx = sad_u8((nv[k] ^ mv[k]) + (nv[k] ^ sv[k]), dx);
+            dy = sad_u8((nv[k] ^ Uv[k]) + (nv[k] ^ Dv[k]), dy);
+        }
+        acc.M += 2 * (int)up - 32;
+        acc.Bx += 32 - 2 * (int)dx;
+        acc.By += 32 - 2 * (int)dy;
+    }
+}
+
+// ---------------------------------------------------------------- Potts
+struct PottsAcc {
+    int Nx, Ny, S;
+};
+
+// Byte-wise "not equal" flags (bit 7 of each byte) for labels < 128.
+__device__ __forceinline__ uint32_t ne_hi(uint32_t a, uint32_t b) {
+    return ((a ^ b) + 0x7F7F7F7Fu) & 0x80808080u;
+}
+
+// 16-site Potts chunk.  thr: LDS [n hi | n lo], n = 9(2q-1).
+template <int PAR, bool REC>
+__device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, int W, int y, int ym,
+                                            int yp, int j0, uint32_t p, uint32_t rid, uint32_t k0,
+                                            uint32_t k1, const uint32_t* thr, int q, int ntab,
+                                            uint32_t lem_thr, PottsAcc& acc, int* lhist) {
+    const size_t ro = (size_t)y * W;
+    const uint4 o = *reinterpret_cast<const uint4*>(own + ro + j0);
+    const uint4 m = *reinterpret_cast<const uint4*>(oth + ro + j0);
+    const uint4 U = *reinterpret_cast<const uint4*>(oth + (size_t)ym * W + j0);
+    const uint4 D = *reinterpret_cast<const uint4*>(oth + (size_t)yp * W + j0);
+    uint32_t e;
+    if (PAR == 0) {
+        const int je = (j0 == 0) ? W - 4 : j0 - 4;
+        e = *reinterpret_cast<const uint32_t*>(oth + ro + je);
+    } else {
+        const int je = (j0 + 16 == W) ? 0 : j0 + 16;
+        e = *reinterpret_cast<const uint32_t*>(oth + ro + je);
+    }
+    const uint32_t ov[4] = {o.x, o.y, o.z, o.w};
+    const uint32_t mv[4] = {m.x, m.y, m.z, m.w};
+    const uint32_t Uv[4] = {U.x, U.y, U.z, U.w};
+    const uint32_t Dv[4] = {D.x, D.y, D.z, D.w};
+    uint32_t sv[4];
+    if (PAR == 0) {
+        sv[0] = __builtin_amdgcn_alignbyte(mv[0], e, 3);
+        sv[1] = __builtin_amdgcn_alignbyte(mv[1], mv[0], 3);
+        sv[2] = __builtin_amdgcn_alignbyte(mv[2], mv[1], 3);
+        sv[3] = __builtin_amdgcn_alignbyte(mv[3], mv[2], 3);
+    } else {
+        sv[0] = __builtin_amdgcn_alignbyte(mv[1], mv[0], 1);
+        sv[1] = __builtin_amdgcn_alignbyte(mv[2], mv[1], 1);
+        sv[2] = __builtin_amdgcn_alignbyte(mv[3], mv[2], 1);
+        sv[3] = __builtin_amdgcn_alignbyte(e, mv[3], 1);
+    }
+    const uint32_t kb = (uint32_t)(ro + j0);
+    uint32_t w[16];
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        philox4x32_10((kb >> 2) + (uint32_t)b, p, rid, kTagMain, k0, k1, &w[4 * b]);
+    const uint32_t mq = (uint32_t)(q - 1);
+    // proposals s' = s + 1 + off (mod q), off uniform in [0, q-1)
+    uint32_t s2v[4] = {0u, 0u, 0u, 0u};
+    uint32_t lemrej = 0u;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t s = (ov[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        const uint32_t prod = (w[j] & 0xFFFFu) * mq;
+        lemrej |= ((prod & 0xFFFFu) < lem_thr ? 1u : 0u) << j;
+        uint32_t s2 = s + 1u + (prod >> 16);
+        s2 = (s2 >= (uint32_t)q) ? s2 - (uint32_t)q : s2;
+        s2v[j >> 2] |= s2 << (8 * (j & 3));
+    }
+    if (lemrej) {
+        for (int j = 0; j < 16; ++j) {
+            if (!((lemrej >> j) & 1u)) continue;
+            uint32_t f[4];
+            philox4x32_10(kb + (uint32_t)j, p, rid, kTagFallback, k0, k1, f);
+            const uint32_t s = (ov[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+            const uint32_t off = (uint32_t)(((uint64_t)f[1] * (uint64_t)mq) >> 32);
+            uint32_t s2 = s + 1u + off;
+            s2 = (s2 >= (uint32_t)q) ? s2 - (uint32_t)q : s2;
+            const int sh = 8 * (j & 3);
+            s2v[j >> 2] = (s2v[j >> 2] & ~(0xFFu << sh)) | (s2 << sh);
+        }
+    }
+    // dn + 4 = #ne(s) - #ne(s') + 4 per byte
+    uint32_t dn4[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t neo = (ne_hi(ov[k], mv[k]) >> 7) + (ne_hi(ov[k], sv[k]) >> 7) +
+                             (ne_hi(ov[k], Uv[k]) >> 7) + (ne_hi(ov[k], Dv[k]) >> 7);
+        const uint32_t nen = (ne_hi(s2v[k], mv[k]) >> 7) + (ne_hi(s2v[k], sv[k]) >> 7) +
+                             (ne_hi(s2v[k], Uv[k]) >> 7) + (ne_hi(s2v[k], Dv[k]) >> 7);
+        dn4[k] = neo + 0x04040404u - nen;
+    }
+    const uint32_t wq = (uint32_t)(2 * q - 1);
+    uint32_t acc_sel[4] = {0u, 0u, 0u, 0u};  // 0xFF in bytes that accept
+    uint32_t amb = 0u;
+    uint32_t cls_keep[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int sh = 8 * (j & 3);
+        const uint32_t s = (ov[j >> 2] >> sh) & 0xFFu;
+        const uint32_t s2 = (s2v[j >> 2] >> sh) & 0xFFu;
+        const uint32_t d4 = (dn4[j >> 2] >> sh) & 0xFFu;
+        const uint32_t cls = d4 * wq + s2 + (uint32_t)(q - 1) - s;
+        cls_keep[j] = cls;
+        const int32_t th = (int32_t)thr[cls];
+        const int32_t r = (int32_t)(w[j] >> 16);
+        const int32_t d = r - th;
+        acc_sel[j >> 2] |= ((uint32_t)(d >> 31)) & (0xFFu << sh);
+        amb |= (d == 0 ? 1u : 0u) << j;
+    }
+    if (amb) {
+        for (int j = 0; j < 16; ++j) {
+            if (!((amb >> j) & 1u)) continue;
+            const uint32_t lo = thr[ntab + cls_keep[j]];
+            if (lo == 0u) continue;
+            uint32_t f[4];
+            philox4x32_10(kb + (uint32_t)j, p, rid, kTagFallback, k0, k1, f);
+            if ((f[0] & 0xFFFFu) < lo) acc_sel[j >> 2] |= 0xFFu << (8 * (j & 3));
+        }
+    }
+    uint32_t nv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) nv[k] = (s2v[k] & acc_sel[k]) | (ov[k] & ~acc_sel[k]);
+    *reinterpret_cast<uint4*>(own + ro + j0) = make_uint4(nv[0], nv[1], nv[2], nv[3]);
+    if (REC) {
+        uint32_t nex = 0u, ney = 0u, ssum = 0u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            nex = sad_u8((ne_hi(nv[k], mv[k]) >> 7) + (ne_hi(nv[k], sv[k]) >> 7), nex);
+            ney = sad_u8((ne_hi(nv[k], Uv[k]) >> 7) + (ne_hi(nv[k], Dv[k]) >> 7), ney);
+            ssum = sad_u8(nv[k], ssum);
+            ssum = sad_u8(mv[k], ssum);
+        }
+        acc.Nx += 32 - (int)nex;
+        acc.Ny += 32 - (int)ney;
+        acc.S += (int)ssum;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            atomicAdd(&lhist[(nv[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1);
+            atomicAdd(&lhist[(mv[j >> 2] >> (8 * (j & 3))) & 0xFFu], 1);
+        }
+    }
+}
+
+// ------------------------------------------------- tile-level iteration
+// Rows [y0, y0+rows) of plane c (y0, rows even).  Rows are visited by parity
+// so that PAR is uniform across a wave.
+template <int MODEL, bool REC>
+__device__ __forceinline__ void run_tile(uint8_t* planes, int W, int Ly, int y0, int rows, int c,
+                                         uint32_t p, uint32_t rid, uint32_t k0, uint32_t k1,
+                                         const uint32_t* thr, int q, int ntab, uint32_t lem_thr,
+                                         IsingAcc& ia, PottsAcc& pa, int* lhist) {
+    uint8_t* own = planes + (size_t)c * Ly * W;
+    const uint8_t* oth = planes + (size_t)(1 - c) * Ly * W;
+    const int cpr = W >> 4;
+    const int half = rows >> 1;
+    const int items = half * cpr;
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+        const int yf = y0 + ((par ^ c) & 1);
+        for (int it = threadIdx.x; it < items; it += blockDim.x) {
+            const int r = it / cpr;
+            const int j0 = (it - r * cpr) << 4;
+            const int y = yf + 2 * r;
+            const int ym = (y == 0) ? Ly - 1 : y - 1;
+            const int yp = (y + 1 == Ly) ? 0 : y + 1;
+            if (MODEL == kModelIsing) {
+                if (par == 0)
+                    ising_chunk<0, REC>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, ia);
+                else
+                    ising_chunk<1, REC>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, ia);
+            } else {
+                if (par == 0)
+                    potts_chunk<0, REC>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, q, ntab,
+                                        lem_thr, pa, lhist);
+                else
+                    potts_chunk<1, REC>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, q, ntab,
+                                        lem_thr, pa, lhist);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void load_table(const uint32_t* tab, const RepDev& R, uint32_t* lthr) {
+    const int n2 = 2 * R.tab_n;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) lthr[i] = tab[R.tab_off + i];
+}
+
+__device__ __forceinline__ uint32_t lemire_threshold(int q) {
+    return 65536u % (uint32_t)(q - 1);
+}
+
+// XCD-aware block order: consecutive logical units land on one XCD (blocks
+// are dispatched round-robin over the 8 XCDs), so neighbouring row tiles of a
+// replica share that XCD's L2.
+__device__ __forceinline__ int logical_block(int n) {
+    const int b = blockIdx.x;
+    if ((n & 7) != 0) return b;
+    return (b & 7) * (n >> 3) + (b >> 3);
+}
+
+
+}  // namespace
+
+// ---------------------------------------------------------------- kernels
+// One colour pass over every row tile of every Ising/Potts replica.
+__global__ void __launch_bounds__(512) k_stream_pass(SweepArgs a, int c, int sweep_off,
+                                                     int rec_row) {
+    extern __shared__ uint32_t lthr[];  // [2 * tab_n] thresholds of this tile's replica
+    __shared__ int lhist[kMaxPottsQ];
+    __shared__ int lred[64];
+    const TileDev T = a.tiles[logical_block(a.n_units)];
+    const RepDev R = a.reps[T.rep];
+    load_table(a.tab, R, lthr);
+    const bool rec = (rec_row >= 0) && (c == 1);
+    if (R.model == kModelPotts && rec)
+        for (int i = threadIdx.x; i < R.q; i += blockDim.x) lhist[i] = 0;
+    __syncthreads();
+    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
+    const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
+    uint8_t* planes = a.lat + R.lat_off;
+    IsingAcc ia{0, 0, 0};
+    PottsAcc pa{0, 0, 0};
+    if (R.model == kModelIsing) {
+        if (rec)
+            run_tile<kModelIsing, true>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0,
+                                        a.key1, lthr, 2, 0, 0u, ia, pa, lhist);
+        else
+            run_tile<kModelIsing, false>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0,
+                                         a.key1, lthr, 2, 0, 0u, ia, pa, lhist);
+    } else {
+        const uint32_t lt = lemire_threshold(R.q);
+        if (rec)
+            run_tile<kModelPotts, true>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0,
+                                        a.key1, lthr, R.q, R.tab_n, lt, ia, pa, lhist);
+        else
+            run_tile<kModelPotts, false>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0,
+                                         a.key1, lthr, R.q, R.tab_n, lt, ia, pa, lhist);
+    }
+    if (rec) {
+        int v[3];
+        if (R.model == kModelIsing) {
+            v[0] = ia.M; v[1] = ia.Bx; v[2] = ia.By;
+        } else {
+            v[0] = pa.Nx; v[1] = pa.Ny; v[2] = pa.S;
+        }
+        block_sum<3>(v, lred);
+        int32_t* row = a.stats + ((size_t)rec_row * a.R + T.rep) * a.width;
+        if (threadIdx.x == 0) {
+            atomicAdd(&row[0], v[0]);
+            atomicAdd(&row[1], v[1]);
+            atomicAdd(&row[2], v[2]);
+        }
+        if (R.model == kModelPotts) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < R.q; i += blockDim.x)
+                if (lhist[i]) atomicAdd(&a.hist[R.hist_off + i], lhist[i]);
+        }
+    }
+}
+
+// nmax of each Potts replica from its histogram; clears the histogram.
+__global__ void k_potts_hist_finalize(SweepArgs a, const int32_t* list, int n, int rec_row) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int r = list[i];
+    const RepDev R = a.reps[r];
+    int mx = 0;
+    for (int k = 0; k < R.q; ++k) {
+        const int v = a.hist[R.hist_off + k];
+        mx = v > mx ? v : mx;
+        a.hist[R.hist_off + k] = 0;
+    }
+    a.stats[((size_t)rec_row * a.R + r) * a.width + 3] = mx;
+}
+
+// ------------------------------------------------------ generic (any L)
+namespace {
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// One site of colour c, within-colour index k, in planes (LDS or global).
+__device__ __forceinline__ void generic_site(int model, uint8_t* planes, int W, int Ly, int c,
+                                             int k, uint32_t p, uint32_t rid, uint32_t k0,
+                                             uint32_t k1, const uint32_t* thr, int q, int ntab) {
+    const int y = k / W;
+    const int j = k - y * W;
+    const int off = (y + c) & 1;
+    uint8_t* own = planes + (size_t)c * Ly * W;
+    const uint8_t* oth = planes + (size_t)(1 - c) * Ly * W;
+    const int ym = wrapi(y - 1, Ly), yp = wrapi(y + 1, Ly);
+    const int js = wrapi(off ? j + 1 : j - 1, W);
+    const uint32_t s = own[(size_t)y * W + j];
+    const uint32_t a0 = oth[(size_t)y * W + j], a1 = oth[(size_t)y * W + js];
+    const uint32_t b0 = oth[(size_t)ym * W + j], b1 = oth[(size_t)yp * W + j];
+    uint32_t w[4];
+    if (model == kModelIsing) {
+        philox4x32_10((uint32_t)k >> 3, p, rid, kTagMain, k0, k1, w);
+        const uint32_t h = (uint32_t)k & 7u;
+        const uint32_t r = (w[h >> 1] >> (16 * (h & 1))) & 0xFFFFu;
+        const uint32_t cls = 9u * s + 3u * (a0 + a1) + (b0 + b1);
+        const uint32_t hi = thr[cls];
+        bool acc = r < hi;
+        if (r == hi && thr[kIsingClasses + cls] != 0u) {
+            uint32_t f[4];
+            philox4x32_10((uint32_t)k, p, rid, kTagFallback, k0, k1, f);
+            acc = (f[0] & 0xFFFFu) < thr[kIsingClasses + cls];
+        }
+        if (acc) own[(size_t)y * W + j] = (uint8_t)(s ^ 1u);
+    } else {
+        philox4x32_10((uint32_t)k >> 2, p, rid, kTagMain, k0, k1, w);
+        const uint32_t word = w[k & 3];
+        const uint32_t mq = (uint32_t)(q - 1);
+        const uint32_t prod = (word & 0xFFFFu) * mq;
+        uint32_t off2 = prod >> 16;
+        uint32_t f[4];
+        bool have_f = false;
+        if ((prod & 0xFFFFu) < 65536u % mq) {
+            philox4x32_10((uint32_t)k, p, rid, kTagFallback, k0, k1, f);
+            have_f = true;
+            off2 = (uint32_t)(((uint64_t)f[1] * (uint64_t)mq) >> 32);
+        }
+        uint32_t s2 = s + 1u + off2;
+        s2 = s2 >= (uint32_t)q ? s2 - (uint32_t)q : s2;
+        const int dn = (int)(a0 == s2) + (int)(a1 == s2) + (int)(b0 == s2) + (int)(b1 == s2) -
+                       (int)(a0 == s) - (int)(a1 == s) - (int)(b0 == s) - (int)(b1 == s);
+        const uint32_t cls = (uint32_t)(dn + 4) * (uint32_t)(2 * q - 1) + s2 + (uint32_t)(q - 1) - s;
+        const uint32_t hi = thr[cls];
+        const uint32_t r = word >> 16;
+        bool acc = r < hi;
+        if (r == hi && thr[ntab + cls] != 0u) {
+            if (!have_f) philox4x32_10((uint32_t)k, p, rid, kTagFallback, k0, k1, f);
+            acc = (f[0] & 0xFFFFu) < thr[ntab + cls];
+        }
+        if (acc) own[(size_t)y * W + j] = (uint8_t)s2;
+    }
+}
+
+__device__ __forceinline__ uint32_t site_at(const uint8_t* planes, int W, int Ly, int y, int x) {
+    return planes[(size_t)((x + y) & 1) * Ly * W + (size_t)y * W + (x >> 1)];
+}
+
+// Integer statistics of a whole lattice (Ising: M, Bx, By; Potts: Nx, Ny, S
+// and the label histogram into hist).  Thread-strided over natural sites.
+__device__ __forceinline__ void lattice_stats(int model, const uint8_t* planes, int Lx, int Ly,
+                                              int W, int n0, int n1, int (&v)[3], int* hist) {
+    for (int n = n0 + (int)threadIdx.x; n < n1; n += blockDim.x) {
+        const int y = n / Lx, x = n - y * Lx;
+        const int s = (int)site_at(planes, W, Ly, y, x);
+        const int r = (int)site_at(planes, W, Ly, y, x + 1 == Lx ? 0 : x + 1);
+        const int d = (int)site_at(planes, W, Ly, y + 1 == Ly ? 0 : y + 1, x);
+        if (model == kModelIsing) {
+            const int ss = 2 * s - 1;
+            v[0] += ss;
+            v[1] += ss * (2 * r - 1);
+            v[2] += ss * (2 * d - 1);
+        } else {
+            v[0] += (s == r);
+            v[1] += (s == d);
+            v[2] += s;
+            atomicAdd(&hist[s], 1);
+        }
+    }
+}
+
+}  // namespace
+
+// Resident kernel: one workgroup owns one replica for the whole call, with
+// both planes in LDS.  CHUNK selects the 16-byte SWAR path (W % 16 == 0).
+template <bool CHUNK>
+__global__ void __launch_bounds__(1024) k_resident(SweepArgs a) {
+    // dynamic LDS: [thresholds (tab_lds_bytes) | plane 0 | plane 1]
+    extern __shared__ __align__(16) uint8_t dyn[];
+    uint32_t* lthr = reinterpret_cast<uint32_t*>(dyn);
+    uint8_t* lds = dyn + a.tab_lds_bytes;
+    __shared__ int lhist[kMaxPottsQ];
+    __shared__ int lred[64];
+    const int rep = a.rep_list[blockIdx.x];
+    const RepDev R = a.reps[rep];
+    const int plane = R.Ly * R.W;
+    const int bytes = 2 * plane;
+    uint8_t* g = a.lat + R.lat_off;
+    // load the lattice (16-byte granules where possible)
+    if ((bytes & 15) == 0) {
+        for (int i = threadIdx.x; i < (bytes >> 4); i += blockDim.x)
+            reinterpret_cast<uint4*>(lds)[i] = reinterpret_cast<const uint4*>(g)[i];
+    } else {
+        for (int i = threadIdx.x; i < bytes; i += blockDim.x) lds[i] = g[i];
+    }
+    load_table(a.tab, R, lthr);
+    __syncthreads();
+    const uint64_t t0 = *a.t_base;
+    const uint32_t lt = (R.model == kModelPotts) ? lemire_threshold(R.q) : 0u;
+    for (int i = 0; i < a.n_sweeps; ++i) {
+        const uint64_t t = t0 + (uint64_t)i;
+        const bool rec = a.record_every > 0 && ((i + 1) % a.record_every) == 0;
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
+            if (CHUNK) {
+                IsingAcc ia{0, 0, 0};
+                PottsAcc pa{0, 0, 0};
+                if (R.model == kModelIsing)
+                    run_tile<kModelIsing, false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0,
+                                                 a.key1, lthr, 2, 0, 0u, ia, pa, lhist);
+                else
+                    run_tile<kModelPotts, false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0,
+                                                 a.key1, lthr, R.q, R.tab_n, lt, ia, pa, lhist);
+            } else {
+                for (int k = threadIdx.x; k < plane; k += blockDim.x)
+                    generic_site(R.model, lds, R.W, R.Ly, c, k, p, R.rid, a.key0, a.key1, lthr,
+                                 R.q, R.tab_n);
+            }
+            __syncthreads();
+        }
+        if (rec) {
+            if (R.model == kModelPotts) {
+                for (int k = threadIdx.x; k < R.q; k += blockDim.x) lhist[k] = 0;
+                __syncthreads();
+            }
+            int v[3] = {0, 0, 0};
+            lattice_stats(R.model, lds, R.Lx, R.Ly, R.W, 0, R.Lx * R.Ly, v, lhist);
+            block_sum<3>(v, lred);
+            int32_t* row = a.stats + ((size_t)((i + 1) / a.record_every - 1) * a.R + rep) * a.width;
+            if (threadIdx.x == 0) {
+                row[0] = v[0];
+                row[1] = v[1];
+                row[2] = v[2];
+                int mx = 0;
+                if (R.model == kModelPotts)
+                    for (int k = 0; k < R.q; ++k) mx = lhist[k] > mx ? lhist[k] : mx;
+                row[3] = mx;
+                for (int k = 4; k < a.width; ++k) row[k] = 0;
+            }
+            __syncthreads();
+        }
+    }
+    if ((bytes & 15) == 0) {
+        for (int i = threadIdx.x; i < (bytes >> 4); i += blockDim.x)
+            reinterpret_cast<uint4*>(g)[i] = reinterpret_cast<const uint4*>(lds)[i];
+    } else {
+        for (int i = threadIdx.x; i < bytes; i += blockDim.x) g[i] = lds[i];
+    }
+}
+
+// Initial state from the init stream: natural index n, block n >> 2, word n & 3.
+__global__ void k_init(const RepDev* reps, const int32_t* list, uint8_t* lat, uint32_t k0,
+                       uint32_t k1) {
+    const RepDev R = reps[list[blockIdx.y]];
+    const int N = R.Lx * R.Ly;
+    uint8_t* planes = lat + R.lat_off;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; 4 * b < N; b += gridDim.x * blockDim.x) {
+        uint32_t w[4];
+        philox4x32_10((uint32_t)b, 0u, R.rid, kTagInit, k0, k1, w);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int n = 4 * b + i;
+            if (n >= N) break;
+            const int y = n / R.Lx, x = n - y * R.Lx;
+            uint8_t v;
+            if (R.model == kModelIsing)
+                v = (w[i] < 0x80000000u) ? 1 : 0;
+            else
+                v = (uint8_t)(((uint64_t)w[i] * (uint64_t)R.q) >> 32);
+            planes[(size_t)((x + y) & 1) * R.Ly * R.W + (size_t)y * R.W + (x >> 1)] = v;
+        }
+    }
+}
+
+// Statistics of the current state: grid (tiles of natural sites, replicas).
+__global__ void k_measure(const RepDev* reps, const int32_t* list, const uint8_t* lat,
+                          int32_t* stats, int32_t* hist, int width) {
+    __shared__ int lred[64];
+    const int r = list[blockIdx.y];
+    const RepDev R = reps[r];
+    const int N = R.Lx * R.Ly;
+    const int per = 4096;
+    const int n0 = blockIdx.x * per;
+    if (n0 >= N) return;
+    const int n1 = min(N, n0 + per);
+    int v[3] = {0, 0, 0};
+    lattice_stats(R.model, lat + R.lat_off, R.Lx, R.Ly, R.W, n0, n1, v, hist + R.hist_off);
+    block_sum<3>(v, lred);
+    if (threadIdx.x == 0) {
+        atomicAdd(&stats[(size_t)r * width + 0], v[0]);
+        atomicAdd(&stats[(size_t)r * width + 1], v[1]);
+        atomicAdd(&stats[(size_t)r * width + 2], v[2]);
+    }
+}
+
+__global__ void k_fill_i32(int32_t* p, size_t n, int32_t v) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_advance(uint64_t* t, uint64_t n) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *t += n;
+}
+
+// FP64 observables from integer statistics (one thread per replica).
+__global__ void k_observables(const RepDev* reps, int R, const int32_t* stats, int width,
+                              double* obs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    const RepDev D = reps[r];
+    const int32_t* s = stats + (size_t)r * width;
+    const double N = (double)D.Lx * (double)D.Ly;
+    double* o = obs + (size_t)r * 4;
+    if (D.model == kModelIsing) {
+        const double M = s[0], Bx = s[1], By = s[2];
+        const double H = -((double)D.Jx * Bx + (double)D.Jy * By + (double)D.h * M);
+        o[0] = H / N;
+        o[1] = fabs(M) / N;
+        o[2] = (M / N) * (M / N);
+        o[3] = M / N;
+    } else if (D.model == kModelPotts) {
+        const double Nx = s[0], Ny = s[1], S = s[2], nm = s[3];
+        const double H = -((double)D.Jx * (Nx + Ny) + (double)D.h * S);
+        o[0] = H / N;
+        o[1] = ((double)D.q * nm / N - 1.0) / ((double)D.q - 1.0);
+        o[2] = S / N;
+        o[3] = 0.0;
+    } else {
+        const uint64_t lo = (uint32_t)s[10], hi = (uint32_t)s[11];
+        const int64_t H = (int64_t)((hi << 32) | lo);
+        o[0] = (double)H / (double)D.S;
+        o[1] = 0.0;
+        o[2] = 0.0;
+        o[3] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_init(const RepDev* reps, const int32_t* list, int n, uint8_t* lat,
+                       uint32_t key0, uint32_t key1, int threads, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    dim3 grid(64, n);
+    hipLaunchKernelGGL(k_init, grid, dim3(threads), 0, s, reps, list, lat, key0, key1);
+    return hipGetLastError();
+}
+
+hipError_t resident_reserve_lds(size_t lds_bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_resident<true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_resident<false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    return e;
+}
+
+hipError_t launch_resident(const SweepArgs& a, int n_list, int model, bool chunk, int threads,
+                           size_t lds_bytes, hipStream_t s) {
+    (void)model;
+    if (n_list <= 0) return hipSuccess;
+    if (chunk)
+        hipLaunchKernelGGL(k_resident<true>, dim3(n_list), dim3(threads), lds_bytes, s, a);
+    else
+        hipLaunchKernelGGL(k_resident<false>, dim3(n_list), dim3(threads), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_pass(const SweepArgs& a, int n_tiles, int c, int sweep_off, int rec_row,
+                              int threads, size_t lds_tab_bytes, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stream_pass, dim3(n_tiles), dim3(threads), lds_tab_bytes, s, a, c,
+                       sweep_off, rec_row);
+    return hipGetLastError();
+}
+
+hipError_t launch_potts_hist_finalize(const SweepArgs& a, const int32_t* list, int n, int rec_row,
+                                      hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_potts_hist_finalize, dim3((n + 255) / 256), dim3(256), 0, s, a, list, n,
+                       rec_row);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    size_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(uint64_t* t, uint64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, t, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_measure(const RepDev* reps, const int32_t* list, int n, int max_sites,
+                          const uint8_t* lat, int32_t* stats, int32_t* hist, int width,
+                          hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    // grid.x covers the largest replica in 4096-site tiles; extra blocks exit
+    const int gx = (max_sites + 4095) / 4096;
+    hipLaunchKernelGGL(k_measure, dim3(gx, n), dim3(256), 0, s, reps, list, lat, stats, hist,
+                       width);
+    return hipGetLastError();
+}
+
+hipError_t launch_observables(const RepDev* reps, int R, const int32_t* stats, int width,
+                              double* obs, hipStream_t s) {
+    hipLaunchKernelGGL(k_observables, dim3((R + 127) / 128), dim3(128), 0, s, reps, R, stats,
+                       width, obs);
+    return hipGetLastError();
+}
+
+}  // namespace spinmc

@@ -1,0 +1,380 @@
+// Surrogate MLP 4-128-128-3 (SiLU) on gfx950 matrix cores.
+//
+// The network maps normalised Hamiltonian parameters (beta, Jx, Jy, h) to
+// normalised equilibrium observables; it steers the parameter optimisation
+// of the paper's optimisation experiments (Results) while Monte Carlo checks
+// its answers.  Weights and activations enter the matrix cores as BF16
+// (round to nearest even from FP32), products accumulate in FP32
+// (v_mfma_f32_16x16x16_bf16).  Rounding points (the oracle mirrors them):
+//   forward : xb = bf16(x); z1 = W1b xb + b1; h1 = bf16(silu z1);
+//             z2 = W2b h1 + b2; h2 = bf16(silu z2); y = W3b h2 + b3
+//   backward: dY = 2 w (y - t) / B (FP32);  dW3 = sum dY h2, dH2 = W3b^T dY;
+//             dz2 = dH2 silu'(z2); dz2b = bf16(dz2);
+//             dW2 = sum dz2b h1 (MFMA), dH1 = W2b^T dz2b (MFMA);
+//             dz1 = dH1 silu'(z1); dW1 = sum dz1 xb; dx = W1b^T dz1;
+//             bias gradients are FP32 sums of the unrounded dz.
+// Batch sums are per-workgroup partials reduced in a fixed order, so the
+// result does not depend on scheduling.  Each workgroup (4 waves) handles
+// 64 samples, 16 per wave.
+#include "spinmc_internal.hpp"
+
+namespace spinmc {
+
+namespace {
+
+constexpr int kIn = 4, kH = 128, kOut = 3;
+constexpr int oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH,
+              oW3 = ob2 + kH, ob3 = oW3 + kOut * kH, kNP = ob3 + kOut;
+constexpr int kSamplesPerWG = 64;
+constexpr int kPadK = 8;             // LDS row padding (bf16 elements) against bank conflicts
+constexpr int kS1 = 16 + kPadK;      // row stride of K=16 tiles
+constexpr int kS2 = kH + kPadK;      // row stride of K=128 tiles
+constexpr int kST = kSamplesPerWG + kPadK;  // row stride of sample-major transposed tiles
+
+typedef short short4v __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
+__device__ __forceinline__ float dsilu(float z) {
+    const float s = sigm(z);
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// 16x16 A fragment (rows r, k in [k0, k0+16)) from a row-major bf16 tile.
+__device__ __forceinline__ short4v frag(const uint16_t* base, int stride, int k0) {
+    const int l = threadIdx.x & 63;
+    const uint16_t* p = base + (l & 15) * stride + k0 + 4 * (l >> 4);
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    short4v r;
+    r[0] = (short)(v.x & 0xFFFFu);
+    r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xFFFFu);
+    r[3] = (short)(v.y >> 16);
+    return r;
+}
+
+__device__ __forceinline__ float4v mfma(short4v a, short4v b, float4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Weights into LDS as BF16, [out][in] rows (B^T layout of the matrix cores).
+__device__ void stage_weights(const float* P, uint16_t* w1, uint16_t* w2, uint16_t* w3,
+                              bool need_w2) {
+    for (int i = threadIdx.x; i < kH * 16; i += blockDim.x) {
+        const int n = i >> 4, k = i & 15;
+        w1[n * kS1 + k] = k < kIn ? f2bf(P[oW1 + n * kIn + k]) : (uint16_t)0;
+    }
+    if (need_w2)
+        for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) {
+            const int n = i >> 7, k = i & 127;
+            w2[n * kS2 + k] = f2bf(P[oW2 + n * kH + k]);
+        }
+    for (int i = threadIdx.x; i < 16 * kH; i += blockDim.x) {
+        const int n = i >> 7, k = i & 127;
+        w3[n * kS2 + k] = n < kOut ? f2bf(P[oW3 + n * kH + k]) : (uint16_t)0;
+    }
+}
+
+// Output layer for the wave's 16 samples from h2 (bf16 tile): lane holds
+// y[row = 4(l/16)+i][col = l%16] (cols >= 3 are padding).
+__device__ __forceinline__ float4v out_layer(const uint16_t* h2, const uint16_t* w3) {
+    float4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < kH / 16; ++kt) acc = mfma(frag(h2, kS2, 16 * kt), frag(w3, kS2, 16 * kt), acc);
+    return acc;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- forward
+__global__ void __launch_bounds__(256) k_mlp_fwd(const float* P, const float* x, int B, float* y,
+                                                 float* act) {
+    __shared__ __align__(16) uint16_t w1[kH * kS1];
+    __shared__ __align__(16) uint16_t w2[kH * kS2];
+    __shared__ __align__(16) uint16_t w3[16 * kS2];
+    __shared__ __align__(16) uint16_t xa[4][16 * kS1];
+    __shared__ __align__(16) uint16_t h1[4][16 * kS2];
+    __shared__ __align__(16) uint16_t h2[4][16 * kS2];
+    stage_weights(P, w1, w2, w3, true);
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int s0 = blockIdx.x * kSamplesPerWG + wave * 16;
+    for (int i = l; i < 16 * 16; i += 64) {
+        const int r = i >> 4, k = i & 15;
+        const int s = s0 + r;
+        xa[wave][r * kS1 + k] = (k < kIn && s < B) ? f2bf(x[(size_t)s * kIn + k]) : (uint16_t)0;
+    }
+    __syncthreads();
+    const int col = l & 15, rb = 4 * (l >> 4);
+    // layer 1 (K = 4, zero-padded to 16)
+#pragma unroll
+    for (int nt = 0; nt < kH / 16; ++nt) {
+        float4v acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mfma(frag(xa[wave], kS1, 0), frag(w1 + nt * 16 * kS1, kS1, 0), acc);
+        const int n = nt * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float z = acc[i] + P[ob1 + n];
+            const int s = s0 + rb + i;
+            if (act && s < B) act[(size_t)s * 2 * kH + n] = z;
+            h1[wave][(rb + i) * kS2 + n] = f2bf(silu(z));
+        }
+    }
+    __syncthreads();
+    // layer 2 (K = 128)
+#pragma unroll
+    for (int nt = 0; nt < kH / 16; ++nt) {
+        float4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < kH / 16; ++kt)
+            acc = mfma(frag(h1[wave], kS2, 16 * kt), frag(w2 + nt * 16 * kS2, kS2, 16 * kt), acc);
+        const int n = nt * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float z = acc[i] + P[ob2 + n];
+            const int s = s0 + rb + i;
+            if (act && s < B) act[(size_t)s * 2 * kH + kH + n] = z;
+            h2[wave][(rb + i) * kS2 + n] = f2bf(silu(z));
+        }
+    }
+    __syncthreads();
+    const float4v o = out_layer(h2[wave], w3);
+    if (col < kOut) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int s = s0 + rb + i;
+            if (s < B) y[(size_t)s * kOut + col] = o[i] + P[ob3 + col];
+        }
+    }
+}
+
+// -------------------------------------------------------------- backward
+// Per-workgroup partial gradients into part[wg][kNP + 1] (last: loss), and
+// input gradients dx (optional).
+__global__ void __launch_bounds__(256) k_mlp_bwd(const float* P, const float* x, const float* act,
+                                                 const float* t, const float* w, int B,
+                                                 float* part, float* dx) {
+    __shared__ __align__(16) uint16_t w2t[kH * kS2];      // W2^T: [in][out]
+    __shared__ __align__(16) uint16_t w3[16 * kS2];
+    __shared__ __align__(16) uint16_t w1[kH * kS1];
+    __shared__ __align__(16) uint16_t h1t[kH * kST];      // h1^T: [neuron][sample]
+    __shared__ __align__(16) uint16_t dz2t[kH * kST];     // dz2b^T: [neuron][sample]
+    __shared__ __align__(16) uint16_t dz2[kSamplesPerWG * kS2];  // dz2b: [sample][neuron]
+    __shared__ __align__(16) uint16_t h2[4][16 * kS2];
+    constexpr int kSZ = kH + 4;
+    __shared__ __align__(16) float dz1[kSamplesPerWG * kSZ];
+    __shared__ float dY[kSamplesPerWG][4];
+    __shared__ float red[256];
+    stage_weights(P, w1, nullptr, w3, false);
+    for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) {
+        const int o = i >> 7, in = i & 127;
+        w2t[in * kS2 + o] = f2bf(P[oW2 + o * kH + in]);
+    }
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int base = blockIdx.x * kSamplesPerWG;
+    // h1 (transposed) and h2 from the stored pre-activations
+    for (int i = threadIdx.x; i < kSamplesPerWG * kH; i += blockDim.x) {
+        const int s = i >> 7, n = i & 127;
+        const int gs = base + s;
+        float z1 = 0.f, z2 = 0.f;
+        if (gs < B) {
+            z1 = act[(size_t)gs * 2 * kH + n];
+            z2 = act[(size_t)gs * 2 * kH + kH + n];
+        }
+        h1t[n * kST + s] = gs < B ? f2bf(silu(z1)) : (uint16_t)0;
+        h2[s >> 4][(s & 15) * kS2 + n] = gs < B ? f2bf(silu(z2)) : (uint16_t)0;
+    }
+    __syncthreads();
+    // recompute y for the wave's samples, then dY and the loss
+    const int col = l & 15, rb = 4 * (l >> 4);
+    const int s0 = wave * 16;
+    const float4v o = out_layer(h2[wave], w3);
+    float lossp = 0.f;
+    if (col < 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int s = s0 + rb + i, gs = base + s;
+            float d = 0.f;
+            if (col < kOut && gs < B) {
+                const float yv = o[i] + P[ob3 + col];
+                const float e = yv - t[(size_t)gs * kOut + col];
+                lossp += w[col] * e * e;
+                d = 2.0f * w[col] * e / (float)B;
+            }
+            dY[s][col] = d;
+        }
+    }
+    red[threadIdx.x] = lossp;
+    __syncthreads();
+    // dH2 = W3b^T dY, dz2 = dH2 silu'(z2)
+    for (int i = threadIdx.x; i < kSamplesPerWG * kH; i += blockDim.x) {
+        const int s = i >> 7, n = i & 127;
+        const int gs = base + s;
+        float d = 0.f;
+        if (gs < B) {
+            float dh = 0.f;
+#pragma unroll
+            for (int j = 0; j < kOut; ++j) dh += dY[s][j] * bf2f(w3[j * kS2 + n]);
+            d = dh * dsilu(act[(size_t)gs * 2 * kH + kH + n]);
+        }
+        const uint16_t db = f2bf(d);
+        dz2t[n * kST + s] = db;
+        dz2[s * kS2 + n] = db;
+    }
+    __syncthreads();
+    float* pg = part + (size_t)blockIdx.x * (kNP + 1);
+    // dW2 = dz2b^T h1 (M = out neuron, N = in neuron, K = 64 samples): wave
+    // owns out-tiles 2*wave, 2*wave+1
+    for (int mt = 2 * wave; mt < 2 * wave + 2; ++mt) {
+#pragma unroll
+        for (int nt = 0; nt < kH / 16; ++nt) {
+            float4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kt = 0; kt < kSamplesPerWG / 16; ++kt)
+                acc = mfma(frag(dz2t + mt * 16 * kST, kST, 16 * kt),
+                           frag(h1t + nt * 16 * kST, kST, 16 * kt), acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                pg[oW2 + (mt * 16 + rb + i) * kH + nt * 16 + col] = acc[i];
+        }
+    }
+    // dW3, db3 (VALU): out j, neuron n
+    for (int i = threadIdx.x; i < kOut * kH; i += blockDim.x) {
+        const int j = i >> 7, n = i & 127;
+        float s = 0.f;
+        for (int q = 0; q < kSamplesPerWG; ++q) s += dY[q][j] * bf2f(h2[q >> 4][(q & 15) * kS2 + n]);
+        pg[oW3 + j * kH + n] = s;
+    }
+    if (threadIdx.x < kOut) {
+        float s = 0.f;
+        for (int q = 0; q < kSamplesPerWG; ++q) s += dY[q][threadIdx.x];
+        pg[ob3 + threadIdx.x] = s;
+    }
+    // db2 = sum of the unrounded dz2: recompute per neuron
+    if (threadIdx.x < kH) {
+        const int n = threadIdx.x;
+        float s = 0.f;
+        for (int q = 0; q < kSamplesPerWG; ++q) {
+            const int gs = base + q;
+            if (gs >= B) break;
+            float dh = 0.f;
+#pragma unroll
+            for (int j = 0; j < kOut; ++j) dh += dY[q][j] * bf2f(w3[j * kS2 + n]);
+            s += dh * dsilu(act[(size_t)gs * 2 * kH + kH + n]);
+        }
+        pg[ob2 + n] = s;
+    }
+    __syncthreads();
+    // dH1 = dz2b W2b (the wave's 16 samples), dz1 = dH1 silu'(z1)
+#pragma unroll
+    for (int nt = 0; nt < kH / 16; ++nt) {
+        float4v acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < kH / 16; ++kt)
+            acc = mfma(frag(dz2 + s0 * kS2, kS2, 16 * kt), frag(w2t + nt * 16 * kS2, kS2, 16 * kt),
+                       acc);
+        const int n = nt * 16 + col;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int s = s0 + rb + i, gs = base + s;
+            dz1[s * kSZ + n] = gs < B ? acc[i] * dsilu(act[(size_t)gs * 2 * kH + n]) : 0.f;
+        }
+    }
+    __syncthreads();
+    // dW1, db1 (VALU) and dx
+    for (int i = threadIdx.x; i < kH * (kIn + 1); i += blockDim.x) {
+        const int n = i / (kIn + 1), k = i % (kIn + 1);
+        float s = 0.f;
+        for (int q = 0; q < kSamplesPerWG; ++q) {
+            const int gs = base + q;
+            if (gs >= B) break;
+            const float xv = k < kIn ? bf2f(f2bf(x[(size_t)gs * kIn + k])) : 1.0f;
+            s += dz1[q * kSZ + n] * xv;
+        }
+        if (k < kIn)
+            pg[oW1 + n * kIn + k] = s;
+        else
+            pg[ob1 + n] = s;
+    }
+    if (dx) {
+        for (int i = threadIdx.x; i < kSamplesPerWG * kIn; i += blockDim.x) {
+            const int q = i >> 2, k = i & 3;
+            const int gs = base + q;
+            if (gs >= B) continue;
+            float s = 0.f;
+            for (int n = 0; n < kH; ++n) s += dz1[q * kSZ + n] * bf2f(w1[n * kS1 + k]);
+            dx[(size_t)gs * kIn + k] = s;
+        }
+    }
+    // loss partial
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) pg[kNP] = red[0] / (float)B;
+}
+
+// Fixed-order sum of the per-workgroup partials.
+__global__ void k_mlp_reduce(const float* part, int n_wg, float* grad, float* loss) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > kNP) return;
+    float s = 0.f;
+    for (int g = 0; g < n_wg; ++g) s += part[(size_t)g * (kNP + 1) + i];
+    if (i < kNP)
+        grad[i] = s;
+    else if (loss)
+        *loss = s;
+}
+
+__global__ void k_mlp_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1,
+                           float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1, vh = vi / c2;
+    p[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+hipError_t launch_mlp_forward(const float* params, const float* x, int B, float* y, float* act,
+                              hipStream_t s) {
+    const int g = (B + kSamplesPerWG - 1) / kSamplesPerWG;
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(g), dim3(256), 0, s, params, x, B, y, act);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_backward(const float* params, const float* x, const float* act,
+                               const float* t, const float* w, int B, float* grad, float* dx,
+                               float* loss, float* scratch, hipStream_t s) {
+    const int g = (B + kSamplesPerWG - 1) / kSamplesPerWG;
+    hipLaunchKernelGGL(k_mlp_bwd, dim3(g), dim3(256), 0, s, params, x, act, t, w, B, scratch, dx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kNP + 1 + 255) / 256), dim3(256), 0, s, scratch, g,
+                       grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v, int n, int step,
+                           float lr, float b1, float b2, float eps, hipStream_t s) {
+    const float c1 = (float)(1.0 - std::pow((double)b1, (double)step));
+    const float c2 = (float)(1.0 - std::pow((double)b2, (double)step));
+    hipLaunchKernelGGL(k_mlp_adam, dim3((n + 255) / 256), dim3(256), 0, s, params, grad, m, v, n,
+                       lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+int mlp_num_params() { return kNP; }
+int mlp_scratch_floats(int B) { return ((B + kSamplesPerWG - 1) / kSamplesPerWG) * (kNP + 1); }
+
+}  // namespace spinmc

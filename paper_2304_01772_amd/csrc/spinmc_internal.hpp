@@ -1,0 +1,142 @@
+// Internal types shared by the host runtime and the gfx950 kernels of
+// libspinmc.  Not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spinmc {
+
+constexpr int kModelIsing = 0;
+constexpr int kModelPotts = 1;
+constexpr int kModelCpm = 2;
+
+// Stream tags: the fourth Philox counter word.
+constexpr uint32_t kTagMain = 0u;
+constexpr uint32_t kTagFallback = 1u;
+constexpr uint32_t kTagInit = 2u;
+
+constexpr int kIsingClasses = 18;
+constexpr int kMaxPottsQ = 128;   // labels fit in 7 bits (SWAR equality test)
+constexpr int kMaxCpmTypes = 4;
+
+// Per-replica record, device visible.
+struct RepDev {
+    int32_t model, Lx, Ly, W;     // W = bytes per plane row = Lx/2 (Ising/Potts)
+    int32_t q;                    // Potts q; CPM number of cells
+    uint32_t rid;
+    int64_t lat_off;              // byte offset of the lattice in the lattice buffer
+    int32_t tab_off, tab_n;       // thresholds: hi16 at tab_off+i, lo16 at tab_off+tab_n+i
+    int32_t hist_off;             // Potts: histogram offset (int32 entries)
+    int32_t cell_off;             // CPM: offset of the per-cell arrays (entries)
+    int32_t n_types;              // CPM
+    int32_t K1;                   // CPM: k in [1,K1) from the table (entry k-1); [K1,K0) T=1
+    int32_t js_off;               // CPM: fixed-point adhesion table offset (int32)
+    int32_t S;                    // CPM: fixed-point scale
+    int32_t pad2;
+    int64_t K0;                   // CPM: k >= K0 has T = 0 (never accepted)
+    int64_t LS;                   // CPM: lambda * S
+    float Jx, Jy, h, pad1;
+    double beta;
+};
+
+// One unit of streamed work: rows [y0, y0 + rows) of both planes of a replica.
+struct TileDev {
+    int32_t rep, y0, rows, pad;
+};
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 bit
+// multiplies and xors; round r uses key + r * (0x9E3779B9, 0xBB67AE85).
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+// Launch parameters common to the lattice kernels.
+struct SweepArgs {
+    const RepDev* reps;
+    const TileDev* tiles;
+    const int32_t* rep_list;      // resident kernels: replicas handled (one per workgroup)
+    const uint32_t* tab;          // thresholds
+    uint8_t* lat;                 // lattices
+    const uint64_t* t_base;       // device sweep counter (start of the call)
+    int32_t* stats;               // [n_rec][R][width] or null
+    int32_t* hist;                // Potts histograms
+    uint32_t key0, key1;
+    int32_t R, width;
+    int32_t n_sweeps, record_every;
+    int32_t n_units;
+    int32_t tab_lds_bytes;        // bytes of LDS reserved for thresholds (multiple of 16)
+};
+
+// Host-side launchers implemented in the kernel translation units.
+hipError_t launch_init(const RepDev* reps, const int32_t* list, int n, uint8_t* lat,
+                       uint32_t key0, uint32_t key1, int threads, hipStream_t s);
+hipError_t launch_resident(const SweepArgs& a, int n_list, int model, bool chunk, int threads,
+                           size_t lds_bytes, hipStream_t s);
+// Allow the resident kernels up to lds_bytes of dynamic LDS (call outside capture).
+hipError_t resident_reserve_lds(size_t lds_bytes);
+hipError_t launch_stream_pass(const SweepArgs& a, int n_tiles, int c, int sweep_off, int rec_row,
+                              int threads, size_t lds_tab_bytes, hipStream_t s);
+hipError_t launch_persistent(const SweepArgs& a, const int32_t* wg_units, const int32_t* wg_ptr,
+                             int32_t* flags, int n_wg, int threads, hipStream_t s);
+hipError_t launch_potts_hist_finalize(const SweepArgs& a, const int32_t* list, int n, int rec_row,
+                                      hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);
+hipError_t launch_advance(uint64_t* t, uint64_t n, hipStream_t s);
+hipError_t launch_measure(const RepDev* reps, const int32_t* list, int n, int max_sites,
+                          const uint8_t* lat, int32_t* stats, int32_t* hist, int width,
+                          hipStream_t s);
+hipError_t launch_observables(const RepDev* reps, int R, const int32_t* stats, int width,
+                              double* obs, hipStream_t s);
+hipError_t launch_cov_grad(const RepDev* reps, int R, const int32_t* stats, int n_rec,
+                           int burn_in, int width, const double* gout, double* means,
+                           double* grads, double* dtheta, hipStream_t s);
+
+// CPM
+struct CpmArgs {
+    const RepDev* reps;
+    const TileDev* tiles;
+    const uint32_t* tab;
+    int32_t* lat;                 // cell ids (int32, natural layout)
+    const int8_t* ctype;
+    const int32_t* target;
+    int32_t* area;                // current areas
+    int32_t* snap;                // pass-start snapshot
+    const int32_t* js;            // fixed-point adhesion
+    const uint64_t* t_base;
+    int32_t* stats;
+    uint32_t key0, key1;
+    int32_t R, width;
+};
+hipError_t launch_cpm_pass(const CpmArgs& a, int n_tiles, int c, int sweep_off, int threads,
+                           size_t lds_tab_bytes, hipStream_t s);
+hipError_t launch_cpm_snapshot(const CpmArgs& a, int total_cells, hipStream_t s);
+hipError_t launch_cpm_stats(const CpmArgs& a, int n_tiles, int rec_row, hipStream_t s);
+hipError_t launch_cpm_area_recount(const CpmArgs& a, int n_tiles, int total_cells, hipStream_t s);
+
+// Surrogate MLP
+hipError_t launch_mlp_forward(const float* params, const float* x, int B, float* y, float* act,
+                              hipStream_t s);
+hipError_t launch_mlp_backward(const float* params, const float* x, const float* act,
+                               const float* t, const float* w, int B, float* grad, float* dx,
+                               float* loss, float* scratch, hipStream_t s);
+hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v, int n, int step,
+                           float lr, float b1, float b2, float eps, hipStream_t s);
+
+}  // namespace spinmc

@@ -1,0 +1,190 @@
+"""Thin Python binding of libspinmc: argument marshalling only.
+
+PyTorch provides the device buffers (statistics, observables, gradients) and
+the HIP stream; every step of the sweep runs in the library's kernels.
+"""
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import ISING, POTTS, CPM, ReplicaDesc, Schedule, check, lib
+
+__all__ = ["Sampler", "ISING", "POTTS", "CPM", "MODES"]
+
+MODES = {"auto": 0, "resident": 1, "stream": 2, "hybrid": 3}
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream, C.c_void_p(stream.cuda_stream)
+
+
+class Sampler:
+    """A batch of independent replicas (Methods, batched tensors) behind one
+    libspinmc context.
+
+    ``replicas``: sequence of dicts with keys model, Lx, Ly and the model's
+    parameters (q, Jx, Jy, h, beta, rid; CPM: n_cells as q, n_types,
+    adhesion, cell_type, target_area, lambda_area, temperature).
+    """
+
+    def __init__(self, replicas, seed, init=True, stream=None, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("spinmc needs a GPU (HIP device); none is visible")
+        self.device = torch.device(device)
+        self.stream, sh = _stream_handle(stream)
+        n = len(replicas)
+        descs = (ReplicaDesc * n)()
+        self._keep = []
+        self.replicas = [dict(r) for r in replicas]
+        for i, r in enumerate(replicas):
+            d = descs[i]
+            d.model = int(r.get("model", ISING))
+            d.Lx, d.Ly = int(r["Lx"]), int(r["Ly"])
+            d.q = int(r.get("q", 2))
+            d.Jx = float(r.get("Jx", 1.0))
+            d.Jy = float(r.get("Jy", r.get("Jx", 1.0)))
+            d.h = float(r.get("h", 0.0))
+            d.beta = float(r.get("beta", 0.0))
+            d.rid = int(r.get("rid", i))
+            if d.model == CPM:
+                adh = np.ascontiguousarray(r["adhesion"], np.float32)
+                ct = np.ascontiguousarray(r["cell_type"], np.int8)
+                ta = np.ascontiguousarray(r["target_area"], np.int32)
+                self._keep += [adh, ct, ta]
+                d.n_types = int(adh.shape[0])
+                d.adhesion = adh.ctypes.data_as(C.POINTER(C.c_float))
+                d.cell_type = ct.ctypes.data_as(C.POINTER(C.c_int8))
+                d.target_area = ta.ctypes.data_as(C.POINTER(C.c_int32))
+                d.lambda_area = float(r["lambda_area"])
+                d.temperature = float(r["temperature"])
+        ctx = C.c_void_p()
+        check(lib().spinmc_create(descs, n, int(seed), 1 if init else 0, sh, C.byref(ctx)))
+        self._keep = []
+        self.ctx = ctx
+        self.R = n
+        self.width = lib().spinmc_stats_width(ctx)
+
+    # -------------------------------------------------------------- basics
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().spinmc_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def t(self):
+        v = C.c_uint64()
+        check(lib().spinmc_sweep_counter(self.ctx, C.byref(v)))
+        return int(v.value)
+
+    def _elem(self, r):
+        m = self.replicas[r].get("model", ISING)
+        return {ISING: np.int8, POTTS: np.uint8, CPM: np.int32}[m]
+
+    def get_state(self, r):
+        rep = self.replicas[r]
+        out = np.empty((rep["Ly"], rep["Lx"]), self._elem(r))
+        check(lib().spinmc_get_state(self.ctx, r, out.ctypes.data, out.nbytes))
+        return out
+
+    def set_state(self, r, arr):
+        arr = np.ascontiguousarray(arr, self._elem(r))
+        check(lib().spinmc_set_state(self.ctx, r, arr.ctypes.data, arr.nbytes))
+
+    def thresholds(self, r):
+        n = C.c_int32()
+        aux = C.c_int64()
+        check(lib().spinmc_thresholds(self.ctx, r, None, 0, C.byref(n), C.byref(aux)))
+        T = np.zeros(max(n.value, 1), np.uint64)
+        check(lib().spinmc_thresholds(self.ctx, r, T.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                      len(T), C.byref(n), C.byref(aux)))
+        return T[: n.value], int(aux.value)
+
+    # ------------------------------------------------------------- sweeps
+    def sweep(self, n, record_every=0, stats=None):
+        """Run n sweeps; returns the int32 statistics tensor
+        [n // record_every, R, width] on the device (or None)."""
+        if record_every > 0:
+            n_rec = n // record_every
+            if stats is None:
+                stats = torch.empty((max(n_rec, 1), self.R, self.width), dtype=torch.int32,
+                                    device=self.device)
+            ptr = C.c_void_p(stats.data_ptr())
+        else:
+            ptr = None
+        check(lib().spinmc_sweep(self.ctx, int(n), int(record_every), ptr))
+        return stats[: n // record_every] if record_every > 0 else None
+
+    def measure(self):
+        stats = torch.empty((self.R, self.width), dtype=torch.int32, device=self.device)
+        obs = torch.empty((self.R, 4), dtype=torch.float64, device=self.device)
+        check(lib().spinmc_measure(self.ctx, C.c_void_p(stats.data_ptr()),
+                                   C.c_void_p(obs.data_ptr())))
+        return stats, obs
+
+    def grad(self, stats, burn_in, grad_out=None):
+        """Covariance-estimator gradients from recorded statistics.
+        Returns (means [R,4] = (<e>, <|m|>, <m^2>, chi), grads [R,2,3],
+        dtheta [R,3] or None)."""
+        stats = stats.contiguous()
+        n_rec = stats.shape[0]
+        means = torch.empty((self.R, 4), dtype=torch.float64, device=self.device)
+        grads = torch.empty((self.R, 2, 3), dtype=torch.float64, device=self.device)
+        dth = None
+        gptr = None
+        if grad_out is not None:
+            grad_out = grad_out.to(device=self.device, dtype=torch.float64).contiguous()
+            dth = torch.empty((self.R, 3), dtype=torch.float64, device=self.device)
+            gptr = C.c_void_p(grad_out.data_ptr())
+        check(lib().spinmc_grad(self.ctx, C.c_void_p(stats.data_ptr()), int(n_rec), int(burn_in),
+                                gptr, C.c_void_p(means.data_ptr()), C.c_void_p(grads.data_ptr()),
+                                C.c_void_p(dth.data_ptr()) if dth is not None else None))
+        return means, grads, dth
+
+    # ------------------------------------------------------------- timing
+    KERNELS = {"stream_pass": 0, "resident": 1, "persistent": 2, "cpm_pass": 3}
+
+    def profile(self, enable=True):
+        check(lib().spinmc_profile(self.ctx, 1 if enable else 0))
+
+    def profile_read(self, kind):
+        ms = C.c_double()
+        n = C.c_int64()
+        check(lib().spinmc_profile_read(self.ctx, self.KERNELS.get(kind, kind), C.byref(ms),
+                                        C.byref(n)))
+        return float(ms.value), int(n.value)
+
+    # ---------------------------------------------------------- schedules
+    def set_schedule(self, mode="auto", tile_rows=0, wg_threads=0):
+        s = Schedule(MODES[mode] if isinstance(mode, str) else int(mode), int(tile_rows),
+                     int(wg_threads), 0)
+        check(lib().spinmc_set_schedule(self.ctx, C.byref(s)))
+
+    def get_schedule(self):
+        s = Schedule()
+        check(lib().spinmc_get_schedule(self.ctx, C.byref(s)))
+        return dict(mode=s.mode, tile_rows=s.tile_rows, wg_threads=s.wg_threads)
+
+    def schedule_sites(self):
+        """(streamed, resident) sites per sweep under the current schedule."""
+        a, b = C.c_int64(), C.c_int64()
+        check(lib().spinmc_schedule_sites(self.ctx, C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
+
+    def autotune(self, trial_sweeps=20):
+        s = Schedule()
+        rates = (C.c_double * 64)()
+        n = C.c_int32()
+        check(lib().spinmc_autotune(self.ctx, int(trial_sweeps), C.byref(s), rates, 64,
+                                    C.byref(n)))
+        return dict(mode=s.mode, tile_rows=s.tile_rows, wg_threads=s.wg_threads), \
+            [rates[i] for i in range(n.value)]

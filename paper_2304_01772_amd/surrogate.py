@@ -1,0 +1,229 @@
+"""Learned surrogate of equilibrium Ising observables, trained on the
+sampler's own data, steering an inverse problem with Monte Carlo as judge
+and fallback.
+
+Pipeline (all device work in libspinmc kernels; this module marshals):
+  1. labels: batched Monte Carlo on LxL Ising replicas at parameter points
+     (beta, Jx, Jy, h); <e>, <|m|> and chi from the covariance kernel's exact
+     integer moments (spinmc_grad means);
+  2. training: 4-128-128-3 MLP (spinmc_mlp_forward / backward / adam, BF16
+     matrix cores, FP32 master weights, Adam with the paper's settings);
+  3. inverse problem: find (Jx, Jy) with <|m|>(beta, Jx, Jy, h) = target.
+     Surrogate-steered: gradient descent on the network's inputs
+     (input gradients from spinmc_mlp_backward), then one Monte Carlo
+     verification; if the verified error exceeds the tolerance, Monte Carlo
+     covariance-gradient steps continue from the surrogate's answer.
+     Monte-Carlo-only: the same covariance-gradient steps from the start.
+"""
+import ctypes as C
+import time
+
+import numpy as np
+import torch
+
+from ._lib import check, lib
+from .sampler import Sampler
+
+# parameter box of the training points (beta, Jx, Jy, h)
+BOX_LO = np.array([0.3, 0.5, 0.5, -0.1])
+BOX_HI = np.array([0.6, 1.5, 1.5, 0.1])
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class SurrogateMLP:
+    """The 4-128-128-3 network on the library's MLP kernels."""
+
+    def __init__(self, seed=0, device="cuda"):
+        self.dev = torch.device(device)
+        L = lib()
+        self.np = L.spinmc_mlp_num_params()
+        g = np.random.default_rng(seed)
+        parts = []
+        for shp in ((128, 4), (128,), (128, 128), (128,), (3, 128), (3,)):
+            if len(shp) == 2:
+                b = np.sqrt(6.0 / shp[1])
+                parts.append(g.uniform(-b, b, size=shp).reshape(-1))
+            else:
+                parts.append(np.zeros(shp))
+        self.params = torch.tensor(np.concatenate(parts), dtype=torch.float32, device=self.dev)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.step_no = 0
+        self.x_lo = torch.tensor(BOX_LO, dtype=torch.float32, device=self.dev)
+        self.x_hi = torch.tensor(BOX_HI, dtype=torch.float32, device=self.dev)
+        self.y_mu = torch.zeros(3, dtype=torch.float32, device=self.dev)
+        self.y_sd = torch.ones(3, dtype=torch.float32, device=self.dev)
+        self._ws = {}
+
+    def _stream(self):
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def normalise_x(self, x):
+        return (2.0 * (x - self.x_lo) / (self.x_hi - self.x_lo) - 1.0).contiguous()
+
+    def _buffers(self, B):
+        if B not in self._ws:
+            L = lib()
+            self._ws[B] = dict(
+                act=torch.empty(L.spinmc_mlp_act_floats(B), dtype=torch.float32, device=self.dev),
+                ws=torch.empty(L.spinmc_mlp_workspace_floats(B), dtype=torch.float32,
+                               device=self.dev),
+                y=torch.empty((B, 3), dtype=torch.float32, device=self.dev),
+                dx=torch.empty((B, 4), dtype=torch.float32, device=self.dev),
+                loss=torch.empty(1, dtype=torch.float32, device=self.dev))
+        return self._ws[B]
+
+    def forward_normalised(self, xn, act=None):
+        B = xn.shape[0]
+        b = self._buffers(B)
+        check(lib().spinmc_mlp_forward(_p(self.params), _p(xn), B, _p(b["y"]),
+                                       _p(act) if act is not None else None, self._stream()))
+        return b["y"]
+
+    def predict(self, x):
+        """Physical outputs (<e>, <|m|>, chi) for physical inputs x [B, 4]."""
+        y = self.forward_normalised(self.normalise_x(x))
+        return y * self.y_sd + self.y_mu
+
+    def train_step(self, xn, tn, w, lr=1e-3):
+        B = xn.shape[0]
+        b = self._buffers(B)
+        L = lib()
+        s = self._stream()
+        check(L.spinmc_mlp_forward(_p(self.params), _p(xn), B, _p(b["y"]), _p(b["act"]), s))
+        check(L.spinmc_mlp_backward(_p(self.params), _p(xn), _p(b["act"]), _p(tn), _p(w), B,
+                                    _p(self.grad), None, _p(b["loss"]), _p(b["ws"]), s))
+        self.step_no += 1
+        check(L.spinmc_mlp_adam(_p(self.params), _p(self.grad), _p(self.m), _p(self.v),
+                                self.step_no, lr, 0.9, 0.999, 1e-8, s))
+        return b["loss"]
+
+    def input_grad(self, xn, tn, w):
+        """d/dx of sum_j w_j (y_j - t_j)^2 / B at normalised inputs xn."""
+        B = xn.shape[0]
+        b = self._buffers(B)
+        L = lib()
+        s = self._stream()
+        check(L.spinmc_mlp_forward(_p(self.params), _p(xn), B, _p(b["y"]), _p(b["act"]), s))
+        check(L.spinmc_mlp_backward(_p(self.params), _p(xn), _p(b["act"]), _p(tn), _p(w), B,
+                                    _p(self.grad), _p(b["dx"]), _p(b["loss"]), _p(b["ws"]), s))
+        return b["dx"], b["y"]
+
+    def fit(self, x, y, epochs=60, batch=1024, lr=1e-3, seed=0, log=None):
+        """Train on physical (x, y); labels are standardised per output."""
+        x = torch.as_tensor(x, dtype=torch.float32, device=self.dev)
+        y = torch.as_tensor(y, dtype=torch.float32, device=self.dev)
+        self.y_mu = y.mean(dim=0)
+        self.y_sd = y.std(dim=0).clamp_min(1e-6)
+        xn = self.normalise_x(x)
+        yn = ((y - self.y_mu) / self.y_sd).contiguous()
+        w = torch.ones(3, dtype=torch.float32, device=self.dev)
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        n = x.shape[0]
+        for ep in range(epochs):
+            perm = torch.randperm(n, generator=g).to(self.dev)
+            last = None
+            for k in range(0, n - batch + 1, batch):
+                idx = perm[k:k + batch]
+                last = self.train_step(xn[idx].contiguous(), yn[idx].contiguous(), w, lr)
+            if log and (ep % 10 == 9 or ep == epochs - 1):
+                log(f"epoch {ep + 1}: batch loss {float(last.item()):.4g}")
+        return self
+
+
+# ----------------------------------------------------------------- labels
+def mc_observables(points, L=64, burn=300, measure=700, every=1, seed=5, rid0=0, chunk=16384):
+    """Monte Carlo labels (<e>, <|m|>, chi) for points [N, 4] = (beta, Jx,
+    Jy, h), one LxL replica per point, plus the standard error of <|m|> from
+    batch means.  Returns (labels [N, 3], se_absm [N]) as numpy arrays."""
+    pts = np.asarray(points, np.float64)
+    out = np.zeros((len(pts), 3))
+    se = np.zeros(len(pts))
+    for c0 in range(0, len(pts), chunk):
+        part = pts[c0:c0 + chunk]
+        reps = [dict(model=0, Lx=L, Ly=L, beta=float(b), Jx=float(jx), Jy=float(jy), h=float(h),
+                     rid=rid0 + c0 + i) for i, (b, jx, jy, h) in enumerate(part)]
+        smp = Sampler(reps, seed, init=True)
+        smp.sweep(burn)
+        st = smp.sweep(measure, every)
+        means, _, _ = smp.grad(st, 0)
+        m = means.cpu().numpy()
+        out[c0:c0 + len(part)] = m[:, [0, 1, 3]]
+        # standard error of <|m|> from 10 batch means of the recorded |M|/N
+        am = st[:, :, 0].abs().double().cpu().numpy() / (L * L)
+        nb = 10
+        bm = am[: (am.shape[0] // nb) * nb].reshape(nb, -1, am.shape[1]).mean(axis=1)
+        se[c0:c0 + len(part)] = bm.std(axis=0, ddof=1) / np.sqrt(nb)
+        smp.close()
+    return out, se
+
+
+def mc_absm_and_grad(beta, Jx, Jy, h, L=64, n_rep=16, burn=300, measure=700, seed=7, rid0=0):
+    """<|m|> over n_rep replicas and its gradient wrt (Jx, Jy) by the
+    covariance estimator; returns (absm, se, dJx, dJy)."""
+    reps = [dict(model=0, Lx=L, Ly=L, beta=float(beta), Jx=float(Jx), Jy=float(Jy), h=float(h),
+                 rid=rid0 + i) for i in range(n_rep)]
+    smp = Sampler(reps, seed, init=True)
+    smp.sweep(burn)
+    st = smp.sweep(measure, 1)
+    means, grads, _ = smp.grad(st, 0)
+    m = means[:, 1].cpu().numpy()
+    g = grads[:, 1, :2].cpu().numpy()
+    smp.close()
+    return float(m.mean()), float(m.std(ddof=1) / np.sqrt(n_rep)), float(g[:, 0].mean()), \
+        float(g[:, 1].mean())
+
+
+# --------------------------------------------------------- inverse problem
+def mc_only_solve(target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, max_iter=40, **mc):
+    """Covariance-gradient (Newton along the gradient) steps on (Jx, Jy)
+    until the Monte Carlo <|m|> is within tol (relative) of the target."""
+    Jx, Jy = start
+    t0 = time.perf_counter()
+    hist = []
+    for it in range(max_iter):
+        m, se, gx, gy = mc_absm_and_grad(beta, Jx, Jy, h, rid0=1000 * it, **mc)
+        hist.append((Jx, Jy, m, se))
+        if abs(m - target) <= tol * target:
+            return dict(Jx=Jx, Jy=Jy, absm=m, se=se, iters=it + 1, mc_calls=it + 1,
+                        seconds=time.perf_counter() - t0, converged=True, history=hist)
+        g2 = gx * gx + gy * gy
+        step = (target - m) / max(g2, 1e-12)
+        step = float(np.clip(step, -0.5 / max(np.sqrt(g2), 1e-12), 0.5 / max(np.sqrt(g2), 1e-12)))
+        Jx = float(np.clip(Jx + step * gx, 0.05, 3.0))
+        Jy = float(np.clip(Jy + step * gy, 0.05, 3.0))
+    return dict(Jx=Jx, Jy=Jy, absm=hist[-1][2], se=hist[-1][3], iters=max_iter, mc_calls=max_iter,
+                seconds=time.perf_counter() - t0, converged=False, history=hist)
+
+
+def surrogate_solve(net, target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, steps=300, lr=0.05,
+                    max_iter=40, **mc):
+    """Gradient descent on the surrogate's inputs, one Monte Carlo check,
+    and Monte Carlo covariance-gradient steps if the check fails."""
+    dev = net.dev
+    t0 = time.perf_counter()
+    x = torch.tensor([[beta, start[0], start[1], h]], dtype=torch.float32, device=dev)
+    xn = net.normalise_x(x)
+    tn = ((torch.tensor([[0.0, target, 0.0]], device=dev) - net.y_mu) / net.y_sd).to(
+        torch.float32).contiguous()
+    w = torch.tensor([0.0, 1.0, 0.0], dtype=torch.float32, device=dev)
+    scale = (2.0 / (net.x_hi - net.x_lo))  # d xn / d x
+    for _ in range(steps):
+        dx, _ = net.input_grad(xn, tn, w)
+        # move only the couplings (inputs 1, 2), in physical units
+        step = torch.zeros_like(xn)
+        step[:, 1:3] = dx[:, 1:3] * scale[1:3] * scale[1:3]
+        xn = (xn - lr * step).clamp(-1.0, 1.0).contiguous()
+    xp = (xn + 1.0) / 2.0 * (net.x_hi - net.x_lo) + net.x_lo
+    Jx, Jy = float(xp[0, 1]), float(xp[0, 2])
+    t_sur = time.perf_counter() - t0
+    res = mc_only_solve(target, beta, h, start=(Jx, Jy), tol=tol, max_iter=max_iter, **mc)
+    res["surrogate_seconds"] = t_sur
+    res["surrogate_guess"] = (Jx, Jy)
+    res["seconds"] += t_sur
+    res["fallback_iters"] = res["iters"] - 1
+    return res

@@ -1,0 +1,127 @@
+"""GPU covariance-estimator gradients: parity with the oracle on identical
+chains, the full differentiation workload, and validation against exact
+enumeration (3 sigma) and finite differences with common random numbers."""
+import math
+
+import numpy as np
+import pytest
+
+import exact
+import synth
+from oracle import chain as orc
+from oracle import gradients as ograd
+from oracle import observables as oobs
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2304_01772_amd.sampler import Sampler
+    assert torch.cuda.is_available()
+    return Sampler
+
+
+def _f32(v):
+    return float(np.float32(v))
+
+
+def test_grad_parity_with_oracle(S):
+    rng = np.random.default_rng(0)
+    reps = [dict(model=0, Lx=L, Ly=L, Jx=_f32(rng.uniform(0.3, 0.6)), Jy=_f32(rng.uniform(0.3, 0.6)),
+                 h=_f32(rng.uniform(-0.05, 0.05)), beta=1.0, rid=i)
+            for i, L in enumerate([4, 8, 16, 32, 32, 64])]
+    seed, n, burn = 3, 400, 100
+    smp = S(reps, seed, init=True)
+    st = smp.sweep(n, 1)
+    means, grads, dth = smp.grad(st, burn, grad_out=torch.tensor([[1.0, -2.0]] * len(reps)))
+    torch.cuda.synchronize()
+    means, grads, dth = means.cpu().numpy(), grads.cpu().numpy(), dth.cpu().numpy()
+    for i, r in enumerate(reps):
+        s0 = orc.ising_init(r["Lx"], r["Ly"], seed, r["rid"])
+        _, ost = orc.ising_run(s0, r["Jx"], r["Jy"], r["h"], 1.0, seed, r["rid"], 0, n, 1)
+        assert np.array_equal(st[:, i].cpu().numpy(), ost)
+        N = r["Lx"] * r["Ly"]
+        mo, go = ograd.ising_grad(ost[burn:, 0], ost[burn:, 1], ost[burn:, 2], r["Jx"], r["Jy"],
+                                  r["h"], 1.0, N)
+        np.testing.assert_allclose(means[i, :2], mo, rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(grads[i], go, rtol=1e-9, atol=1e-12)
+        np.testing.assert_allclose(dth[i], 1.0 * go[0] - 2.0 * go[1], rtol=1e-9, atol=1e-12)
+        ob = oobs.ising(ost[burn:], r["Jx"], r["Jy"], r["h"], N)
+        chi = oobs.susceptibility(ob["absm"], ob["m2"], 1.0, N)
+        assert abs(means[i, 2] - ob["m2"].mean()) <= 1e-12 * ob["m2"].mean()
+        assert abs(means[i, 3] - chi) <= 1e-9 * abs(chi) + 1e-12
+
+
+def test_differentiation_workload_full_size(S):
+    """256 replicas of 128x128, J ~ U(0.3, 0.6), h ~ U(-0.05, 0.05), beta 1,
+    5000 recorded sweeps, burn-in 1000: sampled replicas bit-exact with the
+    oracle chain and their gradients equal to the oracle's."""
+    reps = synth.differentiation()
+    seed, n, burn = 3, 5000, 1000
+    smp = S(reps, seed, init=True)
+    st = smp.sweep(n, 1)
+    means, grads, _ = smp.grad(st, burn)
+    torch.cuda.synchronize()
+    assert torch.isfinite(grads).all()
+    for i in (0, 137):
+        r = reps[i]
+        s0 = orc.ising_init(128, 128, seed, r["rid"])
+        want, ost = orc.ising_run(s0, r["Jx"], r["Jy"], r["h"], 1.0, seed, r["rid"], 0, n, 1)
+        assert np.array_equal(smp.get_state(i), want)
+        assert np.array_equal(st[:, i].cpu().numpy(), ost)
+        _, go = ograd.ising_grad(ost[burn:, 0], ost[burn:, 1], ost[burn:, 2], r["Jx"], r["Jy"],
+                                 r["h"], 1.0, 128 * 128)
+        np.testing.assert_allclose(grads[i].cpu().numpy(), go, rtol=1e-9, atol=1e-12)
+    smp.close()
+
+
+def test_gradients_within_3_sigma_of_exact_enumeration(S):
+    """256 replicas of the 4x4 torus: the replica-averaged covariance
+    estimates of d<e>/dtheta and d<|m|>/dtheta are within 3 standard errors
+    of the exact derivatives (enumeration of all 65536 states)."""
+    Jx, Jy, h, beta = _f32(0.45), _f32(0.45), _f32(0.03), 1.0
+    R, n, burn = 256, 5000, 1000
+    reps = [dict(model=0, Lx=4, Ly=4, Jx=Jx, Jy=Jy, h=h, beta=beta, rid=i) for i in range(R)]
+    smp = S(reps, 11, init=True)
+    st = smp.sweep(n, 1)
+    means, grads, _ = smp.grad(st, burn)
+    g = grads.cpu().numpy()
+    ex = exact.ising_exact(4, 4, Jx, Jy, h, beta)
+    _, gex = ograd.ising_grad(ex["M"], ex["Bx"], ex["By"], Jx, Jy, h, beta, 16, weights=ex["p"])
+    for o in range(2):
+        for j in range(3):
+            est = g[:, o, j]
+            se = est.std(ddof=1) / math.sqrt(R)
+            assert abs(est.mean() - gex[o, j]) <= 3 * se, (o, j, est.mean(), gex[o, j], se)
+    m = means.cpu().numpy()
+    for k, key in ((0, "e"), (1, "absm")):
+        se = m[:, k].std(ddof=1) / math.sqrt(R)
+        assert abs(m[:, k].mean() - ex[key]) <= 3 * se
+    smp.close()
+
+
+def test_gradient_matches_finite_differences_with_common_random_numbers(S):
+    """d<|m|>/dJ (J = Jx = Jy) by the covariance estimator at J against
+    (<|m|>(J + eps) - <|m|>(J - eps)) / 2 eps from chains that share seed
+    and replica ids (common random numbers), 4x4 torus, eps = 1e-2."""
+    J, beta, eps = 0.44, 1.0, 1e-2
+    R, n, burn = 512, 3000, 500
+    mk = lambda j: [dict(model=0, Lx=4, Ly=4, Jx=_f32(j), Jy=_f32(j), h=0.0, beta=beta, rid=i)  # noqa
+                    for i in range(R)]
+    out = {}
+    for key, j in (("0", J), ("+", J + eps), ("-", J - eps)):
+        smp = S(mk(j), 21, init=True)
+        st = smp.sweep(n, 1)
+        means, grads, _ = smp.grad(st, burn)
+        out[key] = (means.cpu().numpy(), grads.cpu().numpy())
+        smp.close()
+    fd = (out["+"][0][:, 1] - out["-"][0][:, 1]) / (2 * eps)
+    cov = out["0"][1][:, 1, 0] + out["0"][1][:, 1, 1]
+    se = math.hypot(fd.std(ddof=1), cov.std(ddof=1)) / math.sqrt(R)
+    assert abs(fd.mean() - cov.mean()) <= 3 * se + 1e-3, (fd.mean(), cov.mean(), se)
+    ex = exact.ising_exact(4, 4, _f32(J), _f32(J), 0.0, beta)
+    _, gex = ograd.ising_grad(ex["M"], ex["Bx"], ex["By"], _f32(J), _f32(J), 0.0, beta, 16,
+                              weights=ex["p"])
+    assert abs(cov.mean() - (gex[1, 0] + gex[1, 1])) <= 3 * cov.std(ddof=1) / math.sqrt(R)
