@@ -114,11 +114,19 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--sweeps", type=int, default=10000, help="sweeps per step")
-    ap.add_argument("--mode", default="auto", choices=["auto", "resident", "stream", "hybrid"])
+    ap.add_argument("--mode", default="tuned",
+                    choices=["tuned", "auto", "resident", "stream", "hybrid"],
+                    help="schedule; 'tuned' runs the library's autotuner first")
+    ap.add_argument("--tune-sweeps", type=int, default=20)
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--cpu-sweeps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-probes", action="store_true",
+                    help="skip the Ising streaming probes (for counter collection runs)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (the reference "
+                         "dispatch that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the workload is "
@@ -136,7 +144,13 @@ def main():
     print(f"# workload: {len(reps)} replicas, {sites} sites/sweep, {args.sweeps} sweeps/step",
           file=sys.stderr, flush=True)
     smp = Sampler(reps, seed=seed, init=True)
-    smp.set_schedule(mode=args.mode, tile_rows=args.tile_rows, wg_threads=args.threads)
+    tuning = None
+    if args.mode == "tuned":
+        chosen, rates = smp.autotune(trial_sweeps=args.tune_sweeps)
+        tuning = dict(chosen=chosen, candidate_rates=[round(r, 1) for r in rates])
+        print(f"# autotune: {tuning}", file=sys.stderr, flush=True)
+    else:
+        smp.set_schedule(mode=args.mode, tile_rows=args.tile_rows, wg_threads=args.threads)
     for w in range(args.warmup):
         smp.sweep(args.sweeps)
         torch.cuda.synchronize()
@@ -174,8 +188,15 @@ def main():
     sched = smp.get_schedule()
     smp.close()
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     probes = {}
-    for n_rep in (1024, 8192):
+    for n_rep in (() if args.no_probes else (1024, 8192)):
         probes[f"ising_{n_rep}x256x256_stream"] = ising_stream_probe(Sampler, torch, n_rep, 100)
         print(f"# Ising stream probe {n_rep}: {probes[f'ising_{n_rep}x256x256_stream']}",
               file=sys.stderr, flush=True)
@@ -206,6 +227,7 @@ def main():
             "sites_per_sweep": sites,
             "sweeps_per_step": args.sweeps,
             "schedule": sched,
+            "autotune": tuning,
             "streamed_sites": streamed,
             "resident_sites": resident,
         },

@@ -115,6 +115,7 @@ struct spinmc_ctx {
     int off_all = 0, off_potts = 0, off_res_chunk = 0, off_res_gen = 0, off_rest = 0;
     TileDev* d_tiles = nullptr;
     int n_tiles = 0;
+    int n_tiles_ising = 0;  // streamed Ising tiles come first in d_tiles
     int tiles_rows = 0;
     spinmc_schedule sched{0, 0, 0, 0};
     bool prepared = false;
@@ -865,7 +866,7 @@ int prepare(spinmc_ctx* c, int mode) {
     const long key = ((long)mode << 32) | (long)(unsigned)tr;
     if (c->prepared && c->prepared_key == key) return SPINMC_OK;
     std::vector<int32_t> res_chunk, res_gen, spotts;
-    std::vector<TileDev> tiles;
+    std::vector<TileDev> tiles, ptiles;  // Ising tiles first, then Potts tiles
     for (int i = 0; i < c->R; ++i) {
         const HostRep& h = c->reps[i];
         const bool resident = (mode == 1) || !h.chunk || (mode == 3 && h.resident);
@@ -875,9 +876,12 @@ int prepare(spinmc_ctx* c, int mode) {
         }
         if (h.dev.model == SPINMC_POTTS) spotts.push_back(i);
         const int rows = tr > 0 ? std::min(tr, h.dev.Ly) : default_tile_rows(h);
+        std::vector<TileDev>& dst = h.dev.model == SPINMC_ISING ? tiles : ptiles;
         for (int y0 = 0; y0 < h.dev.Ly; y0 += rows)
-            tiles.push_back(TileDev{i, y0, std::min(rows, h.dev.Ly - y0), 0});
+            dst.push_back(TileDev{i, y0, std::min(rows, h.dev.Ly - y0), 0});
     }
+    c->n_tiles_ising = (int)tiles.size();
+    tiles.insert(tiles.end(), ptiles.begin(), ptiles.end());
     hipError_t e = hipStreamSynchronize(c->stream);
     drop_graphs(c);
     c->res_chunk = res_chunk;
@@ -965,13 +969,20 @@ hipError_t enqueue_stream(spinmc_ctx* c, const SweepArgs& a, int i0, int n, int 
     for (int i = i0; i < i0 + n && e == hipSuccess; ++i) {
         const bool rec = re > 0 && ((i + 1) % re) == 0;
         const int row = rec ? (i + 1) / re - 1 : -1;
-        e = timed(c, SPINMC_K_STREAM_PASS, [&] {
-            return launch_stream_pass(a, c->n_tiles, 0, i, -1, threads, a.tab_lds_bytes, s);
-        }, s);
-        if (e == hipSuccess)
-            e = timed(c, SPINMC_K_STREAM_PASS, [&] {
-                return launch_stream_pass(a, c->n_tiles, 1, i, row, threads, a.tab_lds_bytes, s);
-            }, s);
+        const int ni = c->n_tiles_ising, np = c->n_tiles - c->n_tiles_ising;
+        for (int col = 0; col < 2 && e == hipSuccess; ++col) {
+            const int rr = col == 1 ? row : -1;
+            if (ni > 0)
+                e = timed(c, SPINMC_K_STREAM_PASS, [&] {
+                    return launch_stream_pass(a, SPINMC_ISING, 0, ni, col, i, rr, threads,
+                                              a.tab_lds_bytes, s);
+                }, s);
+            if (e == hipSuccess && np > 0)
+                e = timed(c, SPINMC_K_STREAM_PASS, [&] {
+                    return launch_stream_pass(a, SPINMC_POTTS, ni, np, col, i, rr, threads,
+                                              a.tab_lds_bytes, s);
+                }, s);
+        }
         if (e == hipSuccess && rec && !c->stream_potts.empty())
             e = launch_potts_hist_finalize(a, c->d_lists + c->off_rest,
                                            (int)c->stream_potts.size(), row, s);

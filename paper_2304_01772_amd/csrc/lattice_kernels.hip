@@ -59,29 +59,41 @@ struct IsingAcc {
 
 // ---------------------------------------------------------------- Ising
 // One 16-site chunk of plane row y starting at byte j0 (j0 % 16 == 0,
-// W % 16 == 0).  PAR = (y + c) & 1 selects which horizontal neighbour the
-// shifted byte stream supplies.  thr: LDS [18 hi | 18 lo].
-template <int PAR, bool REC>
-__device__ __forceinline__ void ising_chunk(uint8_t* own, const uint8_t* oth, int W, int y, int ym,
-                                            int yp, int j0, uint32_t p, uint32_t rid, uint32_t k0,
-                                            uint32_t k1, const uint32_t* thr, IsingAcc& acc) {
-    const size_t ro = (size_t)y * W;
-    const uint4 o = *reinterpret_cast<const uint4*>(own + ro + j0);
-    const uint4 m = *reinterpret_cast<const uint4*>(oth + ro + j0);
-    const uint4 U = *reinterpret_cast<const uint4*>(oth + (size_t)ym * W + j0);
-    const uint4 D = *reinterpret_cast<const uint4*>(oth + (size_t)yp * W + j0);
+// W % 16 == 0): own bytes, the other plane's rows y-1, y, y+1, and the halo
+// dword holding the horizontal neighbour of the first (PAR = 0) or last
+// (PAR = 1) byte.  Loading is split from computing so that a lane can keep
+// two chunks' loads in flight.
+struct ChunkIn {
+    uint4 o, m, U, D;
     uint32_t e;
-    if (PAR == 0) {
-        const int je = (j0 == 0) ? W - 4 : j0 - 4;
-        e = *reinterpret_cast<const uint32_t*>(oth + ro + je);
-    } else {
-        const int je = (j0 + 16 == W) ? 0 : j0 + 16;
-        e = *reinterpret_cast<const uint32_t*>(oth + ro + je);
-    }
-    const uint32_t ov[4] = {o.x, o.y, o.z, o.w};
-    const uint32_t mv[4] = {m.x, m.y, m.z, m.w};
-    const uint32_t Uv[4] = {U.x, U.y, U.z, U.w};
-    const uint32_t Dv[4] = {D.x, D.y, D.z, D.w};
+};
+
+template <int PAR>
+__device__ __forceinline__ ChunkIn chunk_load(const uint8_t* own, const uint8_t* oth, int W,
+                                              int y, int ym, int yp, int j0) {
+    const size_t ro = (size_t)y * W;
+    ChunkIn in;
+    in.o = *reinterpret_cast<const uint4*>(own + ro + j0);
+    in.m = *reinterpret_cast<const uint4*>(oth + ro + j0);
+    in.U = *reinterpret_cast<const uint4*>(oth + (size_t)ym * W + j0);
+    in.D = *reinterpret_cast<const uint4*>(oth + (size_t)yp * W + j0);
+    const int je = PAR == 0 ? ((j0 == 0) ? W - 4 : j0 - 4) : ((j0 + 16 == W) ? 0 : j0 + 16);
+    in.e = *reinterpret_cast<const uint32_t*>(oth + ro + je);
+    return in;
+}
+
+// PAR = (y + c) & 1 selects which horizontal neighbour the shifted byte
+// stream supplies.  thr: LDS [18 hi | 18 lo].
+template <int PAR, bool REC>
+__device__ __forceinline__ void ising_compute(const ChunkIn& in, uint8_t* own, int W, int y, int j0,
+                                              uint32_t p, uint32_t rid, uint32_t k0, uint32_t k1,
+                                              const uint32_t* thr, IsingAcc& acc) {
+    const size_t ro = (size_t)y * W;
+    const uint32_t e = in.e;
+    const uint32_t ov[4] = {in.o.x, in.o.y, in.o.z, in.o.w};
+    const uint32_t mv[4] = {in.m.x, in.m.y, in.m.z, in.m.w};
+    const uint32_t Uv[4] = {in.U.x, in.U.y, in.U.z, in.U.w};
+    const uint32_t Dv[4] = {in.D.x, in.D.y, in.D.z, in.D.w};
     uint32_t sv[4];
     if (PAR == 0) {
         sv[0] = __builtin_amdgcn_alignbyte(mv[0], e, 3);
@@ -105,22 +117,24 @@ __device__ __forceinline__ void ising_chunk(uint8_t* own, const uint8_t* oth, in
     uint32_t w[8];
     philox4x32_10(kb >> 3, p, rid, kTagMain, k0, k1, &w[0]);
     philox4x32_10((kb >> 3) + 1u, p, rid, kTagMain, k0, k1, &w[4]);
+    // d = r - T_hi as unsigned: bit 31 set iff r < T_hi (accept on the prefix),
+    // d == 0 iff the prefix ties; the smallest d flags a tie anywhere.
     uint32_t flip[4] = {0u, 0u, 0u, 0u};
-    uint32_t amb = 0u;
+    uint32_t dmin = 0xFFFFFFFFu;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const uint32_t cls = (idx[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-        const int32_t th = (int32_t)thr[cls];
-        const int32_t r = (int32_t)((w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu);
-        const int32_t d = r - th;
-        flip[j >> 2] |= ((uint32_t)(d >> 31)) & (1u << (8 * (j & 3)));
-        amb |= (d == 0 ? 1u : 0u) << j;
+        const uint32_t r = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+        const uint32_t d = r - thr[cls];
+        flip[j >> 2] |= (d >> 31) << (8 * (j & 3));
+        dmin = min(dmin, d);
     }
-    if (amb) {
+    if (dmin == 0u) {
         // The prefix equals the threshold's high half: the low halves decide.
         for (int j = 0; j < 16; ++j) {
-            if (!((amb >> j) & 1u)) continue;
             const uint32_t cls = (idx[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+            const uint32_t r = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
+            if (r != thr[cls]) continue;
             const uint32_t lo = thr[kIsingClasses + cls];
             if (lo == 0u) continue;
             uint32_t f[4];
@@ -159,11 +173,13 @@ __device__ __forceinline__ uint32_t ne_hi(uint32_t a, uint32_t b) {
     return ((a ^ b) + 0x7F7F7F7Fu) & 0x80808080u;
 }
 
-// 16-site Potts chunk.  thr: LDS [n hi | n lo], n = 9(2q-1).
-template <int PAR, bool REC>
+// 16-site Potts chunk.  thr: LDS [n hi | n lo], n = 9(2q-1); thr9: LDS
+// [9 hi | 9 lo] by dn + 4 (used when HZ, i.e. h = 0).
+template <int PAR, bool REC, bool HZ>
 __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, int W, int y, int ym,
                                             int yp, int j0, uint32_t p, uint32_t rid, uint32_t k0,
-                                            uint32_t k1, const uint32_t* thr, int q, int ntab,
+                                            uint32_t k1, const uint32_t* thr,
+                                            const uint32_t* thr9, int q, int ntab,
                                             uint32_t lem_thr, PottsAcc& acc, int* lhist) {
     const size_t ro = (size_t)y * W;
     const uint4 o = *reinterpret_cast<const uint4*>(own + ro + j0);
@@ -200,67 +216,97 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
     for (int b = 0; b < 4; ++b)
         philox4x32_10((kb >> 2) + (uint32_t)b, p, rid, kTagMain, k0, k1, &w[4 * b]);
     const uint32_t mq = (uint32_t)(q - 1);
-    // proposals s' = s + 1 + off (mod q), off uniform in [0, q-1)
+    // proposals s' = s + 1 + off (mod q), off uniform in [0, q-1); the
+    // smallest low half of the Lemire products flags a rejection anywhere
     uint32_t s2v[4] = {0u, 0u, 0u, 0u};
-    uint32_t lemrej = 0u;
+    uint32_t lmin = 0xFFFFFFFFu;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const uint32_t s = (ov[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-        const uint32_t prod = (w[j] & 0xFFFFu) * mq;
-        lemrej |= ((prod & 0xFFFFu) < lem_thr ? 1u : 0u) << j;
-        uint32_t s2 = s + 1u + (prod >> 16);
-        s2 = (s2 >= (uint32_t)q) ? s2 - (uint32_t)q : s2;
-        s2v[j >> 2] |= s2 << (8 * (j & 3));
+        const uint32_t prod = __umul24(w[j] & 0xFFFFu, mq);  // < 2^24: full-rate multiply
+        lmin = min(lmin, prod & 0xFFFFu);
+        const uint32_t s2 = s + 1u + (prod >> 16);
+        s2v[j >> 2] |= min(s2, s2 - (uint32_t)q) << (8 * (j & 3));  // wrap to [0, q)
     }
-    if (lemrej) {
+    if (lmin < lem_thr) {
         for (int j = 0; j < 16; ++j) {
-            if (!((lemrej >> j) & 1u)) continue;
+            const uint32_t prod = __umul24(w[j] & 0xFFFFu, mq);
+            if ((prod & 0xFFFFu) >= lem_thr) continue;
             uint32_t f[4];
             philox4x32_10(kb + (uint32_t)j, p, rid, kTagFallback, k0, k1, f);
             const uint32_t s = (ov[j >> 2] >> (8 * (j & 3))) & 0xFFu;
             const uint32_t off = (uint32_t)(((uint64_t)f[1] * (uint64_t)mq) >> 32);
-            uint32_t s2 = s + 1u + off;
-            s2 = (s2 >= (uint32_t)q) ? s2 - (uint32_t)q : s2;
+            const uint32_t s2 = s + 1u + off;
             const int sh = 8 * (j & 3);
-            s2v[j >> 2] = (s2v[j >> 2] & ~(0xFFu << sh)) | (s2 << sh);
+            s2v[j >> 2] = (s2v[j >> 2] & ~(0xFFu << sh)) | (min(s2, s2 - (uint32_t)q) << sh);
         }
     }
-    // dn + 4 = #ne(s) - #ne(s') + 4 per byte
+    // dn + 4 = #ne(s) - #ne(s') + 4 per byte.  Labels below 2^b (b <= 4):
+    // ((a ^ c) + (2^b - 1)) has bit b set iff a != c, and four such flags sum
+    // and 4 + dn (times 2^b) stays below 256, so no per-flag shift is needed.
     uint32_t dn4[4];
+    if (q <= 16) {
+        const int b = q <= 2 ? 1 : 32 - __clz(q - 1);
+        const uint32_t F = 0x01010101u << b, A = F - 0x01010101u;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t neo = (ne_hi(ov[k], mv[k]) >> 7) + (ne_hi(ov[k], sv[k]) >> 7) +
-                             (ne_hi(ov[k], Uv[k]) >> 7) + (ne_hi(ov[k], Dv[k]) >> 7);
-        const uint32_t nen = (ne_hi(s2v[k], mv[k]) >> 7) + (ne_hi(s2v[k], sv[k]) >> 7) +
-                             (ne_hi(s2v[k], Uv[k]) >> 7) + (ne_hi(s2v[k], Dv[k]) >> 7);
-        dn4[k] = neo + 0x04040404u - nen;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t neo = (((ov[k] ^ mv[k]) + A) & F) + (((ov[k] ^ sv[k]) + A) & F) +
+                                 (((ov[k] ^ Uv[k]) + A) & F) + (((ov[k] ^ Dv[k]) + A) & F);
+            const uint32_t nen = (((s2v[k] ^ mv[k]) + A) & F) + (((s2v[k] ^ sv[k]) + A) & F) +
+                                 (((s2v[k] ^ Uv[k]) + A) & F) + (((s2v[k] ^ Dv[k]) + A) & F);
+            dn4[k] = (neo + (F << 2) - nen) >> b;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t neo = (ne_hi(ov[k], mv[k]) >> 7) + (ne_hi(ov[k], sv[k]) >> 7) +
+                                 (ne_hi(ov[k], Uv[k]) >> 7) + (ne_hi(ov[k], Dv[k]) >> 7);
+            const uint32_t nen = (ne_hi(s2v[k], mv[k]) >> 7) + (ne_hi(s2v[k], sv[k]) >> 7) +
+                                 (ne_hi(s2v[k], Uv[k]) >> 7) + (ne_hi(s2v[k], Dv[k]) >> 7);
+            dn4[k] = neo + 0x04040404u - nen;
+        }
     }
+    // Class: (dn+4)(2q-1) + (s'-s+q-1); with h = 0 the threshold depends on dn
+    // only and thr9 holds the 9 (hi | lo) entries.  d = r - T_hi unsigned:
+    // bit 31 set iff the prefix accepts, 0 iff it ties.
     const uint32_t wq = (uint32_t)(2 * q - 1);
     uint32_t acc_sel[4] = {0u, 0u, 0u, 0u};  // 0xFF in bytes that accept
-    uint32_t amb = 0u;
-    uint32_t cls_keep[16];
+    uint32_t dmin = 0xFFFFFFFFu;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const int sh = 8 * (j & 3);
-        const uint32_t s = (ov[j >> 2] >> sh) & 0xFFu;
-        const uint32_t s2 = (s2v[j >> 2] >> sh) & 0xFFu;
         const uint32_t d4 = (dn4[j >> 2] >> sh) & 0xFFu;
-        const uint32_t cls = d4 * wq + s2 + (uint32_t)(q - 1) - s;
-        cls_keep[j] = cls;
-        const int32_t th = (int32_t)thr[cls];
-        const int32_t r = (int32_t)(w[j] >> 16);
-        const int32_t d = r - th;
-        acc_sel[j >> 2] |= ((uint32_t)(d >> 31)) & (0xFFu << sh);
-        amb |= (d == 0 ? 1u : 0u) << j;
+        uint32_t th;
+        if (HZ) {
+            th = thr9[d4];
+        } else {
+            const uint32_t s = (ov[j >> 2] >> sh) & 0xFFu;
+            const uint32_t s2 = (s2v[j >> 2] >> sh) & 0xFFu;
+            th = thr[__umul24(d4, wq) + s2 + (uint32_t)(q - 1) - s];
+        }
+        const uint32_t d = (w[j] >> 16) - th;
+        acc_sel[j >> 2] |= (uint32_t)((int32_t)d >> 31) & (0xFFu << sh);
+        dmin = min(dmin, d);
     }
-    if (amb) {
+    if (dmin == 0u) {
         for (int j = 0; j < 16; ++j) {
-            if (!((amb >> j) & 1u)) continue;
-            const uint32_t lo = thr[ntab + cls_keep[j]];
-            if (lo == 0u) continue;
+            const int sh = 8 * (j & 3);
+            const uint32_t d4 = (dn4[j >> 2] >> sh) & 0xFFu;
+            uint32_t hi, lo;
+            if (HZ) {
+                hi = thr9[d4];
+                lo = thr9[9 + d4];
+            } else {
+                const uint32_t s = (ov[j >> 2] >> sh) & 0xFFu;
+                const uint32_t s2 = (s2v[j >> 2] >> sh) & 0xFFu;
+                const uint32_t cls = __umul24(d4, wq) + s2 + (uint32_t)(q - 1) - s;
+                hi = thr[cls];
+                lo = thr[ntab + cls];
+            }
+            if ((w[j] >> 16) != hi || lo == 0u) continue;
             uint32_t f[4];
             philox4x32_10(kb + (uint32_t)j, p, rid, kTagFallback, k0, k1, f);
-            if ((f[0] & 0xFFFFu) < lo) acc_sel[j >> 2] |= 0xFFu << (8 * (j & 3));
+            if ((f[0] & 0xFFFFu) < lo) acc_sel[j >> 2] |= 0xFFu << sh;
         }
     }
     uint32_t nv[4];
@@ -290,11 +336,12 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
 // ------------------------------------------------- tile-level iteration
 // Rows [y0, y0+rows) of plane c (y0, rows even).  Rows are visited by parity
 // so that PAR is uniform across a wave.
-template <int MODEL, bool REC>
+template <int MODEL, bool REC, bool HZ = false>
 __device__ __forceinline__ void run_tile(uint8_t* planes, int W, int Ly, int y0, int rows, int c,
                                          uint32_t p, uint32_t rid, uint32_t k0, uint32_t k1,
-                                         const uint32_t* thr, int q, int ntab, uint32_t lem_thr,
-                                         IsingAcc& ia, PottsAcc& pa, int* lhist) {
+                                         const uint32_t* thr, const uint32_t* thr9, int q,
+                                         int ntab, uint32_t lem_thr, IsingAcc& ia, PottsAcc& pa,
+                                         int* lhist) {
     uint8_t* own = planes + (size_t)c * Ly * W;
     const uint8_t* oth = planes + (size_t)(1 - c) * Ly * W;
     const int cpr = W >> 4;
@@ -310,19 +357,41 @@ __device__ __forceinline__ void run_tile(uint8_t* planes, int W, int Ly, int y0,
             const int ym = (y == 0) ? Ly - 1 : y - 1;
             const int yp = (y + 1 == Ly) ? 0 : y + 1;
             if (MODEL == kModelIsing) {
-                if (par == 0)
-                    ising_chunk<0, REC>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, ia);
-                else
-                    ising_chunk<1, REC>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, ia);
+                // handled by run_tile_ising
             } else {
                 if (par == 0)
-                    potts_chunk<0, REC>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, q, ntab,
-                                        lem_thr, pa, lhist);
+                    potts_chunk<0, REC, HZ>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, thr9,
+                                            q, ntab, lem_thr, pa, lhist);
                 else
-                    potts_chunk<1, REC>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, q, ntab,
-                                        lem_thr, pa, lhist);
+                    potts_chunk<1, REC, HZ>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, thr9,
+                                            q, ntab, lem_thr, pa, lhist);
             }
         }
+    }
+}
+
+// Ising rows [y0, y0+rows) of plane c: each lane takes one chunk of each row
+// parity per iteration and issues both chunks' loads before computing.
+template <bool REC>
+__device__ __forceinline__ void run_tile_ising(uint8_t* planes, int W, int Ly, int y0, int rows,
+                                               int c, uint32_t p, uint32_t rid, uint32_t k0,
+                                               uint32_t k1, const uint32_t* thr, IsingAcc& ia) {
+    uint8_t* own = planes + (size_t)c * Ly * W;
+    const uint8_t* oth = planes + (size_t)(1 - c) * Ly * W;
+    const int cpr = W >> 4;
+    const int items = (rows >> 1) * cpr;
+    const int ya = y0 + (c & 1);        // rows with (y + c) & 1 == 0
+    const int yb = y0 + ((c & 1) ^ 1);  // rows with (y + c) & 1 == 1
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        const int r = it / cpr;
+        const int j0 = (it - r * cpr) << 4;
+        const int y_a = ya + 2 * r, y_b = yb + 2 * r;
+        const int ym_a = (y_a == 0) ? Ly - 1 : y_a - 1, yp_a = (y_a + 1 == Ly) ? 0 : y_a + 1;
+        const int ym_b = (y_b == 0) ? Ly - 1 : y_b - 1, yp_b = (y_b + 1 == Ly) ? 0 : y_b + 1;
+        const ChunkIn A = chunk_load<0>(own, oth, W, y_a, ym_a, yp_a, j0);
+        const ChunkIn B = chunk_load<1>(own, oth, W, y_b, ym_b, yp_b, j0);
+        ising_compute<0, REC>(A, own, W, y_a, j0, p, rid, k0, k1, thr, ia);
+        ising_compute<1, REC>(B, own, W, y_b, j0, p, rid, k0, k1, thr, ia);
     }
 }
 
@@ -333,6 +402,32 @@ __device__ __forceinline__ void load_table(const uint32_t* tab, const RepDev& R,
 
 __device__ __forceinline__ uint32_t lemire_threshold(int q) {
     return 65536u % (uint32_t)(q - 1);
+}
+
+// The 9 Potts thresholds of the dn classes (hi | lo) for h = 0, where the
+// class no longer depends on s' - s (column s' = s of the full table).
+__device__ __forceinline__ void load_table9(const uint32_t* tab, const RepDev& R, uint32_t* t9) {
+    if (R.model != kModelPotts) return;
+    const int wq = 2 * R.q - 1;
+    if (threadIdx.x < 18) {
+        const int i = threadIdx.x % 9, half = threadIdx.x / 9;
+        t9[threadIdx.x] = tab[R.tab_off + half * R.tab_n + i * wq + R.q - 1];
+    }
+}
+
+// Potts tile with the h = 0 specialisation chosen per replica.
+template <bool REC>
+__device__ __forceinline__ void potts_tile(const RepDev& R, uint8_t* planes, int y0, int rows,
+                                           int c, uint32_t p, uint32_t k0, uint32_t k1,
+                                           const uint32_t* thr, const uint32_t* thr9,
+                                           IsingAcc& ia, PottsAcc& pa, int* lhist) {
+    const uint32_t lt = lemire_threshold(R.q);
+    if (R.h == 0.0f)
+        run_tile<kModelPotts, REC, true>(planes, R.W, R.Ly, y0, rows, c, p, R.rid, k0, k1, thr,
+                                         thr9, R.q, R.tab_n, lt, ia, pa, lhist);
+    else
+        run_tile<kModelPotts, REC, false>(planes, R.W, R.Ly, y0, rows, c, p, R.rid, k0, k1, thr,
+                                          thr9, R.q, R.tab_n, lt, ia, pa, lhist);
 }
 
 // XCD-aware block order: consecutive logical units land on one XCD (blocks
@@ -348,17 +443,19 @@ __device__ __forceinline__ int logical_block(int n) {
 }  // namespace
 
 // ---------------------------------------------------------------- kernels
-// One colour pass over every row tile of every Ising/Potts replica.
-__global__ void __launch_bounds__(512) k_stream_pass(SweepArgs a, int c, int sweep_off,
-                                                     int rec_row) {
-    extern __shared__ uint32_t lthr[];  // [2 * tab_n] thresholds of this tile's replica
-    __shared__ int lhist[kMaxPottsQ];
-    __shared__ int lred[64];
-    const TileDev T = a.tiles[logical_block(a.n_units)];
+// One colour pass over the row tiles [tile0, tile0 + n) of one model.  The
+// two models have separate kernels so that each gets its own register
+// budget (Ising needs about half of Potts's, hence twice the waves per SIMD).
+template <int MODEL>
+__device__ __forceinline__ void stream_pass_body(const SweepArgs& a, int tile0, int n, int c,
+                                                 int sweep_off, int rec_row, uint32_t* lthr,
+                                                 uint32_t* lthr9, int* lhist, int* lred) {
+    const TileDev T = a.tiles[tile0 + logical_block(n)];
     const RepDev R = a.reps[T.rep];
     load_table(a.tab, R, lthr);
+    if (MODEL == kModelPotts) load_table9(a.tab, R, lthr9);
     const bool rec = (rec_row >= 0) && (c == 1);
-    if (R.model == kModelPotts && rec)
+    if (MODEL == kModelPotts && rec)
         for (int i = threadIdx.x; i < R.q; i += blockDim.x) lhist[i] = 0;
     __syncthreads();
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
@@ -366,25 +463,24 @@ __global__ void __launch_bounds__(512) k_stream_pass(SweepArgs a, int c, int swe
     uint8_t* planes = a.lat + R.lat_off;
     IsingAcc ia{0, 0, 0};
     PottsAcc pa{0, 0, 0};
-    if (R.model == kModelIsing) {
+    if (MODEL == kModelIsing) {
         if (rec)
-            run_tile<kModelIsing, true>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0,
-                                        a.key1, lthr, 2, 0, 0u, ia, pa, lhist);
+            run_tile_ising<true>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
+                                 lthr, ia);
         else
-            run_tile<kModelIsing, false>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0,
-                                         a.key1, lthr, 2, 0, 0u, ia, pa, lhist);
+            run_tile_ising<false>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
+                                  lthr, ia);
     } else {
-        const uint32_t lt = lemire_threshold(R.q);
         if (rec)
-            run_tile<kModelPotts, true>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0,
-                                        a.key1, lthr, R.q, R.tab_n, lt, ia, pa, lhist);
+            potts_tile<true>(R, planes, T.y0, T.rows, c, p, a.key0, a.key1, lthr, lthr9, ia, pa,
+                             lhist);
         else
-            run_tile<kModelPotts, false>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0,
-                                         a.key1, lthr, R.q, R.tab_n, lt, ia, pa, lhist);
+            potts_tile<false>(R, planes, T.y0, T.rows, c, p, a.key0, a.key1, lthr, lthr9, ia, pa,
+                              lhist);
     }
     if (rec) {
         int v[3];
-        if (R.model == kModelIsing) {
+        if (MODEL == kModelIsing) {
             v[0] = ia.M; v[1] = ia.Bx; v[2] = ia.By;
         } else {
             v[0] = pa.Nx; v[1] = pa.Ny; v[2] = pa.S;
@@ -396,12 +492,32 @@ __global__ void __launch_bounds__(512) k_stream_pass(SweepArgs a, int c, int swe
             atomicAdd(&row[1], v[1]);
             atomicAdd(&row[2], v[2]);
         }
-        if (R.model == kModelPotts) {
+        if (MODEL == kModelPotts) {
             __syncthreads();
             for (int i = threadIdx.x; i < R.q; i += blockDim.x)
                 if (lhist[i]) atomicAdd(&a.hist[R.hist_off + i], lhist[i]);
         }
     }
+}
+
+// Occupancy targets: the Ising pass is memory-streaming and wants many
+// waves in flight; the Potts pass is VALU-heavy and keeps more registers.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 8)))
+k_stream_pass_ising(SweepArgs a, int tile0, int n, int c, int sweep_off, int rec_row) {
+    extern __shared__ uint32_t lthr[];  // [2 * tab_n] thresholds of this tile's replica
+    __shared__ uint32_t lthr9[18];
+    __shared__ int lhist[kMaxPottsQ];
+    __shared__ int lred[64];
+    stream_pass_body<kModelIsing>(a, tile0, n, c, sweep_off, rec_row, lthr, lthr9, lhist, lred);
+}
+
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_stream_pass_potts(SweepArgs a, int tile0, int n, int c, int sweep_off, int rec_row) {
+    extern __shared__ uint32_t lthr[];
+    __shared__ uint32_t lthr9[18];
+    __shared__ int lhist[kMaxPottsQ];
+    __shared__ int lred[64];
+    stream_pass_body<kModelPotts>(a, tile0, n, c, sweep_off, rec_row, lthr, lthr9, lhist, lred);
 }
 
 // nmax of each Potts replica from its histogram; clears the histogram.
@@ -518,6 +634,7 @@ __global__ void __launch_bounds__(1024) k_resident(SweepArgs a) {
     extern __shared__ __align__(16) uint8_t dyn[];
     uint32_t* lthr = reinterpret_cast<uint32_t*>(dyn);
     uint8_t* lds = dyn + a.tab_lds_bytes;
+    __shared__ uint32_t lthr9[18];
     __shared__ int lhist[kMaxPottsQ];
     __shared__ int lred[64];
     const int rep = a.rep_list[blockIdx.x];
@@ -533,6 +650,7 @@ __global__ void __launch_bounds__(1024) k_resident(SweepArgs a) {
         for (int i = threadIdx.x; i < bytes; i += blockDim.x) lds[i] = g[i];
     }
     load_table(a.tab, R, lthr);
+    load_table9(a.tab, R, lthr9);
     __syncthreads();
     const uint64_t t0 = *a.t_base;
     const uint32_t lt = (R.model == kModelPotts) ? lemire_threshold(R.q) : 0u;
@@ -545,11 +663,11 @@ __global__ void __launch_bounds__(1024) k_resident(SweepArgs a) {
                 IsingAcc ia{0, 0, 0};
                 PottsAcc pa{0, 0, 0};
                 if (R.model == kModelIsing)
-                    run_tile<kModelIsing, false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0,
-                                                 a.key1, lthr, 2, 0, 0u, ia, pa, lhist);
+                    run_tile_ising<false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0, a.key1,
+                                          lthr, ia);
                 else
-                    run_tile<kModelPotts, false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0,
-                                                 a.key1, lthr, R.q, R.tab_n, lt, ia, pa, lhist);
+                    potts_tile<false>(R, lds, 0, R.Ly, c, p, a.key0, a.key1, lthr, lthr9, ia, pa,
+                                      lhist);
             } else {
                 for (int k = threadIdx.x; k < plane; k += blockDim.x)
                     generic_site(R.model, lds, R.W, R.Ly, c, k, p, R.rid, a.key0, a.key1, lthr,
@@ -704,11 +822,16 @@ hipError_t launch_resident(const SweepArgs& a, int n_list, int model, bool chunk
     return hipGetLastError();
 }
 
-hipError_t launch_stream_pass(const SweepArgs& a, int n_tiles, int c, int sweep_off, int rec_row,
-                              int threads, size_t lds_tab_bytes, hipStream_t s) {
+hipError_t launch_stream_pass(const SweepArgs& a, int model, int tile0, int n_tiles, int c,
+                              int sweep_off, int rec_row, int threads, size_t lds_tab_bytes,
+                              hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_stream_pass, dim3(n_tiles), dim3(threads), lds_tab_bytes, s, a, c,
-                       sweep_off, rec_row);
+    if (model == kModelIsing)
+        hipLaunchKernelGGL(k_stream_pass_ising, dim3(n_tiles), dim3(threads), lds_tab_bytes, s, a,
+                           tile0, n_tiles, c, sweep_off, rec_row);
+    else
+        hipLaunchKernelGGL(k_stream_pass_potts, dim3(n_tiles), dim3(threads), lds_tab_bytes, s, a,
+                           tile0, n_tiles, c, sweep_off, rec_row);
     return hipGetLastError();
 }
 

@@ -46,14 +46,20 @@ struct TileDev {
 
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 bit
 // multiplies and xors; round r uses key + r * (0x9E3779B9, 0xBB67AE85).
+// Each round is two v_mad_u64_u32 and two three-input xors (v_bitop3_b32,
+// truth table 0x96), which the compiler does not form by itself.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t out[4]) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -91,10 +97,9 @@ hipError_t launch_resident(const SweepArgs& a, int n_list, int model, bool chunk
                            size_t lds_bytes, hipStream_t s);
 // Allow the resident kernels up to lds_bytes of dynamic LDS (call outside capture).
 hipError_t resident_reserve_lds(size_t lds_bytes);
-hipError_t launch_stream_pass(const SweepArgs& a, int n_tiles, int c, int sweep_off, int rec_row,
-                              int threads, size_t lds_tab_bytes, hipStream_t s);
-hipError_t launch_persistent(const SweepArgs& a, const int32_t* wg_units, const int32_t* wg_ptr,
-                             int32_t* flags, int n_wg, int threads, hipStream_t s);
+hipError_t launch_stream_pass(const SweepArgs& a, int model, int tile0, int n_tiles, int c,
+                              int sweep_off, int rec_row, int threads, size_t lds_tab_bytes,
+                              hipStream_t s);
 hipError_t launch_potts_hist_finalize(const SweepArgs& a, const int32_t* list, int n, int rec_row,
                                       hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);

@@ -227,3 +227,66 @@ def surrogate_solve(net, target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, st
     res["seconds"] += t_sur
     res["fallback_iters"] = res["iters"] - 1
     return res
+
+
+# ------------------------------------------------------------ experiment
+def experiment(n_points=100_000, L=64, burn=300, measure=700, epochs=60, targets=(0.2, 0.35, 0.5,
+               0.65, 0.8), beta=0.4, tol=0.01, n_rep=64, log=print, seed=1005):
+    """The surrogate workload end to end: labels on the sampler, 90/10
+    train/validation split, training, and for every target the wall time of
+    the surrogate-steered solve against the Monte-Carlo-only solve (both
+    Monte-Carlo-verified to `tol`)."""
+    import synth
+    pts = synth.surrogate_points(n_points, seed=seed)
+    t0 = time.perf_counter()
+    y, se = mc_observables(pts, L=L, burn=burn, measure=measure)
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t0
+    log(f"labels: {n_points} points in {t_label:.1f} s")
+    n_tr = int(0.9 * n_points)
+    net = SurrogateMLP(seed=0)
+    t0 = time.perf_counter()
+    net.fit(pts[:n_tr], y[:n_tr], epochs=epochs, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    pv = net.predict(torch.tensor(pts[n_tr:], device=net.dev)).cpu().numpy()
+    err = np.abs(pv - y[n_tr:])
+    val = dict(mae_e=float(err[:, 0].mean()), mae_absm=float(err[:, 1].mean()),
+               mae_chi=float(err[:, 2].mean()), label_se_absm=float(np.median(se[n_tr:])))
+    log(f"training {t_train:.1f} s; validation MAE {val}")
+    runs = []
+    for tg in targets:
+        mc = mc_only_solve(tg, beta=beta, tol=tol, n_rep=n_rep)
+        su = surrogate_solve(net, tg, beta=beta, tol=tol, n_rep=n_rep)
+        runs.append(dict(target=tg, mc_only=dict((k, mc[k]) for k in ("Jx", "Jy", "absm", "se",
+                                                                       "iters", "seconds",
+                                                                       "converged")),
+                         surrogate=dict((k, su[k]) for k in ("Jx", "Jy", "absm", "se", "iters",
+                                                             "seconds", "converged",
+                                                             "surrogate_guess",
+                                                             "fallback_iters"))))
+        log(f"target {tg}: MC-only {mc['seconds']:.2f} s ({mc['iters']} MC evals), surrogate "
+            f"{su['seconds']:.2f} s ({su['iters']} MC evals)")
+    return dict(label_seconds=t_label, train_seconds=t_train, validation=val, solves=runs,
+                config=dict(n_points=n_points, L=L, burn=burn, measure=measure, epochs=epochs,
+                            beta=beta, tol=tol, n_rep=n_rep))
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--points", type=int, default=100_000)
+    ap.add_argument("--burn", type=int, default=300)
+    ap.add_argument("--measure", type=int, default=700)
+    ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--n-rep", type=int, default=64)
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    res = experiment(n_points=a.points, burn=a.burn, measure=a.measure, epochs=a.epochs,
+                     n_rep=a.n_rep)
+    txt = json.dumps(res)
+    print(txt)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(txt)
