@@ -10,17 +10,33 @@ states, 10^4 sweeps per step.  Inputs are synthetic (seeded), resident in HBM
 before timing starts.
 
 Prints ONE JSON line.  ``value`` is spin-update attempts per ns over the
-timed steps (all replicas, both colours).  ``roofline`` reports the dominant
-kernel (the streamed colour pass) against the 8 TB/s HBM peak with its
-algorithmic traffic of 3 bytes per attempt (read own + other colour plane,
-write own), timed live with HIP events on the sampler's stream.
-``cpu_baseline`` times the oracle (plain C, OpenMP over replicas) on the
-host cores for all replicas of the workload over a few sweeps.
+timed steps (all replicas, both colours; the library's production path of
+cached hipGraph replays).  Right after the timed steps the same workload runs
+``--prof-sweeps`` more sweeps with every kernel launch bracketed by HIP
+events on the stream it is launched on; ``kernels`` lists those per-kernel
+times and ``roofline`` reports the kernel with the largest share:
+
+* a streamed Ising colour pass is HBM bound: 3 algorithmic bytes per attempt
+  (read the colour's plane and the other plane, write the colour's plane);
+* the streamed Potts pass and the LDS-resident kernel are bound by vector
+  ALU issue: peak 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T
+  lane-instructions/s, achieved from the VALU instruction count per attempt
+  that rocprofv3 (SQ_INSTS_VALU) measured on the same kernel source.
+
+``traffic`` is the HBM bytes per launch from rocprofv3 FETCH_SIZE and
+WRITE_SIZE, each scaled by what the counter reads for a plain device copy of
+known size (``--copy-calibration-mib``), taken from the committed counter
+summary when its kernel-source hash matches (else null).  ``--summarize-
+counters DIR...`` writes that summary from rocprofv3 counter runs of this
+script.  ``cpu_baseline`` times the oracle (plain C, OpenMP over replicas) on
+the host cores for all replicas of the workload over a few sweeps.
 """
 import argparse
+import csv
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -28,7 +44,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_ATTEMPT = 3  # per colour pass: read own plane + other plane, write own plane
+VALU_PEAK = 256 * 4 * 16 * 2.4e9   # lane-instructions / s
+BYTES_PER_ATTEMPT = 3              # streamed pass: read own + other plane, write own plane
+COUNTERS = os.path.join(ROOT, "profiles", "counters_batched_ising_potts.json")
+KERNEL_NAMES = {"stream_ising": "k_stream_pass_ising", "stream_potts": "k_stream_pass_potts",
+                "resident": "k_resident"}
 
 
 def kernel_source_hash():
@@ -39,30 +59,68 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic(sites_per_pass):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
-    was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "stream_pass_batched_ising_potts_pmc.json")
-    if not os.path.exists(path):
+def counter_entry(mode, kernel):
+    """Per-attempt counters of one kernel under one schedule mode from the
+    committed summary, or None if absent or taken on other kernel source."""
+    if not os.path.exists(COUNTERS):
         return None
-    with open(path) as f:
+    with open(COUNTERS) as f:
         d = json.load(f)
     if d.get("kernel_source_hash") != kernel_source_hash():
         return None
-    if d.get("sites_per_pass") != sites_per_pass:
-        return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("modes", {}).get(mode, {}).get(kernel)
 
 
-def pass_roofline(kms, nl, sites, kernel, what):
-    avg_s = kms / nl * 1e-3
-    bytes_per_launch = BYTES_PER_ATTEMPT * sites // 2
-    achieved = bytes_per_launch / avg_s / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(sites // 2),
-            "kernel": kernel, "units": what, "launches": nl, "avg_launch_us": round(avg_s * 1e6, 2),
-            "bytes_per_launch": bytes_per_launch,
-            "attempts_per_ns": round(sites // 2 / avg_s / 1e9, 1)}
+def roofline(kind, k, mode_name):
+    """Roofline entry of one kernel kind from its live timing k (ms,
+    launches, attempts per launch)."""
+    avg_s = k["ms"] / k["launches"] * 1e-3
+    att = k["attempts_per_launch"]
+    kernel = KERNEL_NAMES[kind]
+    ce = counter_entry(mode_name, kernel)
+    traffic = None
+    if ce and ce.get("fetch_bytes_per_attempt") is not None \
+            and ce.get("write_bytes_per_attempt") is not None:
+        traffic = int(round((ce["fetch_bytes_per_attempt"] + ce["write_bytes_per_attempt"]) * att))
+    out = {"kernel": kernel, "launches": k["launches"], "avg_launch_us": round(avg_s * 1e6, 2),
+           "attempts_per_launch": att, "attempts_per_ns": round(att / avg_s / 1e9, 1)}
+    if kind == "stream_ising":
+        b = BYTES_PER_ATTEMPT * att
+        ach = b / avg_s / 1e9
+        out.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                   frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic, bytes_per_launch=b)
+    else:
+        out.update(bound="alu", achieved=None, peak=round(VALU_PEAK / 1e12, 2),
+                   unit="T lane-instr/s", frac=None, traffic=traffic)
+        if ce and ce.get("valu_lane_instr_per_attempt"):
+            per = ce["valu_lane_instr_per_attempt"]
+            ach = per * att / avg_s
+            out.update(achieved=round(ach / 1e12, 2), frac=round(ach / VALU_PEAK, 4),
+                       valu_lane_instr_per_attempt=per)
+        if kind == "stream_potts":
+            # the same pass priced against HBM, for reference
+            out["hbm_GBs_algorithmic"] = round(BYTES_PER_ATTEMPT * att / avg_s / 1e9, 1)
+    return out
+
+
+def profiled_kernels(smp, torch, sweeps):
+    """Run `sweeps` sweeps with per-launch HIP-event timing; returns
+    {kind: {ms, launches, avg_us, attempts_per_launch}}."""
+    st, re_ = smp.schedule_sites(by_model=True)
+    smp.profile(True)
+    smp.sweep(sweeps)
+    torch.cuda.synchronize()
+    total = {"stream_ising": st["ising"] // 2 * 2 * sweeps,
+             "stream_potts": st["potts"] // 2 * 2 * sweeps,
+             "resident": (re_["ising"] + re_["potts"]) * sweeps}
+    kern = {}
+    for kind in ("stream_ising", "stream_potts", "resident"):
+        kms, nl = smp.profile_read(kind)
+        if nl:
+            kern[kind] = dict(ms=round(kms, 3), launches=nl, avg_us=round(kms / nl * 1e3, 2),
+                              attempts_per_launch=total[kind] // nl)
+    smp.profile(False)
+    return kern
 
 
 def ising_stream_probe(Sampler, torch, n_rep, sweeps):
@@ -71,18 +129,15 @@ def ising_stream_probe(Sampler, torch, n_rep, sweeps):
     import synth
     reps = synth.batched_ising_potts(n_ising=n_rep, n_potts=0)
     smp = Sampler(reps, seed=2, init=True)
-    smp.set_schedule(mode="stream")
+    chosen, _ = smp.autotune(trial_sweeps=10, mode="stream")
     smp.sweep(2)
     torch.cuda.synchronize()
-    smp.profile(True)
-    smp.sweep(sweeps)
-    torch.cuda.synchronize()
-    kms, nl = smp.profile_read("stream_pass")
-    smp.profile(False)
-    sites = sum(r["Lx"] * r["Ly"] for r in reps)
+    kern = profiled_kernels(smp, torch, sweeps)
     smp.close()
-    return pass_roofline(kms, nl, sites, "k_stream_pass",
-                         f"{n_rep} Ising 256x256 replicas, {sweeps} sweeps")
+    out = roofline("stream_ising", kern["stream_ising"], "stream")
+    out["units"] = f"{n_rep} Ising 256x256 replicas, {sweeps} sweeps"
+    out["schedule"] = chosen
+    return out
 
 
 def cpu_baseline(reps, seed, sweeps):
@@ -108,6 +163,70 @@ def cpu_baseline(reps, seed, sweeps):
                        f"({att:.3g} attempts, {dt:.1f} s wall)")
 
 
+# ------------------------------------------------------------ counter summary
+def _read_run(d):
+    """One rocprofv3 --pmc run of this script: (bench JSON line, csv rows)."""
+    with open(os.path.join(d, "bench.out")) as f:
+        line = [ln for ln in f if ln.startswith("{")][-1]
+    js = json.loads(line)
+    rows = []
+    for name in sorted(os.listdir(d)):
+        if name.endswith("counter_collection.csv"):
+            with open(os.path.join(d, name)) as f:
+                rows += list(csv.DictReader(f))
+    return js, rows
+
+
+def summarize_counters(dirs):
+    """Per-attempt FETCH / WRITE bytes and VALU lane-instructions of each
+    lattice kernel from counter runs (bench.py --steps 0 --warmup 0 ...
+    under rocprofv3 --pmc, one counter per run), calibrated by the plain
+    device copy each run ends with."""
+    modes, calib, cmds = {}, {}, []
+    for d in dirs:
+        js, rows = _read_run(d)
+        cfg = js["config"]
+        mode = cfg["schedule_name"]
+        sw = cfg["profiled_sweeps"]
+        n_copy = cfg["copy_calibration_bytes"]
+        counter = rows[0]["Counter_Name"]
+        cmds.append(f"rocprofv3 --pmc {counter} --output-format csv -d <dir> -o pmc -- "
+                    f"python bench.py {' '.join(js['argv'])}")
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        scale = 1.0
+        if counter in ("FETCH_SIZE", "WRITE_SIZE"):
+            # counter reads KiB; the copy moves n_copy bytes each way
+            scale = n_copy / (max(copies) * 1024.0)
+            calib[counter] = round(scale, 4)
+        st, re_ = cfg["streamed_sites_by_model"], cfg["resident_sites_by_model"]
+        per_disp = {"k_stream_pass_ising": st["ising"] // 2, "k_stream_pass_potts": st["potts"] // 2}
+        res_total = (re_["ising"] + re_["potts"]) * sw
+        m = modes.setdefault(mode, {})
+        for kname in ("k_stream_pass_ising", "k_stream_pass_potts", "k_resident"):
+            vals = [float(r["Counter_Value"]) for r in rows if kname in r["Kernel_Name"]]
+            if not vals:
+                continue
+            if kname == "k_resident":
+                att, v = res_total, sum(vals)
+            else:
+                att, v = per_disp[kname], statistics.median(vals)
+            if att <= 0:
+                continue
+            e = m.setdefault(kname, {"dispatches": len(vals)})
+            e["attempts_per_dispatch" if kname != "k_resident" else "attempts_total"] = att
+            if counter == "FETCH_SIZE":
+                e["fetch_bytes_per_attempt"] = round(v * 1024.0 * scale / att, 4)
+            elif counter == "WRITE_SIZE":
+                e["write_bytes_per_attempt"] = round(v * 1024.0 * scale / att, 4)
+            elif counter == "SQ_INSTS_VALU":
+                e["valu_lane_instr_per_attempt"] = round(v * 64.0 / att, 3)
+    out = {"kernel_source_hash": kernel_source_hash(), "copy_calibration": calib,
+           "commands": cmds, "modes": modes}
+    with open(COUNTERS, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +237,8 @@ def main():
                     choices=["tuned", "auto", "resident", "stream", "hybrid"],
                     help="schedule; 'tuned' runs the library's autotuner first")
     ap.add_argument("--tune-sweeps", type=int, default=20)
+    ap.add_argument("--prof-sweeps", type=int, default=200,
+                    help="sweeps of the per-kernel timing run after the timed steps")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--cpu-sweeps", type=int, default=3)
@@ -127,16 +248,22 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (the reference "
                          "dispatch that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="write the counter summary from rocprofv3 --pmc runs of this script "
+                         "(each DIR holds the run's counter csv and its stdout as bench.out)")
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the workload is "
-                                   "independent replicas, sharded by replica across GPUs with no "
-                                   "communication (see the design notes); --gpus must be 1"}))
+                                   "independent replicas, which shard by replica across GPUs "
+                                   "with no communication; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
     import synth
-    from paper_2304_01772_amd.sampler import Sampler
+    from paper_2304_01772_amd.sampler import Sampler, MODES
 
     reps = synth.batched_ising_potts()
     seed = 2
@@ -151,50 +278,49 @@ def main():
         print(f"# autotune: {tuning}", file=sys.stderr, flush=True)
     else:
         smp.set_schedule(mode=args.mode, tile_rows=args.tile_rows, wg_threads=args.threads)
+    sched = smp.get_schedule()
+    mode_name = {v: k for k, v in MODES.items()}[sched["mode"]]
     for w in range(args.warmup):
         smp.sweep(args.sweeps)
         torch.cuda.synchronize()
         print(f"# warmup step {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    smp.profile(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(smp.stream)
-    for k in range(args.steps):
-        smp.sweep(args.sweeps)
-    e1.record(smp.stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    print(f"# timed {args.steps} steps: {ms:.1f} ms", file=sys.stderr, flush=True)
-    attempts = sites * args.sweeps * args.steps
-    value = attempts / (ms * 1e6)
 
-    # dominant kernel: the streamed colour pass (resident kernel if nothing streams)
-    streamed, resident = smp.schedule_sites()
-    kms, nl = smp.profile_read("stream_pass")
-    rms, rl = smp.profile_read("resident")
-    smp.profile(False)
+    # timed steps: the production path (cached hipGraph replays)
+    ms, value = None, None
+    if args.steps > 0:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(smp.stream)
+        for k in range(args.steps):
+            smp.sweep(args.sweeps)
+        e1.record(smp.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        print(f"# timed {args.steps} steps: {ms:.1f} ms", file=sys.stderr, flush=True)
+        value = sites * args.sweeps * args.steps / (ms * 1e6)
+
+    # per-kernel timing of the same workload right after the timed steps
+    st_m, re_m = smp.schedule_sites(by_model=True)
+    kern = profiled_kernels(smp, torch, args.prof_sweeps)
+    print(f"# kernels over {args.prof_sweeps} profiled sweeps: {kern}", file=sys.stderr,
+          flush=True)
     roof = None
-    if nl > 0 and streamed > 0:
-        roof = pass_roofline(kms, nl, streamed, "k_stream_pass",
-                             "batched Ising+Potts, streamed replicas")
-    elif rl > 0:
-        # LDS-resident multi-sweep kernel: no HBM traffic per sweep; ALU bound
-        per_launch_attempts = resident * args.sweeps
-        rate = per_launch_attempts / (rms / rl * 1e-3)
-        roof = {"bound": "alu", "achieved": round(rate / 1e12, 4), "peak": None,
-                "unit": "Tattempts/s", "frac": None, "traffic": None,
-                "kernel": "k_resident", "launches": rl}
-    sched = smp.get_schedule()
+    if kern:
+        dom = max(kern, key=lambda k: kern[k]["ms"])
+        roof = roofline(dom, kern[dom], mode_name)
+        roof["units"] = f"{mode_name} schedule of the workload, {args.prof_sweeps} sweeps"
     smp.close()
 
+    n_copy = 0
     if args.copy_calibration_mib > 0:
-        n = args.copy_calibration_mib << 20
-        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        n_copy = args.copy_calibration_mib << 20
+        src = torch.ones(n_copy, dtype=torch.uint8, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
     probes = {}
     for n_rep in (() if args.no_probes else (1024, 8192)):
         probes[f"ising_{n_rep}x256x256_stream"] = ising_stream_probe(Sampler, torch, n_rep, 100)
@@ -208,12 +334,12 @@ def main():
 
     out = {
         "metric": "spin-update attempts/ns",
-        "value": round(value, 2),
+        "value": round(value, 2) if value is not None else None,
         "unit": "attempts/ns",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 2),
+        "ms_per_step": round(ms / args.steps, 2) if ms is not None else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -227,13 +353,18 @@ def main():
             "sites_per_sweep": sites,
             "sweeps_per_step": args.sweeps,
             "schedule": sched,
+            "schedule_name": mode_name,
             "autotune": tuning,
-            "streamed_sites": streamed,
-            "resident_sites": resident,
+            "streamed_sites_by_model": st_m,
+            "resident_sites_by_model": re_m,
+            "profiled_sweeps": args.prof_sweeps,
+            "copy_calibration_bytes": n_copy,
         },
         "roofline": roof,
+        "kernels": kern,
         "ising_stream_roofline": probes,
         "cpu_baseline": cpu,
+        "argv": sys.argv[1:],
     }
     print(json.dumps(out), flush=True)
 

@@ -190,14 +190,18 @@ int spinmc_set_schedule(spinmc_ctx *ctx, const spinmc_schedule *s);
 int spinmc_get_schedule(const spinmc_ctx *ctx, spinmc_schedule *s);
 
 /* Sites per sweep that the current schedule streams through colour-pass
- * launches and that it keeps resident in LDS (host out-parameters).        */
-int spinmc_schedule_sites(const spinmc_ctx *ctx, int64_t *streamed, int64_t *resident);
+ * launches and that it keeps resident in LDS, per model: streamed[m] and
+ * resident[m] for m = SPINMC_ISING, SPINMC_POTTS, SPINMC_CPM (host arrays of
+ * 3 entries each, written in full).                                         */
+int spinmc_schedule_sites(const spinmc_ctx *ctx, int64_t streamed[3], int64_t resident[3]);
 
 /* Time candidate schedules for trial_sweeps sweeps each on a scratch copy of
  * the state (the context's state and counter are restored afterwards), pick
  * the fastest, store it, and return it in *chosen (may be NULL) with the
  * measured attempts per ns of every candidate in host_rates (capacity cap,
- * may be NULL; *n_tried receives the count).  Synchronous.                  */
+ * may be NULL; *n_tried receives the count).  If chosen is not NULL and
+ * chosen->mode > 0 on entry, only candidates of that mode are tried.
+ * Synchronous.                                                              */
 int spinmc_autotune(spinmc_ctx *ctx, int32_t trial_sweeps, spinmc_schedule *chosen,
                     double *host_rates, int32_t cap, int32_t *n_tried);
 
@@ -205,12 +209,15 @@ const char *spinmc_last_error(void);
 
 /* Kernel timing with HIP events, for benchmarks.  spinmc_profile(ctx, 1)
  * clears the record and brackets every following sweep-kernel launch with a
- * pair of events on the context's stream; spinmc_profile(ctx, 0) stops.
- * spinmc_profile_read waits for the recorded events and returns, for one
- * kernel class (0 streamed colour pass, 1 resident, 2 persistent, 3 CPM
- * colour pass), the summed elapsed milliseconds and the launch count.       */
+ * pair of events on the stream it is launched on (sweeps then run without
+ * graph replay); spinmc_profile(ctx, 0) stops.  spinmc_profile_read waits
+ * for the recorded events and returns, for one kernel class, the summed
+ * elapsed milliseconds and the launch count.                                */
 enum spinmc_kernel_kind {
-    SPINMC_K_STREAM_PASS = 0, SPINMC_K_RESIDENT = 1, SPINMC_K_PERSISTENT = 2, SPINMC_K_CPM_PASS = 3
+    SPINMC_K_STREAM_ISING = 0,  /* streamed Ising colour pass                 */
+    SPINMC_K_RESIDENT = 1,      /* resident multi-sweep kernel (all groups)   */
+    SPINMC_K_CPM_PASS = 3,      /* CPM colour pass                            */
+    SPINMC_K_STREAM_POTTS = 4   /* streamed Potts colour pass                 */
 };
 int spinmc_profile(spinmc_ctx *ctx, int32_t enable);
 int spinmc_profile_read(spinmc_ctx *ctx, int32_t kind, double *ms_total, int64_t *launches);

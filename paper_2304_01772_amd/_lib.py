@@ -53,7 +53,7 @@ SIGNATURES = {
                                     C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
     "spinmc_set_schedule": (C.c_int, [C.c_void_p, C.POINTER(Schedule)]),
     "spinmc_get_schedule": (C.c_int, [C.c_void_p, C.POINTER(Schedule)]),
-    "spinmc_schedule_sites": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "spinmc_schedule_sites": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "spinmc_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(Schedule),
                                   C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
     "spinmc_last_error": (C.c_char_p, []),

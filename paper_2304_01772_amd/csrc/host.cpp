@@ -36,6 +36,8 @@ constexpr size_t kAlign = 256;
 constexpr int kResidentMaxBytes = 128 * 1024;  // lattice bytes kept in LDS by the resident kernel
 constexpr int kMaxCpmCells = 1 << 20;
 constexpr int kGraphChunk = 50;  // sweeps per captured graph
+constexpr int kSide = 4;         // side streams for concurrent resident groups
+constexpr size_t kResidentLdsBudget = 150 * 1024;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -124,8 +126,17 @@ struct spinmc_ctx {
     // hipGraphs of whole chunks of unrecorded sweeps, keyed by chunk length
     bool use_graphs = true;
     std::map<int, hipGraphExec_t> graphs;
-    hipStream_t cap[2] = {nullptr, nullptr};
-    hipEvent_t cap_ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    // side streams: [0] graph capture origin, [1..kSide] resident groups;
+    // events: [0] fork, [1..kSide] joins
+    hipStream_t cap[1 + kSide] = {};
+    hipEvent_t cap_ev[1 + kSide] = {};
+    // resident workgroup groups (replicas of one shape packed rpb per workgroup)
+    struct ResGroup {
+        int off, count, rpb, threads;
+        bool chunk;
+        size_t slot;
+    };
+    std::vector<ResGroup> res_groups;
     // Cellular Potts
     int8_t* d_ctype = nullptr;
     int32_t* d_target = nullptr;
@@ -173,11 +184,9 @@ hipError_t timed(spinmc_ctx* c, int kind, F&& launch, hipStream_t s) {
 void free_all(spinmc_ctx* c) {
     for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
     c->graphs.clear();
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 1 + kSide; ++k) {
         if (c->cap[k]) hipStreamDestroy(c->cap[k]);
         c->cap[k] = nullptr;
-    }
-    for (int k = 0; k < 4; ++k) {
         if (c->cap_ev[k]) hipEventDestroy(c->cap_ev[k]);
         c->cap_ev[k] = nullptr;
     }
@@ -587,20 +596,18 @@ int spinmc_thresholds(const spinmc_ctx* c, int32_t r, uint64_t* T, int32_t cap, 
     return SPINMC_OK;
 }
 
-int spinmc_schedule_sites(const spinmc_ctx* c, int64_t* streamed, int64_t* resident) {
+int spinmc_schedule_sites(const spinmc_ctx* c, int64_t streamed[3], int64_t resident[3]) {
     if (!c || !streamed || !resident) return fail(SPINMC_E_INVALID, "schedule_sites: null argument");
-    int64_t st = 0, re = 0;
+    for (int m = 0; m < 3; ++m) streamed[m] = resident[m] = 0;
     if (c->cpm) {
-        for (const HostRep& h : c->reps) st += (int64_t)h.dev.Lx * h.dev.Ly;
+        for (const HostRep& h : c->reps) streamed[kModelCpm] += (int64_t)h.dev.Lx * h.dev.Ly;
     } else {
         const int mode = effective_mode(c);
         for (const HostRep& h : c->reps) {
             const bool res = (mode == 1) || !h.chunk || (mode == 3 && h.resident);
-            (res ? re : st) += (int64_t)h.dev.Lx * h.dev.Ly;
+            (res ? resident : streamed)[h.dev.model] += (int64_t)h.dev.Lx * h.dev.Ly;
         }
     }
-    *streamed = st;
-    *resident = re;
     return SPINMC_OK;
 }
 
@@ -739,6 +746,12 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
                     for (int th : {256, 512}) cand.push_back(spinmc_schedule{mode, tr, th, 0});
             }
         }
+    }
+    if (chosen && chosen->mode > 0) {
+        std::vector<spinmc_schedule> keep;
+        for (const auto& k : cand)
+            if (k.mode == chosen->mode) keep.push_back(k);
+        cand.swap(keep);
     }
     if (cand.empty()) return fail(SPINMC_E_UNSUPPORTED, "autotune: no candidate schedule");
     const spinmc_schedule saved_sched = c->sched;
@@ -887,12 +900,32 @@ int prepare(spinmc_ctx* c, int mode) {
     c->res_chunk = res_chunk;
     c->res_gen = res_gen;
     c->stream_potts = spotts;
+    // Resident groups: replicas of one shape, packed rpb per workgroup so
+    // that the workgroup's threads cover about one 16-byte chunk (chunk
+    // path) or one site (per-site path) each per pass, while keeping at
+    // least two workgroups per CU when there are enough replicas.
+    c->res_groups.clear();
     std::vector<int32_t> buf;
-    buf.insert(buf.end(), res_chunk.begin(), res_chunk.end());
-    buf.insert(buf.end(), res_gen.begin(), res_gen.end());
-    if (e == hipSuccess && !buf.empty())
-        e = hipMemcpy(c->d_lists + c->off_res_chunk, buf.data(), sizeof(int32_t) * buf.size(),
-                      hipMemcpyHostToDevice);
+    const int tmax = c->sched.wg_threads > 0 ? c->sched.wg_threads : 512;
+    for (int pass = 0; pass < 2; ++pass) {
+        const std::vector<int32_t>& L = pass == 0 ? res_chunk : res_gen;
+        std::map<std::tuple<int, int>, std::vector<int32_t>> shapes;
+        for (int i : L) shapes[std::make_tuple(c->reps[i].dev.Lx, c->reps[i].dev.Ly)].push_back(i);
+        for (auto& kv : shapes) {
+            const HostRep& h = c->reps[kv.second[0]];
+            const int items = pass == 0 ? (h.dev.Ly / 2) * (h.dev.W / 16) : h.dev.Ly * h.dev.W;
+            const size_t slot = align_up((size_t)8 * c->max_tab_n, 16) + align_up(h.lat_bytes, 16);
+            const int n = (int)kv.second.size();
+            int P = 1;
+            while (P * 2 <= kMaxRpb && P * 2 * items <= tmax && (size_t)(P * 2) * slot <= kResidentLdsBudget &&
+                   n / (P * 2) >= 512)
+                P *= 2;
+            int threads = 64;
+            while (threads < tmax && threads < P * items) threads *= 2;
+            c->res_groups.push_back({(int)buf.size(), n, P, threads, pass == 0, slot});
+            buf.insert(buf.end(), kv.second.begin(), kv.second.end());
+        }
+    }
     if (e == hipSuccess && !spotts.empty())
         e = hipMemcpy(c->d_lists + c->off_rest, spotts.data(), sizeof(int32_t) * spotts.size(),
                       hipMemcpyHostToDevice);
@@ -908,7 +941,7 @@ int prepare(spinmc_ctx* c, int mode) {
     c->n_tiles = (int)tiles.size();
     if (e == hipSuccess && !buf.empty()) {
         size_t lds = 0;
-        for (int i : buf) lds = std::max(lds, resident_lds(c, c->reps[i]));
+        for (const auto& g : c->res_groups) lds = std::max(lds, g.slot * g.rpb);
         e = resident_reserve_lds(lds);
     }
     if (e == hipSuccess) {
@@ -938,25 +971,38 @@ SweepArgs sweep_args(spinmc_ctx* c, int n, int re, int32_t* stats) {
     return a;
 }
 
-// Resident kernels for n sweeps on stream s.
+int ensure_side_streams(spinmc_ctx* c);
+
+// Resident kernels for the call's sweeps: each group on its own side stream,
+// forked from and joined back into stream s (so they overlap one another and
+// whatever s runs meanwhile).  With join = false the caller joins later via
+// join_resident.
 hipError_t enqueue_resident(spinmc_ctx* c, SweepArgs a, hipStream_t s) {
-    hipError_t e = hipSuccess;
-    const int res_threads = c->sched.wg_threads > 0 ? c->sched.wg_threads : 512;
-    size_t lds = 0;
-    for (int i : c->res_chunk) lds = std::max(lds, resident_lds(c, c->reps[i]));
-    if (!c->res_chunk.empty()) {
-        a.rep_list = c->d_lists + c->off_res_chunk;
+    if (c->res_groups.empty()) return hipSuccess;
+    if (ensure_side_streams(c) != SPINMC_OK) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(c->cap_ev[0], s);
+    for (size_t k = 0; k < c->res_groups.size() && e == hipSuccess; ++k) {
+        const auto& g = c->res_groups[k];
+        hipStream_t side = c->cap[1 + k % kSide];
+        if (k < (size_t)kSide) e = hipStreamWaitEvent(side, c->cap_ev[0], 0);
+        if (e != hipSuccess) break;
+        a.rep_list = c->d_lists + c->off_res_chunk + g.off;
+        a.n_list = g.count;
+        a.rpb = g.rpb;
+        a.res_slot_bytes = (int)g.slot;
         e = timed(c, SPINMC_K_RESIDENT, [&] {
-            return launch_resident(a, (int)c->res_chunk.size(), 0, true, res_threads, lds, s);
-        }, s);
+            return launch_resident(a, g.count, 0, g.chunk, g.threads, g.slot * g.rpb, side);
+        }, side);
     }
-    lds = 0;
-    for (int i : c->res_gen) lds = std::max(lds, resident_lds(c, c->reps[i]));
-    if (e == hipSuccess && !c->res_gen.empty()) {
-        a.rep_list = c->d_lists + c->off_res_chunk + c->res_chunk.size();
-        e = timed(c, SPINMC_K_RESIDENT, [&] {
-            return launch_resident(a, (int)c->res_gen.size(), 0, false, res_threads, lds, s);
-        }, s);
+    return e;
+}
+
+hipError_t join_resident(spinmc_ctx* c, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    const size_t used = std::min(c->res_groups.size(), (size_t)kSide);
+    for (size_t k = 0; k < used && e == hipSuccess; ++k) {
+        e = hipEventRecord(c->cap_ev[1 + k], c->cap[1 + k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, c->cap_ev[1 + k], 0);
     }
     return e;
 }
@@ -973,12 +1019,12 @@ hipError_t enqueue_stream(spinmc_ctx* c, const SweepArgs& a, int i0, int n, int 
         for (int col = 0; col < 2 && e == hipSuccess; ++col) {
             const int rr = col == 1 ? row : -1;
             if (ni > 0)
-                e = timed(c, SPINMC_K_STREAM_PASS, [&] {
+                e = timed(c, SPINMC_K_STREAM_ISING, [&] {
                     return launch_stream_pass(a, SPINMC_ISING, 0, ni, col, i, rr, threads,
                                               a.tab_lds_bytes, s);
                 }, s);
             if (e == hipSuccess && np > 0)
-                e = timed(c, SPINMC_K_STREAM_PASS, [&] {
+                e = timed(c, SPINMC_K_STREAM_POTTS, [&] {
                     return launch_stream_pass(a, SPINMC_POTTS, ni, np, col, i, rr, threads,
                                               a.tab_lds_bytes, s);
                 }, s);
@@ -992,12 +1038,12 @@ hipError_t enqueue_stream(spinmc_ctx* c, const SweepArgs& a, int i0, int n, int 
 
 int ensure_side_streams(spinmc_ctx* c) {
     if (c->cap[0]) return SPINMC_OK;
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < 1 + kSide; ++k) {
         if (hipStreamCreateWithFlags(&c->cap[k], hipStreamNonBlocking) != hipSuccess)
             return fail(SPINMC_E_DEVICE, "side stream creation failed");
-    for (int k = 0; k < 4; ++k)
         if (hipEventCreateWithFlags(&c->cap_ev[k], hipEventDisableTiming) != hipSuccess)
             return fail(SPINMC_E_DEVICE, "event creation failed");
+    }
     return SPINMC_OK;
 }
 
@@ -1015,23 +1061,12 @@ int chunk_graph(spinmc_ctx* c, int G, hipGraphExec_t* out) {
     SweepArgs a = sweep_args(c, G, 0, nullptr);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(c->cap[0], hipStreamCaptureModeRelaxed);
-    const bool res = !c->res_chunk.empty() || !c->res_gen.empty();
-    if (e == hipSuccess && res) {
-        e = hipEventRecord(c->cap_ev[0], c->cap[0]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(c->cap[1], c->cap_ev[0], 0);
-        const bool prof = c->prof;
-        c->prof = false;
-        if (e == hipSuccess) e = enqueue_resident(c, a, c->cap[1]);
-        if (e == hipSuccess && c->n_tiles > 0) e = enqueue_stream(c, a, 0, G, 0, c->cap[0]);
-        c->prof = prof;
-        if (e == hipSuccess) e = hipEventRecord(c->cap_ev[1], c->cap[1]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(c->cap[0], c->cap_ev[1], 0);
-    } else if (e == hipSuccess && c->n_tiles > 0) {
-        const bool prof = c->prof;
-        c->prof = false;
-        e = enqueue_stream(c, a, 0, G, 0, c->cap[0]);
-        c->prof = prof;
-    }
+    const bool prof = c->prof;
+    c->prof = false;
+    if (e == hipSuccess) e = enqueue_resident(c, a, c->cap[0]);
+    if (e == hipSuccess && c->n_tiles > 0) e = enqueue_stream(c, a, 0, G, 0, c->cap[0]);
+    if (e == hipSuccess) e = join_resident(c, c->cap[0]);
+    c->prof = prof;
     if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)G, c->cap[0]);
     hipError_t e2 = hipStreamEndCapture(c->cap[0], &g);
     if (e == hipSuccess) e = e2;
@@ -1071,21 +1106,10 @@ int enqueue_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
         // first (resident replicas overwrite theirs)
         e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
     }
-    const bool res = !c->res_chunk.empty() || !c->res_gen.empty();
-    if (res && c->n_tiles > 0) {
-        // resident kernels on a side stream, concurrent with the streamed passes
-        rc = ensure_side_streams(c);
-        if (rc) return rc;
-        if (e == hipSuccess) e = hipEventRecord(c->cap_ev[2], c->stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent(c->cap[1], c->cap_ev[2], 0);
-        if (e == hipSuccess) e = enqueue_resident(c, a, c->cap[1]);
-        if (e == hipSuccess) e = enqueue_stream(c, a, 0, n, re, c->stream);
-        if (e == hipSuccess) e = hipEventRecord(c->cap_ev[3], c->cap[1]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->cap_ev[3], 0);
-    } else {
-        if (e == hipSuccess) e = enqueue_resident(c, a, c->stream);
-        if (e == hipSuccess && c->n_tiles > 0) e = enqueue_stream(c, a, 0, n, re, c->stream);
-    }
+    // resident groups on side streams, concurrent with the streamed passes
+    if (e == hipSuccess) e = enqueue_resident(c, a, c->stream);
+    if (e == hipSuccess && c->n_tiles > 0) e = enqueue_stream(c, a, 0, n, re, c->stream);
+    if (e == hipSuccess) e = join_resident(c, c->stream);
     if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)n, c->stream);
     return check_dev(c, e, "sweep");
 }

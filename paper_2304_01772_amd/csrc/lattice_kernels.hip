@@ -334,38 +334,36 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
 }
 
 // ------------------------------------------------- tile-level iteration
-// Rows [y0, y0+rows) of plane c (y0, rows even).  Rows are visited by parity
-// so that PAR is uniform across a wave.
-template <int MODEL, bool REC, bool HZ = false>
-__device__ __forceinline__ void run_tile(uint8_t* planes, int W, int Ly, int y0, int rows, int c,
-                                         uint32_t p, uint32_t rid, uint32_t k0, uint32_t k1,
-                                         const uint32_t* thr, const uint32_t* thr9, int q,
-                                         int ntab, uint32_t lem_thr, IsingAcc& ia, PottsAcc& pa,
-                                         int* lhist) {
+// Rows [y0, y0+rows) of plane c (y0, rows even), split over threads
+// tid = 0..nthr-1 (a whole workgroup, or the share of one replica when a
+// workgroup holds several).  Rows are visited by parity so that PAR is
+// uniform across a wave.
+template <bool REC, bool HZ>
+__device__ __forceinline__ void run_tile_potts(uint8_t* planes, int W, int Ly, int y0, int rows,
+                                               int c, uint32_t p, uint32_t rid, uint32_t k0,
+                                               uint32_t k1, const uint32_t* thr,
+                                               const uint32_t* thr9, int q, int ntab,
+                                               uint32_t lem_thr, PottsAcc& pa, int* lhist,
+                                               int tid, int nthr) {
     uint8_t* own = planes + (size_t)c * Ly * W;
     const uint8_t* oth = planes + (size_t)(1 - c) * Ly * W;
     const int cpr = W >> 4;
-    const int half = rows >> 1;
-    const int items = half * cpr;
+    const int items = (rows >> 1) * cpr;
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
         const int yf = y0 + ((par ^ c) & 1);
-        for (int it = threadIdx.x; it < items; it += blockDim.x) {
+        for (int it = tid; it < items; it += nthr) {
             const int r = it / cpr;
             const int j0 = (it - r * cpr) << 4;
             const int y = yf + 2 * r;
             const int ym = (y == 0) ? Ly - 1 : y - 1;
             const int yp = (y + 1 == Ly) ? 0 : y + 1;
-            if (MODEL == kModelIsing) {
-                // handled by run_tile_ising
-            } else {
-                if (par == 0)
-                    potts_chunk<0, REC, HZ>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, thr9,
-                                            q, ntab, lem_thr, pa, lhist);
-                else
-                    potts_chunk<1, REC, HZ>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, thr9,
-                                            q, ntab, lem_thr, pa, lhist);
-            }
+            if (par == 0)
+                potts_chunk<0, REC, HZ>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, thr9, q,
+                                        ntab, lem_thr, pa, lhist);
+            else
+                potts_chunk<1, REC, HZ>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, thr9, q,
+                                        ntab, lem_thr, pa, lhist);
         }
     }
 }
@@ -375,14 +373,15 @@ __device__ __forceinline__ void run_tile(uint8_t* planes, int W, int Ly, int y0,
 template <bool REC>
 __device__ __forceinline__ void run_tile_ising(uint8_t* planes, int W, int Ly, int y0, int rows,
                                                int c, uint32_t p, uint32_t rid, uint32_t k0,
-                                               uint32_t k1, const uint32_t* thr, IsingAcc& ia) {
+                                               uint32_t k1, const uint32_t* thr, IsingAcc& ia,
+                                               int tid, int nthr) {
     uint8_t* own = planes + (size_t)c * Ly * W;
     const uint8_t* oth = planes + (size_t)(1 - c) * Ly * W;
     const int cpr = W >> 4;
     const int items = (rows >> 1) * cpr;
     const int ya = y0 + (c & 1);        // rows with (y + c) & 1 == 0
     const int yb = y0 + ((c & 1) ^ 1);  // rows with (y + c) & 1 == 1
-    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    for (int it = tid; it < items; it += nthr) {
         const int r = it / cpr;
         const int j0 = (it - r * cpr) << 4;
         const int y_a = ya + 2 * r, y_b = yb + 2 * r;
@@ -395,9 +394,10 @@ __device__ __forceinline__ void run_tile_ising(uint8_t* planes, int W, int Ly, i
     }
 }
 
-__device__ __forceinline__ void load_table(const uint32_t* tab, const RepDev& R, uint32_t* lthr) {
+__device__ __forceinline__ void load_table(const uint32_t* tab, const RepDev& R, uint32_t* lthr,
+                                           int tid, int nthr) {
     const int n2 = 2 * R.tab_n;
-    for (int i = threadIdx.x; i < n2; i += blockDim.x) lthr[i] = tab[R.tab_off + i];
+    for (int i = tid; i < n2; i += nthr) lthr[i] = tab[R.tab_off + i];
 }
 
 __device__ __forceinline__ uint32_t lemire_threshold(int q) {
@@ -406,12 +406,13 @@ __device__ __forceinline__ uint32_t lemire_threshold(int q) {
 
 // The 9 Potts thresholds of the dn classes (hi | lo) for h = 0, where the
 // class no longer depends on s' - s (column s' = s of the full table).
-__device__ __forceinline__ void load_table9(const uint32_t* tab, const RepDev& R, uint32_t* t9) {
+__device__ __forceinline__ void load_table9(const uint32_t* tab, const RepDev& R, uint32_t* t9,
+                                            int tid) {
     if (R.model != kModelPotts) return;
     const int wq = 2 * R.q - 1;
-    if (threadIdx.x < 18) {
-        const int i = threadIdx.x % 9, half = threadIdx.x / 9;
-        t9[threadIdx.x] = tab[R.tab_off + half * R.tab_n + i * wq + R.q - 1];
+    if (tid < 18) {
+        const int i = tid % 9, half = tid / 9;
+        t9[tid] = tab[R.tab_off + half * R.tab_n + i * wq + R.q - 1];
     }
 }
 
@@ -420,14 +421,14 @@ template <bool REC>
 __device__ __forceinline__ void potts_tile(const RepDev& R, uint8_t* planes, int y0, int rows,
                                            int c, uint32_t p, uint32_t k0, uint32_t k1,
                                            const uint32_t* thr, const uint32_t* thr9,
-                                           IsingAcc& ia, PottsAcc& pa, int* lhist) {
+                                           PottsAcc& pa, int* lhist, int tid, int nthr) {
     const uint32_t lt = lemire_threshold(R.q);
     if (R.h == 0.0f)
-        run_tile<kModelPotts, REC, true>(planes, R.W, R.Ly, y0, rows, c, p, R.rid, k0, k1, thr,
-                                         thr9, R.q, R.tab_n, lt, ia, pa, lhist);
+        run_tile_potts<REC, true>(planes, R.W, R.Ly, y0, rows, c, p, R.rid, k0, k1, thr, thr9, R.q,
+                                  R.tab_n, lt, pa, lhist, tid, nthr);
     else
-        run_tile<kModelPotts, REC, false>(planes, R.W, R.Ly, y0, rows, c, p, R.rid, k0, k1, thr,
-                                          thr9, R.q, R.tab_n, lt, ia, pa, lhist);
+        run_tile_potts<REC, false>(planes, R.W, R.Ly, y0, rows, c, p, R.rid, k0, k1, thr, thr9,
+                                   R.q, R.tab_n, lt, pa, lhist, tid, nthr);
 }
 
 // XCD-aware block order: consecutive logical units land on one XCD (blocks
@@ -452,8 +453,8 @@ __device__ __forceinline__ void stream_pass_body(const SweepArgs& a, int tile0, 
                                                  uint32_t* lthr9, int* lhist, int* lred) {
     const TileDev T = a.tiles[tile0 + logical_block(n)];
     const RepDev R = a.reps[T.rep];
-    load_table(a.tab, R, lthr);
-    if (MODEL == kModelPotts) load_table9(a.tab, R, lthr9);
+    load_table(a.tab, R, lthr, threadIdx.x, blockDim.x);
+    if (MODEL == kModelPotts) load_table9(a.tab, R, lthr9, threadIdx.x);
     const bool rec = (rec_row >= 0) && (c == 1);
     if (MODEL == kModelPotts && rec)
         for (int i = threadIdx.x; i < R.q; i += blockDim.x) lhist[i] = 0;
@@ -466,17 +467,17 @@ __device__ __forceinline__ void stream_pass_body(const SweepArgs& a, int tile0, 
     if (MODEL == kModelIsing) {
         if (rec)
             run_tile_ising<true>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
-                                 lthr, ia);
+                                 lthr, ia, threadIdx.x, blockDim.x);
         else
             run_tile_ising<false>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
-                                  lthr, ia);
+                                  lthr, ia, threadIdx.x, blockDim.x);
     } else {
         if (rec)
-            potts_tile<true>(R, planes, T.y0, T.rows, c, p, a.key0, a.key1, lthr, lthr9, ia, pa,
-                             lhist);
+            potts_tile<true>(R, planes, T.y0, T.rows, c, p, a.key0, a.key1, lthr, lthr9, pa,
+                             lhist, threadIdx.x, blockDim.x);
         else
-            potts_tile<false>(R, planes, T.y0, T.rows, c, p, a.key0, a.key1, lthr, lthr9, ia, pa,
-                              lhist);
+            potts_tile<false>(R, planes, T.y0, T.rows, c, p, a.key0, a.key1, lthr, lthr9, pa,
+                              lhist, threadIdx.x, blockDim.x);
     }
     if (rec) {
         int v[3];
@@ -626,82 +627,100 @@ __device__ __forceinline__ void lattice_stats(int model, const uint8_t* planes, 
 
 }  // namespace
 
-// Resident kernel: one workgroup owns one replica for the whole call, with
-// both planes in LDS.  CHUNK selects the 16-byte SWAR path (W % 16 == 0).
+// Resident kernel: a workgroup owns a.rpb replicas of one shape for the
+// whole call, each with its thresholds and both planes in LDS, and
+// blockDim/rpb threads; colour passes are separated by workgroup barriers.
+// CHUNK selects the 16-byte SWAR path (W % 16 == 0).
 template <bool CHUNK>
 __global__ void __launch_bounds__(1024) k_resident(SweepArgs a) {
-    // dynamic LDS: [thresholds (tab_lds_bytes) | plane 0 | plane 1]
+    // dynamic LDS: rpb slots of [thresholds (tab_lds_bytes) | plane 0 | plane 1]
     extern __shared__ __align__(16) uint8_t dyn[];
-    uint32_t* lthr = reinterpret_cast<uint32_t*>(dyn);
-    uint8_t* lds = dyn + a.tab_lds_bytes;
-    __shared__ uint32_t lthr9[18];
+    __shared__ uint32_t lthr9[kMaxRpb][18];
     __shared__ int lhist[kMaxPottsQ];
     __shared__ int lred[64];
-    const int rep = a.rep_list[blockIdx.x];
+    const int P = a.rpb;
+    const int nt = blockDim.x / P;
+    const int g = threadIdx.x / nt, lt = threadIdx.x - g * nt;
+    const int first = blockIdx.x * P;
+    const bool active = g < P && first + g < a.n_list;
+    const int rep = a.rep_list[active ? first + g : first];
     const RepDev R = a.reps[rep];
+    uint8_t* slot = dyn + (size_t)(active ? g : 0) * a.res_slot_bytes;
+    uint32_t* lthr = reinterpret_cast<uint32_t*>(slot);
+    uint8_t* lds = slot + a.tab_lds_bytes;
     const int plane = R.Ly * R.W;
     const int bytes = 2 * plane;
-    uint8_t* g = a.lat + R.lat_off;
-    // load the lattice (16-byte granules where possible)
-    if ((bytes & 15) == 0) {
-        for (int i = threadIdx.x; i < (bytes >> 4); i += blockDim.x)
-            reinterpret_cast<uint4*>(lds)[i] = reinterpret_cast<const uint4*>(g)[i];
-    } else {
-        for (int i = threadIdx.x; i < bytes; i += blockDim.x) lds[i] = g[i];
+    uint8_t* gmem = a.lat + R.lat_off;
+    if (active) {
+        if ((bytes & 15) == 0) {
+            for (int i = lt; i < (bytes >> 4); i += nt)
+                reinterpret_cast<uint4*>(lds)[i] = reinterpret_cast<const uint4*>(gmem)[i];
+        } else {
+            for (int i = lt; i < bytes; i += nt) lds[i] = gmem[i];
+        }
+        load_table(a.tab, R, lthr, lt, nt);
+        load_table9(a.tab, R, lthr9[g], lt);
     }
-    load_table(a.tab, R, lthr);
-    load_table9(a.tab, R, lthr9);
     __syncthreads();
     const uint64_t t0 = *a.t_base;
-    const uint32_t lt = (R.model == kModelPotts) ? lemire_threshold(R.q) : 0u;
     for (int i = 0; i < a.n_sweeps; ++i) {
         const uint64_t t = t0 + (uint64_t)i;
-        const bool rec = a.record_every > 0 && ((i + 1) % a.record_every) == 0;
         for (int c = 0; c < 2; ++c) {
             const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
-            if (CHUNK) {
-                IsingAcc ia{0, 0, 0};
-                PottsAcc pa{0, 0, 0};
-                if (R.model == kModelIsing)
-                    run_tile_ising<false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0, a.key1,
-                                          lthr, ia);
-                else
-                    potts_tile<false>(R, lds, 0, R.Ly, c, p, a.key0, a.key1, lthr, lthr9, ia, pa,
-                                      lhist);
-            } else {
-                for (int k = threadIdx.x; k < plane; k += blockDim.x)
-                    generic_site(R.model, lds, R.W, R.Ly, c, k, p, R.rid, a.key0, a.key1, lthr,
-                                 R.q, R.tab_n);
+            if (active) {
+                if (CHUNK) {
+                    IsingAcc ia{0, 0, 0};
+                    PottsAcc pa{0, 0, 0};
+                    if (R.model == kModelIsing)
+                        run_tile_ising<false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0, a.key1,
+                                              lthr, ia, lt, nt);
+                    else
+                        potts_tile<false>(R, lds, 0, R.Ly, c, p, a.key0, a.key1, lthr, lthr9[g],
+                                          pa, lhist, lt, nt);
+                } else {
+                    for (int k = lt; k < plane; k += nt)
+                        generic_site(R.model, lds, R.W, R.Ly, c, k, p, R.rid, a.key0, a.key1,
+                                     lthr, R.q, R.tab_n);
+                }
             }
             __syncthreads();
         }
-        if (rec) {
-            if (R.model == kModelPotts) {
-                for (int k = threadIdx.x; k < R.q; k += blockDim.x) lhist[k] = 0;
+        if (a.record_every > 0 && ((i + 1) % a.record_every) == 0) {
+            // statistics of each replica of the workgroup, all threads per replica
+            for (int gg = 0; gg < P && first + gg < a.n_list; ++gg) {
+                const int rg = a.rep_list[first + gg];
+                const RepDev Q = a.reps[rg];
+                const uint8_t* lq = dyn + (size_t)gg * a.res_slot_bytes + a.tab_lds_bytes;
+                if (Q.model == kModelPotts) {
+                    for (int k = threadIdx.x; k < Q.q; k += blockDim.x) lhist[k] = 0;
+                    __syncthreads();
+                }
+                int v[3] = {0, 0, 0};
+                lattice_stats(Q.model, lq, Q.Lx, Q.Ly, Q.W, 0, Q.Lx * Q.Ly, v, lhist);
+                block_sum<3>(v, lred);
+                int32_t* row =
+                    a.stats + ((size_t)((i + 1) / a.record_every - 1) * a.R + rg) * a.width;
+                if (threadIdx.x == 0) {
+                    row[0] = v[0];
+                    row[1] = v[1];
+                    row[2] = v[2];
+                    int mx = 0;
+                    if (Q.model == kModelPotts)
+                        for (int k = 0; k < Q.q; ++k) mx = lhist[k] > mx ? lhist[k] : mx;
+                    row[3] = mx;
+                    for (int k = 4; k < a.width; ++k) row[k] = 0;
+                }
                 __syncthreads();
             }
-            int v[3] = {0, 0, 0};
-            lattice_stats(R.model, lds, R.Lx, R.Ly, R.W, 0, R.Lx * R.Ly, v, lhist);
-            block_sum<3>(v, lred);
-            int32_t* row = a.stats + ((size_t)((i + 1) / a.record_every - 1) * a.R + rep) * a.width;
-            if (threadIdx.x == 0) {
-                row[0] = v[0];
-                row[1] = v[1];
-                row[2] = v[2];
-                int mx = 0;
-                if (R.model == kModelPotts)
-                    for (int k = 0; k < R.q; ++k) mx = lhist[k] > mx ? lhist[k] : mx;
-                row[3] = mx;
-                for (int k = 4; k < a.width; ++k) row[k] = 0;
-            }
-            __syncthreads();
         }
     }
-    if ((bytes & 15) == 0) {
-        for (int i = threadIdx.x; i < (bytes >> 4); i += blockDim.x)
-            reinterpret_cast<uint4*>(g)[i] = reinterpret_cast<const uint4*>(lds)[i];
-    } else {
-        for (int i = threadIdx.x; i < bytes; i += blockDim.x) g[i] = lds[i];
+    if (active) {
+        if ((bytes & 15) == 0) {
+            for (int i = lt; i < (bytes >> 4); i += nt)
+                reinterpret_cast<uint4*>(gmem)[i] = reinterpret_cast<const uint4*>(lds)[i];
+        } else {
+            for (int i = lt; i < bytes; i += nt) gmem[i] = lds[i];
+        }
     }
 }
 
@@ -815,10 +834,11 @@ hipError_t launch_resident(const SweepArgs& a, int n_list, int model, bool chunk
                            size_t lds_bytes, hipStream_t s) {
     (void)model;
     if (n_list <= 0) return hipSuccess;
+    const int blocks = (n_list + a.rpb - 1) / a.rpb;
     if (chunk)
-        hipLaunchKernelGGL(k_resident<true>, dim3(n_list), dim3(threads), lds_bytes, s, a);
+        hipLaunchKernelGGL(k_resident<true>, dim3(blocks), dim3(threads), lds_bytes, s, a);
     else
-        hipLaunchKernelGGL(k_resident<false>, dim3(n_list), dim3(threads), lds_bytes, s, a);
+        hipLaunchKernelGGL(k_resident<false>, dim3(blocks), dim3(threads), lds_bytes, s, a);
     return hipGetLastError();
 }
 

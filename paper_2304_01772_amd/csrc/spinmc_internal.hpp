@@ -18,6 +18,7 @@ constexpr uint32_t kTagInit = 2u;
 constexpr int kIsingClasses = 18;
 constexpr int kMaxPottsQ = 128;   // labels fit in 7 bits (SWAR equality test)
 constexpr int kMaxCpmTypes = 4;
+constexpr int kMaxRpb = 16;       // replicas per resident workgroup
 
 // Per-replica record, device visible.
 struct RepDev {
@@ -88,6 +89,9 @@ struct SweepArgs {
     int32_t n_sweeps, record_every;
     int32_t n_units;
     int32_t tab_lds_bytes;        // bytes of LDS reserved for thresholds (multiple of 16)
+    // resident kernels: replicas per workgroup, LDS bytes per replica slot,
+    // and the number of entries of rep_list
+    int32_t rpb, res_slot_bytes, n_list;
 };
 
 // Host-side launchers implemented in the kernel translation units.

@@ -151,7 +151,7 @@ class Sampler:
         return means, grads, dth
 
     # ------------------------------------------------------------- timing
-    KERNELS = {"stream_pass": 0, "resident": 1, "persistent": 2, "cpm_pass": 3}
+    KERNELS = {"stream_ising": 0, "resident": 1, "cpm_pass": 3, "stream_potts": 4}
 
     def profile(self, enable=True):
         check(lib().spinmc_profile(self.ctx, 1 if enable else 0))
@@ -174,14 +174,21 @@ class Sampler:
         check(lib().spinmc_get_schedule(self.ctx, C.byref(s)))
         return dict(mode=s.mode, tile_rows=s.tile_rows, wg_threads=s.wg_threads)
 
-    def schedule_sites(self):
-        """(streamed, resident) sites per sweep under the current schedule."""
-        a, b = C.c_int64(), C.c_int64()
-        check(lib().spinmc_schedule_sites(self.ctx, C.byref(a), C.byref(b)))
-        return int(a.value), int(b.value)
+    def schedule_sites(self, by_model=False):
+        """(streamed, resident) sites per sweep under the current schedule;
+        with by_model, two dicts keyed "ising", "potts", "cpm"."""
+        a, b = (C.c_int64 * 3)(), (C.c_int64 * 3)()
+        check(lib().spinmc_schedule_sites(self.ctx, a, b))
+        if by_model:
+            names = ("ising", "potts", "cpm")
+            return ({n: int(a[i]) for i, n in enumerate(names)},
+                    {n: int(b[i]) for i, n in enumerate(names)})
+        return int(sum(a)), int(sum(b))
 
-    def autotune(self, trial_sweeps=20):
-        s = Schedule()
+    def autotune(self, trial_sweeps=20, mode=None):
+        """Time candidate schedules (optionally of one mode) and keep the
+        fastest; returns (schedule dict, candidate rates in attempts/ns)."""
+        s = Schedule(MODES[mode] if isinstance(mode, str) else int(mode or 0), 0, 0, 0)
         rates = (C.c_double * 64)()
         n = C.c_int32()
         check(lib().spinmc_autotune(self.ctx, int(trial_sweeps), C.byref(s), rates, 64,

@@ -261,3 +261,41 @@ def test_hybrid_graphs_and_autotune_keep_the_chain(S):
         states[i], _ = _run_oracle(r, states[i], seed, t0, 5, 0)
         assert np.array_equal(smp.get_state(i), states[i]), (chosen, i)
     smp.close()
+
+
+@pytest.mark.parametrize("shape,n", [((32, 32), 2048), ((6, 10), 1101), ((64, 64), 1027)])
+def test_resident_packing_many_small_replicas(S, shape, n):
+    """Enough replicas of one small shape that the resident kernel packs
+    several per workgroup (each with its own thresholds and LDS slot)."""
+    Lx, Ly = shape
+    rng = np.random.default_rng(n + Lx)
+    reps = [dict(model=int(i % 3 == 0), Lx=Lx, Ly=Ly, q=int(rng.integers(2, 9)),
+                 Jx=1.0, Jy=1.0, h=0.0, beta=float(rng.uniform(0.2, 1.5)), rid=i) for i in range(n)]
+    for r in reps:
+        if r["model"] == 0:
+            r["Jx"] = r["Jy"] = _f32(rng.uniform(0.5, 1.5))
+    seed = 1234
+    smp = S(reps, seed, init=True)
+    smp.set_schedule(mode="resident")
+    st = smp.sweep(12, 4)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    ising = [i for i, r in enumerate(reps) if r["model"] == 0]
+    potts = [i for i, r in enumerate(reps) if r["model"] == 1]
+    si = [orc.ising_init(Lx, Ly, seed, reps[i]["rid"]) for i in ising]
+    out_i, st_i = orc.ising_run_batch(si, [reps[i]["Jx"] for i in ising], [reps[i]["Jy"] for i in ising],
+                                      [0.0] * len(ising), [reps[i]["beta"] for i in ising], seed,
+                                      np.array([reps[i]["rid"] for i in ising]), 0, 12, 4)
+    sp = [orc.potts_init(Lx, Ly, reps[i]["q"], seed, reps[i]["rid"]) for i in potts]
+    out_p, st_p = orc.potts_run_batch(sp, [reps[i]["q"] for i in potts], [1.0] * len(potts),
+                                      [0.0] * len(potts), [reps[i]["beta"] for i in potts], seed,
+                                      np.array([reps[i]["rid"] for i in potts]), 0, 12, 4)
+    for k, i in enumerate(ising):
+        assert np.array_equal(st[:, i], st_i[k]), i
+    for k, i in enumerate(potts):
+        assert np.array_equal(st[:, i], st_p[k]), i
+    for k, i in list(enumerate(ising))[:50] + list(enumerate(ising))[-50:]:
+        assert np.array_equal(smp.get_state(i), out_i[k])
+    for k, i in list(enumerate(potts))[:50] + list(enumerate(potts))[-50:]:
+        assert np.array_equal(smp.get_state(i), out_p[k])
+    smp.close()
