@@ -114,7 +114,7 @@ struct spinmc_ctx {
     int32_t* d_hist = nullptr;
     int32_t* d_lists = nullptr;  // [all | potts | chunk-resident | generic-resident | stream-exempt]
     std::vector<int32_t> all_list, potts_list, res_chunk, res_gen, stream_rest;
-    int off_all = 0, off_potts = 0, off_res_chunk = 0, off_res_gen = 0, off_rest = 0;
+    int off_all = 0, off_potts = 0, off_res_chunk = 0, off_rest = 0;
     TileDev* d_tiles = nullptr;
     int n_tiles = 0;
     int n_tiles_ising = 0;  // streamed Ising tiles come first in d_tiles
@@ -480,7 +480,6 @@ int spinmc_create(const spinmc_replica_desc* d, int32_t n, uint64_t seed, int32_
     c->off_all = 0;
     c->off_potts = n;
     c->off_res_chunk = 2 * n;
-    c->off_res_gen = 3 * n;
     c->off_rest = 4 * n;
     std::copy(c->all_list.begin(), c->all_list.end(), lists.begin() + c->off_all);
     std::copy(c->potts_list.begin(), c->potts_list.end(), lists.begin() + c->off_potts);
@@ -926,6 +925,11 @@ int prepare(spinmc_ctx* c, int mode) {
             buf.insert(buf.end(), kv.second.begin(), kv.second.end());
         }
     }
+    // buf holds every resident replica once (at most R entries): the region
+    // [off_res_chunk, off_res_chunk + R) of the list buffer
+    if (e == hipSuccess && !buf.empty())
+        e = hipMemcpy(c->d_lists + c->off_res_chunk, buf.data(), sizeof(int32_t) * buf.size(),
+                      hipMemcpyHostToDevice);
     if (e == hipSuccess && !spotts.empty())
         e = hipMemcpy(c->d_lists + c->off_rest, spotts.data(), sizeof(int32_t) * spotts.size(),
                       hipMemcpyHostToDevice);
