@@ -182,9 +182,10 @@ def summarize_counters(dirs):
     lattice kernel from counter runs (bench.py --steps 0 --warmup 0 ...
     under rocprofv3 --pmc, one counter per run), calibrated by the plain
     device copy each run ends with."""
-    modes, calib, cmds = {}, {}, []
+    modes, calib, cmds, hashes = {}, {}, [], set()
     for d in dirs:
         js, rows = _read_run(d)
+        hashes.add(js["kernel_source_hash"])
         cfg = js["config"]
         mode = cfg["schedule_name"]
         sw = cfg["profiled_sweeps"]
@@ -220,7 +221,9 @@ def summarize_counters(dirs):
                 e["write_bytes_per_attempt"] = round(v * 1024.0 * scale / att, 4)
             elif counter == "SQ_INSTS_VALU":
                 e["valu_lane_instr_per_attempt"] = round(v * 64.0 / att, 3)
-    out = {"kernel_source_hash": kernel_source_hash(), "copy_calibration": calib,
+    if len(hashes) != 1:
+        raise SystemExit(f"counter runs were taken on different kernel sources: {hashes}")
+    out = {"kernel_source_hash": hashes.pop(), "copy_calibration": calib,
            "commands": cmds, "modes": modes}
     with open(COUNTERS, "w") as f:
         json.dump(out, f, indent=1)
@@ -241,7 +244,7 @@ def main():
                     help="sweeps of the per-kernel timing run after the timed steps")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
-    ap.add_argument("--cpu-sweeps", type=int, default=3)
+    ap.add_argument("--cpu-sweeps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true",
                     help="skip the Ising streaming probes (for counter collection runs)")
@@ -365,6 +368,7 @@ def main():
         "ising_stream_roofline": probes,
         "cpu_baseline": cpu,
         "argv": sys.argv[1:],
+        "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)
 

@@ -57,6 +57,13 @@ struct IsingAcc {
     int M, Bx, By;
 };
 
+// 0xFF in byte i where d_i is negative (bit 31 set), else 0: v_perm_b32
+// selectors 9 and 11 replicate bit 31 of its low and high source dword,
+// 12 gives zero.
+__device__ __forceinline__ uint32_t sign_bytes(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3) {
+    return __builtin_amdgcn_perm(d1, d0, 0x0C0C0B09u) | __builtin_amdgcn_perm(d3, d2, 0x0B090C0Cu);
+}
+
 // ---------------------------------------------------------------- Ising
 // One 16-site chunk of plane row y starting at byte j0 (j0 % 16 == 0,
 // W % 16 == 0): own bytes, the other plane's rows y-1, y, y+1, and the halo
@@ -106,12 +113,14 @@ __device__ __forceinline__ void ising_compute(const ChunkIn& in, uint8_t* own, i
         sv[2] = __builtin_amdgcn_alignbyte(mv[3], mv[2], 1);
         sv[3] = __builtin_amdgcn_alignbyte(e, mv[3], 1);
     }
-    uint32_t idx[4];
+    // class 9u + 3nx + ny per byte (< 18), times 4: the byte offset of its
+    // threshold in LDS (< 72, still one byte)
+    uint32_t idx4[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const uint32_t nx = mv[k] + sv[k];
         const uint32_t ny = Uv[k] + Dv[k];
-        idx[k] = (ov[k] << 3) + ov[k] + (nx << 1) + nx + ny;  // 9u + 3nx + ny per byte
+        idx4[k] = ((ov[k] << 3) + ov[k] + (nx << 1) + nx + ny) << 2;
     }
     const uint32_t kb = (uint32_t)(ro + j0);  // within-colour index of the first site
     uint32_t w[8];
@@ -119,22 +128,24 @@ __device__ __forceinline__ void ising_compute(const ChunkIn& in, uint8_t* own, i
     philox4x32_10((kb >> 3) + 1u, p, rid, kTagMain, k0, k1, &w[4]);
     // d = r - T_hi as unsigned: bit 31 set iff r < T_hi (accept on the prefix),
     // d == 0 iff the prefix ties; the smallest d flags a tie anywhere.
-    uint32_t flip[4] = {0u, 0u, 0u, 0u};
+    const uint8_t* thb = reinterpret_cast<const uint8_t*>(thr);
+    uint32_t d[16];
     uint32_t dmin = 0xFFFFFFFFu;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const uint32_t cls = (idx[j >> 2] >> (8 * (j & 3))) & 0xFFu;
+        const uint32_t off = (idx4[j >> 2] >> (8 * (j & 3))) & 0xFFu;
         const uint32_t r = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-        const uint32_t d = r - thr[cls];
-        flip[j >> 2] |= (d >> 31) << (8 * (j & 3));
-        dmin = min(dmin, d);
+        d[j] = r - *reinterpret_cast<const uint32_t*>(thb + off);
+        dmin = min(dmin, d[j]);
     }
+    uint32_t flip[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) flip[k] = sign_bytes(d[4 * k], d[4 * k + 1], d[4 * k + 2], d[4 * k + 3]) & 0x01010101u;
     if (dmin == 0u) {
         // The prefix equals the threshold's high half: the low halves decide.
         for (int j = 0; j < 16; ++j) {
-            const uint32_t cls = (idx[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-            const uint32_t r = (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu;
-            if (r != thr[cls]) continue;
+            if (d[j] != 0u) continue;
+            const uint32_t cls = ((idx4[j >> 2] >> (8 * (j & 3))) & 0xFFu) >> 2;
             const uint32_t lo = thr[kIsingClasses + cls];
             if (lo == 0u) continue;
             uint32_t f[4];
@@ -216,17 +227,29 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
     for (int b = 0; b < 4; ++b)
         philox4x32_10((kb >> 2) + (uint32_t)b, p, rid, kTagMain, k0, k1, &w[4 * b]);
     const uint32_t mq = (uint32_t)(q - 1);
-    // proposals s' = s + 1 + off (mod q), off uniform in [0, q-1); the
-    // smallest low half of the Lemire products flags a rejection anywhere
-    uint32_t s2v[4] = {0u, 0u, 0u, 0u};
+    // proposals s' = s + 1 + off (mod q), off uniform in [0, q-1): off is
+    // byte 2 of the 16-bit Lemire product (< 2^24), and the smallest low half
+    // of the products flags a rejection anywhere
+    uint32_t pr[16];
     uint32_t lmin = 0xFFFFFFFFu;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const uint32_t s = (ov[j >> 2] >> (8 * (j & 3))) & 0xFFu;
-        const uint32_t prod = __umul24(w[j] & 0xFFFFu, mq);  // < 2^24: full-rate multiply
-        lmin = min(lmin, prod & 0xFFFFu);
-        const uint32_t s2 = s + 1u + (prod >> 16);
-        s2v[j >> 2] |= min(s2, s2 - (uint32_t)q) << (8 * (j & 3));  // wrap to [0, q)
+        pr[j] = __umul24(w[j] & 0xFFFFu, mq);  // full-rate 24-bit multiply
+        lmin = min(lmin, pr[j] & 0xFFFFu);
+    }
+    // Bytewise: t = s + 1 + off <= 2q - 2 < 256; t + (128 - q) has bit 7 set
+    // iff t >= q (and stays below 256); those bytes take t - q.
+    const uint32_t Qb = (uint32_t)q * 0x01010101u;
+    const uint32_t Cb = (uint32_t)(128 - q) * 0x01010101u;
+    uint32_t s2v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t offs = __builtin_amdgcn_perm(pr[4 * k + 1], pr[4 * k], 0x0C0C0602u) |
+                              __builtin_amdgcn_perm(pr[4 * k + 3], pr[4 * k + 2], 0x06020C0Cu);
+        const uint32_t t = ov[k] + offs + 0x01010101u;
+        const uint32_t ge = (t + Cb) & 0x80808080u;
+        const uint32_t wrap = ((ge << 1) - (ge >> 7)) & Qb;  // q in the bytes with t >= q
+        s2v[k] = t - wrap;
     }
     if (lmin < lem_thr) {
         for (int j = 0; j < 16; ++j) {
@@ -270,7 +293,7 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
     // only and thr9 holds the 9 (hi | lo) entries.  d = r - T_hi unsigned:
     // bit 31 set iff the prefix accepts, 0 iff it ties.
     const uint32_t wq = (uint32_t)(2 * q - 1);
-    uint32_t acc_sel[4] = {0u, 0u, 0u, 0u};  // 0xFF in bytes that accept
+    uint32_t d[16];
     uint32_t dmin = 0xFFFFFFFFu;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -284,26 +307,28 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
             const uint32_t s2 = (s2v[j >> 2] >> sh) & 0xFFu;
             th = thr[__umul24(d4, wq) + s2 + (uint32_t)(q - 1) - s];
         }
-        const uint32_t d = (w[j] >> 16) - th;
-        acc_sel[j >> 2] |= (uint32_t)((int32_t)d >> 31) & (0xFFu << sh);
-        dmin = min(dmin, d);
+        d[j] = (w[j] >> 16) - th;
+        dmin = min(dmin, d[j]);
     }
+    uint32_t acc_sel[4];  // 0xFF in bytes that accept
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        acc_sel[k] = sign_bytes(d[4 * k], d[4 * k + 1], d[4 * k + 2], d[4 * k + 3]);
     if (dmin == 0u) {
+        // a prefix equals the threshold's high half: the low halves decide
         for (int j = 0; j < 16; ++j) {
+            if (d[j] != 0u) continue;
             const int sh = 8 * (j & 3);
             const uint32_t d4 = (dn4[j >> 2] >> sh) & 0xFFu;
-            uint32_t hi, lo;
+            uint32_t lo;
             if (HZ) {
-                hi = thr9[d4];
                 lo = thr9[9 + d4];
             } else {
                 const uint32_t s = (ov[j >> 2] >> sh) & 0xFFu;
                 const uint32_t s2 = (s2v[j >> 2] >> sh) & 0xFFu;
-                const uint32_t cls = __umul24(d4, wq) + s2 + (uint32_t)(q - 1) - s;
-                hi = thr[cls];
-                lo = thr[ntab + cls];
+                lo = thr[ntab + __umul24(d4, wq) + s2 + (uint32_t)(q - 1) - s];
             }
-            if ((w[j] >> 16) != hi || lo == 0u) continue;
+            if (lo == 0u) continue;
             uint32_t f[4];
             philox4x32_10(kb + (uint32_t)j, p, rid, kTagFallback, k0, k1, f);
             if ((f[0] & 0xFFFFu) < lo) acc_sel[j >> 2] |= 0xFFu << sh;
