@@ -140,6 +140,120 @@ def ising_stream_probe(Sampler, torch, n_rep, sweeps):
     return out
 
 
+def _events(torch, stream):
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    return a, b
+
+
+def cpm_probe(Sampler, torch, mcs):
+    """Cell sorting: 8 CPM replicas of 512x512 (1000 cells of 14x14, two
+    types, A = 200, lambda = 1, T = 10), `mcs` Monte Carlo steps (4 colour
+    passes each) timed per pass launch."""
+    import synth
+    ids, ctype, A, J, prm = synth.cpm_sorting()
+    reps = [dict(model=2, Lx=ids.shape[2], Ly=ids.shape[1], q=len(ctype) - 1, rid=r, adhesion=J,
+                 cell_type=ctype, target_area=A, lambda_area=prm["lambda_area"],
+                 temperature=prm["temperature"]) for r in range(ids.shape[0])]
+    smp = Sampler(reps, prm["seed"], init=False)
+    for r in range(len(reps)):
+        smp.set_state(r, ids[r])
+    smp.sweep(2)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, smp.stream)
+    smp.sweep(mcs)
+    e1.record(smp.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    smp.profile(True)
+    smp.sweep(mcs)
+    torch.cuda.synchronize()
+    kms, nl = smp.profile_read("cpm_pass")
+    smp.profile(False)
+    smp.close()
+    sites = ids.shape[0] * ids.shape[1] * ids.shape[2]
+    avg_s = kms / nl * 1e-3
+    per_launch = sites // 4
+    return {"config": f"{ids.shape[0]} CPM replicas of {ids.shape[1]}x{ids.shape[2]}, "
+                      f"1000 cells, {mcs} MCS", "attempts_per_ns": round(sites * mcs / (ms * 1e6), 2),
+            "kernel": "k_cpm_pass", "bound": "alu", "launches": nl,
+            "avg_launch_us": round(avg_s * 1e6, 2),
+            "kernel_attempts_per_ns": round(per_launch / avg_s / 1e9, 2),
+            "algorithmic_GBs": round(per_launch * 17 / avg_s / 1e9, 1)}
+
+
+def grad_probe(Sampler, torch):
+    """Differentiation workload: 256 Ising replicas of 128x128 (J ~ U(0.3,
+    0.6), h ~ U(-0.05, 0.05), beta 1), 5000 recorded sweeps, then the
+    covariance backward over the 4000 post-burn-in samples."""
+    import synth
+    reps = synth.differentiation()
+    smp = Sampler(reps, 3, init=True)
+    n, burn = 5000, 1000
+    stats = torch.empty((n, len(reps), smp.width), dtype=torch.int32, device="cuda")
+    smp.sweep(10)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, smp.stream)
+    smp.sweep(n, 1, stats=stats)
+    e1.record(smp.stream)
+    gout = torch.ones((len(reps), 2), dtype=torch.float64, device="cuda")
+    smp.grad(stats, burn, grad_out=gout)
+    torch.cuda.synchronize()
+    ms_sweep = e0.elapsed_time(e1)
+    ms_grad = float("inf")
+    for _ in range(5):  # one launch per bracket, best of five
+        e2, e3 = _events(torch, smp.stream)
+        smp.grad(stats, burn, grad_out=gout)
+        e3.record(smp.stream)
+        torch.cuda.synchronize()
+        ms_grad = min(ms_grad, e2.elapsed_time(e3))
+    smp.close()
+    sites = sum(r["Lx"] * r["Ly"] for r in reps)
+    samples = (n - burn) * len(reps)
+    return {"config": "256 Ising 128x128, 5000 recorded sweeps, burn-in 1000",
+            "recorded_sweep_attempts_per_ns": round(sites * n / (ms_sweep * 1e6), 1),
+            "kernel": "k_cov_grad", "bound": "hbm", "grad_call_us": round(ms_grad * 1e3, 2),
+            "samples": samples, "algorithmic_bytes": 12 * samples,
+            "achieved_GBs": round(12 * samples / (ms_grad * 1e-3) / 1e9, 1)}
+
+
+def mlp_probe(torch, steps=200, batch=1024, infer_batch=100_000):
+    """Surrogate MLP 4-128-128-3: training steps (forward + backward + Adam)
+    at batch 1024 and one forward over 10^5 points, timed with HIP events."""
+    from paper_2304_01772_amd.surrogate import SurrogateMLP
+    net = SurrogateMLP(seed=0)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    xn = (torch.rand((batch, 4), generator=g) * 2 - 1).cuda().contiguous()
+    tn = torch.randn((batch, 3), generator=g).cuda().contiguous()
+    w = torch.ones(3, dtype=torch.float32, device="cuda")
+    for _ in range(5):
+        net.train_step(xn, tn, w)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = _events(torch, st)
+    for _ in range(steps):
+        net.train_step(xn, tn, w)
+    e1.record(st)
+    xi = (torch.rand((infer_batch, 4), generator=g) * 2 - 1).cuda().contiguous()
+    net.forward_normalised(xi)
+    torch.cuda.synchronize()
+    e2, e3 = _events(torch, st)
+    net.forward_normalised(xi)
+    e3.record(st)
+    torch.cuda.synchronize()
+    ms_train = e0.elapsed_time(e1) / steps
+    ms_inf = e2.elapsed_time(e3)
+    fwd = 2 * (4 * 128 + 128 * 128 + 128 * 3)
+    train = 3 * fwd
+    return {"config": "4-128-128-3 bf16 MFMA, fp32 accumulate and master weights",
+            "train_step_us": round(ms_train * 1e3, 2), "train_batch": batch,
+            "train_TFLOPs": round(train * batch / (ms_train * 1e-3) / 1e12, 3),
+            "forward_points": infer_batch, "forward_ms": round(ms_inf, 3),
+            "forward_TFLOPs": round(fwd * infer_batch / (ms_inf * 1e-3) / 1e12, 2),
+            "bound": "mfma", "peak_TFLOPs": 2500.0}
+
+
 def cpu_baseline(reps, seed, sweeps):
     """The oracle on the host cores: every replica of the workload, a few
     sweeps (a bounded sample of the same chain)."""
@@ -248,6 +362,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true",
                     help="skip the Ising streaming probes (for counter collection runs)")
+    ap.add_argument("--no-paths", action="store_true",
+                    help="skip the CPM, covariance-backward and MLP measurements")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (the reference "
                          "dispatch that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -330,6 +446,16 @@ def main():
         print(f"# Ising stream probe {n_rep}: {probes[f'ising_{n_rep}x256x256_stream']}",
               file=sys.stderr, flush=True)
 
+    paths = None
+    if not args.no_paths:
+        paths = {}
+        paths["cpm_cell_sorting"] = cpm_probe(Sampler, torch, 50)
+        print(f"# cpm: {paths['cpm_cell_sorting']}", file=sys.stderr, flush=True)
+        paths["covariance_backward"] = grad_probe(Sampler, torch)
+        print(f"# grad: {paths['covariance_backward']}", file=sys.stderr, flush=True)
+        paths["surrogate_mlp"] = mlp_probe(torch)
+        print(f"# mlp: {paths['surrogate_mlp']}", file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle on host cores)...", file=sys.stderr, flush=True)
@@ -366,6 +492,7 @@ def main():
         "roofline": roof,
         "kernels": kern,
         "ising_stream_roofline": probes,
+        "other_paths": paths,
         "cpu_baseline": cpu,
         "argv": sys.argv[1:],
         "kernel_source_hash": kernel_source_hash(),

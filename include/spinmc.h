@@ -166,9 +166,10 @@ int spinmc_thresholds(const spinmc_ctx *ctx, int32_t replica, uint64_t *host_T, 
                       int32_t *n_out, int64_t *aux);
 
 /* Execution schedule of spinmc_sweep (the batched scheduler).
- * mode 1 resident: one persistent launch for all sweeps of the call; each
- *   workgroup owns one replica whose lattice lives in LDS for the whole call
- *   (lattices up to 128 KiB).
+ * mode 1 resident: one persistent launch per group of replicas (one model
+ *   and shape) for all sweeps of the call; each workgroup owns 1 to 16
+ *   replicas whose lattices live in LDS for the whole call (lattices up to
+ *   128 KiB); groups run concurrently on side streams.
  * mode 2 stream: one launch per colour pass over (replica, row-tile) units of
  *   every replica whose Lx/2 is a multiple of 16 (others go resident).
  * mode 3 hybrid: resident where the lattice fits the LDS budget, streamed
@@ -177,7 +178,7 @@ int spinmc_thresholds(const spinmc_ctx *ctx, int32_t replica, uint64_t *host_T, 
  * Calls without recording replay cached hipGraphs of 50-sweep chunks
  * (streamed passes and the concurrent resident branch captured together).
  * tile_rows: rows of a plane per streamed unit (even; 0 = about 16 KiB);
- * wg_threads: 256 or 512 (resident also 1024; 0 = default).  Invalid values
+ * wg_threads: 256 or 512 (0 = default).  Invalid values
  * return SPINMC_E_INVALID.  CPM contexts use tile_rows and wg_threads only. */
 typedef struct spinmc_schedule {
     int32_t mode;

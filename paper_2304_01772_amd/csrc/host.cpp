@@ -132,7 +132,7 @@ struct spinmc_ctx {
     hipEvent_t cap_ev[1 + kSide] = {};
     // resident workgroup groups (replicas of one shape packed rpb per workgroup)
     struct ResGroup {
-        int off, count, rpb, threads;
+        int off, count, rpb, threads, model;
         bool chunk;
         size_t slot;
     };
@@ -622,9 +622,8 @@ int spinmc_set_schedule(spinmc_ctx* c, const spinmc_schedule* s) {
         return fail(SPINMC_E_INVALID, "set_schedule: mode %d not available", s->mode);
     if (s->tile_rows < 0 || (s->tile_rows & 1))
         return fail(SPINMC_E_INVALID, "set_schedule: tile_rows must be even and >= 0");
-    if (s->wg_threads != 0 && s->wg_threads != 256 && s->wg_threads != 512 &&
-        !(s->mode == 1 && s->wg_threads == 1024))
-        return fail(SPINMC_E_INVALID, "set_schedule: wg_threads must be 256 or 512 (1024 resident)");
+    if (s->wg_threads != 0 && s->wg_threads != 256 && s->wg_threads != 512)
+        return fail(SPINMC_E_INVALID, "set_schedule: wg_threads must be 256 or 512");
     if (s->mode == 1 && !c->cpm)
         for (const HostRep& h : c->reps)
             if (!h.resident)
@@ -734,7 +733,7 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
             if (h.chunk) min_def = std::min(min_def, default_tile_rows(h));
         }
         if (all_res)
-            for (int th : {256, 512, 1024}) cand.push_back(spinmc_schedule{1, 0, th, 0});
+            for (int th : {256, 512}) cand.push_back(spinmc_schedule{1, 0, th, 0});
         if (any_stream) {
             std::vector<int> trs = {0};
             if (min_def >= 8) trs.push_back(std::max(2, (min_def / 2) & ~1));
@@ -908,8 +907,12 @@ int prepare(spinmc_ctx* c, int mode) {
     const int tmax = c->sched.wg_threads > 0 ? c->sched.wg_threads : 512;
     for (int pass = 0; pass < 2; ++pass) {
         const std::vector<int32_t>& L = pass == 0 ? res_chunk : res_gen;
-        std::map<std::tuple<int, int>, std::vector<int32_t>> shapes;
-        for (int i : L) shapes[std::make_tuple(c->reps[i].dev.Lx, c->reps[i].dev.Ly)].push_back(i);
+        // chunk groups: one model and shape each; per-site groups: one shape
+        std::map<std::tuple<int, int, int>, std::vector<int32_t>> shapes;
+        for (int i : L) {
+            const RepDev& d = c->reps[i].dev;
+            shapes[std::make_tuple(pass == 0 ? d.model : 0, d.Lx, d.Ly)].push_back(i);
+        }
         for (auto& kv : shapes) {
             const HostRep& h = c->reps[kv.second[0]];
             const int items = pass == 0 ? (h.dev.Ly / 2) * (h.dev.W / 16) : h.dev.Ly * h.dev.W;
@@ -921,7 +924,8 @@ int prepare(spinmc_ctx* c, int mode) {
                 P *= 2;
             int threads = 64;
             while (threads < tmax && threads < P * items) threads *= 2;
-            c->res_groups.push_back({(int)buf.size(), n, P, threads, pass == 0, slot});
+            c->res_groups.push_back({(int)buf.size(), n, P, threads, std::get<0>(kv.first),
+                                     pass == 0, slot});
             buf.insert(buf.end(), kv.second.begin(), kv.second.end());
         }
     }
@@ -995,7 +999,7 @@ hipError_t enqueue_resident(spinmc_ctx* c, SweepArgs a, hipStream_t s) {
         a.rpb = g.rpb;
         a.res_slot_bytes = (int)g.slot;
         e = timed(c, SPINMC_K_RESIDENT, [&] {
-            return launch_resident(a, g.count, 0, g.chunk, g.threads, g.slot * g.rpb, side);
+            return launch_resident(a, g.count, g.model, g.chunk, g.threads, g.slot * g.rpb, side);
         }, side);
     }
     return e;

@@ -393,9 +393,11 @@ __device__ __forceinline__ void run_tile_potts(uint8_t* planes, int W, int Ly, i
     }
 }
 
-// Ising rows [y0, y0+rows) of plane c: each lane takes one chunk of each row
-// parity per iteration and issues both chunks' loads before computing.
-template <bool REC>
+// Ising rows [y0, y0+rows) of plane c.  DUAL: each lane takes one chunk of
+// each row parity per iteration and issues both chunks' loads before
+// computing (latency hiding for the HBM stream); otherwise one chunk per
+// iteration, parity by parity (fewer registers for the LDS-resident path).
+template <bool REC, bool DUAL>
 __device__ __forceinline__ void run_tile_ising(uint8_t* planes, int W, int Ly, int y0, int rows,
                                                int c, uint32_t p, uint32_t rid, uint32_t k0,
                                                uint32_t k1, const uint32_t* thr, IsingAcc& ia,
@@ -406,16 +408,36 @@ __device__ __forceinline__ void run_tile_ising(uint8_t* planes, int W, int Ly, i
     const int items = (rows >> 1) * cpr;
     const int ya = y0 + (c & 1);        // rows with (y + c) & 1 == 0
     const int yb = y0 + ((c & 1) ^ 1);  // rows with (y + c) & 1 == 1
-    for (int it = tid; it < items; it += nthr) {
-        const int r = it / cpr;
-        const int j0 = (it - r * cpr) << 4;
-        const int y_a = ya + 2 * r, y_b = yb + 2 * r;
-        const int ym_a = (y_a == 0) ? Ly - 1 : y_a - 1, yp_a = (y_a + 1 == Ly) ? 0 : y_a + 1;
-        const int ym_b = (y_b == 0) ? Ly - 1 : y_b - 1, yp_b = (y_b + 1 == Ly) ? 0 : y_b + 1;
-        const ChunkIn A = chunk_load<0>(own, oth, W, y_a, ym_a, yp_a, j0);
-        const ChunkIn B = chunk_load<1>(own, oth, W, y_b, ym_b, yp_b, j0);
-        ising_compute<0, REC>(A, own, W, y_a, j0, p, rid, k0, k1, thr, ia);
-        ising_compute<1, REC>(B, own, W, y_b, j0, p, rid, k0, k1, thr, ia);
+    if (DUAL) {
+        for (int it = tid; it < items; it += nthr) {
+            const int r = it / cpr;
+            const int j0 = (it - r * cpr) << 4;
+            const int y_a = ya + 2 * r, y_b = yb + 2 * r;
+            const int ym_a = (y_a == 0) ? Ly - 1 : y_a - 1, yp_a = (y_a + 1 == Ly) ? 0 : y_a + 1;
+            const int ym_b = (y_b == 0) ? Ly - 1 : y_b - 1, yp_b = (y_b + 1 == Ly) ? 0 : y_b + 1;
+            const ChunkIn A = chunk_load<0>(own, oth, W, y_a, ym_a, yp_a, j0);
+            const ChunkIn B = chunk_load<1>(own, oth, W, y_b, ym_b, yp_b, j0);
+            ising_compute<0, REC>(A, own, W, y_a, j0, p, rid, k0, k1, thr, ia);
+            ising_compute<1, REC>(B, own, W, y_b, j0, p, rid, k0, k1, thr, ia);
+        }
+    } else {
+#pragma unroll
+        for (int par = 0; par < 2; ++par) {
+            const int yf = par == 0 ? ya : yb;
+            for (int it = tid; it < items; it += nthr) {
+                const int r = it / cpr;
+                const int j0 = (it - r * cpr) << 4;
+                const int y = yf + 2 * r;
+                const int ym = (y == 0) ? Ly - 1 : y - 1, yp = (y + 1 == Ly) ? 0 : y + 1;
+                if (par == 0) {
+                    const ChunkIn A = chunk_load<0>(own, oth, W, y, ym, yp, j0);
+                    ising_compute<0, REC>(A, own, W, y, j0, p, rid, k0, k1, thr, ia);
+                } else {
+                    const ChunkIn B = chunk_load<1>(own, oth, W, y, ym, yp, j0);
+                    ising_compute<1, REC>(B, own, W, y, j0, p, rid, k0, k1, thr, ia);
+                }
+            }
+        }
     }
 }
 
@@ -491,10 +513,10 @@ __device__ __forceinline__ void stream_pass_body(const SweepArgs& a, int tile0, 
     PottsAcc pa{0, 0, 0};
     if (MODEL == kModelIsing) {
         if (rec)
-            run_tile_ising<true>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
+            run_tile_ising<true, true>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
                                  lthr, ia, threadIdx.x, blockDim.x);
         else
-            run_tile_ising<false>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
+            run_tile_ising<false, true>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
                                   lthr, ia, threadIdx.x, blockDim.x);
     } else {
         if (rec)
@@ -655,9 +677,13 @@ __device__ __forceinline__ void lattice_stats(int model, const uint8_t* planes, 
 // Resident kernel: a workgroup owns a.rpb replicas of one shape for the
 // whole call, each with its thresholds and both planes in LDS, and
 // blockDim/rpb threads; colour passes are separated by workgroup barriers.
-// CHUNK selects the 16-byte SWAR path (W % 16 == 0).
-template <bool CHUNK>
-__global__ void __launch_bounds__(1024) k_resident(SweepArgs a) {
+// KIND selects the path: kResIsing / kResPotts run the 16-byte SWAR chunks
+// (W % 16 == 0, every replica of the launch of that model), kResGeneric the
+// per-site code for any model and width.  Separate instantiations keep the
+// Ising path's register count (and so its waves per SIMD) free of Potts's.
+template <int KIND>
+__device__ __forceinline__ void resident_body(const SweepArgs& a) {
+    constexpr bool CHUNK = KIND != kResGeneric;
     // dynamic LDS: rpb slots of [thresholds (tab_lds_bytes) | plane 0 | plane 1]
     extern __shared__ __align__(16) uint8_t dyn[];
     __shared__ uint32_t lthr9[kMaxRpb][18];
@@ -693,15 +719,14 @@ __global__ void __launch_bounds__(1024) k_resident(SweepArgs a) {
         for (int c = 0; c < 2; ++c) {
             const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
             if (active) {
-                if (CHUNK) {
+                if (KIND == kResIsing) {
                     IsingAcc ia{0, 0, 0};
+                    run_tile_ising<false, false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0, a.key1,
+                                          lthr, ia, lt, nt);
+                } else if (KIND == kResPotts) {
                     PottsAcc pa{0, 0, 0};
-                    if (R.model == kModelIsing)
-                        run_tile_ising<false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0, a.key1,
-                                              lthr, ia, lt, nt);
-                    else
-                        potts_tile<false>(R, lds, 0, R.Ly, c, p, a.key0, a.key1, lthr, lthr9[g],
-                                          pa, lhist, lt, nt);
+                    potts_tile<false>(R, lds, 0, R.Ly, c, p, a.key0, a.key1, lthr, lthr9[g], pa,
+                                      lhist, lt, nt);
                 } else {
                     for (int k = lt; k < plane; k += nt)
                         generic_site(R.model, lds, R.W, R.Ly, c, k, p, R.rid, a.key0, a.key1,
@@ -747,6 +772,19 @@ __global__ void __launch_bounds__(1024) k_resident(SweepArgs a) {
             for (int i = lt; i < bytes; i += nt) gmem[i] = lds[i];
         }
     }
+}
+
+__global__ void __launch_bounds__(512) k_resident_generic(SweepArgs a) {
+    resident_body<kResGeneric>(a);
+}
+
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 8)))
+k_resident_ising(SweepArgs a) {
+    resident_body<kResIsing>(a);
+}
+
+__global__ void __launch_bounds__(512) k_resident_potts(SweepArgs a) {
+    resident_body<kResPotts>(a);
 }
 
 // Initial state from the init stream: natural index n, block n >> 2, word n & 3.
@@ -847,23 +885,24 @@ hipError_t launch_init(const RepDev* reps, const int32_t* list, int n, uint8_t* 
 }
 
 hipError_t resident_reserve_lds(size_t lds_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_resident<true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void*)k_resident<false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    const void* fns[3] = {(const void*)k_resident_generic, (const void*)k_resident_ising,
+                          (const void*)k_resident_potts};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 3 && e == hipSuccess; ++i)
+        e = hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     return e;
 }
 
 hipError_t launch_resident(const SweepArgs& a, int n_list, int model, bool chunk, int threads,
                            size_t lds_bytes, hipStream_t s) {
-    (void)model;
     if (n_list <= 0) return hipSuccess;
     const int blocks = (n_list + a.rpb - 1) / a.rpb;
-    if (chunk)
-        hipLaunchKernelGGL(k_resident<true>, dim3(blocks), dim3(threads), lds_bytes, s, a);
+    if (!chunk)
+        hipLaunchKernelGGL(k_resident_generic, dim3(blocks), dim3(threads), lds_bytes, s, a);
+    else if (model == kModelIsing)
+        hipLaunchKernelGGL(k_resident_ising, dim3(blocks), dim3(threads), lds_bytes, s, a);
     else
-        hipLaunchKernelGGL(k_resident<false>, dim3(blocks), dim3(threads), lds_bytes, s, a);
+        hipLaunchKernelGGL(k_resident_potts, dim3(blocks), dim3(threads), lds_bytes, s, a);
     return hipGetLastError();
 }
 

@@ -20,6 +20,11 @@ constexpr int kMaxPottsQ = 128;   // labels fit in 7 bits (SWAR equality test)
 constexpr int kMaxCpmTypes = 4;
 constexpr int kMaxRpb = 16;       // replicas per resident workgroup
 
+// Resident kernel paths: per-site (any model or width), Ising chunks, Potts chunks.
+constexpr int kResGeneric = 0;
+constexpr int kResIsing = 1;
+constexpr int kResPotts = 2;
+
 // Per-replica record, device visible.
 struct RepDev {
     int32_t model, Lx, Ly, W;     // W = bytes per plane row = Lx/2 (Ising/Potts)
@@ -97,6 +102,8 @@ struct SweepArgs {
 // Host-side launchers implemented in the kernel translation units.
 hipError_t launch_init(const RepDev* reps, const int32_t* list, int n, uint8_t* lat,
                        uint32_t key0, uint32_t key1, int threads, hipStream_t s);
+// Resident groups: chunk groups hold replicas of one model (model selects
+// the path); per-site groups may mix models.
 hipError_t launch_resident(const SweepArgs& a, int n_list, int model, bool chunk, int threads,
                            size_t lds_bytes, hipStream_t s);
 // Allow the resident kernels up to lds_bytes of dynamic LDS (call outside capture).

@@ -136,7 +136,8 @@ class SurrogateMLP:
 
 
 # ----------------------------------------------------------------- labels
-def mc_observables(points, L=64, burn=300, measure=700, every=1, seed=5, rid0=0, chunk=16384):
+def mc_observables(points, L=64, burn=300, measure=700, every=1, seed=5, rid0=0, chunk=16384,
+                   log=None):
     """Monte Carlo labels (<e>, <|m|>, chi) for points [N, 4] = (beta, Jx,
     Jy, h), one LxL replica per point, plus the standard error of <|m|> from
     batch means.  Returns (labels [N, 3], se_absm [N]) as numpy arrays."""
@@ -159,6 +160,8 @@ def mc_observables(points, L=64, burn=300, measure=700, every=1, seed=5, rid0=0,
         bm = am[: (am.shape[0] // nb) * nb].reshape(nb, -1, am.shape[1]).mean(axis=1)
         se[c0:c0 + len(part)] = bm.std(axis=0, ddof=1) / np.sqrt(nb)
         smp.close()
+        if log:
+            log(f"labels: {c0 + len(part)} / {len(pts)} points")
     return out, se
 
 
@@ -230,7 +233,7 @@ def surrogate_solve(net, target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, st
 
 
 # ------------------------------------------------------------ experiment
-def experiment(n_points=100_000, L=64, burn=300, measure=700, epochs=60, targets=(0.2, 0.35, 0.5,
+def experiment(n_points=100_000, L=64, burn=1000, measure=2000, epochs=60, targets=(0.2, 0.35, 0.5,
                0.65, 0.8), beta=0.4, tol=0.01, n_rep=64, log=print, seed=1005):
     """The surrogate workload end to end: labels on the sampler, 90/10
     train/validation split, training, and for every target the wall time of
@@ -239,7 +242,7 @@ def experiment(n_points=100_000, L=64, burn=300, measure=700, epochs=60, targets
     import synth
     pts = synth.surrogate_points(n_points, seed=seed)
     t0 = time.perf_counter()
-    y, se = mc_observables(pts, L=L, burn=burn, measure=measure)
+    y, se = mc_observables(pts, L=L, burn=burn, measure=measure, log=log)
     torch.cuda.synchronize()
     t_label = time.perf_counter() - t0
     log(f"labels: {n_points} points in {t_label:.1f} s")
@@ -255,9 +258,10 @@ def experiment(n_points=100_000, L=64, burn=300, measure=700, epochs=60, targets
                mae_chi=float(err[:, 2].mean()), label_se_absm=float(np.median(se[n_tr:])))
     log(f"training {t_train:.1f} s; validation MAE {val}")
     runs = []
+    mc_kw = dict(n_rep=n_rep, L=L, burn=burn, measure=measure)
     for tg in targets:
-        mc = mc_only_solve(tg, beta=beta, tol=tol, n_rep=n_rep)
-        su = surrogate_solve(net, tg, beta=beta, tol=tol, n_rep=n_rep)
+        mc = mc_only_solve(tg, beta=beta, tol=tol, **mc_kw)
+        su = surrogate_solve(net, tg, beta=beta, tol=tol, **mc_kw)
         runs.append(dict(target=tg, mc_only=dict((k, mc[k]) for k in ("Jx", "Jy", "absm", "se",
                                                                        "iters", "seconds",
                                                                        "converged")),
@@ -267,7 +271,13 @@ def experiment(n_points=100_000, L=64, burn=300, measure=700, epochs=60, targets
                                                              "fallback_iters"))))
         log(f"target {tg}: MC-only {mc['seconds']:.2f} s ({mc['iters']} MC evals), surrogate "
             f"{su['seconds']:.2f} s ({su['iters']} MC evals)")
+    tot_mc = sum(r["mc_only"]["seconds"] for r in runs)
+    tot_su = sum(r["surrogate"]["seconds"] for r in runs)
+    log(f"all targets: MC-only {tot_mc:.2f} s; surrogate {tot_su:.2f} s without and "
+        f"{tot_su + t_label + t_train:.2f} s with the one-off labels and training")
     return dict(label_seconds=t_label, train_seconds=t_train, validation=val, solves=runs,
+                total_seconds=dict(mc_only=tot_mc, surrogate=tot_su,
+                                   surrogate_with_labels_and_training=tot_su + t_label + t_train),
                 config=dict(n_points=n_points, L=L, burn=burn, measure=measure, epochs=epochs,
                             beta=beta, tol=tol, n_rep=n_rep))
 
@@ -277,14 +287,14 @@ if __name__ == "__main__":
     import json
     ap = argparse.ArgumentParser()
     ap.add_argument("--points", type=int, default=100_000)
-    ap.add_argument("--burn", type=int, default=300)
-    ap.add_argument("--measure", type=int, default=700)
+    ap.add_argument("--burn", type=int, default=1000)
+    ap.add_argument("--measure", type=int, default=2000)
     ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--n-rep", type=int, default=64)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     res = experiment(n_points=a.points, burn=a.burn, measure=a.measure, epochs=a.epochs,
-                     n_rep=a.n_rep)
+                     n_rep=a.n_rep, log=lambda m: print(m, flush=True))
     txt = json.dumps(res)
     print(txt)
     if a.out:
