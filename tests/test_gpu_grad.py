@@ -125,3 +125,48 @@ def test_gradient_matches_finite_differences_with_common_random_numbers(S):
     _, gex = ograd.ising_grad(ex["M"], ex["Bx"], ex["By"], _f32(J), _f32(J), 0.0, beta, 16,
                               weights=ex["p"])
     assert abs(cov.mean() - (gex[1, 0] + gex[1, 1])) <= 3 * cov.std(ddof=1) / math.sqrt(R)
+
+
+def test_autograd_function_backward_is_the_covariance_estimator(S):
+    """torch.autograd through ising_observables: the forward values are the
+    oracle's sample means of the same chain, the backward equals the oracle's
+    covariance gradients contracted with the incoming gradient, and the
+    replica-averaged gradient of a loss on the 4x4 torus is within 3 sigma
+    of the exact one."""
+    from paper_2304_01772_amd.differentiable import ising_observables
+    rng = np.random.default_rng(5)
+    R, L, n, burn, seed = 6, 8, 600, 100, 9
+    jx = torch.tensor(rng.uniform(0.3, 0.6, R), dtype=torch.float32, device="cuda",
+                      requires_grad=True)
+    jy = torch.tensor(rng.uniform(0.3, 0.6, R), dtype=torch.float32, device="cuda",
+                      requires_grad=True)
+    hh = torch.tensor(rng.uniform(-0.05, 0.05, R), dtype=torch.float32, device="cuda",
+                      requires_grad=True)
+    e, am = ising_observables(jx, jy, hh, L=L, beta=1.0, n_sweeps=n, burn_in=burn, seed=seed,
+                              rid0=40)
+    ge, ga = rng.normal(size=R), rng.normal(size=R)
+    (e * torch.tensor(ge, device="cuda") + am * torch.tensor(ga, device="cuda")).sum().backward()
+    for i in range(R):
+        Jx, Jy, h = float(jx[i]), float(jy[i]), float(hh[i])
+        s0 = orc.ising_init(L, L, seed, 40 + i)
+        _, ost = orc.ising_run(s0, Jx, Jy, h, 1.0, seed, 40 + i, 0, n, 1)
+        mo, go = ograd.ising_grad(ost[burn:, 0], ost[burn:, 1], ost[burn:, 2], Jx, Jy, h, 1.0,
+                                  L * L)
+        np.testing.assert_allclose([float(e[i]), float(am[i])], mo, rtol=1e-12, atol=1e-15)
+        want = ge[i] * go[0] + ga[i] * go[1]
+        got = [float(jx.grad[i]), float(jy.grad[i]), float(hh.grad[i])]
+        np.testing.assert_allclose(got, want.astype(np.float32), rtol=1e-5, atol=1e-7)
+    # exact 4x4: d<|m|>/dJx averaged over replicas
+    R4 = 256
+    J0, h0 = _f32(0.45), _f32(0.03)
+    jx4 = torch.full((R4,), J0, dtype=torch.float64, device="cuda", requires_grad=True)
+    jy4 = torch.full((R4,), J0, dtype=torch.float64, device="cuda", requires_grad=True)
+    h4 = torch.full((R4,), h0, dtype=torch.float64, device="cuda", requires_grad=True)
+    _, am4 = ising_observables(jx4, jy4, h4, L=4, beta=1.0, n_sweeps=4000, burn_in=1000, seed=13)
+    am4.sum().backward()
+    ex = exact.ising_exact(4, 4, J0, J0, h0, 1.0)
+    _, gex = ograd.ising_grad(ex["M"], ex["Bx"], ex["By"], J0, J0, h0, 1.0, 16, weights=ex["p"])
+    for t, j in ((jx4, 0), (jy4, 1), (h4, 2)):
+        g = t.grad.cpu().numpy()
+        assert abs(g.mean() - gex[1, j]) <= 3 * g.std(ddof=1) / math.sqrt(R4), (j, g.mean(),
+                                                                             gex[1, j])
