@@ -77,13 +77,12 @@ struct ChunkIn {
 
 template <int PAR>
 __device__ __forceinline__ ChunkIn chunk_load(const uint8_t* own, const uint8_t* oth, int W,
-                                              int y, int ym, int yp, int j0) {
-    const size_t ro = (size_t)y * W;
+                                              uint32_t ro, uint32_t rom, uint32_t rop, int j0) {
     ChunkIn in;
     in.o = *reinterpret_cast<const uint4*>(own + ro + j0);
     in.m = *reinterpret_cast<const uint4*>(oth + ro + j0);
-    in.U = *reinterpret_cast<const uint4*>(oth + (size_t)ym * W + j0);
-    in.D = *reinterpret_cast<const uint4*>(oth + (size_t)yp * W + j0);
+    in.U = *reinterpret_cast<const uint4*>(oth + rom + j0);
+    in.D = *reinterpret_cast<const uint4*>(oth + rop + j0);
     const int je = PAR == 0 ? ((j0 == 0) ? W - 4 : j0 - 4) : ((j0 + 16 == W) ? 0 : j0 + 16);
     in.e = *reinterpret_cast<const uint32_t*>(oth + ro + je);
     return in;
@@ -92,10 +91,9 @@ __device__ __forceinline__ ChunkIn chunk_load(const uint8_t* own, const uint8_t*
 // PAR = (y + c) & 1 selects which horizontal neighbour the shifted byte
 // stream supplies.  thr: LDS [18 hi | 18 lo].
 template <int PAR, bool REC>
-__device__ __forceinline__ void ising_compute(const ChunkIn& in, uint8_t* own, int W, int y, int j0,
+__device__ __forceinline__ void ising_compute(const ChunkIn& in, uint8_t* own, uint32_t ro, int j0,
                                               uint32_t p, uint32_t rid, uint32_t k0, uint32_t k1,
                                               const uint32_t* thr, IsingAcc& acc) {
-    const size_t ro = (size_t)y * W;
     const uint32_t e = in.e;
     const uint32_t ov[4] = {in.o.x, in.o.y, in.o.z, in.o.w};
     const uint32_t mv[4] = {in.m.x, in.m.y, in.m.z, in.m.w};
@@ -187,16 +185,16 @@ __device__ __forceinline__ uint32_t ne_hi(uint32_t a, uint32_t b) {
 // 16-site Potts chunk.  thr: LDS [n hi | n lo], n = 9(2q-1); thr9: LDS
 // [9 hi | 9 lo] by dn + 4 (used when HZ, i.e. h = 0).
 template <int PAR, bool REC, bool HZ>
-__device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, int W, int y, int ym,
-                                            int yp, int j0, uint32_t p, uint32_t rid, uint32_t k0,
-                                            uint32_t k1, const uint32_t* thr,
-                                            const uint32_t* thr9, int q, int ntab,
-                                            uint32_t lem_thr, PottsAcc& acc, int* lhist) {
-    const size_t ro = (size_t)y * W;
+__device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, int W, uint32_t ro,
+                                            uint32_t rom, uint32_t rop, int j0, uint32_t p,
+                                            uint32_t rid, uint32_t k0, uint32_t k1,
+                                            const uint32_t* thr, const uint32_t* thr9, int q,
+                                            int ntab, uint32_t lem_thr, PottsAcc& acc,
+                                            int* lhist) {
     const uint4 o = *reinterpret_cast<const uint4*>(own + ro + j0);
     const uint4 m = *reinterpret_cast<const uint4*>(oth + ro + j0);
-    const uint4 U = *reinterpret_cast<const uint4*>(oth + (size_t)ym * W + j0);
-    const uint4 D = *reinterpret_cast<const uint4*>(oth + (size_t)yp * W + j0);
+    const uint4 U = *reinterpret_cast<const uint4*>(oth + rom + j0);
+    const uint4 D = *reinterpret_cast<const uint4*>(oth + rop + j0);
     uint32_t e;
     if (PAR == 0) {
         const int je = (j0 == 0) ? W - 4 : j0 - 4;
@@ -374,21 +372,32 @@ __device__ __forceinline__ void run_tile_potts(uint8_t* planes, int W, int Ly, i
     const uint8_t* oth = planes + (size_t)(1 - c) * Ly * W;
     const int cpr = W >> 4;
     const int items = (rows >> 1) * cpr;
+    // item it = r * cpr + jc (row pair r, chunk column jc), advanced by nthr
+    // without a division per item
+    const int dr = nthr / cpr, dj = nthr - dr * cpr;
+    const int r0 = tid / cpr, jc0 = tid - r0 * cpr;
+    const uint32_t last = (uint32_t)(Ly - 1) * (uint32_t)W;
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
         const int yf = y0 + ((par ^ c) & 1);
+        int r = r0, jc = jc0;
         for (int it = tid; it < items; it += nthr) {
-            const int r = it / cpr;
-            const int j0 = (it - r * cpr) << 4;
-            const int y = yf + 2 * r;
-            const int ym = (y == 0) ? Ly - 1 : y - 1;
-            const int yp = (y + 1 == Ly) ? 0 : y + 1;
+            const uint32_t ro = (uint32_t)(yf + 2 * r) * (uint32_t)W;
+            const uint32_t rom = ro == 0u ? last : ro - (uint32_t)W;
+            const uint32_t rop = ro == last ? 0u : ro + (uint32_t)W;
+            const int j0 = jc << 4;
             if (par == 0)
-                potts_chunk<0, REC, HZ>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, thr9, q,
+                potts_chunk<0, REC, HZ>(own, oth, W, ro, rom, rop, j0, p, rid, k0, k1, thr, thr9, q,
                                         ntab, lem_thr, pa, lhist);
             else
-                potts_chunk<1, REC, HZ>(own, oth, W, y, ym, yp, j0, p, rid, k0, k1, thr, thr9, q,
+                potts_chunk<1, REC, HZ>(own, oth, W, ro, rom, rop, j0, p, rid, k0, k1, thr, thr9, q,
                                         ntab, lem_thr, pa, lhist);
+            r += dr;
+            jc += dj;
+            if (jc >= cpr) {
+                jc -= cpr;
+                ++r;
+            }
         }
     }
 }
@@ -408,33 +417,51 @@ __device__ __forceinline__ void run_tile_ising(uint8_t* planes, int W, int Ly, i
     const int items = (rows >> 1) * cpr;
     const int ya = y0 + (c & 1);        // rows with (y + c) & 1 == 0
     const int yb = y0 + ((c & 1) ^ 1);  // rows with (y + c) & 1 == 1
+    // item it = r * cpr + jc, advanced by nthr without a division per item
+    const int dr = nthr / cpr, dj = nthr - dr * cpr;
+    const int r0 = tid / cpr, jc0 = tid - r0 * cpr;
+    const uint32_t last = (uint32_t)(Ly - 1) * (uint32_t)W;
     if (DUAL) {
+        int r = r0, jc = jc0;
         for (int it = tid; it < items; it += nthr) {
-            const int r = it / cpr;
-            const int j0 = (it - r * cpr) << 4;
-            const int y_a = ya + 2 * r, y_b = yb + 2 * r;
-            const int ym_a = (y_a == 0) ? Ly - 1 : y_a - 1, yp_a = (y_a + 1 == Ly) ? 0 : y_a + 1;
-            const int ym_b = (y_b == 0) ? Ly - 1 : y_b - 1, yp_b = (y_b + 1 == Ly) ? 0 : y_b + 1;
-            const ChunkIn A = chunk_load<0>(own, oth, W, y_a, ym_a, yp_a, j0);
-            const ChunkIn B = chunk_load<1>(own, oth, W, y_b, ym_b, yp_b, j0);
-            ising_compute<0, REC>(A, own, W, y_a, j0, p, rid, k0, k1, thr, ia);
-            ising_compute<1, REC>(B, own, W, y_b, j0, p, rid, k0, k1, thr, ia);
+            const int j0 = jc << 4;
+            const uint32_t ra = (uint32_t)(ya + 2 * r) * (uint32_t)W;
+            const uint32_t rb = (uint32_t)(yb + 2 * r) * (uint32_t)W;
+            const ChunkIn A = chunk_load<0>(own, oth, W, ra, ra == 0u ? last : ra - (uint32_t)W,
+                                            ra == last ? 0u : ra + (uint32_t)W, j0);
+            const ChunkIn B = chunk_load<1>(own, oth, W, rb, rb == 0u ? last : rb - (uint32_t)W,
+                                            rb == last ? 0u : rb + (uint32_t)W, j0);
+            ising_compute<0, REC>(A, own, ra, j0, p, rid, k0, k1, thr, ia);
+            ising_compute<1, REC>(B, own, rb, j0, p, rid, k0, k1, thr, ia);
+            r += dr;
+            jc += dj;
+            if (jc >= cpr) {
+                jc -= cpr;
+                ++r;
+            }
         }
     } else {
 #pragma unroll
         for (int par = 0; par < 2; ++par) {
             const int yf = par == 0 ? ya : yb;
+            int r = r0, jc = jc0;
             for (int it = tid; it < items; it += nthr) {
-                const int r = it / cpr;
-                const int j0 = (it - r * cpr) << 4;
-                const int y = yf + 2 * r;
-                const int ym = (y == 0) ? Ly - 1 : y - 1, yp = (y + 1 == Ly) ? 0 : y + 1;
+                const int j0 = jc << 4;
+                const uint32_t ro = (uint32_t)(yf + 2 * r) * (uint32_t)W;
+                const uint32_t rom = ro == 0u ? last : ro - (uint32_t)W;
+                const uint32_t rop = ro == last ? 0u : ro + (uint32_t)W;
                 if (par == 0) {
-                    const ChunkIn A = chunk_load<0>(own, oth, W, y, ym, yp, j0);
-                    ising_compute<0, REC>(A, own, W, y, j0, p, rid, k0, k1, thr, ia);
+                    const ChunkIn A = chunk_load<0>(own, oth, W, ro, rom, rop, j0);
+                    ising_compute<0, REC>(A, own, ro, j0, p, rid, k0, k1, thr, ia);
                 } else {
-                    const ChunkIn B = chunk_load<1>(own, oth, W, y, ym, yp, j0);
-                    ising_compute<1, REC>(B, own, W, y, j0, p, rid, k0, k1, thr, ia);
+                    const ChunkIn B = chunk_load<1>(own, oth, W, ro, rom, rop, j0);
+                    ising_compute<1, REC>(B, own, ro, j0, p, rid, k0, k1, thr, ia);
+                }
+                r += dr;
+                jc += dj;
+                if (jc >= cpr) {
+                    jc -= cpr;
+                    ++r;
                 }
             }
         }
