@@ -97,6 +97,9 @@ def roofline(kind, k, mode_name):
             ach = per * att / avg_s
             out.update(achieved=round(ach / 1e12, 2), frac=round(ach / VALU_PEAK, 4),
                        valu_lane_instr_per_attempt=per)
+        if ce and ce.get("valu_busy_pct") is not None:
+            # hardware VALU-busy share of the kernel's time (rocprofv3 VALUBusy)
+            out["valu_busy_pct_counter"] = ce["valu_busy_pct"]
         if kind == "stream_potts":
             # the same pass priced against HBM, for reference
             out["hbm_GBs_algorithmic"] = round(BYTES_PER_ATTEMPT * att / avg_s / 1e9, 1)
@@ -123,21 +126,28 @@ def profiled_kernels(smp, torch, sweeps):
     return kern
 
 
-def ising_stream_probe(Sampler, torch, n_rep, sweeps):
+def ising_stream_probe(Sampler, torch, n_rep, sweeps, schedule=None):
     """The batched Ising sweep alone, streamed through HBM (n_rep replicas of
-    256x256, the beta grid of the workload), timed per colour-pass launch."""
+    256x256, the beta grid of the workload), timed per colour-pass launch;
+    the stream schedule is autotuned unless given."""
     import synth
     reps = synth.batched_ising_potts(n_ising=n_rep, n_potts=0)
     smp = Sampler(reps, seed=2, init=True)
-    chosen, _ = smp.autotune(trial_sweeps=10, mode="stream")
+    if schedule:
+        smp.set_schedule(mode="stream", **schedule)
+        chosen = smp.get_schedule()
+    else:
+        chosen, _ = smp.autotune(trial_sweeps=10, mode="stream")
     smp.sweep(2)
     torch.cuda.synchronize()
+    st_m, re_m = smp.schedule_sites(by_model=True)
     kern = profiled_kernels(smp, torch, sweeps)
     smp.close()
-    out = roofline("stream_ising", kern["stream_ising"], "stream")
+    out = roofline("stream_ising", kern["stream_ising"], f"ising_probe_{n_rep}")
     out["units"] = f"{n_rep} Ising 256x256 replicas, {sweeps} sweeps"
     out["schedule"] = chosen
-    return out
+    return out, dict(streamed_sites_by_model=st_m, resident_sites_by_model=re_m,
+                     schedule=chosen)
 
 
 def _events(torch, stream):
@@ -288,6 +298,7 @@ def _read_run(d):
         if name.endswith("counter_collection.csv"):
             with open(os.path.join(d, name)) as f:
                 rows += list(csv.DictReader(f))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
     return js, rows
 
 
@@ -324,6 +335,8 @@ def summarize_counters(dirs):
             if kname == "k_resident":
                 att, v = res_total, sum(vals)
             else:
+                # the profiled sweeps come last: 2 launches per sweep
+                vals = vals[-2 * sw:]
                 att, v = per_disp[kname], statistics.median(vals)
             if att <= 0:
                 continue
@@ -335,6 +348,8 @@ def summarize_counters(dirs):
                 e["write_bytes_per_attempt"] = round(v * 1024.0 * scale / att, 4)
             elif counter == "SQ_INSTS_VALU":
                 e["valu_lane_instr_per_attempt"] = round(v * 64.0 / att, 3)
+            elif counter == "VALUBusy":
+                e["valu_busy_pct"] = round(statistics.median(vals), 1)
     if len(hashes) != 1:
         raise SystemExit(f"counter runs were taken on different kernel sources: {hashes}")
     out = {"kernel_source_hash": hashes.pop(), "copy_calibration": calib,
@@ -342,6 +357,20 @@ def summarize_counters(dirs):
     with open(COUNTERS, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
+
+
+def copy_calibration(torch, mib):
+    """One plain device copy of mib MiB (the reference dispatch that scales
+    rocprofv3 FETCH_SIZE / WRITE_SIZE); returns its size in bytes."""
+    if mib <= 0:
+        return 0
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    return n
 
 
 def main():
@@ -358,6 +387,8 @@ def main():
                     help="sweeps of the per-kernel timing run after the timed steps")
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--nt", choices=["auto", "on", "off"], default="auto",
+                    help="nontemporal own-plane access of the streamed passes")
     ap.add_argument("--cpu-sweeps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true",
@@ -367,6 +398,9 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (the reference "
                          "dispatch that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
+    ap.add_argument("--ising-probe", type=int, default=0, metavar="N",
+                    help="run only the streamed Ising probe with N replicas of 256x256 "
+                         "(--prof-sweeps sweeps; for counter collection)")
     ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
                     help="write the counter summary from rocprofv3 --pmc runs of this script "
                          "(each DIR holds the run's counter csv and its stdout as bench.out)")
@@ -384,6 +418,20 @@ def main():
     import synth
     from paper_2304_01772_amd.sampler import Sampler, MODES
 
+    if args.ising_probe:
+        # the streamed Ising probe alone (counter collection for its roofline)
+        sched = None
+        if args.tile_rows or args.threads or args.nt != "auto":
+            sched = dict(tile_rows=args.tile_rows, wg_threads=args.threads,
+                         nt={"auto": None, "on": True, "off": False}[args.nt])
+        res, cfg = ising_stream_probe(Sampler, torch, args.ising_probe, args.prof_sweeps, sched)
+        n_copy = copy_calibration(torch, args.copy_calibration_mib)
+        cfg.update(schedule_name=f"ising_probe_{args.ising_probe}",
+                   profiled_sweeps=args.prof_sweeps, copy_calibration_bytes=n_copy)
+        print(json.dumps({"ising_probe": res, "config": cfg, "argv": sys.argv[1:],
+                          "kernel_source_hash": kernel_source_hash()}), flush=True)
+        return
+
     reps = synth.batched_ising_potts()
     seed = 2
     sites = sum(r["Lx"] * r["Ly"] for r in reps)
@@ -396,7 +444,8 @@ def main():
         tuning = dict(chosen=chosen, candidate_rates=[round(r, 1) for r in rates])
         print(f"# autotune: {tuning}", file=sys.stderr, flush=True)
     else:
-        smp.set_schedule(mode=args.mode, tile_rows=args.tile_rows, wg_threads=args.threads)
+        smp.set_schedule(mode=args.mode, tile_rows=args.tile_rows, wg_threads=args.threads,
+                         nt={"auto": None, "on": True, "off": False}[args.nt])
     sched = smp.get_schedule()
     mode_name = {v: k for k, v in MODES.items()}[sched["mode"]]
     for w in range(args.warmup):
@@ -431,18 +480,11 @@ def main():
         roof["units"] = f"{mode_name} schedule of the workload, {args.prof_sweeps} sweeps"
     smp.close()
 
-    n_copy = 0
-    if args.copy_calibration_mib > 0:
-        n_copy = args.copy_calibration_mib << 20
-        src = torch.ones(n_copy, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    n_copy = copy_calibration(torch, args.copy_calibration_mib)
 
     probes = {}
     for n_rep in (() if args.no_probes else (1024, 8192)):
-        probes[f"ising_{n_rep}x256x256_stream"] = ising_stream_probe(Sampler, torch, n_rep, 100)
+        probes[f"ising_{n_rep}x256x256_stream"], _ = ising_stream_probe(Sampler, torch, n_rep, 100)
         print(f"# Ising stream probe {n_rep}: {probes[f'ising_{n_rep}x256x256_stream']}",
               file=sys.stderr, flush=True)
 

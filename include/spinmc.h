@@ -178,13 +178,21 @@ int spinmc_thresholds(const spinmc_ctx *ctx, int32_t replica, uint64_t *host_T, 
  * Calls without recording replay cached hipGraphs of 50-sweep chunks
  * (streamed passes and the concurrent resident branch captured together).
  * tile_rows: rows of a plane per streamed unit (even; 0 = about 16 KiB);
- * wg_threads: 256 or 512 (0 = default).  Invalid values
- * return SPINMC_E_INVALID.  CPM contexts use tile_rows and wg_threads only. */
+ * wg_threads: 256 or 512 (0 = default);
+ * flags: 0, SPINMC_SCHED_NT_ON or SPINMC_SCHED_NT_OFF: streamed passes load
+ *   and store their own colour plane with nontemporal hints (bypassing the
+ *   caches, for lattice sets that do not fit the 256 MB last-level cache).
+ *   0 decides per model: on when that model's streamed lattices exceed
+ *   192 MiB.  The chain is the same either way.
+ * Invalid values return SPINMC_E_INVALID.  CPM contexts use tile_rows and
+ * wg_threads only.  spinmc_autotune also tries the best streaming schedule
+ * with NT forced on and off.                                                */
+enum { SPINMC_SCHED_NT_ON = 1, SPINMC_SCHED_NT_OFF = 2 };
 typedef struct spinmc_schedule {
     int32_t mode;
     int32_t tile_rows;
     int32_t wg_threads;
-    int32_t reserved;
+    int32_t flags;
 } spinmc_schedule;
 
 int spinmc_set_schedule(spinmc_ctx *ctx, const spinmc_schedule *s);

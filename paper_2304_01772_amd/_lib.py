@@ -32,7 +32,7 @@ class ReplicaDesc(C.Structure):
 
 class Schedule(C.Structure):
     _fields_ = [("mode", C.c_int32), ("tile_rows", C.c_int32), ("wg_threads", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("flags", C.c_int32)]
 
 
 # name -> (restype, argtypes); the exported C ABI of include/spinmc.h

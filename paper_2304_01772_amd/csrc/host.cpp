@@ -38,6 +38,9 @@ constexpr int kMaxCpmCells = 1 << 20;
 constexpr int kGraphChunk = 50;  // sweeps per captured graph
 constexpr int kSide = 4;         // side streams for concurrent resident groups
 constexpr size_t kResidentLdsBudget = 150 * 1024;
+// Streamed lattice sets beyond this size do not stay in the 256 MB last-level
+// cache between passes: their own-plane traffic goes nontemporal by default.
+constexpr size_t kNtAutoBytes = 192ull << 20;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -131,6 +134,7 @@ struct spinmc_ctx {
     hipStream_t cap[1 + kSide] = {};
     hipEvent_t cap_ev[1 + kSide] = {};
     // resident workgroup groups (replicas of one shape packed rpb per workgroup)
+    bool nt_ising = false, nt_potts = false;  // nontemporal own-plane access per model
     struct ResGroup {
         int off, count, rpb, threads, model;
         bool chunk;
@@ -624,6 +628,8 @@ int spinmc_set_schedule(spinmc_ctx* c, const spinmc_schedule* s) {
         return fail(SPINMC_E_INVALID, "set_schedule: tile_rows must be even and >= 0");
     if (s->wg_threads != 0 && s->wg_threads != 256 && s->wg_threads != 512)
         return fail(SPINMC_E_INVALID, "set_schedule: wg_threads must be 256 or 512");
+    if (s->flags != 0 && s->flags != SPINMC_SCHED_NT_ON && s->flags != SPINMC_SCHED_NT_OFF)
+        return fail(SPINMC_E_INVALID, "set_schedule: flags must be 0, NT_ON or NT_OFF");
     if (s->mode == 1 && !c->cpm)
         for (const HostRep& h : c->reps)
             if (!h.resident)
@@ -792,8 +798,8 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
     int best = -1;
     double best_rate = 0;
     int tried = 0;
-    for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
-        c->sched = cand[k];
+    auto trial = [&](const spinmc_schedule& sc) -> double {
+        c->sched = sc;
         c->prepared = false;
         // one warm-up sweep builds tiles and graphs
         int rc = c->cpm ? cpm_sweep(c, 1, 0, nullptr) : enqueue_sweep(c, 1, 0, nullptr);
@@ -801,16 +807,16 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
                                          : enqueue_sweep(c, trial_sweeps, 0, nullptr);
         if (rc != SPINMC_OK) {
             e = hipErrorUnknown;
-            break;
+            return 0.0;
         }
         e = restore();
-        if (e != hipSuccess) break;
+        if (e != hipSuccess) return 0.0;
         e = hipEventRecord(e0, c->stream);
         rc = c->cpm ? cpm_sweep(c, trial_sweeps, 0, nullptr)
                     : enqueue_sweep(c, trial_sweeps, 0, nullptr);
         if (rc != SPINMC_OK) {
             e = hipErrorUnknown;
-            break;
+            return 0.0;
         }
         if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
         if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -819,11 +825,32 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
         const double rate = ms > 0 ? sites * trial_sweeps / (ms * 1e6) : 0.0;
         if (rates && tried < cap) rates[tried] = rate;
         ++tried;
-        if (rate > best_rate) {
+        if (e == hipSuccess) e = restore();
+        return rate;
+    };
+    for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
+        const double rate = trial(cand[k]);
+        if (e == hipSuccess && rate > best_rate) {
             best_rate = rate;
             best = (int)k;
         }
-        if (e == hipSuccess) e = restore();
+    }
+    // the best streaming schedule with nontemporal own-plane access forced
+    // on and off (candidates so far use the size rule)
+    if (e == hipSuccess && best >= 0 && !c->cpm && cand[best].mode >= 2) {
+        const size_t nb = cand.size();
+        for (int f : {SPINMC_SCHED_NT_ON, SPINMC_SCHED_NT_OFF}) {
+            spinmc_schedule sc = cand[best];
+            sc.flags = f;
+            cand.push_back(sc);
+        }
+        for (size_t k = nb; k < cand.size() && e == hipSuccess; ++k) {
+            const double rate = trial(cand[k]);
+            if (e == hipSuccess && rate > best_rate) {
+                best_rate = rate;
+                best = (int)k;
+            }
+        }
     }
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
@@ -874,7 +901,7 @@ void drop_graphs(spinmc_ctx* c) {
 //   mode 3: resident if it fits the LDS budget, streamed otherwise.
 int prepare(spinmc_ctx* c, int mode) {
     const int tr = c->sched.tile_rows;
-    const long key = ((long)mode << 32) | (long)(unsigned)tr;
+    const long key = ((long)mode << 40) | ((long)c->sched.flags << 32) | (long)(unsigned)tr;
     if (c->prepared && c->prepared_key == key) return SPINMC_OK;
     std::vector<int32_t> res_chunk, res_gen, spotts;
     std::vector<TileDev> tiles, ptiles;  // Ising tiles first, then Potts tiles
@@ -893,6 +920,17 @@ int prepare(spinmc_ctx* c, int mode) {
     }
     c->n_tiles_ising = (int)tiles.size();
     tiles.insert(tiles.end(), ptiles.begin(), ptiles.end());
+    {
+        size_t bi = 0, bp = 0;
+        for (int i = 0; i < c->R; ++i) {
+            const HostRep& h = c->reps[i];
+            const bool resident = (mode == 1) || !h.chunk || (mode == 3 && h.resident);
+            if (!resident) (h.dev.model == SPINMC_ISING ? bi : bp) += h.lat_bytes;
+        }
+        const int f = c->sched.flags;
+        c->nt_ising = f == SPINMC_SCHED_NT_ON || (f == 0 && bi > kNtAutoBytes);
+        c->nt_potts = f == SPINMC_SCHED_NT_ON || (f == 0 && bp > kNtAutoBytes);
+    }
     hipError_t e = hipStreamSynchronize(c->stream);
     drop_graphs(c);
     c->res_chunk = res_chunk;
@@ -1029,12 +1067,12 @@ hipError_t enqueue_stream(spinmc_ctx* c, const SweepArgs& a, int i0, int n, int 
             if (ni > 0)
                 e = timed(c, SPINMC_K_STREAM_ISING, [&] {
                     return launch_stream_pass(a, SPINMC_ISING, 0, ni, col, i, rr, threads,
-                                              a.tab_lds_bytes, s);
+                                              a.tab_lds_bytes, c->nt_ising, s);
                 }, s);
             if (e == hipSuccess && np > 0)
                 e = timed(c, SPINMC_K_STREAM_POTTS, [&] {
                     return launch_stream_pass(a, SPINMC_POTTS, ni, np, col, i, rr, threads,
-                                              a.tab_lds_bytes, s);
+                                              a.tab_lds_bytes, c->nt_potts, s);
                 }, s);
         }
         if (e == hipSuccess && rec && !c->stream_potts.empty())

@@ -70,16 +70,39 @@ __device__ __forceinline__ uint32_t sign_bytes(uint32_t d0, uint32_t d1, uint32_
 // dword holding the horizontal neighbour of the first (PAR = 0) or last
 // (PAR = 1) byte.  Loading is split from computing so that a lane can keep
 // two chunks' loads in flight.
+// 16-byte accesses of the own-colour plane; NT marks them nontemporal
+// (streamed past the caches) for lattice sets larger than the last-level
+// cache, where the own plane is read once and written once per pass.
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+template <bool NT>
+__device__ __forceinline__ uint4 load_own(const uint8_t* p) {
+    if (NT) {
+        const u32x4_t t = __builtin_nontemporal_load(reinterpret_cast<const u32x4_t*>(p));
+        return make_uint4(t.x, t.y, t.z, t.w);
+    }
+    return *reinterpret_cast<const uint4*>(p);
+}
+template <bool NT>
+__device__ __forceinline__ void store_own(uint8_t* p, uint32_t a, uint32_t b, uint32_t c,
+                                          uint32_t d) {
+    if (NT) {
+        const u32x4_t t = {a, b, c, d};
+        __builtin_nontemporal_store(t, reinterpret_cast<u32x4_t*>(p));
+    } else {
+        *reinterpret_cast<uint4*>(p) = make_uint4(a, b, c, d);
+    }
+}
+
 struct ChunkIn {
     uint4 o, m, U, D;
     uint32_t e;
 };
 
-template <int PAR>
+template <int PAR, bool NT>
 __device__ __forceinline__ ChunkIn chunk_load(const uint8_t* own, const uint8_t* oth, int W,
                                               uint32_t ro, uint32_t rom, uint32_t rop, int j0) {
     ChunkIn in;
-    in.o = *reinterpret_cast<const uint4*>(own + ro + j0);
+    in.o = load_own<NT>(own + ro + j0);
     in.m = *reinterpret_cast<const uint4*>(oth + ro + j0);
     in.U = *reinterpret_cast<const uint4*>(oth + rom + j0);
     in.D = *reinterpret_cast<const uint4*>(oth + rop + j0);
@@ -90,7 +113,7 @@ __device__ __forceinline__ ChunkIn chunk_load(const uint8_t* own, const uint8_t*
 
 // PAR = (y + c) & 1 selects which horizontal neighbour the shifted byte
 // stream supplies.  thr: LDS [18 hi | 18 lo].
-template <int PAR, bool REC>
+template <int PAR, bool REC, bool NT>
 __device__ __forceinline__ void ising_compute(const ChunkIn& in, uint8_t* own, uint32_t ro, int j0,
                                               uint32_t p, uint32_t rid, uint32_t k0, uint32_t k1,
                                               const uint32_t* thr, IsingAcc& acc) {
@@ -154,7 +177,7 @@ __device__ __forceinline__ void ising_compute(const ChunkIn& in, uint8_t* own, u
     uint32_t nv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) nv[k] = ov[k] ^ flip[k];
-    *reinterpret_cast<uint4*>(own + ro + j0) = make_uint4(nv[0], nv[1], nv[2], nv[3]);
+    store_own<NT>(own + ro + j0, nv[0], nv[1], nv[2], nv[3]);
     if (REC) {
         // Colour-1 pass of a recorded sweep: every bond has exactly one
         // colour-1 end, so summing over the updated sites counts each once.
@@ -184,14 +207,14 @@ __device__ __forceinline__ uint32_t ne_hi(uint32_t a, uint32_t b) {
 
 // 16-site Potts chunk.  thr: LDS [n hi | n lo], n = 9(2q-1); thr9: LDS
 // [9 hi | 9 lo] by dn + 4 (used when HZ, i.e. h = 0).
-template <int PAR, bool REC, bool HZ>
+template <int PAR, bool REC, bool HZ, bool NT>
 __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, int W, uint32_t ro,
                                             uint32_t rom, uint32_t rop, int j0, uint32_t p,
                                             uint32_t rid, uint32_t k0, uint32_t k1,
                                             const uint32_t* thr, const uint32_t* thr9, int q,
                                             int ntab, uint32_t lem_thr, PottsAcc& acc,
                                             int* lhist) {
-    const uint4 o = *reinterpret_cast<const uint4*>(own + ro + j0);
+    const uint4 o = load_own<NT>(own + ro + j0);
     const uint4 m = *reinterpret_cast<const uint4*>(oth + ro + j0);
     const uint4 U = *reinterpret_cast<const uint4*>(oth + rom + j0);
     const uint4 D = *reinterpret_cast<const uint4*>(oth + rop + j0);
@@ -335,7 +358,7 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
     uint32_t nv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) nv[k] = (s2v[k] & acc_sel[k]) | (ov[k] & ~acc_sel[k]);
-    *reinterpret_cast<uint4*>(own + ro + j0) = make_uint4(nv[0], nv[1], nv[2], nv[3]);
+    store_own<NT>(own + ro + j0, nv[0], nv[1], nv[2], nv[3]);
     if (REC) {
         uint32_t nex = 0u, ney = 0u, ssum = 0u;
 #pragma unroll
@@ -361,7 +384,7 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
 // tid = 0..nthr-1 (a whole workgroup, or the share of one replica when a
 // workgroup holds several).  Rows are visited by parity so that PAR is
 // uniform across a wave.
-template <bool REC, bool HZ>
+template <bool REC, bool HZ, bool NT>
 __device__ __forceinline__ void run_tile_potts(uint8_t* planes, int W, int Ly, int y0, int rows,
                                                int c, uint32_t p, uint32_t rid, uint32_t k0,
                                                uint32_t k1, const uint32_t* thr,
@@ -387,10 +410,10 @@ __device__ __forceinline__ void run_tile_potts(uint8_t* planes, int W, int Ly, i
             const uint32_t rop = ro == last ? 0u : ro + (uint32_t)W;
             const int j0 = jc << 4;
             if (par == 0)
-                potts_chunk<0, REC, HZ>(own, oth, W, ro, rom, rop, j0, p, rid, k0, k1, thr, thr9, q,
+                potts_chunk<0, REC, HZ, NT>(own, oth, W, ro, rom, rop, j0, p, rid, k0, k1, thr, thr9, q,
                                         ntab, lem_thr, pa, lhist);
             else
-                potts_chunk<1, REC, HZ>(own, oth, W, ro, rom, rop, j0, p, rid, k0, k1, thr, thr9, q,
+                potts_chunk<1, REC, HZ, NT>(own, oth, W, ro, rom, rop, j0, p, rid, k0, k1, thr, thr9, q,
                                         ntab, lem_thr, pa, lhist);
             r += dr;
             jc += dj;
@@ -406,7 +429,7 @@ __device__ __forceinline__ void run_tile_potts(uint8_t* planes, int W, int Ly, i
 // each row parity per iteration and issues both chunks' loads before
 // computing (latency hiding for the HBM stream); otherwise one chunk per
 // iteration, parity by parity (fewer registers for the LDS-resident path).
-template <bool REC, bool DUAL>
+template <bool REC, bool DUAL, bool NT>
 __device__ __forceinline__ void run_tile_ising(uint8_t* planes, int W, int Ly, int y0, int rows,
                                                int c, uint32_t p, uint32_t rid, uint32_t k0,
                                                uint32_t k1, const uint32_t* thr, IsingAcc& ia,
@@ -427,12 +450,12 @@ __device__ __forceinline__ void run_tile_ising(uint8_t* planes, int W, int Ly, i
             const int j0 = jc << 4;
             const uint32_t ra = (uint32_t)(ya + 2 * r) * (uint32_t)W;
             const uint32_t rb = (uint32_t)(yb + 2 * r) * (uint32_t)W;
-            const ChunkIn A = chunk_load<0>(own, oth, W, ra, ra == 0u ? last : ra - (uint32_t)W,
+            const ChunkIn A = chunk_load<0, NT>(own, oth, W, ra, ra == 0u ? last : ra - (uint32_t)W,
                                             ra == last ? 0u : ra + (uint32_t)W, j0);
-            const ChunkIn B = chunk_load<1>(own, oth, W, rb, rb == 0u ? last : rb - (uint32_t)W,
+            const ChunkIn B = chunk_load<1, NT>(own, oth, W, rb, rb == 0u ? last : rb - (uint32_t)W,
                                             rb == last ? 0u : rb + (uint32_t)W, j0);
-            ising_compute<0, REC>(A, own, ra, j0, p, rid, k0, k1, thr, ia);
-            ising_compute<1, REC>(B, own, rb, j0, p, rid, k0, k1, thr, ia);
+            ising_compute<0, REC, NT>(A, own, ra, j0, p, rid, k0, k1, thr, ia);
+            ising_compute<1, REC, NT>(B, own, rb, j0, p, rid, k0, k1, thr, ia);
             r += dr;
             jc += dj;
             if (jc >= cpr) {
@@ -451,11 +474,11 @@ __device__ __forceinline__ void run_tile_ising(uint8_t* planes, int W, int Ly, i
                 const uint32_t rom = ro == 0u ? last : ro - (uint32_t)W;
                 const uint32_t rop = ro == last ? 0u : ro + (uint32_t)W;
                 if (par == 0) {
-                    const ChunkIn A = chunk_load<0>(own, oth, W, ro, rom, rop, j0);
-                    ising_compute<0, REC>(A, own, ro, j0, p, rid, k0, k1, thr, ia);
+                    const ChunkIn A = chunk_load<0, NT>(own, oth, W, ro, rom, rop, j0);
+                    ising_compute<0, REC, NT>(A, own, ro, j0, p, rid, k0, k1, thr, ia);
                 } else {
-                    const ChunkIn B = chunk_load<1>(own, oth, W, ro, rom, rop, j0);
-                    ising_compute<1, REC>(B, own, ro, j0, p, rid, k0, k1, thr, ia);
+                    const ChunkIn B = chunk_load<1, NT>(own, oth, W, ro, rom, rop, j0);
+                    ising_compute<1, REC, NT>(B, own, ro, j0, p, rid, k0, k1, thr, ia);
                 }
                 r += dr;
                 jc += dj;
@@ -491,17 +514,17 @@ __device__ __forceinline__ void load_table9(const uint32_t* tab, const RepDev& R
 }
 
 // Potts tile with the h = 0 specialisation chosen per replica.
-template <bool REC>
+template <bool REC, bool NT>
 __device__ __forceinline__ void potts_tile(const RepDev& R, uint8_t* planes, int y0, int rows,
                                            int c, uint32_t p, uint32_t k0, uint32_t k1,
                                            const uint32_t* thr, const uint32_t* thr9,
                                            PottsAcc& pa, int* lhist, int tid, int nthr) {
     const uint32_t lt = lemire_threshold(R.q);
     if (R.h == 0.0f)
-        run_tile_potts<REC, true>(planes, R.W, R.Ly, y0, rows, c, p, R.rid, k0, k1, thr, thr9, R.q,
+        run_tile_potts<REC, true, NT>(planes, R.W, R.Ly, y0, rows, c, p, R.rid, k0, k1, thr, thr9, R.q,
                                   R.tab_n, lt, pa, lhist, tid, nthr);
     else
-        run_tile_potts<REC, false>(planes, R.W, R.Ly, y0, rows, c, p, R.rid, k0, k1, thr, thr9,
+        run_tile_potts<REC, false, NT>(planes, R.W, R.Ly, y0, rows, c, p, R.rid, k0, k1, thr, thr9,
                                    R.q, R.tab_n, lt, pa, lhist, tid, nthr);
 }
 
@@ -521,7 +544,7 @@ __device__ __forceinline__ int logical_block(int n) {
 // One colour pass over the row tiles [tile0, tile0 + n) of one model.  The
 // two models have separate kernels so that each gets its own register
 // budget (Ising needs about half of Potts's, hence twice the waves per SIMD).
-template <int MODEL>
+template <int MODEL, bool NT>
 __device__ __forceinline__ void stream_pass_body(const SweepArgs& a, int tile0, int n, int c,
                                                  int sweep_off, int rec_row, uint32_t* lthr,
                                                  uint32_t* lthr9, int* lhist, int* lred) {
@@ -540,17 +563,17 @@ __device__ __forceinline__ void stream_pass_body(const SweepArgs& a, int tile0, 
     PottsAcc pa{0, 0, 0};
     if (MODEL == kModelIsing) {
         if (rec)
-            run_tile_ising<true, true>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
+            run_tile_ising<true, true, NT>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
                                  lthr, ia, threadIdx.x, blockDim.x);
         else
-            run_tile_ising<false, true>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
+            run_tile_ising<false, true, NT>(planes, R.W, R.Ly, T.y0, T.rows, c, p, R.rid, a.key0, a.key1,
                                   lthr, ia, threadIdx.x, blockDim.x);
     } else {
         if (rec)
-            potts_tile<true>(R, planes, T.y0, T.rows, c, p, a.key0, a.key1, lthr, lthr9, pa,
+            potts_tile<true, NT>(R, planes, T.y0, T.rows, c, p, a.key0, a.key1, lthr, lthr9, pa,
                              lhist, threadIdx.x, blockDim.x);
         else
-            potts_tile<false>(R, planes, T.y0, T.rows, c, p, a.key0, a.key1, lthr, lthr9, pa,
+            potts_tile<false, NT>(R, planes, T.y0, T.rows, c, p, a.key0, a.key1, lthr, lthr9, pa,
                               lhist, threadIdx.x, blockDim.x);
     }
     if (rec) {
@@ -577,22 +600,24 @@ __device__ __forceinline__ void stream_pass_body(const SweepArgs& a, int tile0, 
 
 // Occupancy targets: the Ising pass is memory-streaming and wants many
 // waves in flight; the Potts pass is VALU-heavy and keeps more registers.
+template <bool NT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 8)))
 k_stream_pass_ising(SweepArgs a, int tile0, int n, int c, int sweep_off, int rec_row) {
     extern __shared__ uint32_t lthr[];  // [2 * tab_n] thresholds of this tile's replica
     __shared__ uint32_t lthr9[18];
     __shared__ int lhist[kMaxPottsQ];
     __shared__ int lred[64];
-    stream_pass_body<kModelIsing>(a, tile0, n, c, sweep_off, rec_row, lthr, lthr9, lhist, lred);
+    stream_pass_body<kModelIsing, NT>(a, tile0, n, c, sweep_off, rec_row, lthr, lthr9, lhist, lred);
 }
 
+template <bool NT>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3, 8)))
 k_stream_pass_potts(SweepArgs a, int tile0, int n, int c, int sweep_off, int rec_row) {
     extern __shared__ uint32_t lthr[];
     __shared__ uint32_t lthr9[18];
     __shared__ int lhist[kMaxPottsQ];
     __shared__ int lred[64];
-    stream_pass_body<kModelPotts>(a, tile0, n, c, sweep_off, rec_row, lthr, lthr9, lhist, lred);
+    stream_pass_body<kModelPotts, NT>(a, tile0, n, c, sweep_off, rec_row, lthr, lthr9, lhist, lred);
 }
 
 // nmax of each Potts replica from its histogram; clears the histogram.
@@ -748,11 +773,11 @@ __device__ __forceinline__ void resident_body(const SweepArgs& a) {
             if (active) {
                 if (KIND == kResIsing) {
                     IsingAcc ia{0, 0, 0};
-                    run_tile_ising<false, false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0, a.key1,
+                    run_tile_ising<false, false, false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0, a.key1,
                                           lthr, ia, lt, nt);
                 } else if (KIND == kResPotts) {
                     PottsAcc pa{0, 0, 0};
-                    potts_tile<false>(R, lds, 0, R.Ly, c, p, a.key0, a.key1, lthr, lthr9[g], pa,
+                    potts_tile<false, false>(R, lds, 0, R.Ly, c, p, a.key0, a.key1, lthr, lthr9[g], pa,
                                       lhist, lt, nt);
                 } else {
                     for (int k = lt; k < plane; k += nt)
@@ -935,14 +960,24 @@ hipError_t launch_resident(const SweepArgs& a, int n_list, int model, bool chunk
 
 hipError_t launch_stream_pass(const SweepArgs& a, int model, int tile0, int n_tiles, int c,
                               int sweep_off, int rec_row, int threads, size_t lds_tab_bytes,
-                              hipStream_t s) {
+                              bool nt, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
-    if (model == kModelIsing)
-        hipLaunchKernelGGL(k_stream_pass_ising, dim3(n_tiles), dim3(threads), lds_tab_bytes, s, a,
-                           tile0, n_tiles, c, sweep_off, rec_row);
-    else
-        hipLaunchKernelGGL(k_stream_pass_potts, dim3(n_tiles), dim3(threads), lds_tab_bytes, s, a,
-                           tile0, n_tiles, c, sweep_off, rec_row);
+    const dim3 g(n_tiles), b(threads);
+    if (model == kModelIsing) {
+        if (nt)
+            hipLaunchKernelGGL(k_stream_pass_ising<true>, g, b, lds_tab_bytes, s, a, tile0, n_tiles,
+                               c, sweep_off, rec_row);
+        else
+            hipLaunchKernelGGL(k_stream_pass_ising<false>, g, b, lds_tab_bytes, s, a, tile0,
+                               n_tiles, c, sweep_off, rec_row);
+    } else {
+        if (nt)
+            hipLaunchKernelGGL(k_stream_pass_potts<true>, g, b, lds_tab_bytes, s, a, tile0, n_tiles,
+                               c, sweep_off, rec_row);
+        else
+            hipLaunchKernelGGL(k_stream_pass_potts<false>, g, b, lds_tab_bytes, s, a, tile0,
+                               n_tiles, c, sweep_off, rec_row);
+    }
     return hipGetLastError();
 }
 

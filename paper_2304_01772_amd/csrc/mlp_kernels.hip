@@ -66,20 +66,49 @@ __device__ __forceinline__ float4v mfma(short4v a, short4v b, float4v c) {
 }
 
 // Weights into LDS as BF16, [out][in] rows (B^T layout of the matrix cores).
+// 16-byte loads, all of a thread's loads issued before their conversions.
 __device__ void stage_weights(const float* P, uint16_t* w1, uint16_t* w2, uint16_t* w3,
                               bool need_w2) {
-    for (int i = threadIdx.x; i < kH * 16; i += blockDim.x) {
-        const int n = i >> 4, k = i & 15;
-        w1[n * kS1 + k] = k < kIn ? f2bf(P[oW1 + n * kIn + k]) : (uint16_t)0;
+    // W1: 128 x 4 -> rows of 16 (k >= 4 zero); one float4 per row
+    for (int n = threadIdx.x; n < kH; n += blockDim.x) {
+        const float4 v = *reinterpret_cast<const float4*>(P + oW1 + n * kIn);
+        uint16_t* r = w1 + n * kS1;
+        r[0] = f2bf(v.x);
+        r[1] = f2bf(v.y);
+        r[2] = f2bf(v.z);
+        r[3] = f2bf(v.w);
+#pragma unroll
+        for (int k = kIn; k < 16; ++k) r[k] = 0;
     }
-    if (need_w2)
-        for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) {
-            const int n = i >> 7, k = i & 127;
-            w2[n * kS2 + k] = f2bf(P[oW2 + n * kH + k]);
+    if (need_w2) {
+        constexpr int kV = kH * kH / 4;  // float4 of W2
+        const float4* src = reinterpret_cast<const float4*>(P + oW2);
+        for (int i0 = threadIdx.x; i0 < kV; i0 += 16 * blockDim.x) {
+            float4 v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                v[u] = i < kV ? src[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                if (i >= kV) break;
+                const int n = (4 * i) >> 7, k = (4 * i) & 127;
+                const uint32_t lo = (uint32_t)f2bf(v[u].x) | ((uint32_t)f2bf(v[u].y) << 16);
+                const uint32_t hi = (uint32_t)f2bf(v[u].z) | ((uint32_t)f2bf(v[u].w) << 16);
+                *reinterpret_cast<uint2*>(w2 + n * kS2 + k) = make_uint2(lo, hi);
+            }
         }
-    for (int i = threadIdx.x; i < 16 * kH; i += blockDim.x) {
-        const int n = i >> 7, k = i & 127;
-        w3[n * kS2 + k] = n < kOut ? f2bf(P[oW3 + n * kH + k]) : (uint16_t)0;
+    }
+    // W3: 3 x 128 -> 16 rows (rows >= 3 zero)
+    for (int i = threadIdx.x; i < 16 * kH / 4; i += blockDim.x) {
+        const int n = (4 * i) >> 7, k = (4 * i) & 127;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (n < kOut) v = *reinterpret_cast<const float4*>(P + oW3 + n * kH + k);
+        const uint32_t lo = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+        const uint32_t hi = (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
+        *reinterpret_cast<uint2*>(w3 + n * kS2 + k) = make_uint2(lo, hi);
     }
 }
 
@@ -171,25 +200,66 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(const float* P, const float* x,
     constexpr int kSZ = kH + 4;
     __shared__ __align__(16) float dz1[kSamplesPerWG * kSZ];
     __shared__ float dY[kSamplesPerWG][4];
+    __shared__ float xs[kSamplesPerWG][kIn];  // bf16-rounded inputs, as float
     __shared__ float red[256];
     stage_weights(P, w1, nullptr, w3, false);
-    for (int i = threadIdx.x; i < kH * kH; i += blockDim.x) {
-        const int o = i >> 7, in = i & 127;
-        w2t[in * kS2 + o] = f2bf(P[oW2 + o * kH + in]);
+    {
+        constexpr int kV = kH * kH / 4;
+        const float4* src = reinterpret_cast<const float4*>(P + oW2);
+        for (int i0 = threadIdx.x; i0 < kV; i0 += 16 * blockDim.x) {
+            float4 v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                v[u] = i < kV ? src[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int i = i0 + u * (int)blockDim.x;
+                if (i >= kV) break;
+                const int o = (4 * i) >> 7, in = (4 * i) & 127;
+                w2t[(in + 0) * kS2 + o] = f2bf(v[u].x);
+                w2t[(in + 1) * kS2 + o] = f2bf(v[u].y);
+                w2t[(in + 2) * kS2 + o] = f2bf(v[u].z);
+                w2t[(in + 3) * kS2 + o] = f2bf(v[u].w);
+            }
+        }
     }
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int base = blockIdx.x * kSamplesPerWG;
+    for (int i = threadIdx.x; i < kSamplesPerWG * kIn; i += blockDim.x) {
+        const int gs = base + i / kIn;
+        xs[i / kIn][i % kIn] = gs < B ? bf2f(f2bf(x[(size_t)gs * kIn + i % kIn])) : 0.f;
+    }
     // h1 (transposed) and h2 from the stored pre-activations
-    for (int i = threadIdx.x; i < kSamplesPerWG * kH; i += blockDim.x) {
-        const int s = i >> 7, n = i & 127;
-        const int gs = base + s;
-        float z1 = 0.f, z2 = 0.f;
-        if (gs < B) {
-            z1 = act[(size_t)gs * 2 * kH + n];
-            z2 = act[(size_t)gs * 2 * kH + kH + n];
+    {
+        constexpr int kV = kSamplesPerWG * kH / 4;  // float4 per layer
+        static_assert(kV % 256 == 0, "act staging assumes 256 threads");
+        float4 z1[kV / 256], z2[kV / 256];
+#pragma unroll
+        for (int u = 0; u < kV / 256; ++u) {
+            const int i = threadIdx.x + 256 * u;
+            const int sm = (4 * i) >> 7, n = (4 * i) & 127;
+            const int gs = base + sm;
+            z1[u] = z2[u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (gs < B) {
+                z1[u] = *reinterpret_cast<const float4*>(act + (size_t)gs * 2 * kH + n);
+                z2[u] = *reinterpret_cast<const float4*>(act + (size_t)gs * 2 * kH + kH + n);
+            }
         }
-        h1t[n * kST + s] = gs < B ? f2bf(silu(z1)) : (uint16_t)0;
-        h2[s >> 4][(s & 15) * kS2 + n] = gs < B ? f2bf(silu(z2)) : (uint16_t)0;
+#pragma unroll
+        for (int u = 0; u < kV / 256; ++u) {
+            const int i = threadIdx.x + 256 * u;
+            const int sm = (4 * i) >> 7, n = (4 * i) & 127;
+            const bool in_b = base + sm < B;
+            const float a1[4] = {z1[u].x, z1[u].y, z1[u].z, z1[u].w};
+            const float a2[4] = {z2[u].x, z2[u].y, z2[u].z, z2[u].w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                h1t[(n + c) * kST + sm] = in_b ? f2bf(silu(a1[c])) : (uint16_t)0;
+                h2[sm >> 4][(sm & 15) * kS2 + n + c] = in_b ? f2bf(silu(a2[c])) : (uint16_t)0;
+            }
+        }
     }
     __syncthreads();
     // recompute y for the wave's samples, then dY and the loss
@@ -227,6 +297,7 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(const float* P, const float* x,
         const uint16_t db = f2bf(d);
         dz2t[n * kST + s] = db;
         dz2[s * kS2 + n] = db;
+        dz1[s * kSZ + n] = d;  // unrounded dz2, for db2 (dz1 is computed later)
     }
     __syncthreads();
     float* pg = part + (size_t)blockIdx.x * (kNP + 1);
@@ -257,18 +328,11 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(const float* P, const float* x,
         for (int q = 0; q < kSamplesPerWG; ++q) s += dY[q][threadIdx.x];
         pg[ob3 + threadIdx.x] = s;
     }
-    // db2 = sum of the unrounded dz2: recompute per neuron
+    // db2 = sum of the unrounded dz2 (zero for samples past B)
     if (threadIdx.x < kH) {
         const int n = threadIdx.x;
         float s = 0.f;
-        for (int q = 0; q < kSamplesPerWG; ++q) {
-            const int gs = base + q;
-            if (gs >= B) break;
-            float dh = 0.f;
-#pragma unroll
-            for (int j = 0; j < kOut; ++j) dh += dY[q][j] * bf2f(w3[j * kS2 + n]);
-            s += dh * dsilu(act[(size_t)gs * 2 * kH + kH + n]);
-        }
+        for (int q = 0; q < kSamplesPerWG; ++q) s += dz1[q * kSZ + n];
         pg[ob2 + n] = s;
     }
     __syncthreads();
@@ -292,12 +356,8 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(const float* P, const float* x,
     for (int i = threadIdx.x; i < kH * (kIn + 1); i += blockDim.x) {
         const int n = i / (kIn + 1), k = i % (kIn + 1);
         float s = 0.f;
-        for (int q = 0; q < kSamplesPerWG; ++q) {
-            const int gs = base + q;
-            if (gs >= B) break;
-            const float xv = k < kIn ? bf2f(f2bf(x[(size_t)gs * kIn + k])) : 1.0f;
-            s += dz1[q * kSZ + n] * xv;
-        }
+        for (int q = 0; q < kSamplesPerWG; ++q)  // dz1 is zero for samples past B
+            s += dz1[q * kSZ + n] * (k < kIn ? xs[q][k] : 1.0f);
         if (k < kIn)
             pg[oW1 + n * kIn + k] = s;
         else

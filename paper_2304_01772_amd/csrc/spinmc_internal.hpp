@@ -108,9 +108,10 @@ hipError_t launch_resident(const SweepArgs& a, int n_list, int model, bool chunk
                            size_t lds_bytes, hipStream_t s);
 // Allow the resident kernels up to lds_bytes of dynamic LDS (call outside capture).
 hipError_t resident_reserve_lds(size_t lds_bytes);
+// nt: own-plane loads and stores nontemporal (lattice sets beyond the cache)
 hipError_t launch_stream_pass(const SweepArgs& a, int model, int tile0, int n_tiles, int c,
                               int sweep_off, int rec_row, int threads, size_t lds_tab_bytes,
-                              hipStream_t s);
+                              bool nt, hipStream_t s);
 hipError_t launch_potts_hist_finalize(const SweepArgs& a, const int32_t* list, int n, int rec_row,
                                       hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);

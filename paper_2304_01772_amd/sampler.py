@@ -14,6 +14,7 @@ from ._lib import ISING, POTTS, CPM, ReplicaDesc, Schedule, check, lib
 __all__ = ["Sampler", "ISING", "POTTS", "CPM", "MODES"]
 
 MODES = {"auto": 0, "resident": 1, "stream": 2, "hybrid": 3}
+NT_ON, NT_OFF = 1, 2  # spinmc_schedule.flags
 
 
 def _stream_handle(stream):
@@ -164,15 +165,18 @@ class Sampler:
         return float(ms.value), int(n.value)
 
     # ---------------------------------------------------------- schedules
-    def set_schedule(self, mode="auto", tile_rows=0, wg_threads=0):
+    def set_schedule(self, mode="auto", tile_rows=0, wg_threads=0, nt=None):
+        """nt: None (size rule), True or False (nontemporal own-plane access
+        of the streamed passes forced on / off)."""
+        flags = 0 if nt is None else (NT_ON if nt else NT_OFF)
         s = Schedule(MODES[mode] if isinstance(mode, str) else int(mode), int(tile_rows),
-                     int(wg_threads), 0)
+                     int(wg_threads), flags)
         check(lib().spinmc_set_schedule(self.ctx, C.byref(s)))
 
     def get_schedule(self):
         s = Schedule()
         check(lib().spinmc_get_schedule(self.ctx, C.byref(s)))
-        return dict(mode=s.mode, tile_rows=s.tile_rows, wg_threads=s.wg_threads)
+        return dict(mode=s.mode, tile_rows=s.tile_rows, wg_threads=s.wg_threads, flags=s.flags)
 
     def schedule_sites(self, by_model=False):
         """(streamed, resident) sites per sweep under the current schedule;
@@ -193,5 +197,5 @@ class Sampler:
         n = C.c_int32()
         check(lib().spinmc_autotune(self.ctx, int(trial_sweeps), C.byref(s), rates, 64,
                                     C.byref(n)))
-        return dict(mode=s.mode, tile_rows=s.tile_rows, wg_threads=s.wg_threads), \
+        return dict(mode=s.mode, tile_rows=s.tile_rows, wg_threads=s.wg_threads, flags=s.flags), \
             [rates[i] for i in range(n.value)]

@@ -113,8 +113,10 @@ class SurrogateMLP:
                                     _p(self.grad), _p(b["dx"]), _p(b["loss"]), _p(b["ws"]), s))
         return b["dx"], b["y"]
 
-    def fit(self, x, y, epochs=60, batch=1024, lr=1e-3, seed=0, log=None):
-        """Train on physical (x, y); labels are standardised per output."""
+    def fit(self, x, y, epochs=60, batch=1024, lr=1e-3, lr_min=None, seed=0, log=None):
+        """Train on physical (x, y); labels are standardised per output.  With
+        lr_min the learning rate follows a cosine from lr to lr_min over the
+        epochs."""
         x = torch.as_tensor(x, dtype=torch.float32, device=self.dev)
         y = torch.as_tensor(y, dtype=torch.float32, device=self.dev)
         self.y_mu = y.mean(dim=0)
@@ -125,11 +127,14 @@ class SurrogateMLP:
         g = torch.Generator(device="cpu").manual_seed(seed)
         n = x.shape[0]
         for ep in range(epochs):
+            lr_ep = lr
+            if lr_min is not None and epochs > 1:
+                lr_ep = lr_min + 0.5 * (lr - lr_min) * (1.0 + np.cos(np.pi * ep / (epochs - 1)))
             perm = torch.randperm(n, generator=g).to(self.dev)
             last = None
             for k in range(0, n - batch + 1, batch):
                 idx = perm[k:k + batch]
-                last = self.train_step(xn[idx].contiguous(), yn[idx].contiguous(), w, lr)
+                last = self.train_step(xn[idx].contiguous(), yn[idx].contiguous(), w, lr_ep)
             if log and (ep % 10 == 9 or ep == epochs - 1):
                 log(f"epoch {ep + 1}: batch loss {float(last.item()):.4g}")
         return self
@@ -165,66 +170,100 @@ def mc_observables(points, L=64, burn=300, measure=700, every=1, seed=5, rid0=0,
     return out, se
 
 
-def mc_absm_and_grad(beta, Jx, Jy, h, L=64, n_rep=16, burn=300, measure=700, seed=7, rid0=0):
-    """<|m|> over n_rep replicas and its gradient wrt (Jx, Jy) by the
-    covariance estimator; returns (absm, se, dJx, dJy)."""
-    reps = [dict(model=0, Lx=L, Ly=L, beta=float(beta), Jx=float(Jx), Jy=float(Jy), h=float(h),
-                 rid=rid0 + i) for i in range(n_rep)]
-    smp = Sampler(reps, seed, init=True)
-    smp.sweep(burn)
-    st = smp.sweep(measure, 1)
-    means, grads, _ = smp.grad(st, 0)
-    m = means[:, 1].cpu().numpy()
-    g = grads[:, 1, :2].cpu().numpy()
-    smp.close()
-    return float(m.mean()), float(m.std(ddof=1) / np.sqrt(n_rep)), float(g[:, 0].mean()), \
-        float(g[:, 1].mean())
+def mc_absm_and_grad(beta, Jx, Jy, h, L=64, n_rep=16, burn=300, measure=700, seed=7, rid0=0,
+                     se_abs=None, n_max=None):
+    """<|m|> over replicas and its gradient wrt (Jx, Jy) by the covariance
+    estimator; returns (absm, se, dJx, dJy, replicas used).  Replicas run in
+    batches of n_rep; with se_abs, batches are added (up to n_max replicas)
+    until the standard error of <|m|> is at most se_abs."""
+    n_max = n_max or n_rep
+    am, gx, gy = [], [], []
+    while True:
+        k = len(am)
+        reps = [dict(model=0, Lx=L, Ly=L, beta=float(beta), Jx=float(Jx), Jy=float(Jy),
+                     h=float(h), rid=rid0 + k + i) for i in range(n_rep)]
+        smp = Sampler(reps, seed, init=True)
+        smp.sweep(burn)
+        st = smp.sweep(measure, 1)
+        means, grads, _ = smp.grad(st, 0)
+        am += means[:, 1].cpu().tolist()
+        g = grads[:, 1, :2].cpu().numpy()
+        gx += g[:, 0].tolist()
+        gy += g[:, 1].tolist()
+        smp.close()
+        se = float(np.std(am, ddof=1) / np.sqrt(len(am)))
+        if se_abs is None or se <= se_abs or len(am) + n_rep > n_max:
+            break
+    return float(np.mean(am)), se, float(np.mean(gx)), float(np.mean(gy)), len(am)
 
 
 # --------------------------------------------------------- inverse problem
-def mc_only_solve(target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, max_iter=40, **mc):
+def mc_only_solve(target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, max_iter=40, se_rel=None,
+                  n_max=None, **mc):
     """Covariance-gradient (Newton along the gradient) steps on (Jx, Jy)
-    until the Monte Carlo <|m|> is within tol (relative) of the target."""
+    until the Monte Carlo <|m|> is within tol (relative) of the target.  With
+    se_rel, every evaluation adds replicas until its standard error is at
+    most se_rel * target (at most n_max), so that the tolerance is resolved."""
     Jx, Jy = start
     t0 = time.perf_counter()
     hist = []
+    se_abs = se_rel * target if se_rel else None
+    n_used = 0
     for it in range(max_iter):
-        m, se, gx, gy = mc_absm_and_grad(beta, Jx, Jy, h, rid0=1000 * it, **mc)
-        hist.append((Jx, Jy, m, se))
+        m, se, gx, gy, n = mc_absm_and_grad(beta, Jx, Jy, h, rid0=100_000 * it, se_abs=se_abs,
+                                            n_max=n_max, **mc)
+        n_used += n
+        hist.append((Jx, Jy, m, se, n))
         if abs(m - target) <= tol * target:
             return dict(Jx=Jx, Jy=Jy, absm=m, se=se, iters=it + 1, mc_calls=it + 1,
-                        seconds=time.perf_counter() - t0, converged=True, history=hist)
+                        replicas=n_used, seconds=time.perf_counter() - t0, converged=True,
+                        history=hist)
         g2 = gx * gx + gy * gy
         step = (target - m) / max(g2, 1e-12)
         step = float(np.clip(step, -0.5 / max(np.sqrt(g2), 1e-12), 0.5 / max(np.sqrt(g2), 1e-12)))
         Jx = float(np.clip(Jx + step * gx, 0.05, 3.0))
         Jy = float(np.clip(Jy + step * gy, 0.05, 3.0))
     return dict(Jx=Jx, Jy=Jy, absm=hist[-1][2], se=hist[-1][3], iters=max_iter, mc_calls=max_iter,
-                seconds=time.perf_counter() - t0, converged=False, history=hist)
+                replicas=n_used, seconds=time.perf_counter() - t0, converged=False, history=hist)
 
 
-def surrogate_solve(net, target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, steps=300, lr=0.05,
-                    max_iter=40, **mc):
-    """Gradient descent on the surrogate's inputs, one Monte Carlo check,
-    and Monte Carlo covariance-gradient steps if the check fails."""
+def surrogate_solve(net, target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, steps=100, lr=0.01,
+                    grid=64, max_iter=40, se_rel=None, n_max=None, **mc):
+    """The surrogate's answer, one Monte Carlo check, and Monte Carlo
+    covariance-gradient steps if the check fails.  The answer: the network
+    over a grid x grid set of couplings (one forward call) gives the points
+    of the target level set, the one nearest to the start is refined by
+    gradient descent on the network's inputs (input gradients from the
+    backward kernel)."""
     dev = net.dev
     t0 = time.perf_counter()
-    x = torch.tensor([[beta, start[0], start[1], h]], dtype=torch.float32, device=dev)
-    xn = net.normalise_x(x)
+    g = torch.linspace(-1.0, 1.0, grid, device=dev)
+    gx, gy = torch.meshgrid(g, g, indexing="ij")
+    x0 = net.normalise_x(torch.tensor([[beta, start[0], start[1], h]], dtype=torch.float32,
+                                      device=dev))
+    xg = x0.repeat(grid * grid, 1)
+    xg[:, 1] = gx.reshape(-1)
+    xg[:, 2] = gy.reshape(-1)
+    xg = xg.contiguous()
+    pred = (net.forward_normalised(xg) * net.y_sd + net.y_mu)[:, 1]
+    err = (pred - target).abs()
+    ok = err <= torch.clamp(err.min() * 1.5, min=0.002 * target)
+    dist = (xg[:, 1] - x0[0, 1]) ** 2 + (xg[:, 2] - x0[0, 2]) ** 2
+    dist = torch.where(ok, dist, torch.full_like(dist, float("inf")))
+    xn = xg[int(torch.argmin(dist))].reshape(1, 4).contiguous()
     tn = ((torch.tensor([[0.0, target, 0.0]], device=dev) - net.y_mu) / net.y_sd).to(
         torch.float32).contiguous()
     w = torch.tensor([0.0, 1.0, 0.0], dtype=torch.float32, device=dev)
-    scale = (2.0 / (net.x_hi - net.x_lo))  # d xn / d x
     for _ in range(steps):
         dx, _ = net.input_grad(xn, tn, w)
-        # move only the couplings (inputs 1, 2), in physical units
-        step = torch.zeros_like(xn)
-        step[:, 1:3] = dx[:, 1:3] * scale[1:3] * scale[1:3]
+        step = torch.zeros_like(xn)  # move only the couplings (inputs 1, 2)
+        step[:, 1:3] = dx[:, 1:3]
         xn = (xn - lr * step).clamp(-1.0, 1.0).contiguous()
     xp = (xn + 1.0) / 2.0 * (net.x_hi - net.x_lo) + net.x_lo
     Jx, Jy = float(xp[0, 1]), float(xp[0, 2])
     t_sur = time.perf_counter() - t0
-    res = mc_only_solve(target, beta, h, start=(Jx, Jy), tol=tol, max_iter=max_iter, **mc)
+    res = mc_only_solve(target, beta, h, start=(Jx, Jy), tol=tol, max_iter=max_iter, se_rel=se_rel,
+                        n_max=n_max, **mc)
     res["surrogate_seconds"] = t_sur
     res["surrogate_guess"] = (Jx, Jy)
     res["seconds"] += t_sur
@@ -233,12 +272,14 @@ def surrogate_solve(net, target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, st
 
 
 # ------------------------------------------------------------ experiment
-def experiment(n_points=100_000, L=64, burn=1000, measure=2000, epochs=60, targets=(0.2, 0.35, 0.5,
-               0.65, 0.8), beta=0.4, tol=0.01, n_rep=64, log=print, seed=1005):
+def experiment(n_points=100_000, L=64, burn=1000, measure=2000, epochs=200, lr=2e-3,
+               targets=(0.2, 0.35, 0.5, 0.65, 0.8), beta=0.4, tol=0.01, se_rel=0.0025,
+               n_rep=1024, n_max=65536, log=print, seed=1005):
     """The surrogate workload end to end: labels on the sampler, 90/10
     train/validation split, training, and for every target the wall time of
     the surrogate-steered solve against the Monte-Carlo-only solve (both
-    Monte-Carlo-verified to `tol`)."""
+    Monte-Carlo-verified to `tol`, each evaluation resolved to a standard
+    error of se_rel * target with up to n_max replicas)."""
     import synth
     pts = synth.surrogate_points(n_points, seed=seed)
     t0 = time.perf_counter()
@@ -249,7 +290,7 @@ def experiment(n_points=100_000, L=64, burn=1000, measure=2000, epochs=60, targe
     n_tr = int(0.9 * n_points)
     net = SurrogateMLP(seed=0)
     t0 = time.perf_counter()
-    net.fit(pts[:n_tr], y[:n_tr], epochs=epochs, log=log)
+    net.fit(pts[:n_tr], y[:n_tr], epochs=epochs, lr=lr, lr_min=lr / 100, log=log)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     pv = net.predict(torch.tensor(pts[n_tr:], device=net.dev)).cpu().numpy()
@@ -258,19 +299,19 @@ def experiment(n_points=100_000, L=64, burn=1000, measure=2000, epochs=60, targe
                mae_chi=float(err[:, 2].mean()), label_se_absm=float(np.median(se[n_tr:])))
     log(f"training {t_train:.1f} s; validation MAE {val}")
     runs = []
-    mc_kw = dict(n_rep=n_rep, L=L, burn=burn, measure=measure)
+    mc_kw = dict(n_rep=n_rep, L=L, burn=burn, measure=measure, se_rel=se_rel, n_max=n_max)
+    keys = ("Jx", "Jy", "absm", "se", "iters", "replicas", "seconds", "converged")
     for tg in targets:
         mc = mc_only_solve(tg, beta=beta, tol=tol, **mc_kw)
         su = surrogate_solve(net, tg, beta=beta, tol=tol, **mc_kw)
-        runs.append(dict(target=tg, mc_only=dict((k, mc[k]) for k in ("Jx", "Jy", "absm", "se",
-                                                                       "iters", "seconds",
-                                                                       "converged")),
-                         surrogate=dict((k, su[k]) for k in ("Jx", "Jy", "absm", "se", "iters",
-                                                             "seconds", "converged",
-                                                             "surrogate_guess",
-                                                             "fallback_iters"))))
-        log(f"target {tg}: MC-only {mc['seconds']:.2f} s ({mc['iters']} MC evals), surrogate "
-            f"{su['seconds']:.2f} s ({su['iters']} MC evals)")
+        runs.append(dict(target=tg, mc_only={k: mc[k] for k in keys},
+                         surrogate=dict({k: su[k] for k in keys},
+                                        surrogate_guess=su["surrogate_guess"],
+                                        fallback_iters=su["fallback_iters"])))
+        log(f"target {tg}: MC-only {mc['seconds']:.2f} s ({mc['iters']} MC evals, "
+            f"{mc['replicas']} replicas, |m| {mc['absm']:.4f} +- {mc['se']:.4f}); surrogate "
+            f"{su['seconds']:.2f} s ({su['iters']} MC evals, {su['replicas']} replicas, "
+            f"|m| {su['absm']:.4f} +- {su['se']:.4f})")
     tot_mc = sum(r["mc_only"]["seconds"] for r in runs)
     tot_su = sum(r["surrogate"]["seconds"] for r in runs)
     log(f"all targets: MC-only {tot_mc:.2f} s; surrogate {tot_su:.2f} s without and "
@@ -279,7 +320,7 @@ def experiment(n_points=100_000, L=64, burn=1000, measure=2000, epochs=60, targe
                 total_seconds=dict(mc_only=tot_mc, surrogate=tot_su,
                                    surrogate_with_labels_and_training=tot_su + t_label + t_train),
                 config=dict(n_points=n_points, L=L, burn=burn, measure=measure, epochs=epochs,
-                            beta=beta, tol=tol, n_rep=n_rep))
+                            lr=lr, beta=beta, tol=tol, se_rel=se_rel, n_rep=n_rep, n_max=n_max))
 
 
 if __name__ == "__main__":
@@ -289,12 +330,15 @@ if __name__ == "__main__":
     ap.add_argument("--points", type=int, default=100_000)
     ap.add_argument("--burn", type=int, default=1000)
     ap.add_argument("--measure", type=int, default=2000)
-    ap.add_argument("--epochs", type=int, default=60)
-    ap.add_argument("--n-rep", type=int, default=64)
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--n-rep", type=int, default=1024)
+    ap.add_argument("--n-max", type=int, default=65536)
+    ap.add_argument("--se-rel", type=float, default=0.0025)
     ap.add_argument("--out", default=None)
     a = ap.parse_args()
     res = experiment(n_points=a.points, burn=a.burn, measure=a.measure, epochs=a.epochs,
-                     n_rep=a.n_rep, log=lambda m: print(m, flush=True))
+                     n_rep=a.n_rep, n_max=a.n_max, se_rel=a.se_rel,
+                     log=lambda m: print(m, flush=True))
     txt = json.dumps(res)
     print(txt)
     if a.out:

@@ -299,3 +299,20 @@ def test_resident_packing_many_small_replicas(S, shape, n):
     for k, i in list(enumerate(potts))[:50] + list(enumerate(potts))[-50:]:
         assert np.array_equal(smp.get_state(i), out_p[k])
     smp.close()
+
+
+@pytest.mark.parametrize("nt", [True, False])
+def test_nontemporal_streaming_keeps_the_chain(S, nt):
+    """Streamed Ising and Potts passes with the own-plane loads and stores
+    nontemporal (forced on) or cached (forced off): the same chain as the
+    oracle, with and without recording, resumed across calls."""
+    rng = np.random.default_rng(77 + int(nt))
+    reps = [dict(model=0, Lx=64, Ly=48, q=2, Jx=_f32(0.9), Jy=_f32(1.1), h=_f32(0.02), beta=0.45,
+                 rid=3),
+            dict(model=1, Lx=96, Ly=32, q=5, Jx=1.0, Jy=1.0, h=0.0, beta=1.2, rid=9),
+            dict(model=1, Lx=32, Ly=64, q=3, Jx=_f32(0.7), Jy=_f32(0.7), h=_f32(0.05), beta=1.0,
+                 rid=11)]
+    _check_batch(S, reps, seed=int(rng.integers(1, 2 ** 62)), n=9, re=3,
+                 schedule=dict(mode="stream", tile_rows=8, nt=nt), split=[6, 3])
+    _check_batch(S, reps, seed=int(rng.integers(1, 2 ** 62)), n=7, re=0,
+                 schedule=dict(mode="stream", nt=nt), split=[5, 2])
