@@ -101,6 +101,173 @@ __global__ void __launch_bounds__(256) k_cpm_pass(CpmArgs a, int c, int sweep_of
     }
 }
 
+// The same pass with four consecutive same-colour sites of one row per lane
+// (Lx a multiple of 8): their attempts share one Philox call (words 0..3 of
+// counter k >> 2), their 3 x 9 id window comes in with six 16-byte loads and
+// three halo loads, and the per-cell tables (type, pass-start area minus
+// target) sit in LDS, so that a lane's attempts wait for one round of
+// global loads.
+__device__ __forceinline__ int sel8(const int (&v)[8], uint32_t j) {
+    const int a0 = (j & 1u) ? v[1] : v[0], a1 = (j & 1u) ? v[3] : v[2];
+    const int a2 = (j & 1u) ? v[5] : v[4], a3 = (j & 1u) ? v[7] : v[6];
+    const int b0 = (j & 2u) ? a1 : a0, b1 = (j & 2u) ? a3 : a2;
+    return (j & 4u) ? b1 : b0;
+}
+
+template <int CX>
+__device__ __forceinline__ void cpm_quads(const CpmArgs& a, const RepDev& R, const TileDev& T,
+                                          int cy, uint32_t p, const uint32_t* qthr,
+                                          const int32_t* lsa, const int8_t* lty,
+                                          const int32_t* ljs);
+
+__global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int sweep_off,
+                                                       int tab_lds_bytes, int cell_cap) {
+    // dynamic LDS: [T hi | T lo] (tab_lds_bytes) | snap - A (int32) | type (int8)
+    extern __shared__ __align__(16) uint8_t dyn[];
+    uint32_t* qthr = reinterpret_cast<uint32_t*>(dyn);
+    int32_t* lsa = reinterpret_cast<int32_t*>(dyn + tab_lds_bytes);
+    int8_t* lty = reinterpret_cast<int8_t*>(lsa + cell_cap);
+    __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
+    const TileDev T = a.tiles[blockIdx.x];
+    const RepDev R = a.reps[T.rep];
+    const int ncell = R.q + 1;
+    const int8_t* ty = a.ctype + R.cell_off;
+    const int32_t* A = a.target + R.cell_off;
+    const int32_t* snap = a.snap + R.cell_off;
+    // staging: each thread issues up to 4 items' loads before storing any,
+    // so that the tables arrive in one round of global loads
+    const int nthr = blockDim.x;
+    const int ntab = 2 * R.tab_n;
+    for (int i0 = threadIdx.x; i0 < ntab; i0 += 4 * nthr) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * nthr;
+            v[u] = i < ntab ? a.tab[R.tab_off + i] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i0 + u * nthr < ntab) qthr[i0 + u * nthr] = v[u];
+    }
+    for (int i = threadIdx.x; i < R.n_types * R.n_types; i += nthr) ljs[i] = a.js[R.js_off + i];
+    for (int i0 = threadIdx.x; i0 < ncell; i0 += 4 * nthr) {
+        int32_t sv[4], av[4];
+        int8_t tv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * nthr;
+            const bool in = i < ncell;
+            sv[u] = in ? snap[i] : 0;
+            av[u] = in ? A[i] : 0;
+            tv[u] = in ? ty[i] : (int8_t)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * nthr;
+            if (i < ncell) {
+                lsa[i] = sv[u] - av[u];
+                lty[i] = tv[u];
+            }
+        }
+    }
+    __syncthreads();
+    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
+    const uint32_t p = (uint32_t)(4 * t + (uint64_t)c);
+    if (c & 1)
+        cpm_quads<1>(a, R, T, c >> 1, p, qthr, lsa, lty, ljs);
+    else
+        cpm_quads<0>(a, R, T, c >> 1, p, qthr, lsa, lty, ljs);
+}
+
+template <int CX>
+__device__ __forceinline__ void cpm_quads(const CpmArgs& a, const RepDev& R, const TileDev& T,
+                                          int cy, uint32_t p, const uint32_t* qthr,
+                                          const int32_t* lsa, const int8_t* lty,
+                                          const int32_t* ljs) {
+    const int Lx = R.Lx, Ly = R.Ly, Wc = Lx >> 1, Q = Wc >> 2, nt = R.n_types;
+    int32_t* ids = a.lat + R.lat_off;
+    int32_t* area = a.area + R.cell_off;
+    const int total = (T.rows >> 1) * Q;
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        const int r = it / Q;
+        const int qi = it - r * Q;
+        const int y = T.y0 + 2 * r + cy;
+        const int x0 = 8 * qi;
+        const uint32_t kq = (uint32_t)((y >> 1) * Q + qi);  // k >> 2 of the four sites
+        const int yr[3] = {wrapc(y - 1, Ly), y, wrapc(y + 1, Ly)};
+        const int xh = CX == 0 ? wrapc(x0 - 1, Lx) : wrapc(x0 + 8, Lx);
+        int win[3][9];
+#pragma unroll
+        for (int rr = 0; rr < 3; ++rr) {
+            const int32_t* row = ids + (size_t)yr[rr] * Lx;
+            const int4 u = *reinterpret_cast<const int4*>(row + x0);
+            const int4 v = *reinterpret_cast<const int4*>(row + x0 + 4);
+            const int h = row[xh];
+            constexpr int o = CX == 0 ? 1 : 0;
+            win[rr][o + 0] = u.x;
+            win[rr][o + 1] = u.y;
+            win[rr][o + 2] = u.z;
+            win[rr][o + 3] = u.w;
+            win[rr][o + 4] = v.x;
+            win[rr][o + 5] = v.y;
+            win[rr][o + 6] = v.z;
+            win[rr][o + 7] = v.w;
+            win[rr][CX == 0 ? 0 : 8] = h;
+        }
+        uint32_t w[4];
+        philox4x32_10(kq, p, R.rid, kTagMain, a.key0, a.key1, w);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            // Moore order (dy, dx): (-1,-1) (-1,0) (-1,1) (0,-1) (0,1) (1,-1) (1,0) (1,1)
+            const int nb[8] = {win[0][2 * u], win[0][2 * u + 1], win[0][2 * u + 2],
+                               win[1][2 * u], win[1][2 * u + 2],
+                               win[2][2 * u], win[2][2 * u + 1], win[2][2 * u + 2]};
+            const int s = win[1][2 * u + 1];
+            const uint32_t word = w[u];
+            const int tg = sel8(nb, word & 7u);
+            if (tg == s) continue;
+            const int ts = lty[s] * nt, tt = lty[tg] * nt;
+            int kadh = 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int m = nb[j];
+                const int tm = lty[m];
+                kadh += (tg != m) ? ljs[tt + tm] : 0;
+                kadh -= (s != m) ? ljs[ts + tm] : 0;
+            }
+            int64_t karea = 0;
+            if (tg != 0) karea += 2 * (int64_t)lsa[tg] + 1;
+            if (s != 0) karea += -2 * (int64_t)lsa[s] + 1;
+            const int64_t kk = (int64_t)kadh + R.LS * karea;
+            bool acc;
+            if (kk <= 0) {
+                acc = true;
+            } else if (kk >= R.K0) {
+                acc = false;
+            } else {
+                uint32_t hi = 0u, lo = 1u;  // T = 1 for K1 <= k < K0
+                if (kk < (int64_t)R.K1) {
+                    hi = qthr[kk - 1];
+                    lo = qthr[R.tab_n + kk - 1];
+                }
+                const uint32_t rr = word >> 16;
+                acc = rr < hi;
+                if (rr == hi && lo != 0u) {
+                    uint32_t f[4];
+                    philox4x32_10(4u * kq + (uint32_t)u, p, R.rid, kTagFallback, a.key0, a.key1,
+                                  f);
+                    acc = (f[0] & 0xFFFFu) < lo;
+                }
+            }
+            if (acc) {
+                ids[(size_t)y * Lx + x0 + 2 * u + CX] = tg;
+                atomicAdd(&area[tg], 1);
+                atomicAdd(&area[s], -1);
+            }
+        }
+    }
+}
+
 __global__ void k_cpm_copy(const int32_t* src, int32_t* dst, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         dst[i] = src[i];
@@ -194,6 +361,19 @@ hipError_t launch_cpm_pass(const CpmArgs& a, int n_tiles, int c, int sweep_off, 
     hipLaunchKernelGGL(k_cpm_pass, dim3(n_tiles), dim3(threads), lds_tab_bytes, s, a, c,
                        sweep_off);
     return hipGetLastError();
+}
+
+hipError_t launch_cpm_pass_quad(const CpmArgs& a, int n_tiles, int c, int sweep_off,
+                                int threads, int tab_lds_bytes, int cell_cap, hipStream_t s) {
+    const size_t lds = (size_t)tab_lds_bytes + (size_t)cell_cap * 5;
+    hipLaunchKernelGGL(k_cpm_pass_quad, dim3(n_tiles), dim3(threads), lds, s, a, c, sweep_off,
+                       tab_lds_bytes, cell_cap);
+    return hipGetLastError();
+}
+
+hipError_t cpm_reserve_lds(size_t lds_bytes) {
+    return hipFuncSetAttribute((const void*)k_cpm_pass_quad,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
 }
 
 hipError_t launch_cpm_snapshot(const CpmArgs& a, int total_cells, hipStream_t s) {

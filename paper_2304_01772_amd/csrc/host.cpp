@@ -41,6 +41,7 @@ constexpr size_t kResidentLdsBudget = 150 * 1024;
 // Streamed lattice sets beyond this size do not stay in the 256 MB last-level
 // cache between passes: their own-plane traffic goes nontemporal by default.
 constexpr size_t kNtAutoBytes = 192ull << 20;
+constexpr int kCpmLdsCells = 16384;  // cells (medium included) per replica in LDS tables
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -148,6 +149,10 @@ struct spinmc_ctx {
     int32_t* d_snap = nullptr;
     int32_t* d_js = nullptr;
     int total_cells = 0;
+    // CPM passes with four sites per lane and LDS cell tables (every Lx a
+    // multiple of 8, at most kCpmLdsCells cells per replica)
+    bool cpm_quad = false, cpm_lds_reserved = false;
+    int cpm_cell_cap = 0;
     // kernel timing
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -1152,10 +1157,20 @@ int enqueue_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
         // first (resident replicas overwrite theirs)
         e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
     }
-    // resident groups on side streams, concurrent with the streamed passes
-    if (e == hipSuccess) e = enqueue_resident(c, a, c->stream);
-    if (e == hipSuccess && c->n_tiles > 0) e = enqueue_stream(c, a, 0, n, re, c->stream);
-    if (e == hipSuccess) e = join_resident(c, c->stream);
+    // resident groups on side streams, concurrent with the streamed passes;
+    // when both exist, in chunks of the graph's length so that direct
+    // launches overlap the way graph replays do
+    const bool mixed = c->n_tiles > 0 && !c->res_groups.empty();
+    const int G = mixed ? kGraphChunk : std::max(n, 1);
+    for (int j0 = 0; j0 < n && e == hipSuccess; j0 += G) {
+        const int m = std::min(G, n - j0);
+        SweepArgs aj = a;
+        aj.n_sweeps = m;
+        aj.sweep_off = j0;
+        e = enqueue_resident(c, aj, c->stream);
+        if (e == hipSuccess && c->n_tiles > 0) e = enqueue_stream(c, a, j0, m, re, c->stream);
+        if (e == hipSuccess) e = join_resident(c, c->stream);
+    }
     if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)n, c->stream);
     return check_dev(c, e, "sweep");
 }
@@ -1274,6 +1289,16 @@ int create_cpm(const spinmc_replica_desc* d, int n, uint64_t seed, void* stream,
     }
     c->total_cells = (int)cell_off;
     c->lat_bytes = lat_off + 64;
+    {
+        int cap = 0;
+        bool quad = true;
+        for (int i = 0; i < n; ++i) {
+            cap = std::max(cap, c->reps[i].dev.q + 1);
+            quad = quad && (c->reps[i].dev.Lx % 8 == 0);
+        }
+        c->cpm_cell_cap = (int)align_up((size_t)cap, 16);
+        c->cpm_quad = quad && c->cpm_cell_cap <= kCpmLdsCells;
+    }
     std::vector<RepDev> rd(n);
     for (int i = 0; i < n; ++i) rd[i] = c->reps[i].dev;
     if (tab.empty()) tab.push_back(0);
@@ -1362,6 +1387,11 @@ int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
     CpmArgs a = cpm_args(c, stats);
     const size_t tab_bytes = align_up((size_t)8 * std::max(c->max_tab_n, 1), 16);
     const int threads = c->sched.wg_threads > 0 ? std::min(c->sched.wg_threads, 256) : 256;
+    if (c->cpm_quad && !c->cpm_lds_reserved) {
+        hipError_t er = cpm_reserve_lds(tab_bytes + (size_t)c->cpm_cell_cap * 5);
+        if (er != hipSuccess) return check_dev(c, er, "CPM LDS reservation");
+        c->cpm_lds_reserved = true;
+    }
     hipError_t e = hipSuccess;
     const int n_rec = re > 0 ? n / re : 0;
     if (n_rec > 0) e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
@@ -1370,6 +1400,9 @@ int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
             e = launch_cpm_snapshot(a, c->total_cells, c->stream);
             if (e == hipSuccess)
                 e = timed(c, SPINMC_K_CPM_PASS, [&] {
+                    if (c->cpm_quad)
+                        return launch_cpm_pass_quad(a, c->n_tiles, col, i, threads,
+                                                    (int)tab_bytes, c->cpm_cell_cap, c->stream);
                     return launch_cpm_pass(a, c->n_tiles, col, i, threads, tab_bytes, c->stream);
                 }, c->stream);
         }

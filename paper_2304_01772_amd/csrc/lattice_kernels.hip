@@ -767,7 +767,8 @@ __device__ __forceinline__ void resident_body(const SweepArgs& a) {
     __syncthreads();
     const uint64_t t0 = *a.t_base;
     for (int i = 0; i < a.n_sweeps; ++i) {
-        const uint64_t t = t0 + (uint64_t)i;
+        const int sw = a.sweep_off + i;  // sweep index within the call
+        const uint64_t t = t0 + (uint64_t)sw;
         for (int c = 0; c < 2; ++c) {
             const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
             if (active) {
@@ -787,7 +788,7 @@ __device__ __forceinline__ void resident_body(const SweepArgs& a) {
             }
             __syncthreads();
         }
-        if (a.record_every > 0 && ((i + 1) % a.record_every) == 0) {
+        if (a.record_every > 0 && ((sw + 1) % a.record_every) == 0) {
             // statistics of each replica of the workgroup, all threads per replica
             for (int gg = 0; gg < P && first + gg < a.n_list; ++gg) {
                 const int rg = a.rep_list[first + gg];
@@ -801,7 +802,7 @@ __device__ __forceinline__ void resident_body(const SweepArgs& a) {
                 lattice_stats(Q.model, lq, Q.Lx, Q.Ly, Q.W, 0, Q.Lx * Q.Ly, v, lhist);
                 block_sum<3>(v, lred);
                 int32_t* row =
-                    a.stats + ((size_t)((i + 1) / a.record_every - 1) * a.R + rg) * a.width;
+                    a.stats + ((size_t)((sw + 1) / a.record_every - 1) * a.R + rg) * a.width;
                 if (threadIdx.x == 0) {
                     row[0] = v[0];
                     row[1] = v[1];

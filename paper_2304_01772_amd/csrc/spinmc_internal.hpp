@@ -92,6 +92,7 @@ struct SweepArgs {
     uint32_t key0, key1;
     int32_t R, width;
     int32_t n_sweeps, record_every;
+    int32_t sweep_off;            // resident kernels: first sweep of the launch within the call
     int32_t n_units;
     int32_t tab_lds_bytes;        // bytes of LDS reserved for thresholds (multiple of 16)
     // resident kernels: replicas per workgroup, LDS bytes per replica slot,
@@ -143,6 +144,13 @@ struct CpmArgs {
 };
 hipError_t launch_cpm_pass(const CpmArgs& a, int n_tiles, int c, int sweep_off, int threads,
                            size_t lds_tab_bytes, hipStream_t s);
+// Four same-colour sites per lane with the cell tables in LDS: needs every
+// Lx a multiple of 8 and cell_cap >= n_cells + 1 (a multiple of 16) for
+// every replica; dynamic LDS tab_lds_bytes + 5 cell_cap.
+hipError_t launch_cpm_pass_quad(const CpmArgs& a, int n_tiles, int c, int sweep_off,
+                                int threads, int tab_lds_bytes, int cell_cap, hipStream_t s);
+// Allow k_cpm_pass_quad up to lds_bytes of dynamic LDS (call outside capture).
+hipError_t cpm_reserve_lds(size_t lds_bytes);
 hipError_t launch_cpm_snapshot(const CpmArgs& a, int total_cells, hipStream_t s);
 hipError_t launch_cpm_stats(const CpmArgs& a, int n_tiles, int rec_row, hipStream_t s);
 hipError_t launch_cpm_area_recount(const CpmArgs& a, int n_tiles, int total_cells, hipStream_t s);

@@ -46,6 +46,8 @@ JS = {
     ((24, 32), 12, "sorting", 2.0, 25.0, 4),
     ((2, 4), 2, "halves", 0.0, 1.0, 0),
     ((64, 64), 30, "sorting", 1.0, 10.0, 6),
+    # more cells than the LDS cell tables hold: the per-site kernel
+    ((128, 128), 17000, "sorting", 1.0, 10.0, 0),
 ])
 def test_cpm_matches_oracle(S, shape, n_cells, Jname, lam, T, tile_rows):
     J = JS[Jname]
