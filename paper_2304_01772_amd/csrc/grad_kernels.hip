@@ -33,23 +33,38 @@ __global__ void __launch_bounds__(256) k_cov_grad(const RepDev* reps, int R,
     long long s[kSums];
 #pragma unroll
     for (int i = 0; i < kSums; ++i) s[i] = 0;
-    for (int k = burn_in + (int)threadIdx.x; k < n_rec; k += blockDim.x) {
-        const int32_t* row = stats + ((size_t)k * R + r) * width;
-        const long long M = row[0], Bx = row[1], By = row[2];
-        const long long aM = M < 0 ? -M : M;
-        s[0] += Bx;
-        s[1] += By;
-        s[2] += M;
-        s[3] += aM;
-        s[4] += Bx * Bx;
-        s[5] += By * By;
-        s[6] += M * M;
-        s[7] += Bx * By;
-        s[8] += Bx * M;
-        s[9] += By * M;
-        s[10] += aM * Bx;
-        s[11] += aM * By;
-        s[12] += aM * M;
+    // eight samples' loads in flight per lane before their products
+    constexpr int kU = 8;
+    const int step = (int)blockDim.x;
+    for (int k0 = burn_in + (int)threadIdx.x; k0 < n_rec; k0 += kU * step) {
+        int3 v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int k = k0 + u * step;
+            v[u] = make_int3(0, 0, 0);
+            if (k < n_rec) {
+                const int32_t* row = stats + ((size_t)k * R + r) * width;
+                v[u] = make_int3(row[0], row[1], row[2]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const long long M = v[u].x, Bx = v[u].y, By = v[u].z;  // zero rows add nothing
+            const long long aM = M < 0 ? -M : M;
+            s[0] += Bx;
+            s[1] += By;
+            s[2] += M;
+            s[3] += aM;
+            s[4] += Bx * Bx;
+            s[5] += By * By;
+            s[6] += M * M;
+            s[7] += Bx * By;
+            s[8] += Bx * M;
+            s[9] += By * M;
+            s[10] += aM * Bx;
+            s[11] += aM * By;
+            s[12] += aM * M;
+        }
     }
 #pragma unroll
     for (int i = 0; i < kSums; ++i) red[i][threadIdx.x] = s[i];

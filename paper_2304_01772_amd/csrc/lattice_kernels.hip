@@ -741,6 +741,7 @@ __device__ __forceinline__ void resident_body(const SweepArgs& a) {
     __shared__ uint32_t lthr9[kMaxRpb][18];
     __shared__ int lhist[kMaxPottsQ];
     __shared__ int lred[64];
+    __shared__ int lsum[kMaxRpb][3];  // Ising: per-slot (M, Bx, By) of a recorded sweep
     const int P = a.rpb;
     const int nt = blockDim.x / P;
     const int g = threadIdx.x / nt, lt = threadIdx.x - g * nt;
@@ -769,13 +770,28 @@ __device__ __forceinline__ void resident_body(const SweepArgs& a) {
     for (int i = 0; i < a.n_sweeps; ++i) {
         const int sw = a.sweep_off + i;  // sweep index within the call
         const uint64_t t = t0 + (uint64_t)sw;
+        const bool rec = a.record_every > 0 && ((sw + 1) % a.record_every) == 0;
         for (int c = 0; c < 2; ++c) {
             const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
+            if (KIND == kResIsing && rec && c == 1) {
+                if (threadIdx.x < 3 * kMaxRpb) (&lsum[0][0])[threadIdx.x] = 0;
+                __syncthreads();
+            }
             if (active) {
                 if (KIND == kResIsing) {
                     IsingAcc ia{0, 0, 0};
-                    run_tile_ising<false, false, false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid, a.key0, a.key1,
-                                          lthr, ia, lt, nt);
+                    if (rec && c == 1) {
+                        // statistics fused into the colour-1 pass: every bond has
+                        // exactly one colour-1 end
+                        run_tile_ising<true, false, false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid,
+                                                           a.key0, a.key1, lthr, ia, lt, nt);
+                        atomicAdd(&lsum[g][0], ia.M);
+                        atomicAdd(&lsum[g][1], ia.Bx);
+                        atomicAdd(&lsum[g][2], ia.By);
+                    } else {
+                        run_tile_ising<false, false, false>(lds, R.W, R.Ly, 0, R.Ly, c, p, R.rid,
+                                                            a.key0, a.key1, lthr, ia, lt, nt);
+                    }
                 } else if (KIND == kResPotts) {
                     PottsAcc pa{0, 0, 0};
                     potts_tile<false, false>(R, lds, 0, R.Ly, c, p, a.key0, a.key1, lthr, lthr9[g], pa,
@@ -788,7 +804,16 @@ __device__ __forceinline__ void resident_body(const SweepArgs& a) {
             }
             __syncthreads();
         }
-        if (a.record_every > 0 && ((sw + 1) % a.record_every) == 0) {
+        if (KIND == kResIsing && rec) {
+            if (active && lt == 0) {
+                int32_t* row =
+                    a.stats + ((size_t)((sw + 1) / a.record_every - 1) * a.R + rep) * a.width;
+                row[0] = lsum[g][0];
+                row[1] = lsum[g][1];
+                row[2] = lsum[g][2];
+                for (int k = 3; k < a.width; ++k) row[k] = 0;
+            }
+        } else if (rec) {
             // statistics of each replica of the workgroup, all threads per replica
             for (int gg = 0; gg < P && first + gg < a.n_list; ++gg) {
                 const int rg = a.rep_list[first + gg];

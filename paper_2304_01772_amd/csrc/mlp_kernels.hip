@@ -283,21 +283,33 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(const float* P, const float* x,
     }
     red[threadIdx.x] = lossp;
     __syncthreads();
-    // dH2 = W3b^T dY, dz2 = dH2 silu'(z2)
-    for (int i = threadIdx.x; i < kSamplesPerWG * kH; i += blockDim.x) {
-        const int s = i >> 7, n = i & 127;
-        const int gs = base + s;
-        float d = 0.f;
-        if (gs < B) {
-            float dh = 0.f;
+    // dH2 = W3b^T dY, dz2 = dH2 silu'(z2); eight pre-activations per lane
+    // loaded before their use
+    static_assert((kSamplesPerWG * kH) % (8 * 256) == 0, "dz2 batches assume 256 threads");
+    for (int i0 = threadIdx.x; i0 < kSamplesPerWG * kH; i0 += 8 * 256) {
+        float z2v[8];
 #pragma unroll
-            for (int j = 0; j < kOut; ++j) dh += dY[s][j] * bf2f(w3[j * kS2 + n]);
-            d = dh * dsilu(act[(size_t)gs * 2 * kH + kH + n]);
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 256 * u;
+            const int gs = base + (i >> 7);
+            z2v[u] = gs < B ? act[(size_t)gs * 2 * kH + kH + (i & 127)] : 0.f;
         }
-        const uint16_t db = f2bf(d);
-        dz2t[n * kST + s] = db;
-        dz2[s * kS2 + n] = db;
-        dz1[s * kSZ + n] = d;  // unrounded dz2, for db2 (dz1 is computed later)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = i0 + 256 * u;
+            const int s = i >> 7, n = i & 127;
+            float d = 0.f;
+            if (base + s < B) {
+                float dh = 0.f;
+#pragma unroll
+                for (int j = 0; j < kOut; ++j) dh += dY[s][j] * bf2f(w3[j * kS2 + n]);
+                d = dh * dsilu(z2v[u]);
+            }
+            const uint16_t db = f2bf(d);
+            dz2t[n * kST + s] = db;
+            dz2[s * kS2 + n] = db;
+            dz1[s * kSZ + n] = d;  // unrounded dz2, for db2 (dz1 is computed later)
+        }
     }
     __syncthreads();
     float* pg = part + (size_t)blockIdx.x * (kNP + 1);

@@ -316,3 +316,72 @@ def test_nontemporal_streaming_keeps_the_chain(S, nt):
                  schedule=dict(mode="stream", tile_rows=8, nt=nt), split=[6, 3])
     _check_batch(S, reps, seed=int(rng.integers(1, 2 ** 62)), n=7, re=0,
                  schedule=dict(mode="stream", nt=nt), split=[5, 2])
+
+
+def test_zero_sweeps_and_schedule_boundaries(S):
+    """Degenerate calls and the LDS-residency boundary: zero sweeps change
+    nothing; a lattice of exactly 128 KiB stays resident and one two rows
+    larger is streamed under the hybrid schedule, both on the oracle's chain;
+    q above 128 is rejected."""
+    from paper_2304_01772_amd import SpinmcError
+    reps = [dict(model=0, Lx=512, Ly=256, q=2, Jx=1.0, Jy=1.0, h=0.0, beta=0.42, rid=5),
+            dict(model=0, Lx=512, Ly=258, q=2, Jx=1.0, Jy=1.0, h=0.0, beta=0.42, rid=6),
+            dict(model=1, Lx=256, Ly=512, q=4, Jx=1.0, Jy=1.0, h=0.0, beta=1.1, rid=7)]
+    smp = S(reps, 99, init=True)
+    smp.set_schedule(mode="hybrid")
+    streamed, resident = smp.schedule_sites(by_model=True)
+    assert resident["ising"] == 512 * 256 and streamed["ising"] == 512 * 258
+    assert resident["potts"] == 256 * 512 and streamed["potts"] == 0
+    before = [smp.get_state(i) for i in range(3)]
+    smp.sweep(0)
+    st = smp.sweep(0, 1)
+    torch.cuda.synchronize()
+    assert smp.t == 0 and st.shape[0] == 0
+    for i in range(3):
+        assert np.array_equal(smp.get_state(i), before[i])
+    smp.close()
+    _check_batch(S, reps, seed=99, n=4, re=2, schedule=dict(mode="hybrid"), split=[3, 1])
+    with pytest.raises(SpinmcError):
+        S([dict(model=1, Lx=32, Ly=32, q=129)], 1)
+
+
+def test_batched_workload_full_size_sampled(S):
+    """The benchmark's batched workload at full size (1024 Ising 256^2 + 512
+    Potts up to 1024^2) under its tuned schedule, sweeps replayed as graphs
+    and recorded: sampled replicas, among them the largest Potts lattices,
+    bit-exact with the oracle; every replica's recorded statistics equal a
+    recount of its final state."""
+    reps = synth.batched_ising_potts()
+    seed, n = 2, 7
+    smp = S(reps, seed, init=True)
+    smp.autotune(trial_sweeps=2)
+    smp.sweep(5)                 # graph replays (5-sweep chunk)
+    st = smp.sweep(2, 2)         # one recorded sweep pair, direct launches
+    torch.cuda.synchronize()
+    big = [i for i, r in enumerate(reps) if r["model"] == 1 and r["Lx"] == 1024][:2]
+    sample = [0, 517, 1023, 1024, 1535] + big
+    for i in sample:
+        r = reps[i]
+        want, _ = _run_oracle(r, _init_oracle(r, seed), seed, 0, n, 0)
+        assert np.array_equal(smp.get_state(i), want), f"replica {i} {r}"
+    stats, _ = smp.measure()
+    torch.cuda.synchronize()
+    assert np.array_equal(st[0].cpu().numpy()[:, :3], stats.cpu().numpy()[:, :3])
+    smp.close()
+
+
+def test_ising_stream_8192_nontemporal_full_size_sampled(S):
+    """The HBM-bound probe configuration (8192 Ising replicas of 256^2, 512
+    MiB of lattices, streamed with nontemporal own-plane access, 128-row
+    tiles): sampled replicas bit-exact with the oracle."""
+    reps = synth.batched_ising_potts(n_ising=8192, n_potts=0)
+    seed, n = 2, 3
+    smp = S(reps, seed, init=True)
+    smp.set_schedule(mode="stream", tile_rows=128, wg_threads=256, nt=True)
+    smp.sweep(n)
+    torch.cuda.synchronize()
+    for i in (0, 1, 4095, 4096, 8191):
+        r = reps[i]
+        want, _ = _run_oracle(r, _init_oracle(r, seed), seed, 0, n, 0)
+        assert np.array_equal(smp.get_state(i), want), f"replica {i}"
+    smp.close()
