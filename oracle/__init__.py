@@ -15,6 +15,9 @@ Contents
 * ``gradients``   fluctuation (covariance) estimator of d<O>/d(theta).
 * ``mlp``         FP64 reference of the 4-128-128-3 surrogate with the BF16
                   rounding points of the HIP kernels, its backward and Adam.
+* ``dmc``         FP64 relaxed chain of the differentiable Monte Carlo
+                  (Algorithm 2) with per-bond couplings, and its reverse-mode
+                  gradients.
 
 Parity status of every function is listed in its module docstring.
 """

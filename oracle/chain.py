@@ -80,6 +80,9 @@ def lib():
                                       C.c_uint64, _u32p, C.c_uint64, C.c_int, C.c_int, _u8p,
                                       _i64p, C.c_void_p]
     L.orc_potts_run_batch.restype = C.c_int
+    L.orc_philox_grid.argtypes = [C.c_int, C.c_uint32, _u32p, C.c_int, C.c_uint32, C.c_uint32,
+                                  C.c_uint32, _u32p]
+    L.orc_philox_grid.restype = None
     L.orc_num_threads.argtypes = []
     L.orc_num_threads.restype = C.c_int
     _LIB = L
@@ -99,6 +102,16 @@ def philox4x32_10(ctr, key):
     k = np.ascontiguousarray(key, dtype=np.uint32)
     out = np.zeros(4, np.uint32)
     lib().orc_philox4x32_10(c, k, out)
+    return out
+
+
+def philox_grid(n_blocks, c1, rids, c3, seed):
+    """Philox4x32-10 words for counters (b, c1, rid, c3), b < n_blocks, one
+    row per replica id: uint32 array [len(rids), n_blocks, 4]."""
+    rids = np.ascontiguousarray(rids, dtype=np.uint32)
+    out = np.zeros((len(rids), n_blocks, 4), np.uint32)
+    lib().orc_philox_grid(int(n_blocks), int(c1) & 0xFFFFFFFF, rids, len(rids), int(c3),
+                          int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF, out)
     return out
 
 

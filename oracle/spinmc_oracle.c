@@ -560,6 +560,20 @@ int orc_potts_run_batch(int R, const int32_t *Lx, const int32_t *Ly, const int32
     return bad ? ORC_EINVAL : n_rec;
 }
 
+/* Philox outputs on a grid of counters: out[r][b][0..3] = Philox4x32-10 of
+ * counter (b, c1, rids[r], c3) under key (k0, k1), b = 0..n_blocks-1.       */
+void orc_philox_grid(int n_blocks, uint32_t c1, const uint32_t *rids, int n_rid, uint32_t c3,
+                     uint32_t k0, uint32_t k1, uint32_t *out)
+{
+    int r, b;
+    const uint32_t key[2] = {k0, k1};
+    for (r = 0; r < n_rid; r++)
+        for (b = 0; b < n_blocks; b++) {
+            const uint32_t ctr[4] = {(uint32_t)b, c1, rids[r], c3};
+            orc_philox4x32_10(ctr, key, out + ((size_t)r * n_blocks + b) * 4);
+        }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
