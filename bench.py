@@ -264,6 +264,39 @@ def mlp_probe(torch, steps=200, batch=1024, infer_batch=100_000):
             "bound": "mfma", "peak_TFLOPs": 2500.0}
 
 
+def dmc_probe(torch, R=256, L=128, sweeps=10):
+    """Differentiable Monte Carlo (relaxed chain of Algorithm 2): R replicas
+    of L x L with per-bond couplings, `sweeps` sweeps forward and the reverse
+    replay, timed with HIP events; algorithmic HBM bytes of a forward pass
+    are 32 per attempt (spins of both colours 8, the four bond couplings 16,
+    the updated spin 4 and its saved value 4)."""
+    from paper_2304_01772_amd.dmc import relaxed_ising
+    g = torch.Generator(device="cpu").manual_seed(0)
+    s0 = (torch.rand((R, L, L), generator=g) * 2 - 1).cuda()
+    jx = (torch.rand((R, L, L), generator=g) * 0.8 + 0.1).cuda().requires_grad_(True)
+    jy = (torch.rand((R, L, L), generator=g) * 0.8 + 0.1).cuda().requires_grad_(True)
+    out = relaxed_ising(s0, jx, jy, 0.5, 10.0, 0.0, 1, 1)
+    out.sum().backward()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = _events(torch, st)
+    out = relaxed_ising(s0, jx, jy, 0.5, 10.0, 0.0, sweeps, 1)
+    e1.record(st)
+    e2, e3 = _events(torch, st)
+    out.sum().backward()
+    e3.record(st)
+    torch.cuda.synchronize()
+    att = R * L * L * sweeps
+    fwd_ms, bwd_ms = e0.elapsed_time(e1), e2.elapsed_time(e3)
+    return {"config": f"{R} Ising replicas of {L}x{L}, per-bond couplings, {sweeps} sweeps, "
+                      "alpha 10, beta 0.5",
+            "kernel": "k_dmc_pass / k_dmc_back + k_dmc_gather", "bound": "hbm",
+            "forward_attempts_per_ns": round(att / (fwd_ms * 1e6), 1),
+            "backward_attempts_per_ns": round(att / (bwd_ms * 1e6), 1),
+            "forward_GBs_algorithmic": round(32 * att / (fwd_ms * 1e-3) / 1e9, 1),
+            "forward_frac": round(32 * att / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(reps, seed, sweeps):
     """The oracle on the host cores: every replica of the workload, a few
     sweeps (a bounded sample of the same chain)."""
@@ -394,7 +427,8 @@ def main():
     ap.add_argument("--no-probes", action="store_true",
                     help="skip the Ising streaming probes (for counter collection runs)")
     ap.add_argument("--no-paths", action="store_true",
-                    help="skip the CPM, covariance-backward and MLP measurements")
+                    help="skip the CPM, covariance-backward, MLP and differentiable-MC "
+                         "measurements")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (the reference "
                          "dispatch that scales rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -497,6 +531,8 @@ def main():
         print(f"# grad: {paths['covariance_backward']}", file=sys.stderr, flush=True)
         paths["surrogate_mlp"] = mlp_probe(torch)
         print(f"# mlp: {paths['surrogate_mlp']}", file=sys.stderr, flush=True)
+        paths["differentiable_mc"] = dmc_probe(torch)
+        print(f"# dmc: {paths['differentiable_mc']}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:

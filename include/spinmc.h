@@ -267,6 +267,53 @@ int spinmc_mlp_adam(void *dev_params, const void *dev_grad, void *dev_m, void *d
                     int32_t step, float lr, float beta1, float beta2, float eps,
                     void *hip_stream);
 
+/* One Adam step on n FP32 parameters (any buffer): m, v the moment buffers
+ * of the same size, step >= 1 the 1-based step number.  Used by the
+ * optimisation experiments (Results: Adam, learning rate 1e-3).            */
+int spinmc_adam(void *dev_params, const void *dev_grad, void *dev_m, void *dev_v, int64_t n,
+                int32_t step, float lr, float beta1, float beta2, float eps, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Differentiable Monte Carlo (Methods, Algorithm 2) for the Ising model:
+ * the relaxed checkerboard chain on continuous spins s in [-1, 1] with one
+ * coupling per bond, and its reverse-mode gradient.  Per colour pass
+ * (colour c = (x+y) & 1 first c = 0, pass p = 2t + c), every site of colour c:
+ *   hloc = Jx[y][x] s(y,x+1) + Jx[y][x-1] s(y,x-1) + Jy[y][x] s(y+1,x)
+ *          + Jy[y-1][x] s(y-1,x) + h                     (periodic),
+ *   P = exp(-beta * 2 s hloc)   (energy change of the flip proposal),
+ *   q = 1 / (1 + exp(-alpha (P - r))),   s <- q (-s) + (1 - q) s,
+ * r = (w >> 8) 2^-24 with w word k & 3 of Philox4x32-10 counter
+ * (k >> 2, p, rid0 + replica, 3), key (seed lo, seed hi), k = y Lx/2 + x>>1.
+ * alpha -> infinity recovers the Metropolis chain.  FP32 arithmetic.
+ * Buffers (caller-owned device memory, row-major [R][Ly][Lx] FP32): spins,
+ * Jx (bond (y,x)-(y,x+1)), Jy (bond (y,x)-(y+1,x)).  Invalid arguments
+ * return SPINMC_E_INVALID before anything is enqueued.                      */
+typedef struct spinmc_dmc_params {
+    int32_t R, Lx, Ly, n_sweeps;   /* replicas, even Lx and Ly >= 2, sweeps >= 0 */
+    float beta, alpha, h, reserved; /* alpha >= 0                                 */
+    uint64_t seed, t0;              /* Philox key, first sweep counter            */
+    uint32_t rid0, reserved2;       /* replica ids rid0 .. rid0 + R - 1           */
+} spinmc_dmc_params;
+
+/* Sizes (floats) of the forward's save buffer (pre-pass spins of the
+ * updated colour, 2 n_sweeps R Ly Lx/2) and of the backward's work buffer
+ * (R Ly Lx/2); negative on invalid parameters.                              */
+int64_t spinmc_dmc_save_floats(const spinmc_dmc_params *p);
+int64_t spinmc_dmc_work_floats(const spinmc_dmc_params *p);
+
+/* n_sweeps relaxed sweeps of dev_s in place; dev_save receives what the
+ * backward replay needs.                                                    */
+int spinmc_dmc_forward(const spinmc_dmc_params *p, void *dev_s, const void *dev_Jx,
+                       const void *dev_Jy, void *dev_save, void *hip_stream);
+
+/* Reverse replay of the forward call with the same parameters: on entry
+ * dev_s holds the final spins and dev_gs = dL/ds_final; on exit dev_s holds
+ * the initial spins and dev_gs = dL/ds_initial; dL/dJx and dL/dJy are added
+ * to dev_gJx, dev_gJy.                                                      */
+int spinmc_dmc_backward(const spinmc_dmc_params *p, void *dev_s, const void *dev_Jx,
+                        const void *dev_Jy, const void *dev_save, void *dev_gs, void *dev_gJx,
+                        void *dev_gJy, void *dev_work, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -35,6 +35,13 @@ class Schedule(C.Structure):
                 ("flags", C.c_int32)]
 
 
+class DmcParams(C.Structure):
+    _fields_ = [("R", C.c_int32), ("Lx", C.c_int32), ("Ly", C.c_int32), ("n_sweeps", C.c_int32),
+                ("beta", C.c_float), ("alpha", C.c_float), ("h", C.c_float),
+                ("reserved", C.c_float), ("seed", C.c_uint64), ("t0", C.c_uint64),
+                ("rid0", C.c_uint32), ("reserved2", C.c_uint32)]
+
+
 # name -> (restype, argtypes); the exported C ABI of include/spinmc.h
 SIGNATURES = {
     "spinmc_create": (C.c_int, [C.POINTER(ReplicaDesc), C.c_int32, C.c_uint64, C.c_int32,
@@ -70,6 +77,16 @@ SIGNATURES = {
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
     "spinmc_mlp_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                   C.c_float, C.c_float, C.c_float, C.c_float, C.c_void_p]),
+    "spinmc_adam": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                              C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float,
+                              C.c_void_p]),
+    "spinmc_dmc_save_floats": (C.c_int64, [C.POINTER(DmcParams)]),
+    "spinmc_dmc_work_floats": (C.c_int64, [C.POINTER(DmcParams)]),
+    "spinmc_dmc_forward": (C.c_int, [C.POINTER(DmcParams), C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p]),
+    "spinmc_dmc_backward": (C.c_int, [C.POINTER(DmcParams), C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 _LIB = None

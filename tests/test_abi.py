@@ -87,3 +87,33 @@ def test_no_device_is_reported(L):
 
 def test_mlp_parameter_count(L):
     assert L.spinmc_mlp_num_params() == 4 * 128 + 128 + 128 * 128 + 128 + 3 * 128 + 3
+
+
+def _dmc(**kw):
+    from paper_2304_01772_amd import _lib
+    p = _lib.DmcParams()
+    p.R, p.Lx, p.Ly, p.n_sweeps = 2, 8, 6, 3
+    p.beta, p.alpha, p.h = 0.5, 4.0, 0.0
+    p.seed, p.t0, p.rid0 = 1, 0, 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_dmc_sizes_and_validation_without_a_device(L):
+    """Buffer sizes of the differentiable-MC calls, and their argument checks
+    (rejected before anything touches a device)."""
+    p = _dmc()
+    assert L.spinmc_dmc_save_floats(C.byref(p)) == 2 * 3 * 2 * 6 * 4
+    assert L.spinmc_dmc_work_floats(C.byref(p)) == 2 * 6 * 4
+    for bad in (dict(Lx=7), dict(Ly=0), dict(R=0), dict(n_sweeps=-1), dict(alpha=-1.0),
+                dict(beta=float("nan")), dict(h=float("inf")), dict(rid0=2 ** 32 - 1)):
+        q = _dmc(**bad)
+        assert L.spinmc_dmc_save_floats(C.byref(q)) < 0, bad
+        assert L.spinmc_dmc_forward(C.byref(q), 1, 1, 1, 1, None) == -1, bad
+    # null buffers
+    assert L.spinmc_dmc_forward(C.byref(p), None, 1, 1, 1, None) == -1
+    assert L.spinmc_dmc_forward(C.byref(p), 1, 1, 1, None, None) == -1
+    assert L.spinmc_dmc_backward(C.byref(p), 1, 1, 1, 1, 1, 1, 1, None, None) == -1
+    assert L.spinmc_adam(1, 1, 1, 1, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    assert L.spinmc_adam(1, 1, 1, 1, 10, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
