@@ -85,25 +85,31 @@ __global__ void __launch_bounds__(256) k_dmc_pass(DmcArgs a, int c, uint32_t p, 
     float* sv_save = save + (size_t)r * n_sites;
     uint32_t w[4];
     philox4x32_10((uint32_t)b, p, a.rid0 + (uint32_t)r, kTagDmc, a.key0, a.key1, w);
-    // all four sites read their neighbours (colour 1 - c) before any writes
-    float snew[4];
+    // every load of the four sites first, then the stores (the buffers may
+    // alias as far as the compiler knows); no two of a lane's sites share a
+    // bond, since every bond has one end of each colour
+    float snew[4], sold[4];
     size_t idx[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int k = 4 * b + u;
         idx[u] = 0;
+        snew[u] = sold[u] = 0.f;
         if (k >= n_sites) continue;
         const DmcSite d = dmc_site(k, W, c);
         idx[u] = d.i;
         const float sv = s[d.i];
         const DmcLocal L = dmc_local(s, Jx, Jy, a.Lx, a.Ly, d.y, d.x, sv, a.beta, a.alpha, a.h,
                                      w[u]);
-        sv_save[k] = sv;
+        sold[u] = sv;
         snew[u] = sv * (1.0f - 2.0f * L.q);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-        if (4 * b + u < n_sites) s[idx[u]] = snew[u];
+        if (4 * b + u < n_sites) {
+            sv_save[4 * b + u] = sold[u];
+            s[idx[u]] = snew[u];
+        }
 }
 
 __global__ void __launch_bounds__(256) k_dmc_back(DmcArgs a, int c, uint32_t p,
@@ -126,9 +132,17 @@ __global__ void __launch_bounds__(256) k_dmc_back(DmcArgs a, int c, uint32_t p,
     float* tw = work + (size_t)r * n_sites;
     uint32_t w[4];
     philox4x32_10((uint32_t)b, p, a.rid0 + (uint32_t)r, kTagDmc, a.key0, a.key1, w);
+    // phase 1: every load of the four sites (including the coupling
+    // gradients they add to); phase 2: every store
+    float gout[4], tv[4], sold[4], gr[4], gl[4], gd[4], gu[4];
+    float cr[4], cl[4], cd[4], cu[4];
+    size_t ii[4], ir[4], il[4], idn[4], iu[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int k = 4 * b + u;
+        gout[u] = tv[u] = sold[u] = gr[u] = gl[u] = gd[u] = gu[u] = 0.f;
+        cr[u] = cl[u] = cd[u] = cu[u] = 0.f;
+        ii[u] = ir[u] = il[u] = idn[u] = iu[u] = 0;
         if (k >= n_sites) continue;
         const DmcSite d = dmc_site(k, W, c);
         const float sv = sv_save[k];
@@ -136,16 +150,37 @@ __global__ void __launch_bounds__(256) k_dmc_back(DmcArgs a, int c, uint32_t p,
                                      w[u]);
         const float av = g[d.i];
         const float wq = 4.0f * a.alpha * a.beta * L.q * (1.0f - L.q) * L.P;
-        g[d.i] = av * ((1.0f - 2.0f * L.q) + wq * sv * L.hloc);
+        gout[u] = av * ((1.0f - 2.0f * L.q) + wq * sv * L.hloc);
         const float t = av * wq * sv * sv;
-        tw[k] = t;
+        tv[u] = t;
+        sold[u] = sv;
         const int xl = wrapd(d.x - 1, a.Lx), yu = wrapd(d.y - 1, a.Ly);
         const size_t row = (size_t)d.y * a.Lx;
-        gx[row + d.x] += t * L.sr;
-        gx[row + xl] += t * L.sl;
-        gy[row + d.x] += t * L.sd;
-        gy[(size_t)yu * a.Lx + d.x] += t * L.su;
-        s[d.i] = sv;  // the state before this pass
+        ii[u] = d.i;
+        ir[u] = row + d.x;
+        il[u] = row + xl;
+        idn[u] = row + d.x;
+        iu[u] = (size_t)yu * a.Lx + d.x;
+        gr[u] = gx[ir[u]];
+        gl[u] = gx[il[u]];
+        gd[u] = gy[idn[u]];
+        gu[u] = gy[iu[u]];
+        cr[u] = t * L.sr;
+        cl[u] = t * L.sl;
+        cd[u] = t * L.sd;
+        cu[u] = t * L.su;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int k = 4 * b + u;
+        if (k >= n_sites) continue;
+        g[ii[u]] = gout[u];
+        tw[k] = tv[u];
+        gx[ir[u]] = gr[u] + cr[u];
+        gx[il[u]] = gl[u] + cl[u];
+        gy[idn[u]] = gd[u] + cd[u];
+        gy[iu[u]] = gu[u] + cu[u];
+        s[ii[u]] = sold[u];  // the state before this pass
     }
 }
 
