@@ -297,7 +297,10 @@ typedef struct spinmc_dmc_params {
 
 /* Sizes (floats) of the forward's save buffer (pre-pass spins of the
  * updated colour, 2 n_sweeps R Ly Lx/2) and of the backward's work buffer
- * (R Ly Lx/2); negative on invalid parameters.                              */
+ * (dL/dhloc of two consecutive passes, 2 R Ly Lx/2); negative on invalid
+ * parameters.  Buffers with 16-byte aligned addresses and Lx a multiple of
+ * 8 take the vectorised kernels; any other case takes per-site kernels with
+ * the same results.                                                         */
 int64_t spinmc_dmc_save_floats(const spinmc_dmc_params *p);
 int64_t spinmc_dmc_work_floats(const spinmc_dmc_params *p);
 

@@ -48,7 +48,7 @@ int64_t spinmc_dmc_save_floats(const spinmc_dmc_params* p) {
 
 int64_t spinmc_dmc_work_floats(const spinmc_dmc_params* p) {
     if (!valid(p)) return SPINMC_E_INVALID;
-    return (int64_t)p->R * p->Ly * (p->Lx / 2);
+    return (int64_t)2 * p->R * p->Ly * (p->Lx / 2);
 }
 
 int spinmc_dmc_forward(const spinmc_dmc_params* p, void* dev_s, const void* dev_Jx,

@@ -20,7 +20,7 @@ hipError_t launch_dmc_forward(const DmcArgs& a, uint64_t t0, int n_sweeps, float
                               hipStream_t s);
 // Reverse replay: a.s holds the final spins on entry and the initial spins on
 // exit; gs holds dL/ds_final on entry and dL/ds_initial on exit; gJx, gJy
-// accumulate; work is [R][Ly Lx/2].
+// accumulate; work is [2][R][Ly Lx/2].
 hipError_t launch_dmc_backward(const DmcArgs& a, uint64_t t0, int n_sweeps, const float* save,
                                float* gs, float* gJx, float* gJy, float* work, hipStream_t s);
 

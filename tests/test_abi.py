@@ -105,7 +105,7 @@ def test_dmc_sizes_and_validation_without_a_device(L):
     (rejected before anything touches a device)."""
     p = _dmc()
     assert L.spinmc_dmc_save_floats(C.byref(p)) == 2 * 3 * 2 * 6 * 4
-    assert L.spinmc_dmc_work_floats(C.byref(p)) == 2 * 6 * 4
+    assert L.spinmc_dmc_work_floats(C.byref(p)) == 2 * 2 * 6 * 4
     for bad in (dict(Lx=7), dict(Ly=0), dict(R=0), dict(n_sweeps=-1), dict(alpha=-1.0),
                 dict(beta=float("nan")), dict(h=float("inf")), dict(rid0=2 ** 32 - 1)):
         q = _dmc(**bad)

@@ -19,9 +19,11 @@ def _case(seed, R, Ly, Lx):
     return s0, Jx, Jy, g
 
 
+# Lx a multiple of 8 takes the span kernels, the others the per-site kernels;
+# 34 x 136 and 34 x 138 span three workgroups per replica with a ragged tail
 @pytest.mark.parametrize("R,Ly,Lx,alpha,beta,n", [
     (3, 6, 8, 4.0, 0.5, 4), (2, 16, 32, 10.0, 0.8, 3), (2, 2, 2, 2.0, 1.0, 5),
-    (1, 10, 6, 0.5, 0.3, 6)])
+    (1, 10, 6, 0.5, 0.3, 6), (2, 34, 136, 6.0, 0.6, 3), (1, 34, 138, 3.0, 0.45, 2)])
 def test_forward_and_backward_match_oracle(R, Ly, Lx, alpha, beta, n):
     from paper_2304_01772_amd.dmc import relaxed_ising
     s0, Jx, Jy, g = _case(R * 1000 + Lx, R, Ly, Lx)
@@ -92,3 +94,41 @@ def test_spin_pattern_optimisation_lowers_the_loss():
     np.testing.assert_allclose(hist[:5], ref, rtol=1e-4)
     assert hist[-1] < 0.7 * hist[0], (hist[0], hist[-1])
     assert (s_disc.cpu() == target).float().mean() > 0.75
+
+
+def test_span_and_per_site_kernels_agree():
+    """Buffers 4 bytes off 16-byte alignment take the per-site kernels even
+    when Lx % 8 == 0; forward and backward agree with the span kernels."""
+    import ctypes as C
+    from paper_2304_01772_amd._lib import DmcParams, check, lib
+    R, Ly, Lx, n = 2, 12, 24, 3
+    s0, Jx, Jy, g = _case(77, R, Ly, Lx)
+    p = DmcParams()
+    p.R, p.Lx, p.Ly, p.n_sweeps = R, Lx, Ly, n
+    p.beta, p.alpha, p.h = 0.7, 5.0, 0.02
+    p.seed, p.t0, p.rid0 = 4242, 3, 5
+    L = lib()
+    n_save = L.spinmc_dmc_save_floats(C.byref(p))
+    n_work = L.spinmc_dmc_work_floats(C.byref(p))
+    N = R * Ly * Lx
+    out = []
+    for shift in (0, 1):
+        def buf(n_, init=None):
+            b = torch.zeros(n_ + 4, dtype=torch.float32, device="cuda")[shift:shift + n_]
+            if init is not None:
+                b.copy_(torch.tensor(init.ravel(), device="cuda"))
+            return b
+        s, jx, jy = buf(N, s0), buf(N, Jx), buf(N, Jy)
+        save, work = buf(n_save), buf(n_work)
+        gs, gjx, gjy = buf(N, g), buf(N), buf(N)
+        ptr = lambda t: C.c_void_p(t.data_ptr())
+        check(L.spinmc_dmc_forward(C.byref(p), ptr(s), ptr(jx), ptr(jy), ptr(save), None))
+        s_fin = s.clone()
+        check(L.spinmc_dmc_backward(C.byref(p), ptr(s), ptr(jx), ptr(jy), ptr(save), ptr(gs),
+                                    ptr(gjx), ptr(gjy), ptr(work), None))
+        torch.cuda.synchronize()
+        out.append([x.cpu().numpy() for x in (s_fin, s, gs, gjx, gjy)])
+    np.testing.assert_array_equal(out[0][1], s0.ravel())  # replay restores s0 exactly
+    np.testing.assert_array_equal(out[1][1], s0.ravel())
+    for a, b in zip(out[0], out[1]):
+        np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6)
