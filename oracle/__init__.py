@@ -18,6 +18,10 @@ Contents
 * ``dmc``         FP64 relaxed chain of the differentiable Monte Carlo
                   (Algorithm 2) with per-bond couplings, and its reverse-mode
                   gradients.
+* ``spinopt``     FP64 energy with per-bond couplings, its gradient, the
+                  quantised step, and the three spin-value optimisation
+                  methods (annealed Monte Carlo, gradient, differentiable
+                  Monte Carlo).
 
 Parity status of every function is listed in its module docstring.
 """
