@@ -317,6 +317,25 @@ int spinmc_dmc_backward(const spinmc_dmc_params *p, void *dev_s, const void *dev
                         const void *dev_Jy, const void *dev_save, void *dev_gs, void *dev_gJx,
                         void *dev_gJy, void *dev_work, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Spin-value optimisation (Results, optimisation of the spin values): the
+ * energy the methods minimise and the quantised update.
+ *
+ * Energy of the spins dev_s with the couplings of p's layout (R, Lx, Ly;
+ * field p->h; the other fields of p are not used):
+ *   H = -sum_{y,x} s[y][x] (Jx[y][x] s[y][x+1] + Jy[y][x] s[y+1][x]) - h sum s
+ * into dev_energy (double[R], summed in FP64 in a fixed order, so repeated
+ * calls agree bit for bit) and, if dev_grad is not null, dH/ds =
+ * -(local field of the relaxed chain) into dev_grad (FP32 [R][Ly][Lx]).   */
+int spinmc_dmc_energy(const spinmc_dmc_params *p, const void *dev_s, const void *dev_Jx,
+                      const void *dev_Jy, void *dev_energy, void *dev_grad, void *hip_stream);
+
+/* The discretisation of Algorithm 2 after a gradient step on n FP32 values:
+ * out = -1 where base - eta g < 0, +1 elsewhere (dev_g null: base alone).
+ * dev_out may equal dev_base.  0 <= n <= 2^31, eta finite.                */
+int spinmc_dmc_discretize(int64_t n, const void *dev_base, const void *dev_g, float eta,
+                          void *dev_out, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

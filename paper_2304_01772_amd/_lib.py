@@ -87,6 +87,10 @@ SIGNATURES = {
     "spinmc_dmc_backward": (C.c_int, [C.POINTER(DmcParams), C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
+    "spinmc_dmc_energy": (C.c_int, [C.POINTER(DmcParams), C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p]),
+    "spinmc_dmc_discretize": (C.c_int, [C.c_int64, C.c_void_p, C.c_void_p, C.c_float,
+                                        C.c_void_p, C.c_void_p]),
 }
 
 _LIB = None

@@ -75,6 +75,24 @@ int spinmc_dmc_backward(const spinmc_dmc_params* p, void* dev_s, const void* dev
                                       (hipStream_t)stream));
 }
 
+int spinmc_dmc_energy(const spinmc_dmc_params* p, const void* dev_s, const void* dev_Jx,
+                      const void* dev_Jy, void* dev_energy, void* dev_grad, void* stream) {
+    if (!valid(p) || !dev_s || !dev_Jx || !dev_Jy || !dev_energy) return SPINMC_E_INVALID;
+    return status(launch_dmc_energy(args(p, (float*)dev_s, (const float*)dev_Jx,
+                                         (const float*)dev_Jy),
+                                    (double*)dev_energy, (float*)dev_grad, (hipStream_t)stream));
+}
+
+int spinmc_dmc_discretize(int64_t n, const void* dev_base, const void* dev_g, float eta,
+                          void* dev_out, void* stream) {
+    if (n < 0 || n > ((int64_t)1 << 31) || (n > 0 && (!dev_base || !dev_out)) ||
+        !std::isfinite(eta))
+        return SPINMC_E_INVALID;
+    if (n == 0) return SPINMC_OK;
+    return status(launch_dmc_discretize(n, (const float*)dev_base, (const float*)dev_g, eta,
+                                        (float*)dev_out, (hipStream_t)stream));
+}
+
 int spinmc_adam(void* params, const void* grad, void* m, void* v, int64_t n, int32_t step,
                 float lr, float beta1, float beta2, float eps, void* stream) {
     if (!params || !grad || !m || !v || n < 1 || n > (int64_t)1 << 31 || step < 1 ||

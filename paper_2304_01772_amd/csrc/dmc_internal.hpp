@@ -24,4 +24,11 @@ hipError_t launch_dmc_forward(const DmcArgs& a, uint64_t t0, int n_sweeps, float
 hipError_t launch_dmc_backward(const DmcArgs& a, uint64_t t0, int n_sweeps, const float* save,
                                float* gs, float* gJx, float* gJy, float* work, hipStream_t s);
 
+// Energy H per replica (FP64, e_out[R]) and optionally dH/ds (FP32,
+// [R][Ly][Lx]) of the spins a.s with the couplings a.Jx, a.Jy and field a.h.
+hipError_t launch_dmc_energy(const DmcArgs& a, double* e_out, float* grad, hipStream_t s);
+// out[i] = -1 if base[i] - eta g[i] < 0 else +1 (g may be null: base alone).
+hipError_t launch_dmc_discretize(int64_t n, const float* base, const float* g, float eta,
+                                 float* out, hipStream_t s);
+
 }  // namespace spinmc

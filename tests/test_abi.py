@@ -117,3 +117,11 @@ def test_dmc_sizes_and_validation_without_a_device(L):
     assert L.spinmc_dmc_backward(C.byref(p), 1, 1, 1, 1, 1, 1, 1, None, None) == -1
     assert L.spinmc_adam(1, 1, 1, 1, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == -1
     assert L.spinmc_adam(1, 1, 1, 1, 10, 0, 1e-3, 0.9, 0.999, 1e-8, None) == -1
+    # spin-value optimisation pieces
+    assert L.spinmc_dmc_energy(C.byref(_dmc(Lx=7)), 1, 1, 1, 1, None, None) == -1
+    assert L.spinmc_dmc_energy(C.byref(p), 1, 1, 1, None, None, None) == -1
+    assert L.spinmc_dmc_discretize(-1, 1, None, 1.0, 1, None) == -1
+    assert L.spinmc_dmc_discretize(2 ** 31 + 1, 1, None, 1.0, 1, None) == -1
+    assert L.spinmc_dmc_discretize(4, 1, None, float("nan"), 1, None) == -1
+    assert L.spinmc_dmc_discretize(4, None, None, 1.0, 1, None) == -1
+    assert L.spinmc_dmc_discretize(0, None, None, 1.0, None, None) == 0
