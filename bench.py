@@ -303,6 +303,35 @@ def dmc_probe(torch, R=256, L=128, sweeps=10):
             "backward_frac": round(76 * att / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def spinopt_probe(torch, R=64, L=64, steps=200):
+    """Spin-value optimisation (Results): annealed Monte Carlo, gradient and
+    differentiable Monte Carlo from the same random states over the same
+    linear beta schedule 0.3 -> 3, on J = 1 and on +-J couplings; mean final
+    and best energy per site and the time per step of each method."""
+    from paper_2304_01772_amd.spinopt import SpinOptimiser, spin_glass_couplings
+    g = torch.Generator(device="cpu").manual_seed(1)
+    s0 = (torch.randint(0, 2, (R, L, L), generator=g).float() * 2 - 1).cuda()
+    out = {"config": f"{R} replicas of {L}x{L}, {steps} steps, beta 0.3 -> 3, DMC alpha 20, "
+                     "1 sweep per step, eta 0.05; gradient eta 1"}
+    for kind in ("ferro", "glass"):
+        if kind == "ferro":
+            Jx = torch.ones((R, L, L), device="cuda")
+            Jy = torch.ones((R, L, L), device="cuda")
+        else:
+            Jx, Jy = spin_glass_couplings(R, L, L, 7)
+        o = SpinOptimiser(Jx, Jy, 0.0, seed=3)
+        o.compare(s0, 2)  # warm-up (buffers, first launches)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = o.compare(s0, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[kind] = {m: {"final": round(float(h[-1].mean()), 4), "best": round(float(b.mean()), 4)}
+                     for m, (h, b) in res.items()}
+        out[kind]["wall_s_all_methods"] = round(wall, 3)
+    return out
+
+
 def cpu_baseline(reps, seed, sweeps):
     """The oracle on the host cores: every replica of the workload, a few
     sweeps (a bounded sample of the same chain)."""
@@ -539,6 +568,8 @@ def main():
         print(f"# mlp: {paths['surrogate_mlp']}", file=sys.stderr, flush=True)
         paths["differentiable_mc"] = dmc_probe(torch)
         print(f"# dmc: {paths['differentiable_mc']}", file=sys.stderr, flush=True)
+        paths["spin_value_optimisation"] = spinopt_probe(torch)
+        print(f"# spinopt: {paths['spin_value_optimisation']}", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:
