@@ -303,6 +303,30 @@ def dmc_probe(torch, R=256, L=128, sweeps=10):
             "backward_frac": round(76 * att / (bwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def dmc_vs_covariance_probe(torch, R=4096, L=4):
+    """d<e>/dJ for uniform couplings on R replicas of the L x L torus: the
+    fluctuation (covariance) estimator of the library's backward kernel
+    against the differentiable chain's pathwise derivative (alpha 10, 1 and
+    5 sweeps after a discretised burn-in).  Exact values come from
+    enumeration (2^16 states for 4 x 4) in the tests' helpers."""
+    from paper_2304_01772_amd.differentiable import ising_observables
+    from paper_2304_01772_amd.dmc import pathwise_energy_gradient
+    out = {"config": f"{R} replicas of {L}x{L}, J = 1, h = 0"}
+    for beta in (0.2, 0.44, 0.8):
+        J = torch.ones(R, dtype=torch.float64, device="cuda", requires_grad=True)
+        Jy = torch.ones(R, dtype=torch.float64, device="cuda", requires_grad=True)
+        e, _ = ising_observables(J, Jy, torch.zeros(R, dtype=torch.float64, device="cuda"), L,
+                                 beta, 2000, 500, 11, 0)
+        e.sum().backward()
+        d = (J.grad + Jy.grad).double()
+        row = {"covariance": [round(float(d.mean()), 4), round(float(d.std() / R ** 0.5), 4)]}
+        for n in (1, 5):
+            _, m, se = pathwise_energy_gradient(L, R, beta, 10.0, n, 50, 11)
+            row[f"pathwise_alpha10_{n}sweeps"] = [round(m, 4), round(se, 4)]
+        out[f"beta_{beta}"] = row
+    return out
+
+
 def spinopt_probe(torch, R=64, L=64, steps=200):
     """Spin-value optimisation (Results): annealed Monte Carlo, gradient and
     differentiable Monte Carlo from the same random states over the same
@@ -568,6 +592,8 @@ def main():
         print(f"# mlp: {paths['surrogate_mlp']}", file=sys.stderr, flush=True)
         paths["differentiable_mc"] = dmc_probe(torch)
         print(f"# dmc: {paths['differentiable_mc']}", file=sys.stderr, flush=True)
+        paths["dmc_vs_covariance"] = dmc_vs_covariance_probe(torch)
+        print(f"# dmc vs covariance: {paths['dmc_vs_covariance']}", file=sys.stderr, flush=True)
         paths["spin_value_optimisation"] = spinopt_probe(torch)
         print(f"# spinopt: {paths['spin_value_optimisation']}", file=sys.stderr, flush=True)
 

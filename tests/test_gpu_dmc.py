@@ -132,3 +132,25 @@ def test_span_and_per_site_kernels_agree():
     np.testing.assert_array_equal(out[1][1], s0.ravel())
     for a, b in zip(out[0], out[1]):
         np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-6)
+
+
+def test_pathwise_energy_gradient_matches_oracle():
+    """The chain's pathwise d e/dJ per replica (after a discretised burn-in)
+    equals the same computation on the FP64 oracle from the same state."""
+    from paper_2304_01772_amd.dmc import discretize, pathwise_energy_gradient, relaxed_ising
+    R, L, beta, alpha, n, burn, seed = 64, 4, float(np.float32(0.44)), 10.0, 3, 20, 5
+    d, mean, se = pathwise_energy_gradient(L, R, beta, alpha, n, burn, seed)
+    # the oracle from the GPU's discretised burn-in state (a +-1 lattice)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    s = (torch.randint(0, 2, (R, L, L), generator=g).to(torch.float32) * 2 - 1).cuda()
+    one = torch.ones((R, L, L), device="cuda")
+    with torch.no_grad():
+        s = discretize(relaxed_ising(s, one, one, beta, alpha, 0.0, burn, seed, 0)).cpu().double()
+    Jx = torch.ones((R, L, L), dtype=torch.float64, requires_grad=True)
+    Jy = torch.ones((R, L, L), dtype=torch.float64, requires_grad=True)
+    sf = odmc.forward(s, Jx, Jy, 0.0, beta, alpha, seed, list(range(R)), burn, n)
+    e = -(sf * (Jx * torch.roll(sf, -1, 2) + Jy * torch.roll(sf, -1, 1))).sum(dim=(1, 2)) / (L * L)
+    e.sum().backward()
+    want = (Jx.grad.sum(dim=(1, 2)) + Jy.grad.sum(dim=(1, 2))).numpy()
+    np.testing.assert_allclose(d.cpu().numpy(), want, rtol=0, atol=1e-3 * max(1.0, np.abs(want).max()))
+    assert abs(mean - want.mean()) < 1e-3 and se > 0
