@@ -12,7 +12,8 @@ first) updates every site of colour c at once from the current spins:
 
     hloc = sum over the four bonds of J * s_neighbour + h
     dE   = 2 s hloc                   (the proposal flips the spin, s' = -s)
-    P    = exp(-beta dE)               (no clipping at 1, as the algorithm states)
+    P    = exp(-beta dE)               (no clipping at 1, as the algorithm states;
+                                        the exponent is capped at EXP_CAP)
     r    = uniform in [0, 1)
     q    = 1 / (1 + exp(-alpha (P - r)))
     s   <- q s' + (1 - q) s = s (1 - 2 q)
@@ -37,6 +38,11 @@ import torch
 from . import chain
 
 TAG_DMC = 3
+# P = exp(min(-beta dE, EXP_CAP)): beyond the cap q is exactly 1 in FP32 and
+# FP64 for any alpha >= 2e-33 (or alpha = 0, where q = 1/2 anyway), so no
+# forward value changes; only the infinite P of an overflowing exponent, and
+# the 0 * inf in its gradient, are avoided (FP32 overflows at 88.7).
+EXP_CAP = 80.0
 
 
 def uniforms(Lx, Ly, seed, rids, p):
@@ -83,7 +89,7 @@ def forward(s0, Jx, Jy, h, beta, alpha, seed, rids, t0, n_sweeps):
             p = 2 * t + c
             m = colour_mask(Lx, Ly, c)
             hloc = local_field(s, Jx, Jy, h)
-            P = torch.exp(-beta * 2.0 * s * hloc)
+            P = torch.exp(torch.clamp(-beta * 2.0 * s * hloc, max=EXP_CAP))
             r = uniforms(Lx, Ly, seed, rids, p)
             q = 1.0 / (1.0 + torch.exp(-alpha * (P - r)))
             s = torch.where(m, s * (1.0 - 2.0 * q), s)

@@ -134,3 +134,22 @@ def test_gradients_match_finite_differences(alpha, beta):
             assert abs(fd - grad[idx]) <= 1e-6 * max(1.0, abs(fd)), (name, idx, fd, grad[idx])
     fd_h = (f(s0, Jx, Jy, h + eps) - f(s0, Jx, Jy, h - eps)) / (2 * eps)
     assert abs(fd_h - gh) <= 1e-6 * max(1.0, abs(fd_h))
+
+
+def test_exponent_cap_changes_no_forward_value(monkeypatch):
+    """At beta = 1000 the exponent -beta dE reaches thousands: with the cap
+    the forward equals the uncapped one (q is exactly 1 past the cap) and
+    the gradients stay finite."""
+    rng = np.random.default_rng(6)
+    R, Ly, Lx, beta, alpha = 2, 4, 6, 1000.0, 10.0
+    s0 = _rng_state(rng, R, Ly, Lx)
+    J = rng.uniform(0.2, 1.0, size=(R, Ly, Lx))
+    g = rng.normal(size=(R, Ly, Lx))
+    capped, gs0, gJx, gJy, gh = dmc.forward_backward(s0, J, J, 0.0, beta, alpha, 4, [0, 1], 0, 2,
+                                                     g)
+    for a in (gs0, gJx, gJy, np.array(gh)):
+        assert np.all(np.isfinite(a))
+    monkeypatch.setattr(dmc, "EXP_CAP", float("inf"))
+    plain = dmc.forward(torch.tensor(s0), torch.tensor(J), torch.tensor(J), 0.0, beta, alpha, 4,
+                        [0, 1], 0, 2).numpy()
+    assert np.array_equal(capped, plain)
