@@ -280,7 +280,8 @@ int spinmc_adam(void *dev_params, const void *dev_grad, void *dev_m, void *dev_v
  * (colour c = (x+y) & 1 first c = 0, pass p = 2t + c), every site of colour c:
  *   hloc = Jx[y][x] s(y,x+1) + Jx[y][x-1] s(y,x-1) + Jy[y][x] s(y+1,x)
  *          + Jy[y-1][x] s(y-1,x) + h                     (periodic),
- *   P = exp(-beta * 2 s hloc)   (energy change of the flip proposal),
+ *   P = exp(min(-beta * 2 s hloc, 80))   (energy change of the flip
+ *       proposal; past the cap q is exactly 1 either way),
  *   q = 1 / (1 + exp(-alpha (P - r))),   s <- q (-s) + (1 - q) s,
  * r = (w >> 8) 2^-24 with w word k & 3 of Philox4x32-10 counter
  * (k >> 2, p, rid0 + replica, 3), key (seed lo, seed hi), k = y Lx/2 + x>>1.

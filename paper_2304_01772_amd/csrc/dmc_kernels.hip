@@ -6,7 +6,7 @@
 // site of colour c from the current spins:
 //     hloc = Jx[y][x] s(y,x+1) + Jx[y][x-1] s(y,x-1) + Jy[y][x] s(y+1,x)
 //            + Jy[y-1][x] s(y-1,x) + h
-//     P = exp(-2 beta s hloc),  q = 1 / (1 + exp(-alpha (P - r))),
+//     P = exp(min(-2 beta s hloc, 80)),  q = 1 / (1 + exp(-alpha (P - r))),
 //     s <- s (1 - 2 q)          (the flip s' = -s mixed in with weight q)
 // with r = (word >> 8) 2^-24 from Philox4x32-10 counter (k >> 2, p, rid, 3),
 // word k & 3, k = y Lx/2 + (x >> 1).  A lane handles the four sites of one
@@ -63,7 +63,9 @@ __device__ __forceinline__ DmcUpd dmc_update(float sv, float jr, float sr, float
                                              float alpha, float h, uint32_t word) {
     DmcUpd U;
     U.hloc = jr * sr + jl * sl + jd * sd + ju * su + h;
-    U.P = expf(-beta * (2.0f * sv * U.hloc));
+    // exponent capped at 80: beyond it q is exactly 1 anyway, and an infinite
+    // P would turn the backward's q (1 - q) P into 0 * inf
+    U.P = expf(fminf(-beta * (2.0f * sv * U.hloc), 80.0f));
     const float r = (float)(word >> 8) * 0x1p-24f;
     U.q = 1.0f / (1.0f + expf(-alpha * (U.P - r)));
     return U;

@@ -16,7 +16,7 @@ import torch
 from ._lib import DmcParams, check, lib
 
 __all__ = ["RelaxedIsing", "relaxed_ising", "optimise_couplings", "discretize",
-           "pathwise_energy_gradient"]
+           "pathwise_energy_gradient", "gradient_vs_temperature"]
 
 
 def _p(t):
@@ -140,3 +140,20 @@ def pathwise_energy_gradient(L=4, R=4096, beta=0.44, alpha=10.0, n_sweeps=1, bur
     mean = float(d.mean())
     se = float(d.std() / R ** 0.5) if R > 1 else float("nan")
     return d, mean, se
+
+
+def gradient_vs_temperature(target, s0, Jx, Jy, temperatures, alpha=10.0, n_sweeps=10, seed=1):
+    """Mean |dL/dJ| over all bonds and replicas of the spin-pattern loss
+    L = mean((s_final - target)^2) at each temperature T = 1/beta, from the
+    same start and the same random numbers (Results, optimisation of the
+    exchange parameters: the gradients are small at high and at low T and
+    largest in between).  Returns a list of floats."""
+    out = []
+    target = target.to(torch.float32)
+    for T in temperatures:
+        jx = Jx.detach().to(torch.float32).clone().requires_grad_(True)
+        jy = Jy.detach().to(torch.float32).clone().requires_grad_(True)
+        s = relaxed_ising(s0, jx, jy, 1.0 / float(T), alpha, 0.0, n_sweeps, seed)
+        ((s - target) ** 2).mean().backward()
+        out.append(float(torch.cat([jx.grad.abs().flatten(), jy.grad.abs().flatten()]).mean()))
+    return out
