@@ -465,6 +465,16 @@ def copy_calibration(torch, mib):
     return n
 
 
+PATH_PROBES = {
+    "cpm": lambda S, torch: cpm_probe(S, torch, 50),
+    "grad": lambda S, torch: grad_probe(S, torch),
+    "mlp": lambda S, torch: mlp_probe(torch),
+    "dmc": lambda S, torch: dmc_probe(torch),
+    "dmc_vs_covariance": lambda S, torch: dmc_vs_covariance_probe(torch),
+    "spinopt": lambda S, torch: spinopt_probe(torch),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -494,6 +504,9 @@ def main():
     ap.add_argument("--ising-probe", type=int, default=0, metavar="N",
                     help="run only the streamed Ising probe with N replicas of 256x256 "
                          "(--prof-sweeps sweeps; for counter collection)")
+    ap.add_argument("--path", choices=sorted(PATH_PROBES), default=None,
+                    help="run only this measurement of the other paths and print it "
+                         "(for profiling runs)")
     ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
                     help="write the counter summary from rocprofv3 --pmc runs of this script "
                          "(each DIR holds the run's counter csv and its stdout as bench.out)")
@@ -510,6 +523,12 @@ def main():
     import torch
     import synth
     from paper_2304_01772_amd.sampler import Sampler, MODES
+
+    if args.path:
+        res = PATH_PROBES[args.path](Sampler, torch)
+        print(json.dumps({"path": args.path, "result": res, "argv": sys.argv[1:],
+                          "kernel_source_hash": kernel_source_hash()}), flush=True)
+        return
 
     if args.ising_probe:
         # the streamed Ising probe alone (counter collection for its roofline)
