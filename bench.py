@@ -193,6 +193,41 @@ def cpm_probe(Sampler, torch, mcs):
             "algorithmic_GBs": round(per_launch * 17 / avg_s / 1e9, 1)}
 
 
+def cpm_paper_probe(Sampler, torch, n_rep=256, mcs=2000):
+    """The paper's own CPM setting (Results, Table 2) batched: n_rep replicas
+    of the 6 x 6 aggregate of 5 x 5 cells in 64 x 64, k_B T = 8, A = 25,
+    lambda = 1, for `mcs` Monte Carlo steps; rate and mean boundary lengths
+    (von Neumann bonds) by type pair at the start and the end."""
+    import synth
+    ids, types, A, J, prm = synth.cpm_paper_aggregate(n_rep=n_rep)
+    reps = [dict(model=2, Lx=ids.shape[2], Ly=ids.shape[1], q=len(types[r]) - 1, rid=r,
+                 adhesion=J, cell_type=types[r], target_area=A,
+                 lambda_area=prm["lambda_area"], temperature=prm["temperature"])
+            for r in range(n_rep)]
+    smp = Sampler(reps, prm["seed"], init=False)
+    for r in range(n_rep):
+        smp.set_state(r, ids[r])
+    b0, _ = smp.measure()
+    b0 = b0.float().mean(0).cpu()
+    smp.sweep(2)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, smp.stream)
+    smp.sweep(mcs)
+    e1.record(smp.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    b1, _ = smp.measure()
+    b1 = b1.float().mean(0).cpu()
+    smp.close()
+    sites = n_rep * ids.shape[1] * ids.shape[2]
+    names = {1: "light-medium", 2: "dark-medium", 4: "light-dark"}
+    return {"config": f"{n_rep} replicas of {ids.shape[1]}x{ids.shape[2]}, 36 cells of 5x5, "
+                      f"Table 2 adhesion, kT 8, A 25, lambda 1, {mcs + 2} MCS",
+            "attempts_per_ns": round(sites * mcs / (ms * 1e6), 2),
+            "boundary_start": {v: round(float(b0[k]), 1) for k, v in names.items()},
+            "boundary_end": {v: round(float(b1[k]), 1) for k, v in names.items()}}
+
+
 def grad_probe(Sampler, torch):
     """Differentiation workload: 256 Ising replicas of 128x128 (J ~ U(0.3,
     0.6), h ~ U(-0.05, 0.05), beta 1), 5000 recorded sweeps, then the
@@ -467,6 +502,7 @@ def copy_calibration(torch, mib):
 
 PATH_PROBES = {
     "cpm": lambda S, torch: cpm_probe(S, torch, 50),
+    "cpm_paper": lambda S, torch: cpm_paper_probe(S, torch),
     "grad": lambda S, torch: grad_probe(S, torch),
     "mlp": lambda S, torch: mlp_probe(torch),
     "dmc": lambda S, torch: dmc_probe(torch),
@@ -605,6 +641,8 @@ def main():
         paths = {}
         paths["cpm_cell_sorting"] = cpm_probe(Sampler, torch, 50)
         print(f"# cpm: {paths['cpm_cell_sorting']}", file=sys.stderr, flush=True)
+        paths["cpm_paper_setting"] = cpm_paper_probe(Sampler, torch)
+        print(f"# cpm paper setting: {paths['cpm_paper_setting']}", file=sys.stderr, flush=True)
         paths["covariance_backward"] = grad_probe(Sampler, torch)
         print(f"# grad: {paths['covariance_backward']}", file=sys.stderr, flush=True)
         paths["surrogate_mlp"] = mlp_probe(torch)

@@ -9,7 +9,7 @@ energy, an acceptance or an observable.
 import numpy as np
 
 __all__ = [
-    "single_ising", "batched_ising_potts", "differentiation", "cpm_sorting",
+    "single_ising", "batched_ising_potts", "differentiation", "cpm_sorting", "cpm_paper_aggregate",
     "surrogate_points", "random_ising", "random_potts", "ISING", "POTTS", "CPM",
 ]
 
@@ -86,6 +86,35 @@ def cpm_sorting(n_rep=8, L=512, n_cells=1000, side=14, seed=1004, slot=14, offse
     J = np.array([[0, 16, 16], [16, 2, 11], [16, 11, 16]], np.float32)
     params = dict(lambda_area=1.0, temperature=10.0, seed=4, n_mcs=2000)
     return ids, cell_type, target_area, J, params
+
+
+def cpm_paper_aggregate(n_rep=16, L=64, side=5, grid=6, seed=1006):
+    """The paper's own CPM setting (Results, Table 2): an aggregate of
+    grid x grid square cells of side x side sites (36 cells of area 25)
+    touching each other, centred in an L x L medium; types light (1) and dark
+    (2) half and half by a seeded permutation per replica; target area 25,
+    lambda 1, k_B T = 8, adhesion (medium, light, dark) J_mm = 0,
+    J_ml = J_md = 16, J_ll = 2, J_dd = 14, J_ld = 11.  Returns (ids[n_rep, L,
+    L] int32, cell_type[n_rep][n + 1] int8, target_area, J[3, 3], params)."""
+    rng = np.random.default_rng(seed)
+    n_cells = grid * grid
+    y0 = (L - grid * side) // 2
+    ids = np.zeros((n_rep, L, L), np.int32)
+    types = []
+    for r in range(n_rep):
+        for c in range(n_cells):
+            gy, gx = divmod(c, grid)
+            ids[r, y0 + gy * side:y0 + (gy + 1) * side, y0 + gx * side:y0 + (gx + 1) * side] = c + 1
+        ct = np.zeros(n_cells + 1, np.int8)
+        perm = rng.permutation(n_cells)
+        ct[1 + perm[: n_cells // 2]] = 1
+        ct[1 + perm[n_cells // 2:]] = 2
+        types.append(ct)
+    target_area = np.full(n_cells + 1, side * side, np.int32)
+    target_area[0] = 0
+    J = np.array([[0, 16, 16], [16, 2, 11], [16, 11, 14]], np.float32)
+    params = dict(lambda_area=1.0, temperature=8.0, seed=6)
+    return ids, types, target_area, J, params
 
 
 def surrogate_points(n=100_000, seed=1005):

@@ -112,3 +112,33 @@ def test_cell_sorting_config_full_size(S):
         assert set(np.unique(got)) <= set(np.unique(ids[r]))
         assert np.array_equal(stats[r], orc.cpm_stats(got, J, ctype, A, prm["lambda_area"]))
     smp.close()
+
+
+def test_paper_cell_sorting_setting(S):
+    """The paper's own CPM setting (36 cells of area 25 in a touching 6 x 6
+    aggregate, Table 2 adhesion, k_B T = 8, A = 25, lambda = 1) on 16
+    replicas of 64 x 64: 2000 Monte Carlo steps bit-exact with the oracle
+    for two replicas (state and recorded statistics), and the sorting the
+    paper reports: the light cells lose all contact with the medium and the
+    light-dark boundary shrinks (statistics: b1 light-medium, b2
+    dark-medium, b4 light-dark)."""
+    ids, types, A, J, prm = synth.cpm_paper_aggregate()
+    reps = [_rep(ids[r], J, types[r], A, prm["lambda_area"], prm["temperature"], r)
+            for r in range(ids.shape[0])]
+    smp = S(reps, prm["seed"], init=False)
+    for r in range(len(reps)):
+        smp.set_state(r, ids[r])
+    start, _ = smp.measure()
+    start = start.cpu().numpy()
+    n, every = 2000, 500
+    st = smp.sweep(n, every).cpu().numpy()
+    for r in (0, 9):
+        want, _, ost = orc.cpm_run(ids[r], J, types[r], A, prm["lambda_area"], prm["temperature"],
+                                   prm["seed"], r, 0, n, every)
+        assert np.array_equal(smp.get_state(r), want)
+        assert np.array_equal(st[:, r], ost)
+    end = st[-1]
+    assert start[:, 1].mean() > 30 and end[:, 1].mean() < 0.1 * start[:, 1].mean()
+    assert end[:, 4].mean() < 0.75 * start[:, 4].mean()
+    assert end[:, 2].mean() > start[:, 2].mean()  # the dark cells now face the medium
+    smp.close()
