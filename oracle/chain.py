@@ -72,6 +72,13 @@ def lib():
                               C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int, C.c_int,
                               _i32p, _i32p, C.c_void_p]
     L.orc_cpm_run.restype = C.c_int
+    L.orc_cpm_stats_r.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _f32p, _i8p, _i32p,
+                                  C.c_float, _i32p, C.c_int, _i32p]
+    L.orc_cpm_stats_r.restype = None
+    L.orc_cpm_run_r.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _f32p, _i8p, _i32p,
+                                C.c_float, C.c_double, C.c_uint64, C.c_uint32, C.c_uint64,
+                                C.c_int, C.c_int, C.c_int, _i32p, _i32p, C.c_void_p]
+    L.orc_cpm_run_r.restype = C.c_int
     L.orc_ising_run_batch.argtypes = [C.c_int, _i32p, _i32p, _f32p, _f32p, _f32p, _f64p,
                                       C.c_uint64, _u32p, C.c_uint64, C.c_int, C.c_int, _i8p,
                                       _i64p, C.c_void_p]
@@ -184,29 +191,34 @@ def cpm_scale(J, lam):
     return int(S.value)
 
 
-def cpm_stats(ids, J, cell_type, target_area, lam):
+def cpm_stats(ids, J, cell_type, target_area, lam, nrange=1):
+    """nrange: neighbourhood range of the adhesion energy (1: Moore 3x3,
+    2: 5x5)."""
     ids = np.ascontiguousarray(ids, np.int32)
     J = np.ascontiguousarray(J, np.float32)
     out = np.zeros(16, np.int32)
-    lib().orc_cpm_stats(ids.shape[1], ids.shape[0], len(cell_type) - 1, J.shape[0],
-                        J.reshape(-1), np.ascontiguousarray(cell_type, np.int8),
-                        np.ascontiguousarray(target_area, np.int32), lam, ids, out)
+    lib().orc_cpm_stats_r(ids.shape[1], ids.shape[0], len(cell_type) - 1, J.shape[0],
+                          J.reshape(-1), np.ascontiguousarray(cell_type, np.int8),
+                          np.ascontiguousarray(target_area, np.int32), lam, ids, int(nrange),
+                          out)
     return out
 
 
 def cpm_run(ids, J, cell_type, target_area, lam, temperature, seed, rid, t0, n_mcs,
-            record_every=0):
-    """Returns (ids, area[n_cells+1], stats[n_rec, 16])."""
+            record_every=0, nrange=1):
+    """Returns (ids, area[n_cells+1], stats[n_rec, 16]).  nrange: 1 (Moore
+    3x3, 4 colours) or 2 (5x5, 9 colours; Lx and Ly multiples of 6)."""
     ids = np.ascontiguousarray(ids, np.int32).copy()
     J = np.ascontiguousarray(J, np.float32)
     n_cells = len(cell_type) - 1
     area = np.zeros(n_cells + 1, np.int32)
     n_rec = n_mcs // record_every if record_every > 0 else 0
     stats = np.zeros((max(n_rec, 1), 16), np.int32)
-    rc = lib().orc_cpm_run(ids.shape[1], ids.shape[0], n_cells, J.shape[0], J.reshape(-1),
-                           np.ascontiguousarray(cell_type, np.int8),
-                           np.ascontiguousarray(target_area, np.int32), lam, temperature, seed,
-                           rid, t0, n_mcs, record_every, ids, area, stats.ctypes.data)
+    rc = lib().orc_cpm_run_r(ids.shape[1], ids.shape[0], n_cells, J.shape[0], J.reshape(-1),
+                             np.ascontiguousarray(cell_type, np.int8),
+                             np.ascontiguousarray(target_area, np.int32), lam, temperature,
+                             seed, rid, t0, n_mcs, record_every, int(nrange), ids, area,
+                             stats.ctypes.data)
     _check(rc, "cpm_run")
     return ids, area, stats[:n_rec]
 

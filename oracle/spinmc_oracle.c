@@ -335,9 +335,7 @@ int orc_potts_run(int Lx, int Ly, int q, float J, float h, double beta, uint64_t
 }
 
 /* ------------------------------------------------------------------------ */
-/* Cellular Potts, Eq. (3).  Moore neighbourhood, order (dy,dx) below.       */
-static const int MOORE_DY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
-static const int MOORE_DX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
+/* Cellular Potts, Eq. (3).                                                   */
 
 /* Smallest power-of-two scale S = 2^s, s <= 8, that makes every adhesion
  * J*S and lambda*S an integer of magnitude below 2^20.                      */
@@ -389,21 +387,40 @@ static int cpm_check(int Lx, int Ly, int n_cells, int n_types, const float *J,
     return ORC_OK;
 }
 
+/* Neighbourhood of range r (Chebyshev distance <= r, the Moore
+ * neighbourhood for r = 1 and its second shell added for r = 2): the offsets
+ * in row-major order of (dy, dx) without (0, 0); n = (2r+1)^2 - 1.          */
+static int cpm_neighbours(int range, int *dy, int *dx)
+{
+    int n = 0, i, j;
+    for (i = -range; i <= range; i++)
+        for (j = -range; j <= range; j++)
+            if (i != 0 || j != 0) {
+                dy[n] = i;
+                dx[n] = j;
+                n++;
+            }
+    return n;
+}
+
 /* CPM statistics: von Neumann boundary bonds between different ids, by
  * unordered type pair (a<=b, index a*n_types - a(a-1)/2 + (b-a)), into
  * out[0..9]; fixed-point energy H*S as int64 into out[10] (lo), out[11] (hi).
- * Moore pairs are counted once each (right, down, down-right, down-left).   */
-void orc_cpm_stats(int Lx, int Ly, int n_cells, int n_types, const float *J,
-                   const int8_t *type, const int32_t *A, float lambda, const int32_t *ids,
-                   int32_t out[16])
+ * Adhesion pairs within the neighbourhood of range 1 or 2 are counted once
+ * each (the offsets that come later in row-major order).                     */
+void orc_cpm_stats_r(int Lx, int Ly, int n_cells, int n_types, const float *J,
+                     const int8_t *type, const int32_t *A, float lambda, const int32_t *ids,
+                     int range, int32_t out[16])
 {
     int32_t S = 1;
-    int y, x, d, a;
+    int y, x, d, a, nn;
     int64_t H = 0;
     int32_t *area;
-    static const int FDY[4] = {0, 1, 1, 1};
-    static const int FDX[4] = {1, 0, 1, -1};
+    int NDY[24], NDX[24];
+    static const int FDY[2] = {0, 1};
+    static const int FDX[2] = {1, 0};
     memset(out, 0, 16 * sizeof(int32_t));
+    nn = cpm_neighbours(range, NDY, NDX);
     if (orc_cpm_scale(n_types, J, lambda, &S) != ORC_OK)
         return;
     area = (int32_t *)calloc((size_t)n_cells + 1, sizeof(int32_t));
@@ -423,8 +440,8 @@ void orc_cpm_stats(int Lx, int Ly, int n_cells, int n_types, const float *J,
                     out[ta * n_types - ta * (ta - 1) / 2 + (tb - ta)]++;
                 }
             }
-            for (d = 0; d < 4; d++) {
-                int t = ids[wrap(y + FDY[d], Ly) * Lx + wrap(x + FDX[d], Lx)];
+            for (d = nn / 2; d < nn; d++) {  /* the forward half of the offsets */
+                int t = ids[wrap(y + NDY[d], Ly) * Lx + wrap(x + NDX[d], Lx)];
                 if (t != s)
                     H += (int64_t)llround((double)J[type[s] * n_types + type[t]] * S);
             }
@@ -438,21 +455,41 @@ void orc_cpm_stats(int Lx, int Ly, int n_cells, int n_types, const float *J,
     out[11] = (int32_t)(uint32_t)((uint64_t)H >> 32);
 }
 
-/* One CPM run of n Monte Carlo steps (4 colour passes each, p = 4t + c)
- * from global step t0.  ids: Ly*Lx cell ids; area: [n_cells+1] in/out,
- * recomputed from ids at entry.                                             */
-int orc_cpm_run(int Lx, int Ly, int n_cells, int n_types, const float *J, const int8_t *type,
-                const int32_t *A, float lambda, double temperature, uint64_t seed, uint32_t rid,
-                uint64_t t0, int n_mcs, int record_every, int32_t *ids, int32_t *area,
-                int32_t *stats)
+void orc_cpm_stats(int Lx, int Ly, int n_cells, int n_types, const float *J,
+                   const int8_t *type, const int32_t *A, float lambda, const int32_t *ids,
+                   int32_t out[16])
+{
+    orc_cpm_stats_r(Lx, Ly, n_cells, n_types, J, type, A, lambda, ids, 1, out);
+}
+
+/* One CPM run of n Monte Carlo steps from global step t0.  Range 1: the
+ * 2x2 sublattice, 4 colour passes c = 2 (y & 1) + (x & 1), p = 4t + c,
+ * within-colour index k = (y >> 1) Lx/2 + (x >> 1), neighbour = bits 0..2 of
+ * the main word.  Range 2 (5x5 neighbourhood, Lx and Ly multiples of 6): the
+ * 3x3 sublattice, 9 passes c = 3 (y % 3) + x % 3, p = 9t + c, k = (y / 3)
+ * Lx/3 + x / 3, neighbour j of 24 by the multiply-shift j = (u 24) >> 16 of
+ * the low 16 bits u, rejected when (u 24) mod 2^16 < 2^16 mod 24 = 16, in
+ * which case j = (f1 24) >> 32 with f1 word 1 of the fallback block.
+ * ids: Ly*Lx cell ids; area: [n_cells+1] in/out, recomputed from ids.      */
+int orc_cpm_run_r(int Lx, int Ly, int n_cells, int n_types, const float *J, const int8_t *type,
+                  const int32_t *A, float lambda, double temperature, uint64_t seed, uint32_t rid,
+                  uint64_t t0, int n_mcs, int record_every, int range, int32_t *ids,
+                  int32_t *area, int32_t *stats)
 {
     int32_t S;
     int64_t *JS, LS;
     int32_t *snap;
     uint32_t key[2], w[4], f[4];
-    int i, c, y, x, j, rec = 0;
+    int i, c, y, x, j, rec = 0, nn, nc;
+    int NDY[24], NDX[24];
+    if (range != 1 && range != 2)
+        return ORC_EINVAL;
+    if (range == 2 && (Lx % 6 != 0 || Ly % 6 != 0))
+        return ORC_EINVAL;
     if (cpm_check(Lx, Ly, n_cells, n_types, J, type, lambda, temperature) != ORC_OK)
         return ORC_EINVAL;
+    nn = cpm_neighbours(range, NDY, NDX);
+    nc = range == 1 ? 4 : 9;
     if (n_mcs < 0 || record_every < 0)
         return ORC_EINVAL;
     for (i = 0; i < Lx * Ly; i++)
@@ -471,27 +508,42 @@ int orc_cpm_run(int Lx, int Ly, int n_cells, int n_types, const float *J, const 
     seed_key(seed, key);
     for (i = 0; i < n_mcs; i++) {
         uint64_t t = t0 + (uint64_t)i;
-        for (c = 0; c < 4; c++) {
-            uint32_t p = (uint32_t)(4 * t + (uint64_t)c);
+        for (c = 0; c < nc; c++) {
+            uint32_t p = (uint32_t)((uint64_t)nc * t + (uint64_t)c);
             memcpy(snap, area, sizeof(int32_t) * ((size_t)n_cells + 1));
             for (y = 0; y < Ly; y++)
                 for (x = 0; x < Lx; x++) {
-                    if (2 * (y & 1) + (x & 1) != c)
+                    int col = range == 1 ? 2 * (y & 1) + (x & 1) : 3 * (y % 3) + x % 3;
+                    if (col != c)
                         continue;
-                    uint32_t k = (uint32_t)((y >> 1) * (Lx / 2) + (x >> 1));
+                    uint32_t k = range == 1 ? (uint32_t)((y >> 1) * (Lx / 2) + (x >> 1))
+                                            : (uint32_t)((y / 3) * (Lx / 3) + x / 3);
                     draw(k >> 2, p, rid, TAG_MAIN, key, w);
                     uint32_t word = w[k & 3u];
-                    int jn = (int)(word & 7u);
+                    int jn;
+                    int have_f = 0;
+                    if (range == 1) {
+                        jn = (int)(word & 7u);
+                    } else {
+                        uint32_t l = (word & 0xFFFFu) * 24u;
+                        jn = (int)(l >> 16);
+                        if ((l & 0xFFFFu) < 16u) {
+                            draw(k, p, rid, TAG_FALLBACK, key, f);
+                            have_f = 1;
+                            jn = (int)(((uint64_t)f[1] * 24u) >> 32);
+                        }
+                    }
                     uint32_t ra = word >> 16;
                     int s = ids[y * Lx + x];
-                    int tgt = ids[wrap(y + MOORE_DY[jn], Ly) * Lx + wrap(x + MOORE_DX[jn], Lx)];
+                    int tgt = ids[wrap(y + NDY[jn], Ly) * Lx + wrap(x + NDX[jn], Lx)];
                     if (tgt == s)
                         continue;
-                    draw(k, p, rid, TAG_FALLBACK, key, f);
+                    if (!have_f)
+                        draw(k, p, rid, TAG_FALLBACK, key, f);
                     uint64_t W = ((uint64_t)ra << 16) | (uint64_t)(f[0] & 0xFFFFu);
                     int64_t kk = 0;
-                    for (j = 0; j < 8; j++) {
-                        int m = ids[wrap(y + MOORE_DY[j], Ly) * Lx + wrap(x + MOORE_DX[j], Lx)];
+                    for (j = 0; j < nn; j++) {
+                        int m = ids[wrap(y + NDY[j], Ly) * Lx + wrap(x + NDX[j], Lx)];
                         if (tgt != m)
                             kk += JS[type[tgt] * n_types + type[m]];
                         if (s != m)
@@ -512,13 +564,23 @@ int orc_cpm_run(int Lx, int Ly, int n_cells, int n_types, const float *J, const 
                 }
         }
         if (record_every > 0 && ((i + 1) % record_every) == 0 && stats) {
-            orc_cpm_stats(Lx, Ly, n_cells, n_types, J, type, A, lambda, ids, stats + 16 * rec);
+            orc_cpm_stats_r(Lx, Ly, n_cells, n_types, J, type, A, lambda, ids, range,
+                            stats + 16 * rec);
             rec++;
         }
     }
     free(JS);
     free(snap);
     return rec;
+}
+
+int orc_cpm_run(int Lx, int Ly, int n_cells, int n_types, const float *J, const int8_t *type,
+                const int32_t *A, float lambda, double temperature, uint64_t seed, uint32_t rid,
+                uint64_t t0, int n_mcs, int record_every, int32_t *ids, int32_t *area,
+                int32_t *stats)
+{
+    return orc_cpm_run_r(Lx, Ly, n_cells, n_types, J, type, A, lambda, temperature, seed, rid,
+                         t0, n_mcs, record_every, 1, ids, area, stats);
 }
 
 /* ------------------------------------------------------------------------ */

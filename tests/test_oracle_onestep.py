@@ -241,3 +241,132 @@ def test_cpm_mcs_matches_bruteforce(orc, seed, lam, T, Jset):
     got, area, _ = orc.cpm_run(ids, J, ctype, A, lam, T, seed, 2, 5, 1)
     assert np.array_equal(got, want)
     assert np.array_equal(area, np.bincount(got.reshape(-1), minlength=len(A)))
+
+
+# ------------------------------------------------ CPM, 5 x 5 neighbourhood
+# the 24 offsets within Chebyshev distance 2, row-major, and the 12 that
+# count each unordered pair once
+N24 = [(dy, dx) for dy in range(-2, 3) for dx in range(-2, 3) if (dy, dx) != (0, 0)]
+F12 = [(0, 1), (0, 2), (1, -2), (1, -1), (1, 0), (1, 1), (1, 2), (2, -2), (2, -1), (2, 0),
+       (2, 1), (2, 2)]
+
+
+def cpm_energy5(ids, J, ctype, A, lam, area):
+    """Eq. (3) with the second shell: adhesion over unordered pairs at
+    Chebyshev distance <= 2 between different ids, plus the area term."""
+    H = 0.0
+    for dy, dx in F12:
+        nb = np.roll(np.roll(ids, -dy, axis=0), -dx, axis=1)
+        diff = ids != nb
+        H += float(J[ctype[ids[diff]], ctype[nb[diff]]].astype(np.float64).sum())
+    cells = np.arange(1, len(A))
+    H += lam * float(((area[cells].astype(np.float64) - A[cells]) ** 2).sum())
+    return H
+
+
+def predict_cpm5(orc, ids, J, ctype, A, lam, T, seed, rid, t):
+    """Nine passes c = 3 (y % 3) + x % 3; neighbour by Lemire's
+    multiply-shift of the low 16 bits into 24 with rejection, then 24 times
+    word 1 of the fallback block shifted by 32."""
+    ids = ids.copy()
+    Ly, Lx = ids.shape
+    for c in range(9):
+        p = 9 * t + c
+        snap = np.bincount(ids.reshape(-1), minlength=len(A))
+        E0 = cpm_energy5(ids, J, ctype, A, lam, snap)
+        new = ids.copy()
+        for y in range(Ly):
+            for x in range(Lx):
+                if 3 * (y % 3) + x % 3 != c:
+                    continue
+                k = (y // 3) * (Lx // 3) + x // 3
+                word = _u(orc, k >> 2, p, rid, 0, seed)[k & 3]
+                f = _u(orc, k, p, rid, 1, seed)
+                l = (word & MASK16) * 24
+                j = l >> 16 if (l & MASK16) >= 65536 % 24 else (f[1] * 24) >> 32
+                dy, dx = N24[j]
+                s, tg = ids[y, x], ids[(y + dy) % Ly, (x + dx) % Lx]
+                if s == tg:
+                    continue
+                W = ((word >> 16) << 16) | (f[0] & MASK16)
+                trial = ids.copy()
+                trial[y, x] = tg
+                a1 = snap.copy()
+                a1[tg] += 1
+                a1[s] -= 1
+                dH = cpm_energy5(trial, J, ctype, A, lam, a1) - E0
+                if dH <= 0 or W < math.ldexp(math.exp(-dH / T), 32):
+                    new[y, x] = tg
+        ids = new
+    return ids
+
+
+def test_lemire_choice_of_24_is_exactly_uniform():
+    counts = np.zeros(24, np.int64)
+    rej = 0
+    for u in range(65536):
+        l = u * 24
+        if (l & MASK16) < 65536 % 24:
+            rej += 1
+        else:
+            counts[l >> 16] += 1
+    assert rej == 16 and np.all(counts == 2730)
+
+
+@pytest.mark.parametrize("seed,lam,T,shape", [
+    (11, 1.0, 10.0, (6, 12)), (12, 0.5, 3.0, (12, 6)), (13, 2.0, 25.0, (6, 6))])
+def test_cpm5_mcs_matches_bruteforce(orc, seed, lam, T, shape):
+    ids, ctype, A = _cpm_case(seed, L=shape, n_cells=6)
+    J = np.array([[0, 16, 16], [16, 2, 11], [16, 11, 14]], np.float32)
+    want = predict_cpm5(orc, ids, J, ctype, A, lam, T, seed, 3, 4)
+    got, area, _ = orc.cpm_run(ids, J, ctype, A, lam, T, seed, 3, 4, 1, nrange=2)
+    assert np.array_equal(got, want)
+    assert np.array_equal(area, np.bincount(got.reshape(-1), minlength=len(A)))
+
+
+def test_cpm5_energy_statistic_matches_bruteforce(orc):
+    rng = np.random.default_rng(14)
+    J = np.array([[0, 3.5, 4.5], [3.5, 1.5, 2.0], [4.5, 2.0, 0.5]], np.float32)
+    S = orc.cpm_scale(J, 0.5)
+    for shape in ((6, 6), (12, 18)):
+        ids, ctype, A = _cpm_case(int(rng.integers(1 << 30)), L=shape, n_cells=7)
+        area = np.bincount(ids.reshape(-1), minlength=len(A))
+        st = orc.cpm_stats(ids, J, ctype, A, 0.5, nrange=2)
+        H = (int(st[11]) << 32) | (int(st[10]) & 0xFFFFFFFF)
+        assert H == round(cpm_energy5(ids, J, ctype, A, 0.5, area) * S)
+        # the boundary bonds stay von Neumann: the same as for range 1
+        assert np.array_equal(st[:10], orc.cpm_stats(ids, J, ctype, A, 0.5)[:10])
+
+
+def test_cpm5_rejects_shapes_off_the_3x3_sublattice(orc):
+    ids, ctype, A = _cpm_case(15, L=(8, 12), n_cells=3)
+    J = np.array([[0, 1], [1, 0]], np.float32)
+    with pytest.raises(Exception):
+        orc.cpm_run(ids, J, np.minimum(ctype, 1), A, 1.0, 5.0, 1, 0, 0, 1, nrange=2)
+
+
+def test_cpm5_neighbour_fallback_path(orc):
+    """A seed whose Monte Carlo step meets the rejected branch of the
+    neighbour choice (probability 16/65536 per attempt): the oracle still
+    equals the brute-force prediction there."""
+    Ly, Lx, rid, t = 6, 6, 1, 0
+    hit = None
+    for seed in range(1, 5000):
+        for c in range(9):
+            for blk in range(((Ly // 3) * (Lx // 3) + 3) // 4):
+                for word in _u(orc, blk, 9 * t + c, rid, 0, seed):
+                    if ((word & MASK16) * 24) & MASK16 < 16:
+                        hit = seed
+                        break
+                if hit:
+                    break
+            if hit:
+                break
+        if hit:
+            break
+    assert hit is not None
+    ids, ctype, A = _cpm_case(hit, L=(Ly, Lx), n_cells=5)
+    J = np.array([[0, 16, 16], [16, 2, 11], [16, 11, 14]], np.float32)
+    want = predict_cpm5(orc, ids, J, ctype, A, 1.0, 50.0, hit, rid, t)
+    got, _, _ = orc.cpm_run(ids, J, ctype, A, 1.0, 50.0, hit, rid, t, 1, nrange=2)
+    assert np.array_equal(got, want)
