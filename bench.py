@@ -221,11 +221,30 @@ def cpm_paper_probe(Sampler, torch, n_rep=256, mcs=2000):
     smp.close()
     sites = n_rep * ids.shape[1] * ids.shape[2]
     names = {1: "light-medium", 2: "dark-medium", 4: "light-dark"}
-    return {"config": f"{n_rep} replicas of {ids.shape[1]}x{ids.shape[2]}, 36 cells of 5x5, "
-                      f"Table 2 adhesion, kT 8, A 25, lambda 1, {mcs + 2} MCS",
-            "attempts_per_ns": round(sites * mcs / (ms * 1e6), 2),
-            "boundary_start": {v: round(float(b0[k]), 1) for k, v in names.items()},
-            "boundary_end": {v: round(float(b1[k]), 1) for k, v in names.items()}}
+    out = {"config": f"{n_rep} replicas of {ids.shape[1]}x{ids.shape[2]}, 36 cells of 5x5, "
+                     f"Table 2 adhesion, kT 8, A 25, lambda 1, {mcs + 2} MCS",
+           "attempts_per_ns": round(sites * mcs / (ms * 1e6), 2),
+           "boundary_start": {v: round(float(b0[k]), 1) for k, v in names.items()},
+           "boundary_end": {v: round(float(b1[k]), 1) for k, v in names.items()}}
+    # the same aggregate with the 5x5 neighbourhood (66 x 66: multiples of 6)
+    ids, types, A, J, prm = synth.cpm_paper_aggregate(n_rep=n_rep, L=66)
+    reps = [dict(model=2, Lx=66, Ly=66, q=len(types[r]) - 1, rid=r, adhesion=J,
+                 cell_type=types[r], target_area=A, lambda_area=prm["lambda_area"],
+                 temperature=prm["temperature"], cpm_range=2) for r in range(n_rep)]
+    smp = Sampler(reps, prm["seed"], init=False)
+    for r in range(n_rep):
+        smp.set_state(r, ids[r])
+    smp.sweep(2)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, smp.stream)
+    smp.sweep(mcs // 4)
+    e1.record(smp.stream)
+    torch.cuda.synchronize()
+    ms5 = e0.elapsed_time(e1)
+    smp.close()
+    out["range2_5x5"] = {"config": f"{n_rep} replicas of 66x66, {mcs // 4} MCS (9 passes each)",
+                         "attempts_per_ns": round(n_rep * 66 * 66 * (mcs // 4) / (ms5 * 1e6), 2)}
+    return out
 
 
 def grad_probe(Sampler, torch):

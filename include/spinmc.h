@@ -60,8 +60,10 @@ enum spinmc_status {
  *   CPM    [b0..b9, Hlo, Hhi, 0...] von Neumann bonds between different ids
  *                              by unordered type pair (a <= b, index
  *                              a*n_types - a(a-1)/2 + (b - a)), and the
- *                              energy of Eq. (3) times the fixed-point scale
- *                              S as an int64 split in two int32 words.      */
+ *                              energy of Eq. (3) (adhesion over the pairs
+ *                              of the replica's neighbourhood) times the
+ *                              fixed-point scale S as an int64 split in two
+ *                              int32 words.                                 */
 
 /* Hamiltonian parameters of one replica (Eq. (1), Eq. (2), Eq. (3)).
  * Signs: Ising H = -Jx sum_h s s' - Jy sum_v s s' - h sum s with s = +-1;
@@ -85,6 +87,18 @@ typedef struct spinmc_replica_desc {
     const int32_t *target_area;  /* host [q + 1] (entry 0 unused)                   */
     float lambda_area;           /* >= 0                                            */
     double temperature;          /* > 0                                             */
+    int32_t cpm_range;           /* neighbourhood of the adhesion sum and of the
+                                    copy source: 0 or 1 = Moore 3x3 (2x2
+                                    sublattice, 4 passes per step, neighbour =
+                                    bits 0..2 of the main word); 2 = 5x5, the
+                                    second shell added (3x3 sublattice, 9 passes
+                                    c = 3 (y % 3) + x % 3 per step, p = 9t + c,
+                                    k = (y/3) Lx/3 + x/3, neighbour j of 24 in
+                                    row-major order by (u 24) >> 16 of the low 16
+                                    bits u, or (f1 24) >> 32 with f1 word 1 of
+                                    the fallback block when (u 24) mod 2^16 < 16;
+                                    Lx, Ly multiples of 6).  One value for every
+                                    replica of a context.                        */
 } spinmc_replica_desc;
 
 /* Create a batch of n replicas (Methods, batched tensors: one context runs
@@ -185,7 +199,8 @@ int spinmc_thresholds(const spinmc_ctx *ctx, int32_t replica, uint64_t *host_T, 
  *   0 decides per model: on when that model's streamed lattices exceed
  *   192 MiB.  The chain is the same either way.
  * Invalid values return SPINMC_E_INVALID.  CPM contexts use tile_rows and
- * wg_threads only.  spinmc_autotune also tries the best streaming schedule
+ * wg_threads only (tile_rows rounded down to whole periods of the colouring:
+ * 2 rows, or 6 with the 5x5 neighbourhood).  spinmc_autotune also tries the best streaming schedule
  * with NT forced on and off.                                                */
 enum { SPINMC_SCHED_NT_ON = 1, SPINMC_SCHED_NT_OFF = 2 };
 typedef struct spinmc_schedule {

@@ -26,7 +26,7 @@ class ReplicaDesc(C.Structure):
         ("beta", C.c_double), ("rid", C.c_uint32),
         ("n_types", C.c_int32), ("adhesion", C.POINTER(C.c_float)),
         ("cell_type", C.POINTER(C.c_int8)), ("target_area", C.POINTER(C.c_int32)),
-        ("lambda_area", C.c_float), ("temperature", C.c_double),
+        ("lambda_area", C.c_float), ("temperature", C.c_double), ("cpm_range", C.c_int32),
     ]
 
 

@@ -101,6 +101,108 @@ __global__ void __launch_bounds__(256) k_cpm_pass(CpmArgs a, int c, int sweep_of
     }
 }
 
+// The 5x5 neighbourhood (the Moore neighbourhood with its second shell):
+// 24 neighbours in row-major order of (dy, dx) for both the adhesion sum and
+// the copy source; the 3x3 sublattice c = 3 (y % 3) + x % 3 keeps the sites
+// of one colour out of each other's neighbourhoods; pass p = 9t + c, within-
+// colour index k = (y / 3) Lx/3 + x / 3.  The neighbour index is Lemire's
+// multiply-shift of the low 16 bits of the main word into 24, and where
+// that rejects (16 of the 65536 values) the 32-bit multiply-shift of word 1
+// of the fallback block.
+__global__ void __launch_bounds__(256) k_cpm_pass5(CpmArgs a, int c, int sweep_off) {
+    extern __shared__ uint32_t lthr[];  // [2 * tab_n]: hi16 | lo16 of T(k), k = 1..K1-1
+    __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
+    const TileDev T = a.tiles[blockIdx.x];
+    const RepDev R = a.reps[T.rep];
+    for (int i = threadIdx.x; i < 2 * R.tab_n; i += blockDim.x) lthr[i] = a.tab[R.tab_off + i];
+    for (int i = threadIdx.x; i < R.n_types * R.n_types; i += blockDim.x)
+        ljs[i] = a.js[R.js_off + i];
+    __syncthreads();
+    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
+    const uint32_t p = (uint32_t)(9 * t + (uint64_t)c);
+    const int cy = c / 3, cx = c - 3 * cy;
+    const int Lx = R.Lx, Ly = R.Ly, Wc = Lx / 3, nt = R.n_types;
+    int32_t* ids = a.lat + R.lat_off;
+    const int8_t* ty = a.ctype + R.cell_off;
+    const int32_t* A = a.target + R.cell_off;
+    const int32_t* snap = a.snap + R.cell_off;
+    int32_t* area = a.area + R.cell_off;
+    const int total = (T.rows / 3) * Wc;
+    for (int it = threadIdx.x; it < total; it += blockDim.x) {
+        const int r = it / Wc;
+        const int i = it - r * Wc;
+        const int y = T.y0 + 3 * r + cy;
+        const int x = 3 * i + cx;
+        const uint32_t k = (uint32_t)((y / 3) * Wc + i);
+        uint32_t w[4];
+        philox4x32_10(k >> 2, p, R.rid, kTagMain, a.key0, a.key1, w);
+        const uint32_t word = w[k & 3u];
+        uint32_t f[4];
+        bool have_f = false;
+        const uint32_t l = (word & 0xFFFFu) * 24u;
+        int jn = (int)(l >> 16);
+        if ((l & 0xFFFFu) < 16u) {
+            philox4x32_10(k, p, R.rid, kTagFallback, a.key0, a.key1, f);
+            have_f = true;
+            jn = (int)(((uint64_t)f[1] * 24u) >> 32);
+        }
+        // row-major offsets without the centre: jn < 12 lies before it
+        const int jj = jn < 12 ? jn : jn + 1;
+        const int ndy = jj / 5 - 2, ndx = jj % 5 - 2;
+        int rows[5], cols[5];
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+            rows[d] = wrapc(y + d - 2, Ly) * Lx;
+            cols[d] = wrapc(x + d - 2, Lx);
+        }
+        const int s = ids[(size_t)rows[2] + x];
+        const int tg = ids[(size_t)wrapc(y + ndy, Ly) * Lx + wrapc(x + ndx, Lx)];
+        if (tg == s) continue;
+        int nb[25];
+#pragma unroll
+        for (int dy = 0; dy < 5; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 5; ++dx) nb[dy * 5 + dx] = ids[(size_t)rows[dy] + cols[dx]];
+        const int ts = ty[s] * nt, tt = ty[tg] * nt;
+        int kadh = 0;
+#pragma unroll
+        for (int j = 0; j < 25; ++j) {
+            if (j == 12) continue;  // the site itself
+            const int m = nb[j];
+            const int tm = ty[m];
+            kadh += (tg != m) ? ljs[tt + tm] : 0;
+            kadh -= (s != m) ? ljs[ts + tm] : 0;
+        }
+        int64_t karea = 0;
+        if (tg != 0) karea += 2 * ((int64_t)snap[tg] - (int64_t)A[tg]) + 1;
+        if (s != 0) karea += -2 * ((int64_t)snap[s] - (int64_t)A[s]) + 1;
+        const int64_t kk = (int64_t)kadh + R.LS * karea;
+        bool acc;
+        if (kk <= 0) {
+            acc = true;
+        } else if (kk >= R.K0) {
+            acc = false;
+        } else {
+            uint32_t hi = 0u, lo = 1u;  // T = 1 for K1 <= k < K0
+            if (kk < (int64_t)R.K1) {
+                hi = lthr[kk - 1];
+                lo = lthr[R.tab_n + kk - 1];
+            }
+            const uint32_t rr = word >> 16;
+            acc = rr < hi;
+            if (rr == hi && lo != 0u) {
+                if (!have_f) philox4x32_10(k, p, R.rid, kTagFallback, a.key0, a.key1, f);
+                acc = (f[0] & 0xFFFFu) < lo;
+            }
+        }
+        if (acc) {
+            ids[(size_t)rows[2] + x] = tg;
+            atomicAdd(&area[tg], 1);
+            atomicAdd(&area[s], -1);
+        }
+    }
+}
+
 // The same pass with four consecutive same-colour sites of one row per lane
 // (Lx a multiple of 8): their attempts share one Philox call (words 0..3 of
 // counter k >> 2), their 3 x 9 id window comes in with six 16-byte loads and
@@ -326,6 +428,17 @@ __global__ void __launch_bounds__(256) k_cpm_stats(CpmArgs a, int rec_row) {
         }
         if (dr != s) H += ljs[ts * nt + ty[dr]];
         if (dl != s) H += ljs[ts * nt + ty[dl]];
+        if (a.range == 2) {
+            // the second shell's forward half: (0,2), (1,+-2), (2,-2..2)
+            const int x2 = wrapc(x + 2, Lx), xm2 = wrapc(x - 2, Lx), y2 = wrapc(y + 2, Ly);
+            const int o[8] = {ids[(size_t)y * Lx + x2],   ids[(size_t)yp * Lx + xm2],
+                              ids[(size_t)yp * Lx + x2],  ids[(size_t)y2 * Lx + xm2],
+                              ids[(size_t)y2 * Lx + xm],  ids[(size_t)y2 * Lx + x],
+                              ids[(size_t)y2 * Lx + xp],  ids[(size_t)y2 * Lx + x2]};
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (o[j] != s) H += ljs[ts * nt + ty[o[j]]];
+        }
     }
     atomicAdd(&lH, (unsigned long long)H);
     __syncthreads();
@@ -359,6 +472,13 @@ __global__ void k_cpm_area_energy(CpmArgs a, int rec_row) {
 hipError_t launch_cpm_pass(const CpmArgs& a, int n_tiles, int c, int sweep_off, int threads,
                            size_t lds_tab_bytes, hipStream_t s) {
     hipLaunchKernelGGL(k_cpm_pass, dim3(n_tiles), dim3(threads), lds_tab_bytes, s, a, c,
+                       sweep_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_cpm_pass5(const CpmArgs& a, int n_tiles, int c, int sweep_off, int threads,
+                            size_t lds_tab_bytes, hipStream_t s) {
+    hipLaunchKernelGGL(k_cpm_pass5, dim3(n_tiles), dim3(threads), lds_tab_bytes, s, a, c,
                        sweep_off);
     return hipGetLastError();
 }

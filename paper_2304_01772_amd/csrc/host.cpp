@@ -152,6 +152,7 @@ struct spinmc_ctx {
     // CPM passes with four sites per lane and LDS cell tables (every Lx a
     // multiple of 8, at most kCpmLdsCells cells per replica)
     bool cpm_quad = false, cpm_lds_reserved = false;
+    int cpm_range = 1;  // 1: Moore 3x3, 4 colours; 2: 5x5, 9 colours
     int cpm_cell_cap = 0;
     // kernel timing
     bool prof = false;
@@ -252,6 +253,11 @@ int validate(const spinmc_replica_desc& d, int i, bool& cpm_seen, bool& lat_seen
             return fail(SPINMC_E_INVALID, "replica %d: CPM lambda must be >= 0", i);
         if (d.cell_type[0] != 0)
             return fail(SPINMC_E_INVALID, "replica %d: cell_type[0] (medium) must be 0", i);
+        if (d.cpm_range < 0 || d.cpm_range > 2)
+            return fail(SPINMC_E_INVALID, "replica %d: cpm_range must be 0, 1 or 2", i);
+        if (d.cpm_range == 2 && (d.Lx % 6 != 0 || d.Ly % 6 != 0))
+            return fail(SPINMC_E_INVALID,
+                        "replica %d: the 5x5 neighbourhood needs Lx, Ly multiples of 6", i);
         for (int k = 0; k <= d.q; ++k)
             if (d.cell_type[k] < 0 || d.cell_type[k] >= d.n_types)
                 return fail(SPINMC_E_INVALID, "replica %d: cell type out of range", i);
@@ -402,6 +408,10 @@ int spinmc_create(const spinmc_replica_desc* d, int32_t n, uint64_t seed, int32_
     if (cpm_seen && lat_seen)
         return fail(SPINMC_E_UNSUPPORTED, "create: CPM replicas cannot share a context with Ising/Potts");
     if (cpm_seen) {
+        for (int i = 1; i < n; ++i)
+            if ((d[i].cpm_range == 2) != (d[0].cpm_range == 2))
+                return fail(SPINMC_E_INVALID,
+                            "create: the CPM replicas of one context must share cpm_range");
         int rc = cpm_prepare_tables(d, n);
         if (rc) return rc;
     }
@@ -1197,15 +1207,20 @@ CpmArgs cpm_args(spinmc_ctx* c, int32_t* stats) {
     a.key1 = (uint32_t)(c->seed >> 32);
     a.R = c->R;
     a.width = c->width;
+    a.range = c->cpm_range;
     return a;
 }
 
+// Row tiles: whole periods of the colouring (2 rows for the 2x2 sublattice,
+// 6 for the 3x3 one, which also keeps them even).
 int cpm_build_tiles(spinmc_ctx* c) {
     std::vector<TileDev> tiles;
+    const int period = c->cpm_range == 2 ? 6 : 2;
     for (int i = 0; i < c->R; ++i) {
         const RepDev& r = c->reps[i].dev;
-        int rows = c->sched.tile_rows > 0 ? c->sched.tile_rows : ((4096 / r.Lx) & ~1);
-        rows = std::max(2, std::min(rows, r.Ly));
+        int rows = c->sched.tile_rows > 0 ? c->sched.tile_rows : 4096 / r.Lx;
+        rows -= rows % period;
+        rows = std::max(period, std::min(rows, r.Ly));
         for (int y0 = 0; y0 < r.Ly; y0 += rows)
             tiles.push_back(TileDev{i, y0, std::min(rows, r.Ly - y0), 0});
     }
@@ -1289,9 +1304,10 @@ int create_cpm(const spinmc_replica_desc* d, int n, uint64_t seed, void* stream,
     }
     c->total_cells = (int)cell_off;
     c->lat_bytes = lat_off + 64;
+    c->cpm_range = d[0].cpm_range == 2 ? 2 : 1;  // shared by every replica (checked)
     {
         int cap = 0;
-        bool quad = true;
+        bool quad = c->cpm_range == 1;
         for (int i = 0; i < n; ++i) {
             cap = std::max(cap, c->reps[i].dev.q + 1);
             quad = quad && (c->reps[i].dev.Lx % 8 == 0);
@@ -1395,11 +1411,15 @@ int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
     hipError_t e = hipSuccess;
     const int n_rec = re > 0 ? n / re : 0;
     if (n_rec > 0) e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
+    const int n_col = c->cpm_range == 2 ? 9 : 4;
     for (int i = 0; i < n && e == hipSuccess; ++i) {
-        for (int col = 0; col < 4 && e == hipSuccess; ++col) {
+        for (int col = 0; col < n_col && e == hipSuccess; ++col) {
             e = launch_cpm_snapshot(a, c->total_cells, c->stream);
             if (e == hipSuccess)
                 e = timed(c, SPINMC_K_CPM_PASS, [&] {
+                    if (c->cpm_range == 2)
+                        return launch_cpm_pass5(a, c->n_tiles, col, i, threads, tab_bytes,
+                                                c->stream);
                     if (c->cpm_quad)
                         return launch_cpm_pass_quad(a, c->n_tiles, col, i, threads,
                                                     (int)tab_bytes, c->cpm_cell_cap, c->stream);

@@ -141,9 +141,14 @@ struct CpmArgs {
     int32_t* stats;
     uint32_t key0, key1;
     int32_t R, width;
+    int32_t range;                // neighbourhood: 1 Moore 3x3, 2 the 5x5 square
 };
 hipError_t launch_cpm_pass(const CpmArgs& a, int n_tiles, int c, int sweep_off, int threads,
                            size_t lds_tab_bytes, hipStream_t s);
+// The 5x5 neighbourhood (range 2): colour c of the 3x3 sublattice, one site
+// per lane; tiles of whole multiples of 3 rows.
+hipError_t launch_cpm_pass5(const CpmArgs& a, int n_tiles, int c, int sweep_off, int threads,
+                            size_t lds_tab_bytes, hipStream_t s);
 // Four same-colour sites per lane with the cell tables in LDS: needs every
 // Lx a multiple of 8 and cell_cap >= n_cells + 1 (a multiple of 16) for
 // every replica; dynamic LDS tab_lds_bytes + 5 cell_cap.

@@ -29,7 +29,8 @@ class Sampler:
 
     ``replicas``: sequence of dicts with keys model, Lx, Ly and the model's
     parameters (q, Jx, Jy, h, beta, rid; CPM: n_cells as q, n_types,
-    adhesion, cell_type, target_area, lambda_area, temperature).
+    adhesion, cell_type, target_area, lambda_area, temperature and optionally
+    cpm_range, 1 for the Moore 3x3 neighbourhood or 2 for 5x5).
     """
 
     def __init__(self, replicas, seed, init=True, stream=None, device="cuda"):
@@ -62,6 +63,7 @@ class Sampler:
                 d.target_area = ta.ctypes.data_as(C.POINTER(C.c_int32))
                 d.lambda_area = float(r["lambda_area"])
                 d.temperature = float(r["temperature"])
+                d.cpm_range = int(r.get("cpm_range", 1))
         ctx = C.c_void_p()
         check(lib().spinmc_create(descs, n, int(seed), 1 if init else 0, sh, C.byref(ctx)))
         self._keep = []

@@ -125,3 +125,30 @@ def test_dmc_sizes_and_validation_without_a_device(L):
     assert L.spinmc_dmc_discretize(4, 1, None, float("nan"), 1, None) == -1
     assert L.spinmc_dmc_discretize(4, None, None, 1.0, 1, None) == -1
     assert L.spinmc_dmc_discretize(0, None, None, 1.0, None, None) == 0
+
+
+def test_cpm_neighbourhood_validation_without_a_device(L):
+    """cpm_range outside {0, 1, 2}, the 5x5 neighbourhood on widths that are
+    not multiples of 6, and mixed ranges in one context are rejected before
+    any device call."""
+    import numpy as np
+    from paper_2304_01772_amd import _lib
+    J = np.zeros((2, 2), np.float32)
+    ct = np.array([0, 1], np.int8)
+    A = np.array([0, 4], np.int32)
+
+    def descs(*specs):
+        d = (_lib.ReplicaDesc * len(specs))()
+        for i, (Lx, Ly, rng) in enumerate(specs):
+            d[i].model, d[i].Lx, d[i].Ly, d[i].q, d[i].rid = 2, Lx, Ly, 1, i
+            d[i].n_types = 2
+            d[i].adhesion = J.ctypes.data_as(C.POINTER(C.c_float))
+            d[i].cell_type = ct.ctypes.data_as(C.POINTER(C.c_int8))
+            d[i].target_area = A.ctypes.data_as(C.POINTER(C.c_int32))
+            d[i].lambda_area, d[i].temperature, d[i].cpm_range = 1.0, 2.0, rng
+        return d
+    ctx = C.c_void_p()
+    for specs in [((12, 12, 3),), ((12, 12, -1),), ((8, 12, 2),), ((12, 16, 2),),
+                  ((12, 12, 2), (12, 12, 1))]:
+        assert L.spinmc_create(descs(*specs), len(specs), 1, 0, None, C.byref(ctx)) == -1, specs
+        assert not ctx.value

@@ -142,3 +142,72 @@ def test_paper_cell_sorting_setting(S):
     assert end[:, 4].mean() < 0.75 * start[:, 4].mean()
     assert end[:, 2].mean() > start[:, 2].mean()  # the dark cells now face the medium
     smp.close()
+
+
+def _rep5(ids, J, ctype, A, lam, T, rid):
+    d = _rep(ids, J, ctype, A, lam, T, rid)
+    d["cpm_range"] = 2
+    return d
+
+
+# the 5x5 neighbourhood: 3x3 sublattice, one site per lane; several tiles
+# (tile_rows rounds down to whole periods of 6 rows) and widths that are not
+# multiples of 8
+@pytest.mark.parametrize("shape,n_cells,Jname,lam,T,tile_rows", [
+    ((6, 6), 3, "sorting", 1.0, 10.0, 0),
+    ((12, 18), 8, "halves", 0.5, 3.0, 6),
+    ((36, 48), 20, "sorting", 2.0, 25.0, 8),
+    ((66, 60), 40, "sorting", 1.0, 10.0, 0),
+])
+def test_cpm5_matches_oracle(S, shape, n_cells, Jname, lam, T, tile_rows):
+    J = JS[Jname]
+    reps, cases = [], []
+    for rid in range(3):
+        ids, ctype, A = _random_case(100 * rid + n_cells, shape, n_cells)
+        cases.append((ids, ctype, A))
+        reps.append(_rep5(ids, J, ctype, A, lam, T, rid))
+    smp = S(reps, 77, init=False)
+    if tile_rows:
+        smp.set_schedule(mode="stream", tile_rows=tile_rows)
+    for r, (ids, _, _) in enumerate(cases):
+        smp.set_state(r, ids)
+    n = 4
+    st = smp.sweep(n, 1).cpu().numpy()
+    for r, (ids, ctype, A) in enumerate(cases):
+        want, area, ost = orc.cpm_run(ids, J, ctype, A, lam, T, 77, r, 0, n, 1, nrange=2)
+        assert np.array_equal(smp.get_state(r), want), r
+        assert np.array_equal(st[:, r], ost), r
+    stats, _ = smp.measure()
+    for r in range(3):
+        got = smp.get_state(r)
+        assert np.array_equal(stats.cpu().numpy()[r],
+                              orc.cpm_stats(got, J, cases[r][1], cases[r][2], lam, nrange=2))
+    smp.close()
+
+
+def test_paper_setting_with_the_second_shell(S):
+    """The paper's aggregate in a 66 x 66 medium with the 5x5 neighbourhood:
+    300 Monte Carlo steps bit-exact with the oracle for two replicas.  With
+    Table 2's adhesion summed over 24 neighbours the boundary cost outweighs
+    the lambda = 1 area term at k_B T = 8 and the cells dissolve into the
+    medium (the oracle shows the same), which supports reading the paper's
+    setting with the 3x3 neighbourhood."""
+    ids, types, A, J, prm = synth.cpm_paper_aggregate(n_rep=8, L=66)
+    reps = [_rep5(ids[r], J, types[r], A, prm["lambda_area"], prm["temperature"], r)
+            for r in range(ids.shape[0])]
+    smp = S(reps, prm["seed"], init=False)
+    for r in range(len(reps)):
+        smp.set_state(r, ids[r])
+    start, _ = smp.measure()
+    start = start.cpu().numpy()
+    n = 300
+    st = smp.sweep(n, 100).cpu().numpy()
+    for r in (0, 5):
+        want, _, ost = orc.cpm_run(ids[r], J, types[r], A, prm["lambda_area"],
+                                   prm["temperature"], prm["seed"], r, 0, n, 100, nrange=2)
+        assert np.array_equal(smp.get_state(r), want)
+        assert np.array_equal(st[:, r], ost)
+    assert start[:, 1].mean() > 30
+    for r in range(len(reps)):
+        assert len(np.unique(smp.get_state(r))) < 37  # cells have vanished
+    smp.close()
