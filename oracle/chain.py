@@ -72,6 +72,13 @@ def lib():
                               C.c_double, C.c_uint64, C.c_uint32, C.c_uint64, C.c_int, C.c_int,
                               _i32p, _i32p, C.c_void_p]
     L.orc_cpm_run.restype = C.c_int
+    L.orc_tri_table.argtypes = [C.c_float, C.c_float, C.c_double, _u64p]
+    L.orc_tri_table.restype = C.c_int
+    L.orc_tri_stats.argtypes = [C.c_int, C.c_int, _i8p, _i32p]
+    L.orc_tri_stats.restype = None
+    L.orc_tri_run.argtypes = [C.c_int, C.c_int, C.c_float, C.c_float, C.c_double, C.c_uint64,
+                              C.c_uint32, C.c_uint64, C.c_int, C.c_int, _i8p, C.c_void_p]
+    L.orc_tri_run.restype = C.c_int
     L.orc_cpm_stats_r.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _f32p, _i8p, _i32p,
                                   C.c_float, _i32p, C.c_int, _i32p]
     L.orc_cpm_stats_r.restype = None
@@ -180,6 +187,33 @@ def potts_run(s, q, J, h, beta, seed, rid, t0, n_sweeps, record_every=0):
     rc = lib().orc_potts_run(s.shape[1], s.shape[0], q, J, h, beta, seed, rid, t0, n_sweeps,
                              record_every, s, stats.ctypes.data)
     _check(rc, "potts_run")
+    return s, stats[:n_rec]
+
+
+def tri_table(J, h, beta):
+    """Thresholds of the triangular-lattice Ising flip, idx = 7 [s > 0] +
+    (S6 + 6) / 2."""
+    T = np.zeros(14, np.uint64)
+    _check(lib().orc_tri_table(J, h, beta, T), "tri_table")
+    return T
+
+
+def tri_stats(sigma):
+    """[M, Bh, Bv, Bd, 0...] of a triangular-lattice state (int8 [Ly, Lx])."""
+    sigma = np.ascontiguousarray(sigma, np.int8)
+    out = np.zeros(8, np.int32)
+    lib().orc_tri_stats(sigma.shape[1], sigma.shape[0], sigma, out)
+    return out
+
+
+def tri_run(sigma, J, h, beta, seed, rid, t0, n_sweeps, record_every=0):
+    """Triangular-lattice Ising chain on a copy: (state, stats[n_rec, 8])."""
+    s = np.ascontiguousarray(sigma, np.int8).copy()
+    n_rec = n_sweeps // record_every if record_every > 0 else 0
+    stats = np.zeros((max(n_rec, 1), 8), np.int32)
+    rc = lib().orc_tri_run(s.shape[1], s.shape[0], J, h, beta, seed, rid, t0, n_sweeps,
+                           record_every, s, stats.ctypes.data)
+    _check(rc, "tri_run")
     return s, stats[:n_rec]
 
 

@@ -212,6 +212,91 @@ int orc_ising_run(int Lx, int Ly, float Jx, float Jy, float h, double beta, uint
 }
 
 /* ------------------------------------------------------------------------ */
+/* Triangular-lattice Ising (the triangular kernels of the Methods): sites on
+ * an Ly x Lx array, the six neighbours (y, x-1), (y, x+1), (y-1, x),
+ * (y+1, x), (y-1, x+1), (y+1, x-1) (periodic), one coupling J for every
+ * bond: H = -J sum_bonds s s' - h sum s.  Three colours c = (x + 2y) mod 3
+ * (no bond joins two sites of one colour; Lx and Ly multiples of 3), passes
+ * p = 3t + c; within-colour index k = y Lx/3 + x/3; W = word k & 3 of the
+ * main block (k >> 2, p, rid, 0) as a whole 32-bit word; accept the flip iff
+ * W < T(class), class idx = 7 [s > 0] + (S6 + 6) / 2 with S6 the sum of the
+ * six neighbours, dE = 2 s (J S6 + h).                                      */
+int orc_tri_table(float J, float h, double beta, uint64_t T[14])
+{
+    int si, a;
+    if (!(beta >= 0.0) || !isfinite(beta) || !isfinite(J) || !isfinite(h))
+        return ORC_EINVAL;
+    for (si = 0; si < 2; si++)
+        for (a = 0; a < 7; a++) {
+            double s = si ? 1.0 : -1.0;
+            double u = (double)J * (double)(2 * a - 6);
+            u = u + (double)h;
+            T[7 * si + a] = threshold_from_dE(2.0 * s * u, beta);
+        }
+    return ORC_OK;
+}
+
+/* M, Bh = sum s(y,x)s(y,x+1), Bv = sum s(y,x)s(y+1,x), Bd = sum s(y,x)s(y+1,x-1). */
+void orc_tri_stats(int Lx, int Ly, const int8_t *sg, int32_t out[8])
+{
+    int32_t M = 0, Bh = 0, Bv = 0, Bd = 0;
+    int y, x;
+    for (y = 0; y < Ly; y++)
+        for (x = 0; x < Lx; x++) {
+            int s = sg[y * Lx + x];
+            M += s;
+            Bh += s * sg[y * Lx + wrap(x + 1, Lx)];
+            Bv += s * sg[wrap(y + 1, Ly) * Lx + x];
+            Bd += s * sg[wrap(y + 1, Ly) * Lx + wrap(x - 1, Lx)];
+        }
+    memset(out, 0, 8 * sizeof(int32_t));
+    out[0] = M;
+    out[1] = Bh;
+    out[2] = Bv;
+    out[3] = Bd;
+}
+
+int orc_tri_run(int Lx, int Ly, float J, float h, double beta, uint64_t seed, uint32_t rid,
+                uint64_t t0, int n_sweeps, int record_every, int8_t *sg, int32_t *stats)
+{
+    uint64_t T[14];
+    uint32_t key[2], w[4];
+    int i, c, y, x, rec = 0;
+    if (Lx < 3 || Ly < 3 || Lx % 3 != 0 || Ly % 3 != 0 || n_sweeps < 0 || record_every < 0)
+        return ORC_EINVAL;
+    if (orc_tri_table(J, h, beta, T) != ORC_OK)
+        return ORC_EINVAL;
+    seed_key(seed, key);
+    for (i = 0; i < n_sweeps; i++) {
+        uint64_t t = t0 + (uint64_t)i;
+        for (c = 0; c < 3; c++) {
+            uint32_t p = (uint32_t)(3 * t + (uint64_t)c);
+            for (y = 0; y < Ly; y++)
+                for (x = 0; x < Lx; x++) {
+                    if ((x + 2 * y) % 3 != c)
+                        continue;
+                    uint32_t k = (uint32_t)(y * (Lx / 3) + x / 3);
+                    draw(k >> 2, p, rid, TAG_MAIN, key, w);
+                    uint32_t W = w[k & 3u];
+                    int s = sg[y * Lx + x];
+                    int S6 = sg[y * Lx + wrap(x - 1, Lx)] + sg[y * Lx + wrap(x + 1, Lx)] +
+                             sg[wrap(y - 1, Ly) * Lx + x] + sg[wrap(y + 1, Ly) * Lx + x] +
+                             sg[wrap(y - 1, Ly) * Lx + wrap(x + 1, Lx)] +
+                             sg[wrap(y + 1, Ly) * Lx + wrap(x - 1, Lx)];
+                    int idx = 7 * (s > 0) + (S6 + 6) / 2;
+                    if ((uint64_t)W < T[idx])
+                        sg[y * Lx + x] = (int8_t)(-s);
+                }
+        }
+        if (record_every > 0 && ((i + 1) % record_every) == 0 && stats) {
+            orc_tri_stats(Lx, Ly, sg, stats + 8 * rec);
+            rec++;
+        }
+    }
+    return rec;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Potts, Eq. (2), H = -J sum delta - h sum s.  For a proposal s -> s':
  * dn = #{nbrs == s'} - #{nbrs == s} in [-4,4], ds = s'-s;
  * dE = -(J dn + h ds); idx = (dn+4)(2q-1) + (ds + q - 1).                   */

@@ -37,6 +37,30 @@ def ising_bond_sums(states):
     return M, Bx, By
 
 
+def tri_bond_sums(states):
+    """M and the bond sums of the triangular lattice's three directions:
+    (y, x)-(y, x+1), (y, x)-(y+1, x), (y, x)-(y+1, x-1)."""
+    s = states.astype(np.int64)
+    M = s.sum(axis=(1, 2))
+    Bh = (s * np.roll(s, -1, axis=2)).sum(axis=(1, 2))
+    Bv = (s * np.roll(s, -1, axis=1)).sum(axis=(1, 2))
+    Bd = (s * np.roll(np.roll(s, -1, axis=1), 1, axis=2)).sum(axis=(1, 2))
+    return M, Bh, Bv, Bd
+
+
+def tri_exact(Ly, Lx, J, h, beta):
+    """Exact <e> and <|m|> of the triangular-lattice Ising torus by
+    enumeration, H = -J (Bh + Bv + Bd) - h M."""
+    st = ising_states(Ly, Lx)
+    M, Bh, Bv, Bd = tri_bond_sums(st)
+    N = Ly * Lx
+    E = -(J * (Bh + Bv + Bd) + h * M)
+    a = -beta * E
+    w = np.exp(a - a.max())
+    p = w / w.sum()
+    return dict(e=float((p * E).sum() / N), absm=float((p * np.abs(M)).sum() / N))
+
+
 def ising_exact(Ly, Lx, Jx, Jy, h, beta):
     """Exact <e>, <|m|>, <m^2>, ln Z and Boltzmann weights by enumeration."""
     st = ising_states(Ly, Lx)
