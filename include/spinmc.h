@@ -38,7 +38,7 @@ extern "C" {
 
 typedef struct spinmc_ctx spinmc_ctx;
 
-enum spinmc_model { SPINMC_ISING = 0, SPINMC_POTTS = 1, SPINMC_CPM = 2 };
+enum spinmc_model { SPINMC_ISING = 0, SPINMC_POTTS = 1, SPINMC_CPM = 2, SPINMC_ISING_TRI = 3 };
 
 enum spinmc_status {
     SPINMC_OK = 0,
@@ -57,6 +57,9 @@ enum spinmc_status {
  *   Potts  [Nx, Ny, S, nmax, 0...]  equal horizontal / vertical bonds, sum
  *                              of labels, population of the largest state
  *                              (Eq. (2))
+ *   Triangular Ising [M, Bh, Bv, Bd, 0...]  Bh = sum s(y,x) s(y,x+1),
+ *                              Bv = sum s(y,x) s(y+1,x), Bd = sum s(y,x)
+ *                              s(y+1,x-1)
  *   CPM    [b0..b9, Hlo, Hhi, 0...] von Neumann bonds between different ids
  *                              by unordered type pair (a <= b, index
  *                              a*n_types - a(a-1)/2 + (b - a)), and the
@@ -64,6 +67,17 @@ enum spinmc_status {
  *                              of the replica's neighbourhood) times the
  *                              fixed-point scale S as an int64 split in two
  *                              int32 words.                                 */
+
+/* Triangular-lattice Ising (the triangular kernels of the Methods;
+ * SPINMC_ISING_TRI): spins on an Ly x Lx array, neighbours (y, x+-1),
+ * (y+-1, x), (y-1, x+1), (y+1, x-1), periodic; one coupling J = Jx (Jy must
+ * equal Jx) for every bond, H = -J sum s s' - h sum s.  Three colours
+ * c = (x + 2y) mod 3, passes p = 3t + c per sweep; the sites of colour c with
+ * within-colour index k = y Lx/3 + x/3 take word k & 3 of Philox block
+ * (k >> 2, p, rid, 0) whole as W and flip iff W < ceil(2^32 exp(-beta dE)),
+ * dE = 2 s (J S6 + h) (always when dE <= 0).  Initial state as for Ising.
+ * A context holds only triangular replicas; its schedule is ignored and
+ * spinmc_autotune returns it unchanged; spinmc_grad is not available.      */
 
 /* Hamiltonian parameters of one replica (Eq. (1), Eq. (2), Eq. (3)).
  * Signs: Ising H = -Jx sum_h s s' - Jy sum_v s s' - h sum s with s = +-1;
@@ -75,7 +89,7 @@ enum spinmc_status {
  *         medium).  The descriptor is deep-copied by spinmc_create.          */
 typedef struct spinmc_replica_desc {
     int32_t model;               /* enum spinmc_model                              */
-    int32_t Lx, Ly;              /* even, >= 2                                      */
+    int32_t Lx, Ly;              /* even, >= 2 (triangular: multiples of 3, >= 3)    */
     int32_t q;                   /* Potts: 2..255; CPM: number of cells n (ids 0..n); Ising: ignored */
     float Jx, Jy, h;             /* couplings and field (Ising, Potts)              */
     double beta;                 /* inverse temperature (Ising, Potts), >= 0         */
@@ -241,7 +255,8 @@ enum spinmc_kernel_kind {
     SPINMC_K_STREAM_ISING = 0,  /* streamed Ising colour pass                 */
     SPINMC_K_RESIDENT = 1,      /* resident multi-sweep kernel (all groups)   */
     SPINMC_K_CPM_PASS = 3,      /* CPM colour pass                            */
-    SPINMC_K_STREAM_POTTS = 4   /* streamed Potts colour pass                 */
+    SPINMC_K_STREAM_POTTS = 4,  /* streamed Potts colour pass                 */
+    SPINMC_K_TRI_PASS = 5       /* triangular-lattice Ising colour pass       */
 };
 int spinmc_profile(spinmc_ctx *ctx, int32_t enable);
 int spinmc_profile_read(spinmc_ctx *ctx, int32_t kind, double *ms_total, int64_t *launches);

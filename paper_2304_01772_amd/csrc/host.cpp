@@ -11,6 +11,8 @@
 #include <map>
 #include <string>
 #include <tuple>
+
+#include "tri_internal.hpp"
 #include <vector>
 
 #include "spinmc.h"
@@ -153,6 +155,9 @@ struct spinmc_ctx {
     // multiple of 8, at most kCpmLdsCells cells per replica)
     bool cpm_quad = false, cpm_lds_reserved = false;
     int cpm_range = 1;  // 1: Moore 3x3, 4 colours; 2: 5x5, 9 colours
+    // triangular-lattice Ising
+    bool tri = false;
+    uint64_t* d_tab64 = nullptr;  // [R][14] thresholds
     int cpm_cell_cap = 0;
     // kernel timing
     bool prof = false;
@@ -216,6 +221,8 @@ void free_all(spinmc_ctx* c) {
     hipFree(c->d_area);
     hipFree(c->d_snap);
     hipFree(c->d_js);
+    hipFree(c->d_tab64);
+    c->d_tab64 = nullptr;
     c->d_ctype = nullptr;
     c->d_target = nullptr;
     c->d_area = nullptr;
@@ -231,8 +238,21 @@ void free_all(spinmc_ctx* c) {
 }
 
 int validate(const spinmc_replica_desc& d, int i, bool& cpm_seen, bool& lat_seen) {
-    if (d.model != SPINMC_ISING && d.model != SPINMC_POTTS && d.model != SPINMC_CPM)
+    if (d.model != SPINMC_ISING && d.model != SPINMC_POTTS && d.model != SPINMC_CPM &&
+        d.model != SPINMC_ISING_TRI)
         return fail(SPINMC_E_INVALID, "replica %d: unknown model %d", i, d.model);
+    if (d.model == SPINMC_ISING_TRI) {
+        if (d.Lx < 3 || d.Ly < 3 || d.Lx % 3 || d.Ly % 3)
+            return fail(SPINMC_E_INVALID,
+                        "replica %d: the triangular lattice needs Lx, Ly multiples of 3", i);
+        if ((int64_t)d.Lx * d.Ly > (1 << 28))
+            return fail(SPINMC_E_INVALID, "replica %d: lattice too large", i);
+        if (!std::isfinite(d.Jx) || !std::isfinite(d.h) || d.Jy != d.Jx)
+            return fail(SPINMC_E_INVALID, "replica %d: triangular J must be finite, Jy == Jx", i);
+        if (!(d.beta >= 0.0) || !std::isfinite(d.beta))
+            return fail(SPINMC_E_INVALID, "replica %d: beta must be finite and >= 0", i);
+        return SPINMC_OK;
+    }
     if (d.Lx < 2 || d.Ly < 2 || (d.Lx & 1) || (d.Ly & 1))
         return fail(SPINMC_E_INVALID, "replica %d: Lx, Ly must be even and >= 2 (got %d x %d)", i,
                     d.Lx, d.Ly);
@@ -384,6 +404,12 @@ int enqueue_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
 int cpm_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes);
 int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes);
 int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
+int create_tri(const spinmc_replica_desc* d, int n, uint64_t seed, int init, void* stream,
+               spinmc_ctx** out);
+int tri_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes);
+int tri_get_state(spinmc_ctx* c, int r, void* host, size_t bytes);
+int tri_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
+int tri_measure(spinmc_ctx* c, int32_t* stats, double* obs);
 int cpm_measure(spinmc_ctx* c, int32_t* stats, double* obs);
 int default_tile_rows(const HostRep& h);
 int effective_mode(const spinmc_ctx* c);
@@ -401,9 +427,20 @@ int spinmc_create(const spinmc_replica_desc* d, int32_t n, uint64_t seed, int32_
     *out = nullptr;
     if (init != 0 && init != 1) return fail(SPINMC_E_INVALID, "create: init must be 0 or 1");
     bool cpm_seen = false, lat_seen = false;
+    int n_tri = 0;
     for (int i = 0; i < n; ++i) {
         int rc = validate(d[i], i, cpm_seen, lat_seen);
         if (rc) return rc;
+        n_tri += d[i].model == SPINMC_ISING_TRI;
+    }
+    if (n_tri > 0 && n_tri < n)
+        return fail(SPINMC_E_UNSUPPORTED,
+                    "create: triangular replicas cannot share a context with other models");
+    if (n_tri == n) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+            return fail(SPINMC_E_DEVICE, "create: no HIP device available");
+        return create_tri(d, n, seed, init, hip_stream, out);
     }
     if (cpm_seen && lat_seen)
         return fail(SPINMC_E_UNSUPPORTED, "create: CPM replicas cannot share a context with Ising/Potts");
@@ -551,6 +588,7 @@ int spinmc_set_state(spinmc_ctx* c, int32_t r, const void* host, size_t bytes) {
     if (c->poisoned) return fail(SPINMC_E_DEVICE, "set_state: context poisoned");
     if (r < 0 || r >= c->R) return fail(SPINMC_E_INVALID, "set_state: replica out of range");
     if (c->cpm) return cpm_set_state(c, r, host, bytes);
+    if (c->tri) return tri_set_state(c, r, host, bytes);
     const HostRep& h = c->reps[r];
     const int Lx = h.dev.Lx, Ly = h.dev.Ly, W = h.dev.W;
     if (bytes != (size_t)Lx * Ly) return fail(SPINMC_E_INVALID, "set_state: wrong byte count");
@@ -582,6 +620,7 @@ int spinmc_get_state(spinmc_ctx* c, int32_t r, void* host, size_t bytes) {
     if (c->poisoned) return fail(SPINMC_E_DEVICE, "get_state: context poisoned");
     if (r < 0 || r >= c->R) return fail(SPINMC_E_INVALID, "get_state: replica out of range");
     if (c->cpm) return cpm_get_state(c, r, host, bytes);
+    if (c->tri) return tri_get_state(c, r, host, bytes);
     const HostRep& h = c->reps[r];
     const int Lx = h.dev.Lx, Ly = h.dev.Ly, W = h.dev.W;
     if (bytes != (size_t)Lx * Ly) return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
@@ -619,6 +658,8 @@ int spinmc_schedule_sites(const spinmc_ctx* c, int64_t streamed[3], int64_t resi
     for (int m = 0; m < 3; ++m) streamed[m] = resident[m] = 0;
     if (c->cpm) {
         for (const HostRep& h : c->reps) streamed[kModelCpm] += (int64_t)h.dev.Lx * h.dev.Ly;
+    } else if (c->tri) {  // counted with the Ising lattices
+        for (const HostRep& h : c->reps) streamed[kModelIsing] += (int64_t)h.dev.Lx * h.dev.Ly;
     } else {
         const int mode = effective_mode(c);
         for (const HostRep& h : c->reps) {
@@ -662,8 +703,9 @@ int spinmc_sweep(spinmc_ctx* c, int32_t n, int32_t re, void* dev_stats) {
     if ((uint64_t)c->t + (uint64_t)n >= ((uint64_t)1 << 31))
         return fail(SPINMC_E_INVALID, "sweep: sweep counter would exceed 2^31");
     if (n == 0) return SPINMC_OK;
-    int rc = c->cpm ? cpm_sweep(c, n, re, (int32_t*)dev_stats)
-                    : enqueue_sweep(c, n, re, (int32_t*)dev_stats);
+    int rc = c->cpm   ? cpm_sweep(c, n, re, (int32_t*)dev_stats)
+             : c->tri ? tri_sweep(c, n, re, (int32_t*)dev_stats)
+                      : enqueue_sweep(c, n, re, (int32_t*)dev_stats);
     if (rc == SPINMC_OK) c->t += (uint64_t)n;
     return rc;
 }
@@ -673,6 +715,7 @@ int spinmc_measure(spinmc_ctx* c, void* dev_stats, void* dev_obs) {
     if (c->poisoned) return fail(SPINMC_E_DEVICE, "measure: context poisoned");
     int32_t* st = (int32_t*)dev_stats;
     if (c->cpm) return cpm_measure(c, st, (double*)dev_obs);
+    if (c->tri) return tri_measure(c, st, (double*)dev_obs);
     hipError_t e = launch_fill_i32(st, (size_t)c->R * c->width, 0, c->stream);
     SweepArgs a{};
     a.reps = c->d_reps;
@@ -740,6 +783,11 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
     if (!c) return fail(SPINMC_E_INVALID, "autotune: null context");
     if (c->poisoned) return fail(SPINMC_E_DEVICE, "autotune: context poisoned");
     if (trial_sweeps < 1) return fail(SPINMC_E_INVALID, "autotune: trial_sweeps must be >= 1");
+    if (c->tri) {  // one kernel shape: nothing to choose
+        if (chosen) *chosen = c->sched;
+        if (n_tried) *n_tried = 0;
+        return SPINMC_OK;
+    }
     // candidate schedules
     std::vector<spinmc_schedule> cand;
     if (c->cpm) {
@@ -1439,6 +1487,154 @@ int cpm_measure(spinmc_ctx* c, int32_t* stats, double* obs) {
     if (e == hipSuccess) e = launch_cpm_stats(a, c->n_tiles, 0, c->stream);
     if (e == hipSuccess && obs)
         e = launch_observables(c->d_reps, c->R, stats, c->width, obs, c->stream);
+    return check_dev(c, e, "measure");
+}
+
+// ============================================================ triangular Ising
+// Thresholds of the flip for idx = 7 [s > 0] + (S6 + 6) / 2 in FP64 (the
+// Algorithm-1 test; T = 2^32 accepts always).
+void tri_thresholds(const spinmc_replica_desc& d, std::vector<uint64_t>& T) {
+    T.resize(kTriClasses);
+    for (int si = 0; si < 2; ++si)
+        for (int a = 0; a < 7; ++a) {
+            const double s = si ? 1.0 : -1.0;
+            double u = (double)d.Jx * (double)(2 * a - 6);
+            u = u + (double)d.h;
+            const double dE = 2.0 * s * u;
+            T[7 * si + a] = dE <= 0.0 ? ((uint64_t)1 << 32)
+                                      : (uint64_t)std::ceil(std::ldexp(std::exp(-d.beta * dE), 32));
+        }
+}
+
+TriArgs tri_args(spinmc_ctx* c, int32_t* stats) {
+    TriArgs a{};
+    a.reps = c->d_reps;
+    a.lat = reinterpret_cast<int8_t*>(c->d_lat);
+    a.tab = c->d_tab64;
+    a.t_base = c->d_t;
+    a.stats = stats;
+    a.key0 = (uint32_t)(c->seed & 0xffffffffu);
+    a.key1 = (uint32_t)(c->seed >> 32);
+    a.R = c->R;
+    a.width = c->width;
+    int mb = 0;
+    for (const HostRep& h : c->reps) mb = std::max(mb, (h.dev.Lx * h.dev.Ly / 3 + 3) / 4);
+    a.max_blocks = mb;
+    a.max_sites = c->max_sites;
+    return a;
+}
+
+int create_tri(const spinmc_replica_desc* d, int n, uint64_t seed, int init, void* stream,
+               spinmc_ctx** out) {
+    spinmc_ctx* c = new spinmc_ctx();
+    hipGetDevice(&c->device);
+    c->stream = (hipStream_t)stream;
+    c->seed = seed;
+    c->R = n;
+    c->width = 8;
+    c->tri = true;
+    c->reps.resize(n);
+    std::vector<uint64_t> tab((size_t)n * kTriClasses);
+    std::vector<RepDev> rd(n);
+    size_t lat_off = 0;
+    for (int i = 0; i < n; ++i) {
+        HostRep& h = c->reps[i];
+        h.d = d[i];
+        tri_thresholds(d[i], h.T);
+        std::copy(h.T.begin(), h.T.end(), tab.begin() + (size_t)i * kTriClasses);
+        RepDev& r = h.dev;
+        r.model = kModelIsingTri;
+        r.Lx = d[i].Lx;
+        r.Ly = d[i].Ly;
+        r.W = d[i].Lx;
+        r.rid = d[i].rid;
+        r.Jx = d[i].Jx;
+        r.Jy = d[i].Jy;
+        r.h = d[i].h;
+        r.beta = d[i].beta;
+        h.lat_bytes = (size_t)r.Lx * r.Ly;
+        r.lat_off = (int64_t)lat_off;
+        lat_off = align_up(lat_off + h.lat_bytes, kAlign);
+        rd[i] = r;
+        c->max_sites = std::max(c->max_sites, r.Lx * r.Ly);
+    }
+    c->lat_bytes = lat_off + 64;
+    auto A = [&](void** p, size_t b) { return hipMalloc(p, std::max<size_t>(b, 16)); };
+    hipError_t e = hipSuccess;
+    if ((e = A((void**)&c->d_lat, c->lat_bytes)) || (e = A((void**)&c->d_reps, sizeof(RepDev) * n)) ||
+        (e = A((void**)&c->d_tab64, sizeof(uint64_t) * tab.size())) ||
+        (e = A((void**)&c->d_t, sizeof(uint64_t)))) {
+        free_all(c);
+        delete c;
+        hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? SPINMC_E_NOMEM : SPINMC_E_DEVICE,
+                    "create: device allocation failed: %s", hipGetErrorString(e));
+    }
+    const uint64_t zero = 0;
+    if ((e = hipMemcpy(c->d_reps, rd.data(), sizeof(RepDev) * n, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_tab64, tab.data(), sizeof(uint64_t) * tab.size(),
+                       hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_t, &zero, sizeof zero, hipMemcpyHostToDevice))) {
+        free_all(c);
+        delete c;
+        return fail(SPINMC_E_DEVICE, "create: upload failed: %s", hipGetErrorString(e));
+    }
+    // init = 0: every spin -1 (as for the square lattice); init = 1: the init stream
+    e = hipMemset(c->d_lat, 0xFF, c->lat_bytes);
+    if (e == hipSuccess && init) {
+        TriArgs a = tri_args(c, nullptr);
+        e = launch_tri_init(a, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e != hipSuccess) {
+        free_all(c);
+        delete c;
+        return fail(SPINMC_E_DEVICE, "create: init failed: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return SPINMC_OK;
+}
+
+int tri_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes) {
+    const HostRep& h = c->reps[r];
+    if (bytes != (size_t)h.dev.Lx * h.dev.Ly) return fail(SPINMC_E_INVALID, "set_state: wrong byte count");
+    const int8_t* v = (const int8_t*)host;
+    for (size_t i = 0; i < bytes; ++i)
+        if (v[i] != 1 && v[i] != -1) return fail(SPINMC_E_INVALID, "set_state: Ising spins must be +-1");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(c->d_lat + h.dev.lat_off, host, bytes, hipMemcpyHostToDevice);
+    return check_dev(c, e, "set_state");
+}
+
+int tri_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
+    const HostRep& h = c->reps[r];
+    if (bytes != (size_t)h.dev.Lx * h.dev.Ly) return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(host, c->d_lat + h.dev.lat_off, bytes, hipMemcpyDeviceToHost);
+    return check_dev(c, e, "get_state");
+}
+
+int tri_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
+    TriArgs a = tri_args(c, stats);
+    hipError_t e = hipSuccess;
+    const int n_rec = re > 0 ? n / re : 0;
+    if (n_rec > 0) e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        for (int col = 0; col < 3 && e == hipSuccess; ++col)
+            e = timed(c, SPINMC_K_TRI_PASS, [&] { return launch_tri_pass(a, col, i, c->stream); },
+                      c->stream);
+        if (e == hipSuccess && re > 0 && ((i + 1) % re) == 0)
+            e = launch_tri_stats(a, (i + 1) / re - 1, c->stream);
+    }
+    if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)n, c->stream);
+    return check_dev(c, e, "sweep");
+}
+
+int tri_measure(spinmc_ctx* c, int32_t* stats, double* obs) {
+    TriArgs a = tri_args(c, stats);
+    hipError_t e = launch_fill_i32(stats, (size_t)c->R * c->width, 0, c->stream);
+    if (e == hipSuccess) e = launch_tri_stats(a, 0, c->stream);
+    if (e == hipSuccess && obs) e = launch_tri_observables(a, obs, c->stream);
     return check_dev(c, e, "measure");
 }
 

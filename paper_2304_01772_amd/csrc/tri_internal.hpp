@@ -1,0 +1,31 @@
+// Internal declarations of the triangular-lattice Ising kernels.  Not part
+// of the C ABI.
+#pragma once
+#include "spinmc_internal.hpp"
+
+namespace spinmc {
+
+constexpr int kModelIsingTri = 3;
+constexpr int kTriClasses = 14;  // 7 [s > 0] + (S6 + 6) / 2
+
+struct TriArgs {
+    const RepDev* reps;       // Lx, Ly, rid, lat_off (bytes), Jx = J, h
+    int8_t* lat;              // natural row-major int8 spins, +-1
+    const uint64_t* tab;      // [R][14] thresholds (2^32 = always)
+    const uint64_t* t_base;   // device sweep counter
+    int32_t* stats;           // [rows][R][width]
+    uint32_t key0, key1;
+    int32_t R, width;
+    int32_t max_blocks;       // max over replicas of ceil(Lx Ly / 12)
+    int32_t max_sites;
+};
+
+hipError_t launch_tri_init(const TriArgs& a, hipStream_t s);
+// Colour pass c of sweep *t_base + sweep_off for every replica.
+hipError_t launch_tri_pass(const TriArgs& a, int c, int sweep_off, hipStream_t s);
+// Adds [M, Bh, Bv, Bd] of every replica to stats row rec_row (zeroed first
+// by the caller).
+hipError_t launch_tri_stats(const TriArgs& a, int rec_row, hipStream_t s);
+hipError_t launch_tri_observables(const TriArgs& a, double* obs, hipStream_t s);
+
+}  // namespace spinmc

@@ -1,0 +1,145 @@
+// Triangular-lattice Ising (the triangular kernels of the Methods): the
+// checkerboard Metropolis chain of Algorithm 1 on the six-neighbour lattice.
+//
+// Sites sit on an Ly x Lx array (int8 spins, natural row-major); the
+// neighbours of (y, x) are (y, x+-1), (y+-1, x), (y-1, x+1) and (y+1, x-1)
+// (periodic), one coupling J for every bond, H = -J sum s s' - h sum s.
+// Three colours c = (x + 2y) mod 3 -- no bond joins two sites of one colour
+// when Lx and Ly are multiples of 3 -- make a sweep of three passes
+// p = 3t + c.  The sites of colour c in row y are x = 3i + (c + y) mod 3; the
+// within-colour index k = y Lx/3 + i selects word k & 3 of Philox4x32-10
+// block (k >> 2, p, rid, 0), used whole as W; the flip is accepted iff
+// W < T[7 [s > 0] + (S6 + 6) / 2] with the FP64 host thresholds
+// T = ceil(2^32 exp(-beta 2 s (J S6 + h))) (2^32 when that change is <= 0).
+// A lane takes the four sites of one Philox block.
+#include "tri_internal.hpp"
+
+namespace spinmc {
+
+namespace {
+constexpr uint32_t kTriTagMain = 0u, kTriTagInit = 2u;
+
+__device__ __forceinline__ int wrapt(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+}  // namespace
+
+// Initial spins from the init stream of the Ising model: site n = y Lx + x
+// takes word n & 3 of block (n >> 2, 0, rid, 2); +1 iff it is < 2^31.
+__global__ void __launch_bounds__(256) k_tri_init(TriArgs a) {
+    const RepDev D = a.reps[blockIdx.y];
+    const int n = D.Lx * D.Ly;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (4 * b >= n) return;
+    uint32_t w[4];
+    philox4x32_10((uint32_t)b, 0u, D.rid, kTriTagInit, a.key0, a.key1, w);
+    int8_t* lat = a.lat + D.lat_off;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (4 * b + u < n) lat[4 * b + u] = w[u] < 0x80000000u ? (int8_t)1 : (int8_t)-1;
+}
+
+__global__ void __launch_bounds__(256) k_tri_pass(TriArgs a, int c, int sweep_off) {
+    __shared__ uint64_t lt[kTriClasses];
+    const int r = blockIdx.y;
+    if (threadIdx.x < kTriClasses) lt[threadIdx.x] = a.tab[(size_t)r * kTriClasses + threadIdx.x];
+    __syncthreads();
+    const RepDev D = a.reps[r];
+    const int Lx = D.Lx, Ly = D.Ly, W3 = Lx / 3;
+    const int nk = Ly * W3;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (4 * b >= nk) return;
+    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
+    const uint32_t p = (uint32_t)(3 * t + (uint64_t)c);
+    uint32_t w[4];
+    philox4x32_10((uint32_t)b, p, D.rid, kTriTagMain, a.key0, a.key1, w);
+    int8_t* lat = a.lat + D.lat_off;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int k = 4 * b + u;
+        if (k >= nk) break;
+        const int y = k / W3;
+        const int x = 3 * (k - y * W3) + (c + y) % 3;
+        const int yu = wrapt(y - 1, Ly), yd = wrapt(y + 1, Ly);
+        const int xl = wrapt(x - 1, Lx), xr = wrapt(x + 1, Lx);
+        const int8_t* row = lat + (size_t)y * Lx;
+        const int8_t* up = lat + (size_t)yu * Lx;
+        const int8_t* dn = lat + (size_t)yd * Lx;
+        const int s = row[x];
+        const int S6 = row[xl] + row[xr] + up[x] + dn[x] + up[xr] + dn[xl];
+        const int idx = 7 * (s > 0) + (S6 + 6) / 2;
+        if ((uint64_t)w[u] < lt[idx]) lat[(size_t)y * Lx + x] = (int8_t)(-s);
+    }
+}
+
+// [M, Bh, Bv, Bd]: wave sums of each lane's sites, one atomic per wave and
+// statistic (integers, so the order does not matter).
+__global__ void __launch_bounds__(256) k_tri_stats(TriArgs a, int rec_row) {
+    const int r = blockIdx.y;
+    const RepDev D = a.reps[r];
+    const int Lx = D.Lx, Ly = D.Ly, n = Lx * Ly;
+    const int8_t* lat = a.lat + D.lat_off;
+    int M = 0, Bh = 0, Bv = 0, Bd = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int y = i / Lx, x = i - y * Lx;
+        const int yd = wrapt(y + 1, Ly), xr = wrapt(x + 1, Lx), xl = wrapt(x - 1, Lx);
+        const int s = lat[i];
+        M += s;
+        Bh += s * lat[(size_t)y * Lx + xr];
+        Bv += s * lat[(size_t)yd * Lx + x];
+        Bd += s * lat[(size_t)yd * Lx + xl];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        M += __shfl_xor(M, o);
+        Bh += __shfl_xor(Bh, o);
+        Bv += __shfl_xor(Bv, o);
+        Bd += __shfl_xor(Bd, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        int32_t* row = a.stats + ((size_t)rec_row * a.R + r) * a.width;
+        atomicAdd(&row[0], M);
+        atomicAdd(&row[1], Bh);
+        atomicAdd(&row[2], Bv);
+        atomicAdd(&row[3], Bd);
+    }
+}
+
+// (e, |m|, m^2, m) per replica from [M, Bh, Bv, Bd].
+__global__ void k_tri_observables(TriArgs a, double* obs) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.R) return;
+    const RepDev D = a.reps[r];
+    const int32_t* s = a.stats + (size_t)r * a.width;
+    const double N = (double)D.Lx * (double)D.Ly;
+    const double M = s[0];
+    const double H = -((double)D.Jx * ((double)s[1] + (double)s[2] + (double)s[3]) +
+                       (double)D.h * M);
+    double* o = obs + (size_t)r * 4;
+    o[0] = H / N;
+    o[1] = fabs(M) / N;
+    o[2] = (M / N) * (M / N);
+    o[3] = M / N;
+}
+
+hipError_t launch_tri_init(const TriArgs& a, hipStream_t s) {
+    const int nb = (a.max_sites + 3) / 4;
+    hipLaunchKernelGGL(k_tri_init, dim3((nb + 255) / 256, a.R), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_pass(const TriArgs& a, int c, int sweep_off, hipStream_t s) {
+    hipLaunchKernelGGL(k_tri_pass, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s, a, c,
+                       sweep_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_stats(const TriArgs& a, int rec_row, hipStream_t s) {
+    const int per = (a.max_sites + 255) / 256;
+    hipLaunchKernelGGL(k_tri_stats, dim3(per < 64 ? per : 64, a.R), dim3(256), 0, s, a, rec_row);
+    return hipGetLastError();
+}
+
+hipError_t launch_tri_observables(const TriArgs& a, double* obs, hipStream_t s) {
+    hipLaunchKernelGGL(k_tri_observables, dim3((a.R + 127) / 128), dim3(128), 0, s, a, obs);
+    return hipGetLastError();
+}
+
+}  // namespace spinmc

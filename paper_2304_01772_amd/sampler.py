@@ -9,7 +9,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import ISING, POTTS, CPM, ReplicaDesc, Schedule, check, lib
+from ._lib import ISING, ISING_TRI, POTTS, CPM, ReplicaDesc, Schedule, check, lib
 
 __all__ = ["Sampler", "ISING", "POTTS", "CPM", "MODES"]
 
@@ -27,8 +27,9 @@ class Sampler:
     """A batch of independent replicas (Methods, batched tensors) behind one
     libspinmc context.
 
-    ``replicas``: sequence of dicts with keys model, Lx, Ly and the model's
-    parameters (q, Jx, Jy, h, beta, rid; CPM: n_cells as q, n_types,
+    ``replicas``: sequence of dicts with keys model (0 Ising, 1 Potts, 2 CPM,
+    3 triangular-lattice Ising), Lx, Ly and the model's parameters (q, Jx,
+    Jy, h, beta, rid; CPM: n_cells as q, n_types,
     adhesion, cell_type, target_area, lambda_area, temperature and optionally
     cpm_range, 1 for the Moore 3x3 neighbourhood or 2 for 5x5).
     """
@@ -91,7 +92,7 @@ class Sampler:
 
     def _elem(self, r):
         m = self.replicas[r].get("model", ISING)
-        return {ISING: np.int8, POTTS: np.uint8, CPM: np.int32}[m]
+        return {ISING: np.int8, ISING_TRI: np.int8, POTTS: np.uint8, CPM: np.int32}[m]
 
     def get_state(self, r):
         rep = self.replicas[r]
@@ -154,7 +155,7 @@ class Sampler:
         return means, grads, dth
 
     # ------------------------------------------------------------- timing
-    KERNELS = {"stream_ising": 0, "resident": 1, "cpm_pass": 3, "stream_potts": 4}
+    KERNELS = {"stream_ising": 0, "resident": 1, "cpm_pass": 3, "stream_potts": 4, "tri_pass": 5}
 
     def profile(self, enable=True):
         check(lib().spinmc_profile(self.ctx, 1 if enable else 0))

@@ -58,6 +58,9 @@ def _desc(**kw):
     (dict(Lx=7), -1), (dict(Ly=0), -1), (dict(model=5), -1), (dict(beta=-1.0), -1),
     (dict(beta=float("nan")), -1), (dict(model=1, q=1), -1), (dict(model=1, q=300), -1),
     (dict(model=1, q=200), -2), (dict(model=1, q=3, Jy=0.5), -2), (dict(h=float("inf")), -1),
+    # triangular lattice: multiples of 3, one coupling
+    (dict(model=3), -1), (dict(model=3, Lx=9, Ly=10), -1), (dict(model=3, Lx=9, Ly=9, Jy=0.5), -1),
+    (dict(model=3, Lx=9, Ly=9, beta=-1.0), -1),
 ])
 def test_validation_precedes_device(L, kw, code):
     ctx = C.c_void_p()

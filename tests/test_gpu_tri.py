@@ -1,0 +1,74 @@
+"""GPU parity of the triangular-lattice Ising chain (six neighbours, three
+colours) against the oracle: the initial state, the states and recorded
+statistics of whole runs bit-exact, and the observables."""
+import numpy as np
+import pytest
+
+from oracle import chain as orc
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _rep(Ly, Lx, J, h, beta, rid):
+    return dict(model=3, Lx=Lx, Ly=Ly, Jx=J, Jy=J, h=h, beta=beta, rid=rid)
+
+
+# 3 x 3 (smallest), row counts with k-blocks across rows, several workgroups
+# per replica with a ragged tail (93 x 99: 3069 blocks of 4 sites per colour)
+@pytest.mark.parametrize("shapes", [
+    [(3, 3), (6, 9), (9, 6)],
+    [(12, 15), (3, 30)],
+    [(93, 99), (30, 33)],
+])
+def test_tri_runs_match_oracle(shapes):
+    from paper_2304_01772_amd.sampler import Sampler
+    params = [(0.9, 0.05, 0.3), (-1.0, 0.0, 0.8), (1.0, -0.2, 0.2736)]
+    reps = []
+    for i, (Ly, Lx) in enumerate(shapes):
+        J, h, beta = params[i % len(params)]
+        reps.append(_rep(Ly, Lx, J, h, beta, 10 + i))
+    seed = 0x5EED_1234_5678
+    smp = Sampler(reps, seed, init=True)
+    init = [smp.get_state(r) for r in range(len(reps))]
+    for r, (Ly, Lx) in enumerate(shapes):
+        want = orc.ising_init(Lx, Ly, seed, 10 + r).reshape(Ly, Lx)
+        assert np.array_equal(init[r], want), r
+    n, every = 7, 1
+    st = smp.sweep(n, every).cpu().numpy()
+    st2 = smp.sweep(5, 5).cpu().numpy()  # resumes at sweep counter 7
+    stats, obs = smp.measure()
+    stats, obs = stats.cpu().numpy(), obs.cpu().numpy()
+    for r, (Ly, Lx) in enumerate(shapes):
+        J, h, beta = params[r % len(params)]
+        s1, ost = orc.tri_run(init[r], J, h, beta, seed, 10 + r, 0, n, every)
+        assert np.array_equal(st[:, r], ost), r
+        s2, ost2 = orc.tri_run(s1, J, h, beta, seed, 10 + r, n, 5, 5)
+        assert np.array_equal(smp.get_state(r), s2), r
+        assert np.array_equal(st2[:, r], ost2), r
+        M, Bh, Bv, Bd = orc.tri_stats(s2)[:4]
+        assert np.array_equal(stats[r][:4], [M, Bh, Bv, Bd])
+        N = Ly * Lx
+        e = -(float(np.float32(J)) * float(Bh + Bv + Bd) + float(np.float32(h)) * float(M)) / N
+        assert abs(obs[r, 0] - e) < 1e-12 and abs(obs[r, 1] - abs(M) / N) < 1e-15
+    smp.close()
+
+
+def test_tri_thresholds_and_set_state():
+    from paper_2304_01772_amd.sampler import Sampler
+    reps = [_rep(6, 6, 0.7, 0.1, 0.45, 0), _rep(9, 12, -0.4, 0.0, 1.3, 1)]
+    smp = Sampler(reps, 3, init=False)
+    for r, d in enumerate(reps):
+        T, _ = smp.thresholds(r)
+        assert np.array_equal(T, orc.tri_table(np.float32(d["Jx"]), np.float32(d["h"]),
+                                               d["beta"]))
+        assert np.all(smp.get_state(r) == -1)  # init = 0: every spin -1
+    rng = np.random.default_rng(0)
+    s = rng.choice([-1, 1], size=(9, 12)).astype(np.int8)
+    smp.set_state(1, s)
+    smp.sweep(3)
+    want, _ = orc.tri_run(s, np.float32(-0.4), 0.0, 1.3, 3, 1, 0, 3)
+    assert np.array_equal(smp.get_state(1), want)
+    with pytest.raises(Exception):
+        smp.set_state(1, np.zeros((9, 12), np.int8))
+    smp.close()
