@@ -247,6 +247,39 @@ def cpm_paper_probe(Sampler, torch, n_rep=256, mcs=2000):
     return out
 
 
+def tri_probe(Sampler, torch, n_rep=1024, L=96, sweeps=200):
+    """Triangular-lattice Ising: n_rep replicas of L x L at the exact
+    critical coupling beta_c = ln(3)/4 (J = 1), `sweeps` sweeps of three
+    colour passes; algorithmic HBM bytes 4 per attempt (a pass reads the
+    lattice once, 3 B per attempt of its colour, and writes the colour's
+    sites, 1 B)."""
+    import math
+    reps = [dict(model=3, Lx=L, Ly=L, Jx=1.0, Jy=1.0, h=0.0, beta=math.log(3.0) / 4, rid=r)
+            for r in range(n_rep)]
+    smp = Sampler(reps, 11, init=True)
+    smp.sweep(5)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, smp.stream)
+    smp.sweep(sweeps)
+    e1.record(smp.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    smp.profile(True)
+    smp.sweep(20)
+    torch.cuda.synchronize()
+    kms, nl = smp.profile_read("tri_pass")
+    smp.profile(False)
+    smp.close()
+    sites = n_rep * L * L
+    per_launch = sites / 3
+    avg_s = kms / nl * 1e-3
+    gbs = per_launch * 4 / avg_s / 1e9
+    return {"config": f"{n_rep} triangular replicas of {L}x{L}, beta_c = ln(3)/4, {sweeps} sweeps",
+            "attempts_per_ns": round(sites * sweeps / (ms * 1e6), 1), "kernel": "k_tri_pass",
+            "avg_launch_us": round(avg_s * 1e6, 2), "GBs_algorithmic": round(gbs, 1),
+            "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def grad_probe(Sampler, torch):
     """Differentiation workload: 256 Ising replicas of 128x128 (J ~ U(0.3,
     0.6), h ~ U(-0.05, 0.05), beta 1), 5000 recorded sweeps, then the
@@ -523,6 +556,7 @@ PATH_PROBES = {
     "cpm": lambda S, torch: cpm_probe(S, torch, 50),
     "cpm_paper": lambda S, torch: cpm_paper_probe(S, torch),
     "grad": lambda S, torch: grad_probe(S, torch),
+    "tri": lambda S, torch: tri_probe(S, torch),
     "mlp": lambda S, torch: mlp_probe(torch),
     "dmc": lambda S, torch: dmc_probe(torch),
     "dmc_vs_covariance": lambda S, torch: dmc_vs_covariance_probe(torch),
@@ -662,6 +696,8 @@ def main():
         print(f"# cpm: {paths['cpm_cell_sorting']}", file=sys.stderr, flush=True)
         paths["cpm_paper_setting"] = cpm_paper_probe(Sampler, torch)
         print(f"# cpm paper setting: {paths['cpm_paper_setting']}", file=sys.stderr, flush=True)
+        paths["triangular_ising"] = tri_probe(Sampler, torch)
+        print(f"# triangular: {paths['triangular_ising']}", file=sys.stderr, flush=True)
         paths["covariance_backward"] = grad_probe(Sampler, torch)
         print(f"# grad: {paths['covariance_backward']}", file=sys.stderr, flush=True)
         paths["surrogate_mlp"] = mlp_probe(torch)

@@ -1518,8 +1518,13 @@ TriArgs tri_args(spinmc_ctx* c, int32_t* stats) {
     a.R = c->R;
     a.width = c->width;
     int mb = 0;
-    for (const HostRep& h : c->reps) mb = std::max(mb, (h.dev.Lx * h.dev.Ly / 3 + 3) / 4);
+    bool l12 = true;
+    for (const HostRep& h : c->reps) {
+        mb = std::max(mb, (h.dev.Lx * h.dev.Ly / 3 + 3) / 4);
+        l12 = l12 && h.dev.Lx % 12 == 0;
+    }
     a.max_blocks = mb;
+    a.all_lx12 = l12 ? 1 : 0;
     a.max_sites = c->max_sites;
     return a;
 }

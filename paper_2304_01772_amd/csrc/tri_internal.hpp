@@ -18,6 +18,7 @@ struct TriArgs {
     int32_t R, width;
     int32_t max_blocks;       // max over replicas of ceil(Lx Ly / 12)
     int32_t max_sites;
+    int32_t all_lx12;         // every Lx a multiple of 12: the span kernel
 };
 
 hipError_t launch_tri_init(const TriArgs& a, hipStream_t s);

@@ -70,6 +70,64 @@ __global__ void __launch_bounds__(256) k_tri_pass(TriArgs a, int c, int sweep_of
     }
 }
 
+// Lx a multiple of 12: the four sites of a Philox block lie in one row,
+// x = 12 j + xc + 3u (xc = (c + y) mod 3), inside the 12-byte span
+// [12 j, 12 j + 12) of rows y - 1, y, y + 1, which come in as dwords (plus one
+// halo byte at either end of row y, the right one of row y - 1 and the left
+// one of row y + 1).  The row-y span is written back whole: no other lane
+// writes it during the pass, and the other colours' bytes are unchanged.
+namespace {
+__device__ __forceinline__ int sbyte(const uint32_t (&v)[3], int i) {
+    return (int)(int8_t)(v[i >> 2] >> (8 * (i & 3)));
+}
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_tri_pass12(TriArgs a, int c, int sweep_off) {
+    __shared__ uint64_t lt[kTriClasses];
+    const int r = blockIdx.y;
+    if (threadIdx.x < kTriClasses) lt[threadIdx.x] = a.tab[(size_t)r * kTriClasses + threadIdx.x];
+    __syncthreads();
+    const RepDev D = a.reps[r];
+    const int Lx = D.Lx, Ly = D.Ly, G = Lx / 12;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= Ly * G) return;
+    const int y = b / G, x0 = 12 * (b - y * G);
+    const int xc = (c + y) % 3;
+    const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
+    const int xl = x0 == 0 ? Lx - 1 : x0 - 1, xr = x0 + 12 == Lx ? 0 : x0 + 12;
+    int8_t* lat = a.lat + D.lat_off;
+    const uint32_t* row = reinterpret_cast<const uint32_t*>(lat + (size_t)y * Lx + x0);
+    const uint32_t* up = reinterpret_cast<const uint32_t*>(lat + (size_t)yu * Lx + x0);
+    const uint32_t* dn = reinterpret_cast<const uint32_t*>(lat + (size_t)yd * Lx + x0);
+    uint32_t S[3] = {row[0], row[1], row[2]};
+    const uint32_t U[3] = {up[0], up[1], up[2]};
+    const uint32_t Dn[3] = {dn[0], dn[1], dn[2]};
+    const int sl = lat[(size_t)y * Lx + xl], sr = lat[(size_t)y * Lx + xr];
+    const int ur = lat[(size_t)yu * Lx + xr], dl = lat[(size_t)yd * Lx + xl];
+    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
+    const uint32_t p = (uint32_t)(3 * t + (uint64_t)c);
+    uint32_t w[4];
+    philox4x32_10((uint32_t)b, p, D.rid, 0u, a.key0, a.key1, w);
+    uint32_t flip[3] = {0u, 0u, 0u};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int o = xc + 3 * u;  // offset of the site in the span, 0..11
+        const int s = sbyte(S, o);
+        const int left = o == 0 ? sl : sbyte(S, o - 1);
+        const int right = o == 11 ? sr : sbyte(S, o + 1);
+        const int upr = o == 11 ? ur : sbyte(U, o + 1);
+        const int dnl = o == 0 ? dl : sbyte(Dn, o - 1);
+        const int S6 = left + right + sbyte(U, o) + sbyte(Dn, o) + upr + dnl;
+        const int idx = 7 * (s > 0) + (S6 + 6) / 2;
+        // a flip negates the byte: s -> -s is s ^ 0xFE for s = +-1
+        if ((uint64_t)w[u] < lt[idx]) flip[o >> 2] |= 0xFEu << (8 * (o & 3));
+    }
+    uint32_t* rw = reinterpret_cast<uint32_t*>(lat + (size_t)y * Lx + x0);
+    rw[0] = S[0] ^ flip[0];
+    rw[1] = S[1] ^ flip[1];
+    rw[2] = S[2] ^ flip[2];
+}
+
 // [M, Bh, Bv, Bd]: wave sums of each lane's sites, one atomic per wave and
 // statistic (integers, so the order does not matter).
 __global__ void __launch_bounds__(256) k_tri_stats(TriArgs a, int rec_row) {
@@ -126,8 +184,12 @@ hipError_t launch_tri_init(const TriArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_tri_pass(const TriArgs& a, int c, int sweep_off, hipStream_t s) {
-    hipLaunchKernelGGL(k_tri_pass, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s, a, c,
-                       sweep_off);
+    if (a.all_lx12)
+        hipLaunchKernelGGL(k_tri_pass12, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s,
+                           a, c, sweep_off);
+    else
+        hipLaunchKernelGGL(k_tri_pass, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s, a,
+                           c, sweep_off);
     return hipGetLastError();
 }
 

@@ -20,6 +20,9 @@ def _rep(Ly, Lx, J, h, beta, rid):
     [(3, 3), (6, 9), (9, 6)],
     [(12, 15), (3, 30)],
     [(93, 99), (30, 33)],
+    # every Lx a multiple of 12: the span kernel (one row span per lane)
+    [(12, 12), (6, 24), (9, 36)],
+    [(99, 96), (33, 60), (3, 12)],
 ])
 def test_tri_runs_match_oracle(shapes):
     from paper_2304_01772_amd.sampler import Sampler
