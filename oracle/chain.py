@@ -79,6 +79,12 @@ def lib():
     L.orc_tri_run.argtypes = [C.c_int, C.c_int, C.c_float, C.c_float, C.c_double, C.c_uint64,
                               C.c_uint32, C.c_uint64, C.c_int, C.c_int, _i8p, C.c_void_p]
     L.orc_tri_run.restype = C.c_int
+    L.orc_hc_stats.argtypes = [C.c_int, C.c_int, C.c_int, _i8p, _i32p]
+    L.orc_hc_stats.restype = None
+    L.orc_hc_run.argtypes = [C.c_int, C.c_int, C.c_int, C.c_float, C.c_float, C.c_double,
+                             C.c_uint64, C.c_uint32, C.c_uint64, C.c_int, C.c_int, _i8p,
+                             C.c_void_p]
+    L.orc_hc_run.restype = C.c_int
     L.orc_cpm_stats_r.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _f32p, _i8p, _i32p,
                                   C.c_float, _i32p, C.c_int, _i32p]
     L.orc_cpm_stats_r.restype = None
@@ -214,6 +220,32 @@ def tri_run(sigma, J, h, beta, seed, rid, t0, n_sweeps, record_every=0):
     rc = lib().orc_tri_run(s.shape[1], s.shape[0], J, h, beta, seed, rid, t0, n_sweeps,
                            record_every, s, stats.ctypes.data)
     _check(rc, "tri_run")
+    return s, stats[:n_rec]
+
+
+def hc_init(Lx, Ly, Lz, seed, rid):
+    """Initial state of an Lz x Ly x Lx lattice: the Ising init stream over
+    the natural index n = (z Ly + y) Lx + x."""
+    return ising_init(Lx, Ly * Lz, seed, rid).reshape(Lz, Ly, Lx)
+
+
+def hc_stats(sigma):
+    """[M, Bx, By, Bz, 0...] of an int8 [Lz, Ly, Lx] state."""
+    sigma = np.ascontiguousarray(sigma, np.int8)
+    out = np.zeros(8, np.int32)
+    lib().orc_hc_stats(sigma.shape[2], sigma.shape[1], sigma.shape[0], sigma.reshape(-1), out)
+    return out
+
+
+def hc_run(sigma, J, h, beta, seed, rid, t0, n_sweeps, record_every=0):
+    """Chain / square / cubic Ising chain on a copy of an int8 [Lz, Ly, Lx]
+    state: (state, stats[n_rec, 8])."""
+    s = np.ascontiguousarray(sigma, np.int8).copy()
+    n_rec = n_sweeps // record_every if record_every > 0 else 0
+    stats = np.zeros((max(n_rec, 1), 8), np.int32)
+    rc = lib().orc_hc_run(s.shape[2], s.shape[1], s.shape[0], J, h, beta, seed, rid, t0,
+                          n_sweeps, record_every, s.reshape(-1), stats.ctypes.data)
+    _check(rc, "hc_run")
     return s, stats[:n_rec]
 
 

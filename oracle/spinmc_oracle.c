@@ -297,6 +297,95 @@ int orc_tri_run(int Lx, int Ly, float J, float h, double beta, uint64_t seed, ui
 }
 
 /* ------------------------------------------------------------------------ */
+/* Ising on the chain, square and simple-cubic lattices (the 1D, 2D and 3D
+ * convolutions of the Methods) in one natural layout: an Lz x Ly x Lx array,
+ * n = (z Ly + y) Lx + x; a dimension of extent 1 is absent, every other
+ * extent is even and >= 2; the neighbours are x +- 1 and, where present,
+ * y +- 1 and z +- 1 (periodic), one coupling J for every bond.  Two colours
+ * c = (x + y + z) & 1, passes p = 2t + c; the colour-c site of the pair
+ * (2k, 2k + 1) is the one with within-colour index k, and takes word k & 3 of
+ * the main block (k >> 2, p, rid, 0) whole as W; flip iff W < T(class),
+ * class idx = 7 [s > 0] + (S + 6) / 2 with S the sum of the neighbours,
+ * dE = 2 s (J S + h) -- the same 14-entry table as the triangular lattice.  */
+int orc_hc_table(float J, float h, double beta, uint64_t T[14])
+{
+    return orc_tri_table(J, h, beta, T);
+}
+
+/* M, Bx = sum s(n)s(n+x), By = sum s(n)s(n+y), Bz = sum s(n)s(n+z) (By, Bz
+ * zero for absent dimensions).                                              */
+void orc_hc_stats(int Lx, int Ly, int Lz, const int8_t *sg, int32_t out[8])
+{
+    int32_t M = 0, Bx = 0, By = 0, Bz = 0;
+    int z, y, x;
+    for (z = 0; z < Lz; z++)
+        for (y = 0; y < Ly; y++)
+            for (x = 0; x < Lx; x++) {
+                int s = sg[(z * Ly + y) * Lx + x];
+                M += s;
+                Bx += s * sg[(z * Ly + y) * Lx + wrap(x + 1, Lx)];
+                if (Ly > 1)
+                    By += s * sg[(z * Ly + wrap(y + 1, Ly)) * Lx + x];
+                if (Lz > 1)
+                    Bz += s * sg[(wrap(z + 1, Lz) * Ly + y) * Lx + x];
+            }
+    memset(out, 0, 8 * sizeof(int32_t));
+    out[0] = M;
+    out[1] = Bx;
+    out[2] = By;
+    out[3] = Bz;
+}
+
+static int hc_extent_ok(int L) { return L == 1 || (L >= 2 && L % 2 == 0); }
+
+int orc_hc_run(int Lx, int Ly, int Lz, float J, float h, double beta, uint64_t seed, uint32_t rid,
+               uint64_t t0, int n_sweeps, int record_every, int8_t *sg, int32_t *stats)
+{
+    uint64_t T[14];
+    uint32_t key[2], w[4];
+    int i, c, z, y, x, rec = 0;
+    if (Lx < 2 || Lx % 2 != 0 || !hc_extent_ok(Ly) || !hc_extent_ok(Lz) || n_sweeps < 0 ||
+        record_every < 0)
+        return ORC_EINVAL;
+    if (orc_hc_table(J, h, beta, T) != ORC_OK)
+        return ORC_EINVAL;
+    seed_key(seed, key);
+    for (i = 0; i < n_sweeps; i++) {
+        uint64_t t = t0 + (uint64_t)i;
+        for (c = 0; c < 2; c++) {
+            uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
+            for (z = 0; z < Lz; z++)
+                for (y = 0; y < Ly; y++)
+                    for (x = 0; x < Lx; x++) {
+                        if (((x + y + z) & 1) != c)
+                            continue;
+                        uint32_t n = (uint32_t)((z * Ly + y) * Lx + x);
+                        uint32_t k = n >> 1;
+                        draw(k >> 2, p, rid, TAG_MAIN, key, w);
+                        uint32_t W = w[k & 3u];
+                        int s = sg[n];
+                        int S = sg[(z * Ly + y) * Lx + wrap(x - 1, Lx)] +
+                                sg[(z * Ly + y) * Lx + wrap(x + 1, Lx)];
+                        if (Ly > 1)
+                            S += sg[(z * Ly + wrap(y - 1, Ly)) * Lx + x] +
+                                 sg[(z * Ly + wrap(y + 1, Ly)) * Lx + x];
+                        if (Lz > 1)
+                            S += sg[(wrap(z - 1, Lz) * Ly + y) * Lx + x] +
+                                 sg[(wrap(z + 1, Lz) * Ly + y) * Lx + x];
+                        int idx = 7 * (s > 0) + (S + 6) / 2;
+                        if ((uint64_t)W < T[idx])
+                            sg[n] = (int8_t)(-s);
+                    }
+        }
+        if (record_every > 0 && ((i + 1) % record_every) == 0 && stats) {
+            orc_hc_stats(Lx, Ly, Lz, sg, stats + 8 * rec);
+            rec++;
+        }
+    }
+    return rec;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Potts, Eq. (2), H = -J sum delta - h sum s.  For a proposal s -> s':
  * dn = #{nbrs == s'} - #{nbrs == s} in [-4,4], ds = s'-s;
  * dE = -(J dn + h ds); idx = (dn+4)(2q-1) + (ds + q - 1).                   */
