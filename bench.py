@@ -280,6 +280,36 @@ def tri_probe(Sampler, torch, n_rep=1024, L=96, sweeps=200):
             "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def hc_probe(Sampler, torch, n_rep=256, L=32, sweeps=200):
+    """Simple-cubic Ising: n_rep replicas of L^3 near the 3D critical
+    coupling (beta 0.2216546, J = 1), `sweeps` sweeps of two colour passes;
+    algorithmic HBM bytes 3 per attempt (a pass reads the lattice once, 2 B
+    per attempt of its colour, and writes the colour's sites, 1 B)."""
+    reps = [dict(model=4, Lx=L, Ly=L, Lz=L, Jx=1.0, Jy=1.0, h=0.0, beta=0.2216546, rid=r)
+            for r in range(n_rep)]
+    smp = Sampler(reps, 12, init=True)
+    smp.sweep(5)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, smp.stream)
+    smp.sweep(sweeps)
+    e1.record(smp.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    smp.profile(True)
+    smp.sweep(20)
+    torch.cuda.synchronize()
+    kms, nl = smp.profile_read("hc_pass")
+    smp.profile(False)
+    smp.close()
+    sites = n_rep * L ** 3
+    avg_s = kms / nl * 1e-3
+    gbs = sites / 2 * 3 / avg_s / 1e9
+    return {"config": f"{n_rep} simple-cubic replicas of {L}^3, beta 0.2216546, {sweeps} sweeps",
+            "attempts_per_ns": round(sites * sweeps / (ms * 1e6), 1), "kernel": "k_hc_pass",
+            "avg_launch_us": round(avg_s * 1e6, 2), "GBs_algorithmic": round(gbs, 1),
+            "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def grad_probe(Sampler, torch):
     """Differentiation workload: 256 Ising replicas of 128x128 (J ~ U(0.3,
     0.6), h ~ U(-0.05, 0.05), beta 1), 5000 recorded sweeps, then the
@@ -557,6 +587,7 @@ PATH_PROBES = {
     "cpm_paper": lambda S, torch: cpm_paper_probe(S, torch),
     "grad": lambda S, torch: grad_probe(S, torch),
     "tri": lambda S, torch: tri_probe(S, torch),
+    "hc": lambda S, torch: hc_probe(S, torch),
     "mlp": lambda S, torch: mlp_probe(torch),
     "dmc": lambda S, torch: dmc_probe(torch),
     "dmc_vs_covariance": lambda S, torch: dmc_vs_covariance_probe(torch),
@@ -698,6 +729,8 @@ def main():
         print(f"# cpm paper setting: {paths['cpm_paper_setting']}", file=sys.stderr, flush=True)
         paths["triangular_ising"] = tri_probe(Sampler, torch)
         print(f"# triangular: {paths['triangular_ising']}", file=sys.stderr, flush=True)
+        paths["cubic_ising"] = hc_probe(Sampler, torch)
+        print(f"# cubic: {paths['cubic_ising']}", file=sys.stderr, flush=True)
         paths["covariance_backward"] = grad_probe(Sampler, torch)
         print(f"# grad: {paths['covariance_backward']}", file=sys.stderr, flush=True)
         paths["surrogate_mlp"] = mlp_probe(torch)

@@ -38,7 +38,13 @@ extern "C" {
 
 typedef struct spinmc_ctx spinmc_ctx;
 
-enum spinmc_model { SPINMC_ISING = 0, SPINMC_POTTS = 1, SPINMC_CPM = 2, SPINMC_ISING_TRI = 3 };
+enum spinmc_model {
+    SPINMC_ISING = 0,
+    SPINMC_POTTS = 1,
+    SPINMC_CPM = 2,
+    SPINMC_ISING_TRI = 3,   /* triangular lattice                                  */
+    SPINMC_ISING_HC = 4     /* chain / square / simple cubic, natural layout (Lz)  */
+};
 
 enum spinmc_status {
     SPINMC_OK = 0,
@@ -57,6 +63,8 @@ enum spinmc_status {
  *   Potts  [Nx, Ny, S, nmax, 0...]  equal horizontal / vertical bonds, sum
  *                              of labels, population of the largest state
  *                              (Eq. (2))
+ *   Chain / cubic Ising (SPINMC_ISING_HC) [M, Bx, By, Bz, 0...] bond sums
+ *                              along x, y, z (0 for an absent dimension)
  *   Triangular Ising [M, Bh, Bv, Bd, 0...]  Bh = sum s(y,x) s(y,x+1),
  *                              Bv = sum s(y,x) s(y+1,x), Bd = sum s(y,x)
  *                              s(y+1,x-1)
@@ -77,7 +85,17 @@ enum spinmc_status {
  * (k >> 2, p, rid, 0) whole as W and flip iff W < ceil(2^32 exp(-beta dE)),
  * dE = 2 s (J S6 + h) (always when dE <= 0).  Initial state as for Ising.
  * A context holds only triangular replicas; its schedule is ignored and
- * spinmc_autotune returns it unchanged; spinmc_grad is not available.      */
+ * spinmc_autotune returns it unchanged; spinmc_grad is not available.
+ *
+ * Chain, square and simple-cubic Ising in one natural layout (the 1D, 2D and
+ * 3D convolutions of the Methods; SPINMC_ISING_HC): an Lz x Ly x Lx array,
+ * n = (z Ly + y) Lx + x; Lx even >= 2, Ly and Lz each 1 (absent) or even
+ * >= 2; neighbours x +- 1 and, where present, y +- 1, z +- 1 (periodic); one
+ * coupling J = Jx (Jy must equal Jx).  Two colours c = (x + y + z) & 1,
+ * p = 2t + c; the colour-c site of the pair (2k, 2k + 1) takes word k & 3 of
+ * Philox block (k >> 2, p, rid, 0) whole as W; flip iff
+ * W < ceil(2^32 exp(-beta 2 s (J S + h))), S the neighbour sum.  States are
+ * int8 [Lz][Ly][Lx]; contexts as for the triangular lattice.               */
 
 /* Hamiltonian parameters of one replica (Eq. (1), Eq. (2), Eq. (3)).
  * Signs: Ising H = -Jx sum_h s s' - Jy sum_v s s' - h sum s with s = +-1;
@@ -113,6 +131,7 @@ typedef struct spinmc_replica_desc {
                                     the fallback block when (u 24) mod 2^16 < 16;
                                     Lx, Ly multiples of 6).  One value for every
                                     replica of a context.                        */
+    int32_t Lz;                  /* SPINMC_ISING_HC: third extent (0 or 1 = none) */
 } spinmc_replica_desc;
 
 /* Create a batch of n replicas (Methods, batched tensors: one context runs
@@ -256,7 +275,8 @@ enum spinmc_kernel_kind {
     SPINMC_K_RESIDENT = 1,      /* resident multi-sweep kernel (all groups)   */
     SPINMC_K_CPM_PASS = 3,      /* CPM colour pass                            */
     SPINMC_K_STREAM_POTTS = 4,  /* streamed Potts colour pass                 */
-    SPINMC_K_TRI_PASS = 5       /* triangular-lattice Ising colour pass       */
+    SPINMC_K_TRI_PASS = 5,      /* triangular-lattice Ising colour pass       */
+    SPINMC_K_HC_PASS = 6        /* chain / cubic Ising colour pass            */
 };
 int spinmc_profile(spinmc_ctx *ctx, int32_t enable);
 int spinmc_profile_read(spinmc_ctx *ctx, int32_t kind, double *ms_total, int64_t *launches);

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspinmc.so")
 
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_NOT_REPRESENTABLE, E_STATE = 0, -1, -2, -3, -4, -5, -6
-ISING, POTTS, CPM, ISING_TRI = 0, 1, 2, 3
+ISING, POTTS, CPM, ISING_TRI, ISING_HC = 0, 1, 2, 3, 4
 
 
 class SpinmcError(RuntimeError):
@@ -27,6 +27,7 @@ class ReplicaDesc(C.Structure):
         ("n_types", C.c_int32), ("adhesion", C.POINTER(C.c_float)),
         ("cell_type", C.POINTER(C.c_int8)), ("target_area", C.POINTER(C.c_int32)),
         ("lambda_area", C.c_float), ("temperature", C.c_double), ("cpm_range", C.c_int32),
+        ("Lz", C.c_int32),
     ]
 
 

@@ -239,8 +239,22 @@ void free_all(spinmc_ctx* c) {
 
 int validate(const spinmc_replica_desc& d, int i, bool& cpm_seen, bool& lat_seen) {
     if (d.model != SPINMC_ISING && d.model != SPINMC_POTTS && d.model != SPINMC_CPM &&
-        d.model != SPINMC_ISING_TRI)
+        d.model != SPINMC_ISING_TRI && d.model != SPINMC_ISING_HC)
         return fail(SPINMC_E_INVALID, "replica %d: unknown model %d", i, d.model);
+    if (d.model == SPINMC_ISING_HC) {
+        const int64_t Lz = d.Lz > 1 ? d.Lz : 1;
+        auto ok = [](int64_t L) { return L == 1 || (L >= 2 && L % 2 == 0); };
+        if (d.Lx < 2 || (d.Lx & 1) || !ok(d.Ly) || !ok(Lz) || d.Lz < 0)
+            return fail(SPINMC_E_INVALID,
+                        "replica %d: chain / cubic lattice needs Lx even >= 2, Ly and Lz 1 or even", i);
+        if ((int64_t)d.Lx * d.Ly * Lz > (1 << 28))
+            return fail(SPINMC_E_INVALID, "replica %d: lattice too large", i);
+        if (!std::isfinite(d.Jx) || !std::isfinite(d.h) || d.Jy != d.Jx)
+            return fail(SPINMC_E_INVALID, "replica %d: J must be finite, Jy == Jx", i);
+        if (!(d.beta >= 0.0) || !std::isfinite(d.beta))
+            return fail(SPINMC_E_INVALID, "replica %d: beta must be finite and >= 0", i);
+        return SPINMC_OK;
+    }
     if (d.model == SPINMC_ISING_TRI) {
         if (d.Lx < 3 || d.Ly < 3 || d.Lx % 3 || d.Ly % 3)
             return fail(SPINMC_E_INVALID,
@@ -427,15 +441,22 @@ int spinmc_create(const spinmc_replica_desc* d, int32_t n, uint64_t seed, int32_
     *out = nullptr;
     if (init != 0 && init != 1) return fail(SPINMC_E_INVALID, "create: init must be 0 or 1");
     bool cpm_seen = false, lat_seen = false;
-    int n_tri = 0;
+    int n_tri = 0, n_hc = 0;
     for (int i = 0; i < n; ++i) {
         int rc = validate(d[i], i, cpm_seen, lat_seen);
         if (rc) return rc;
         n_tri += d[i].model == SPINMC_ISING_TRI;
+        n_hc += d[i].model == SPINMC_ISING_HC;
     }
-    if (n_tri > 0 && n_tri < n)
-        return fail(SPINMC_E_UNSUPPORTED,
-                    "create: triangular replicas cannot share a context with other models");
+    if ((n_tri > 0 && n_tri < n) || (n_hc > 0 && n_hc < n))
+        return fail(SPINMC_E_UNSUPPORTED, "create: triangular and chain / cubic replicas need a "
+                                          "context of their own model");
+    if (n_hc == n) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+            return fail(SPINMC_E_DEVICE, "create: no HIP device available");
+        return create_tri(d, n, seed, init, hip_stream, out);
+    }
     if (n_tri == n) {
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
@@ -659,7 +680,7 @@ int spinmc_schedule_sites(const spinmc_ctx* c, int64_t streamed[3], int64_t resi
     if (c->cpm) {
         for (const HostRep& h : c->reps) streamed[kModelCpm] += (int64_t)h.dev.Lx * h.dev.Ly;
     } else if (c->tri) {  // counted with the Ising lattices
-        for (const HostRep& h : c->reps) streamed[kModelIsing] += (int64_t)h.dev.Lx * h.dev.Ly;
+        for (const HostRep& h : c->reps) streamed[kModelIsing] += (int64_t)h.lat_bytes;
     } else {
         const int mode = effective_mode(c);
         for (const HostRep& h : c->reps) {
@@ -1518,13 +1539,19 @@ TriArgs tri_args(spinmc_ctx* c, int32_t* stats) {
     a.R = c->R;
     a.width = c->width;
     int mb = 0;
-    bool l12 = true;
+    bool l12 = true, l8 = true;
+    a.model = c->reps[0].dev.model;
     for (const HostRep& h : c->reps) {
-        mb = std::max(mb, (h.dev.Lx * h.dev.Ly / 3 + 3) / 4);
+        l8 = l8 && h.dev.Lx % 8 == 0;
+        if (a.model == kModelIsingHC)
+            mb = std::max(mb, (h.dev.Lx * h.dev.Ly * h.dev.q / 2 + 3) / 4);
+        else
+            mb = std::max(mb, (h.dev.Lx * h.dev.Ly / 3 + 3) / 4);
         l12 = l12 && h.dev.Lx % 12 == 0;
     }
     a.max_blocks = mb;
     a.all_lx12 = l12 ? 1 : 0;
+    a.all_lx8 = l8 ? 1 : 0;
     a.max_sites = c->max_sites;
     return a;
 }
@@ -1548,20 +1575,21 @@ int create_tri(const spinmc_replica_desc* d, int n, uint64_t seed, int init, voi
         tri_thresholds(d[i], h.T);
         std::copy(h.T.begin(), h.T.end(), tab.begin() + (size_t)i * kTriClasses);
         RepDev& r = h.dev;
-        r.model = kModelIsingTri;
+        r.model = d[i].model == SPINMC_ISING_HC ? kModelIsingHC : kModelIsingTri;
         r.Lx = d[i].Lx;
         r.Ly = d[i].Ly;
+        r.q = d[i].model == SPINMC_ISING_HC && d[i].Lz > 1 ? d[i].Lz : 1;  // Lz
         r.W = d[i].Lx;
         r.rid = d[i].rid;
         r.Jx = d[i].Jx;
         r.Jy = d[i].Jy;
         r.h = d[i].h;
         r.beta = d[i].beta;
-        h.lat_bytes = (size_t)r.Lx * r.Ly;
+        h.lat_bytes = (size_t)r.Lx * r.Ly * r.q;
         r.lat_off = (int64_t)lat_off;
         lat_off = align_up(lat_off + h.lat_bytes, kAlign);
         rd[i] = r;
-        c->max_sites = std::max(c->max_sites, r.Lx * r.Ly);
+        c->max_sites = std::max(c->max_sites, r.Lx * r.Ly * r.q);
     }
     c->lat_bytes = lat_off + 64;
     auto A = [&](void** p, size_t b) { return hipMalloc(p, std::max<size_t>(b, 16)); };
@@ -1602,7 +1630,7 @@ int create_tri(const spinmc_replica_desc* d, int n, uint64_t seed, int init, voi
 
 int tri_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes) {
     const HostRep& h = c->reps[r];
-    if (bytes != (size_t)h.dev.Lx * h.dev.Ly) return fail(SPINMC_E_INVALID, "set_state: wrong byte count");
+    if (bytes != h.lat_bytes) return fail(SPINMC_E_INVALID, "set_state: wrong byte count");
     const int8_t* v = (const int8_t*)host;
     for (size_t i = 0; i < bytes; ++i)
         if (v[i] != 1 && v[i] != -1) return fail(SPINMC_E_INVALID, "set_state: Ising spins must be +-1");
@@ -1613,7 +1641,7 @@ int tri_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes) {
 
 int tri_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
     const HostRep& h = c->reps[r];
-    if (bytes != (size_t)h.dev.Lx * h.dev.Ly) return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
+    if (bytes != h.lat_bytes) return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipMemcpy(host, c->d_lat + h.dev.lat_off, bytes, hipMemcpyDeviceToHost);
     return check_dev(c, e, "get_state");
@@ -1624,10 +1652,12 @@ int tri_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
     hipError_t e = hipSuccess;
     const int n_rec = re > 0 ? n / re : 0;
     if (n_rec > 0) e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
+    const bool hc = a.model == kModelIsingHC;
+    const int n_col = hc ? 2 : 3;
     for (int i = 0; i < n && e == hipSuccess; ++i) {
-        for (int col = 0; col < 3 && e == hipSuccess; ++col)
-            e = timed(c, SPINMC_K_TRI_PASS, [&] { return launch_tri_pass(a, col, i, c->stream); },
-                      c->stream);
+        for (int col = 0; col < n_col && e == hipSuccess; ++col)
+            e = timed(c, hc ? SPINMC_K_HC_PASS : SPINMC_K_TRI_PASS,
+                      [&] { return launch_tri_pass(a, col, i, c->stream); }, c->stream);
         if (e == hipSuccess && re > 0 && ((i + 1) % re) == 0)
             e = launch_tri_stats(a, (i + 1) / re - 1, c->stream);
     }

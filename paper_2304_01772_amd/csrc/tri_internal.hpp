@@ -1,11 +1,13 @@
-// Internal declarations of the triangular-lattice Ising kernels.  Not part
-// of the C ABI.
+// Internal declarations of the natural-layout Ising kernels: the triangular
+// lattice and the chain / square / simple-cubic lattices.  Not part of the
+// C ABI.
 #pragma once
 #include "spinmc_internal.hpp"
 
 namespace spinmc {
 
 constexpr int kModelIsingTri = 3;
+constexpr int kModelIsingHC = 4;  // chain / square / cubic; RepDev.q holds Lz
 constexpr int kTriClasses = 14;  // 7 [s > 0] + (S6 + 6) / 2
 
 struct TriArgs {
@@ -19,6 +21,8 @@ struct TriArgs {
     int32_t max_blocks;       // max over replicas of ceil(Lx Ly / 12)
     int32_t max_sites;
     int32_t all_lx12;         // every Lx a multiple of 12: the span kernel
+    int32_t model;            // kModelIsingTri or kModelIsingHC (one per context)
+    int32_t all_lx8;          // every Lx a multiple of 8: the chain / cubic span kernel
 };
 
 hipError_t launch_tri_init(const TriArgs& a, hipStream_t s);

@@ -26,7 +26,7 @@ __device__ __forceinline__ int wrapt(int i, int n) { return i < 0 ? i + n : (i >
 // takes word n & 3 of block (n >> 2, 0, rid, 2); +1 iff it is < 2^31.
 __global__ void __launch_bounds__(256) k_tri_init(TriArgs a) {
     const RepDev D = a.reps[blockIdx.y];
-    const int n = D.Lx * D.Ly;
+    const int n = D.Lx * D.Ly * (D.model == kModelIsingHC ? D.q : 1);
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (4 * b >= n) return;
     uint32_t w[4];
@@ -160,13 +160,142 @@ __global__ void __launch_bounds__(256) k_tri_stats(TriArgs a, int rec_row) {
     }
 }
 
-// (e, |m|, m^2, m) per replica from [M, Bh, Bv, Bd].
+// Chain / square / simple cubic (Lz = D.q): the colour-c site of the pair
+// (2k, 2k + 1) -- both in one row since Lx is even -- for the four k of a
+// Philox block; neighbours x +- 1 and, where the extent exceeds 1, y +- 1 and
+// z +- 1.
+__global__ void __launch_bounds__(256) k_hc_pass(TriArgs a, int c, int sweep_off) {
+    __shared__ uint64_t lt[kTriClasses];
+    const int r = blockIdx.y;
+    if (threadIdx.x < kTriClasses) lt[threadIdx.x] = a.tab[(size_t)r * kTriClasses + threadIdx.x];
+    __syncthreads();
+    const RepDev D = a.reps[r];
+    const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, plane = Lx * Ly;
+    const int nk = plane * Lz / 2;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (4 * b >= nk) return;
+    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
+    const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
+    uint32_t w[4];
+    philox4x32_10((uint32_t)b, p, D.rid, kTriTagMain, a.key0, a.key1, w);
+    int8_t* lat = a.lat + D.lat_off;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int k = 4 * b + u;
+        if (k >= nk) break;
+        const int row = (2 * k) / Lx;  // z Ly + y
+        const int z = row / Ly, y = row - z * Ly;
+        const int x = 2 * k - row * Lx + ((c + y + z) & 1);
+        const size_t rb = (size_t)row * Lx;
+        const int s = lat[rb + x];
+        int S = lat[rb + wrapt(x - 1, Lx)] + lat[rb + wrapt(x + 1, Lx)];
+        if (Ly > 1)
+            S += lat[(size_t)(z * Ly + wrapt(y - 1, Ly)) * Lx + x] +
+                 lat[(size_t)(z * Ly + wrapt(y + 1, Ly)) * Lx + x];
+        if (Lz > 1)
+            S += lat[(size_t)wrapt(z - 1, Lz) * plane + (size_t)y * Lx + x] +
+                 lat[(size_t)wrapt(z + 1, Lz) * plane + (size_t)y * Lx + x];
+        const int idx = 7 * (s > 0) + (S + 6) / 2;
+        if ((uint64_t)w[u] < lt[idx]) lat[rb + x] = (int8_t)(-s);
+    }
+}
+
+// Lx a multiple of 8: the four sites of a Philox block are the colour-c
+// bytes of one 8-byte row span [x0, x0 + 8), offsets o = 2u + par with
+// par = (c + y + z) & 1; the spans of the neighbouring rows (y +- 1) and
+// planes (z +- 1) come in as dword pairs, plus the halo bytes x0 - 1 and
+// x0 + 8 of the own row.  The own span is written back whole (its other
+// colour's bytes unchanged; no other lane writes it during the pass).
+namespace {
+__device__ __forceinline__ int sbyte2(uint2 v, int i) {
+    return (int)(int8_t)((i < 4 ? v.x : v.y) >> (8 * (i & 3)));
+}
+}  // namespace
+
+__global__ void __launch_bounds__(256) k_hc_pass8(TriArgs a, int c, int sweep_off) {
+    __shared__ uint64_t lt[kTriClasses];
+    const int r = blockIdx.y;
+    if (threadIdx.x < kTriClasses) lt[threadIdx.x] = a.tab[(size_t)r * kTriClasses + threadIdx.x];
+    __syncthreads();
+    const RepDev D = a.reps[r];
+    const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, plane = Lx * Ly;
+    const int nb = plane * Lz / 8;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int row = (8 * b) / Lx;  // z Ly + y
+    const int z = row / Ly, y = row - z * Ly;
+    const int x0 = 8 * b - row * Lx;
+    const int par = (c + y + z) & 1;
+    int8_t* lat = a.lat + D.lat_off;
+    const size_t own = (size_t)row * Lx + x0;
+    const uint2 S = *reinterpret_cast<const uint2*>(lat + own);
+    const int hl = lat[(size_t)row * Lx + (x0 == 0 ? Lx - 1 : x0 - 1)];
+    const int hr = lat[(size_t)row * Lx + (x0 + 8 == Lx ? 0 : x0 + 8)];
+    uint2 Yu = make_uint2(0u, 0u), Yd = Yu, Zu = Yu, Zd = Yu;
+    if (Ly > 1) {
+        Yu = *reinterpret_cast<const uint2*>(lat + (size_t)(z * Ly + wrapt(y - 1, Ly)) * Lx + x0);
+        Yd = *reinterpret_cast<const uint2*>(lat + (size_t)(z * Ly + wrapt(y + 1, Ly)) * Lx + x0);
+    }
+    if (Lz > 1) {
+        Zu = *reinterpret_cast<const uint2*>(lat + (size_t)wrapt(z - 1, Lz) * plane + own - (size_t)z * plane);
+        Zd = *reinterpret_cast<const uint2*>(lat + (size_t)wrapt(z + 1, Lz) * plane + own - (size_t)z * plane);
+    }
+    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
+    const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
+    uint32_t w[4];
+    philox4x32_10((uint32_t)b, p, D.rid, kTriTagMain, a.key0, a.key1, w);
+    uint32_t flip[2] = {0u, 0u};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int o = 2 * u + par;
+        const int s = sbyte2(S, o);
+        int Sn = (o == 0 ? hl : sbyte2(S, o - 1)) + (o == 7 ? hr : sbyte2(S, o + 1));
+        if (Ly > 1) Sn += sbyte2(Yu, o) + sbyte2(Yd, o);
+        if (Lz > 1) Sn += sbyte2(Zu, o) + sbyte2(Zd, o);
+        const int idx = 7 * (s > 0) + (Sn + 6) / 2;
+        if ((uint64_t)w[u] < lt[idx]) flip[o >> 2] |= 0xFEu << (8 * (o & 3));
+    }
+    *reinterpret_cast<uint2*>(lat + own) = make_uint2(S.x ^ flip[0], S.y ^ flip[1]);
+}
+
+// [M, Bx, By, Bz] of the chain / square / cubic lattices.
+__global__ void __launch_bounds__(256) k_hc_stats(TriArgs a, int rec_row) {
+    const int r = blockIdx.y;
+    const RepDev D = a.reps[r];
+    const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, plane = Lx * Ly, n = plane * Lz;
+    const int8_t* lat = a.lat + D.lat_off;
+    int M = 0, Bx = 0, By = 0, Bz = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int row = i / Lx, x = i - row * Lx;
+        const int z = row / Ly, y = row - z * Ly;
+        const int s = lat[i];
+        M += s;
+        Bx += s * lat[(size_t)row * Lx + wrapt(x + 1, Lx)];
+        if (Ly > 1) By += s * lat[(size_t)(z * Ly + wrapt(y + 1, Ly)) * Lx + x];
+        if (Lz > 1) Bz += s * lat[(size_t)wrapt(z + 1, Lz) * plane + (size_t)y * Lx + x];
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        M += __shfl_xor(M, o);
+        Bx += __shfl_xor(Bx, o);
+        By += __shfl_xor(By, o);
+        Bz += __shfl_xor(Bz, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        int32_t* rw = a.stats + ((size_t)rec_row * a.R + r) * a.width;
+        atomicAdd(&rw[0], M);
+        atomicAdd(&rw[1], Bx);
+        atomicAdd(&rw[2], By);
+        atomicAdd(&rw[3], Bz);
+    }
+}
+
+// (e, |m|, m^2, m) per replica from [M, B1, B2, B3] (either lattice).
 __global__ void k_tri_observables(TriArgs a, double* obs) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= a.R) return;
     const RepDev D = a.reps[r];
     const int32_t* s = a.stats + (size_t)r * a.width;
-    const double N = (double)D.Lx * (double)D.Ly;
+    const double N = (double)D.Lx * (double)D.Ly * (D.model == kModelIsingHC ? (double)D.q : 1.0);
     const double M = s[0];
     const double H = -((double)D.Jx * ((double)s[1] + (double)s[2] + (double)s[3]) +
                        (double)D.h * M);
@@ -184,7 +313,13 @@ hipError_t launch_tri_init(const TriArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_tri_pass(const TriArgs& a, int c, int sweep_off, hipStream_t s) {
-    if (a.all_lx12)
+    if (a.model == kModelIsingHC && a.all_lx8)
+        hipLaunchKernelGGL(k_hc_pass8, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s, a,
+                           c, sweep_off);
+    else if (a.model == kModelIsingHC)
+        hipLaunchKernelGGL(k_hc_pass, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s, a,
+                           c, sweep_off);
+    else if (a.all_lx12)
         hipLaunchKernelGGL(k_tri_pass12, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s,
                            a, c, sweep_off);
     else
@@ -195,7 +330,11 @@ hipError_t launch_tri_pass(const TriArgs& a, int c, int sweep_off, hipStream_t s
 
 hipError_t launch_tri_stats(const TriArgs& a, int rec_row, hipStream_t s) {
     const int per = (a.max_sites + 255) / 256;
-    hipLaunchKernelGGL(k_tri_stats, dim3(per < 64 ? per : 64, a.R), dim3(256), 0, s, a, rec_row);
+    if (a.model == kModelIsingHC)
+        hipLaunchKernelGGL(k_hc_stats, dim3(per < 64 ? per : 64, a.R), dim3(256), 0, s, a, rec_row);
+    else
+        hipLaunchKernelGGL(k_tri_stats, dim3(per < 64 ? per : 64, a.R), dim3(256), 0, s, a,
+                           rec_row);
     return hipGetLastError();
 }
 

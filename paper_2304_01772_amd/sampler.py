@@ -9,7 +9,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import ISING, ISING_TRI, POTTS, CPM, ReplicaDesc, Schedule, check, lib
+from ._lib import ISING, ISING_HC, ISING_TRI, POTTS, CPM, ReplicaDesc, Schedule, check, lib
 
 __all__ = ["Sampler", "ISING", "POTTS", "CPM", "MODES"]
 
@@ -28,7 +28,8 @@ class Sampler:
     libspinmc context.
 
     ``replicas``: sequence of dicts with keys model (0 Ising, 1 Potts, 2 CPM,
-    3 triangular-lattice Ising), Lx, Ly and the model's parameters (q, Jx,
+    3 triangular-lattice Ising, 4 chain / square / cubic Ising with an extra
+    key Lz), Lx, Ly and the model's parameters (q, Jx,
     Jy, h, beta, rid; CPM: n_cells as q, n_types,
     adhesion, cell_type, target_area, lambda_area, temperature and optionally
     cpm_range, 1 for the Moore 3x3 neighbourhood or 2 for 5x5).
@@ -53,6 +54,7 @@ class Sampler:
             d.h = float(r.get("h", 0.0))
             d.beta = float(r.get("beta", 0.0))
             d.rid = int(r.get("rid", i))
+            d.Lz = int(r.get("Lz", 1))
             if d.model == CPM:
                 adh = np.ascontiguousarray(r["adhesion"], np.float32)
                 ct = np.ascontiguousarray(r["cell_type"], np.int8)
@@ -92,11 +94,17 @@ class Sampler:
 
     def _elem(self, r):
         m = self.replicas[r].get("model", ISING)
-        return {ISING: np.int8, ISING_TRI: np.int8, POTTS: np.uint8, CPM: np.int32}[m]
+        return {ISING: np.int8, ISING_TRI: np.int8, ISING_HC: np.int8, POTTS: np.uint8,
+                CPM: np.int32}[m]
+
+    def _shape(self, r):
+        rep = self.replicas[r]
+        if rep.get("model", ISING) == ISING_HC:
+            return (max(int(rep.get("Lz", 1)), 1), rep["Ly"], rep["Lx"])
+        return (rep["Ly"], rep["Lx"])
 
     def get_state(self, r):
-        rep = self.replicas[r]
-        out = np.empty((rep["Ly"], rep["Lx"]), self._elem(r))
+        out = np.empty(self._shape(r), self._elem(r))
         check(lib().spinmc_get_state(self.ctx, r, out.ctypes.data, out.nbytes))
         return out
 
@@ -155,7 +163,8 @@ class Sampler:
         return means, grads, dth
 
     # ------------------------------------------------------------- timing
-    KERNELS = {"stream_ising": 0, "resident": 1, "cpm_pass": 3, "stream_potts": 4, "tri_pass": 5}
+    KERNELS = {"stream_ising": 0, "resident": 1, "cpm_pass": 3, "stream_potts": 4, "tri_pass": 5,
+               "hc_pass": 6}
 
     def profile(self, enable=True):
         check(lib().spinmc_profile(self.ctx, 1 if enable else 0))

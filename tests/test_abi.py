@@ -61,6 +61,9 @@ def _desc(**kw):
     # triangular lattice: multiples of 3, one coupling
     (dict(model=3), -1), (dict(model=3, Lx=9, Ly=10), -1), (dict(model=3, Lx=9, Ly=9, Jy=0.5), -1),
     (dict(model=3, Lx=9, Ly=9, beta=-1.0), -1),
+    # chain / cubic: Lx even, Ly and Lz 1 or even
+    (dict(model=4, Lx=7), -1), (dict(model=4, Ly=3), -1), (dict(model=4, Lz=3), -1),
+    (dict(model=4, Lz=-2), -1), (dict(model=4, Jy=0.5), -1),
 ])
 def test_validation_precedes_device(L, kw, code):
     ctx = C.c_void_p()
