@@ -85,6 +85,14 @@ def lib():
                              C.c_uint64, C.c_uint32, C.c_uint64, C.c_int, C.c_int, _i8p,
                              C.c_void_p]
     L.orc_hc_run.restype = C.c_int
+    L.orc_msc_init.argtypes = [C.c_int, C.c_int, C.c_uint64, C.c_uint32, _u32p]
+    L.orc_msc_init.restype = None
+    L.orc_msc_stats.argtypes = [C.c_int, C.c_int, _u32p, _i32p]
+    L.orc_msc_stats.restype = None
+    L.orc_msc_run.argtypes = [C.c_int, C.c_int, C.c_float, C.c_float, C.c_float, C.c_double,
+                              C.c_uint64, C.c_uint32, C.c_uint64, C.c_int, C.c_int, _u32p,
+                              C.c_void_p]
+    L.orc_msc_run.restype = C.c_int
     L.orc_cpm_stats_r.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _f32p, _i8p, _i32p,
                                   C.c_float, _i32p, C.c_int, _i32p]
     L.orc_cpm_stats_r.restype = None
@@ -247,6 +255,39 @@ def hc_run(sigma, J, h, beta, seed, rid, t0, n_sweeps, record_every=0):
                           n_sweeps, record_every, s.reshape(-1), stats.ctypes.data)
     _check(rc, "hc_run")
     return s, stats[:n_rec]
+
+
+def msc_init(Lx, Ly, seed, rid):
+    """Multispin-coded initial words [Ly, Lx] (uint32, bit b = replica b)."""
+    w = np.zeros(Lx * Ly, np.uint32)
+    lib().orc_msc_init(Lx, Ly, seed, rid, w)
+    return w.reshape(Ly, Lx)
+
+
+def msc_stats(words):
+    """[32, 8] statistics [M, Bx, By, 0...] of the 32 packed replicas."""
+    words = np.ascontiguousarray(words, np.uint32)
+    out = np.zeros((32, 8), np.int32)
+    lib().orc_msc_stats(words.shape[1], words.shape[0], words.reshape(-1), out.reshape(-1))
+    return out
+
+
+def msc_run(words, Jx, Jy, h, beta, seed, rid, t0, n_sweeps, record_every=0):
+    """Multispin-coded chain on a copy: (words, stats[n_rec, 32, 8])."""
+    w = np.ascontiguousarray(words, np.uint32).copy()
+    n_rec = n_sweeps // record_every if record_every > 0 else 0
+    stats = np.zeros((max(n_rec, 1), 32, 8), np.int32)
+    rc = lib().orc_msc_run(w.shape[1], w.shape[0], Jx, Jy, h, beta, seed, rid, t0, n_sweeps,
+                           record_every, w.reshape(-1), stats.ctypes.data)
+    _check(rc, "msc_run")
+    return w, stats[:n_rec]
+
+
+def msc_unpack(words):
+    """int8 spins [32, Ly, Lx] of packed words."""
+    w = np.asarray(words, np.uint32)
+    return np.stack([np.where((w >> np.uint32(b)) & np.uint32(1), 1, -1).astype(np.int8)
+                     for b in range(32)])
 
 
 def cpm_scale(J, lam):

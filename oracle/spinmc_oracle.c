@@ -386,6 +386,94 @@ int orc_hc_run(int Lx, int Ly, int Lz, float J, float h, double beta, uint64_t s
 }
 
 /* ------------------------------------------------------------------------ */
+/* Multispin-coded square-lattice Ising: 32 replicas with the same Lx, Ly,
+ * Jx, Jy, h and beta packed bit by bit in one uint32 per site (bit b = 1 is
+ * s = +1 in replica b), natural layout n = y Lx + x.  The replicas share the
+ * random numbers: in pass p = 2t + c every site of colour c = (x + y) & 1
+ * takes W = word k & 3 (k = n >> 1) of the main block (k >> 2, p, rid, 0)
+ * whole, and every bit of it flips iff W < T[idx] with the square lattice's
+ * classes idx = 9 [s > 0] + 3 (Sx/2 + 1) + (Sy/2 + 1) of that bit.  Bit b of
+ * the initial word of site n is 1 iff word n & 3 of the init block
+ * (n >> 2, b, rid, 2) is < 2^31.                                            */
+void orc_msc_init(int Lx, int Ly, uint64_t seed, uint32_t rid, uint32_t *w32)
+{
+    uint32_t key[2], w[4];
+    int n, b;
+    seed_key(seed, key);
+    for (n = 0; n < Lx * Ly; n++) {
+        uint32_t v = 0;
+        for (b = 0; b < 32; b++) {
+            draw((uint32_t)n >> 2, (uint32_t)b, rid, TAG_INIT, key, w);
+            if (w[n & 3] < 0x80000000u)
+                v |= 1u << b;
+        }
+        w32[n] = v;
+    }
+}
+
+/* Statistics of bit b: [M, Bx, By] into out + 8 b (32 rows of 8).           */
+void orc_msc_stats(int Lx, int Ly, const uint32_t *w32, int32_t *out)
+{
+    int b, y, x;
+    memset(out, 0, 32 * 8 * sizeof(int32_t));
+    for (b = 0; b < 32; b++)
+        for (y = 0; y < Ly; y++)
+            for (x = 0; x < Lx; x++) {
+                int s = (w32[y * Lx + x] >> b) & 1u ? 1 : -1;
+                int r = (w32[y * Lx + wrap(x + 1, Lx)] >> b) & 1u ? 1 : -1;
+                int d = (w32[wrap(y + 1, Ly) * Lx + x] >> b) & 1u ? 1 : -1;
+                out[8 * b] += s;
+                out[8 * b + 1] += s * r;
+                out[8 * b + 2] += s * d;
+            }
+}
+
+int orc_msc_run(int Lx, int Ly, float Jx, float Jy, float h, double beta, uint64_t seed,
+                uint32_t rid, uint64_t t0, int n_sweeps, int record_every, uint32_t *w32,
+                int32_t *stats /* [n_rec][32][8] */)
+{
+    uint64_t T[18];
+    uint32_t key[2], w[4];
+    int i, c, y, x, b, rec = 0;
+    if (!check_shape(Lx, Ly) || n_sweeps < 0 || record_every < 0)
+        return ORC_EINVAL;
+    if (orc_ising_table(Jx, Jy, h, beta, T) != ORC_OK)
+        return ORC_EINVAL;
+    seed_key(seed, key);
+    for (i = 0; i < n_sweeps; i++) {
+        uint64_t t = t0 + (uint64_t)i;
+        for (c = 0; c < 2; c++) {
+            uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
+            for (y = 0; y < Ly; y++)
+                for (x = 0; x < Lx; x++) {
+                    if (((x + y) & 1) != c)
+                        continue;
+                    uint32_t n = (uint32_t)(y * Lx + x), k = n >> 1;
+                    draw(k >> 2, p, rid, TAG_MAIN, key, w);
+                    uint64_t W = w[k & 3u];
+                    uint32_t v = w32[n], flip = 0;
+                    for (b = 0; b < 32; b++) {
+                        int s = (v >> b) & 1u ? 1 : -1;
+                        int l = (w32[y * Lx + wrap(x - 1, Lx)] >> b) & 1u ? 1 : -1;
+                        int r = (w32[y * Lx + wrap(x + 1, Lx)] >> b) & 1u ? 1 : -1;
+                        int u = (w32[wrap(y - 1, Ly) * Lx + x] >> b) & 1u ? 1 : -1;
+                        int d = (w32[wrap(y + 1, Ly) * Lx + x] >> b) & 1u ? 1 : -1;
+                        int idx = 9 * (s > 0) + 3 * ((l + r) / 2 + 1) + ((u + d) / 2 + 1);
+                        if (W < T[idx])
+                            flip |= 1u << b;
+                    }
+                    w32[n] = v ^ flip;
+                }
+        }
+        if (record_every > 0 && ((i + 1) % record_every) == 0 && stats) {
+            orc_msc_stats(Lx, Ly, w32, stats + 256 * rec);
+            rec++;
+        }
+    }
+    return rec;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Potts, Eq. (2), H = -J sum delta - h sum s.  For a proposal s -> s':
  * dn = #{nbrs == s'} - #{nbrs == s} in [-4,4], ds = s'-s;
  * dE = -(J dn + h ds); idx = (dn+4)(2q-1) + (ds + q - 1).                   */
