@@ -310,6 +310,40 @@ def hc_probe(Sampler, torch, n_rep=256, L=32, sweeps=200):
             "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
 
 
+def msc_probe(Sampler, torch, n_groups=256, L=256, sweeps=200):
+    """Multispin-coded Ising: n_groups groups of 32 replicas (8192 replicas
+    of L x L for the defaults) at beta 0.4407, `sweeps` sweeps; the 32
+    replicas of a group share each site's random word.  Algorithmic HBM
+    bytes 0.375 per attempt (a pass reads the words once, 4 B per site, and
+    writes the colour's words, 2 B per site, for 16 attempts per site)."""
+    reps = [dict(model=5, Lx=L, Ly=L, Jx=1.0, Jy=1.0, h=0.0, beta=0.4407, rid=g)
+            for g in range(n_groups)]
+    smp = Sampler(reps, 13, init=True)
+    smp.sweep(5)
+    torch.cuda.synchronize()
+    e0, e1 = _events(torch, smp.stream)
+    smp.sweep(sweeps)
+    e1.record(smp.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    smp.profile(True)
+    smp.sweep(20)
+    torch.cuda.synchronize()
+    kms, nl = smp.profile_read("msc_pass")
+    smp.profile(False)
+    smp.close()
+    attempts = 32 * n_groups * L * L
+    avg_s = kms / nl * 1e-3
+    per_launch = attempts / 2
+    gbs = per_launch * 0.375 / avg_s / 1e9
+    return {"config": f"{n_groups} groups x 32 replicas of {L}x{L} (shared random words), "
+                      f"beta 0.4407, {sweeps} sweeps",
+            "attempts_per_ns": round(attempts * sweeps / (ms * 1e6), 1), "kernel": "k_msc_pass8",
+            "avg_launch_us": round(avg_s * 1e6, 2),
+            "kernel_attempts_per_ns": round(per_launch / avg_s / 1e9, 1),
+            "GBs_algorithmic": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def grad_probe(Sampler, torch):
     """Differentiation workload: 256 Ising replicas of 128x128 (J ~ U(0.3,
     0.6), h ~ U(-0.05, 0.05), beta 1), 5000 recorded sweeps, then the
@@ -588,6 +622,7 @@ PATH_PROBES = {
     "grad": lambda S, torch: grad_probe(S, torch),
     "tri": lambda S, torch: tri_probe(S, torch),
     "hc": lambda S, torch: hc_probe(S, torch),
+    "msc": lambda S, torch: msc_probe(S, torch),
     "mlp": lambda S, torch: mlp_probe(torch),
     "dmc": lambda S, torch: dmc_probe(torch),
     "dmc_vs_covariance": lambda S, torch: dmc_vs_covariance_probe(torch),
@@ -731,6 +766,8 @@ def main():
         print(f"# triangular: {paths['triangular_ising']}", file=sys.stderr, flush=True)
         paths["cubic_ising"] = hc_probe(Sampler, torch)
         print(f"# cubic: {paths['cubic_ising']}", file=sys.stderr, flush=True)
+        paths["multispin_ising"] = msc_probe(Sampler, torch)
+        print(f"# multispin: {paths['multispin_ising']}", file=sys.stderr, flush=True)
         paths["covariance_backward"] = grad_probe(Sampler, torch)
         print(f"# grad: {paths['covariance_backward']}", file=sys.stderr, flush=True)
         paths["surrogate_mlp"] = mlp_probe(torch)

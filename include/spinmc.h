@@ -43,7 +43,8 @@ enum spinmc_model {
     SPINMC_POTTS = 1,
     SPINMC_CPM = 2,
     SPINMC_ISING_TRI = 3,   /* triangular lattice                                  */
-    SPINMC_ISING_HC = 4     /* chain / square / simple cubic, natural layout (Lz)  */
+    SPINMC_ISING_HC = 4,    /* chain / square / simple cubic, natural layout (Lz)  */
+    SPINMC_ISING_MSC = 5    /* multispin-coded square lattice: 32 replicas a word */
 };
 
 enum spinmc_status {
@@ -95,7 +96,22 @@ enum spinmc_status {
  * p = 2t + c; the colour-c site of the pair (2k, 2k + 1) takes word k & 3 of
  * Philox block (k >> 2, p, rid, 0) whole as W; flip iff
  * W < ceil(2^32 exp(-beta 2 s (J S + h))), S the neighbour sum.  States are
- * int8 [Lz][Ly][Lx]; contexts as for the triangular lattice.               */
+ * int8 [Lz][Ly][Lx]; contexts as for the triangular lattice.
+ *
+ * Multispin-coded square-lattice Ising (1-bit spins; SPINMC_ISING_MSC): one
+ * descriptor is a group of 32 replicas with its Lx (a multiple of 8), Ly
+ * (even), Jx, Jy, h, beta and rid, packed bit by bit in one uint32 per site
+ * (bit b = 1: s = +1 in replica b; natural layout y Lx + x).  The 32 replicas
+ * share the random numbers: in pass p = 2t + c each site of colour
+ * c = (x + y) & 1 with within-colour index k = n >> 1 takes W = word k & 3
+ * of Philox block (k >> 2, p, rid, 0) whole, and every bit whose
+ * square-lattice class (as for SPINMC_ISING) has W < T flips.  Initial bit
+ * b of site n: 1 iff word n & 3 of block (n >> 2, b, rid, 2) is < 2^31.
+ * The replicas are correlated through the shared draws; each one alone is
+ * a Metropolis chain.  A context of G groups reports 32 G replicas to
+ * spinmc_num_replicas / sweep / measure (replica 32 g + b, statistics
+ * [M, Bx, By] as for SPINMC_ISING); spinmc_get_state / set_state move the
+ * uint32 words of group g (Ly Lx * 4 bytes).  Only groups in a context.     */
 
 /* Hamiltonian parameters of one replica (Eq. (1), Eq. (2), Eq. (3)).
  * Signs: Ising H = -Jx sum_h s s' - Jy sum_v s s' - h sum s with s = +-1;
@@ -276,7 +292,8 @@ enum spinmc_kernel_kind {
     SPINMC_K_CPM_PASS = 3,      /* CPM colour pass                            */
     SPINMC_K_STREAM_POTTS = 4,  /* streamed Potts colour pass                 */
     SPINMC_K_TRI_PASS = 5,      /* triangular-lattice Ising colour pass       */
-    SPINMC_K_HC_PASS = 6        /* chain / cubic Ising colour pass            */
+    SPINMC_K_HC_PASS = 6,       /* chain / cubic Ising colour pass            */
+    SPINMC_K_MSC_PASS = 7       /* multispin-coded Ising colour pass          */
 };
 int spinmc_profile(spinmc_ctx *ctx, int32_t enable);
 int spinmc_profile_read(spinmc_ctx *ctx, int32_t kind, double *ms_total, int64_t *launches);

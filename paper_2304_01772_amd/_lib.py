@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libspinmc.so")
 
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_NOT_REPRESENTABLE, E_STATE = 0, -1, -2, -3, -4, -5, -6
-ISING, POTTS, CPM, ISING_TRI, ISING_HC = 0, 1, 2, 3, 4
+ISING, POTTS, CPM, ISING_TRI, ISING_HC, ISING_MSC = 0, 1, 2, 3, 4, 5
 
 
 class SpinmcError(RuntimeError):

@@ -12,6 +12,7 @@
 #include <string>
 #include <tuple>
 
+#include "msc_internal.hpp"
 #include "tri_internal.hpp"
 #include <vector>
 
@@ -155,9 +156,12 @@ struct spinmc_ctx {
     // multiple of 8, at most kCpmLdsCells cells per replica)
     bool cpm_quad = false, cpm_lds_reserved = false;
     int cpm_range = 1;  // 1: Moore 3x3, 4 colours; 2: 5x5, 9 colours
-    // triangular-lattice Ising
+    // triangular-lattice Ising (and chain / cubic)
     bool tri = false;
-    uint64_t* d_tab64 = nullptr;  // [R][14] thresholds
+    uint64_t* d_tab64 = nullptr;  // [R][14] thresholds ([G][18] multispin-coded)
+    // multispin-coded Ising: reps holds the G groups, R = 32 G
+    bool msc = false;
+    RepDev* d_reps_obs = nullptr;  // one square-lattice Ising entry per replica
     int cpm_cell_cap = 0;
     // kernel timing
     bool prof = false;
@@ -223,6 +227,8 @@ void free_all(spinmc_ctx* c) {
     hipFree(c->d_js);
     hipFree(c->d_tab64);
     c->d_tab64 = nullptr;
+    hipFree(c->d_reps_obs);
+    c->d_reps_obs = nullptr;
     c->d_ctype = nullptr;
     c->d_target = nullptr;
     c->d_area = nullptr;
@@ -239,8 +245,20 @@ void free_all(spinmc_ctx* c) {
 
 int validate(const spinmc_replica_desc& d, int i, bool& cpm_seen, bool& lat_seen) {
     if (d.model != SPINMC_ISING && d.model != SPINMC_POTTS && d.model != SPINMC_CPM &&
-        d.model != SPINMC_ISING_TRI && d.model != SPINMC_ISING_HC)
+        d.model != SPINMC_ISING_TRI && d.model != SPINMC_ISING_HC && d.model != SPINMC_ISING_MSC)
         return fail(SPINMC_E_INVALID, "replica %d: unknown model %d", i, d.model);
+    if (d.model == SPINMC_ISING_MSC) {
+        if (d.Lx < 8 || d.Lx % 8 || d.Ly < 2 || (d.Ly & 1))
+            return fail(SPINMC_E_INVALID,
+                        "replica %d: multispin coding needs Lx a multiple of 8, Ly even >= 2", i);
+        if ((int64_t)d.Lx * d.Ly > (1 << 28))
+            return fail(SPINMC_E_INVALID, "replica %d: lattice too large", i);
+        if (!std::isfinite(d.Jx) || !std::isfinite(d.Jy) || !std::isfinite(d.h))
+            return fail(SPINMC_E_INVALID, "replica %d: non-finite coupling or field", i);
+        if (!(d.beta >= 0.0) || !std::isfinite(d.beta))
+            return fail(SPINMC_E_INVALID, "replica %d: beta must be finite and >= 0", i);
+        return SPINMC_OK;
+    }
     if (d.model == SPINMC_ISING_HC) {
         const int64_t Lz = d.Lz > 1 ? d.Lz : 1;
         auto ok = [](int64_t L) { return L == 1 || (L >= 2 && L % 2 == 0); };
@@ -424,6 +442,10 @@ int tri_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes);
 int tri_get_state(spinmc_ctx* c, int r, void* host, size_t bytes);
 int tri_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
 int tri_measure(spinmc_ctx* c, int32_t* stats, double* obs);
+int create_msc(const spinmc_replica_desc* d, int n, uint64_t seed, int init, void* stream,
+               spinmc_ctx** out);
+int msc_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
+int msc_measure(spinmc_ctx* c, int32_t* stats, double* obs);
 int cpm_measure(spinmc_ctx* c, int32_t* stats, double* obs);
 int default_tile_rows(const HostRep& h);
 int effective_mode(const spinmc_ctx* c);
@@ -441,12 +463,22 @@ int spinmc_create(const spinmc_replica_desc* d, int32_t n, uint64_t seed, int32_
     *out = nullptr;
     if (init != 0 && init != 1) return fail(SPINMC_E_INVALID, "create: init must be 0 or 1");
     bool cpm_seen = false, lat_seen = false;
-    int n_tri = 0, n_hc = 0;
+    int n_tri = 0, n_hc = 0, n_msc = 0;
     for (int i = 0; i < n; ++i) {
         int rc = validate(d[i], i, cpm_seen, lat_seen);
         if (rc) return rc;
         n_tri += d[i].model == SPINMC_ISING_TRI;
         n_hc += d[i].model == SPINMC_ISING_HC;
+        n_msc += d[i].model == SPINMC_ISING_MSC;
+    }
+    if (n_msc > 0 && n_msc < n)
+        return fail(SPINMC_E_UNSUPPORTED, "create: multispin-coded groups need a context of their own");
+    if (n_msc == n) {
+        if ((int64_t)n * 32 > (1 << 30)) return fail(SPINMC_E_INVALID, "create: too many groups");
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+            return fail(SPINMC_E_DEVICE, "create: no HIP device available");
+        return create_msc(d, n, seed, init, hip_stream, out);
     }
     if ((n_tri > 0 && n_tri < n) || (n_hc > 0 && n_hc < n))
         return fail(SPINMC_E_UNSUPPORTED, "create: triangular and chain / cubic replicas need a "
@@ -609,6 +641,15 @@ int spinmc_set_state(spinmc_ctx* c, int32_t r, const void* host, size_t bytes) {
     if (c->poisoned) return fail(SPINMC_E_DEVICE, "set_state: context poisoned");
     if (r < 0 || r >= c->R) return fail(SPINMC_E_INVALID, "set_state: replica out of range");
     if (c->cpm) return cpm_set_state(c, r, host, bytes);
+    if (c->msc) {
+        if (r >= (int)c->reps.size()) return fail(SPINMC_E_INVALID, "set_state: group out of range");
+        const HostRep& h = c->reps[r];
+        if (bytes != h.lat_bytes) return fail(SPINMC_E_INVALID, "set_state: wrong byte count");
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpy(c->d_lat + h.dev.lat_off, host, bytes, hipMemcpyHostToDevice);
+        return check_dev(c, e, "set_state");
+    }
     if (c->tri) return tri_set_state(c, r, host, bytes);
     const HostRep& h = c->reps[r];
     const int Lx = h.dev.Lx, Ly = h.dev.Ly, W = h.dev.W;
@@ -641,6 +682,15 @@ int spinmc_get_state(spinmc_ctx* c, int32_t r, void* host, size_t bytes) {
     if (c->poisoned) return fail(SPINMC_E_DEVICE, "get_state: context poisoned");
     if (r < 0 || r >= c->R) return fail(SPINMC_E_INVALID, "get_state: replica out of range");
     if (c->cpm) return cpm_get_state(c, r, host, bytes);
+    if (c->msc) {
+        if (r >= (int)c->reps.size()) return fail(SPINMC_E_INVALID, "get_state: group out of range");
+        const HostRep& h = c->reps[r];
+        if (bytes != h.lat_bytes) return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpy(host, c->d_lat + h.dev.lat_off, bytes, hipMemcpyDeviceToHost);
+        return check_dev(c, e, "get_state");
+    }
     if (c->tri) return tri_get_state(c, r, host, bytes);
     const HostRep& h = c->reps[r];
     const int Lx = h.dev.Lx, Ly = h.dev.Ly, W = h.dev.W;
@@ -663,7 +713,8 @@ int spinmc_get_state(spinmc_ctx* c, int32_t r, void* host, size_t bytes) {
 int spinmc_thresholds(const spinmc_ctx* c, int32_t r, uint64_t* T, int32_t cap, int32_t* n_out,
                       int64_t* aux) {
     if (!c || !n_out) return fail(SPINMC_E_INVALID, "thresholds: null argument");
-    if (r < 0 || r >= c->R) return fail(SPINMC_E_INVALID, "thresholds: replica out of range");
+    if (r < 0 || r >= (int)c->reps.size())
+        return fail(SPINMC_E_INVALID, "thresholds: replica out of range");
     const HostRep& h = c->reps[r];
     *n_out = (int32_t)h.T.size();
     if (aux) *aux = h.aux;
@@ -679,6 +730,8 @@ int spinmc_schedule_sites(const spinmc_ctx* c, int64_t streamed[3], int64_t resi
     for (int m = 0; m < 3; ++m) streamed[m] = resident[m] = 0;
     if (c->cpm) {
         for (const HostRep& h : c->reps) streamed[kModelCpm] += (int64_t)h.dev.Lx * h.dev.Ly;
+    } else if (c->msc) {  // 32 replicas per site, counted with the Ising lattices
+        for (const HostRep& h : c->reps) streamed[kModelIsing] += 32 * (int64_t)h.dev.Lx * h.dev.Ly;
     } else if (c->tri) {  // counted with the Ising lattices
         for (const HostRep& h : c->reps) streamed[kModelIsing] += (int64_t)h.lat_bytes;
     } else {
@@ -725,6 +778,7 @@ int spinmc_sweep(spinmc_ctx* c, int32_t n, int32_t re, void* dev_stats) {
         return fail(SPINMC_E_INVALID, "sweep: sweep counter would exceed 2^31");
     if (n == 0) return SPINMC_OK;
     int rc = c->cpm   ? cpm_sweep(c, n, re, (int32_t*)dev_stats)
+             : c->msc ? msc_sweep(c, n, re, (int32_t*)dev_stats)
              : c->tri ? tri_sweep(c, n, re, (int32_t*)dev_stats)
                       : enqueue_sweep(c, n, re, (int32_t*)dev_stats);
     if (rc == SPINMC_OK) c->t += (uint64_t)n;
@@ -736,6 +790,7 @@ int spinmc_measure(spinmc_ctx* c, void* dev_stats, void* dev_obs) {
     if (c->poisoned) return fail(SPINMC_E_DEVICE, "measure: context poisoned");
     int32_t* st = (int32_t*)dev_stats;
     if (c->cpm) return cpm_measure(c, st, (double*)dev_obs);
+    if (c->msc) return msc_measure(c, st, (double*)dev_obs);
     if (c->tri) return tri_measure(c, st, (double*)dev_obs);
     hipError_t e = launch_fill_i32(st, (size_t)c->R * c->width, 0, c->stream);
     SweepArgs a{};
@@ -804,7 +859,7 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
     if (!c) return fail(SPINMC_E_INVALID, "autotune: null context");
     if (c->poisoned) return fail(SPINMC_E_DEVICE, "autotune: context poisoned");
     if (trial_sweeps < 1) return fail(SPINMC_E_INVALID, "autotune: trial_sweeps must be >= 1");
-    if (c->tri) {  // one kernel shape: nothing to choose
+    if (c->tri || c->msc) {  // one kernel shape: nothing to choose
         if (chosen) *chosen = c->sched;
         if (n_tried) *n_tried = 0;
         return SPINMC_OK;
@@ -1670,6 +1725,147 @@ int tri_measure(spinmc_ctx* c, int32_t* stats, double* obs) {
     hipError_t e = launch_fill_i32(stats, (size_t)c->R * c->width, 0, c->stream);
     if (e == hipSuccess) e = launch_tri_stats(a, 0, c->stream);
     if (e == hipSuccess && obs) e = launch_tri_observables(a, obs, c->stream);
+    return check_dev(c, e, "measure");
+}
+
+// ================================================= multispin-coded Ising
+// The square lattice's 18 classes idx = 9 [s > 0] + 3 (Sx/2 + 1) + (Sy/2 + 1)
+// in FP64 (dE = 2 s (Jx Sx + Jy Sy + h); T = 2^32 accepts always).
+void msc_thresholds(const spinmc_replica_desc& d, std::vector<uint64_t>& T) {
+    T.resize(kMscClasses);
+    for (int si = 0; si < 2; ++si)
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                const double s = si ? 1.0 : -1.0;
+                double u = (double)d.Jx * (2.0 * a - 2.0);
+                u = u + (double)d.Jy * (2.0 * b - 2.0);
+                u = u + (double)d.h;
+                const double dE = 2.0 * s * u;
+                T[9 * si + 3 * a + b] =
+                    dE <= 0.0 ? ((uint64_t)1 << 32)
+                              : (uint64_t)std::ceil(std::ldexp(std::exp(-d.beta * dE), 32));
+            }
+}
+
+MscArgs msc_args(spinmc_ctx* c, int32_t* stats) {
+    MscArgs a{};
+    a.reps = c->d_reps;
+    a.lat = reinterpret_cast<uint32_t*>(c->d_lat);
+    a.tab = c->d_tab64;
+    a.t_base = c->d_t;
+    a.stats = stats;
+    a.key0 = (uint32_t)(c->seed & 0xffffffffu);
+    a.key1 = (uint32_t)(c->seed >> 32);
+    a.G = (int)c->reps.size();
+    a.width = c->width;
+    int mb = 0;
+    for (const HostRep& h : c->reps) mb = std::max(mb, h.dev.Lx * h.dev.Ly / 8);
+    a.max_blocks = mb;
+    a.max_sites = c->max_sites;
+    return a;
+}
+
+int create_msc(const spinmc_replica_desc* d, int n, uint64_t seed, int init, void* stream,
+               spinmc_ctx** out) {
+    spinmc_ctx* c = new spinmc_ctx();
+    hipGetDevice(&c->device);
+    c->stream = (hipStream_t)stream;
+    c->seed = seed;
+    c->R = 32 * n;
+    c->width = 8;
+    c->msc = true;
+    c->reps.resize(n);
+    std::vector<uint64_t> tab((size_t)n * kMscClasses);
+    std::vector<RepDev> rd(n), robs((size_t)32 * n);
+    size_t lat_off = 0;
+    for (int i = 0; i < n; ++i) {
+        HostRep& h = c->reps[i];
+        h.d = d[i];
+        msc_thresholds(d[i], h.T);
+        std::copy(h.T.begin(), h.T.end(), tab.begin() + (size_t)i * kMscClasses);
+        RepDev& r = h.dev;
+        r.model = kModelIsingMsc;
+        r.Lx = d[i].Lx;
+        r.Ly = d[i].Ly;
+        r.W = d[i].Lx;
+        r.rid = d[i].rid;
+        r.Jx = d[i].Jx;
+        r.Jy = d[i].Jy;
+        r.h = d[i].h;
+        r.beta = d[i].beta;
+        h.lat_bytes = (size_t)r.Lx * r.Ly * 4;
+        r.lat_off = (int64_t)lat_off;
+        lat_off = align_up(lat_off + h.lat_bytes, kAlign);
+        rd[i] = r;
+        for (int b = 0; b < 32; ++b) {  // observables: square-lattice Ising entries
+            RepDev o = r;
+            o.model = kModelIsing;
+            robs[(size_t)32 * i + b] = o;
+        }
+        c->max_sites = std::max(c->max_sites, r.Lx * r.Ly);
+    }
+    c->lat_bytes = lat_off + 64;
+    auto A = [&](void** p, size_t b) { return hipMalloc(p, std::max<size_t>(b, 16)); };
+    hipError_t e = hipSuccess;
+    if ((e = A((void**)&c->d_lat, c->lat_bytes)) || (e = A((void**)&c->d_reps, sizeof(RepDev) * n)) ||
+        (e = A((void**)&c->d_reps_obs, sizeof(RepDev) * robs.size())) ||
+        (e = A((void**)&c->d_tab64, sizeof(uint64_t) * tab.size())) ||
+        (e = A((void**)&c->d_t, sizeof(uint64_t)))) {
+        free_all(c);
+        delete c;
+        hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? SPINMC_E_NOMEM : SPINMC_E_DEVICE,
+                    "create: device allocation failed: %s", hipGetErrorString(e));
+    }
+    const uint64_t zero = 0;
+    if ((e = hipMemcpy(c->d_reps, rd.data(), sizeof(RepDev) * n, hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_reps_obs, robs.data(), sizeof(RepDev) * robs.size(),
+                       hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_tab64, tab.data(), sizeof(uint64_t) * tab.size(),
+                       hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(c->d_t, &zero, sizeof zero, hipMemcpyHostToDevice))) {
+        free_all(c);
+        delete c;
+        return fail(SPINMC_E_DEVICE, "create: upload failed: %s", hipGetErrorString(e));
+    }
+    // init = 0: every spin -1 (all bits 0); init = 1: the init stream per bit
+    e = hipMemset(c->d_lat, 0, c->lat_bytes);
+    if (e == hipSuccess && init) {
+        MscArgs a = msc_args(c, nullptr);
+        e = launch_msc_init(a, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    }
+    if (e != hipSuccess) {
+        free_all(c);
+        delete c;
+        return fail(SPINMC_E_DEVICE, "create: init failed: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return SPINMC_OK;
+}
+
+int msc_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
+    MscArgs a = msc_args(c, stats);
+    hipError_t e = hipSuccess;
+    const int n_rec = re > 0 ? n / re : 0;
+    if (n_rec > 0) e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        for (int col = 0; col < 2 && e == hipSuccess; ++col)
+            e = timed(c, SPINMC_K_MSC_PASS, [&] { return launch_msc_pass(a, col, i, c->stream); },
+                      c->stream);
+        if (e == hipSuccess && re > 0 && ((i + 1) % re) == 0)
+            e = launch_msc_stats(a, (i + 1) / re - 1, c->stream);
+    }
+    if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)n, c->stream);
+    return check_dev(c, e, "sweep");
+}
+
+int msc_measure(spinmc_ctx* c, int32_t* stats, double* obs) {
+    MscArgs a = msc_args(c, stats);
+    hipError_t e = launch_fill_i32(stats, (size_t)c->R * c->width, 0, c->stream);
+    if (e == hipSuccess) e = launch_msc_stats(a, 0, c->stream);
+    if (e == hipSuccess && obs)
+        e = launch_observables(c->d_reps_obs, c->R, stats, c->width, obs, c->stream);
     return check_dev(c, e, "measure");
 }
 

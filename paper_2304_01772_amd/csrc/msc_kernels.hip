@@ -1,0 +1,191 @@
+// Multispin-coded square-lattice Ising (1-bit spins): 32 replicas with the
+// same lattice shape, couplings, field and temperature packed bit by bit in
+// one uint32 per site (bit b = 1 is s = +1 in replica b), natural row-major
+// layout.  The replicas share the random numbers, so one Philox word decides
+// 32 attempts: in pass p = 2t + c (colour c = (x + y) & 1) the site n with
+// within-colour index k = n >> 1 takes W = word k & 3 of block
+// (k >> 2, p, rid, 0), and every bit whose class idx = 9 [s > 0] +
+// 3 (Sx/2 + 1) + (Sy/2 + 1) has W < T[idx] flips (Algorithm 1; the
+// thresholds are the FP64 host table of the square lattice).  The classes of
+// all 32 bits come from bitwise logic: a neighbour bit agrees with the own
+// bit where their xor is 0, and counts of 0, 1 or 2 agreeing horizontal
+// (vertical) neighbours are ~(a | b), a ^ b and a & b.
+//
+// Lx is a multiple of 8: a lane takes the four sites of one Philox block,
+// the own-colour words of the 8-word row span [x0, x0 + 8); the spans of
+// rows y - 1, y, y + 1 come in as 16-byte loads plus the two halo words of
+// row y, and the own span is written back whole (the other colour's words
+// unchanged; no other lane writes the span in the pass).
+#include "msc_internal.hpp"
+
+namespace spinmc {
+
+namespace {
+constexpr uint32_t kMscTagMain = 0u, kMscTagInit = 2u;
+
+struct Span32 {
+    uint4 a, b;
+};
+
+__device__ __forceinline__ Span32 ld_span(const uint32_t* p) {
+    return Span32{*reinterpret_cast<const uint4*>(p), *reinterpret_cast<const uint4*>(p + 4)};
+}
+
+__device__ __forceinline__ uint32_t e4(const uint4& v, int i) {
+    return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
+}
+
+__device__ __forceinline__ uint32_t el(const Span32& s, int i) {
+    return i < 4 ? e4(s.a, i) : e4(s.b, i - 4);
+}
+}  // namespace
+
+// Bit b of site n: 1 iff word n & 3 of block (n >> 2, b, rid, 2) is < 2^31.
+__global__ void __launch_bounds__(256) k_msc_init(MscArgs a) {
+    const RepDev D = a.reps[blockIdx.y];
+    const int n = D.Lx * D.Ly;
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;  // block of 4 sites
+    if (4 * q >= n) return;
+    uint32_t v[4] = {0u, 0u, 0u, 0u};
+    for (int b = 0; b < 32; ++b) {
+        uint32_t w[4];
+        philox4x32_10((uint32_t)q, (uint32_t)b, D.rid, kMscTagInit, a.key0, a.key1, w);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] |= (w[u] < 0x80000000u ? 1u : 0u) << b;
+    }
+    uint32_t* lat = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(a.lat) + D.lat_off);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (4 * q + u < n) lat[4 * q + u] = v[u];
+}
+
+__global__ void __launch_bounds__(256) k_msc_pass8(MscArgs a, int c, int sweep_off) {
+    __shared__ uint64_t lt[kMscClasses];
+    const int g = blockIdx.y;
+    if (threadIdx.x < kMscClasses) lt[threadIdx.x] = a.tab[(size_t)g * kMscClasses + threadIdx.x];
+    __syncthreads();
+    const RepDev D = a.reps[g];
+    const int Lx = D.Lx, Ly = D.Ly;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= Lx * Ly / 8) return;
+    const int y = (8 * b) / Lx, x0 = 8 * b - y * Lx;
+    const int par = (c + y) & 1;
+    const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
+    uint32_t* lat = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(a.lat) + D.lat_off);
+    const Span32 S = ld_span(lat + (size_t)y * Lx + x0);
+    const Span32 U = ld_span(lat + (size_t)yu * Lx + x0);
+    const Span32 Dn = ld_span(lat + (size_t)yd * Lx + x0);
+    const uint32_t hl = lat[(size_t)y * Lx + (x0 == 0 ? Lx - 1 : x0 - 1)];
+    const uint32_t hr = lat[(size_t)y * Lx + (x0 + 8 == Lx ? 0 : x0 + 8)];
+    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
+    const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
+    uint32_t w[4];
+    philox4x32_10((uint32_t)b, p, D.rid, kMscTagMain, a.key0, a.key1, w);
+    uint32_t flip[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int o = 2 * u;  // the own site is at o + par
+        const uint32_t s = par ? el(S, o + 1) : el(S, o);
+        const uint32_t l = par ? el(S, o) : (o == 0 ? hl : el(S, o - 1));
+        const uint32_t r = par ? (o + 2 == 8 ? hr : el(S, o + 2)) : el(S, o + 1);
+        const uint32_t up = par ? el(U, o + 1) : el(U, o);
+        const uint32_t dn = par ? el(Dn, o + 1) : el(Dn, o);
+        // agreeing neighbours per bit
+        const uint32_t al = ~(s ^ l), ar = ~(s ^ r), au = ~(s ^ up), ad = ~(s ^ dn);
+        const uint32_t ax[3] = {~(al | ar), al ^ ar, al & ar};
+        const uint32_t ay[3] = {~(au | ad), au ^ ad, au & ad};
+        // for s = +1, Sx/2 + 1 is the agreeing count; for s = -1, 2 minus it
+        const uint64_t W = w[u];
+        uint32_t fp = 0u, fn = 0u;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const uint32_t m = ax[i] & ay[j];
+                fp |= (W < lt[9 + 3 * i + j]) ? m : 0u;
+                fn |= (W < lt[3 * (2 - i) + (2 - j)]) ? m : 0u;
+            }
+        flip[o] = (s & fp) | (~s & fn);
+    }
+    // the own words sit at odd offsets when par = 1
+    uint32_t f[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) f[i] = 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        f[2 * u] = par ? 0u : flip[2 * u];
+        f[2 * u + 1] = par ? flip[2 * u] : 0u;
+    }
+    uint32_t* out = lat + (size_t)y * Lx + x0;
+    *reinterpret_cast<uint4*>(out) =
+        make_uint4(S.a.x ^ f[0], S.a.y ^ f[1], S.a.z ^ f[2], S.a.w ^ f[3]);
+    *reinterpret_cast<uint4*>(out + 4) =
+        make_uint4(S.b.x ^ f[4], S.b.y ^ f[5], S.b.z ^ f[6], S.b.w ^ f[7]);
+}
+
+// Per bit b: M = 2 ones - N, Bx = N - 2 (ones of s ^ right), By likewise;
+// wave ballots count the bits, one LDS atomic per wave, bit and statistic.
+__global__ void __launch_bounds__(256) k_msc_stats(MscArgs a, int rec_row) {
+    __shared__ int cnt[3][32];
+    const int g = blockIdx.y;
+    const RepDev D = a.reps[g];
+    const int Lx = D.Lx, Ly = D.Ly, n = Lx * Ly;
+    if (threadIdx.x < 96) (&cnt[0][0])[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t* lat =
+        reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(a.lat) + D.lat_off);
+    for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        const int i = base + threadIdx.x;
+        uint32_t s = 0u, xr = 0u, xd = 0u;
+        const bool in = i < n;
+        if (in) {
+            const int y = i / Lx, x = i - y * Lx;
+            s = lat[i];
+            xr = s ^ lat[(size_t)y * Lx + (x + 1 == Lx ? 0 : x + 1)];
+            xd = s ^ lat[(size_t)(y + 1 == Ly ? 0 : y + 1) * Lx + x];
+        }
+        for (int bit = 0; bit < 32; ++bit) {
+            const int c0 = __popcll(__ballot(in && ((s >> bit) & 1u)));
+            const int c1 = __popcll(__ballot(in && ((xr >> bit) & 1u)));
+            const int c2 = __popcll(__ballot(in && ((xd >> bit) & 1u)));
+            if ((threadIdx.x & 63) == 0) {
+                atomicAdd(&cnt[0][bit], c0);
+                atomicAdd(&cnt[1][bit], c1);
+                atomicAdd(&cnt[2][bit], c2);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        const int bit = threadIdx.x;
+        int32_t* row = a.stats + ((size_t)rec_row * (32 * a.G) + 32 * g + bit) * a.width;
+        // partial counts of this workgroup; every workgroup adds its share of
+        // 2 ones - N as 2 ones - n_visited
+        int visited = 0;
+        for (int base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x)
+            visited += min((int)blockDim.x, n - base);
+        atomicAdd(&row[0], 2 * cnt[0][bit] - visited);
+        atomicAdd(&row[1], visited - 2 * cnt[1][bit]);
+        atomicAdd(&row[2], visited - 2 * cnt[2][bit]);
+    }
+}
+
+hipError_t launch_msc_init(const MscArgs& a, hipStream_t s) {
+    const int nq = (a.max_sites + 3) / 4;
+    hipLaunchKernelGGL(k_msc_init, dim3((nq + 255) / 256, a.G), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_msc_pass(const MscArgs& a, int c, int sweep_off, hipStream_t s) {
+    hipLaunchKernelGGL(k_msc_pass8, dim3((a.max_blocks + 255) / 256, a.G), dim3(256), 0, s, a, c,
+                       sweep_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_msc_stats(const MscArgs& a, int rec_row, hipStream_t s) {
+    const int per = (a.max_sites + 255) / 256;
+    hipLaunchKernelGGL(k_msc_stats, dim3(per < 64 ? per : 64, a.G), dim3(256), 0, s, a, rec_row);
+    return hipGetLastError();
+}
+
+}  // namespace spinmc

@@ -9,7 +9,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import ISING, ISING_HC, ISING_TRI, POTTS, CPM, ReplicaDesc, Schedule, check, lib
+from ._lib import (CPM, ISING, ISING_HC, ISING_MSC, ISING_TRI, POTTS, ReplicaDesc, Schedule,
+                   check, lib)
 
 __all__ = ["Sampler", "ISING", "POTTS", "CPM", "MODES"]
 
@@ -29,7 +30,9 @@ class Sampler:
 
     ``replicas``: sequence of dicts with keys model (0 Ising, 1 Potts, 2 CPM,
     3 triangular-lattice Ising, 4 chain / square / cubic Ising with an extra
-    key Lz), Lx, Ly and the model's parameters (q, Jx,
+    key Lz, 5 a multispin-coded group of 32 square-lattice Ising replicas,
+    whose state is one uint32 word per site), Lx, Ly and the model's
+    parameters (q, Jx,
     Jy, h, beta, rid; CPM: n_cells as q, n_types,
     adhesion, cell_type, target_area, lambda_area, temperature and optionally
     cpm_range, 1 for the Moore 3x3 neighbourhood or 2 for 5x5).
@@ -71,7 +74,7 @@ class Sampler:
         check(lib().spinmc_create(descs, n, int(seed), 1 if init else 0, sh, C.byref(ctx)))
         self._keep = []
         self.ctx = ctx
-        self.R = n
+        self.R = lib().spinmc_num_replicas(ctx)  # 32 per multispin-coded group
         self.width = lib().spinmc_stats_width(ctx)
 
     # -------------------------------------------------------------- basics
@@ -95,7 +98,7 @@ class Sampler:
     def _elem(self, r):
         m = self.replicas[r].get("model", ISING)
         return {ISING: np.int8, ISING_TRI: np.int8, ISING_HC: np.int8, POTTS: np.uint8,
-                CPM: np.int32}[m]
+                CPM: np.int32, ISING_MSC: np.uint32}[m]
 
     def _shape(self, r):
         rep = self.replicas[r]
@@ -164,7 +167,7 @@ class Sampler:
 
     # ------------------------------------------------------------- timing
     KERNELS = {"stream_ising": 0, "resident": 1, "cpm_pass": 3, "stream_potts": 4, "tri_pass": 5,
-               "hc_pass": 6}
+               "hc_pass": 6, "msc_pass": 7}
 
     def profile(self, enable=True):
         check(lib().spinmc_profile(self.ctx, 1 if enable else 0))

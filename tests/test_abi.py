@@ -55,7 +55,7 @@ def _desc(**kw):
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(Lx=7), -1), (dict(Ly=0), -1), (dict(model=5), -1), (dict(beta=-1.0), -1),
+    (dict(Lx=7), -1), (dict(Ly=0), -1), (dict(model=6), -1), (dict(beta=-1.0), -1),
     (dict(beta=float("nan")), -1), (dict(model=1, q=1), -1), (dict(model=1, q=300), -1),
     (dict(model=1, q=200), -2), (dict(model=1, q=3, Jy=0.5), -2), (dict(h=float("inf")), -1),
     # triangular lattice: multiples of 3, one coupling
@@ -64,6 +64,8 @@ def _desc(**kw):
     # chain / cubic: Lx even, Ly and Lz 1 or even
     (dict(model=4, Lx=7), -1), (dict(model=4, Ly=3), -1), (dict(model=4, Lz=3), -1),
     (dict(model=4, Lz=-2), -1), (dict(model=4, Jy=0.5), -1),
+    # multispin coding: Lx a multiple of 8, Ly even
+    (dict(model=5, Lx=12), -1), (dict(model=5, Ly=7), -1), (dict(model=5, beta=-2.0), -1),
 ])
 def test_validation_precedes_device(L, kw, code):
     ctx = C.c_void_p()
