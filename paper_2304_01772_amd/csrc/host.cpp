@@ -156,6 +156,7 @@ struct spinmc_ctx {
     // multiple of 8, at most kCpmLdsCells cells per replica)
     bool cpm_quad = false, cpm_lds_reserved = false;
     int cpm_range = 1;  // 1: Moore 3x3, 4 colours; 2: 5x5, 9 colours
+    bool cpm_areas_dirty = false;  // set_state since the last area count
     // triangular-lattice Ising (and chain / cubic)
     bool tri = false;
     uint64_t* d_tab64 = nullptr;  // [R][14] thresholds ([G][18] multispin-coded)
@@ -436,6 +437,7 @@ int enqueue_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
 int cpm_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes);
 int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes);
 int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
+int cpm_recount_if_dirty(spinmc_ctx* c);
 int create_tri(const spinmc_replica_desc* d, int n, uint64_t seed, int init, void* stream,
                spinmc_ctx** out);
 int tri_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes);
@@ -897,6 +899,9 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
         cand.swap(keep);
     }
     if (cand.empty()) return fail(SPINMC_E_UNSUPPORTED, "autotune: no candidate schedule");
+    if (c->cpm) {  // current areas before they are saved
+        if (int rc = cpm_recount_if_dirty(c)) return rc;
+    }
     const spinmc_schedule saved_sched = c->sched;
     const uint64_t saved_t = c->t;
     // scratch copy of the state (lattices, sweep counter, CPM areas)
@@ -1500,12 +1505,18 @@ int cpm_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes) {
     if (e == hipSuccess)
         e = hipMemcpy(reinterpret_cast<int32_t*>(c->d_lat) + h.dev.lat_off, host, bytes,
                       hipMemcpyHostToDevice);
-    if (e == hipSuccess) {
-        CpmArgs a = cpm_args(c, nullptr);
-        e = launch_cpm_area_recount(a, c->n_tiles, c->total_cells, c->stream);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    // the areas are recounted once before the next sweep or measurement, so
+    // that setting every replica's state costs one count, not one per call
+    c->cpm_areas_dirty = true;
     return check_dev(c, e, "set_state");
+}
+
+int cpm_recount_if_dirty(spinmc_ctx* c) {
+    if (!c->cpm_areas_dirty) return SPINMC_OK;
+    CpmArgs a = cpm_args(c, nullptr);
+    hipError_t e = launch_cpm_area_recount(a, c->n_tiles, c->total_cells, c->stream);
+    if (e == hipSuccess) c->cpm_areas_dirty = false;
+    return check_dev(c, e, "area count");
 }
 
 int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
@@ -1524,6 +1535,7 @@ int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
         int rc = cpm_build_tiles(c);
         if (rc) return rc;
     }
+    if (int rc = cpm_recount_if_dirty(c)) return rc;
     CpmArgs a = cpm_args(c, stats);
     const size_t tab_bytes = align_up((size_t)8 * std::max(c->max_tab_n, 1), 16);
     const int threads = c->sched.wg_threads > 0 ? std::min(c->sched.wg_threads, 256) : 256;
@@ -1558,6 +1570,7 @@ int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
 }
 
 int cpm_measure(spinmc_ctx* c, int32_t* stats, double* obs) {
+    if (int rc = cpm_recount_if_dirty(c)) return rc;
     CpmArgs a = cpm_args(c, stats);
     hipError_t e = launch_fill_i32(stats, (size_t)c->R * c->width, 0, c->stream);
     if (e == hipSuccess) e = launch_cpm_stats(a, c->n_tiles, 0, c->stream);
