@@ -60,10 +60,18 @@ __global__ void __launch_bounds__(256) k_msc_init(MscArgs a) {
 }
 
 __global__ void __launch_bounds__(256) k_msc_pass8(MscArgs a, int c, int sweep_off) {
-    __shared__ uint64_t lt[kMscClasses];
     const int g = blockIdx.y;
-    if (threadIdx.x < kMscClasses) lt[threadIdx.x] = a.tab[(size_t)g * kMscClasses + threadIdx.x];
-    __syncthreads();
+    // W < T as a 32-bit compare: W <= T - 1 for 1 <= T <= 2^32, and never
+    // for T = 0 (uniform per class: scalar registers and scalar logic)
+    uint32_t tm1[kMscClasses];
+    bool never[kMscClasses];
+    const uint64_t* tg = a.tab + (size_t)g * kMscClasses;
+#pragma unroll
+    for (int i = 0; i < kMscClasses; ++i) {
+        const uint64_t T = tg[i];
+        never[i] = T == 0;
+        tm1[i] = T == 0 ? 0u : (uint32_t)(T - 1);
+    }
     const RepDev D = a.reps[g];
     const int Lx = D.Lx, Ly = D.Ly;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -95,15 +103,16 @@ __global__ void __launch_bounds__(256) k_msc_pass8(MscArgs a, int c, int sweep_o
         const uint32_t ax[3] = {~(al | ar), al ^ ar, al & ar};
         const uint32_t ay[3] = {~(au | ad), au ^ ad, au & ad};
         // for s = +1, Sx/2 + 1 is the agreeing count; for s = -1, 2 minus it
-        const uint64_t W = w[u];
+        const uint32_t W = w[u];
         uint32_t fp = 0u, fn = 0u;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
                 const uint32_t m = ax[i] & ay[j];
-                fp |= (W < lt[9 + 3 * i + j]) ? m : 0u;
-                fn |= (W < lt[3 * (2 - i) + (2 - j)]) ? m : 0u;
+                const int cp = 9 + 3 * i + j, cn = 3 * (2 - i) + (2 - j);
+                fp |= (W <= tm1[cp] && !never[cp]) ? m : 0u;
+                fn |= (W <= tm1[cn] && !never[cn]) ? m : 0u;
             }
         flip[o] = (s & fp) | (~s & fn);
     }
