@@ -211,3 +211,22 @@ def test_paper_setting_with_the_second_shell(S):
     for r in range(len(reps)):
         assert len(np.unique(smp.get_state(r))) < 37  # cells have vanished
     smp.close()
+
+
+def test_measure_right_after_set_state_counts_the_areas(S):
+    """set_state defers the area count: a measurement straight after setting
+    every replica's state (no sweep in between) still sees the new areas in
+    its energy, and a second round of set_state replaces them."""
+    J = JS["sorting"]
+    cases = [_random_case(500 + r, (16, 24), 9) for r in range(3)]
+    reps = [_rep(ids, J, ct, A, 1.5, 10.0, r) for r, (ids, ct, A) in enumerate(cases)]
+    smp = S(reps, 3, init=False)
+    for _ in range(2):
+        cases = [(np.roll(ids, 1, axis=1), ct, A) for ids, ct, A in cases]
+        for r, (ids, _, _) in enumerate(cases):
+            smp.set_state(r, ids)
+        stats, _ = smp.measure()
+        stats = stats.cpu().numpy()
+        for r, (ids, ct, A) in enumerate(cases):
+            assert np.array_equal(stats[r], orc.cpm_stats(ids, J, ct, A, 1.5))
+    smp.close()
