@@ -1715,9 +1715,36 @@ int tri_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
     return check_dev(c, e, "get_state");
 }
 
+// Resident schedule for unrecorded sweeps: every lattice in LDS (<= 64 KiB,
+// so that two workgroups fit a compute unit) and the span alignment.
+bool tri_resident_ok(const spinmc_ctx* c, const TriArgs& a, int* lds) {
+    if (c->sched.mode == 2) return false;  // streamed passes requested
+    size_t mx = 0;
+    for (const HostRep& h : c->reps) {
+        mx = std::max(mx, h.lat_bytes);
+        if (a.model == kModelIsingHC ? h.dev.Lx % 8 : h.dev.Lx % 12) return false;
+        if (h.lat_bytes % 4) return false;
+    }
+    if (mx > 64 * 1024) return false;
+    *lds = (int)align_up(mx, 16);
+    return true;
+}
+
 int tri_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
     TriArgs a = tri_args(c, stats);
     hipError_t e = hipSuccess;
+    int lds = 0;
+    if (re == 0 && tri_resident_ok(c, a, &lds)) {
+        // chunks of at most 1000 sweeps per launch; the counter advances after each
+        for (int done = 0; done < n && e == hipSuccess;) {
+            const int k = std::min(1000, n - done);
+            e = timed(c, SPINMC_K_RESIDENT,
+                      [&] { return launch_nat_resident(a, k, lds, c->stream); }, c->stream);
+            if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)k, c->stream);
+            done += k;
+        }
+        return check_dev(c, e, "sweep");
+    }
     const int n_rec = re > 0 ? n / re : 0;
     if (n_rec > 0) e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
     const bool hc = a.model == kModelIsingHC;

@@ -306,6 +306,93 @@ __global__ void k_tri_observables(TriArgs a, double* obs) {
     o[3] = M / N;
 }
 
+// All n_sweeps unrecorded sweeps in one launch, one workgroup per replica
+// with its lattice in LDS (the layout of global memory) and a barrier after
+// every colour pass: the same decisions as the streamed passes, without the
+// per-pass launches and lattice round trips.  Needs Lx % 12 == 0 for the
+// triangular lattice (the four sites of a Philox block in one row) and
+// Lx % 8 == 0 for the chain / cubic lattices.
+template <int MODEL>
+__global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps) {
+    extern __shared__ __align__(16) int8_t ls[];
+    __shared__ uint64_t lt[kTriClasses];
+    const int r = blockIdx.x;
+    const RepDev D = a.reps[r];
+    const int Lx = D.Lx, Ly = D.Ly, Lz = MODEL == kModelIsingHC ? D.q : 1;
+    const int n = Lx * Ly * Lz;
+    int8_t* lat = a.lat + D.lat_off;
+    if (threadIdx.x < kTriClasses) lt[threadIdx.x] = a.tab[(size_t)r * kTriClasses + threadIdx.x];
+    for (int i = threadIdx.x; i < n / 4; i += blockDim.x)
+        reinterpret_cast<uint32_t*>(ls)[i] = reinterpret_cast<const uint32_t*>(lat)[i];
+    __syncthreads();
+    const uint64_t t0 = *a.t_base;
+    constexpr int ncol = MODEL == kModelIsingHC ? 2 : 3;
+    const int nb = MODEL == kModelIsingHC ? n / 8 : n / 12;  // Philox blocks per pass
+    const int plane = Lx * Ly;
+    for (int sw = 0; sw < n_sweeps; ++sw) {
+        const uint64_t t = t0 + (uint64_t)sw;
+        for (int c = 0; c < ncol; ++c) {
+            const uint32_t p = (uint32_t)((uint64_t)ncol * t + (uint64_t)c);
+            for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+                uint32_t w[4];
+                philox4x32_10((uint32_t)b, p, D.rid, kTriTagMain, a.key0, a.key1, w);
+                if (MODEL == kModelIsingTri) {
+                    const int G = Lx / 12;
+                    const int y = b / G, x0 = 12 * (b - y * G), xc = (c + y) % 3;
+                    const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int x = x0 + xc + 3 * u;
+                        const int xl = x == 0 ? Lx - 1 : x - 1, xr = x + 1 == Lx ? 0 : x + 1;
+                        const int s = ls[y * Lx + x];
+                        const int S6 = ls[y * Lx + xl] + ls[y * Lx + xr] + ls[yu * Lx + x] +
+                                       ls[yd * Lx + x] + ls[yu * Lx + xr] + ls[yd * Lx + xl];
+                        if ((uint64_t)w[u] < lt[7 * (s > 0) + (S6 + 6) / 2])
+                            ls[y * Lx + x] = (int8_t)(-s);
+                    }
+                } else {
+                    const int row = (8 * b) / Lx;
+                    const int z = row / Ly, y = row - z * Ly;
+                    const int x0 = 8 * b - row * Lx, par = (c + y + z) & 1;
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int x = x0 + 2 * u + par;
+                        const int i = row * Lx + x;
+                        const int s = ls[i];
+                        int S = ls[row * Lx + (x == 0 ? Lx - 1 : x - 1)] +
+                                ls[row * Lx + (x + 1 == Lx ? 0 : x + 1)];
+                        if (Ly > 1)
+                            S += ls[(z * Ly + (y == 0 ? Ly - 1 : y - 1)) * Lx + x] +
+                                 ls[(z * Ly + (y + 1 == Ly ? 0 : y + 1)) * Lx + x];
+                        if (Lz > 1)
+                            S += ls[(z == 0 ? Lz - 1 : z - 1) * plane + y * Lx + x] +
+                                 ls[(z + 1 == Lz ? 0 : z + 1) * plane + y * Lx + x];
+                        if ((uint64_t)w[u] < lt[7 * (s > 0) + (S + 6) / 2]) ls[i] = (int8_t)(-s);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n / 4; i += blockDim.x)
+        reinterpret_cast<uint32_t*>(lat)[i] = reinterpret_cast<const uint32_t*>(ls)[i];
+}
+
+hipError_t launch_nat_resident(const TriArgs& a, int n_sweeps, int lds_bytes, hipStream_t s) {
+    if (a.model == kModelIsingHC) {
+        hipFuncSetAttribute((const void*)k_nat_resident<kModelIsingHC>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        hipLaunchKernelGGL(k_nat_resident<kModelIsingHC>, dim3(a.R), dim3(1024), lds_bytes, s, a,
+                           n_sweeps);
+    } else {
+        hipFuncSetAttribute((const void*)k_nat_resident<kModelIsingTri>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        hipLaunchKernelGGL(k_nat_resident<kModelIsingTri>, dim3(a.R), dim3(1024), lds_bytes, s, a,
+                           n_sweeps);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_tri_init(const TriArgs& a, hipStream_t s) {
     const int nb = (a.max_sites + 3) / 4;
     hipLaunchKernelGGL(k_tri_init, dim3((nb + 255) / 256, a.R), dim3(256), 0, s, a);

@@ -70,3 +70,23 @@ def test_hc_set_state_and_validation():
     for bad in (_rep(3, 2, 6, 1.0, 0.0, 0.5, 0), _rep(1, 1, 7, 1.0, 0.0, 0.5, 0)):
         with pytest.raises(Exception):
             Sampler([bad], 1)
+
+
+@pytest.mark.parametrize("mode", ["auto", "stream"])
+def test_hc_unrecorded_sweeps_resident_and_streamed(mode):
+    """As for the triangular lattice: resident (every Lx a multiple of 8,
+    lattices <= 64 KiB) unless the stream schedule is set; both equal the
+    oracle across two calls."""
+    from paper_2304_01772_amd.sampler import Sampler
+    shapes = [(1, 1, 64), (1, 16, 24), (32, 32, 32), (8, 6, 40)]
+    reps = [_rep(Lz, Ly, Lx, 0.8, 0.05, 0.3, 70 + i) for i, (Lz, Ly, Lx) in enumerate(shapes)]
+    smp = Sampler(reps, 22, init=True)
+    if mode == "stream":
+        smp.set_schedule(mode="stream")
+    init = [smp.get_state(r) for r in range(len(reps))]
+    smp.sweep(11)
+    smp.sweep(6)
+    for r in range(len(shapes)):
+        want, _ = orc.hc_run(init[r], 0.8, 0.05, 0.3, 22, 70 + r, 0, 17)
+        assert np.array_equal(smp.get_state(r), want), (mode, r)
+    smp.close()

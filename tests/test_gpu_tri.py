@@ -75,3 +75,23 @@ def test_tri_thresholds_and_set_state():
     with pytest.raises(Exception):
         smp.set_state(1, np.zeros((9, 12), np.int8))
     smp.close()
+
+
+@pytest.mark.parametrize("mode", ["auto", "stream"])
+def test_tri_unrecorded_sweeps_resident_and_streamed(mode):
+    """Unrecorded sweeps run resident in LDS (every Lx a multiple of 12,
+    lattices <= 64 KiB) unless the stream schedule is set; both equal the
+    oracle, across two calls (the sweep counter carries over)."""
+    from paper_2304_01772_amd.sampler import Sampler
+    shapes = [(12, 12), (96, 96), (30, 36), (180, 180)]
+    reps = [_rep(Ly, Lx, 1.0, 0.0, 0.2747, 60 + i) for i, (Ly, Lx) in enumerate(shapes)]
+    smp = Sampler(reps, 21, init=True)
+    if mode == "stream":
+        smp.set_schedule(mode="stream")
+    init = [smp.get_state(r) for r in range(len(reps))]
+    smp.sweep(13)
+    smp.sweep(7)
+    for r, (Ly, Lx) in enumerate(shapes):
+        want, _ = orc.tri_run(init[r], 1.0, 0.0, 0.2747, 21, 60 + r, 0, 20)
+        assert np.array_equal(smp.get_state(r), want), (mode, r)
+    smp.close()
