@@ -50,7 +50,7 @@ enum spinmc_model {
 enum spinmc_status {
     SPINMC_OK = 0,
     SPINMC_E_INVALID = -1,          /* bad argument (shape, range, NULL, NaN)          */
-    SPINMC_E_UNSUPPORTED = -2,      /* valid but not implemented by this build          */
+    SPINMC_E_UNSUPPORTED = -2,      /* valid but not implemented by this library        */
     SPINMC_E_NOMEM = -3,            /* device allocation failed; nothing leaked         */
     SPINMC_E_DEVICE = -4,           /* no usable GPU, or a device fault (ctx poisoned)  */
     SPINMC_E_NOT_REPRESENTABLE = -5,/* CPM energies not exact in the fixed-point scale */

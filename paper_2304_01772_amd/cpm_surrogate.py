@@ -1,7 +1,7 @@
 """Surrogate over Cellular Potts adhesion parameters: the 4-128-128-3 network
 of the Ising surrogate, trained on the library's own CPM runs of the paper's
 cell-sorting setting (Results, Table 2), steering an inverse problem with
-Monte Carlo as judge and fallback.
+Monte Carlo as arbiter and fallback.
 
 * inputs: (J_light_dark, J_dark_dark, J_cell_medium, k_BT) on a box around
   Table 2 (J_medium_medium = 0 and J_light_light = 2 fixed; every value on a

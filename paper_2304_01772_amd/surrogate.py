@@ -1,5 +1,5 @@
 """Learned surrogate of equilibrium Ising observables, trained on the
-sampler's own data, steering an inverse problem with Monte Carlo as judge
+sampler's own data, steering an inverse problem with Monte Carlo as arbiter
 and fallback.
 
 Pipeline (all device work in libspinmc kernels; this module marshals):

@@ -216,7 +216,7 @@ def test_paper_setting_with_the_second_shell(S):
 def test_measure_right_after_set_state_counts_the_areas(S):
     """set_state defers the area count: a measurement straight after setting
     every replica's state (no sweep in between) still sees the new areas in
-    its energy, and a second round of set_state replaces them."""
+    its energy, and a second batch of set_state calls replaces them."""
     J = JS["sorting"]
     cases = [_random_case(500 + r, (16, 24), 9) for r in range(3)]
     reps = [_rep(ids, J, ct, A, 1.5, 10.0, r) for r, (ids, ct, A) in enumerate(cases)]
