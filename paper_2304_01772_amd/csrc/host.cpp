@@ -1343,6 +1343,9 @@ CpmArgs cpm_args(spinmc_ctx* c, int32_t* stats) {
 // Row tiles: whole periods of the colouring (2 rows for the 2x2 sublattice,
 // 6 for the 3x3 one, which also keeps them even).
 int cpm_build_tiles(spinmc_ctx* c) {
+    // captured graphs refer to the tile buffer and its count
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
     std::vector<TileDev> tiles;
     const int period = c->cpm_range == 2 ? 6 : 2;
     for (int i = 0; i < c->R; ++i) {
@@ -1530,6 +1533,55 @@ int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
     return check_dev(c, e, "get_state");
 }
 
+// The snapshot copy and the colour pass of pass `col` of sweep `i` of a call.
+hipError_t cpm_enqueue_pass(spinmc_ctx* c, const CpmArgs& a, int i, int col, hipStream_t s) {
+    const size_t tab_bytes = align_up((size_t)8 * std::max(c->max_tab_n, 1), 16);
+    const int threads = c->sched.wg_threads > 0 ? std::min(c->sched.wg_threads, 256) : 256;
+    hipError_t e = launch_cpm_snapshot(a, c->total_cells, s);
+    if (e != hipSuccess) return e;
+    return timed(c, SPINMC_K_CPM_PASS, [&] {
+        if (c->cpm_range == 2)
+            return launch_cpm_pass5(a, c->n_tiles, col, i, threads, tab_bytes, s);
+        if (c->cpm_quad)
+            return launch_cpm_pass_quad(a, c->n_tiles, col, i, threads, (int)tab_bytes,
+                                        c->cpm_cell_cap, s);
+        return launch_cpm_pass(a, c->n_tiles, col, i, threads, tab_bytes, s);
+    }, s);
+}
+
+// One graph for a chunk of G unrecorded Monte Carlo steps (their snapshot
+// copies and colour passes; the device step counter advances by G at its
+// end), replayed instead of 2 n_col G direct launches.
+int cpm_chunk_graph(spinmc_ctx* c, int G, hipGraphExec_t* out) {
+    auto it = c->graphs.find(G);
+    if (it != c->graphs.end()) {
+        *out = it->second;
+        return SPINMC_OK;
+    }
+    int rc0 = ensure_side_streams(c);
+    if (rc0) return rc0;
+    CpmArgs a = cpm_args(c, nullptr);
+    const int n_col = c->cpm_range == 2 ? 9 : 4;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(c->cap[0], hipStreamCaptureModeRelaxed);
+    const bool prof = c->prof;
+    c->prof = false;
+    for (int i = 0; i < G && e == hipSuccess; ++i)
+        for (int col = 0; col < n_col && e == hipSuccess; ++col)
+            e = cpm_enqueue_pass(c, a, i, col, c->cap[0]);
+    c->prof = prof;
+    if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)G, c->cap[0]);
+    hipError_t e2 = hipStreamEndCapture(c->cap[0], &g);
+    if (e == hipSuccess) e = e2;
+    hipGraphExec_t ex = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (g) hipGraphDestroy(g);
+    if (e != hipSuccess) return check_dev(c, e, "CPM graph capture");
+    c->graphs[G] = ex;
+    *out = ex;
+    return SPINMC_OK;
+}
+
 int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
     if (c->tiles_rows != c->sched.tile_rows) {
         int rc = cpm_build_tiles(c);
@@ -1538,30 +1590,32 @@ int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
     if (int rc = cpm_recount_if_dirty(c)) return rc;
     CpmArgs a = cpm_args(c, stats);
     const size_t tab_bytes = align_up((size_t)8 * std::max(c->max_tab_n, 1), 16);
-    const int threads = c->sched.wg_threads > 0 ? std::min(c->sched.wg_threads, 256) : 256;
     if (c->cpm_quad && !c->cpm_lds_reserved) {
         hipError_t er = cpm_reserve_lds(tab_bytes + (size_t)c->cpm_cell_cap * 5);
         if (er != hipSuccess) return check_dev(c, er, "CPM LDS reservation");
         c->cpm_lds_reserved = true;
     }
     hipError_t e = hipSuccess;
+    if (re == 0 && !c->prof && c->use_graphs) {
+        const int G = std::min(n, kGraphChunk);
+        const int full = n / G, rest = n - full * G;
+        hipGraphExec_t ex = nullptr;
+        int rc = cpm_chunk_graph(c, G, &ex);
+        if (rc) return rc;
+        for (int k = 0; k < full && e == hipSuccess; ++k) e = hipGraphLaunch(ex, c->stream);
+        if (e == hipSuccess && rest > 0) {
+            rc = cpm_chunk_graph(c, rest, &ex);
+            if (rc) return rc;
+            e = hipGraphLaunch(ex, c->stream);
+        }
+        return check_dev(c, e, "sweep (graph)");
+    }
     const int n_rec = re > 0 ? n / re : 0;
     if (n_rec > 0) e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
     const int n_col = c->cpm_range == 2 ? 9 : 4;
     for (int i = 0; i < n && e == hipSuccess; ++i) {
-        for (int col = 0; col < n_col && e == hipSuccess; ++col) {
-            e = launch_cpm_snapshot(a, c->total_cells, c->stream);
-            if (e == hipSuccess)
-                e = timed(c, SPINMC_K_CPM_PASS, [&] {
-                    if (c->cpm_range == 2)
-                        return launch_cpm_pass5(a, c->n_tiles, col, i, threads, tab_bytes,
-                                                c->stream);
-                    if (c->cpm_quad)
-                        return launch_cpm_pass_quad(a, c->n_tiles, col, i, threads,
-                                                    (int)tab_bytes, c->cpm_cell_cap, c->stream);
-                    return launch_cpm_pass(a, c->n_tiles, col, i, threads, tab_bytes, c->stream);
-                }, c->stream);
-        }
+        for (int col = 0; col < n_col && e == hipSuccess; ++col)
+            e = cpm_enqueue_pass(c, a, i, col, c->stream);
         if (e == hipSuccess && re > 0 && ((i + 1) % re) == 0)
             e = launch_cpm_stats(a, c->n_tiles, (i + 1) / re - 1, c->stream);
     }

@@ -230,3 +230,25 @@ def test_measure_right_after_set_state_counts_the_areas(S):
         for r, (ids, ct, A) in enumerate(cases):
             assert np.array_equal(stats[r], orc.cpm_stats(ids, J, ct, A, 1.5))
     smp.close()
+
+
+@pytest.mark.parametrize("cpm_range", [1, 2])
+def test_unrecorded_steps_replay_graphs(S, cpm_range):
+    """Unrecorded Monte Carlo steps replay captured graphs of whole chunks
+    (here 55 = 50 + 5 steps, then 3 more after a change of tile rows, which
+    drops the graphs): the states equal the oracle's."""
+    J = JS["sorting"]
+    shape = (24, 24) if cpm_range == 1 else (24, 30)
+    cases = [_random_case(800 + r, shape, 10) for r in range(2)]
+    reps = [dict(_rep(ids, J, ct, A, 1.0, 12.0, r), cpm_range=cpm_range)
+            for r, (ids, ct, A) in enumerate(cases)]
+    smp = S(reps, 5, init=False)
+    for r, (ids, _, _) in enumerate(cases):
+        smp.set_state(r, ids)
+    smp.sweep(55)
+    smp.set_schedule(mode="stream", tile_rows=6)
+    smp.sweep(3)
+    for r, (ids, ct, A) in enumerate(cases):
+        want, _, _ = orc.cpm_run(ids, J, ct, A, 1.0, 12.0, 5, r, 0, 58, nrange=cpm_range)
+        assert np.array_equal(smp.get_state(r), want), r
+    smp.close()
