@@ -633,6 +633,10 @@ PATH_PROBES = {
     "grad": lambda S, torch: grad_probe(S, torch),
     "tri": lambda S, torch: tri_probe(S, torch),
     "hc": lambda S, torch: hc_probe(S, torch),
+    # the streamed passes with more spins than the 256 MB last-level cache
+    # holds (302 and 268 MB)
+    "tri_large": lambda S, torch: tri_probe(S, torch, n_rep=8192, L=192, sweeps=50),
+    "hc_large": lambda S, torch: hc_probe(S, torch, n_rep=8192, sweeps=50),
     "msc": lambda S, torch: msc_probe(S, torch),
     "mlp": lambda S, torch: mlp_probe(torch),
     "dmc": lambda S, torch: dmc_probe(torch),

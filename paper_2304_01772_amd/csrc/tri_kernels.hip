@@ -70,62 +70,158 @@ __global__ void __launch_bounds__(256) k_tri_pass(TriArgs a, int c, int sweep_of
     }
 }
 
+// Span form of a pass (four sites of one Philox block per lane, byte
+// arithmetic in 32-bit words).  A spin byte is 0x01 (+1) or 0xFF (-1), so
+// v & 0x02020202 flags the -1 bytes of a word as 2 per byte.  Sums of such
+// flags stay below 16 per byte (at most six neighbours), so whole words add
+// without carries between bytes: one add chain gives 2n, n the number of -1
+// neighbours, at every byte position of a span.  The threshold class
+// 7 [s > 0] + (S + 6) / 2 (S the neighbour sum over the k neighbours present,
+// S = k - 2n) is then keyed by j = n + 8 [s < 0], read from a 16-entry table.
+namespace {
+constexpr uint32_t kNegFlag = 0x02020202u;
+
+__device__ __forceinline__ uint32_t abyte(uint32_t hi, uint32_t lo, uint32_t sel) {
+    return __builtin_amdgcn_alignbyte(hi, lo, sel);  // ({hi, lo} >> 8 sel)[31:0]
+}
+
+// entry j = n + 8 neg of the keyed table from the 14 classes, k neighbours
+__device__ __forceinline__ uint64_t keyed_threshold(const uint64_t* tab, int j, int k) {
+    const int n = j & 7, neg = j >> 3;
+    return n > k ? 0ull : tab[7 * (1 - neg) + (k + 6) / 2 - n];
+}
+
+// Triangular: S, U, Dn are the 12-byte spans [x0, x0 + 12) of rows y, y - 1,
+// y + 1; the own sites are x0 + xc + 3u.  hl = flags of (y, x0 - 1) and
+// (y + 1, x0 - 1) added, hr = those of (y, x0 + 12) and (y - 1, x0 + 12).
+// Neighbour flags at position o: S[o -+ 1], U[o], U[o + 1], Dn[o], Dn[o - 1],
+// i.e. (S + Dn) moved up one byte position, (S + U) moved down one, U + Dn
+// in place.  A funnel shift by xc bytes brings the own sites to byte
+// positions 0, 3, 6, 9; their flips are shifted back.  Bytes of other
+// positions may read values another lane is writing: they never reach an
+// own site's count.
+__device__ __forceinline__ void tri_span(uint32_t (&S)[3], const uint32_t (&U)[3],
+                                         const uint32_t (&Dn)[3], uint32_t hl, uint32_t hr,
+                                         uint32_t xc, const uint32_t (&w)[4],
+                                         const uint64_t* lt) {
+    uint32_t m[4], A[3], B[3], C[4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        m[i] = S[i] & kNegFlag;
+        const uint32_t mu = U[i] & kNegFlag, md = Dn[i] & kNegFlag;
+        A[i] = m[i] + md;
+        B[i] = m[i] + mu;
+        C[i] = mu + md;
+    }
+    m[3] = 0u;
+    C[0] += abyte(A[0], hl << 24, 3) + abyte(B[1], B[0], 1);
+    C[1] += abyte(A[1], A[0], 3) + abyte(B[2], B[1], 1);
+    C[2] += abyte(A[2], A[1], 3) + abyte(hr, B[2], 1);
+    C[3] = 0u;
+    // key bytes 2n + 16 [s < 0] with the own sites at bytes 0, 3, 6, 9
+    uint32_t K[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) K[i] = abyte(C[i + 1], C[i], xc) | (abyte(m[i + 1], m[i], xc) << 3);
+    const bool f0 = (uint64_t)w[0] < lt[(K[0] >> 1) & 15u];
+    const bool f1 = (uint64_t)w[1] < lt[(K[0] >> 25) & 15u];
+    const bool f2 = (uint64_t)w[2] < lt[(K[1] >> 17) & 15u];
+    const bool f3 = (uint64_t)w[3] < lt[(K[2] >> 9) & 15u];
+    // a flip negates the byte: s -> -s is s ^ 0xFE for s = +-1
+    const uint32_t F0 = (f0 ? 0xFEu : 0u) | (f1 ? 0xFE000000u : 0u);
+    const uint32_t F1 = f2 ? 0x00FE0000u : 0u;
+    const uint32_t F2 = f3 ? 0x0000FE00u : 0u;
+    if (xc == 0u) {
+        S[0] ^= F0;
+        S[1] ^= F1;
+        S[2] ^= F2;
+    } else {
+        const uint32_t sh = 4u - xc;  // a left shift by xc bytes
+        S[0] ^= abyte(F0, 0u, sh);
+        S[1] ^= abyte(F1, F0, sh);
+        S[2] ^= abyte(F2, F1, sh);
+    }
+}
+
+// Chain / square / cubic: S the 8-byte span [x0, x0 + 8) of the own row, the
+// own sites x0 + 2u + par; N0, N1 the added flags of the neighbouring rows
+// and planes over the span; hl, hr the flags of (x0 - 1) and (x0 + 8).
+__device__ __forceinline__ void hc_span(uint32_t (&S)[2], uint32_t N0, uint32_t N1, uint32_t hl,
+                                        uint32_t hr, uint32_t par, const uint32_t (&w)[4],
+                                        const uint64_t* lt) {
+    const uint32_t m0 = S[0] & kNegFlag, m1 = S[1] & kNegFlag;
+    const uint32_t K0 = (N0 + abyte(m0, hl << 24, 3) + abyte(m1, m0, 1)) | (m0 << 3);
+    const uint32_t K1 = (N1 + abyte(m1, m0, 3) + abyte(hr, m1, 1)) | (m1 << 3);
+    const uint32_t o0 = 8u * par, o1 = 16u + 8u * par;  // bit offsets of the own bytes
+    const bool f0 = (uint64_t)w[0] < lt[(K0 >> (o0 + 1u)) & 15u];
+    const bool f1 = (uint64_t)w[1] < lt[(K0 >> (o1 + 1u)) & 15u];
+    const bool f2 = (uint64_t)w[2] < lt[(K1 >> (o0 + 1u)) & 15u];
+    const bool f3 = (uint64_t)w[3] < lt[(K1 >> (o1 + 1u)) & 15u];
+    const uint32_t e0 = 0xFEu << o0, e1 = 0xFEu << o1;
+    S[0] ^= (f0 ? e0 : 0u) | (f1 ? e1 : 0u);
+    S[1] ^= (f2 ? e0 : 0u) | (f3 ? e1 : 0u);
+}
+
+// b / d for 0 <= b < 2^22, d >= 1: the FP32 estimate b (1/d) is within one
+// of the quotient there (relative error below 2^-22), one correction each way
+__device__ __forceinline__ int qdiv(int b, int d, bool small) {
+    if (!small) return b / d;
+    int q = (int)((float)b * __builtin_amdgcn_rcpf((float)d));
+    const int rem = b - (int)__umul24((uint32_t)q, (uint32_t)d);
+    q += rem >= d ? 1 : 0;
+    q -= rem < 0 ? 1 : 0;
+    return q;
+}
+
+__device__ __forceinline__ uint32_t ld32(const int8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
+__device__ __forceinline__ uint3 ld96(const int8_t* p) { return *reinterpret_cast<const uint3*>(p); }
+__device__ __forceinline__ uint2 ld64(const int8_t* p) { return *reinterpret_cast<const uint2*>(p); }
+__device__ __forceinline__ uint32_t negflag(const int8_t* p) { return (uint32_t)(uint8_t)*p & 2u; }
+}  // namespace
+
 // Lx a multiple of 12: the four sites of a Philox block lie in one row,
 // x = 12 j + xc + 3u (xc = (c + y) mod 3), inside the 12-byte span
 // [12 j, 12 j + 12) of rows y - 1, y, y + 1, which come in as dwords (plus one
 // halo byte at either end of row y, the right one of row y - 1 and the left
 // one of row y + 1).  The row-y span is written back whole: no other lane
 // writes it during the pass, and the other colours' bytes are unchanged.
-namespace {
-__device__ __forceinline__ int sbyte(const uint32_t (&v)[3], int i) {
-    return (int)(int8_t)(v[i >> 2] >> (8 * (i & 3)));
-}
-}  // namespace
-
 __global__ void __launch_bounds__(256) k_tri_pass12(TriArgs a, int c, int sweep_off) {
-    __shared__ uint64_t lt[kTriClasses];
+    __shared__ uint64_t lt[16];
     const int r = blockIdx.y;
-    if (threadIdx.x < kTriClasses) lt[threadIdx.x] = a.tab[(size_t)r * kTriClasses + threadIdx.x];
-    __syncthreads();
     const RepDev D = a.reps[r];
-    const int Lx = D.Lx, Ly = D.Ly, G = Lx / 12;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= Ly * G) return;
-    const int y = b / G, x0 = 12 * (b - y * G);
-    const int xc = (c + y) % 3;
+    const int Lx = D.Lx, Ly = D.Ly, G = Lx / 12, nb = Ly * G;
+    // lanes past the end compute the last block and store nothing (every lane
+    // reaches the barrier)
+    const int bt = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x * blockDim.x >= nb) return;  // whole workgroup past the end
+    const int b = bt < nb ? bt : nb - 1;
+    const int y = qdiv(b, G, nb < (1 << 22));
+    const int x0 = 12 * (b - (int)__umul24((uint32_t)y, (uint32_t)G));
     const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
     const int xl = x0 == 0 ? Lx - 1 : x0 - 1, xr = x0 + 12 == Lx ? 0 : x0 + 12;
+    // 32-bit offsets from the replica's base (rows and columns below 2^24,
+    // a lattice below 2^31 bytes)
     int8_t* lat = a.lat + D.lat_off;
-    const uint32_t* row = reinterpret_cast<const uint32_t*>(lat + (size_t)y * Lx + x0);
-    const uint32_t* up = reinterpret_cast<const uint32_t*>(lat + (size_t)yu * Lx + x0);
-    const uint32_t* dn = reinterpret_cast<const uint32_t*>(lat + (size_t)yd * Lx + x0);
-    uint32_t S[3] = {row[0], row[1], row[2]};
-    const uint32_t U[3] = {up[0], up[1], up[2]};
-    const uint32_t Dn[3] = {dn[0], dn[1], dn[2]};
-    const int sl = lat[(size_t)y * Lx + xl], sr = lat[(size_t)y * Lx + xr];
-    const int ur = lat[(size_t)yu * Lx + xr], dl = lat[(size_t)yd * Lx + xl];
+    const uint32_t orow = __umul24((uint32_t)y, (uint32_t)Lx);
+    const uint32_t oup = __umul24((uint32_t)yu, (uint32_t)Lx);
+    const uint32_t odn = __umul24((uint32_t)yd, (uint32_t)Lx);
+    const uint3 s3 = ld96(lat + (orow + x0)), u3 = ld96(lat + (oup + x0)),
+                d3 = ld96(lat + (odn + x0));
+    uint32_t S[3] = {s3.x, s3.y, s3.z};
+    const uint32_t U[3] = {u3.x, u3.y, u3.z};
+    const uint32_t Dn[3] = {d3.x, d3.y, d3.z};
+    const uint32_t hl = negflag(lat + (orow + xl)) + negflag(lat + (odn + xl));
+    const uint32_t hr = negflag(lat + (orow + xr)) + negflag(lat + (oup + xr));
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
     const uint32_t p = (uint32_t)(3 * t + (uint64_t)c);
     uint32_t w[4];
-    philox4x32_10((uint32_t)b, p, D.rid, 0u, a.key0, a.key1, w);
-    uint32_t flip[3] = {0u, 0u, 0u};
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int o = xc + 3 * u;  // offset of the site in the span, 0..11
-        const int s = sbyte(S, o);
-        const int left = o == 0 ? sl : sbyte(S, o - 1);
-        const int right = o == 11 ? sr : sbyte(S, o + 1);
-        const int upr = o == 11 ? ur : sbyte(U, o + 1);
-        const int dnl = o == 0 ? dl : sbyte(Dn, o - 1);
-        const int S6 = left + right + sbyte(U, o) + sbyte(Dn, o) + upr + dnl;
-        const int idx = 7 * (s > 0) + (S6 + 6) / 2;
-        // a flip negates the byte: s -> -s is s ^ 0xFE for s = +-1
-        if ((uint64_t)w[u] < lt[idx]) flip[o >> 2] |= 0xFEu << (8 * (o & 3));
-    }
-    uint32_t* rw = reinterpret_cast<uint32_t*>(lat + (size_t)y * Lx + x0);
-    rw[0] = S[0] ^ flip[0];
-    rw[1] = S[1] ^ flip[1];
-    rw[2] = S[2] ^ flip[2];
+    philox4x32_10((uint32_t)b, p, D.rid, kTriTagMain, a.key0, a.key1, w);
+    // the table after the loads and the random words: its latency overlaps theirs
+    if (threadIdx.x < 16)
+        lt[threadIdx.x] = keyed_threshold(a.tab + (size_t)r * kTriClasses, threadIdx.x, 6);
+    __syncthreads();
+    tri_span(S, U, Dn, hl, hr, (uint32_t)((c + y) % 3), w, lt);
+    if (bt >= nb) return;
+    *reinterpret_cast<uint3*>(lat + (orow + x0)) = make_uint3(S[0], S[1], S[2]);
 }
 
 // [M, Bh, Bv, Bd]: wave sums of each lane's sites, one atomic per wave and
@@ -206,56 +302,53 @@ __global__ void __launch_bounds__(256) k_hc_pass(TriArgs a, int c, int sweep_off
 // planes (z +- 1) come in as dword pairs, plus the halo bytes x0 - 1 and
 // x0 + 8 of the own row.  The own span is written back whole (its other
 // colour's bytes unchanged; no other lane writes it during the pass).
-namespace {
-__device__ __forceinline__ int sbyte2(uint2 v, int i) {
-    return (int)(int8_t)((i < 4 ? v.x : v.y) >> (8 * (i & 3)));
-}
-}  // namespace
-
 __global__ void __launch_bounds__(256) k_hc_pass8(TriArgs a, int c, int sweep_off) {
-    __shared__ uint64_t lt[kTriClasses];
+    __shared__ uint64_t lt[16];
     const int r = blockIdx.y;
-    if (threadIdx.x < kTriClasses) lt[threadIdx.x] = a.tab[(size_t)r * kTriClasses + threadIdx.x];
-    __syncthreads();
     const RepDev D = a.reps[r];
     const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, plane = Lx * Ly;
     const int nb = plane * Lz / 8;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
-    const int row = (8 * b) / Lx;  // z Ly + y
-    const int z = row / Ly, y = row - z * Ly;
-    const int x0 = 8 * b - row * Lx;
-    const int par = (c + y + z) & 1;
+    const int bt = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x * blockDim.x >= nb) return;  // whole workgroup past the end
+    const int b = bt < nb ? bt : nb - 1;        // see k_tri_pass12
+    const bool small = 8 * (int64_t)nb < (1 << 22);
+    const int row = qdiv(8 * b, Lx, small);  // z Ly + y
+    const int z = qdiv(row, Ly, small), y = row - (int)__umul24((uint32_t)z, (uint32_t)Ly);
+    // 32-bit offsets from the replica's base (a lattice below 2^31 bytes)
+    const uint32_t orow = (uint32_t)row * (uint32_t)Lx;
+    const int x0 = 8 * b - (int)orow;
     int8_t* lat = a.lat + D.lat_off;
-    const size_t own = (size_t)row * Lx + x0;
-    const uint2 S = *reinterpret_cast<const uint2*>(lat + own);
-    const int hl = lat[(size_t)row * Lx + (x0 == 0 ? Lx - 1 : x0 - 1)];
-    const int hr = lat[(size_t)row * Lx + (x0 + 8 == Lx ? 0 : x0 + 8)];
-    uint2 Yu = make_uint2(0u, 0u), Yd = Yu, Zu = Yu, Zd = Yu;
+    const uint32_t own = orow + x0;
+    const uint2 S2 = ld64(lat + own);
+    uint32_t S[2] = {S2.x, S2.y};
+    const uint32_t hl = negflag(lat + (orow + (x0 == 0 ? Lx - 1 : x0 - 1)));
+    const uint32_t hr = negflag(lat + (orow + (x0 + 8 == Lx ? 0 : x0 + 8)));
+    uint32_t N0 = 0u, N1 = 0u;
     if (Ly > 1) {
-        Yu = *reinterpret_cast<const uint2*>(lat + (size_t)(z * Ly + wrapt(y - 1, Ly)) * Lx + x0);
-        Yd = *reinterpret_cast<const uint2*>(lat + (size_t)(z * Ly + wrapt(y + 1, Ly)) * Lx + x0);
+        const uint32_t zr = (uint32_t)(z * Ly);
+        const uint2 vu = ld64(lat + ((zr + wrapt(y - 1, Ly)) * (uint32_t)Lx + x0));
+        const uint2 vd = ld64(lat + ((zr + wrapt(y + 1, Ly)) * (uint32_t)Lx + x0));
+        N0 += (vu.x & kNegFlag) + (vd.x & kNegFlag);
+        N1 += (vu.y & kNegFlag) + (vd.y & kNegFlag);
     }
     if (Lz > 1) {
-        Zu = *reinterpret_cast<const uint2*>(lat + (size_t)wrapt(z - 1, Lz) * plane + own - (size_t)z * plane);
-        Zd = *reinterpret_cast<const uint2*>(lat + (size_t)wrapt(z + 1, Lz) * plane + own - (size_t)z * plane);
+        const uint32_t in_plane = own - (uint32_t)(z * plane);
+        const uint2 vu = ld64(lat + ((uint32_t)(wrapt(z - 1, Lz) * plane) + in_plane));
+        const uint2 vd = ld64(lat + ((uint32_t)(wrapt(z + 1, Lz) * plane) + in_plane));
+        N0 += (vu.x & kNegFlag) + (vd.x & kNegFlag);
+        N1 += (vu.y & kNegFlag) + (vd.y & kNegFlag);
     }
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
     const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
     uint32_t w[4];
     philox4x32_10((uint32_t)b, p, D.rid, kTriTagMain, a.key0, a.key1, w);
-    uint32_t flip[2] = {0u, 0u};
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int o = 2 * u + par;
-        const int s = sbyte2(S, o);
-        int Sn = (o == 0 ? hl : sbyte2(S, o - 1)) + (o == 7 ? hr : sbyte2(S, o + 1));
-        if (Ly > 1) Sn += sbyte2(Yu, o) + sbyte2(Yd, o);
-        if (Lz > 1) Sn += sbyte2(Zu, o) + sbyte2(Zd, o);
-        const int idx = 7 * (s > 0) + (Sn + 6) / 2;
-        if ((uint64_t)w[u] < lt[idx]) flip[o >> 2] |= 0xFEu << (8 * (o & 3));
-    }
-    *reinterpret_cast<uint2*>(lat + own) = make_uint2(S.x ^ flip[0], S.y ^ flip[1]);
+    if (threadIdx.x < 16)
+        lt[threadIdx.x] = keyed_threshold(a.tab + (size_t)r * kTriClasses, threadIdx.x,
+                                          2 + 2 * (Ly > 1) + 2 * (Lz > 1));
+    __syncthreads();
+    hc_span(S, N0, N1, hl, hr, (uint32_t)((c + y + z) & 1), w, lt);
+    if (bt >= nb) return;
+    *reinterpret_cast<uint2*>(lat + own) = make_uint2(S[0], S[1]);
 }
 
 // [M, Bx, By, Bz] of the chain / square / cubic lattices.
@@ -315,13 +408,16 @@ __global__ void k_tri_observables(TriArgs a, double* obs) {
 template <int MODEL>
 __global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps) {
     extern __shared__ __align__(16) int8_t ls[];
-    __shared__ uint64_t lt[kTriClasses];
+    __shared__ uint64_t lt[16];
     const int r = blockIdx.x;
     const RepDev D = a.reps[r];
     const int Lx = D.Lx, Ly = D.Ly, Lz = MODEL == kModelIsingHC ? D.q : 1;
     const int n = Lx * Ly * Lz;
     int8_t* lat = a.lat + D.lat_off;
-    if (threadIdx.x < kTriClasses) lt[threadIdx.x] = a.tab[(size_t)r * kTriClasses + threadIdx.x];
+    if (threadIdx.x < 16)
+        lt[threadIdx.x] = keyed_threshold(
+            a.tab + (size_t)r * kTriClasses, threadIdx.x,
+            MODEL == kModelIsingHC ? 2 + 2 * (Ly > 1) + 2 * (Lz > 1) : 6);
     for (int i = threadIdx.x; i < n / 4; i += blockDim.x)
         reinterpret_cast<uint32_t*>(ls)[i] = reinterpret_cast<const uint32_t*>(lat)[i];
     __syncthreads();
@@ -338,37 +434,47 @@ __global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps) 
                 philox4x32_10((uint32_t)b, p, D.rid, kTriTagMain, a.key0, a.key1, w);
                 if (MODEL == kModelIsingTri) {
                     const int G = Lx / 12;
-                    const int y = b / G, x0 = 12 * (b - y * G), xc = (c + y) % 3;
+                    const int y = qdiv(b, G, true), x0 = 12 * (b - y * G);  // b < 2^16
                     const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int x = x0 + xc + 3 * u;
-                        const int xl = x == 0 ? Lx - 1 : x - 1, xr = x + 1 == Lx ? 0 : x + 1;
-                        const int s = ls[y * Lx + x];
-                        const int S6 = ls[y * Lx + xl] + ls[y * Lx + xr] + ls[yu * Lx + x] +
-                                       ls[yd * Lx + x] + ls[yu * Lx + xr] + ls[yd * Lx + xl];
-                        if ((uint64_t)w[u] < lt[7 * (s > 0) + (S6 + 6) / 2])
-                            ls[y * Lx + x] = (int8_t)(-s);
-                    }
+                    const int xl = x0 == 0 ? Lx - 1 : x0 - 1, xr = x0 + 12 == Lx ? 0 : x0 + 12;
+                    int8_t* row = ls + y * Lx;
+                    const int8_t* up = ls + yu * Lx;
+                    const int8_t* dn = ls + yd * Lx;
+                    uint32_t S[3] = {ld32(row + x0), ld32(row + x0 + 4), ld32(row + x0 + 8)};
+                    const uint32_t U[3] = {ld32(up + x0), ld32(up + x0 + 4), ld32(up + x0 + 8)};
+                    const uint32_t Dn[3] = {ld32(dn + x0), ld32(dn + x0 + 4), ld32(dn + x0 + 8)};
+                    const uint32_t hl = negflag(row + xl) + negflag(dn + xl);
+                    const uint32_t hr = negflag(row + xr) + negflag(up + xr);
+                    tri_span(S, U, Dn, hl, hr, (uint32_t)((c + y) % 3), w, lt);
+                    uint32_t* rw = reinterpret_cast<uint32_t*>(row + x0);
+                    rw[0] = S[0];
+                    rw[1] = S[1];
+                    rw[2] = S[2];
                 } else {
-                    const int row = (8 * b) / Lx;
-                    const int z = row / Ly, y = row - z * Ly;
-                    const int x0 = 8 * b - row * Lx, par = (c + y + z) & 1;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const int x = x0 + 2 * u + par;
-                        const int i = row * Lx + x;
-                        const int s = ls[i];
-                        int S = ls[row * Lx + (x == 0 ? Lx - 1 : x - 1)] +
-                                ls[row * Lx + (x + 1 == Lx ? 0 : x + 1)];
-                        if (Ly > 1)
-                            S += ls[(z * Ly + (y == 0 ? Ly - 1 : y - 1)) * Lx + x] +
-                                 ls[(z * Ly + (y + 1 == Ly ? 0 : y + 1)) * Lx + x];
-                        if (Lz > 1)
-                            S += ls[(z == 0 ? Lz - 1 : z - 1) * plane + y * Lx + x] +
-                                 ls[(z + 1 == Lz ? 0 : z + 1) * plane + y * Lx + x];
-                        if ((uint64_t)w[u] < lt[7 * (s > 0) + (S + 6) / 2]) ls[i] = (int8_t)(-s);
+                    const int row = qdiv(8 * b, Lx, true);  // 8 b < 2^16
+                    const int z = qdiv(row, Ly, true), y = row - z * Ly;
+                    const int x0 = 8 * b - row * Lx;
+                    int8_t* own = ls + row * Lx + x0;
+                    const uint2 S2 = ld64(own);
+                    uint32_t S[2] = {S2.x, S2.y};
+                    const uint32_t hl = negflag(ls + row * Lx + (x0 == 0 ? Lx - 1 : x0 - 1));
+                    const uint32_t hr = negflag(ls + row * Lx + (x0 + 8 == Lx ? 0 : x0 + 8));
+                    uint32_t N0 = 0u, N1 = 0u;
+                    if (Ly > 1) {
+                        const uint2 vu = ld64(ls + (z * Ly + (y == 0 ? Ly - 1 : y - 1)) * Lx + x0);
+                        const uint2 vd = ld64(ls + (z * Ly + (y + 1 == Ly ? 0 : y + 1)) * Lx + x0);
+                        N0 += (vu.x & kNegFlag) + (vd.x & kNegFlag);
+                        N1 += (vu.y & kNegFlag) + (vd.y & kNegFlag);
                     }
+                    if (Lz > 1) {
+                        const int ip = y * Lx + x0;
+                        const uint2 vu = ld64(ls + (z == 0 ? Lz - 1 : z - 1) * plane + ip);
+                        const uint2 vd = ld64(ls + (z + 1 == Lz ? 0 : z + 1) * plane + ip);
+                        N0 += (vu.x & kNegFlag) + (vd.x & kNegFlag);
+                        N1 += (vu.y & kNegFlag) + (vd.y & kNegFlag);
+                    }
+                    hc_span(S, N0, N1, hl, hr, (uint32_t)((c + y + z) & 1), w, lt);
+                    *reinterpret_cast<uint2*>(own) = make_uint2(S[0], S[1]);
                 }
             }
             __syncthreads();
