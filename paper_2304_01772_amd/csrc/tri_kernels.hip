@@ -172,6 +172,13 @@ __device__ __forceinline__ int qdiv(int b, int d, bool small) {
     return q;
 }
 
+// Workgroup w of a 1-D grid of n runs on XCD w mod 8 (round-robin
+// dispatch); the logical index (w mod 8) n/8 + w/8 keeps consecutive logical
+// workgroups -- neighbouring spans of one replica -- on one XCD and its L2.
+__device__ __forceinline__ int xcd_logical(int w, int n) {
+    return (n & 7) ? w : (w & 7) * (n >> 3) + (w >> 3);
+}
+
 __device__ __forceinline__ uint32_t ld32(const int8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
 __device__ __forceinline__ uint3 ld96(const int8_t* p) { return *reinterpret_cast<const uint3*>(p); }
 __device__ __forceinline__ uint2 ld64(const int8_t* p) { return *reinterpret_cast<const uint2*>(p); }
@@ -184,44 +191,62 @@ __device__ __forceinline__ uint32_t negflag(const int8_t* p) { return (uint32_t)
 // halo byte at either end of row y, the right one of row y - 1 and the left
 // one of row y + 1).  The row-y span is written back whole: no other lane
 // writes it during the pass, and the other colours' bytes are unchanged.
-__global__ void __launch_bounds__(256) k_tri_pass12(TriArgs a, int c, int sweep_off) {
+// A lane takes NB Philox blocks, 256 apart (a wave's loads of one block
+// index stay contiguous), their loads all in flight together: NB = 2 for
+// large passes (see launch_tri_pass), 1 otherwise.
+// The grid is 1-D: gx workgroups per replica, replica-major in logical order.
+template <int NB>
+__global__ void __launch_bounds__(256) k_tri_pass12(TriArgs a, int c, int sweep_off, int gx) {
     __shared__ uint64_t lt[16];
-    const int r = blockIdx.y;
+    const int wl = xcd_logical((int)blockIdx.x, (int)gridDim.x);
+    const int r = wl / gx, wx = wl - r * gx;
     const RepDev D = a.reps[r];
     const int Lx = D.Lx, Ly = D.Ly, G = Lx / 12, nb = Ly * G;
-    // lanes past the end compute the last block and store nothing (every lane
-    // reaches the barrier)
-    const int bt = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x * blockDim.x >= nb) return;  // whole workgroup past the end
-    const int b = bt < nb ? bt : nb - 1;
-    const int y = qdiv(b, G, nb < (1 << 22));
-    const int x0 = 12 * (b - (int)__umul24((uint32_t)y, (uint32_t)G));
-    const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
-    const int xl = x0 == 0 ? Lx - 1 : x0 - 1, xr = x0 + 12 == Lx ? 0 : x0 + 12;
-    // 32-bit offsets from the replica's base (rows and columns below 2^24,
-    // a lattice below 2^31 bytes)
+    const int bt = NB * wx * 256 + (int)threadIdx.x;  // block k: bt + 256 k
+    if (NB * wx * 256 >= nb) return;  // whole workgroup past the end
     int8_t* lat = a.lat + D.lat_off;
-    const uint32_t orow = __umul24((uint32_t)y, (uint32_t)Lx);
-    const uint32_t oup = __umul24((uint32_t)yu, (uint32_t)Lx);
-    const uint32_t odn = __umul24((uint32_t)yd, (uint32_t)Lx);
-    const uint3 s3 = ld96(lat + (orow + x0)), u3 = ld96(lat + (oup + x0)),
-                d3 = ld96(lat + (odn + x0));
-    uint32_t S[3] = {s3.x, s3.y, s3.z};
-    const uint32_t U[3] = {u3.x, u3.y, u3.z};
-    const uint32_t Dn[3] = {d3.x, d3.y, d3.z};
-    const uint32_t hl = negflag(lat + (orow + xl)) + negflag(lat + (odn + xl));
-    const uint32_t hr = negflag(lat + (orow + xr)) + negflag(lat + (oup + xr));
+    const bool small = nb < (1 << 22);
+    // blocks past the end compute the last block and store nothing (every
+    // lane reaches the barrier)
+    uint32_t S[NB][3], U[NB][3], Dn[NB][3], hl[NB], hr[NB], orow[NB], x0[NB], xc[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int b = bt + 256 * k < nb ? bt + 256 * k : nb - 1;
+        const int y = qdiv(b, G, small);
+        const int x = 12 * (b - (int)__umul24((uint32_t)y, (uint32_t)G));
+        const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
+        const int xl = x == 0 ? Lx - 1 : x - 1, xr = x + 12 == Lx ? 0 : x + 12;
+        // 32-bit offsets from the replica's base (rows and columns below
+        // 2^24, a lattice below 2^31 bytes)
+        const uint32_t o = __umul24((uint32_t)y, (uint32_t)Lx);
+        const uint32_t ou = __umul24((uint32_t)yu, (uint32_t)Lx);
+        const uint32_t od = __umul24((uint32_t)yd, (uint32_t)Lx);
+        const uint3 s3 = ld96(lat + (o + x)), u3 = ld96(lat + (ou + x)), d3 = ld96(lat + (od + x));
+        S[k][0] = s3.x; S[k][1] = s3.y; S[k][2] = s3.z;
+        U[k][0] = u3.x; U[k][1] = u3.y; U[k][2] = u3.z;
+        Dn[k][0] = d3.x; Dn[k][1] = d3.y; Dn[k][2] = d3.z;
+        hl[k] = negflag(lat + (o + xl)) + negflag(lat + (od + xl));
+        hr[k] = negflag(lat + (o + xr)) + negflag(lat + (ou + xr));
+        orow[k] = o;
+        x0[k] = (uint32_t)x;
+        xc[k] = (uint32_t)((c + y) % 3);
+    }
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
     const uint32_t p = (uint32_t)(3 * t + (uint64_t)c);
-    uint32_t w[4];
-    philox4x32_10((uint32_t)b, p, D.rid, kTriTagMain, a.key0, a.key1, w);
+    uint32_t w[NB][4];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        philox4x32_10((uint32_t)(bt + 256 * k), p, D.rid, kTriTagMain, a.key0, a.key1, w[k]);
     // the table after the loads and the random words: its latency overlaps theirs
     if (threadIdx.x < 16)
         lt[threadIdx.x] = keyed_threshold(a.tab + (size_t)r * kTriClasses, threadIdx.x, 6);
     __syncthreads();
-    tri_span(S, U, Dn, hl, hr, (uint32_t)((c + y) % 3), w, lt);
-    if (bt >= nb) return;
-    *reinterpret_cast<uint3*>(lat + (orow + x0)) = make_uint3(S[0], S[1], S[2]);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        tri_span(S[k], U[k], Dn[k], hl[k], hr[k], xc[k], w[k], lt);
+        if (bt + 256 * k < nb)
+            *reinterpret_cast<uint3*>(lat + (orow[k] + x0[k])) = make_uint3(S[k][0], S[k][1], S[k][2]);
+    }
 }
 
 // [M, Bh, Bv, Bd]: wave sums of each lane's sites, one atomic per wave and
@@ -302,53 +327,65 @@ __global__ void __launch_bounds__(256) k_hc_pass(TriArgs a, int c, int sweep_off
 // planes (z +- 1) come in as dword pairs, plus the halo bytes x0 - 1 and
 // x0 + 8 of the own row.  The own span is written back whole (its other
 // colour's bytes unchanged; no other lane writes it during the pass).
-__global__ void __launch_bounds__(256) k_hc_pass8(TriArgs a, int c, int sweep_off) {
+template <int NB>
+__global__ void __launch_bounds__(256) k_hc_pass8(TriArgs a, int c, int sweep_off, int gx) {
     __shared__ uint64_t lt[16];
-    const int r = blockIdx.y;
+    const int wl = xcd_logical((int)blockIdx.x, (int)gridDim.x);  // see k_tri_pass12
+    const int r = wl / gx, wx = wl - r * gx;
     const RepDev D = a.reps[r];
     const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, plane = Lx * Ly;
     const int nb = plane * Lz / 8;
-    const int bt = blockIdx.x * blockDim.x + threadIdx.x;
-    if (blockIdx.x * blockDim.x >= nb) return;  // whole workgroup past the end
-    const int b = bt < nb ? bt : nb - 1;        // see k_tri_pass12
+    const int bt = NB * wx * 256 + (int)threadIdx.x;  // block k: bt + 256 k
+    if (NB * wx * 256 >= nb) return;  // whole workgroup past the end
     const bool small = 8 * (int64_t)nb < (1 << 22);
-    const int row = qdiv(8 * b, Lx, small);  // z Ly + y
-    const int z = qdiv(row, Ly, small), y = row - (int)__umul24((uint32_t)z, (uint32_t)Ly);
-    // 32-bit offsets from the replica's base (a lattice below 2^31 bytes)
-    const uint32_t orow = (uint32_t)row * (uint32_t)Lx;
-    const int x0 = 8 * b - (int)orow;
     int8_t* lat = a.lat + D.lat_off;
-    const uint32_t own = orow + x0;
-    const uint2 S2 = ld64(lat + own);
-    uint32_t S[2] = {S2.x, S2.y};
-    const uint32_t hl = negflag(lat + (orow + (x0 == 0 ? Lx - 1 : x0 - 1)));
-    const uint32_t hr = negflag(lat + (orow + (x0 + 8 == Lx ? 0 : x0 + 8)));
-    uint32_t N0 = 0u, N1 = 0u;
-    if (Ly > 1) {
-        const uint32_t zr = (uint32_t)(z * Ly);
-        const uint2 vu = ld64(lat + ((zr + wrapt(y - 1, Ly)) * (uint32_t)Lx + x0));
-        const uint2 vd = ld64(lat + ((zr + wrapt(y + 1, Ly)) * (uint32_t)Lx + x0));
-        N0 += (vu.x & kNegFlag) + (vd.x & kNegFlag);
-        N1 += (vu.y & kNegFlag) + (vd.y & kNegFlag);
-    }
-    if (Lz > 1) {
-        const uint32_t in_plane = own - (uint32_t)(z * plane);
-        const uint2 vu = ld64(lat + ((uint32_t)(wrapt(z - 1, Lz) * plane) + in_plane));
-        const uint2 vd = ld64(lat + ((uint32_t)(wrapt(z + 1, Lz) * plane) + in_plane));
-        N0 += (vu.x & kNegFlag) + (vd.x & kNegFlag);
-        N1 += (vu.y & kNegFlag) + (vd.y & kNegFlag);
+    uint32_t S[NB][2], N0[NB], N1[NB], hl[NB], hr[NB], own[NB], par[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        const int b = bt + 256 * k < nb ? bt + 256 * k : nb - 1;  // see k_tri_pass12
+        const int row = qdiv(8 * b, Lx, small);        // z Ly + y
+        const int z = qdiv(row, Ly, small), y = row - (int)__umul24((uint32_t)z, (uint32_t)Ly);
+        // 32-bit offsets from the replica's base (a lattice below 2^31 bytes)
+        const uint32_t orow = (uint32_t)row * (uint32_t)Lx;
+        const int x0 = 8 * b - (int)orow;
+        own[k] = orow + x0;
+        const uint2 S2 = ld64(lat + own[k]);
+        S[k][0] = S2.x;
+        S[k][1] = S2.y;
+        hl[k] = negflag(lat + (orow + (x0 == 0 ? Lx - 1 : x0 - 1)));
+        hr[k] = negflag(lat + (orow + (x0 + 8 == Lx ? 0 : x0 + 8)));
+        N0[k] = N1[k] = 0u;
+        if (Ly > 1) {
+            const uint32_t zr = (uint32_t)(z * Ly);
+            const uint2 vu = ld64(lat + ((zr + wrapt(y - 1, Ly)) * (uint32_t)Lx + x0));
+            const uint2 vd = ld64(lat + ((zr + wrapt(y + 1, Ly)) * (uint32_t)Lx + x0));
+            N0[k] += (vu.x & kNegFlag) + (vd.x & kNegFlag);
+            N1[k] += (vu.y & kNegFlag) + (vd.y & kNegFlag);
+        }
+        if (Lz > 1) {
+            const uint32_t in_plane = own[k] - (uint32_t)(z * plane);
+            const uint2 vu = ld64(lat + ((uint32_t)(wrapt(z - 1, Lz) * plane) + in_plane));
+            const uint2 vd = ld64(lat + ((uint32_t)(wrapt(z + 1, Lz) * plane) + in_plane));
+            N0[k] += (vu.x & kNegFlag) + (vd.x & kNegFlag);
+            N1[k] += (vu.y & kNegFlag) + (vd.y & kNegFlag);
+        }
+        par[k] = (uint32_t)((c + y + z) & 1);
     }
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
     const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
-    uint32_t w[4];
-    philox4x32_10((uint32_t)b, p, D.rid, kTriTagMain, a.key0, a.key1, w);
+    uint32_t w[NB][4];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        philox4x32_10((uint32_t)(bt + 256 * k), p, D.rid, kTriTagMain, a.key0, a.key1, w[k]);
     if (threadIdx.x < 16)
         lt[threadIdx.x] = keyed_threshold(a.tab + (size_t)r * kTriClasses, threadIdx.x,
                                           2 + 2 * (Ly > 1) + 2 * (Lz > 1));
     __syncthreads();
-    hc_span(S, N0, N1, hl, hr, (uint32_t)((c + y + z) & 1), w, lt);
-    if (bt >= nb) return;
-    *reinterpret_cast<uint2*>(lat + own) = make_uint2(S[0], S[1]);
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+        hc_span(S[k], N0[k], N1[k], hl[k], hr[k], par[k], w[k], lt);
+        if (bt + 256 * k < nb) *reinterpret_cast<uint2*>(lat + own[k]) = make_uint2(S[k][0], S[k][1]);
+    }
 }
 
 // [M, Bx, By, Bz] of the chain / square / cubic lattices.
@@ -506,15 +543,24 @@ hipError_t launch_tri_init(const TriArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_tri_pass(const TriArgs& a, int c, int sweep_off, hipStream_t s) {
-    if (a.model == kModelIsingHC && a.all_lx8)
-        hipLaunchKernelGGL(k_hc_pass8, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s, a,
-                           c, sweep_off);
-    else if (a.model == kModelIsingHC)
+    // two blocks per lane from 1 M blocks per pass (two for every lane the
+    // chip holds at once) when a replica has at least 2048 (four workgroups of
+    // 512 blocks: little lost to a ragged last one)
+    const bool two = (int64_t)a.max_blocks * a.R >= (int64_t)1 << 20 && a.max_blocks >= 2048;
+    const int gx1 = (a.max_blocks + 255) / 256, gx2 = (a.max_blocks + 511) / 512;
+    const dim3 g1((unsigned)gx1 * a.R), g2((unsigned)gx2 * a.R);
+    if (a.model == kModelIsingHC && a.all_lx8) {
+        if (two)
+            hipLaunchKernelGGL(k_hc_pass8<2>, g2, dim3(256), 0, s, a, c, sweep_off, gx2);
+        else
+            hipLaunchKernelGGL(k_hc_pass8<1>, g1, dim3(256), 0, s, a, c, sweep_off, gx1);
+    } else if (a.model == kModelIsingHC)
         hipLaunchKernelGGL(k_hc_pass, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s, a,
                            c, sweep_off);
+    else if (a.all_lx12 && two)
+        hipLaunchKernelGGL(k_tri_pass12<2>, g2, dim3(256), 0, s, a, c, sweep_off, gx2);
     else if (a.all_lx12)
-        hipLaunchKernelGGL(k_tri_pass12, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s,
-                           a, c, sweep_off);
+        hipLaunchKernelGGL(k_tri_pass12<1>, g1, dim3(256), 0, s, a, c, sweep_off, gx1);
     else
         hipLaunchKernelGGL(k_tri_pass, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s, a,
                            c, sweep_off);

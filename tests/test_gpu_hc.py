@@ -90,3 +90,24 @@ def test_hc_unrecorded_sweeps_resident_and_streamed(mode):
         want, _ = orc.hc_run(init[r], 0.8, 0.05, 0.3, 22, 70 + r, 0, 17)
         assert np.array_equal(smp.get_state(r), want), (mode, r)
     smp.close()
+
+
+def test_hc_large_batch_streamed_two_blocks_per_lane():
+    """Large streamed passes (1024 replicas of up to 32^3, 2^22 Philox blocks
+    per pass) give each lane two blocks; sampled replicas -- a square lattice, a
+    chain, a cubic box with a ragged last workgroup, and 32^3 tori -- equal
+    the oracle bit for bit."""
+    from paper_2304_01772_amd.sampler import Sampler
+    n_rep = 1024  # 1024 * 4096 blocks = 2^22
+    shapes = [(1, 40, 48), (1, 1, 64), (24, 20, 40)] + [(32, 32, 32)] * (n_rep - 3)
+    reps = [_rep(Lz, Ly, Lx, 1.0, 0.05, 0.2216546, 900 + i)
+            for i, (Lz, Ly, Lx) in enumerate(shapes)]
+    smp = Sampler(reps, 24, init=True)
+    smp.set_schedule(mode="stream")
+    picks = [0, 1, 2, 3, 511, n_rep - 1]
+    init = {r: smp.get_state(r) for r in picks}
+    smp.sweep(3)
+    for r in picks:
+        want, _ = orc.hc_run(init[r], 1.0, 0.05, 0.2216546, 24, 900 + r, 0, 3)
+        assert np.array_equal(smp.get_state(r), want), r
+    smp.close()

@@ -95,3 +95,22 @@ def test_tri_unrecorded_sweeps_resident_and_streamed(mode):
         want, _ = orc.tri_run(init[r], 1.0, 0.0, 0.2747, 21, 60 + r, 0, 20)
         assert np.array_equal(smp.get_state(r), want), (mode, r)
     smp.close()
+
+
+def test_tri_large_batch_streamed_two_blocks_per_lane():
+    """Large streamed passes (here 1366 replicas, 192 x 192 but the first
+    180 x 180, a ragged last workgroup; 2^22 Philox blocks per pass) give
+    each lane two blocks; sampled replicas equal the oracle bit for bit."""
+    from paper_2304_01772_amd.sampler import Sampler
+    n_rep = 1366  # 1366 * 3072 blocks >= 2^22
+    shapes = [(180, 180)] + [(192, 192)] * (n_rep - 1)
+    reps = [_rep(Ly, Lx, 1.0, 0.05, 0.2747, 500 + i) for i, (Ly, Lx) in enumerate(shapes)]
+    smp = Sampler(reps, 23, init=True)
+    smp.set_schedule(mode="stream")
+    picks = [0, 1, 683, n_rep - 1]
+    init = {r: smp.get_state(r) for r in picks}
+    smp.sweep(3)
+    for r in picks:
+        want, _ = orc.tri_run(init[r], 1.0, 0.05, 0.2747, 23, 500 + r, 0, 3)
+        assert np.array_equal(smp.get_state(r), want), r
+    smp.close()
