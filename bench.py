@@ -385,7 +385,8 @@ def grad_probe(Sampler, torch):
     samples = (n - burn) * len(reps)
     return {"config": "256 Ising 128x128, 5000 recorded sweeps, burn-in 1000",
             "recorded_sweep_attempts_per_ns": round(sites * n / (ms_sweep * 1e6), 1),
-            "kernel": "k_cov_grad", "bound": "hbm", "grad_call_us": round(ms_grad * 1e3, 2),
+            "kernel": "k_cov_partial + k_cov_final (chunk sums, then per replica)", "bound": "hbm",
+            "grad_call_us": round(ms_grad * 1e3, 2),
             "samples": samples, "algorithmic_bytes": 12 * samples,
             "achieved_GBs": round(12 * samples / (ms_grad * 1e-3) / 1e9, 1)}
 

@@ -206,7 +206,11 @@ int spinmc_measure(spinmc_ctx *ctx, void *dev_stats, void *dev_obs);
  * dev_grads [n][2][3] = d<O_o>/dtheta_j; dev_dtheta [n][3] =
  * sum_o dev_grad_out[n][o] * d<O_o>/dtheta (dev_grad_out FP64 [n][2],
  * required when dev_dtheta is set).  Moments are exact int64 sums combined
- * in FP64.  Ising-only contexts.  Asynchronous.                             */
+ * in FP64, so the result does not depend on how the sums are split.  From
+ * 512 samples on, the context keeps a device buffer of chunk sums,
+ * 104 B x n x ceil((n_rec - burn_in) / 64), allocated on the first call
+ * that needs it (SPINMC_E_NOMEM if that fails) and kept for later calls.
+ * Ising-only contexts.  Asynchronous.                                       */
 int spinmc_grad(spinmc_ctx *ctx, const void *dev_stats, int32_t n_rec, int32_t burn_in,
                 const void *dev_grad_out, void *dev_means, void *dev_grads, void *dev_dtheta);
 

@@ -12,6 +12,7 @@
 #include <string>
 #include <tuple>
 
+#include "grad_internal.hpp"
 #include "msc_internal.hpp"
 #include "tri_internal.hpp"
 #include <vector>
@@ -163,6 +164,8 @@ struct spinmc_ctx {
     // multispin-coded Ising: reps holds the G groups, R = 32 G
     bool msc = false;
     RepDev* d_reps_obs = nullptr;  // one square-lattice Ising entry per replica
+    long long* d_cov_part = nullptr;  // chunk sums of the split covariance estimator
+    size_t cov_part_n = 0;
     int cpm_cell_cap = 0;
     // kernel timing
     bool prof = false;
@@ -230,6 +233,9 @@ void free_all(spinmc_ctx* c) {
     c->d_tab64 = nullptr;
     hipFree(c->d_reps_obs);
     c->d_reps_obs = nullptr;
+    hipFree(c->d_cov_part);
+    c->d_cov_part = nullptr;
+    c->cov_part_n = 0;
     c->d_ctype = nullptr;
     c->d_target = nullptr;
     c->d_area = nullptr;
@@ -821,9 +827,30 @@ int spinmc_grad(spinmc_ctx* c, const void* dev_stats, int32_t n_rec, int32_t bur
     if (n_rec < 1 || burn_in < 0 || burn_in >= n_rec)
         return fail(SPINMC_E_INVALID, "grad: need 0 <= burn_in < n_rec");
     if (dtheta && !gout) return fail(SPINMC_E_INVALID, "grad: dtheta needs grad_out");
-    hipError_t e = launch_cov_grad(c->d_reps, c->R, (const int32_t*)dev_stats, n_rec, burn_in,
-                                   c->width, (const double*)gout, (double*)means, (double*)grads,
-                                   (double*)dtheta, c->stream);
+    const int n = n_rec - burn_in;
+    const bool split = n >= kCovSplitMin && (n + kCovChunk - 1) / kCovChunk <= 65535;
+    hipError_t e = hipSuccess;
+    if (split) {
+        const size_t need = cov_partial_entries(c->R, n);
+        if (need > c->cov_part_n) {  // grown on demand; hipFree waits for the device
+            hipFree(c->d_cov_part);
+            c->d_cov_part = nullptr;
+            c->cov_part_n = 0;
+            if (hipMalloc((void**)&c->d_cov_part, need * sizeof(long long)) != hipSuccess) {
+                (void)hipGetLastError();
+                c->d_cov_part = nullptr;
+                return fail(SPINMC_E_NOMEM, "grad: %zu bytes of chunk sums", need * sizeof(long long));
+            }
+            c->cov_part_n = need;
+        }
+        e = launch_cov_grad_split(c->d_reps, c->R, (const int32_t*)dev_stats, n_rec, burn_in,
+                                  c->width, (const double*)gout, (double*)means, (double*)grads,
+                                  (double*)dtheta, c->d_cov_part, c->stream);
+    } else {
+        e = launch_cov_grad(c->d_reps, c->R, (const int32_t*)dev_stats, n_rec, burn_in, c->width,
+                            (const double*)gout, (double*)means, (double*)grads, (double*)dtheta,
+                            c->stream);
+    }
     return check_dev(c, e, "grad");
 }
 

@@ -27,12 +27,15 @@ def _f32(v):
     return float(np.float32(v))
 
 
-def test_grad_parity_with_oracle(S):
+# 300 samples: one workgroup per replica; 1100: chunk sums of 64 samples
+# (the last chunk ragged) with one lane per replica, 6 of a wave's 64 lanes
+@pytest.mark.parametrize("n,burn", [(400, 100), (1300, 200)])
+def test_grad_parity_with_oracle(S, n, burn):
     rng = np.random.default_rng(0)
     reps = [dict(model=0, Lx=L, Ly=L, Jx=_f32(rng.uniform(0.3, 0.6)), Jy=_f32(rng.uniform(0.3, 0.6)),
                  h=_f32(rng.uniform(-0.05, 0.05)), beta=1.0, rid=i)
             for i, L in enumerate([4, 8, 16, 32, 32, 64])]
-    seed, n, burn = 3, 400, 100
+    seed = 3
     smp = S(reps, seed, init=True)
     st = smp.sweep(n, 1)
     means, grads, dth = smp.grad(st, burn, grad_out=torch.tensor([[1.0, -2.0]] * len(reps)))
