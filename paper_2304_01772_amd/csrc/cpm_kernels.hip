@@ -12,7 +12,7 @@
 // start of the pass (so the outcome does not depend on the order in which
 // the sites of one pass are visited), and accepted copies update the live
 // areas with integer atomics, which commute.
-#include "spinmc_internal.hpp"
+#include "cpm_internal.hpp"
 
 namespace spinmc {
 
@@ -216,11 +216,59 @@ __device__ __forceinline__ int sel8(const int (&v)[8], uint32_t j) {
     return (j & 4u) ? b1 : b0;
 }
 
+// The copy attempt of site x (id s, Moore neighbours nb in the order
+// (dy, dx) = (-1,-1) (-1,0) (-1,1) (0,-1) (0,1) (1,-1) (1,0) (1,1)) with main
+// word `word` (bits 0..2 the neighbour, bits 16..31 the prefix r of W) and
+// within-colour index k (the fallback counter): the id to copy, or -1.
+__device__ __forceinline__ int cpm_decide(const CpmArgs& a, const RepDev& R, const int (&nb)[8],
+                                          int s, uint32_t word, uint32_t k, uint32_t p,
+                                          const uint32_t* qthr, const int32_t* lsa,
+                                          const int8_t* lty, const int32_t* ljs) {
+    const int nt = R.n_types;
+    const int tg = sel8(nb, word & 7u);
+    if (tg == s) return -1;
+    const int ts = lty[s] * nt, tt = lty[tg] * nt;
+    int kadh = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int m = nb[j];
+        const int tm = lty[m];
+        kadh += (tg != m) ? ljs[tt + tm] : 0;
+        kadh -= (s != m) ? ljs[ts + tm] : 0;
+    }
+    int64_t karea = 0;
+    if (tg != 0) karea += 2 * (int64_t)lsa[tg] + 1;
+    if (s != 0) karea += -2 * (int64_t)lsa[s] + 1;
+    const int64_t kk = (int64_t)kadh + R.LS * karea;
+    bool acc;
+    if (kk <= 0) {
+        acc = true;
+    } else if (kk >= R.K0) {
+        acc = false;
+    } else {
+        uint32_t hi = 0u, lo = 1u;  // T = 1 for K1 <= k < K0
+        if (kk < (int64_t)R.K1) {
+            hi = qthr[kk - 1];
+            lo = qthr[R.tab_n + kk - 1];
+        }
+        const uint32_t rr = word >> 16;
+        acc = rr < hi;
+        if (rr == hi && lo != 0u) {
+            uint32_t f[4];
+            philox4x32_10(k, p, R.rid, kTagFallback, a.key0, a.key1, f);
+            acc = (f[0] & 0xFFFFu) < lo;
+        }
+    }
+    return acc ? tg : -1;
+}
+
+// ids / area: the replica's cell ids and live areas (global memory for the
+// streamed pass, LDS for the resident kernel); rows y0 .. y0 + rows - 1.
 template <int CX>
-__device__ __forceinline__ void cpm_quads(const CpmArgs& a, const RepDev& R, const TileDev& T,
-                                          int cy, uint32_t p, const uint32_t* qthr,
-                                          const int32_t* lsa, const int8_t* lty,
-                                          const int32_t* ljs);
+__device__ __forceinline__ void cpm_quads(const CpmArgs& a, const RepDev& R, int32_t* ids,
+                                          int32_t* area, int y0, int rows, int cy, uint32_t p,
+                                          const uint32_t* qthr, const int32_t* lsa,
+                                          const int8_t* lty, const int32_t* ljs);
 
 __global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int sweep_off,
                                                        int tab_lds_bytes, int cell_cap) {
@@ -275,25 +323,25 @@ __global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int swe
     __syncthreads();
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
     const uint32_t p = (uint32_t)(4 * t + (uint64_t)c);
+    int32_t* ids = a.lat + R.lat_off;
+    int32_t* area = a.area + R.cell_off;
     if (c & 1)
-        cpm_quads<1>(a, R, T, c >> 1, p, qthr, lsa, lty, ljs);
+        cpm_quads<1>(a, R, ids, area, T.y0, T.rows, c >> 1, p, qthr, lsa, lty, ljs);
     else
-        cpm_quads<0>(a, R, T, c >> 1, p, qthr, lsa, lty, ljs);
+        cpm_quads<0>(a, R, ids, area, T.y0, T.rows, c >> 1, p, qthr, lsa, lty, ljs);
 }
 
 template <int CX>
-__device__ __forceinline__ void cpm_quads(const CpmArgs& a, const RepDev& R, const TileDev& T,
-                                          int cy, uint32_t p, const uint32_t* qthr,
-                                          const int32_t* lsa, const int8_t* lty,
-                                          const int32_t* ljs) {
-    const int Lx = R.Lx, Ly = R.Ly, Wc = Lx >> 1, Q = Wc >> 2, nt = R.n_types;
-    int32_t* ids = a.lat + R.lat_off;
-    int32_t* area = a.area + R.cell_off;
-    const int total = (T.rows >> 1) * Q;
+__device__ __forceinline__ void cpm_quads(const CpmArgs& a, const RepDev& R, int32_t* ids,
+                                          int32_t* area, int y0, int rows, int cy, uint32_t p,
+                                          const uint32_t* qthr, const int32_t* lsa,
+                                          const int8_t* lty, const int32_t* ljs) {
+    const int Lx = R.Lx, Ly = R.Ly, Wc = Lx >> 1, Q = Wc >> 2;
+    const int total = (rows >> 1) * Q;
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
         const int r = it / Q;
         const int qi = it - r * Q;
-        const int y = T.y0 + 2 * r + cy;
+        const int y = y0 + 2 * r + cy;
         const int x0 = 8 * qi;
         const uint32_t kq = (uint32_t)((y >> 1) * Q + qi);  // k >> 2 of the four sites
         const int yr[3] = {wrapc(y - 1, Ly), y, wrapc(y + 1, Ly)};
@@ -325,49 +373,110 @@ __device__ __forceinline__ void cpm_quads(const CpmArgs& a, const RepDev& R, con
                                win[1][2 * u], win[1][2 * u + 2],
                                win[2][2 * u], win[2][2 * u + 1], win[2][2 * u + 2]};
             const int s = win[1][2 * u + 1];
-            const uint32_t word = w[u];
-            const int tg = sel8(nb, word & 7u);
-            if (tg == s) continue;
-            const int ts = lty[s] * nt, tt = lty[tg] * nt;
-            int kadh = 0;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int m = nb[j];
-                const int tm = lty[m];
-                kadh += (tg != m) ? ljs[tt + tm] : 0;
-                kadh -= (s != m) ? ljs[ts + tm] : 0;
-            }
-            int64_t karea = 0;
-            if (tg != 0) karea += 2 * (int64_t)lsa[tg] + 1;
-            if (s != 0) karea += -2 * (int64_t)lsa[s] + 1;
-            const int64_t kk = (int64_t)kadh + R.LS * karea;
-            bool acc;
-            if (kk <= 0) {
-                acc = true;
-            } else if (kk >= R.K0) {
-                acc = false;
-            } else {
-                uint32_t hi = 0u, lo = 1u;  // T = 1 for K1 <= k < K0
-                if (kk < (int64_t)R.K1) {
-                    hi = qthr[kk - 1];
-                    lo = qthr[R.tab_n + kk - 1];
-                }
-                const uint32_t rr = word >> 16;
-                acc = rr < hi;
-                if (rr == hi && lo != 0u) {
-                    uint32_t f[4];
-                    philox4x32_10(4u * kq + (uint32_t)u, p, R.rid, kTagFallback, a.key0, a.key1,
-                                  f);
-                    acc = (f[0] & 0xFFFFu) < lo;
-                }
-            }
-            if (acc) {
+            const int tg = cpm_decide(a, R, nb, s, w[u], 4u * kq + (uint32_t)u, p, qthr, lsa, lty,
+                                      ljs);
+            if (tg >= 0) {
                 ids[(size_t)y * Lx + x0 + 2 * u + CX] = tg;
                 atomicAdd(&area[tg], 1);
                 atomicAdd(&area[s], -1);
             }
         }
     }
+}
+
+// All n_steps unrecorded Monte Carlo steps (range 1, Lx % 8 == 0) of every
+// replica in one launch: one 1024-thread workgroup per replica with its ids,
+// areas, cell tables and thresholds in LDS.  Per pass the snapshot (area
+// minus target) is taken in LDS; then one site per thread: the four lanes of
+// a quad (four consecutive same-colour sites of a row, one Philox block)
+// compute the block alike and take one word each, so that a replica has 16
+// waves to hide the latency of its table lookups; accepted copies update
+// the areas with LDS atomics, and a barrier closes the pass.  The same
+// decisions as the streamed passes; ids and areas are written back at the
+// end (the stored snapshot equals the areas then).
+__global__ void __launch_bounds__(1024) k_cpm_resident(CpmArgs a, int n_steps,
+                                                       int tab_lds_bytes, int cell_cap) {
+    // dynamic LDS: [T hi | T lo] (tab_lds_bytes) | snap - A | area | A (int32 [cell_cap] each)
+    // | type (int8 [cell_cap], padded to 16) | ids (int32 [Ly Lx])
+    extern __shared__ __align__(16) uint8_t dyn[];
+    uint32_t* qthr = reinterpret_cast<uint32_t*>(dyn);
+    int32_t* lsa = reinterpret_cast<int32_t*>(dyn + tab_lds_bytes);
+    int32_t* larea = lsa + cell_cap;
+    int32_t* lA = larea + cell_cap;
+    int8_t* lty = reinterpret_cast<int8_t*>(lA + cell_cap);
+    int32_t* lids = reinterpret_cast<int32_t*>(lty + ((cell_cap + 15) & ~15));
+    __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
+    const RepDev R = a.reps[blockIdx.x];
+    const int Lx = R.Lx, Ly = R.Ly, Q = Lx >> 3;
+    const int ncell = R.q + 1, n = Lx * Ly, nthr = (int)blockDim.x;
+    int32_t* gids = a.lat + R.lat_off;
+    int32_t* garea = a.area + R.cell_off;
+    for (int i = threadIdx.x; i < 2 * R.tab_n; i += nthr) qthr[i] = a.tab[R.tab_off + i];
+    for (int i = threadIdx.x; i < R.n_types * R.n_types; i += nthr) ljs[i] = a.js[R.js_off + i];
+    for (int i = threadIdx.x; i < ncell; i += nthr) {
+        larea[i] = garea[i];
+        lA[i] = a.target[R.cell_off + i];
+        lty[i] = a.ctype[R.cell_off + i];
+    }
+    for (int i = threadIdx.x; i < n / 4; i += nthr)
+        reinterpret_cast<int4*>(lids)[i] = reinterpret_cast<const int4*>(gids)[i];
+    __syncthreads();
+    const uint64_t t0 = *a.t_base;
+    const int n_sites = n >> 2;  // sites of one colour
+    for (int st = 0; st < n_steps; ++st) {
+        for (int c = 0; c < 4; ++c) {
+            for (int i = threadIdx.x; i < ncell; i += nthr) lsa[i] = larea[i] - lA[i];
+            __syncthreads();
+            const uint32_t p = (uint32_t)(4 * (t0 + (uint64_t)st) + (uint64_t)c);
+            const int cy = c >> 1, cx = c & 1;
+            for (int j = threadIdx.x; j < n_sites; j += nthr) {
+                const int it = j >> 2, u = j & 3;
+                const int r = it / Q, qi = it - r * Q;
+                const int y = 2 * r + cy, x = 8 * qi + 2 * u + cx;
+                const uint32_t kq = (uint32_t)((y >> 1) * Q + qi);
+                const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
+                const int xl = x == 0 ? Lx - 1 : x - 1, xr = x + 1 == Lx ? 0 : x + 1;
+                const int32_t* ru = lids + yu * Lx;
+                const int32_t* ry = lids + y * Lx;
+                const int32_t* rd = lids + yd * Lx;
+                const int nb[8] = {ru[xl], ru[x], ru[xr], ry[xl], ry[xr], rd[xl], rd[x], rd[xr]};
+                const int s = ry[x];
+                uint32_t w[4];
+                philox4x32_10(kq, p, R.rid, kTagMain, a.key0, a.key1, w);
+                const uint32_t word = (u & 2) ? ((u & 1) ? w[3] : w[2]) : ((u & 1) ? w[1] : w[0]);
+                const int tg = cpm_decide(a, R, nb, s, word, 4u * kq + (uint32_t)u, p, qthr, lsa,
+                                          lty, ljs);
+                if (tg >= 0) {
+                    lids[y * Lx + x] = tg;
+                    atomicAdd(&larea[tg], 1);
+                    atomicAdd(&larea[s], -1);
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < n / 4; i += nthr)
+        reinterpret_cast<int4*>(gids)[i] = reinterpret_cast<const int4*>(lids)[i];
+    for (int i = threadIdx.x; i < ncell; i += nthr) {
+        garea[i] = larea[i];
+        a.snap[R.cell_off + i] = larea[i];
+    }
+}
+
+size_t cpm_resident_lds_bytes(int tab_lds_bytes, int cell_cap, int max_sites) {
+    return (size_t)tab_lds_bytes + (size_t)12 * cell_cap + (size_t)((cell_cap + 15) & ~15) +
+           (size_t)4 * max_sites;
+}
+
+hipError_t launch_cpm_resident(const CpmArgs& a, int n_steps, int tab_lds_bytes, int cell_cap,
+                               int max_sites, hipStream_t s) {
+    const size_t lds = cpm_resident_lds_bytes(tab_lds_bytes, cell_cap, max_sites);
+    hipError_t e = hipFuncSetAttribute((const void*)k_cpm_resident,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cpm_resident, dim3(a.R), dim3(1024), lds, s, a, n_steps, tab_lds_bytes,
+                       cell_cap);
+    return hipGetLastError();
 }
 
 __global__ void k_cpm_copy(const int32_t* src, int32_t* dst, int n) {

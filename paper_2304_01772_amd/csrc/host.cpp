@@ -12,6 +12,7 @@
 #include <string>
 #include <tuple>
 
+#include "cpm_internal.hpp"
 #include "grad_internal.hpp"
 #include "msc_internal.hpp"
 #include "tri_internal.hpp"
@@ -1623,6 +1624,20 @@ int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
         c->cpm_lds_reserved = true;
     }
     hipError_t e = hipSuccess;
+    // unrecorded steps of lattices whose ids and tables fit 64 KiB of LDS:
+    // the resident kernel, one launch per chunk of at most 500 steps (the
+    // step counter advances after each), unless streamed passes are requested
+    if (re == 0 && !c->prof && c->cpm_quad && c->cpm_range == 1 && c->sched.mode != 2 &&
+        cpm_resident_lds_bytes((int)tab_bytes, c->cpm_cell_cap, c->max_sites) <= 64 * 1024) {
+        for (int done = 0; done < n && e == hipSuccess;) {
+            const int k = std::min(500, n - done);
+            e = launch_cpm_resident(a, k, (int)tab_bytes, c->cpm_cell_cap, c->max_sites,
+                                    c->stream);
+            if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)k, c->stream);
+            done += k;
+        }
+        return check_dev(c, e, "sweep (resident)");
+    }
     if (re == 0 && !c->prof && c->use_graphs) {
         const int G = std::min(n, kGraphChunk);
         const int full = n / G, rest = n - full * G;

@@ -234,15 +234,17 @@ def test_measure_right_after_set_state_counts_the_areas(S):
 
 @pytest.mark.parametrize("cpm_range", [1, 2])
 def test_unrecorded_steps_replay_graphs(S, cpm_range):
-    """Unrecorded Monte Carlo steps replay captured graphs of whole chunks
-    (here 55 = 50 + 5 steps, then 3 more after a change of tile rows, which
-    drops the graphs): the states equal the oracle's."""
+    """Unrecorded Monte Carlo steps of the streamed schedule replay captured
+    graphs of whole chunks (here 55 = 50 + 5 steps, then 3 more after a
+    change of tile rows, which drops the graphs): the states equal the
+    oracle's."""
     J = JS["sorting"]
     shape = (24, 24) if cpm_range == 1 else (24, 30)
     cases = [_random_case(800 + r, shape, 10) for r in range(2)]
     reps = [dict(_rep(ids, J, ct, A, 1.0, 12.0, r), cpm_range=cpm_range)
             for r, (ids, ct, A) in enumerate(cases)]
     smp = S(reps, 5, init=False)
+    smp.set_schedule(mode="stream")  # small range-1 lattices would run resident
     for r, (ids, _, _) in enumerate(cases):
         smp.set_state(r, ids)
     smp.sweep(55)
@@ -251,4 +253,27 @@ def test_unrecorded_steps_replay_graphs(S, cpm_range):
     for r, (ids, ct, A) in enumerate(cases):
         want, _, _ = orc.cpm_run(ids, J, ct, A, 1.0, 12.0, 5, r, 0, 58, nrange=cpm_range)
         assert np.array_equal(smp.get_state(r), want), r
+    smp.close()
+
+
+def test_unrecorded_steps_resident(S):
+    """Unrecorded steps of range-1 lattices whose ids and tables fit 64 KiB of
+    LDS run in one workgroup per replica: mixed shapes and cell counts, two
+    calls (the step counter carries over) and a chunk boundary (500 steps);
+    states and then measured statistics equal the oracle's."""
+    J = JS["sorting"]
+    shapes = [((16, 24), 7), ((64, 64), 30), ((8, 8), 2), ((40, 32), 25)]
+    cases = [_random_case(900 + r, sh, nc) for r, (sh, nc) in enumerate(shapes)]
+    reps = [_rep(ids, J, ct, A, 1.0, 10.0, 40 + r) for r, (ids, ct, A) in enumerate(cases)]
+    smp = S(reps, 9, init=False)
+    for r, (ids, _, _) in enumerate(cases):
+        smp.set_state(r, ids)
+    smp.sweep(520)
+    smp.sweep(7)
+    stats, _ = smp.measure()
+    stats = stats.cpu().numpy()
+    for r, (ids, ct, A) in enumerate(cases):
+        want, area, _ = orc.cpm_run(ids, J, ct, A, 1.0, 10.0, 9, 40 + r, 0, 527)
+        assert np.array_equal(smp.get_state(r), want), r
+        assert np.array_equal(stats[r], orc.cpm_stats(want, J, ct, A, 1.0)), r
     smp.close()
