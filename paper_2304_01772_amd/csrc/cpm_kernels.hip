@@ -109,6 +109,83 @@ __global__ void __launch_bounds__(256) k_cpm_pass(CpmArgs a, int c, int sweep_of
 // multiply-shift of the low 16 bits of the main word into 24, and where
 // that rejects (16 of the 65536 values) the 32-bit multiply-shift of word 1
 // of the fallback block.
+// The 5x5 copy attempt of site (y, x), within-colour index k, colour pass p:
+// ty the cell types, sa(i) the pass-start area minus target of cell i (as
+// int64); accepted copies update ids and area.
+template <class SA>
+__device__ __forceinline__ void cpm5_attempt(const CpmArgs& a, const RepDev& R, int32_t* ids,
+                                             int32_t* area, int y, int x, uint32_t k, uint32_t p,
+                                             const uint32_t* lthr, const int8_t* ty,
+                                             const int32_t* ljs, SA sa) {
+    const int Lx = R.Lx, Ly = R.Ly, nt = R.n_types;
+    uint32_t w[4];
+    philox4x32_10(k >> 2, p, R.rid, kTagMain, a.key0, a.key1, w);
+    const uint32_t word = w[k & 3u];
+    uint32_t f[4];
+    bool have_f = false;
+    const uint32_t l = (word & 0xFFFFu) * 24u;
+    int jn = (int)(l >> 16);
+    if ((l & 0xFFFFu) < 16u) {
+        philox4x32_10(k, p, R.rid, kTagFallback, a.key0, a.key1, f);
+        have_f = true;
+        jn = (int)(((uint64_t)f[1] * 24u) >> 32);
+    }
+    // row-major offsets without the centre: jn < 12 lies before it
+    const int jj = jn < 12 ? jn : jn + 1;
+    const int ndy = jj / 5 - 2, ndx = jj % 5 - 2;
+    int rows[5], cols[5];
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        rows[d] = wrapc(y + d - 2, Ly) * Lx;
+        cols[d] = wrapc(x + d - 2, Lx);
+    }
+    const int s = ids[(size_t)rows[2] + x];
+    const int tg = ids[(size_t)wrapc(y + ndy, Ly) * Lx + wrapc(x + ndx, Lx)];
+    if (tg == s) return;
+    int nb[25];
+#pragma unroll
+    for (int dy = 0; dy < 5; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 5; ++dx) nb[dy * 5 + dx] = ids[(size_t)rows[dy] + cols[dx]];
+    const int ts = ty[s] * nt, tt = ty[tg] * nt;
+    int kadh = 0;
+#pragma unroll
+    for (int j = 0; j < 25; ++j) {
+        if (j == 12) continue;  // the site itself
+        const int m = nb[j];
+        const int tm = ty[m];
+        kadh += (tg != m) ? ljs[tt + tm] : 0;
+        kadh -= (s != m) ? ljs[ts + tm] : 0;
+    }
+    int64_t karea = 0;
+    if (tg != 0) karea += 2 * sa(tg) + 1;
+    if (s != 0) karea += -2 * sa(s) + 1;
+    const int64_t kk = (int64_t)kadh + R.LS * karea;
+    bool acc;
+    if (kk <= 0) {
+        acc = true;
+    } else if (kk >= R.K0) {
+        acc = false;
+    } else {
+        uint32_t hi = 0u, lo = 1u;  // T = 1 for K1 <= k < K0
+        if (kk < (int64_t)R.K1) {
+            hi = lthr[kk - 1];
+            lo = lthr[R.tab_n + kk - 1];
+        }
+        const uint32_t rr = word >> 16;
+        acc = rr < hi;
+        if (rr == hi && lo != 0u) {
+            if (!have_f) philox4x32_10(k, p, R.rid, kTagFallback, a.key0, a.key1, f);
+            acc = (f[0] & 0xFFFFu) < lo;
+        }
+    }
+    if (acc) {
+        ids[(size_t)rows[2] + x] = tg;
+        atomicAdd(&area[tg], 1);
+        atomicAdd(&area[s], -1);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_cpm_pass5(CpmArgs a, int c, int sweep_off) {
     extern __shared__ uint32_t lthr[];  // [2 * tab_n]: hi16 | lo16 of T(k), k = 1..K1-1
     __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
@@ -121,12 +198,13 @@ __global__ void __launch_bounds__(256) k_cpm_pass5(CpmArgs a, int c, int sweep_o
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
     const uint32_t p = (uint32_t)(9 * t + (uint64_t)c);
     const int cy = c / 3, cx = c - 3 * cy;
-    const int Lx = R.Lx, Ly = R.Ly, Wc = Lx / 3, nt = R.n_types;
+    const int Lx = R.Lx, Wc = Lx / 3;
     int32_t* ids = a.lat + R.lat_off;
     const int8_t* ty = a.ctype + R.cell_off;
     const int32_t* A = a.target + R.cell_off;
     const int32_t* snap = a.snap + R.cell_off;
     int32_t* area = a.area + R.cell_off;
+    const auto sa = [=](int i) -> int64_t { return (int64_t)snap[i] - (int64_t)A[i]; };
     const int total = (T.rows / 3) * Wc;
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
         const int r = it / Wc;
@@ -134,72 +212,7 @@ __global__ void __launch_bounds__(256) k_cpm_pass5(CpmArgs a, int c, int sweep_o
         const int y = T.y0 + 3 * r + cy;
         const int x = 3 * i + cx;
         const uint32_t k = (uint32_t)((y / 3) * Wc + i);
-        uint32_t w[4];
-        philox4x32_10(k >> 2, p, R.rid, kTagMain, a.key0, a.key1, w);
-        const uint32_t word = w[k & 3u];
-        uint32_t f[4];
-        bool have_f = false;
-        const uint32_t l = (word & 0xFFFFu) * 24u;
-        int jn = (int)(l >> 16);
-        if ((l & 0xFFFFu) < 16u) {
-            philox4x32_10(k, p, R.rid, kTagFallback, a.key0, a.key1, f);
-            have_f = true;
-            jn = (int)(((uint64_t)f[1] * 24u) >> 32);
-        }
-        // row-major offsets without the centre: jn < 12 lies before it
-        const int jj = jn < 12 ? jn : jn + 1;
-        const int ndy = jj / 5 - 2, ndx = jj % 5 - 2;
-        int rows[5], cols[5];
-#pragma unroll
-        for (int d = 0; d < 5; ++d) {
-            rows[d] = wrapc(y + d - 2, Ly) * Lx;
-            cols[d] = wrapc(x + d - 2, Lx);
-        }
-        const int s = ids[(size_t)rows[2] + x];
-        const int tg = ids[(size_t)wrapc(y + ndy, Ly) * Lx + wrapc(x + ndx, Lx)];
-        if (tg == s) continue;
-        int nb[25];
-#pragma unroll
-        for (int dy = 0; dy < 5; ++dy)
-#pragma unroll
-            for (int dx = 0; dx < 5; ++dx) nb[dy * 5 + dx] = ids[(size_t)rows[dy] + cols[dx]];
-        const int ts = ty[s] * nt, tt = ty[tg] * nt;
-        int kadh = 0;
-#pragma unroll
-        for (int j = 0; j < 25; ++j) {
-            if (j == 12) continue;  // the site itself
-            const int m = nb[j];
-            const int tm = ty[m];
-            kadh += (tg != m) ? ljs[tt + tm] : 0;
-            kadh -= (s != m) ? ljs[ts + tm] : 0;
-        }
-        int64_t karea = 0;
-        if (tg != 0) karea += 2 * ((int64_t)snap[tg] - (int64_t)A[tg]) + 1;
-        if (s != 0) karea += -2 * ((int64_t)snap[s] - (int64_t)A[s]) + 1;
-        const int64_t kk = (int64_t)kadh + R.LS * karea;
-        bool acc;
-        if (kk <= 0) {
-            acc = true;
-        } else if (kk >= R.K0) {
-            acc = false;
-        } else {
-            uint32_t hi = 0u, lo = 1u;  // T = 1 for K1 <= k < K0
-            if (kk < (int64_t)R.K1) {
-                hi = lthr[kk - 1];
-                lo = lthr[R.tab_n + kk - 1];
-            }
-            const uint32_t rr = word >> 16;
-            acc = rr < hi;
-            if (rr == hi && lo != 0u) {
-                if (!have_f) philox4x32_10(k, p, R.rid, kTagFallback, a.key0, a.key1, f);
-                acc = (f[0] & 0xFFFFu) < lo;
-            }
-        }
-        if (acc) {
-            ids[(size_t)rows[2] + x] = tg;
-            atomicAdd(&area[tg], 1);
-            atomicAdd(&area[s], -1);
-        }
+        cpm5_attempt(a, R, ids, area, y, x, k, p, lthr, ty, ljs, sa);
     }
 }
 
@@ -384,16 +397,18 @@ __device__ __forceinline__ void cpm_quads(const CpmArgs& a, const RepDev& R, int
     }
 }
 
-// All n_steps unrecorded Monte Carlo steps (range 1, Lx % 8 == 0) of every
-// replica in one launch: one 1024-thread workgroup per replica with its ids,
-// areas, cell tables and thresholds in LDS.  Per pass the snapshot (area
-// minus target) is taken in LDS; then one site per thread: the four lanes of
-// a quad (four consecutive same-colour sites of a row, one Philox block)
-// compute the block alike and take one word each, so that a replica has 16
-// waves to hide the latency of its table lookups; accepted copies update
-// the areas with LDS atomics, and a barrier closes the pass.  The same
+// All n_steps unrecorded Monte Carlo steps of every replica in one launch:
+// one 1024-thread workgroup per replica with its ids, areas, cell tables and
+// thresholds in LDS.  Per pass the snapshot (area minus target) is taken in
+// LDS; then one site per thread.  Range 1 (Lx % 8 == 0): the four lanes of a
+// quad (four consecutive same-colour sites of a row, one Philox block)
+// compute the block alike and take one word each; range 2: the attempt of
+// the streamed 5x5 pass on the LDS ids.  A replica has 16 waves to hide the
+// latency of its table lookups; accepted copies update the areas with LDS
+// atomics, and a barrier closes the pass.  The same
 // decisions as the streamed passes; ids and areas are written back at the
 // end (the stored snapshot equals the areas then).
+template <int RANGE>
 __global__ void __launch_bounds__(1024) k_cpm_resident(CpmArgs a, int n_steps,
                                                        int tab_lds_bytes, int cell_cap) {
     // dynamic LDS: [T hi | T lo] (tab_lds_bytes) | snap - A | area | A (int32 [cell_cap] each)
@@ -422,12 +437,25 @@ __global__ void __launch_bounds__(1024) k_cpm_resident(CpmArgs a, int n_steps,
         reinterpret_cast<int4*>(lids)[i] = reinterpret_cast<const int4*>(gids)[i];
     __syncthreads();
     const uint64_t t0 = *a.t_base;
-    const int n_sites = n >> 2;  // sites of one colour
+    constexpr int ncol = RANGE == 2 ? 9 : 4;
+    const int n_sites = n / ncol;  // sites of one colour
+    const auto sa = [=](int i) -> int64_t { return (int64_t)lsa[i]; };
     for (int st = 0; st < n_steps; ++st) {
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < ncol; ++c) {
             for (int i = threadIdx.x; i < ncell; i += nthr) lsa[i] = larea[i] - lA[i];
             __syncthreads();
-            const uint32_t p = (uint32_t)(4 * (t0 + (uint64_t)st) + (uint64_t)c);
+            const uint32_t p = (uint32_t)(ncol * (t0 + (uint64_t)st) + (uint64_t)c);
+            if (RANGE == 2) {
+                // the 3x3 sublattice: colour c = 3 (y mod 3) + (x mod 3)
+                const int cy = c / 3, cx = c - 3 * cy, Wc = Lx / 3;
+                for (int j = threadIdx.x; j < n_sites; j += nthr) {
+                    const int r = j / Wc, i = j - r * Wc;
+                    cpm5_attempt(a, R, lids, larea, 3 * r + cy, 3 * i + cx, (uint32_t)j, p, qthr,
+                                 lty, ljs, sa);
+                }
+                __syncthreads();
+                continue;
+            }
             const int cy = c >> 1, cx = c & 1;
             for (int j = threadIdx.x; j < n_sites; j += nthr) {
                 const int it = j >> 2, u = j & 3;
@@ -471,11 +499,15 @@ size_t cpm_resident_lds_bytes(int tab_lds_bytes, int cell_cap, int max_sites) {
 hipError_t launch_cpm_resident(const CpmArgs& a, int n_steps, int tab_lds_bytes, int cell_cap,
                                int max_sites, hipStream_t s) {
     const size_t lds = cpm_resident_lds_bytes(tab_lds_bytes, cell_cap, max_sites);
-    hipError_t e = hipFuncSetAttribute((const void*)k_cpm_resident,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void* fn = a.range == 2 ? (const void*)k_cpm_resident<2> : (const void*)k_cpm_resident<1>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cpm_resident, dim3(a.R), dim3(1024), lds, s, a, n_steps, tab_lds_bytes,
-                       cell_cap);
+    if (a.range == 2)
+        hipLaunchKernelGGL(k_cpm_resident<2>, dim3(a.R), dim3(1024), lds, s, a, n_steps,
+                           tab_lds_bytes, cell_cap);
+    else
+        hipLaunchKernelGGL(k_cpm_resident<1>, dim3(a.R), dim3(1024), lds, s, a, n_steps,
+                           tab_lds_bytes, cell_cap);
     return hipGetLastError();
 }
 

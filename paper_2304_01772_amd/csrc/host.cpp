@@ -1624,10 +1624,11 @@ int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
         c->cpm_lds_reserved = true;
     }
     hipError_t e = hipSuccess;
-    // unrecorded steps of lattices whose ids and tables fit 64 KiB of LDS:
-    // the resident kernel, one launch per chunk of at most 500 steps (the
-    // step counter advances after each), unless streamed passes are requested
-    if (re == 0 && !c->prof && c->cpm_quad && c->cpm_range == 1 && c->sched.mode != 2 &&
+    // unrecorded steps of lattices whose ids and tables fit 64 KiB of LDS (the
+    // 3x3 neighbourhood with every Lx % 8 == 0, or the 5x5 one): the resident
+    // kernel, one launch per chunk of at most 500 steps (the step counter
+    // advances after each), unless streamed passes are requested
+    if (re == 0 && !c->prof && (c->cpm_quad || c->cpm_range == 2) && c->sched.mode != 2 &&
         cpm_resident_lds_bytes((int)tab_bytes, c->cpm_cell_cap, c->max_sites) <= 64 * 1024) {
         for (int done = 0; done < n && e == hipSuccess;) {
             const int k = std::min(500, n - done);

@@ -256,15 +256,20 @@ def test_unrecorded_steps_replay_graphs(S, cpm_range):
     smp.close()
 
 
-def test_unrecorded_steps_resident(S):
-    """Unrecorded steps of range-1 lattices whose ids and tables fit 64 KiB of
-    LDS run in one workgroup per replica: mixed shapes and cell counts, two
-    calls (the step counter carries over) and a chunk boundary (500 steps);
-    states and then measured statistics equal the oracle's."""
+@pytest.mark.parametrize("cpm_range", [1, 2])
+def test_unrecorded_steps_resident(S, cpm_range):
+    """Unrecorded steps of lattices whose ids and tables fit 64 KiB of LDS run
+    in one workgroup per replica: mixed shapes and cell counts, two calls
+    (the step counter carries over) and a chunk boundary (500 steps); states
+    and then measured statistics equal the oracle's."""
     J = JS["sorting"]
-    shapes = [((16, 24), 7), ((64, 64), 30), ((8, 8), 2), ((40, 32), 25)]
+    if cpm_range == 1:
+        shapes = [((16, 24), 7), ((64, 64), 30), ((8, 8), 2), ((40, 32), 25)]
+    else:
+        shapes = [((18, 24), 7), ((66, 66), 30), ((6, 6), 2), ((36, 48), 25)]
     cases = [_random_case(900 + r, sh, nc) for r, (sh, nc) in enumerate(shapes)]
-    reps = [_rep(ids, J, ct, A, 1.0, 10.0, 40 + r) for r, (ids, ct, A) in enumerate(cases)]
+    reps = [dict(_rep(ids, J, ct, A, 1.0, 10.0, 40 + r), cpm_range=cpm_range)
+            for r, (ids, ct, A) in enumerate(cases)]
     smp = S(reps, 9, init=False)
     for r, (ids, _, _) in enumerate(cases):
         smp.set_state(r, ids)
@@ -273,7 +278,8 @@ def test_unrecorded_steps_resident(S):
     stats, _ = smp.measure()
     stats = stats.cpu().numpy()
     for r, (ids, ct, A) in enumerate(cases):
-        want, area, _ = orc.cpm_run(ids, J, ct, A, 1.0, 10.0, 9, 40 + r, 0, 527)
+        want, area, _ = orc.cpm_run(ids, J, ct, A, 1.0, 10.0, 9, 40 + r, 0, 527,
+                                    nrange=cpm_range)
         assert np.array_equal(smp.get_state(r), want), r
-        assert np.array_equal(stats[r], orc.cpm_stats(want, J, ct, A, 1.0)), r
+        assert np.array_equal(stats[r], orc.cpm_stats(want, J, ct, A, 1.0, nrange=cpm_range)), r
     smp.close()
