@@ -251,10 +251,13 @@ int spinmc_thresholds(const spinmc_ctx *ctx, int32_t replica, uint64_t *host_T, 
  *   caches, for lattice sets that do not fit the 256 MB last-level cache).
  *   0 decides per model: on when that model's streamed lattices exceed
  *   192 MiB.  The chain is the same either way.
- * Invalid values return SPINMC_E_INVALID.  CPM contexts use tile_rows and
- * wg_threads only (tile_rows rounded down to whole periods of the colouring:
- * 2 rows, or 6 with the 5x5 neighbourhood).  spinmc_autotune also tries the best streaming schedule
- * with NT forced on and off.                                                */
+ * Invalid values return SPINMC_E_INVALID.  CPM contexts: mode 2 keeps every
+ * step on streamed passes; any other mode lets the unrecorded steps of
+ * lattices whose ids and tables fit 64 KiB of LDS run resident (one
+ * workgroup per replica).  tile_rows is rounded down to whole periods of
+ * the colouring (2 rows, or 6 with the 5x5 neighbourhood); wg_threads caps
+ * the threads of a streamed pass at 256.  spinmc_autotune also tries the
+ * best streaming schedule with NT forced on and off.                        */
 enum { SPINMC_SCHED_NT_ON = 1, SPINMC_SCHED_NT_OFF = 2 };
 typedef struct spinmc_schedule {
     int32_t mode;

@@ -283,22 +283,16 @@ __device__ __forceinline__ void cpm_quads(const CpmArgs& a, const RepDev& R, int
                                           const uint32_t* qthr, const int32_t* lsa,
                                           const int8_t* lty, const int32_t* ljs);
 
-__global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int sweep_off,
-                                                       int tab_lds_bytes, int cell_cap) {
-    // dynamic LDS: [T hi | T lo] (tab_lds_bytes) | snap - A (int32) | type (int8)
-    extern __shared__ __align__(16) uint8_t dyn[];
-    uint32_t* qthr = reinterpret_cast<uint32_t*>(dyn);
-    int32_t* lsa = reinterpret_cast<int32_t*>(dyn + tab_lds_bytes);
-    int8_t* lty = reinterpret_cast<int8_t*>(lsa + cell_cap);
-    __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
-    const TileDev T = a.tiles[blockIdx.x];
-    const RepDev R = a.reps[T.rep];
+// Per-cell tables of replica R into LDS for one pass of a tile: thresholds,
+// adhesion, types and pass-start area minus target.  Each thread issues up
+// to 4 items' loads before storing any, so that the tables arrive in one
+// round of global loads.
+__device__ __forceinline__ void cpm_stage(const CpmArgs& a, const RepDev& R, uint32_t* qthr,
+                                          int32_t* lsa, int8_t* lty, int32_t* ljs) {
     const int ncell = R.q + 1;
     const int8_t* ty = a.ctype + R.cell_off;
     const int32_t* A = a.target + R.cell_off;
     const int32_t* snap = a.snap + R.cell_off;
-    // staging: each thread issues up to 4 items' loads before storing any,
-    // so that the tables arrive in one round of global loads
     const int nthr = blockDim.x;
     const int ntab = 2 * R.tab_n;
     for (int i0 = threadIdx.x; i0 < ntab; i0 += 4 * nthr) {
@@ -333,6 +327,19 @@ __global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int swe
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int sweep_off,
+                                                       int tab_lds_bytes, int cell_cap) {
+    // dynamic LDS: [T hi | T lo] (tab_lds_bytes) | snap - A (int32) | type (int8)
+    extern __shared__ __align__(16) uint8_t dyn[];
+    uint32_t* qthr = reinterpret_cast<uint32_t*>(dyn);
+    int32_t* lsa = reinterpret_cast<int32_t*>(dyn + tab_lds_bytes);
+    int8_t* lty = reinterpret_cast<int8_t*>(lsa + cell_cap);
+    __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
+    const TileDev T = a.tiles[blockIdx.x];
+    const RepDev R = a.reps[T.rep];
+    cpm_stage(a, R, qthr, lsa, lty, ljs);
     __syncthreads();
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
     const uint32_t p = (uint32_t)(4 * t + (uint64_t)c);
@@ -342,6 +349,51 @@ __global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int swe
         cpm_quads<1>(a, R, ids, area, T.y0, T.rows, c >> 1, p, qthr, lsa, lty, ljs);
     else
         cpm_quads<0>(a, R, ids, area, T.y0, T.rows, c >> 1, p, qthr, lsa, lty, ljs);
+}
+
+// The copy attempt of site (y, x) of colour pass p, word u of Philox block kq
+// (the quad of four consecutive same-colour sites of the row): its Moore
+// window from ids, the decision, and on acceptance the id and area updates.
+__device__ __forceinline__ void cpm_moore_site(const CpmArgs& a, const RepDev& R, int32_t* ids,
+                                               int32_t* area, int y, int x, uint32_t kq, int u,
+                                               uint32_t p, const uint32_t* qthr,
+                                               const int32_t* lsa, const int8_t* lty,
+                                               const int32_t* ljs) {
+    const int Lx = R.Lx, Ly = R.Ly;
+    const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
+    const int xl = x == 0 ? Lx - 1 : x - 1, xr = x + 1 == Lx ? 0 : x + 1;
+    const int32_t* ru = ids + (size_t)yu * Lx;
+    const int32_t* ry = ids + (size_t)y * Lx;
+    const int32_t* rd = ids + (size_t)yd * Lx;
+    const int nb[8] = {ru[xl], ru[x], ru[xr], ry[xl], ry[xr], rd[xl], rd[x], rd[xr]};
+    const int s = ry[x];
+    uint32_t w[4];
+    philox4x32_10(kq, p, R.rid, kTagMain, a.key0, a.key1, w);
+    const uint32_t word = (u & 2) ? ((u & 1) ? w[3] : w[2]) : ((u & 1) ? w[1] : w[0]);
+    const int tg = cpm_decide(a, R, nb, s, word, 4u * kq + (uint32_t)u, p, qthr, lsa, lty, ljs);
+    if (tg >= 0) {
+        ids[(size_t)y * Lx + x] = tg;
+        atomicAdd(&area[tg], 1);
+        atomicAdd(&area[s], -1);
+    }
+}
+
+// The colour-c sites of rows y0 .. y0 + rows - 1 (rows even), one per thread
+// of the loop: site j is word j & 3 of quad j >> 2.  (Streamed from global
+// memory the quad form is faster: its window loads serve four sites.)
+__device__ __forceinline__ void cpm_sites(const CpmArgs& a, const RepDev& R, int32_t* ids,
+                                          int32_t* area, int y0, int rows, int c, uint32_t p,
+                                          const uint32_t* qthr, const int32_t* lsa,
+                                          const int8_t* lty, const int32_t* ljs) {
+    const int Q = R.Lx >> 3, cy = c >> 1, cx = c & 1;
+    const int n = (rows >> 1) * (R.Lx >> 1);
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const int it = j >> 2, u = j & 3;
+        const int r = it / Q, qi = it - r * Q;
+        const int y = y0 + 2 * r + cy, x = 8 * qi + 2 * u + cx;
+        cpm_moore_site(a, R, ids, area, y, x, (uint32_t)((y >> 1) * Q + qi), u, p, qthr, lsa,
+                       lty, ljs);
+    }
 }
 
 template <int CX>
@@ -422,7 +474,7 @@ __global__ void __launch_bounds__(1024) k_cpm_resident(CpmArgs a, int n_steps,
     int32_t* lids = reinterpret_cast<int32_t*>(lty + ((cell_cap + 15) & ~15));
     __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
     const RepDev R = a.reps[blockIdx.x];
-    const int Lx = R.Lx, Ly = R.Ly, Q = Lx >> 3;
+    const int Lx = R.Lx, Ly = R.Ly;
     const int ncell = R.q + 1, n = Lx * Ly, nthr = (int)blockDim.x;
     int32_t* gids = a.lat + R.lat_off;
     int32_t* garea = a.area + R.cell_off;
@@ -456,30 +508,7 @@ __global__ void __launch_bounds__(1024) k_cpm_resident(CpmArgs a, int n_steps,
                 __syncthreads();
                 continue;
             }
-            const int cy = c >> 1, cx = c & 1;
-            for (int j = threadIdx.x; j < n_sites; j += nthr) {
-                const int it = j >> 2, u = j & 3;
-                const int r = it / Q, qi = it - r * Q;
-                const int y = 2 * r + cy, x = 8 * qi + 2 * u + cx;
-                const uint32_t kq = (uint32_t)((y >> 1) * Q + qi);
-                const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
-                const int xl = x == 0 ? Lx - 1 : x - 1, xr = x + 1 == Lx ? 0 : x + 1;
-                const int32_t* ru = lids + yu * Lx;
-                const int32_t* ry = lids + y * Lx;
-                const int32_t* rd = lids + yd * Lx;
-                const int nb[8] = {ru[xl], ru[x], ru[xr], ry[xl], ry[xr], rd[xl], rd[x], rd[xr]};
-                const int s = ry[x];
-                uint32_t w[4];
-                philox4x32_10(kq, p, R.rid, kTagMain, a.key0, a.key1, w);
-                const uint32_t word = (u & 2) ? ((u & 1) ? w[3] : w[2]) : ((u & 1) ? w[1] : w[0]);
-                const int tg = cpm_decide(a, R, nb, s, word, 4u * kq + (uint32_t)u, p, qthr, lsa,
-                                          lty, ljs);
-                if (tg >= 0) {
-                    lids[y * Lx + x] = tg;
-                    atomicAdd(&larea[tg], 1);
-                    atomicAdd(&larea[s], -1);
-                }
-            }
+            cpm_sites(a, R, lids, larea, 0, Ly, c, p, qthr, lsa, lty, ljs);
             __syncthreads();
         }
     }

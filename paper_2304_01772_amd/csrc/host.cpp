@@ -897,6 +897,9 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
     // candidate schedules
     std::vector<spinmc_schedule> cand;
     if (c->cpm) {
+        // resident where the lattices fit (else the default streamed passes),
+        // then streamed passes over several tile heights
+        cand.push_back(spinmc_schedule{0, 0, 0, 0});
         for (int tr : {0, 2, 4, 8, 16}) cand.push_back(spinmc_schedule{2, tr, 256, 0});
     } else {
         bool all_res = true, any_res_chunk = false, any_stream = false;

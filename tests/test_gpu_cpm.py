@@ -283,3 +283,41 @@ def test_unrecorded_steps_resident(S, cpm_range):
         assert np.array_equal(smp.get_state(r), want), r
         assert np.array_equal(stats[r], orc.cpm_stats(want, J, ct, A, 1.0, nrange=cpm_range)), r
     smp.close()
+
+
+def test_streamed_passes_over_ragged_tiles_match_oracle(S):
+    """The 3x3 streamed pass, recorded, over several tiles of 8 rows with a
+    ragged last one (22 rows): states and statistics equal the oracle's."""
+    J = JS["sorting"]
+    cases = [_random_case(950 + r, (22, 40), 9) for r in range(2)]
+    reps = [_rep(ids, J, ct, A, 1.0, 10.0, 60 + r) for r, (ids, ct, A) in enumerate(cases)]
+    smp = S(reps, 13, init=False)
+    smp.set_schedule(mode="stream", tile_rows=8)
+    for r, (ids, _, _) in enumerate(cases):
+        smp.set_state(r, ids)
+    st = smp.sweep(6, 3).cpu().numpy()
+    for r, (ids, ct, A) in enumerate(cases):
+        want, _, ost = orc.cpm_run(ids, J, ct, A, 1.0, 10.0, 13, 60 + r, 0, 6, 3)
+        assert np.array_equal(smp.get_state(r), want), r
+        assert np.array_equal(st[:, r], ost), r
+    smp.close()
+
+
+def test_autotune_keeps_the_chain(S):
+    """The autotuner's trials (resident, and streamed passes over several
+    tile heights) restore the state and the step counter; the chosen
+    schedule continues the oracle's chain."""
+    J = JS["sorting"]
+    cases = [_random_case(970 + r, (32, 48), 11) for r in range(3)]
+    reps = [_rep(ids, J, ct, A, 1.0, 10.0, 80 + r) for r, (ids, ct, A) in enumerate(cases)]
+    smp = S(reps, 15, init=False)
+    for r, (ids, _, _) in enumerate(cases):
+        smp.set_state(r, ids)
+    smp.sweep(4)
+    chosen, rates = smp.autotune(trial_sweeps=5)
+    assert len(rates) == 6 and all(x > 0 for x in rates)
+    smp.sweep(5)
+    for r, (ids, ct, A) in enumerate(cases):
+        want, _, _ = orc.cpm_run(ids, J, ct, A, 1.0, 10.0, 15, 80 + r, 0, 9)
+        assert np.array_equal(smp.get_state(r), want), (r, chosen)
+    smp.close()
