@@ -266,7 +266,14 @@ def tri_probe(Sampler, torch, n_rep=1024, L=96, sweeps=200):
     e1.record(smp.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    # the streamed colour passes alone (the schedule for recorded sweeps)
+    # recorded sweeps (statistics every sweep, still resident)
+    rec = torch.empty((sweeps, n_rep, smp.width), dtype=torch.int32, device="cuda")
+    e2, e3 = _events(torch, smp.stream)
+    smp.sweep(sweeps, 1, stats=rec)
+    e3.record(smp.stream)
+    torch.cuda.synchronize()
+    ms_rec = e2.elapsed_time(e3)
+    # the streamed colour passes alone (the schedule for lattices beyond LDS)
     smp.set_schedule(mode="stream")
     smp.profile(True)
     smp.sweep(20)
@@ -280,7 +287,8 @@ def tri_probe(Sampler, torch, n_rep=1024, L=96, sweeps=200):
     gbs = per_launch * 4 / avg_s / 1e9
     return {"config": f"{n_rep} triangular replicas of {L}x{L}, beta_c = ln(3)/4, {sweeps} sweeps",
             "attempts_per_ns": round(sites * sweeps / (ms * 1e6), 1),
-            "kernel": "k_nat_resident (unrecorded sweeps, lattices in LDS)",
+            "recorded_attempts_per_ns": round(sites * sweeps / (ms_rec * 1e6), 1),
+            "kernel": "k_nat_resident (lattices in LDS)",
             "stream_pass": {"kernel": "k_tri_pass12", "avg_launch_us": round(avg_s * 1e6, 2),
                             "attempts_per_ns": round(per_launch / avg_s / 1e9, 1),
                             "GBs_algorithmic": round(gbs, 1),
@@ -302,6 +310,12 @@ def hc_probe(Sampler, torch, n_rep=256, L=32, sweeps=200):
     e1.record(smp.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    rec = torch.empty((sweeps, n_rep, smp.width), dtype=torch.int32, device="cuda")
+    e2, e3 = _events(torch, smp.stream)  # recorded sweeps, still resident
+    smp.sweep(sweeps, 1, stats=rec)
+    e3.record(smp.stream)
+    torch.cuda.synchronize()
+    ms_rec = e2.elapsed_time(e3)
     smp.set_schedule(mode="stream")
     smp.profile(True)
     smp.sweep(20)
@@ -314,7 +328,8 @@ def hc_probe(Sampler, torch, n_rep=256, L=32, sweeps=200):
     gbs = sites / 2 * 3 / avg_s / 1e9
     return {"config": f"{n_rep} simple-cubic replicas of {L}^3, beta 0.2216546, {sweeps} sweeps",
             "attempts_per_ns": round(sites * sweeps / (ms * 1e6), 1),
-            "kernel": "k_nat_resident (unrecorded sweeps, lattices in LDS)",
+            "recorded_attempts_per_ns": round(sites * sweeps / (ms_rec * 1e6), 1),
+            "kernel": "k_nat_resident (lattices in LDS)",
             "stream_pass": {"kernel": "k_hc_pass8", "avg_launch_us": round(avg_s * 1e6, 2),
                             "attempts_per_ns": round(sites / 2 / avg_s / 1e9, 1),
                             "GBs_algorithmic": round(gbs, 1),

@@ -1834,19 +1834,21 @@ int tri_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
     TriArgs a = tri_args(c, stats);
     hipError_t e = hipSuccess;
     int lds = 0;
-    if (re == 0 && tri_resident_ok(c, a, &lds)) {
-        // chunks of at most 1000 sweeps per launch; the counter advances after each
+    const int n_rec = re > 0 ? n / re : 0;
+    if (n_rec > 0) e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
+    if (tri_resident_ok(c, a, &lds)) {
+        // chunks of at most 1000 sweeps per launch (statistics recorded inside);
+        // the counter advances after each
         for (int done = 0; done < n && e == hipSuccess;) {
             const int k = std::min(1000, n - done);
             e = timed(c, SPINMC_K_RESIDENT,
-                      [&] { return launch_nat_resident(a, k, lds, c->stream); }, c->stream);
+                      [&] { return launch_nat_resident(a, k, done, re, lds, c->stream); },
+                      c->stream);
             if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)k, c->stream);
             done += k;
         }
         return check_dev(c, e, "sweep");
     }
-    const int n_rec = re > 0 ? n / re : 0;
-    if (n_rec > 0) e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
     const bool hc = a.model == kModelIsingHC;
     const int n_col = hc ? 2 : 3;
     for (int i = 0; i < n && e == hipSuccess; ++i) {

@@ -32,9 +32,12 @@ hipError_t launch_tri_pass(const TriArgs& a, int c, int sweep_off, hipStream_t s
 // by the caller).
 hipError_t launch_tri_stats(const TriArgs& a, int rec_row, hipStream_t s);
 hipError_t launch_tri_observables(const TriArgs& a, double* obs, hipStream_t s);
-// n_sweeps unrecorded sweeps of every replica in one launch, lattices in LDS
+// n_sweeps sweeps of every replica in one launch, lattices in LDS
 // (lds_bytes >= the largest lattice; Lx % 12 == 0 triangular, % 8 == 0
-// chain / cubic).
-hipError_t launch_nat_resident(const TriArgs& a, int n_sweeps, int lds_bytes, hipStream_t s);
+// chain / cubic).  The launch holds sweeps sw0 .. sw0 + n_sweeps - 1 of a
+// call; with re > 0, sweep k re of the call adds its statistics to stats row
+// k - 1 (zeroed by the caller).
+hipError_t launch_nat_resident(const TriArgs& a, int n_sweeps, int sw0, int re, int lds_bytes,
+                               hipStream_t s);
 
 }  // namespace spinmc

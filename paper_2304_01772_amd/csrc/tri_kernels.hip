@@ -442,8 +442,46 @@ __global__ void k_tri_observables(TriArgs a, double* obs) {
 // per-pass launches and lattice round trips.  Needs Lx % 12 == 0 for the
 // triangular lattice (the four sites of a Philox block in one row) and
 // Lx % 8 == 0 for the chain / cubic lattices.
+// The statistics of k_tri_stats / k_hc_stats ([M, B1, B2, B3]) of an LDS
+// lattice, this thread's share: four sites per 32-bit word.  A -1 byte has
+// bit 7 set, so M = sites - 2 popc(v & 0x80808080); two +-1 bytes differ
+// iff their xor is 0xFE (7 bits), so a bond sum is sites - 2 popc(v ^ w) / 7
+// with w the word of the bond partners (byte funnel shifts for the x + 1
+// and, on the triangular lattice, the down-left partners).
 template <int MODEL>
-__global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps) {
+__device__ __forceinline__ int4 nat_stats(const int8_t* ls, int Lx, int Ly, int Lz) {
+    const int plane = Lx * Ly, nq = (plane * Lz) >> 2;
+    int cnt = 0;
+    uint32_t pm = 0, p1 = 0, p2 = 0, p3 = 0;
+    for (int q = threadIdx.x; q < nq; q += blockDim.x) {
+        const int i = 4 * q;
+        const int row = qdiv(i, Lx, true), x0 = i - row * Lx;  // i < 2^16
+        const uint32_t v = ld32(ls + i);
+        const uint32_t nx = ld32(ls + row * Lx + (x0 + 4 == Lx ? 0 : x0 + 4));
+        pm += __popc(v & 0x80808080u);
+        p1 += __popc(v ^ abyte(nx, v, 1));
+        if (MODEL == kModelIsingTri) {
+            const int yd = row + 1 == Ly ? 0 : row + 1;
+            const uint32_t d = ld32(ls + yd * Lx + x0);
+            const uint32_t dp = ld32(ls + yd * Lx + (x0 == 0 ? Lx - 4 : x0 - 4));
+            p2 += __popc(v ^ d);
+            p3 += __popc(v ^ abyte(d, dp, 3));
+        } else {
+            const int z = qdiv(row, Ly, true), y = row - z * Ly;
+            if (Ly > 1) p2 += __popc(v ^ ld32(ls + (z * Ly + (y + 1 == Ly ? 0 : y + 1)) * Lx + x0));
+            if (Lz > 1) p3 += __popc(v ^ ld32(ls + (z + 1 == Lz ? 0 : z + 1) * plane + y * Lx + x0));
+        }
+        cnt += 4;
+    }
+    const bool has2 = MODEL == kModelIsingTri || Ly > 1, has3 = MODEL == kModelIsingTri || Lz > 1;
+    return make_int4(cnt - 2 * (int)pm, cnt - 2 * (int)(p1 / 7), has2 ? cnt - 2 * (int)(p2 / 7) : 0,
+                     has3 ? cnt - 2 * (int)(p3 / 7) : 0);
+}
+
+// REC (re > 0): after sweep sw0 + sw + 1 = k re of the call the statistics
+// of the LDS lattice are added to stats row k - 1 (zeroed by the caller).
+template <int MODEL, bool REC>
+__global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps, int sw0, int re) {
     extern __shared__ __align__(16) int8_t ls[];
     __shared__ uint64_t lt[16];
     const int r = blockIdx.x;
@@ -516,23 +554,49 @@ __global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps) 
             }
             __syncthreads();
         }
+        if (REC && (sw0 + sw + 1) % re == 0) {
+            int4 st = nat_stats<MODEL>(ls, Lx, Ly, Lz);
+            for (int o = 32; o > 0; o >>= 1) {
+                st.x += __shfl_xor(st.x, o);
+                st.y += __shfl_xor(st.y, o);
+                st.z += __shfl_xor(st.z, o);
+                st.w += __shfl_xor(st.w, o);
+            }
+            if ((threadIdx.x & 63) == 0) {
+                int32_t* rw = a.stats + ((size_t)((sw0 + sw + 1) / re - 1) * a.R + r) * a.width;
+                atomicAdd(&rw[0], st.x);
+                atomicAdd(&rw[1], st.y);
+                atomicAdd(&rw[2], st.z);
+                atomicAdd(&rw[3], st.w);
+            }
+            __syncthreads();  // the next sweep writes the lattice
+        }
     }
     for (int i = threadIdx.x; i < n / 4; i += blockDim.x)
         reinterpret_cast<uint32_t*>(lat)[i] = reinterpret_cast<const uint32_t*>(ls)[i];
 }
 
-hipError_t launch_nat_resident(const TriArgs& a, int n_sweeps, int lds_bytes, hipStream_t s) {
-    if (a.model == kModelIsingHC) {
-        hipFuncSetAttribute((const void*)k_nat_resident<kModelIsingHC>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        hipLaunchKernelGGL(k_nat_resident<kModelIsingHC>, dim3(a.R), dim3(1024), lds_bytes, s, a,
-                           n_sweeps);
-    } else {
-        hipFuncSetAttribute((const void*)k_nat_resident<kModelIsingTri>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-        hipLaunchKernelGGL(k_nat_resident<kModelIsingTri>, dim3(a.R), dim3(1024), lds_bytes, s, a,
-                           n_sweeps);
-    }
+hipError_t launch_nat_resident(const TriArgs& a, int n_sweeps, int sw0, int re, int lds_bytes,
+                               hipStream_t s) {
+    const bool hc = a.model == kModelIsingHC, rec = re > 0;
+    const void* fn = hc ? (rec ? (const void*)k_nat_resident<kModelIsingHC, true>
+                               : (const void*)k_nat_resident<kModelIsingHC, false>)
+                        : (rec ? (const void*)k_nat_resident<kModelIsingTri, true>
+                               : (const void*)k_nat_resident<kModelIsingTri, false>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return e;
+    if (hc && rec)
+        hipLaunchKernelGGL((k_nat_resident<kModelIsingHC, true>), dim3(a.R), dim3(1024), lds_bytes,
+                           s, a, n_sweeps, sw0, re);
+    else if (hc)
+        hipLaunchKernelGGL((k_nat_resident<kModelIsingHC, false>), dim3(a.R), dim3(1024),
+                           lds_bytes, s, a, n_sweeps, sw0, re);
+    else if (rec)
+        hipLaunchKernelGGL((k_nat_resident<kModelIsingTri, true>), dim3(a.R), dim3(1024),
+                           lds_bytes, s, a, n_sweeps, sw0, re);
+    else
+        hipLaunchKernelGGL((k_nat_resident<kModelIsingTri, false>), dim3(a.R), dim3(1024),
+                           lds_bytes, s, a, n_sweeps, sw0, re);
     return hipGetLastError();
 }
 
