@@ -85,8 +85,12 @@ enum spinmc_status {
  * within-colour index k = y Lx/3 + x/3 take word k & 3 of Philox block
  * (k >> 2, p, rid, 0) whole as W and flip iff W < ceil(2^32 exp(-beta dE)),
  * dE = 2 s (J S6 + h) (always when dE <= 0).  Initial state as for Ising.
- * A context holds only triangular replicas; its schedule is ignored and
- * spinmc_autotune returns it unchanged; spinmc_grad is not available.
+ * A context holds only triangular replicas.  Sweeps, recorded or not, run
+ * resident in LDS (one workgroup per replica) when every lattice holds at
+ * most 64 KiB and every Lx is a multiple of 12, unless the schedule's mode
+ * is 2 (streamed passes); tile_rows and wg_threads are ignored, and
+ * spinmc_autotune returns the schedule unchanged.  spinmc_grad is not
+ * available.
  *
  * Chain, square and simple-cubic Ising in one natural layout (the 1D, 2D and
  * 3D convolutions of the Methods; SPINMC_ISING_HC): an Lz x Ly x Lx array,
@@ -96,7 +100,8 @@ enum spinmc_status {
  * p = 2t + c; the colour-c site of the pair (2k, 2k + 1) takes word k & 3 of
  * Philox block (k >> 2, p, rid, 0) whole as W; flip iff
  * W < ceil(2^32 exp(-beta 2 s (J S + h))), S the neighbour sum.  States are
- * int8 [Lz][Ly][Lx]; contexts as for the triangular lattice.
+ * int8 [Lz][Ly][Lx]; contexts as for the triangular lattice (resident when
+ * every lattice holds at most 64 KiB and every Lx is a multiple of 8).
  *
  * Multispin-coded square-lattice Ising (1-bit spins; SPINMC_ISING_MSC): one
  * descriptor is a group of 32 replicas with its Lx (a multiple of 8), Ly

@@ -1815,7 +1815,7 @@ int tri_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
     return check_dev(c, e, "get_state");
 }
 
-// Resident schedule for unrecorded sweeps: every lattice in LDS (<= 64 KiB,
+// Resident schedule (recorded sweeps too): every lattice in LDS (<= 64 KiB,
 // so that two workgroups fit a compute unit) and the span alignment.
 bool tri_resident_ok(const spinmc_ctx* c, const TriArgs& a, int* lds) {
     if (c->sched.mode == 2) return false;  // streamed passes requested
