@@ -98,11 +98,12 @@ def test_tri_unrecorded_sweeps_resident_and_streamed(mode):
 
 
 def test_tri_large_batch_streamed_two_blocks_per_lane():
-    """Large streamed passes (here 1366 replicas, 192 x 192 but the first
-    180 x 180, a ragged last workgroup; 2^22 Philox blocks per pass) give
-    each lane two blocks; sampled replicas equal the oracle bit for bit."""
+    """Large streamed passes (here 1368 replicas, 192 x 192 but the first
+    180 x 180, a ragged last workgroup; over 2^22 Philox blocks per pass)
+    give each lane two blocks; 6 x 1368 workgroups, a multiple of 8, take the
+    XCD-grouped order.  Sampled replicas equal the oracle bit for bit."""
     from paper_2304_01772_amd.sampler import Sampler
-    n_rep = 1366  # 1366 * 3072 blocks >= 2^22
+    n_rep = 1368
     shapes = [(180, 180)] + [(192, 192)] * (n_rep - 1)
     reps = [_rep(Ly, Lx, 1.0, 0.05, 0.2747, 500 + i) for i, (Ly, Lx) in enumerate(shapes)]
     smp = Sampler(reps, 23, init=True)
@@ -113,4 +114,22 @@ def test_tri_large_batch_streamed_two_blocks_per_lane():
     for r in picks:
         want, _ = orc.tri_run(init[r], 1.0, 0.05, 0.2747, 23, 500 + r, 0, 3)
         assert np.array_equal(smp.get_state(r), want), r
+    smp.close()
+
+
+def test_tri_streamed_xcd_order_small_grid():
+    """Eight replicas of one workgroup each (24 x 24 and 36 x 48): the
+    streamed grid of 8 workgroups takes the XCD-grouped order; recorded
+    states and statistics equal the oracle's."""
+    from paper_2304_01772_amd.sampler import Sampler
+    shapes = [(24, 24)] * 4 + [(36, 48)] * 4
+    reps = [_rep(Ly, Lx, 0.8, 0.1, 0.5, 300 + i) for i, (Ly, Lx) in enumerate(shapes)]
+    smp = Sampler(reps, 31, init=True)
+    smp.set_schedule(mode="stream")
+    init = [smp.get_state(r) for r in range(len(reps))]
+    st = smp.sweep(6, 2).cpu().numpy()
+    for r in range(len(reps)):
+        want, ost = orc.tri_run(init[r], 0.8, 0.1, 0.5, 31, 300 + r, 0, 6, 2)
+        assert np.array_equal(smp.get_state(r), want), r
+        assert np.array_equal(st[:, r], ost), r
     smp.close()
