@@ -362,9 +362,10 @@ __device__ __forceinline__ void cpm_moore_site(const CpmArgs& a, const RepDev& R
     const int Lx = R.Lx, Ly = R.Ly;
     const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
     const int xl = x == 0 ? Lx - 1 : x - 1, xr = x + 1 == Lx ? 0 : x + 1;
-    const int32_t* ru = ids + (size_t)yu * Lx;
-    const int32_t* ry = ids + (size_t)y * Lx;
-    const int32_t* rd = ids + (size_t)yd * Lx;
+    // int offsets: a replica holds fewer than 2^31 sites
+    const int32_t* ru = ids + yu * Lx;
+    const int32_t* ry = ids + y * Lx;
+    const int32_t* rd = ids + yd * Lx;
     const int nb[8] = {ru[xl], ru[x], ru[xr], ry[xl], ry[xr], rd[xl], rd[x], rd[xr]};
     const int s = ry[x];
     uint32_t w[4];
@@ -372,7 +373,7 @@ __device__ __forceinline__ void cpm_moore_site(const CpmArgs& a, const RepDev& R
     const uint32_t word = (u & 2) ? ((u & 1) ? w[3] : w[2]) : ((u & 1) ? w[1] : w[0]);
     const int tg = cpm_decide(a, R, nb, s, word, 4u * kq + (uint32_t)u, p, qthr, lsa, lty, ljs);
     if (tg >= 0) {
-        ids[(size_t)y * Lx + x] = tg;
+        ids[y * Lx + x] = tg;
         atomicAdd(&area[tg], 1);
         atomicAdd(&area[s], -1);
     }
