@@ -1841,8 +1841,11 @@ int tri_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
         // the counter advances after each
         for (int done = 0; done < n && e == hipSuccess;) {
             const int k = std::min(1000, n - done);
+            // the launch's recorded rows (16 B each) gather in LDS behind the lattice
+            const int rows = re > 0 ? (done + k) / re - done / re : 0;
+            const int lds_k = lds + 16 * rows;
             e = timed(c, SPINMC_K_RESIDENT,
-                      [&] { return launch_nat_resident(a, k, done, re, lds, c->stream); },
+                      [&] { return launch_nat_resident(a, k, done, re, lds_k, c->stream); },
                       c->stream);
             if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)k, c->stream);
             done += k;

@@ -34,9 +34,10 @@ hipError_t launch_tri_stats(const TriArgs& a, int rec_row, hipStream_t s);
 hipError_t launch_tri_observables(const TriArgs& a, double* obs, hipStream_t s);
 // n_sweeps sweeps of every replica in one launch, lattices in LDS
 // (lds_bytes >= the largest lattice; Lx % 12 == 0 triangular, % 8 == 0
-// chain / cubic).  The launch holds sweeps sw0 .. sw0 + n_sweeps - 1 of a
-// call; with re > 0, sweep k re of the call adds its statistics to stats row
-// k - 1 (zeroed by the caller).
+// chain / cubic; with re > 0 also 16 B per recorded row of the launch).
+// The launch holds sweeps sw0 .. sw0 + n_sweeps - 1 of a call; with re > 0,
+// sweep k re of the call stores its statistics in stats row k - 1 (columns
+// 0..3; the caller zeroes the rows).
 hipError_t launch_nat_resident(const TriArgs& a, int n_sweeps, int sw0, int re, int lds_bytes,
                                hipStream_t s);
 

@@ -479,7 +479,10 @@ __device__ __forceinline__ int4 nat_stats(const int8_t* ls, int Lx, int Ly, int 
 }
 
 // REC (re > 0): after sweep sw0 + sw + 1 = k re of the call the statistics
-// of the LDS lattice are added to stats row k - 1 (zeroed by the caller).
+// of the LDS lattice go to stats row k - 1 (columns 0..3; the caller zeroes
+// the rows).  The rows of the launch gather in LDS behind the lattice (LDS
+// atomics of the waves) and are stored once at its end, so no sweep waits
+// for global memory.
 template <int MODEL, bool REC>
 __global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps, int sw0, int re) {
     extern __shared__ __align__(16) int8_t ls[];
@@ -495,6 +498,11 @@ __global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps, 
             MODEL == kModelIsingHC ? 2 + 2 * (Ly > 1) + 2 * (Lz > 1) : 6);
     for (int i = threadIdx.x; i < n / 4; i += blockDim.x)
         reinterpret_cast<uint32_t*>(ls)[i] = reinterpret_cast<const uint32_t*>(lat)[i];
+    // recorded rows rec0 .. rec0 + n_rows - 1 (1-based) of this launch
+    int* lrec = reinterpret_cast<int*>(ls + ((n + 15) & ~15));
+    const int rec0 = REC ? sw0 / re + 1 : 0;
+    const int n_rows = REC ? (sw0 + n_sweeps) / re - sw0 / re : 0;
+    for (int i = threadIdx.x; i < 4 * n_rows; i += blockDim.x) lrec[i] = 0;
     __syncthreads();
     const uint64_t t0 = *a.t_base;
     constexpr int ncol = MODEL == kModelIsingHC ? 2 : 3;
@@ -563,15 +571,18 @@ __global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps, 
                 st.w += __shfl_xor(st.w, o);
             }
             if ((threadIdx.x & 63) == 0) {
-                int32_t* rw = a.stats + ((size_t)((sw0 + sw + 1) / re - 1) * a.R + r) * a.width;
-                atomicAdd(&rw[0], st.x);
-                atomicAdd(&rw[1], st.y);
-                atomicAdd(&rw[2], st.z);
-                atomicAdd(&rw[3], st.w);
+                int* row = lrec + 4 * ((sw0 + sw + 1) / re - rec0);
+                atomicAdd(&row[0], st.x);
+                atomicAdd(&row[1], st.y);
+                atomicAdd(&row[2], st.z);
+                atomicAdd(&row[3], st.w);
             }
             __syncthreads();  // the next sweep writes the lattice
         }
     }
+    if (REC)
+        for (int i = threadIdx.x; i < 4 * n_rows; i += blockDim.x)
+            a.stats[((size_t)(rec0 - 1 + (i >> 2)) * a.R + r) * a.width + (i & 3)] = lrec[i];
     for (int i = threadIdx.x; i < n / 4; i += blockDim.x)
         reinterpret_cast<uint32_t*>(lat)[i] = reinterpret_cast<const uint32_t*>(ls)[i];
 }
