@@ -177,7 +177,7 @@ __global__ void __launch_bounds__(256) k_cov_partial(int R, const int32_t* stats
 // Stage 2: one wave per replica; lane j adds chunks j, j + 64, ..., the wave
 // adds the lanes (butterfly: every lane ends with the sums), lanes 0..9 take
 // one covariance each, lane 0 evaluates the outputs.
-__global__ void __launch_bounds__(64) k_cov_final(const RepDev* reps, int R, int n_chunks,
+__global__ void __launch_bounds__(64) k_cov_final(const RepDev* reps, int n_chunks,
                                                   long long n, const long long* partial,
                                                   const double* gout, double* means,
                                                   double* grads, double* dtheta) {
@@ -211,7 +211,7 @@ hipError_t launch_cov_grad_split(const RepDev* reps, int R, const int32_t* stats
     const int n_chunks = (n + kCovChunk - 1) / kCovChunk;
     hipLaunchKernelGGL(k_cov_partial, dim3((R + 63) / 64, n_chunks), dim3(256), 0, s, R, stats,
                        n_rec, burn_in, width, n_chunks, partial);
-    hipLaunchKernelGGL(k_cov_final, dim3(R), dim3(64), 0, s, reps, R, n_chunks, (long long)n,
+    hipLaunchKernelGGL(k_cov_final, dim3(R), dim3(64), 0, s, reps, n_chunks, (long long)n,
                        partial, gout, means, grads, dtheta);
     return hipGetLastError();
 }
