@@ -564,12 +564,12 @@ __global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps, 
         }
         if (REC && (sw0 + sw + 1) % re == 0) {
             int4 st = nat_stats<MODEL>(ls, Lx, Ly, Lz);
-            for (int o = 32; o > 0; o >>= 1) {
-                st.x += __shfl_xor(st.x, o);
-                st.y += __shfl_xor(st.y, o);
-                st.z += __shfl_xor(st.z, o);
-                st.w += __shfl_xor(st.w, o);
-            }
+            // wave sums over the active lanes (every wave of the workgroup is
+            // full and has reconverged after the loop)
+            st.x = __ockl_wfred_add_i32(st.x);
+            st.y = __ockl_wfred_add_i32(st.y);
+            st.z = __ockl_wfred_add_i32(st.z);
+            st.w = __ockl_wfred_add_i32(st.w);
             if ((threadIdx.x & 63) == 0) {
                 int* row = lrec + 4 * ((sw0 + sw + 1) / re - rec0);
                 atomicAdd(&row[0], st.x);
