@@ -13,6 +13,8 @@
 // workgroup per replica.  Long records: chunk sums with one lane per replica
 // (rows of consecutive replicas are contiguous), then one thread per replica
 // adds its chunks.
+// the 64-bit wavefront reduction (__ockl_wfred_add_i64) of the HIP headers
+#define HIP_ENABLE_EXTRA_WARP_SYNC_TYPES 1
 #include "grad_internal.hpp"
 
 namespace spinmc {
@@ -174,9 +176,9 @@ __global__ void __launch_bounds__(256) k_cov_partial(int R, const int32_t* stats
     for (int i = 0; i < kSums; ++i) out[i] = s[i] + red[0][i][l] + red[1][i][l] + red[2][i][l];
 }
 
-// Stage 2: one wave per replica; lane j adds chunks j, j + 64, ..., the wave
-// adds the lanes (butterfly: every lane ends with the sums), lanes 0..9 take
-// one covariance each, lane 0 evaluates the outputs.
+// Stage 2: one wave per replica; lane j adds chunks j, j + 64, ..., the
+// wavefront reduction gives every lane the sums, lanes 0..9 take one
+// covariance each, lane 0 evaluates the outputs.
 __global__ void __launch_bounds__(64) k_cov_final(const RepDev* reps, int n_chunks,
                                                   long long n, const long long* partial,
                                                   const double* gout, double* means,
@@ -191,10 +193,9 @@ __global__ void __launch_bounds__(64) k_cov_final(const RepDev* reps, int n_chun
 #pragma unroll
         for (int i = 0; i < kSums; ++i) S[i] += p[i];
     }
+    // the wave's sums in every lane (one full wave, reconverged after the loop)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int i = 0; i < kSums; ++i) S[i] += __shfl_xor(S[i], off, 64);
+    for (int i = 0; i < kSums; ++i) S[i] = __ockl_wfred_add_i64(S[i]);
     __shared__ double cv[10];
     if (lane < 10) cv[lane] = cov_term(lane, S, n);  // every lane holds the sums
     __syncthreads();
