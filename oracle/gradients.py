@@ -63,3 +63,50 @@ def ising_grad_batch(stats, Jx, Jy, h, beta, N, burn_in, grad_out=None):
         return means, grads
     g = np.asarray(grad_out, np.float64)
     return means, grads, np.einsum("ro,rop->rp", g, grads)
+
+
+def ising_grad_exact(M, Bx, By, Jx, Jy, h, beta, N):
+    """The same estimator in exact rational arithmetic, for parity at FP64
+    rounding level.  Integer moments of the samples (Python ints), every
+    parameter taken as the exact value of its binary floating-point number
+    (``Fraction(float)``), covariances Cov(a, b) = (n S_ab - S_a S_b) / n^2.
+
+    Returns (values, scales), two dicts of ``Fraction`` keyed "e", "absm",
+    "m2", "chi" (the replica means, chi = beta N (<m^2> - <|m|>^2)) and
+    "grad" (a 2 x 3 nested list, O = (e, |m|), theta = (Jx, Jy, h)).  A
+    scale is the sum of the absolute values of the terms that make up its
+    value: a floating-point evaluation of the same expression that rounds
+    each term and each operation errs by a few units of 2^-53 of it."""
+    from fractions import Fraction as F
+    M = [int(v) for v in np.asarray(M, np.int64)]
+    Bx = [int(v) for v in np.asarray(Bx, np.int64)]
+    By = [int(v) for v in np.asarray(By, np.int64)]
+    n = len(M)
+    aM = [abs(v) for v in M]
+    X = [Bx, By, M]
+    S = [sum(x) for x in X]
+    Sa = sum(aM)
+
+    def cov(a, b):
+        return F(n * sum(u * v for u, v in zip(a, b)) - sum(a) * sum(b), n * n)
+
+    Jx, Jy, h, beta = F(float(Jx)), F(float(Jy)), F(float(h)), F(float(beta))
+    N = F(int(N))
+    J = [Jx, Jy, h]
+    vals, scales = {}, {}
+    vals["e"] = -(Jx * S[0] + Jy * S[1] + h * S[2]) / (n * N)
+    scales["e"] = (abs(Jx * S[0]) + abs(Jy * S[1]) + abs(h * S[2])) / (n * N)
+    vals["absm"] = scales["absm"] = F(Sa, n) / N
+    vals["m2"] = scales["m2"] = F(sum(v * v for v in M), n) / (N * N)
+    vals["chi"] = beta * cov(aM, aM) / N
+    scales["chi"] = abs(vals["chi"])
+    C = [[cov(X[i], X[j]) for j in range(3)] for i in range(3)]
+    g, gs = [[None] * 3, [None] * 3], [[None] * 3, [None] * 3]
+    for j in range(3):
+        adh = sum(J[i] * C[i][j] for i in range(3))
+        g[0][j] = -F(S[j], n) / N - beta * adh / N
+        gs[0][j] = abs(F(S[j], n) / N) + beta * sum(abs(J[i] * C[i][j]) for i in range(3)) / N
+        g[1][j] = beta * cov(aM, X[j]) / N
+        gs[1][j] = abs(g[1][j])
+    vals["grad"], scales["grad"] = g, gs
+    return vals, scales

@@ -10,7 +10,11 @@ boundary lengths = von Neumann bonds between different ids by type pair
 (the cell-sorting boundary measure of the Results section).
 
 Pins: integer statistics are recounted from lattices in the tests; the energy
-conventions are pinned through exact enumeration (tests/test_oracle_exact.py).
+conventions are pinned through exact enumeration; chi through the exact 4x4
+distribution, where beta N <m^2> at h = 0 equals the field derivative
+d<m>/dh of the exact magnetisation, and through oracle chains; the CPM energy
+against a brute-force Eq. (3) and the boundary slots against a recount
+(tests/test_oracle_exact.py, tests/test_oracle_cpm.py).
 """
 import numpy as np
 
@@ -26,10 +30,19 @@ def ising(stats, Jx, Jy, h, N):
     return dict(e=H / N, absm=np.abs(M) / N, m2=(M / N) ** 2)
 
 
-def susceptibility(absm, m2, beta, N, axis=0):
-    """chi = beta N (<m^2> - <|m|>^2) with plain FP64 means over ``axis``."""
-    mean_abs = np.mean(np.asarray(absm, np.float64), axis=axis)
-    mean_m2 = np.mean(np.asarray(m2, np.float64), axis=axis)
+def susceptibility(absm, m2, beta, N, axis=0, weights=None):
+    """chi = beta N (<m^2> - <|m|>^2) with plain FP64 means over ``axis``;
+    ``weights`` (same shape as the samples) turns the means into weighted
+    means, so that a test can feed an exact distribution."""
+    absm = np.asarray(absm, np.float64)
+    m2 = np.asarray(m2, np.float64)
+    if weights is None:
+        mean_abs = np.mean(absm, axis=axis)
+        mean_m2 = np.mean(m2, axis=axis)
+    else:
+        w = np.asarray(weights, np.float64)
+        mean_abs = np.sum(w * absm, axis=axis) / np.sum(w, axis=axis)
+        mean_m2 = np.sum(w * m2, axis=axis) / np.sum(w, axis=axis)
     return np.asarray(beta, np.float64) * N * (mean_m2 - mean_abs ** 2)
 
 

@@ -17,7 +17,8 @@ bool valid(const spinmc_dmc_params* p) {
     return p && p->R >= 1 && p->Lx >= 2 && p->Ly >= 2 && (p->Lx & 1) == 0 && (p->Ly & 1) == 0 &&
            (int64_t)p->Lx * p->Ly <= (1 << 28) && p->n_sweeps >= 0 && std::isfinite(p->beta) &&
            std::isfinite(p->alpha) && p->alpha >= 0.f && std::isfinite(p->h) &&
-           (uint64_t)p->rid0 + (uint64_t)p->R <= (1ull << 32);
+           (uint64_t)p->rid0 + (uint64_t)p->R <= (1ull << 32) &&
+           p->t0 <= (1ull << 31) && p->t0 + (uint64_t)p->n_sweeps <= (1ull << 31);
 }
 
 DmcArgs args(const spinmc_dmc_params* p, float* s, const float* Jx, const float* Jy) {

@@ -783,8 +783,15 @@ int spinmc_sweep(spinmc_ctx* c, int32_t n, int32_t re, void* dev_stats) {
     if (c->poisoned) return fail(SPINMC_E_DEVICE, "sweep: context poisoned");
     if (n < 0 || re < 0) return fail(SPINMC_E_INVALID, "sweep: negative count");
     if (re > 0 && !dev_stats) return fail(SPINMC_E_INVALID, "sweep: recording needs dev_stats");
-    if ((uint64_t)c->t + (uint64_t)n >= ((uint64_t)1 << 31))
-        return fail(SPINMC_E_INVALID, "sweep: sweep counter would exceed 2^31");
+    // Philox counter word 1 carries the pass p = n_col t + c: every pass of
+    // the call must fit 32 bits, i.e. (t + n) n_col <= 2^32, or later passes
+    // would reuse the random words of earlier ones.
+    const uint64_t n_col = c->cpm ? (c->cpm_range == 2 ? 9u : 4u)
+                           : (c->tri && !c->reps.empty() &&
+                              c->reps[0].d.model == SPINMC_ISING_TRI) ? 3u : 2u;
+    if (((uint64_t)c->t + (uint64_t)n) * n_col > ((uint64_t)1 << 32))
+        return fail(SPINMC_E_INVALID, "sweep: pass counter %llu (t + n) x %llu colours exceeds 2^32",
+                    (unsigned long long)(c->t + (uint64_t)n), (unsigned long long)n_col);
     if (n == 0) return SPINMC_OK;
     int rc = c->cpm   ? cpm_sweep(c, n, re, (int32_t*)dev_stats)
              : c->msc ? msc_sweep(c, n, re, (int32_t*)dev_stats)
@@ -829,6 +836,15 @@ int spinmc_grad(spinmc_ctx* c, const void* dev_stats, int32_t n_rec, int32_t bur
         return fail(SPINMC_E_INVALID, "grad: need 0 <= burn_in < n_rec");
     if (dtheta && !gout) return fail(SPINMC_E_INVALID, "grad: dtheta needs grad_out");
     const int n = n_rec - burn_in;
+    // The moment sums are exact int64: |M|, |Bx|, |By| <= N (sites per
+    // lattice) bound every product by N^2 and a sum over n samples by n N^2.
+    for (const HostRep& h : c->reps) {
+        const unsigned __int128 N = (unsigned __int128)h.dev.Lx * (unsigned)h.dev.Ly;
+        if ((unsigned __int128)n * N * N >= ((unsigned __int128)1 << 63))
+            return fail(SPINMC_E_INVALID,
+                        "grad: %d samples of a %d x %d lattice overflow the int64 moment sums",
+                        n, h.dev.Lx, h.dev.Ly);
+    }
     const bool split = n >= kCovSplitMin && (n + kCovChunk - 1) / kCovChunk <= 65535;
     hipError_t e = hipSuccess;
     if (split) {

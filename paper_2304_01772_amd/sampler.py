@@ -125,6 +125,31 @@ class Sampler:
         return T[: n.value], int(aux.value)
 
     # ------------------------------------------------------------- sweeps
+    def _same_device(self, t):
+        want = self.device
+        if t.device.type != want.type:
+            return False
+        if want.index is not None:
+            return t.device.index == want.index
+        return want.type != "cuda" or t.device.index == torch.cuda.current_device()
+
+    def _check_stats(self, stats, rows, what):
+        """The library writes or reads stats rows through a raw pointer: the
+        tensor must be int32, contiguous, on this sampler's device, shaped
+        [>= rows, R, width]."""
+        if not isinstance(stats, torch.Tensor):
+            raise ValueError(f"{what}: stats must be a torch.Tensor")
+        if stats.dtype != torch.int32:
+            raise ValueError(f"{what}: stats must be int32, got {stats.dtype}")
+        if not self._same_device(stats):
+            raise ValueError(f"{what}: stats is on {stats.device}, the sampler on {self.device}")
+        if not stats.is_contiguous():
+            raise ValueError(f"{what}: stats must be contiguous")
+        if stats.dim() != 3 or tuple(stats.shape[1:]) != (self.R, self.width) or \
+                stats.shape[0] < rows:
+            raise ValueError(f"{what}: stats of shape {tuple(stats.shape)}, need "
+                             f"[>= {rows}, {self.R}, {self.width}]")
+
     def sweep(self, n, record_every=0, stats=None):
         """Run n sweeps; returns the int32 statistics tensor
         [n // record_every, R, width] on the device (or None)."""
@@ -133,6 +158,7 @@ class Sampler:
             if stats is None:
                 stats = torch.empty((max(n_rec, 1), self.R, self.width), dtype=torch.int32,
                                     device=self.device)
+            self._check_stats(stats, n_rec, "sweep")
             ptr = C.c_void_p(stats.data_ptr())
         else:
             ptr = None
@@ -150,7 +176,9 @@ class Sampler:
         """Covariance-estimator gradients from recorded statistics.
         Returns (means [R,4] = (<e>, <|m|>, <m^2>, chi), grads [R,2,3],
         dtheta [R,3] or None)."""
-        stats = stats.contiguous()
+        if isinstance(stats, torch.Tensor) and stats.dim() == 3:
+            stats = stats.contiguous()
+        self._check_stats(stats, 1, "grad")
         n_rec = stats.shape[0]
         means = torch.empty((self.R, 4), dtype=torch.float64, device=self.device)
         grads = torch.empty((self.R, 2, 3), dtype=torch.float64, device=self.device)

@@ -6,7 +6,7 @@
   (B. Kaufman, Phys. Rev. 76, 1232 (1949));
 * Onsager's infinite-lattice energy per site and Yang's spontaneous
   magnetisation (C. N. Yang, Phys. Rev. 85, 808 (1952));
-* the Potts critical coupling ln(1 + sqrt q) and Baxter's energy at it.
+* the Potts critical coupling ln(1 + sqrt q).
 
 Conventions (the ferromagnetic reading of Eq. (1) and Eq. (2)):
 Ising H = -Jx sum_h s s' - Jy sum_v s s' - h sum s; Potts

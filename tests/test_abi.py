@@ -115,7 +115,9 @@ def test_dmc_sizes_and_validation_without_a_device(L):
     assert L.spinmc_dmc_save_floats(C.byref(p)) == 2 * 3 * 2 * 6 * 4
     assert L.spinmc_dmc_work_floats(C.byref(p)) == 2 * 2 * 6 * 4
     for bad in (dict(Lx=7), dict(Ly=0), dict(R=0), dict(n_sweeps=-1), dict(alpha=-1.0),
-                dict(beta=float("nan")), dict(h=float("inf")), dict(rid0=2 ** 32 - 1)):
+                dict(beta=float("nan")), dict(h=float("inf")), dict(rid0=2 ** 32 - 1),
+                # pass counters p = 2t + c of every sweep must fit 32 bits
+                dict(t0=2 ** 31 - 2), dict(t0=2 ** 40)):
         q = _dmc(**bad)
         assert L.spinmc_dmc_save_floats(C.byref(q)) < 0, bad
         assert L.spinmc_dmc_forward(C.byref(q), 1, 1, 1, 1, None) == -1, bad

@@ -27,6 +27,28 @@ def _f32(v):
     return float(np.float32(v))
 
 
+def _assert_exact(means, grads, ost, r, N, gout=None, dth=None):
+    """GPU means and gradients of one replica against the exact rational
+    estimator: each output within 1e-12 of the sum of the magnitudes of its
+    terms.  The kernels form exact integer moments and int128 covariance
+    numerators, then round each of at most about ten FP64 operations per
+    output, i.e. an error of order 1e-15 of that sum; 1e-12 leaves a factor
+    of about a thousand."""
+    v, s = ograd.ising_grad_exact(ost[:, 0], ost[:, 1], ost[:, 2], r["Jx"], r["Jy"], r["h"],
+                                  r.get("beta", 1.0), N)
+    for k, key in enumerate(("e", "absm", "m2", "chi")):
+        assert abs(means[k] - float(v[key])) <= 1e-12 * float(s[key]) + 1e-300, key
+    for o in range(2):
+        for j in range(3):
+            assert abs(grads[o, j] - float(v["grad"][o][j])) <= \
+                1e-12 * float(s["grad"][o][j]) + 1e-300, (o, j)
+    if dth is not None:
+        for j in range(3):
+            want = gout[0] * v["grad"][0][j] + gout[1] * v["grad"][1][j]
+            scale = abs(gout[0]) * s["grad"][0][j] + abs(gout[1]) * s["grad"][1][j]
+            assert abs(dth[j] - float(want)) <= 1e-12 * float(scale) + 1e-300, j
+
+
 # 300 samples: one workgroup per replica; 1100: chunk sums of 64 samples
 # (the last chunk ragged) with one lane per replica, 6 of a wave's 64 lanes
 @pytest.mark.parametrize("n,burn", [(400, 100), (1300, 200)])
@@ -46,14 +68,13 @@ def test_grad_parity_with_oracle(S, n, burn):
         _, ost = orc.ising_run(s0, r["Jx"], r["Jy"], r["h"], 1.0, seed, r["rid"], 0, n, 1)
         assert np.array_equal(st[:, i].cpu().numpy(), ost)
         N = r["Lx"] * r["Ly"]
+        _assert_exact(means[i], grads[i], ost[burn:], r, N, gout=(1, -2), dth=dth[i])
+        # and the plain two-pass FP64 estimator (pinned by exact enumeration)
         mo, go = ograd.ising_grad(ost[burn:, 0], ost[burn:, 1], ost[burn:, 2], r["Jx"], r["Jy"],
                                   r["h"], 1.0, N)
-        np.testing.assert_allclose(means[i, :2], mo, rtol=1e-12, atol=1e-15)
         np.testing.assert_allclose(grads[i], go, rtol=1e-9, atol=1e-12)
-        np.testing.assert_allclose(dth[i], 1.0 * go[0] - 2.0 * go[1], rtol=1e-9, atol=1e-12)
         ob = oobs.ising(ost[burn:], r["Jx"], r["Jy"], r["h"], N)
         chi = oobs.susceptibility(ob["absm"], ob["m2"], 1.0, N)
-        assert abs(means[i, 2] - ob["m2"].mean()) <= 1e-12 * ob["m2"].mean()
         assert abs(means[i, 3] - chi) <= 1e-9 * abs(chi) + 1e-12
 
 
@@ -74,9 +95,7 @@ def test_differentiation_workload_full_size(S):
         want, ost = orc.ising_run(s0, r["Jx"], r["Jy"], r["h"], 1.0, seed, r["rid"], 0, n, 1)
         assert np.array_equal(smp.get_state(i), want)
         assert np.array_equal(st[:, i].cpu().numpy(), ost)
-        _, go = ograd.ising_grad(ost[burn:, 0], ost[burn:, 1], ost[burn:, 2], r["Jx"], r["Jy"],
-                                 r["h"], 1.0, 128 * 128)
-        np.testing.assert_allclose(grads[i].cpu().numpy(), go, rtol=1e-9, atol=1e-12)
+        _assert_exact(means[i].cpu().numpy(), grads[i].cpu().numpy(), ost[burn:], r, 128 * 128)
     smp.close()
 
 

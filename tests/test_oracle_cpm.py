@@ -109,3 +109,106 @@ def test_cell_sorting_trend(orc):
     assert b1["aa"] > b0["aa"]
     assert b1["ma"] < b0["ma"]
     assert math.isfinite(float(b1["ab"]))
+
+
+# ------------------------------------------- statistics against a recount
+def _pair_slots(n_types):
+    """Unordered type pairs (a <= b) in the order a = 0, 1, ...; b = a ...:
+    the position of a pair in this list is its statistics slot."""
+    return [(a, b) for a in range(n_types) for b in range(a, n_types)]
+
+
+def _recount_boundary(ids, ctype, n_types):
+    """Results, Fig. 6 boundary lengths: every von Neumann bond (right and
+    down neighbour on the torus, so each bond once) whose two ids differ,
+    tallied by the unordered pair of the two cells' types."""
+    slots = {p: i for i, p in enumerate(_pair_slots(n_types))}
+    out = np.zeros(10, np.int64)
+    Ly, Lx = ids.shape
+    for y in range(Ly):
+        for x in range(Lx):
+            for ny, nx in ((y, (x + 1) % Lx), ((y + 1) % Ly, x)):
+                a, b = int(ids[y, x]), int(ids[ny, nx])
+                if a == b:
+                    continue
+                ta, tb = sorted((int(ctype[a]), int(ctype[b])))
+                out[slots[(ta, tb)]] += 1
+    return out
+
+
+@pytest.mark.parametrize("n_types,shape,seed", [(2, (6, 8), 21), (3, (12, 10), 22),
+                                                 (4, (8, 16), 23), (4, (12, 18), 24)])
+def test_boundary_counts_equal_a_recount(orc, n_types, shape, seed):
+    """The ten boundary slots of the CPM statistics equal a plain recount of
+    von Neumann bonds between different ids by unordered type pair, for both
+    neighbourhood ranges (the boundary measure does not depend on the range
+    of the adhesion energy)."""
+    rng = np.random.default_rng(seed)
+    n_cells = 9
+    ids = rng.integers(0, n_cells + 1, size=shape).astype(np.int32)
+    # clusters as well as noise: copy a shifted block so that equal-id bonds occur
+    ids[: shape[0] // 2, : shape[1] // 2] = ids[0, 0]
+    ctype = np.concatenate([[0], rng.integers(1, n_types, size=n_cells)]).astype(np.int8)
+    if n_types > 2:
+        ctype[1:n_types] = np.arange(1, n_types)  # every type present
+    A = np.concatenate([[0], rng.integers(3, 12, size=n_cells)]).astype(np.int32)
+    J = rng.integers(0, 9, size=(n_types, n_types)).astype(np.float32)
+    J = np.triu(J) + np.triu(J, 1).T
+    want = _recount_boundary(ids, ctype, n_types)
+    assert want.sum() > 0
+    for nrange in (1, 2):
+        if nrange == 2 and (shape[0] % 6 or shape[1] % 6):
+            continue
+        st = orc.cpm_stats(ids, J, ctype, A, 1.0, nrange=nrange)
+        assert np.array_equal(st[:10].astype(np.int64), want), (nrange, st[:10], want)
+
+
+def test_boundary_slot_of_each_type_pair(orc):
+    """The bonds of an interface between two cells of given types land in
+    the slot of that unordered pair and nowhere else (both orders of the two
+    types, the medium included)."""
+    n_types = 4
+    J = np.zeros((4, 4), np.float32)
+    slots = _pair_slots(n_types)
+    for ta in range(n_types):
+        for tb in range(n_types):
+            # a 2 x 4 torus, left half one id, right half another: two vertical
+            # interfaces crossed by two rows each, 4 bonds.  A type-0 side is
+            # the medium (id 0); the other sides are cells 1 and 2.
+            left = 0 if ta == 0 else 1
+            right = 0 if (tb == 0 and ta != 0) else 2
+            ids = np.array([[left, left, right, right]] * 2, np.int32)
+            ctype = np.array([0, ta, tb], np.int8)
+            A = np.array([0, 4, 4], np.int32)
+            st = orc.cpm_stats(ids, J, ctype, A, 0.0)
+            want = np.zeros(10, np.int64)
+            want[slots.index(tuple(sorted((ta, tb))))] = 4
+            assert np.array_equal(st[:10].astype(np.int64), want), (ta, tb, st[:10])
+
+
+@pytest.mark.parametrize("J,lam", [
+    (np.array([[0, 16, 16], [16, 2, 11], [16, 11, 16]], np.float32), 1.0),
+    (np.array([[0, 3.5, 4.5], [3.5, 1.5, 2.0], [4.5, 2.0, 0.5]], np.float32), 0.5),
+    (np.array([[0, 1.25, 2.0, 0.75], [1.25, 0.5, 1.0, 3.0], [2.0, 1.0, 0.25, 1.5],
+               [0.75, 3.0, 1.5, 2.0]], np.float32), 1.5),
+])
+def test_range1_energy_statistic_matches_bruteforce(orc, J, lam):
+    """Eq. (3) with the Moore neighbourhood: the fixed-point energy statistic
+    H S equals the brute-force energy (adhesion over unordered Moore pairs of
+    different ids plus the area term over cells) times the scale S."""
+    from test_oracle_onestep import cpm_energy
+    rng = np.random.default_rng(31)
+    S = orc.cpm_scale(J, lam)
+    n_types = J.shape[0]
+    for shape in ((4, 6), (8, 8), (10, 14)):
+        n_cells = 7
+        ids = rng.integers(0, n_cells + 1, size=shape).astype(np.int32)
+        ctype = np.concatenate([[0], rng.integers(1, n_types, size=n_cells)]).astype(np.int8)
+        A = np.concatenate([[0], rng.integers(2, 20, size=n_cells)]).astype(np.int32)
+        area = np.bincount(ids.reshape(-1), minlength=n_cells + 1)
+        st = orc.cpm_stats(ids, J, ctype, A, lam)
+        H = (int(st[11]) << 32) | (int(st[10]) & 0xFFFFFFFF)
+        if H >= 1 << 63:
+            H -= 1 << 64
+        want = cpm_energy(ids, J, ctype, A, lam, area) * S
+        assert H == round(want), (shape, H, want)

@@ -268,3 +268,68 @@ def test_covariance_estimator_on_oracle_chain_within_3sigma(orc):
             est = grads[:, o, j]
             se = est.std(ddof=1) / math.sqrt(R)
             assert abs(est.mean() - g_exact[o, j]) <= 4 * se + 1e-3 * abs(g_exact[o, j]), (o, j)
+
+
+# ---------------------------------------------------------- susceptibility
+def _exact_m(Jx, Jy, h, beta):
+    ex = exact.ising_exact(4, 4, Jx, Jy, h, beta)
+    return float((ex["p"] * ex["M"]).sum() / 16)
+
+
+@pytest.mark.parametrize("beta", [0.2, 0.44, 0.7])
+def test_susceptibility_with_exact_weights(beta):
+    """chi = beta N (<m^2> - <|m|>^2) over the exact 4x4 distribution.  At
+    h = 0 the first term is the field response of the exact magnetisation,
+    beta N <m^2> = d<m>/dh (fluctuation-dissipation, <m> = 0 by symmetry),
+    taken here by central differences of the enumeration; the second uses the
+    exact <|m|>."""
+    ex = exact.ising_exact(4, 4, 1.0, 1.0, 0.0, beta)
+    absm = np.abs(ex["M"]) / 16.0
+    m2 = (ex["M"] / 16.0) ** 2
+    chi = float(observables.susceptibility(absm, m2, beta, 16, weights=ex["p"]))
+    eps = 1e-5
+    dm_dh = (_exact_m(1.0, 1.0, eps, beta) - _exact_m(1.0, 1.0, -eps, beta)) / (2 * eps)
+    want = dm_dh - beta * 16 * ex["absm"] ** 2
+    # central differences err by O(eps^2) of the larger term d<m>/dh
+    assert abs(chi - want) < 1e-8 * max(1.0, abs(dm_dh)), (chi, want)
+    # the plain-sample form equals the weighted one on equally weighted samples
+    rng = np.random.default_rng(3)
+    idx = rng.choice(len(absm), size=5000, p=ex["p"])
+    assert abs(float(observables.susceptibility(absm[idx], m2[idx], beta, 16)) -
+               float(observables.susceptibility(absm[idx], m2[idx], beta, 16,
+                                                weights=np.ones(5000)))) < 1e-12
+
+
+def test_susceptibility_on_oracle_chain_within_4sigma(orc):
+    """chi of each replica's recorded chain, averaged over replicas, against
+    the exact 4x4 value (per-replica chi carries an O(1/n) bias from its own
+    mean, far below the tolerance at 3000 samples)."""
+    beta, R, n, burn = 0.44, 64, 3000, 300
+    states = [orc.ising_init(4, 4, 17, r) for r in range(R)]
+    _, st = orc.ising_run_batch(states, [1.0] * R, [1.0] * R, [0.0] * R, [beta] * R, 17,
+                                np.arange(R), 0, n, 1)
+    obs = observables.ising(st, 1.0, 1.0, 0.0, 16)
+    chi = observables.susceptibility(obs["absm"][:, burn:], obs["m2"][:, burn:], beta, 16,
+                                     axis=1)
+    ex = exact.ising_exact(4, 4, 1.0, 1.0, 0.0, beta)
+    want = beta * 16 * (ex["m2"] - ex["absm"] ** 2)
+    _within(chi, want)
+
+
+def test_exact_rational_estimator_equals_two_pass(orc):
+    """The rational form of the estimator (used for FP64 parity) equals the
+    two-pass FP64 form, which the tests above pin to the derivative of the
+    exact expectation, on chain samples to rounding."""
+    Jx, Jy, h = (float(np.float32(v)) for v in (0.7, 0.9, 0.05))
+    states = [orc.ising_init(4, 4, 5, r) for r in range(4)]
+    _, st = orc.ising_run_batch(states, [Jx] * 4, [Jy] * 4, [h] * 4, [0.5] * 4, 5,
+                                np.arange(4), 0, 800, 1)
+    for r in range(4):
+        s = st[r, 100:]
+        mo, go = gradients.ising_grad(s[:, 0], s[:, 1], s[:, 2], Jx, Jy, h, 0.5, 16)
+        v, sc = gradients.ising_grad_exact(s[:, 0], s[:, 1], s[:, 2], Jx, Jy, h, 0.5, 16)
+        assert abs(float(v["e"]) - mo[0]) <= 1e-12 * float(sc["e"])
+        assert abs(float(v["absm"]) - mo[1]) <= 1e-12 * float(sc["absm"])
+        for o in range(2):
+            for j in range(3):
+                assert abs(float(v["grad"][o][j]) - go[o, j]) <= 1e-9 * float(sc["grad"][o][j])
