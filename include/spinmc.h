@@ -219,6 +219,25 @@ int spinmc_measure(spinmc_ctx *ctx, void *dev_stats, void *dev_obs);
 int spinmc_grad(spinmc_ctx *ctx, const void *dev_stats, int32_t n_rec, int32_t burn_in,
                 const void *dev_grad_out, void *dev_means, void *dev_grads, void *dev_dtheta);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * outputs as spinmc_grad, bit for bit, with the chunk sums in a static
+ * per-device array of 4 MiB instead of a buffer the context allocates.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine); the array's device address is resolved once per device, at
+ * spinmc_create or at the first call, with the context's device current.
+ * Every record length takes the split form (chunks of 64 samples), so
+ * n x ceil((n_rec - burn_in) / 64) x 104 B must not exceed 4 MiB
+ * (SPINMC_E_INVALID otherwise; spinmc_grad has no such limit).  Each call
+ * rewrites every entry it reads, so no state carries over between calls, but
+ * all calls on one device share the array: calls that overlap in time on one
+ * device (different streams or host threads) race and must be serialised by
+ * the caller.  Arguments, outputs and errors otherwise as spinmc_grad.
+ * Asynchronous.                                                             */
+int spinmc_grad_noalloc(spinmc_ctx *ctx, const void *dev_stats, int32_t n_rec, int32_t burn_in,
+                        const void *dev_grad_out, void *dev_means, void *dev_grads,
+                        void *dev_dtheta);
+
 /* Global sweep counter t (host mirror of the device counter).               */
 int spinmc_sweep_counter(const spinmc_ctx *ctx, uint64_t *t);
 

@@ -54,6 +54,8 @@ SIGNATURES = {
     "spinmc_measure": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "spinmc_grad": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p]),
+    "spinmc_grad_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p]),
     "spinmc_sweep_counter": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint64)]),
     "spinmc_stats_width": (C.c_int, [C.c_void_p]),
     "spinmc_num_replicas": (C.c_int, [C.c_void_p]),

@@ -19,6 +19,16 @@ inline size_t cov_partial_entries(int R, int n) {
     return (size_t)((n + kCovChunk - 1) / kCovChunk) * kCovSums * (size_t)R;
 }
 
+// Capacity of the per-device static chunk-sum array behind
+// spinmc_grad_noalloc: 4 MiB of int64 entries (for 256 replicas, records of
+// up to 10,048 samples), for devices 0 .. kCovScratchDevices - 1.
+constexpr size_t kCovScratchEntries = ((size_t)4 << 20) / sizeof(long long);
+constexpr int kCovScratchDevices = 64;
+
+// Device address of that array on `device`, which must be the current
+// device the first time it is asked for (resolved once per device).
+hipError_t cov_scratch(int device, long long** out);
+
 hipError_t launch_cov_grad_split(const RepDev* reps, int R, const int32_t* stats, int n_rec,
                                  int burn_in, int width, const double* gout, double* means,
                                  double* grads, double* dtheta, long long* partial,

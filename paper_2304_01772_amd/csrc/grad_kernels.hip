@@ -17,6 +17,8 @@
 #define HIP_ENABLE_EXTRA_WARP_SYNC_TYPES 1
 #include "grad_internal.hpp"
 
+#include <mutex>
+
 namespace spinmc {
 
 namespace {
@@ -215,6 +217,33 @@ hipError_t launch_cov_grad_split(const RepDev* reps, int R, const int32_t* stats
     hipLaunchKernelGGL(k_cov_final, dim3(R), dim3(64), 0, s, reps, n_chunks, (long long)n,
                        partial, gout, means, grads, dtheta);
     return hipGetLastError();
+}
+
+// Chunk sums of the allocation-free entry point (spinmc_grad_noalloc): one
+// array per device for the life of the process.  Host code never passes the
+// name itself (a host-side stand-in); cov_scratch resolves its device address
+// once per device.  k_cov_partial writes every entry k_cov_final reads, so no
+// call depends on what an earlier one left there.
+static __device__ __align__(256) long long scratch[kCovScratchEntries];
+
+hipError_t cov_scratch(int device, long long** out) {
+    static std::mutex mu;
+    static long long* ptr[kCovScratchDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kCovScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;  // the device must be current
+        long long* p = nullptr;
+        e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+        ptr[device] = p;
+    }
+    *out = ptr[device];
+    return hipSuccess;
 }
 
 hipError_t launch_cov_grad(const RepDev* reps, int R, const int32_t* stats, int n_rec,

@@ -520,6 +520,12 @@ int spinmc_create(const spinmc_replica_desc* d, int32_t n, uint64_t seed, int32_
     if (cpm_seen) return create_cpm(d, n, seed, hip_stream, out);
     spinmc_ctx* c = new spinmc_ctx();
     hipGetDevice(&c->device);
+    {
+        // set-up of spinmc_grad_noalloc's per-device scratch address (the
+        // entry point resolves it itself if this fails)
+        long long* part = nullptr;
+        if (cov_scratch(c->device, &part) != hipSuccess) (void)hipGetLastError();
+    }
     c->stream = (hipStream_t)hip_stream;
     c->seed = seed;
     c->R = n;
@@ -826,15 +832,20 @@ int spinmc_measure(spinmc_ctx* c, void* dev_stats, void* dev_obs) {
     return check_dev(c, e, "measure");
 }
 
-int spinmc_grad(spinmc_ctx* c, const void* dev_stats, int32_t n_rec, int32_t burn_in,
-                const void* gout, void* means, void* grads, void* dtheta) {
-    if (!c || !dev_stats) return fail(SPINMC_E_INVALID, "grad: null argument");
-    if (c->poisoned) return fail(SPINMC_E_DEVICE, "grad: context poisoned");
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by spinmc_grad and spinmc_grad_noalloc.
+int grad_check(spinmc_ctx* c, const void* dev_stats, int32_t n_rec, int32_t burn_in,
+               const void* gout, void* dtheta, const char* who) {
+    if (!c || !dev_stats) return fail(SPINMC_E_INVALID, "%s: null argument", who);
+    if (c->poisoned) return fail(SPINMC_E_DEVICE, "%s: context poisoned", who);
     for (const HostRep& h : c->reps)
-        if (h.dev.model != SPINMC_ISING) return fail(SPINMC_E_UNSUPPORTED, "grad: Ising contexts only");
+        if (h.dev.model != SPINMC_ISING) return fail(SPINMC_E_UNSUPPORTED, "%s: Ising contexts only", who);
     if (n_rec < 1 || burn_in < 0 || burn_in >= n_rec)
-        return fail(SPINMC_E_INVALID, "grad: need 0 <= burn_in < n_rec");
-    if (dtheta && !gout) return fail(SPINMC_E_INVALID, "grad: dtheta needs grad_out");
+        return fail(SPINMC_E_INVALID, "%s: need 0 <= burn_in < n_rec", who);
+    if (dtheta && !gout) return fail(SPINMC_E_INVALID, "%s: dtheta needs grad_out", who);
     const int n = n_rec - burn_in;
     // The moment sums are exact int64: |M|, |Bx|, |By| <= N (sites per
     // lattice) bound every product by N^2 and a sum over n samples by n N^2.
@@ -842,9 +853,21 @@ int spinmc_grad(spinmc_ctx* c, const void* dev_stats, int32_t n_rec, int32_t bur
         const unsigned __int128 N = (unsigned __int128)h.dev.Lx * (unsigned)h.dev.Ly;
         if ((unsigned __int128)n * N * N >= ((unsigned __int128)1 << 63))
             return fail(SPINMC_E_INVALID,
-                        "grad: %d samples of a %d x %d lattice overflow the int64 moment sums",
+                        "%s: %d samples of a %d x %d lattice overflow the int64 moment sums", who,
                         n, h.dev.Lx, h.dev.Ly);
     }
+    return SPINMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int spinmc_grad(spinmc_ctx* c, const void* dev_stats, int32_t n_rec, int32_t burn_in,
+                const void* gout, void* means, void* grads, void* dtheta) {
+    int rc = grad_check(c, dev_stats, n_rec, burn_in, gout, dtheta, "grad");
+    if (rc) return rc;
+    const int n = n_rec - burn_in;
     const bool split = n >= kCovSplitMin && (n + kCovChunk - 1) / kCovChunk <= 65535;
     hipError_t e = hipSuccess;
     if (split) {
@@ -869,6 +892,31 @@ int spinmc_grad(spinmc_ctx* c, const void* dev_stats, int32_t n_rec, int32_t bur
                             c->stream);
     }
     return check_dev(c, e, "grad");
+}
+
+int spinmc_grad_noalloc(spinmc_ctx* c, const void* dev_stats, int32_t n_rec, int32_t burn_in,
+                        const void* gout, void* means, void* grads, void* dtheta) {
+    int rc = grad_check(c, dev_stats, n_rec, burn_in, gout, dtheta, "grad_noalloc");
+    if (rc) return rc;
+    const int n = n_rec - burn_in;
+    const size_t need = cov_partial_entries(c->R, n);
+    if (need > kCovScratchEntries)
+        return fail(SPINMC_E_INVALID,
+                    "grad_noalloc: %d replicas x %d samples need %zu bytes of chunk sums, above "
+                    "the %zu bytes of the static scratch array (use spinmc_grad)",
+                    c->R, n, need * sizeof(long long), kCovScratchEntries * sizeof(long long));
+    long long* part = nullptr;
+    hipError_t e = cov_scratch(c->device, &part);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SPINMC_E_DEVICE, "grad_noalloc: device address of the scratch array on "
+                                     "device %d (%s; that device must be current)",
+                    c->device, hipGetErrorString(e));
+    }
+    e = launch_cov_grad_split(c->d_reps, c->R, (const int32_t*)dev_stats, n_rec, burn_in, c->width,
+                              (const double*)gout, (double*)means, (double*)grads,
+                              (double*)dtheta, part, c->stream);
+    return check_dev(c, e, "grad_noalloc");
 }
 
 int spinmc_profile(spinmc_ctx* c, int32_t enable) {

@@ -176,6 +176,15 @@ class Sampler:
         """Covariance-estimator gradients from recorded statistics.
         Returns (means [R,4] = (<e>, <|m|>, <m^2>, chi), grads [R,2,3],
         dtheta [R,3] or None)."""
+        return self._grad("spinmc_grad", stats, burn_in, grad_out)
+
+    def grad_noalloc(self, stats, burn_in, grad_out=None):
+        """As grad, through spinmc_grad_noalloc (chunk sums in the library's
+        static per-device array; the library allocates nothing, the outputs
+        are still new tensors here)."""
+        return self._grad("spinmc_grad_noalloc", stats, burn_in, grad_out)
+
+    def _grad(self, entry, stats, burn_in, grad_out):
         if isinstance(stats, torch.Tensor) and stats.dim() == 3:
             stats = stats.contiguous()
         self._check_stats(stats, 1, "grad")
@@ -188,9 +197,10 @@ class Sampler:
             grad_out = grad_out.to(device=self.device, dtype=torch.float64).contiguous()
             dth = torch.empty((self.R, 3), dtype=torch.float64, device=self.device)
             gptr = C.c_void_p(grad_out.data_ptr())
-        check(lib().spinmc_grad(self.ctx, C.c_void_p(stats.data_ptr()), int(n_rec), int(burn_in),
-                                gptr, C.c_void_p(means.data_ptr()), C.c_void_p(grads.data_ptr()),
-                                C.c_void_p(dth.data_ptr()) if dth is not None else None))
+        check(getattr(lib(), entry)(self.ctx, C.c_void_p(stats.data_ptr()), int(n_rec),
+                                    int(burn_in), gptr, C.c_void_p(means.data_ptr()),
+                                    C.c_void_p(grads.data_ptr()),
+                                    C.c_void_p(dth.data_ptr()) if dth is not None else None))
         return means, grads, dth
 
     # ------------------------------------------------------------- timing
