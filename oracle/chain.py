@@ -113,6 +113,8 @@ def lib():
     L.orc_philox_grid.restype = None
     L.orc_num_threads.argtypes = []
     L.orc_num_threads.restype = C.c_int
+    L.orc_set_num_threads.argtypes = [C.c_int]
+    L.orc_set_num_threads.restype = None
     _LIB = L
     return L
 
@@ -371,3 +373,8 @@ def potts_run_batch(states, q, J, h, beta, seed, rids, t0, n_sweeps, record_ever
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    """OpenMP threads of later oracle calls (1: every chain on one thread)."""
+    lib().orc_set_num_threads(int(n))

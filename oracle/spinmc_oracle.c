@@ -1,7 +1,7 @@
 /*
  * spinmc oracle -- TEST INFRASTRUCTURE ONLY.
  *
- * A plain, slow, single-threaded-per-chain CPU implementation of the
+ * A plain, slow CPU implementation of the
  * checkerboard Metropolis-Hastings chain for the Ising, q-state Potts and
  * Cellular Potts models of "A differentiable programming framework for spin
  * models" (Farias, Schultz, Mombach, Maziero).  Only the test-suite, the
@@ -99,6 +99,14 @@ static void draw(uint32_t a, uint32_t b, uint32_t rid, uint32_t tag, const uint3
 
 static int wrap(int i, int n) { return ((i % n) + n) % n; }
 
+/* Square-lattice Ising and Potts passes of lattices from 2^16 sites on split
+ * their rows over OpenMP threads when called outside a parallel region (the
+ * batch runners below are one; nested regions stay on one thread).  A pass
+ * updates only sites of one colour and reads only the other colour, so the
+ * split changes no bit; orc_set_num_threads(1) runs every chain on one
+ * thread.                                                                   */
+#define PASS_THREADS(Lx, Ly) ((int64_t)(Lx) * (Ly) >= 65536)
+
 /* Metropolis threshold: accept iff W < T, W uniform on [0, 2^32). */
 static uint64_t threshold_from_dE(double dE, double beta)
 {
@@ -174,8 +182,8 @@ int orc_ising_run(int Lx, int Ly, float Jx, float Jy, float h, double beta, uint
                   int32_t *stats)
 {
     uint64_t T[18];
-    uint32_t key[2], w[4], f[4];
-    int i, c, y, x, rec = 0;
+    uint32_t key[2];
+    int i, c, y, rec = 0;
     if (!check_shape(Lx, Ly) || n_sweeps < 0 || record_every < 0)
         return ORC_EINVAL;
     if (orc_ising_table(Jx, Jy, h, beta, T) != ORC_OK)
@@ -185,8 +193,12 @@ int orc_ising_run(int Lx, int Ly, float Jx, float Jy, float h, double beta, uint
         uint64_t t = t0 + (uint64_t)i;
         for (c = 0; c < 2; c++) {
             uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
+            /* the colour's sites are independent (see the header): rows of a
+             * large lattice may run on several threads, same result */
+#pragma omp parallel for schedule(static) if (PASS_THREADS(Lx, Ly))
             for (y = 0; y < Ly; y++)
-                for (x = 0; x < Lx; x++) {
+                for (int x = 0; x < Lx; x++) {
+                    uint32_t w[4], f[4];
                     if (((x + y) & 1) != c)
                         continue;
                     uint32_t k = (uint32_t)(y * (Lx / 2) + (x >> 1));
@@ -548,8 +560,8 @@ int orc_potts_run(int Lx, int Ly, int q, float J, float h, double beta, uint64_t
                   int32_t *stats)
 {
     uint64_t *T;
-    uint32_t key[2], w[4], f[4];
-    int i, c, y, x, rec = 0;
+    uint32_t key[2];
+    int i, c, y, rec = 0;
     if (!check_shape(Lx, Ly) || n_sweeps < 0 || record_every < 0 || q < 2 || q > 255)
         return ORC_EINVAL;
     T = (uint64_t *)malloc(sizeof(uint64_t) * 9 * (size_t)(2 * q - 1));
@@ -562,8 +574,10 @@ int orc_potts_run(int Lx, int Ly, int q, float J, float h, double beta, uint64_t
         uint64_t t = t0 + (uint64_t)i;
         for (c = 0; c < 2; c++) {
             uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
+#pragma omp parallel for schedule(static) if (PASS_THREADS(Lx, Ly))
             for (y = 0; y < Ly; y++)
-                for (x = 0; x < Lx; x++) {
+                for (int x = 0; x < Lx; x++) {
+                    uint32_t w[4], f[4];
                     if (((x + y) & 1) != c)
                         continue;
                     uint32_t k = (uint32_t)(y * (Lx / 2) + (x >> 1));
@@ -896,6 +910,16 @@ void orc_philox_grid(int n_blocks, uint32_t c1, const uint32_t *rids, int n_rid,
             const uint32_t ctr[4] = {(uint32_t)b, c1, rids[r], c3};
             orc_philox4x32_10(ctr, key, out + ((size_t)r * n_blocks + b) * 4);
         }
+}
+
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
 }
 
 int orc_num_threads(void)

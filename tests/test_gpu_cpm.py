@@ -114,6 +114,38 @@ def test_cell_sorting_config_full_size(S):
     smp.close()
 
 
+def test_cell_sorting_config_full_length(S):
+    """The cell-sorting workload at its full length, 2000 Monte Carlo steps:
+    the first 1000 unrecorded (cached graph replays, as the benchmark runs
+    them), the next 1000 recorded every 100 steps (direct launches).  Two
+    replicas' states and recorded statistics bit-exact with the oracle (the
+    two oracle chains run on two host threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+    ids, ctype, A, J, prm = synth.cpm_sorting()
+    reps = [_rep(ids[r], J, ctype, A, prm["lambda_area"], prm["temperature"], r)
+            for r in range(ids.shape[0])]
+    smp = S(reps, prm["seed"], init=False)
+    for r in range(len(reps)):
+        smp.set_state(r, ids[r])
+    half = prm["n_mcs"] // 2
+    smp.sweep(half)
+    st = smp.sweep(half, 100)
+    torch.cuda.synchronize()
+    sample = (2, 6)
+
+    def oracle(r):
+        lam, T, seed = prm["lambda_area"], prm["temperature"], prm["seed"]
+        mid, _, _ = orc.cpm_run(ids[r], J, ctype, A, lam, T, seed, r, 0, half)
+        return orc.cpm_run(mid, J, ctype, A, lam, T, seed, r, half, half, 100)
+
+    with ThreadPoolExecutor(len(sample)) as ex:
+        outs = list(ex.map(oracle, sample))
+    for r, (want, _, ost) in zip(sample, outs):
+        assert np.array_equal(smp.get_state(r), want), f"replica {r}"
+        assert np.array_equal(st[:, r].cpu().numpy(), ost), f"stats replica {r}"
+    smp.close()
+
+
 def test_paper_cell_sorting_setting(S):
     """The paper's own CPM setting (36 cells of area 25 in a touching 6 x 6
     aggregate, Table 2 adhesion, k_B T = 8, A = 25, lambda = 1) on 16

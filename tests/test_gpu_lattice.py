@@ -370,6 +370,33 @@ def test_batched_workload_full_size_sampled(S):
     smp.close()
 
 
+def test_batched_workload_full_length_sampled(S):
+    """The benchmark's batched workload as one step runs it: autotuned
+    schedule, 10^4 unrecorded sweeps replayed as graphs.  Sampled replicas
+    at the full length are bit-exact with the oracle: three Ising 256^2,
+    Potts lattices of 64^2, 128^2 and 256^2 (LDS-resident when the tuner
+    picks the hybrid schedule) and a Potts 512^2 (always streamed)."""
+    reps = synth.batched_ising_potts()
+    seed, n = 2, 10_000
+    smp = S(reps, seed, init=True)
+    smp.autotune(trial_sweeps=20)
+    st_sites, res_sites = smp.schedule_sites(by_model=True)
+    smp.sweep(n)
+    torch.cuda.synchronize()
+    first = {}
+    for i, r in enumerate(reps):
+        if r["model"] == 1:
+            first.setdefault(r["Lx"], i)
+    sample = [0, 517, 1023, first[64], first[128], first[256], first[512]]
+    print(f"full-length batched parity: schedule {smp.get_schedule()}, streamed sites "
+          f"{st_sites}, resident sites {res_sites}, sample {sample}", flush=True)
+    for i in sample:
+        r = reps[i]
+        want, _ = _run_oracle(r, _init_oracle(r, seed), seed, 0, n, 0)
+        assert np.array_equal(smp.get_state(i), want), f"replica {i} {r}"
+    smp.close()
+
+
 def test_ising_stream_8192_nontemporal_full_size_sampled(S):
     """The HBM-bound probe configuration (8192 Ising replicas of 256^2, 512
     MiB of lattices, streamed with nontemporal own-plane access, 128-row

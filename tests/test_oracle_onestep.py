@@ -370,3 +370,23 @@ def test_cpm5_neighbour_fallback_path(orc):
     want = predict_cpm5(orc, ids, J, ctype, A, 1.0, 50.0, hit, rid, t)
     got, _, _ = orc.cpm_run(ids, J, ctype, A, 1.0, 50.0, hit, rid, t, 1, nrange=2)
     assert np.array_equal(got, want)
+
+
+def test_pass_rows_on_threads_change_no_bit(orc):
+    """Large square lattices split a colour pass's rows over threads: the
+    chain (states and recorded statistics) equals the one-thread chain."""
+    n_thr = orc.num_threads()
+    try:
+        out = {}
+        for k in (1, max(n_thr, 4)):
+            orc.set_num_threads(k)
+            s = orc.ising_init(256, 256, 9, 3)
+            a = orc.ising_run(s, 0.9, 1.1, 0.02, 0.44, 9, 3, 5, 6, 2)
+            s = orc.potts_init(512, 128, 5, 9, 4)
+            b = orc.potts_run(s, 5, 1.0, 0.01, 1.2, 9, 4, 5, 6, 3)
+            out[k] = (a, b)
+        (a1, b1), (a2, b2) = out[1], out[max(n_thr, 4)]
+        for u, v in ((a1, a2), (b1, b2)):
+            assert np.array_equal(u[0], v[0]) and np.array_equal(u[1], v[1])
+    finally:
+        orc.set_num_threads(n_thr)
