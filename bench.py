@@ -48,7 +48,12 @@ VALU_PEAK = 256 * 4 * 16 * 2.4e9   # lane-instructions / s
 BYTES_PER_ATTEMPT = 3              # streamed pass: read own + other plane, write own plane
 COUNTERS = os.path.join(ROOT, "profiles", "counters_batched_ising_potts.json")
 KERNEL_NAMES = {"stream_ising": "k_stream_pass_ising", "stream_potts": "k_stream_pass_potts",
-                "resident": "k_resident"}
+                "resident": "k_resident", "persist_ising": "k_persist_ising",
+                "persist_potts": "k_persist_potts"}
+# kernels whose work is streamed colour passes (3 algorithmic HBM bytes per
+# attempt); the HBM-bound ones among them
+STREAMED = ("stream_ising", "stream_potts", "persist_ising", "persist_potts")
+HBM_BOUND = ("stream_ising", "persist_ising")
 
 
 def kernel_source_hash():
@@ -84,7 +89,7 @@ def roofline(kind, k, mode_name):
         traffic = int(round((ce["fetch_bytes_per_attempt"] + ce["write_bytes_per_attempt"]) * att))
     out = {"kernel": kernel, "launches": k["launches"], "avg_launch_us": round(avg_s * 1e6, 2),
            "attempts_per_launch": att, "attempts_per_ns": round(att / avg_s / 1e9, 1)}
-    if kind == "stream_ising":
+    if kind in HBM_BOUND:
         b = BYTES_PER_ATTEMPT * att
         ach = b / avg_s / 1e9
         out.update(bound="hbm", achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -100,9 +105,15 @@ def roofline(kind, k, mode_name):
         if ce and ce.get("valu_busy_pct") is not None:
             # hardware VALU-busy share of the kernel's time (rocprofv3 VALUBusy)
             out["valu_busy_pct_counter"] = ce["valu_busy_pct"]
-        if kind == "stream_potts":
-            # the same pass priced against HBM, for reference
-            out["hbm_GBs_algorithmic"] = round(BYTES_PER_ATTEMPT * att / avg_s / 1e9, 1)
+    if kind in STREAMED:
+        # every streamed kernel priced against HBM as well (3 algorithmic bytes
+        # per attempt), next to the fraction of its own bound
+        gbs = BYTES_PER_ATTEMPT * att / avg_s / 1e9
+        out["hbm_GBs_algorithmic"] = round(gbs, 1)
+        out["frac_hbm"] = round(gbs / HBM_PEAK_GBS, 4)
+        if traffic is not None:
+            out["hbm_GBs_measured"] = round(traffic / avg_s / 1e9, 1)
+            out["frac_hbm_measured"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
     return out
 
 
@@ -115,9 +126,10 @@ def profiled_kernels(smp, torch, sweeps):
     torch.cuda.synchronize()
     total = {"stream_ising": st["ising"] // 2 * 2 * sweeps,
              "stream_potts": st["potts"] // 2 * 2 * sweeps,
+             "persist_ising": st["ising"] * sweeps, "persist_potts": st["potts"] * sweeps,
              "resident": (re_["ising"] + re_["potts"]) * sweeps}
     kern = {}
-    for kind in ("stream_ising", "stream_potts", "resident"):
+    for kind in ("stream_ising", "stream_potts", "persist_ising", "persist_potts", "resident"):
         kms, nl = smp.profile_read(kind)
         if nl:
             kern[kind] = dict(ms=round(kms, 3), launches=nl, avg_us=round(kms / nl * 1e3, 2),
@@ -143,11 +155,22 @@ def ising_stream_probe(Sampler, torch, n_rep, sweeps, schedule=None):
     st_m, re_m = smp.schedule_sites(by_model=True)
     kern = profiled_kernels(smp, torch, sweeps)
     smp.close()
-    out = roofline("stream_ising", kern["stream_ising"], f"ising_probe_{n_rep}")
+    kind = "persist_ising" if "persist_ising" in kern else "stream_ising"
+    out = roofline(kind, kern[kind], f"ising_probe_{n_rep}")
     out["units"] = f"{n_rep} Ising 256x256 replicas, {sweeps} sweeps"
+    if kind == "persist_ising":
+        # one launch runs all passes of a chunk: per colour pass
+        out["us_per_pass"] = round(out["avg_launch_us"] * k_launch_passes(kern[kind], sweeps), 2)
     out["schedule"] = chosen
+    out["kernels"] = kern
     return out, dict(streamed_sites_by_model=st_m, resident_sites_by_model=re_m,
                      schedule=chosen)
+
+
+def k_launch_passes(k, sweeps):
+    """1 / colour passes per launch of a persistent kernel timed over
+    `sweeps` sweeps (2 passes per sweep)."""
+    return k["launches"] / (2.0 * sweeps)
 
 
 def _events(torch, stream):
@@ -599,13 +622,25 @@ def summarize_counters(dirs):
         st, re_ = cfg["streamed_sites_by_model"], cfg["resident_sites_by_model"]
         per_disp = {"k_stream_pass_ising": st["ising"] // 2, "k_stream_pass_potts": st["potts"] // 2}
         res_total = (re_["ising"] + re_["potts"]) * sw
+        # persistent kernels: the profiled sweeps' launches come last
+        kern = js.get("kernels") or js.get("ising_probe", {}).get("kernels") or {}
+        n_pers = {"k_persist_ising": (kern.get("persist_ising") or {}).get("launches", 0),
+                  "k_persist_potts": (kern.get("persist_potts") or {}).get("launches", 0)}
+        pers_total = {"k_persist_ising": st["ising"] * sw, "k_persist_potts": st["potts"] * sw}
         m = modes.setdefault(mode, {})
-        for kname in ("k_stream_pass_ising", "k_stream_pass_potts", "k_resident"):
+        for kname in ("k_stream_pass_ising", "k_stream_pass_potts", "k_persist_ising",
+                      "k_persist_potts", "k_resident"):
             vals = [float(r["Counter_Value"]) for r in rows if kname in r["Kernel_Name"]]
             if not vals:
                 continue
             if kname == "k_resident":
                 att, v = res_total, sum(vals)
+            elif kname in n_pers:
+                if not n_pers[kname]:
+                    continue
+                vals = vals[-n_pers[kname]:]
+                # per dispatch: the mean over the profiled launches
+                att, v = pers_total[kname] // len(vals), sum(vals) / len(vals)
             else:
                 # the profiled sweeps come last: 2 launches per sweep
                 vals = vals[-2 * sw:]

@@ -275,6 +275,18 @@ int spinmc_thresholds(const spinmc_ctx *ctx, int32_t replica, uint64_t *host_T, 
  *   caches, for lattice sets that do not fit the 256 MB last-level cache).
  *   0 decides per model: on when that model's streamed lattices exceed
  *   192 MiB.  The chain is the same either way.
+ * SPINMC_SCHED_PERSIST (or-ed with the NT setting; modes 2 and 3 of Ising
+ *   and Potts contexts, else SPINMC_E_UNSUPPORTED): unrecorded sweeps run
+ *   the streamed replicas of each model in ONE launch per chunk instead of
+ *   one per colour pass: an occupancy-sized grid of 256-thread workgroups,
+ *   each owning whole replicas or one row slab of a replica cut into slabs
+ *   (tile_rows rows, or 0 = slabs sized so that the slab workgroups fill the
+ *   chip once); a slab starts a pass once the slabs above and below it have
+ *   published the previous one (per-slab pass counters, no grid barrier).
+ *   Recorded sweeps keep one launch per pass.  A wait that runs past its
+ *   bound (which only a slab workgroup that never became resident could
+ *   cause) ends the launch early; the next spinmc_get_state then returns
+ *   SPINMC_E_DEVICE and poisons the context.
  * Invalid values return SPINMC_E_INVALID.  CPM contexts: mode 2 keeps every
  * step on streamed passes; any other mode lets the unrecorded steps of
  * lattices whose ids and tables fit 64 KiB of LDS run resident (one
@@ -282,7 +294,7 @@ int spinmc_thresholds(const spinmc_ctx *ctx, int32_t replica, uint64_t *host_T, 
  * the colouring (2 rows, or 6 with the 5x5 neighbourhood); wg_threads caps
  * the threads of a streamed pass at 256.  spinmc_autotune also tries the
  * best streaming schedule with NT forced on and off.                        */
-enum { SPINMC_SCHED_NT_ON = 1, SPINMC_SCHED_NT_OFF = 2 };
+enum { SPINMC_SCHED_NT_ON = 1, SPINMC_SCHED_NT_OFF = 2, SPINMC_SCHED_PERSIST = 4 };
 typedef struct spinmc_schedule {
     int32_t mode;
     int32_t tile_rows;
@@ -324,7 +336,9 @@ enum spinmc_kernel_kind {
     SPINMC_K_STREAM_POTTS = 4,  /* streamed Potts colour pass                 */
     SPINMC_K_TRI_PASS = 5,      /* triangular-lattice Ising colour pass       */
     SPINMC_K_HC_PASS = 6,       /* chain / cubic Ising colour pass            */
-    SPINMC_K_MSC_PASS = 7       /* multispin-coded Ising colour pass          */
+    SPINMC_K_MSC_PASS = 7,      /* multispin-coded Ising colour pass          */
+    SPINMC_K_PERSIST_ISING = 8, /* persistent streamed Ising chunk            */
+    SPINMC_K_PERSIST_POTTS = 9  /* persistent streamed Potts chunk            */
 };
 int spinmc_profile(spinmc_ctx *ctx, int32_t enable);
 int spinmc_profile_read(spinmc_ctx *ctx, int32_t kind, double *ms_total, int64_t *launches);

@@ -147,6 +147,20 @@ struct spinmc_ctx {
         size_t slot;
     };
     std::vector<ResGroup> res_groups;
+    // persistent streamed passes (schedule flag SPINMC_SCHED_PERSIST): one
+    // plan per model (Ising, Potts) over the streamed replicas
+    struct PersistPlan {
+        int n_wg = 0, n_slabs = 0, off0 = 0, slot_words = 0;
+        size_t lds = 0;
+    };
+    bool persist = false;
+    PersistPlan pplan[2];
+    PersistItem* d_pitems = nullptr;
+    int32_t* d_poff = nullptr;
+    uint32_t* d_pflags = nullptr;  // [0] abort word, [1 .. n_pflags] pass flags of the slabs
+    int n_pflags = 0;              // capacity in flags
+    int n_pflags_used = 0;
+    bool persist_used = false;
     // Cellular Potts
     int8_t* d_ctype = nullptr;
     int32_t* d_target = nullptr;
@@ -237,6 +251,12 @@ void free_all(spinmc_ctx* c) {
     hipFree(c->d_cov_part);
     c->d_cov_part = nullptr;
     c->cov_part_n = 0;
+    hipFree(c->d_pitems);
+    hipFree(c->d_poff);
+    hipFree(c->d_pflags);
+    c->d_pitems = nullptr;
+    c->d_poff = nullptr;
+    c->d_pflags = nullptr;
     c->d_ctype = nullptr;
     c->d_target = nullptr;
     c->d_area = nullptr;
@@ -441,6 +461,7 @@ size_t resident_lds(const spinmc_ctx* c, const HostRep& r) {
 }
 
 int enqueue_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
+int persist_check(spinmc_ctx* c);
 int cpm_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes);
 int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes);
 int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
@@ -710,6 +731,7 @@ int spinmc_get_state(spinmc_ctx* c, int32_t r, void* host, size_t bytes) {
     const HostRep& h = c->reps[r];
     const int Lx = h.dev.Lx, Ly = h.dev.Ly, W = h.dev.W;
     if (bytes != (size_t)Lx * Ly) return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
+    if (int rc = persist_check(c)) return rc;
     std::vector<uint8_t> planes((size_t)Lx * Ly);
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess)
@@ -773,8 +795,14 @@ int spinmc_set_schedule(spinmc_ctx* c, const spinmc_schedule* s) {
         return fail(SPINMC_E_INVALID, "set_schedule: tile_rows must be even and >= 0");
     if (s->wg_threads != 0 && s->wg_threads != 256 && s->wg_threads != 512)
         return fail(SPINMC_E_INVALID, "set_schedule: wg_threads must be 256 or 512");
-    if (s->flags != 0 && s->flags != SPINMC_SCHED_NT_ON && s->flags != SPINMC_SCHED_NT_OFF)
-        return fail(SPINMC_E_INVALID, "set_schedule: flags must be 0, NT_ON or NT_OFF");
+    if ((s->flags & ~(SPINMC_SCHED_NT_ON | SPINMC_SCHED_NT_OFF | SPINMC_SCHED_PERSIST)) != 0 ||
+        (s->flags & (SPINMC_SCHED_NT_ON | SPINMC_SCHED_NT_OFF)) ==
+            (SPINMC_SCHED_NT_ON | SPINMC_SCHED_NT_OFF))
+        return fail(SPINMC_E_INVALID,
+                    "set_schedule: flags must be 0, NT_ON or NT_OFF, optionally with PERSIST");
+    if ((s->flags & SPINMC_SCHED_PERSIST) && (c->cpm || c->tri || c->msc))
+        return fail(SPINMC_E_UNSUPPORTED,
+                    "set_schedule: persistent passes serve square-lattice Ising and Potts only");
     if (s->mode == 1 && !c->cpm)
         for (const HostRep& h : c->reps)
             if (!h.resident)
@@ -984,6 +1012,10 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
                 if (mode == 3 && !any_res_chunk) continue;
                 for (int tr : trs)
                     for (int th : {256, 512}) cand.push_back(spinmc_schedule{mode, tr, th, 0});
+                // persistent passes: slabs sized by the chip's occupancy, and
+                // slabs of four default tiles
+                cand.push_back(spinmc_schedule{mode, 0, 256, SPINMC_SCHED_PERSIST});
+                cand.push_back(spinmc_schedule{mode, min_def * 4, 256, SPINMC_SCHED_PERSIST});
             }
         }
     }
@@ -1080,7 +1112,7 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
         const size_t nb = cand.size();
         for (int f : {SPINMC_SCHED_NT_ON, SPINMC_SCHED_NT_OFF}) {
             spinmc_schedule sc = cand[best];
-            sc.flags = f;
+            sc.flags = (sc.flags & SPINMC_SCHED_PERSIST) | f;
             cand.push_back(sc);
         }
         for (size_t k = nb; k < cand.size() && e == hipSuccess; ++k) {
@@ -1093,6 +1125,11 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
     }
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
+    if (e == hipSuccess && persist_check(c) != SPINMC_OK) {
+        hipFree(lat_copy);
+        hipFree(area_copy);
+        return SPINMC_E_DEVICE;
+    }
     hipError_t er = restore();
     hipFree(lat_copy);
     hipFree(area_copy);
@@ -1134,6 +1171,200 @@ void drop_graphs(spinmc_ctx* c) {
     c->graphs.clear();
 }
 
+// Work items of the persistent streamed passes of one model.  Replicas are
+// cut into row slabs of about `target` sites (tile_rows rows when the
+// schedule names a height); a replica of one slab is a whole item, and whole
+// items are packed longest first into bins of about `target` sites (at most
+// items_cap per bin); each slab gets a workgroup of its own.  The slab
+// workgroups come first and, since they wait on one another, their number
+// stays within the occupancy of the chip (cap): otherwise the slabs grow.
+int plan_model(const spinmc_ctx* c, const std::vector<int>& reps, int tile_rows, int cap,
+               int items_cap, int flag0, std::vector<PersistItem>& items,
+               std::vector<int32_t>& wg_items, int* n_slabs_out) {
+    double total = 0;
+    int max_ly = 2;
+    for (int i : reps) {
+        total += (double)c->reps[i].dev.Lx * c->reps[i].dev.Ly;
+        max_ly = std::max(max_ly, c->reps[i].dev.Ly);
+    }
+    double target = std::max(1.0, total / std::max(cap, 1));
+    int rows_fixed = tile_rows;
+    for (int attempt = 0; attempt < 64; ++attempt) {
+        items.clear();
+        wg_items.clear();
+        std::vector<std::pair<double, int>> whole;  // (sites, replica)
+        int n_slabs = 0;
+        for (int i : reps) {
+            const RepDev& d = c->reps[i].dev;
+            int rows;
+            if (rows_fixed > 0) {
+                rows = std::min(rows_fixed, d.Ly);
+            } else {
+                const int S = std::max(1, (int)std::ceil((double)d.Lx * d.Ly / target - 1e-9));
+                rows = std::min(d.Ly, ((d.Ly + S - 1) / S + 1) & ~1);
+            }
+            const int S = (d.Ly + rows - 1) / rows;
+            if (S == 1) {
+                whole.push_back({(double)d.Lx * d.Ly, i});
+                continue;
+            }
+            const int f0 = flag0 + n_slabs;
+            for (int k = 0; k < S; ++k) {
+                const int y0 = k * rows;
+                PersistItem it{};
+                it.rep = i;
+                it.y0 = y0;
+                it.rows = std::min(rows, d.Ly - y0);
+                it.slab = f0 + k;
+                it.up = f0 + (k + S - 1) % S;
+                it.down = f0 + (k + 1) % S;
+                items.push_back(it);
+                wg_items.push_back(1);
+            }
+            n_slabs += S;
+        }
+        if (n_slabs > cap) {
+            // too many slab workgroups to be resident together: larger slabs
+            if (rows_fixed > 0) {
+                if (rows_fixed >= max_ly) return fail(SPINMC_E_UNSUPPORTED, "persistent plan");
+                rows_fixed = std::min(max_ly, rows_fixed * 2);
+            } else {
+                target *= 1.25;
+            }
+            continue;
+        }
+        if (!whole.empty()) {
+            std::sort(whole.begin(), whole.end(),
+                      [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+                          return a.first > b.first || (a.first == b.first && a.second < b.second);
+                      });
+            double wsum = 0;
+            for (const auto& w : whole) wsum += w.first;
+            const double bin_target = std::max(target, whole[0].first);
+            int n_bins = (int)std::ceil(wsum / bin_target - 1e-9);
+            n_bins = std::max(n_bins, ((int)whole.size() + items_cap - 1) / items_cap);
+            n_bins = std::max(1, std::min(n_bins, (int)whole.size()));
+            std::vector<double> load(n_bins, 0.0);
+            std::vector<std::vector<int>> bin(n_bins);
+            for (const auto& w : whole) {
+                int best = -1;
+                for (int b = 0; b < n_bins; ++b)
+                    if ((int)bin[b].size() < items_cap && (best < 0 || load[b] < load[best])) best = b;
+                bin[best].push_back(w.second);
+                load[best] += w.first;
+            }
+            for (int b = 0; b < n_bins; ++b) {
+                std::sort(bin[b].begin(), bin[b].end());
+                for (int i : bin[b]) {
+                    PersistItem it{};
+                    it.rep = i;
+                    it.y0 = 0;
+                    it.rows = c->reps[i].dev.Ly;
+                    it.slab = it.up = it.down = -1;
+                    items.push_back(it);
+                }
+                wg_items.push_back((int)bin[b].size());
+            }
+        }
+        *n_slabs_out = n_slabs;
+        return SPINMC_OK;
+    }
+    return fail(SPINMC_E_UNSUPPORTED, "persistent plan: no slab size fits the chip");
+}
+
+int plan_persist(spinmc_ctx* c, int mode) {
+    std::vector<int> by_model[2];
+    for (int i = 0; i < c->R; ++i) {
+        const HostRep& h = c->reps[i];
+        const bool resident = (mode == 1) || !h.chunk || (mode == 3 && h.resident);
+        if (!resident) by_model[h.dev.model == SPINMC_ISING ? 0 : 1].push_back(i);
+    }
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess ||
+        n_cu < 1)
+        return fail(SPINMC_E_DEVICE, "persistent plan: compute-unit count");
+    std::vector<PersistItem> all_items;
+    std::vector<int32_t> offs{0};
+    int n_flags = 0;
+    size_t lds_max = 0;
+    for (int m = 0; m < 2; ++m) {
+        auto& P = c->pplan[m];
+        P = spinmc_ctx::PersistPlan{};
+        if (by_model[m].empty()) continue;
+        P.slot_words = (int)align_up((size_t)2 * c->max_tab_n + 18, 4);
+        const int items_cap = std::max(1, std::min(16, 8192 / (4 * P.slot_words)));
+        P.lds = (size_t)items_cap * P.slot_words * 4;
+        const bool nt = m == 0 ? c->nt_ising : c->nt_potts;
+        int per_cu = 0;
+        if (persist_occupancy(m == 0 ? kModelIsing : kModelPotts, nt, P.lds, &per_cu) != hipSuccess ||
+            per_cu < 1) {
+            (void)hipGetLastError();
+            return fail(SPINMC_E_DEVICE, "persistent plan: occupancy query");
+        }
+        std::vector<PersistItem> items;
+        std::vector<int32_t> wg_items;
+        int rc = plan_model(c, by_model[m], c->sched.tile_rows, per_cu * n_cu, items_cap, n_flags,
+                            items, wg_items, &P.n_slabs);
+        if (rc) return rc;
+        P.n_wg = (int)wg_items.size();
+        P.off0 = (int)offs.size() - 1;
+        const int base = (int)all_items.size();
+        int acc = 0;
+        for (int k : wg_items) {
+            acc += k;
+            offs.push_back(base + acc);
+        }
+        all_items.insert(all_items.end(), items.begin(), items.end());
+        n_flags += P.n_slabs;
+        lds_max = std::max(lds_max, P.lds);
+    }
+    hipError_t e = hipSuccess;
+    hipFree(c->d_pitems);
+    hipFree(c->d_poff);
+    c->d_pitems = nullptr;
+    c->d_poff = nullptr;
+    e = hipMalloc((void**)&c->d_pitems, sizeof(PersistItem) * std::max<size_t>(all_items.size(), 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&c->d_poff, sizeof(int32_t) * offs.size());
+    if (e == hipSuccess && !all_items.empty())
+        e = hipMemcpy(c->d_pitems, all_items.data(), sizeof(PersistItem) * all_items.size(),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(c->d_poff, offs.data(), sizeof(int32_t) * offs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && (n_flags > c->n_pflags || !c->d_pflags)) {
+        // word 0 is the abort word, which survives re-planning; flags follow
+        uint32_t abort_word = 0;
+        if (c->d_pflags)
+            e = hipMemcpy(&abort_word, c->d_pflags, sizeof abort_word, hipMemcpyDeviceToHost);
+        hipFree(c->d_pflags);
+        c->d_pflags = nullptr;
+        if (e == hipSuccess) e = hipMalloc((void**)&c->d_pflags, sizeof(uint32_t) * (n_flags + 1));
+        if (e == hipSuccess) e = hipMemset(c->d_pflags, 0, sizeof(uint32_t) * (n_flags + 1));
+        if (e == hipSuccess)
+            e = hipMemcpy(c->d_pflags, &abort_word, sizeof abort_word, hipMemcpyHostToDevice);
+        if (e == hipSuccess) c->n_pflags = n_flags;
+    }
+    c->n_pflags_used = n_flags;
+    if (e == hipSuccess) e = persist_reserve_lds(std::max<size_t>(lds_max, 1024));
+    return check_dev(c, e, "persistent plan");
+}
+
+// A persistent launch whose wait ran past its bound leaves the state
+// undefined: report it (synchronising) and poison the context.
+int persist_check(spinmc_ctx* c) {
+    if (!c->persist_used || !c->d_pflags) return SPINMC_OK;
+    uint32_t abort_word = 0;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(&abort_word, c->d_pflags, sizeof abort_word, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return check_dev(c, e, "persistent check");
+    if (abort_word != 0) {
+        c->poisoned = true;
+        return fail(SPINMC_E_DEVICE, "persistent passes: a workgroup waited past its bound "
+                                     "(slab workgroups not resident together); state undefined");
+    }
+    return SPINMC_OK;
+}
+
 // (Re)build the tile table and the resident lists for a schedule.
 //   mode 1: every replica resident;
 //   mode 2: every replica with the chunk layout streamed (others resident);
@@ -1166,7 +1397,7 @@ int prepare(spinmc_ctx* c, int mode) {
             const bool resident = (mode == 1) || !h.chunk || (mode == 3 && h.resident);
             if (!resident) (h.dev.model == SPINMC_ISING ? bi : bp) += h.lat_bytes;
         }
-        const int f = c->sched.flags;
+        const int f = c->sched.flags & (SPINMC_SCHED_NT_ON | SPINMC_SCHED_NT_OFF);
         c->nt_ising = f == SPINMC_SCHED_NT_ON || (f == 0 && bi > kNtAutoBytes);
         c->nt_potts = f == SPINMC_SCHED_NT_ON || (f == 0 && bp > kNtAutoBytes);
     }
@@ -1229,11 +1460,15 @@ int prepare(spinmc_ctx* c, int mode) {
         for (const auto& g : c->res_groups) lds = std::max(lds, g.slot * g.rpb);
         e = resident_reserve_lds(lds);
     }
-    if (e == hipSuccess) {
-        c->prepared = true;
-        c->prepared_key = key;
+    if (e != hipSuccess) return check_dev(c, e, "prepare schedule");
+    c->persist = (c->sched.flags & SPINMC_SCHED_PERSIST) != 0 && mode != 1 && !tiles.empty();
+    if (c->persist) {
+        int rc = plan_persist(c, mode);
+        if (rc) return rc;
     }
-    return check_dev(c, e, "prepare schedule");
+    c->prepared = true;
+    c->prepared_key = key;
+    return SPINMC_OK;
 }
 
 SweepArgs sweep_args(spinmc_ctx* c, int n, int re, int32_t* stats) {
@@ -1321,6 +1556,29 @@ hipError_t enqueue_stream(spinmc_ctx* c, const SweepArgs& a, int i0, int n, int 
     return e;
 }
 
+// Persistent streamed passes for n unrecorded sweeps from sweep a.sweep_off
+// of the call on stream s: the slab flags cleared by a fill kernel (no memset
+// node in captured graphs), then one launch per model.
+hipError_t enqueue_persist(spinmc_ctx* c, SweepArgs a, int n, hipStream_t s) {
+    a.n_sweeps = n;
+    hipError_t e = hipSuccess;
+    uint32_t* abort_flag = c->d_pflags;
+    uint32_t* flags = c->d_pflags + 1;
+    if (c->n_pflags_used > 0) e = launch_fill_i32((int32_t*)flags, (size_t)c->n_pflags_used, 0, s);
+    for (int m = 0; m < 2 && e == hipSuccess; ++m) {
+        const auto& P = c->pplan[m];
+        if (P.n_wg == 0) continue;
+        const bool nt = m == 0 ? c->nt_ising : c->nt_potts;
+        e = timed(c, m == 0 ? SPINMC_K_PERSIST_ISING : SPINMC_K_PERSIST_POTTS, [&] {
+            return launch_persist(a, m == 0 ? kModelIsing : kModelPotts, c->d_pitems,
+                                  c->d_poff + P.off0, P.n_wg, flags, abort_flag, P.slot_words,
+                                  P.lds, nt, s);
+        }, s);
+    }
+    c->persist_used = true;
+    return e;
+}
+
 int ensure_side_streams(spinmc_ctx* c) {
     if (c->cap[0]) return SPINMC_OK;
     for (int k = 0; k < 1 + kSide; ++k) {
@@ -1349,7 +1607,8 @@ int chunk_graph(spinmc_ctx* c, int G, hipGraphExec_t* out) {
     const bool prof = c->prof;
     c->prof = false;
     if (e == hipSuccess) e = enqueue_resident(c, a, c->cap[0]);
-    if (e == hipSuccess && c->n_tiles > 0) e = enqueue_stream(c, a, 0, G, 0, c->cap[0]);
+    if (e == hipSuccess && c->n_tiles > 0)
+        e = c->persist ? enqueue_persist(c, a, G, c->cap[0]) : enqueue_stream(c, a, 0, G, 0, c->cap[0]);
     if (e == hipSuccess) e = join_resident(c, c->cap[0]);
     c->prof = prof;
     if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)G, c->cap[0]);
@@ -1402,7 +1661,9 @@ int enqueue_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
         aj.n_sweeps = m;
         aj.sweep_off = j0;
         e = enqueue_resident(c, aj, c->stream);
-        if (e == hipSuccess && c->n_tiles > 0) e = enqueue_stream(c, a, j0, m, re, c->stream);
+        if (e == hipSuccess && c->n_tiles > 0)
+            e = (c->persist && re == 0) ? enqueue_persist(c, aj, m, c->stream)
+                                        : enqueue_stream(c, a, j0, m, re, c->stream);
         if (e == hipSuccess) e = join_resident(c, c->stream);
     }
     if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)n, c->stream);

@@ -620,6 +620,121 @@ k_stream_pass_potts(SweepArgs a, int tile0, int n, int c, int sweep_off, int rec
     stream_pass_body<kModelPotts, NT>(a, tile0, n, c, sweep_off, rec_row, lthr, lthr9, lhist, lred);
 }
 
+// ------------------------------------------------- persistent streamed passes
+// One launch runs every colour pass of a chunk of unrecorded sweeps over the
+// streamed replicas of one model (the batched scheduler without a launch per
+// pass).  Workgroup g owns its items for the whole launch: whole replicas,
+// which no other workgroup touches, so the workgroup's barrier between
+// passes orders their passes, or one row slab of a replica cut into slabs
+// owned by different workgroups.  A slab's pass j (counted from 0 within the
+// launch) reads the other plane's rows just above and below it, which the
+// neighbouring slabs write in their pass j - 1, and writes rows that they
+// read in their pass j - 1; so it starts once both neighbours have published
+// pass j - 1 (flag >= j), and a slab never runs more than one pass ahead of
+// its neighbours.  Publishing: every lane waits for its stores, the
+// workgroup meets at a barrier, lane 0 stores flag = j + 1 with agent-scope
+// release (write-back of the XCD's L2).  Waiting: lane 0 polls the
+// neighbours' flags, then takes an agent-scope acquire (invalidation of its
+// L1 and L2) before the barrier that lets the other lanes read.  All slab
+// workgroups must be resident at once: the host keeps their number within
+// the occupancy of the whole chip and numbers them first, so that in-order
+// dispatch places them before any whole-replica workgroup.  A wait that
+// exceeds its bound (about two seconds) raises *abort, and every waiting
+// workgroup then leaves: a launch always ends.
+constexpr uint32_t kPersistSpinCap = 1u << 25;  // polls of ~128 cycles each
+
+// every store of this lane has completed (vmcnt 0; exp and lgkm counts
+// left at their maxima)
+__device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+__device__ int persist_wait(uint32_t* flags, int up, int down, uint32_t need, uint32_t* abort_flag) {
+    for (uint32_t spin = 0;; ++spin) {
+        const uint32_t u = __hip_atomic_load(&flags[up], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t d = __hip_atomic_load(&flags[down], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (u >= need && d >= need) break;
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return 0;
+        if (spin >= kPersistSpinCap) {
+            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return 1;
+}
+
+template <int MODEL, bool NT>
+__device__ __forceinline__ void persist_body(const SweepArgs& a, const PersistItem* items,
+                                             const int32_t* item_off, uint32_t* flags,
+                                             uint32_t* abort_flag, int slot_words, uint32_t* lds,
+                                             int* go) {
+    const int i0 = item_off[blockIdx.x], i1 = item_off[blockIdx.x + 1];
+    // threshold tables of the items' replicas (Potts: the h = 0 table of 9
+    // entries in the last 18 words of the slot)
+    for (int k = i0; k < i1; ++k) {
+        const RepDev R = a.reps[items[k].rep];
+        uint32_t* t = lds + (k - i0) * slot_words;
+        load_table(a.tab, R, t, threadIdx.x, blockDim.x);
+        if (MODEL == kModelPotts) load_table9(a.tab, R, t + slot_words - 18, threadIdx.x);
+    }
+    __syncthreads();
+    const uint64_t t0 = *a.t_base + (uint64_t)a.sweep_off;
+    for (int sw = 0; sw < a.n_sweeps; ++sw) {
+        for (int c = 0; c < 2; ++c) {
+            const uint32_t j = (uint32_t)(2 * sw + c);
+            const uint32_t p = (uint32_t)(2 * (t0 + (uint64_t)sw) + (uint64_t)c);
+            for (int k = i0; k < i1; ++k) {
+                const PersistItem it = items[k];
+                if (it.slab >= 0 && j > 0) {
+                    if (threadIdx.x == 0) *go = persist_wait(flags, it.up, it.down, j, abort_flag);
+                    __syncthreads();
+                    if (!*go) return;  // uniform: the whole workgroup leaves
+                }
+                const RepDev R = a.reps[it.rep];
+                uint32_t* tab = lds + (k - i0) * slot_words;
+                uint8_t* planes = a.lat + R.lat_off;
+                if (MODEL == kModelIsing) {
+                    IsingAcc ia{0, 0, 0};
+                    run_tile_ising<false, true, NT>(planes, R.W, R.Ly, it.y0, it.rows, c, p, R.rid,
+                                                    a.key0, a.key1, tab, ia, threadIdx.x,
+                                                    blockDim.x);
+                } else {
+                    PottsAcc pa{0, 0, 0};
+                    potts_tile<false, NT>(R, planes, it.y0, it.rows, c, p, a.key0, a.key1, tab,
+                                          tab + slot_words - 18, pa, nullptr, threadIdx.x,
+                                          blockDim.x);
+                }
+                if (it.slab >= 0) {
+                    wait_stores();
+                    __syncthreads();
+                    if (threadIdx.x == 0)
+                        __hip_atomic_store(&flags[it.slab], j + 1u, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+            __syncthreads();  // the workgroup's pass boundary
+        }
+    }
+}
+
+template <bool NT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 8)))
+k_persist_ising(SweepArgs a, const PersistItem* items, const int32_t* item_off, uint32_t* flags,
+                uint32_t* abort_flag, int slot_words) {
+    extern __shared__ uint32_t ptab[];
+    __shared__ int go;
+    persist_body<kModelIsing, NT>(a, items, item_off, flags, abort_flag, slot_words, ptab, &go);
+}
+
+template <bool NT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8)))
+k_persist_potts(SweepArgs a, const PersistItem* items, const int32_t* item_off, uint32_t* flags,
+                uint32_t* abort_flag, int slot_words) {
+    extern __shared__ uint32_t ptab[];
+    __shared__ int go;
+    persist_body<kModelPotts, NT>(a, items, item_off, flags, abort_flag, slot_words, ptab, &go);
+}
+
 // nmax of each Potts replica from its histogram; clears the histogram.
 __global__ void k_potts_hist_finalize(SweepArgs a, const int32_t* list, int n, int rec_row) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1003,6 +1118,52 @@ hipError_t launch_stream_pass(const SweepArgs& a, int model, int tile0, int n_ti
         else
             hipLaunchKernelGGL(k_stream_pass_potts<false>, g, b, lds_tab_bytes, s, a, tile0,
                                n_tiles, c, sweep_off, rec_row);
+    }
+    return hipGetLastError();
+}
+
+namespace {
+const void* persist_fn(int model, bool nt) {
+    if (model == kModelIsing)
+        return nt ? (const void*)k_persist_ising<true> : (const void*)k_persist_ising<false>;
+    return nt ? (const void*)k_persist_potts<true> : (const void*)k_persist_potts<false>;
+}
+}  // namespace
+
+hipError_t persist_reserve_lds(size_t lds_bytes) {
+    hipError_t e = hipSuccess;
+    for (int m = 0; m < 2 && e == hipSuccess; ++m)
+        for (int nt = 0; nt < 2 && e == hipSuccess; ++nt)
+            e = hipFuncSetAttribute(persist_fn(m, nt != 0),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    return e;
+}
+
+hipError_t persist_occupancy(int model, bool nt, size_t lds_bytes, int* per_cu) {
+    *per_cu = 0;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, persist_fn(model, nt), 256,
+                                                        lds_bytes);
+}
+
+hipError_t launch_persist(const SweepArgs& a, int model, const PersistItem* items,
+                          const int32_t* item_off, int n_wg, uint32_t* flags, uint32_t* abort_flag,
+                          int slot_words, size_t lds_bytes, bool nt, hipStream_t s) {
+    if (n_wg <= 0) return hipSuccess;
+    const dim3 g(n_wg), b(256);
+    if (model == kModelIsing) {
+        if (nt)
+            hipLaunchKernelGGL(k_persist_ising<true>, g, b, lds_bytes, s, a, items, item_off, flags,
+                               abort_flag, slot_words);
+        else
+            hipLaunchKernelGGL(k_persist_ising<false>, g, b, lds_bytes, s, a, items, item_off,
+                               flags, abort_flag, slot_words);
+    } else {
+        if (nt)
+            hipLaunchKernelGGL(k_persist_potts<true>, g, b, lds_bytes, s, a, items, item_off, flags,
+                               abort_flag, slot_words);
+        else
+            hipLaunchKernelGGL(k_persist_potts<false>, g, b, lds_bytes, s, a, items, item_off,
+                               flags, abort_flag, slot_words);
     }
     return hipGetLastError();
 }

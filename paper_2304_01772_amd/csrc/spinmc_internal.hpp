@@ -50,6 +50,16 @@ struct TileDev {
     int32_t rep, y0, rows, pad;
 };
 
+// One unit of a persistent workgroup's work (rows [y0, y0 + rows) of both
+// planes of replica rep): a whole replica (slab = -1) or one row slab of a
+// replica cut into slabs owned by different workgroups, with the pass flags
+// of this slab and of the slabs above and below it.
+struct PersistItem {
+    int32_t rep, y0, rows;
+    int32_t slab, up, down;
+    int32_t pad[2];
+};
+
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 bit
 // multiplies and xors; round r uses key + r * (0x9E3779B9, 0xBB67AE85).
 // Each round is two v_mad_u64_u32 and two three-input xors (v_bitop3_b32,
@@ -115,6 +125,20 @@ hipError_t launch_stream_pass(const SweepArgs& a, int model, int tile0, int n_ti
                               bool nt, hipStream_t s);
 hipError_t launch_potts_hist_finalize(const SweepArgs& a, const int32_t* list, int n, int rec_row,
                                       hipStream_t s);
+// Persistent streamed passes: all 2 n_sweeps colour passes of a chunk of
+// unrecorded sweeps over the streamed replicas of one model in one launch of
+// n_wg workgroups of 256 threads; workgroup g owns items[item_off[g] ..
+// item_off[g + 1]) (slab items alone in their workgroup, and all slab
+// workgroups first).  flags: one uint32 per slab, zero at launch; *abort is
+// set (and the launch leaves early) when a wait exceeds its bound.  Dynamic
+// LDS: items per workgroup x slot_words x 4 bytes (threshold tables).
+hipError_t launch_persist(const SweepArgs& a, int model, const PersistItem* items,
+                          const int32_t* item_off, int n_wg, uint32_t* flags, uint32_t* abort_flag,
+                          int slot_words, size_t lds_bytes, bool nt, hipStream_t s);
+// Workgroups of 256 threads of the persistent kernel of a model that one CU
+// holds at once with lds_bytes of dynamic LDS.
+hipError_t persist_occupancy(int model, bool nt, size_t lds_bytes, int* per_cu);
+hipError_t persist_reserve_lds(size_t lds_bytes);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);
 hipError_t launch_advance(uint64_t* t, uint64_t n, hipStream_t s);
 hipError_t launch_measure(const RepDev* reps, const int32_t* list, int n, int max_sites,

@@ -15,7 +15,7 @@ from ._lib import (CPM, ISING, ISING_HC, ISING_MSC, ISING_TRI, POTTS, ReplicaDes
 __all__ = ["Sampler", "ISING", "POTTS", "CPM", "MODES"]
 
 MODES = {"auto": 0, "resident": 1, "stream": 2, "hybrid": 3}
-NT_ON, NT_OFF = 1, 2  # spinmc_schedule.flags
+NT_ON, NT_OFF, PERSIST = 1, 2, 4  # spinmc_schedule.flags
 
 
 def _stream_handle(stream):
@@ -205,7 +205,7 @@ class Sampler:
 
     # ------------------------------------------------------------- timing
     KERNELS = {"stream_ising": 0, "resident": 1, "cpm_pass": 3, "stream_potts": 4, "tri_pass": 5,
-               "hc_pass": 6, "msc_pass": 7}
+               "hc_pass": 6, "msc_pass": 7, "persist_ising": 8, "persist_potts": 9}
 
     def profile(self, enable=True):
         check(lib().spinmc_profile(self.ctx, 1 if enable else 0))
@@ -218,10 +218,14 @@ class Sampler:
         return float(ms.value), int(n.value)
 
     # ---------------------------------------------------------- schedules
-    def set_schedule(self, mode="auto", tile_rows=0, wg_threads=0, nt=None):
+    def set_schedule(self, mode="auto", tile_rows=0, wg_threads=0, nt=None, persistent=False):
         """nt: None (size rule), True or False (nontemporal own-plane access
-        of the streamed passes forced on / off)."""
+        of the streamed passes forced on / off); persistent: unrecorded
+        sweeps run the streamed replicas in one persistent launch per chunk
+        (tile_rows = slab height, 0 = sized by the chip's occupancy)."""
         flags = 0 if nt is None else (NT_ON if nt else NT_OFF)
+        if persistent:
+            flags |= PERSIST
         s = Schedule(MODES[mode] if isinstance(mode, str) else int(mode), int(tile_rows),
                      int(wg_threads), flags)
         check(lib().spinmc_set_schedule(self.ctx, C.byref(s)))

@@ -318,6 +318,74 @@ def test_nontemporal_streaming_keeps_the_chain(S, nt):
                  schedule=dict(mode="stream", nt=nt), split=[5, 2])
 
 
+# Persistent streamed passes: whole replicas packed per workgroup and row
+# slabs that wait on their neighbours' pass flags, across graph-chunk
+# boundaries (50 sweeps), recorded calls in between (one launch per pass),
+# thin (2-row), ragged and two-slab replicas, and the hybrid schedule with
+# resident groups running beside them.
+def _pers_batch(kind):
+    rng = np.random.default_rng(5)
+    reps = []
+    if kind in ("ising", "mixed"):
+        for i, (lx, ly) in enumerate([(64, 64), (64, 64), (128, 64), (32, 128), (64, 130), (256, 32),
+                                      (512, 512)]):
+            reps.append(dict(model=0, Lx=lx, Ly=ly, Jx=_f32(rng.uniform(0.2, 0.6)),
+                             Jy=_f32(rng.uniform(0.2, 0.6)), h=_f32(rng.uniform(-0.1, 0.1)),
+                             beta=1.0, rid=i))
+    if kind in ("potts", "mixed"):
+        for i, (lx, ly, q) in enumerate([(64, 64, 3), (96, 48, 8), (32, 70, 5), (128, 128, 4),
+                                         (384, 384, 6)]):
+            reps.append(dict(model=1, Lx=lx, Ly=ly, q=q, Jx=1.0, Jy=1.0,
+                             h=0.0 if i % 2 == 0 else _f32(0.05), beta=float(rng.uniform(0.8, 1.3)),
+                             rid=100 + i))
+    return reps
+
+
+@pytest.mark.parametrize("kind,mode,tile_rows", [
+    ("ising", "stream", 0), ("ising", "stream", 6), ("ising", "stream", 64),
+    ("potts", "stream", 0), ("potts", "stream", 16), ("mixed", "hybrid", 0),
+    ("mixed", "stream", 32)])
+def test_persistent_schedule_keeps_the_chain(S, kind, mode, tile_rows):
+    reps = _pers_batch(kind)
+    _check_batch(S, reps, seed=41, n=None, re=0,
+                 schedule=dict(mode=mode, tile_rows=tile_rows, persistent=True),
+                 split=[120, 7, 53])
+    # recorded sweeps (one launch per pass) between persistent chunks
+    smp = S(reps, 42, init=True)
+    smp.set_schedule(mode=mode, tile_rows=tile_rows, persistent=True)
+    states = [_init_oracle(r, 42) for r in reps]
+    t0 = 0
+    for m, re in ((60, 0), (6, 3), (51, 0)):
+        st = smp.sweep(m, re)
+        torch.cuda.synchronize()
+        for i, r in enumerate(reps):
+            states[i], ost = _run_oracle(r, states[i], 42, t0, m, re)
+            assert np.array_equal(smp.get_state(i), states[i]), f"replica {i} after {t0 + m}"
+            if re:
+                assert np.array_equal(st[:, i].cpu().numpy(), ost)
+        t0 += m
+    smp.close()
+
+
+def test_persistent_schedule_direct_launches_and_profile(S):
+    """Profiled (direct, per-launch timed) persistent chunks in the hybrid
+    schedule: chunks of 50 sweeps with a sweep offset inside the call."""
+    reps = _pers_batch("mixed")
+    smp = S(reps, 43, init=True)
+    smp.set_schedule(mode="hybrid", persistent=True)
+    smp.profile(True)
+    smp.sweep(110)
+    torch.cuda.synchronize()
+    ms_i, n_i = smp.profile_read("persist_ising")
+    ms_p, n_p = smp.profile_read("persist_potts")
+    smp.profile(False)
+    assert n_i == 3 and n_p == 3 and ms_i > 0 and ms_p > 0
+    for i, r in enumerate(reps):
+        want, _ = _run_oracle(r, _init_oracle(r, 43), 43, 0, 110, 0)
+        assert np.array_equal(smp.get_state(i), want), f"replica {i}"
+    smp.close()
+
+
 def test_zero_sweeps_and_schedule_boundaries(S):
     """Degenerate calls and the LDS-residency boundary: zero sweeps change
     nothing; a lattice of exactly 128 KiB stays resident and one two rows
