@@ -12,8 +12,9 @@ Pipeline (all device work in libspinmc kernels; this module marshals):
      Surrogate-steered: gradient descent on the network's inputs
      (input gradients from spinmc_mlp_backward), then one Monte Carlo
      verification; if the verified error exceeds the tolerance, Monte Carlo
-     covariance-gradient steps continue from the surrogate's answer.
-     Monte-Carlo-only: the same covariance-gradient steps from the start.
+     bracketed Newton steps on the couplings (slopes from the covariance
+     estimator) continue from the surrogate's answer.  Monte-Carlo-only: the
+     same bracketed Newton iteration from the start.
 """
 import ctypes as C
 import time
@@ -199,17 +200,30 @@ def mc_absm_and_grad(beta, Jx, Jy, h, L=64, n_rep=16, burn=300, measure=700, see
 
 # --------------------------------------------------------- inverse problem
 def mc_only_solve(target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, max_iter=40, se_rel=None,
-                  n_max=None, **mc):
-    """Covariance-gradient (Newton along the gradient) steps on (Jx, Jy)
-    until the Monte Carlo <|m|> is within tol (relative) of the target.  With
-    se_rel, every evaluation adds replicas until its standard error is at
-    most se_rel * target (at most n_max), so that the tolerance is resolved."""
-    Jx, Jy = start
+                  n_max=None, j_lo=0.05, j_hi=3.0, max_step=0.5, **mc):
+    """Monte Carlo root finding of <|m|>(Jx, Jy) = target along the
+    coupling diagonal through the start, J(s) = start + s (1, 1): a
+    bracketed, damped Newton iteration on s whose slope is the covariance
+    estimator's d<|m|>/dJx + d<|m|>/dJy.  <|m|> rises with both couplings,
+    so every evaluation below the target raises the bracket's lower end and
+    every one above lowers its upper end (initially the couplings' range
+    [j_lo, j_hi]).  A Newton step is capped at max_step and, if it leaves the
+    bracket or the slope is not positive, replaced by the secant through the
+    bracket's measured ends (or its midpoint while an end is unmeasured).
+    Stops when the Monte Carlo <|m|> is within tol (relative) of the target.
+    With se_rel every evaluation adds replicas until its standard error is at
+    most se_rel * target (at most n_max replicas), so the tolerance is
+    resolved."""
+    x0, y0 = float(start[0]), float(start[1])
+    lo, hi = j_lo - min(x0, y0), j_hi - max(x0, y0)  # bracket on s
+    m_lo = m_hi = None
+    s_cur = 0.0
     t0 = time.perf_counter()
     hist = []
     se_abs = se_rel * target if se_rel else None
     n_used = 0
     for it in range(max_iter):
+        Jx, Jy = x0 + s_cur, y0 + s_cur
         m, se, gx, gy, n = mc_absm_and_grad(beta, Jx, Jy, h, rid0=100_000 * it, se_abs=se_abs,
                                             n_max=n_max, **mc)
         n_used += n
@@ -218,19 +232,31 @@ def mc_only_solve(target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, max_iter=
             return dict(Jx=Jx, Jy=Jy, absm=m, se=se, iters=it + 1, mc_calls=it + 1,
                         replicas=n_used, seconds=time.perf_counter() - t0, converged=True,
                         history=hist)
-        g2 = gx * gx + gy * gy
-        step = (target - m) / max(g2, 1e-12)
-        step = float(np.clip(step, -0.5 / max(np.sqrt(g2), 1e-12), 0.5 / max(np.sqrt(g2), 1e-12)))
-        Jx = float(np.clip(Jx + step * gx, 0.05, 3.0))
-        Jy = float(np.clip(Jy + step * gy, 0.05, 3.0))
-    return dict(Jx=Jx, Jy=Jy, absm=hist[-1][2], se=hist[-1][3], iters=max_iter, mc_calls=max_iter,
-                replicas=n_used, seconds=time.perf_counter() - t0, converged=False, history=hist)
+        if m < target:
+            lo, m_lo = s_cur, m
+        else:
+            hi, m_hi = s_cur, m
+        slope = gx + gy
+        s_new = None
+        if slope > 0:
+            s_new = s_cur + float(np.clip((target - m) / slope, -max_step, max_step))
+            if not lo < s_new < hi:
+                s_new = None
+        if s_new is None:
+            if m_lo is not None and m_hi is not None and m_hi > m_lo:
+                s_new = lo + (target - m_lo) * (hi - lo) / (m_hi - m_lo)
+            else:
+                s_new = 0.5 * (lo + hi)
+        s_cur = s_new
+    return dict(Jx=hist[-1][0], Jy=hist[-1][1], absm=hist[-1][2], se=hist[-1][3], iters=max_iter,
+                mc_calls=max_iter, replicas=n_used, seconds=time.perf_counter() - t0,
+                converged=False, history=hist)
 
 
 def surrogate_solve(net, target, beta=0.4, h=0.0, start=(1.0, 1.0), tol=0.01, steps=100, lr=0.01,
                     grid=64, max_iter=40, se_rel=None, n_max=None, **mc):
-    """The surrogate's answer, one Monte Carlo check, and Monte Carlo
-    covariance-gradient steps if the check fails.  The answer: the network
+    """The surrogate's answer, one Monte Carlo check, and the Monte Carlo
+    root finding of mc_only_solve from that answer if the check fails.  The answer: the network
     over a grid x grid set of couplings (one forward call) gives the points
     of the target level set, the one nearest to the start is refined by
     gradient descent on the network's inputs (input gradients from the
