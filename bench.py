@@ -29,7 +29,8 @@ known size (``--copy-calibration-mib``), taken from the committed counter
 summary when its kernel-source hash matches (else null).  ``--summarize-
 counters DIR...`` writes that summary from rocprofv3 counter runs of this
 script.  ``cpu_baseline`` times the oracle (plain C, OpenMP over replicas) on
-the host cores for all replicas of the workload over a few sweeps.
+the host cores for all replicas of the workload over a few sweeps, and on one
+thread for a strided subset of the replicas.
 """
 import argparse
 import csv
@@ -602,9 +603,9 @@ def spinopt_probe(torch, R=64, L=64, steps=200):
     return out
 
 
-def cpu_baseline(reps, seed, sweeps):
-    """The oracle on the host cores: every replica of the workload, a few
-    sweeps (a bounded sample of the same chain)."""
+def _oracle_rate(reps, seed, sweeps):
+    """Wall time of the oracle over `sweeps` sweeps of every replica in
+    reps (OpenMP over replicas); returns (attempts/ns, attempts, seconds)."""
     import numpy as np
     from oracle import chain as orc
     ising = [r for r in reps if r["model"] == 0]
@@ -612,17 +613,41 @@ def cpu_baseline(reps, seed, sweeps):
     si = [orc.ising_init(r["Lx"], r["Ly"], seed, r["rid"]) for r in ising]
     sp = [orc.potts_init(r["Lx"], r["Ly"], r["q"], seed, r["rid"]) for r in potts]
     t0 = time.perf_counter()
-    orc.ising_run_batch(si, [r["Jx"] for r in ising], [r["Jy"] for r in ising],
-                        [r["h"] for r in ising], [r["beta"] for r in ising], seed,
-                        np.array([r["rid"] for r in ising]), 0, sweeps)
-    orc.potts_run_batch(sp, [r["q"] for r in potts], [r["Jx"] for r in potts],
-                        [r["h"] for r in potts], [r["beta"] for r in potts], seed,
-                        np.array([r["rid"] for r in potts]), 0, sweeps)
+    if ising:
+        orc.ising_run_batch(si, [r["Jx"] for r in ising], [r["Jy"] for r in ising],
+                            [r["h"] for r in ising], [r["beta"] for r in ising], seed,
+                            np.array([r["rid"] for r in ising]), 0, sweeps)
+    if potts:
+        orc.potts_run_batch(sp, [r["q"] for r in potts], [r["Jx"] for r in potts],
+                            [r["h"] for r in potts], [r["beta"] for r in potts], seed,
+                            np.array([r["rid"] for r in potts]), 0, sweeps)
     dt = time.perf_counter() - t0
     att = sum(r["Lx"] * r["Ly"] for r in reps) * sweeps
-    return dict(value=att / dt / 1e9, unit="attempts/ns", cores=orc.num_threads(), kind="oracle",
+    return att / dt / 1e9, att, dt
+
+
+def cpu_baseline(reps, seed, sweeps, single_sweeps=20, single_stride=16):
+    """The oracle on the host cores: every replica of the workload for a
+    few sweeps on all threads (a bounded sample of the same chain), and
+    every single_stride-th replica on one thread."""
+    from oracle import chain as orc
+    n_thr = orc.num_threads()
+    v, att, dt = _oracle_rate(reps, seed, sweeps)
+    sub = reps[::single_stride]
+    orc.set_num_threads(1)
+    try:
+        v1, att1, dt1 = _oracle_rate(sub, seed, single_sweeps)
+    finally:
+        orc.set_num_threads(n_thr)
+    return dict(value=v, unit="attempts/ns", cores=n_thr, kind="oracle",
                 sample=f"all {len(reps)} replicas of the workload, {sweeps} sweeps "
-                       f"({att:.3g} attempts, {dt:.1f} s wall)")
+                       f"({att:.3g} attempts, {dt:.1f} s wall)",
+                single_thread=dict(value=v1, unit="attempts/ns", cores=1,
+                                   sample=f"every {single_stride}th replica ({len(sub)}: "
+                                          f"{sum(r['model'] == 0 for r in sub)} Ising, "
+                                          f"{sum(r['model'] == 1 for r in sub)} Potts), "
+                                          f"{single_sweeps} sweeps ({att1:.3g} attempts, "
+                                          f"{dt1:.1f} s wall)"))
 
 
 # ------------------------------------------------------------ counter summary

@@ -300,6 +300,9 @@ typedef struct spinmc_schedule {
     int32_t tile_rows;
     int32_t wg_threads;
     int32_t flags;
+    int32_t rpb;     /* replicas per resident workgroup: 0 = packing rule, else a
+                      * power of two up to 8 (capped by the LDS budget, by one
+                      * wave per replica and by the group's size)              */
 } spinmc_schedule;
 
 int spinmc_set_schedule(spinmc_ctx *ctx, const spinmc_schedule *s);
@@ -317,7 +320,17 @@ int spinmc_schedule_sites(const spinmc_ctx *ctx, int64_t streamed[3], int64_t re
  * measured attempts per ns of every candidate in host_rates (capacity cap,
  * may be NULL; *n_tried receives the count).  If chosen is not NULL and
  * chosen->mode > 0 on entry, only candidates of that mode are tried.
- * Synchronous.                                                              */
+ * The candidates: modes, tile heights, workgroup sizes, persistent passes,
+ * then nontemporal access forced on and off for the best streaming
+ * candidate and replicas per resident workgroup 1, 2, 4 and 8 for the best
+ * candidate with resident groups.  Choices are cached per process, keyed by
+ * the device's architecture and compute-unit count and the context's shape
+ * signature (model, Lx, Ly, q and the multiplicity of every shape, CPM
+ * neighbourhood range): a later call for an equal signature returns the
+ * cached schedule without trials (*n_tried = 0) unless chosen->mode is -1 on
+ * entry.  With the environment variable SPINMC_AUTOTUNE_CACHE naming a file,
+ * the cache is also read from and appended to that file (one line per
+ * choice).  Synchronous.                                                     */
 int spinmc_autotune(spinmc_ctx *ctx, int32_t trial_sweeps, spinmc_schedule *chosen,
                     double *host_rates, int32_t cap, int32_t *n_tried);
 

@@ -33,7 +33,7 @@ class ReplicaDesc(C.Structure):
 
 class Schedule(C.Structure):
     _fields_ = [("mode", C.c_int32), ("tile_rows", C.c_int32), ("wg_threads", C.c_int32),
-                ("flags", C.c_int32)]
+                ("flags", C.c_int32), ("rpb", C.c_int32)]
 
 
 class DmcParams(C.Structure):

@@ -8,7 +8,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
+#include <fstream>
 #include <map>
+#include <mutex>
+#include <sstream>
 #include <string>
 #include <tuple>
 
@@ -795,6 +799,8 @@ int spinmc_set_schedule(spinmc_ctx* c, const spinmc_schedule* s) {
         return fail(SPINMC_E_INVALID, "set_schedule: tile_rows must be even and >= 0");
     if (s->wg_threads != 0 && s->wg_threads != 256 && s->wg_threads != 512)
         return fail(SPINMC_E_INVALID, "set_schedule: wg_threads must be 256 or 512");
+    if (s->rpb != 0 && s->rpb != 1 && s->rpb != 2 && s->rpb != 4 && s->rpb != 8)
+        return fail(SPINMC_E_INVALID, "set_schedule: rpb must be 0, 1, 2, 4 or 8");
     if ((s->flags & ~(SPINMC_SCHED_NT_ON | SPINMC_SCHED_NT_OFF | SPINMC_SCHED_PERSIST)) != 0 ||
         (s->flags & (SPINMC_SCHED_NT_ON | SPINMC_SCHED_NT_OFF)) ==
             (SPINMC_SCHED_NT_ON | SPINMC_SCHED_NT_OFF))
@@ -976,6 +982,68 @@ int spinmc_profile_read(spinmc_ctx* c, int32_t kind, double* ms, int64_t* launch
     return SPINMC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Per-process cache of autotuned schedules (optionally mirrored in the file
+// named by SPINMC_AUTOTUNE_CACHE), keyed by device architecture, compute-unit
+// count and the context's shape signature.
+std::mutex g_tune_mu;
+std::map<std::string, spinmc_schedule> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const spinmc_ctx* c, int mode_filter) {
+    std::ostringstream k;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess)
+        k << prop.gcnArchName << "/" << prop.multiProcessorCount;
+    else
+        k << "?";
+    k << "|m" << mode_filter << "|";
+    std::map<std::tuple<int, int, int, int, int, int>, int> shapes;
+    for (const HostRep& h : c->reps)
+        ++shapes[std::make_tuple(h.d.model, h.d.Lx, h.d.Ly, h.d.model == SPINMC_ISING ? 2 : h.d.q,
+                                 h.d.Lz, c->cpm ? c->cpm_range : 0)];
+    for (const auto& kv : shapes)
+        k << std::get<0>(kv.first) << "," << std::get<1>(kv.first) << "," << std::get<2>(kv.first)
+          << "," << std::get<3>(kv.first) << "," << std::get<4>(kv.first) << ","
+          << std::get<5>(kv.first) << "*" << kv.second << ";";
+    return k.str();
+}
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("SPINMC_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        const size_t tab = line.find('\t');
+        if (tab == std::string::npos) continue;
+        std::istringstream v(line.substr(tab + 1));
+        spinmc_schedule sc{};
+        if (v >> sc.mode >> sc.tile_rows >> sc.wg_threads >> sc.flags >> sc.rpb)
+            g_tune[line.substr(0, tab)] = sc;
+    }
+}
+
+void tune_store(const std::string& key, const spinmc_schedule& sc) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_load_locked();
+    g_tune[key] = sc;
+    const char* path = std::getenv("SPINMC_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    std::ofstream f(path, std::ios::app);
+    if (f) f << key << '\t' << sc.mode << ' ' << sc.tile_rows << ' ' << sc.wg_threads << ' '
+             << sc.flags << ' ' << sc.rpb << '\n';
+}
+
+}  // namespace
+
+extern "C" {
+
 int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen, double* rates,
                     int32_t cap, int32_t* n_tried) {
     if (!c) return fail(SPINMC_E_INVALID, "autotune: null context");
@@ -985,6 +1053,21 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
         if (chosen) *chosen = c->sched;
         if (n_tried) *n_tried = 0;
         return SPINMC_OK;
+    }
+    const bool use_cache = !(chosen && chosen->mode == -1);
+    const int mode_filter = chosen && chosen->mode > 0 ? chosen->mode : 0;
+    const std::string key = tune_key(c, mode_filter);
+    if (use_cache) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            c->sched = it->second;
+            c->prepared = false;
+            if (chosen) *chosen = it->second;
+            if (n_tried) *n_tried = 0;
+            return SPINMC_OK;
+        }
     }
     // candidate schedules
     std::vector<spinmc_schedule> cand;
@@ -1019,10 +1102,10 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
             }
         }
     }
-    if (chosen && chosen->mode > 0) {
+    if (mode_filter > 0) {
         std::vector<spinmc_schedule> keep;
         for (const auto& k : cand)
-            if (k.mode == chosen->mode) keep.push_back(k);
+            if (k.mode == mode_filter) keep.push_back(k);
         cand.swap(keep);
     }
     if (cand.empty()) return fail(SPINMC_E_UNSUPPORTED, "autotune: no candidate schedule");
@@ -1123,6 +1206,27 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
             }
         }
     }
+    // replicas per resident workgroup for the best candidate with resident
+    // groups (the packing rule's choice is the baseline already measured)
+    if (e == hipSuccess && best >= 0 && !c->cpm && cand[best].mode != 2 && cand[best].rpb == 0) {
+        bool any_res = false;
+        for (const HostRep& h : c->reps) any_res = any_res || h.resident;
+        if (any_res) {
+            const size_t nb = cand.size();
+            for (int r : {1, 2, 4, 8}) {
+                spinmc_schedule sc = cand[best];
+                sc.rpb = r;
+                cand.push_back(sc);
+            }
+            for (size_t k = nb; k < cand.size() && e == hipSuccess; ++k) {
+                const double rate = trial(cand[k]);
+                if (e == hipSuccess && rate > best_rate) {
+                    best_rate = rate;
+                    best = (int)k;
+                }
+            }
+        }
+    }
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     if (e == hipSuccess && persist_check(c) != SPINMC_OK) {
@@ -1141,6 +1245,7 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
     }
     c->sched = cand[best];
     c->prepared = false;
+    tune_store(key, cand[best]);
     if (chosen) *chosen = cand[best];
     if (n_tried) *n_tried = tried;
     return SPINMC_OK;
@@ -1371,7 +1476,9 @@ int persist_check(spinmc_ctx* c) {
 //   mode 3: resident if it fits the LDS budget, streamed otherwise.
 int prepare(spinmc_ctx* c, int mode) {
     const int tr = c->sched.tile_rows;
-    const long key = ((long)mode << 40) | ((long)c->sched.flags << 32) | (long)(unsigned)tr;
+    const long key = ((long)mode << 56) | ((long)c->sched.rpb << 48) |
+                     ((long)(c->sched.wg_threads >> 8) << 40) | ((long)c->sched.flags << 32) |
+                     (long)(unsigned)tr;
     if (c->prepared && c->prepared_key == key) return SPINMC_OK;
     std::vector<int32_t> res_chunk, res_gen, spotts;
     std::vector<TileDev> tiles, ptiles;  // Ising tiles first, then Potts tiles
@@ -1427,10 +1534,19 @@ int prepare(spinmc_ctx* c, int mode) {
             const size_t slot = align_up((size_t)8 * c->max_tab_n, 16) + align_up(h.lat_bytes, 16);
             const int n = (int)kv.second.size();
             int P = 1;
-            while (P * 2 <= kMaxRpb && P * 2 * items <= tmax && (size_t)(P * 2) * slot <= kResidentLdsBudget &&
-                   n / (P * 2) >= 512)
-                P *= 2;
-            int threads = 64;
+            if (c->sched.rpb > 0) {
+                // forced packing: at most rpb, within the LDS budget, one
+                // wave per replica at least, and no more than the group holds
+                while (P * 2 <= c->sched.rpb && P * 2 <= kMaxRpb && P * 2 * 64 <= tmax &&
+                       (size_t)(P * 2) * slot <= kResidentLdsBudget && P * 2 <= n)
+                    P *= 2;
+            } else {
+                while (P * 2 <= kMaxRpb && P * 2 * items <= tmax &&
+                       (size_t)(P * 2) * slot <= kResidentLdsBudget && n / (P * 2) >= 512)
+                    P *= 2;
+            }
+            // forced packing gives every replica a wave at least (64 P <= tmax)
+            int threads = c->sched.rpb > 0 ? 64 * P : 64;
             while (threads < tmax && threads < P * items) threads *= 2;
             c->res_groups.push_back({(int)buf.size(), n, P, threads, std::get<0>(kv.first),
                                      pass == 0, slot});

@@ -218,22 +218,27 @@ class Sampler:
         return float(ms.value), int(n.value)
 
     # ---------------------------------------------------------- schedules
-    def set_schedule(self, mode="auto", tile_rows=0, wg_threads=0, nt=None, persistent=False):
+    def set_schedule(self, mode="auto", tile_rows=0, wg_threads=0, nt=None, persistent=False,
+                     rpb=0, flags=None):
         """nt: None (size rule), True or False (nontemporal own-plane access
         of the streamed passes forced on / off); persistent: unrecorded
         sweeps run the streamed replicas in one persistent launch per chunk
-        (tile_rows = slab height, 0 = sized by the chip's occupancy)."""
-        flags = 0 if nt is None else (NT_ON if nt else NT_OFF)
-        if persistent:
-            flags |= PERSIST
+        (tile_rows = slab height, 0 = sized by the chip's occupancy); rpb:
+        replicas per resident workgroup (0 = packing rule).  flags, if
+        given, replaces nt and persistent (the raw schedule flags)."""
+        if flags is None:
+            flags = 0 if nt is None else (NT_ON if nt else NT_OFF)
+            if persistent:
+                flags |= PERSIST
         s = Schedule(MODES[mode] if isinstance(mode, str) else int(mode), int(tile_rows),
-                     int(wg_threads), flags)
+                     int(wg_threads), int(flags), int(rpb))
         check(lib().spinmc_set_schedule(self.ctx, C.byref(s)))
 
     def get_schedule(self):
         s = Schedule()
         check(lib().spinmc_get_schedule(self.ctx, C.byref(s)))
-        return dict(mode=s.mode, tile_rows=s.tile_rows, wg_threads=s.wg_threads, flags=s.flags)
+        return dict(mode=s.mode, tile_rows=s.tile_rows, wg_threads=s.wg_threads, flags=s.flags,
+                    rpb=s.rpb)
 
     def schedule_sites(self, by_model=False):
         """(streamed, resident) sites per sweep under the current schedule;
@@ -246,13 +251,21 @@ class Sampler:
                     {n: int(b[i]) for i, n in enumerate(names)})
         return int(sum(a)), int(sum(b))
 
-    def autotune(self, trial_sweeps=20, mode=None):
+    def autotune(self, trial_sweeps=20, mode=None, cache=True):
         """Time candidate schedules (optionally of one mode) and keep the
-        fastest; returns (schedule dict, candidate rates in attempts/ns)."""
-        s = Schedule(MODES[mode] if isinstance(mode, str) else int(mode or 0), 0, 0, 0)
+        fastest; returns (schedule dict, candidate rates in attempts/ns).
+        With cache, a choice already made in this process (or in the file
+        named by SPINMC_AUTOTUNE_CACHE) for the same device and shapes is
+        reused without trials (the rates list is then empty)."""
+        m = MODES[mode] if isinstance(mode, str) else int(mode or 0)
+        if not cache:
+            if m > 0:
+                raise ValueError("autotune: cache=False tries every mode")
+            m = -1
+        s = Schedule(m, 0, 0, 0, 0)
         rates = (C.c_double * 64)()
         n = C.c_int32()
         check(lib().spinmc_autotune(self.ctx, int(trial_sweeps), C.byref(s), rates, 64,
                                     C.byref(n)))
-        return dict(mode=s.mode, tile_rows=s.tile_rows, wg_threads=s.wg_threads, flags=s.flags), \
-            [rates[i] for i in range(n.value)]
+        return dict(mode=s.mode, tile_rows=s.tile_rows, wg_threads=s.wg_threads, flags=s.flags,
+                    rpb=s.rpb), [rates[i] for i in range(n.value)]

@@ -386,6 +386,44 @@ def test_persistent_schedule_direct_launches_and_profile(S):
     smp.close()
 
 
+@pytest.mark.parametrize("rpb", [1, 2, 4, 8])
+def test_forced_resident_packing_keeps_the_chain(S, rpb):
+    """Replicas per resident workgroup forced by the schedule (the
+    autotuner's rpb candidates), for a group larger and one smaller than the
+    packing, recorded and not."""
+    rng = np.random.default_rng(rpb)
+    reps = [dict(model=0, Lx=64, Ly=32, Jx=_f32(rng.uniform(0.3, 0.6)), Jy=0.5, h=0.0,
+                 beta=1.0, rid=i) for i in range(11)]
+    reps += [dict(model=1, Lx=32, Ly=32, q=5, Jx=1.0, Jy=1.0, h=0.0, beta=1.2, rid=50 + i)
+             for i in range(3)]
+    _check_batch(S, reps, seed=7 + rpb, n=None, re=0,
+                 schedule=dict(mode="resident", rpb=rpb), split=[30, 4])
+    _check_batch(S, reps, seed=8 + rpb, n=6, re=2, schedule=dict(mode="resident", rpb=rpb))
+
+
+def test_autotune_cache_and_bypass(S):
+    """A second context with the same shapes reuses the first one's choice
+    without trials; cache=False times the candidates again; the chain is
+    unchanged either way."""
+    reps = [dict(model=0, Lx=64, Ly=64, Jx=1.0, Jy=1.0, h=0.0, beta=0.4, rid=i) for i in range(5)]
+    reps += [dict(model=1, Lx=160, Ly=96, q=3, Jx=1.0, Jy=1.0, h=0.0, beta=1.0, rid=9)]
+    a = S(reps, 3, init=True)
+    chosen_a, rates_a = a.autotune(trial_sweeps=2)
+    assert len(rates_a) > 0
+    b = S(reps, 3, init=True)
+    chosen_b, rates_b = b.autotune(trial_sweeps=2)
+    assert rates_b == [] and chosen_b == chosen_a and b.get_schedule() == chosen_a
+    chosen_c, rates_c = b.autotune(trial_sweeps=2, cache=False)
+    assert len(rates_c) > 0
+    b.sweep(12)
+    torch.cuda.synchronize()
+    for i, r in enumerate(reps):
+        want, _ = _run_oracle(r, _init_oracle(r, 3), 3, 0, 12, 0)
+        assert np.array_equal(b.get_state(i), want)
+    a.close()
+    b.close()
+
+
 def test_zero_sweeps_and_schedule_boundaries(S):
     """Degenerate calls and the LDS-residency boundary: zero sweeps change
     nothing; a lattice of exactly 128 KiB stays resident and one two rows
