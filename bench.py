@@ -193,6 +193,7 @@ def cpm_probe(Sampler, torch, mcs):
     smp = Sampler(reps, prm["seed"], init=False)
     for r in range(len(reps)):
         smp.set_state(r, ids[r])
+    chosen, _ = smp.autotune(trial_sweeps=10)
     smp.sweep(mcs)  # warm-up at the timed length (captures its graph)
     torch.cuda.synchronize()
     e0, e1 = _events(torch, smp.stream)
@@ -210,7 +211,7 @@ def cpm_probe(Sampler, torch, mcs):
     avg_s = kms / nl * 1e-3
     per_launch = sites // 4
     return {"config": f"{ids.shape[0]} CPM replicas of {ids.shape[1]}x{ids.shape[2]}, "
-                      f"1000 cells, {mcs} MCS (graph replays)",
+                      f"1000 cells, {mcs} MCS (graph replays)", "schedule": chosen,
             "attempts_per_ns": round(sites * mcs / (ms * 1e6), 2),
             "kernel": "k_cpm_pass", "bound": "alu", "launches": nl,
             "avg_launch_us": round(avg_s * 1e6, 2),

@@ -10,14 +10,49 @@
 // through the Algorithm-1 test.  Energies are integers in a fixed-point
 // scale S; the area term reads a snapshot of the cell areas taken at the
 // start of the pass (so the outcome does not depend on the order in which
-// the sites of one pass are visited), and accepted copies update the live
-// areas with integer atomics, which commute.
+// the sites of one pass are visited), and accepted copies update the areas
+// with integer atomics, which commute.  The streamed passes keep the
+// snapshot without a copy launch: pass P reads it as S[P & 1] + D[(P-1) % 3]
+// (the previous snapshot plus the previous pass's changes), adds its own
+// changes into D[P % 3], and on the side writes its snapshot to S[(P+1) & 1]
+// and clears D[(P+1) % 3] for pass P + 1 (buffers no other pass of the
+// launch touches).
 #include "cpm_internal.hpp"
 
 namespace spinmc {
 
 namespace {
 __device__ __forceinline__ int wrapc(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// The rotating snapshot / change buffers of pass P for cells at offset off.
+struct PassAreas {
+    const int32_t* s_rd;  // previous snapshot
+    const int32_t* d_rd;  // previous pass's changes
+    int32_t* d_wr;        // this pass's changes
+};
+__device__ __forceinline__ PassAreas pass_areas(const CpmArgs& a, uint64_t P, int off) {
+    const size_t n = (size_t)a.total_cells;
+    PassAreas r;
+    r.s_rd = a.sbuf + (size_t)(P & 1u) * n + off;
+    r.d_rd = a.dbuf + (size_t)((P + 2u) % 3u) * n + off;
+    r.d_wr = a.dbuf + (size_t)(P % 3u) * n + off;
+    return r;
+}
+
+// Side work of pass P, spread over the launch's threads: the snapshot it
+// reads goes to S[(P+1) & 1] and D[(P+1) % 3] is cleared.
+__device__ __forceinline__ void pass_rotate(const CpmArgs& a, uint64_t P) {
+    const size_t n = (size_t)a.total_cells;
+    const int32_t* s_rd = a.sbuf + (size_t)(P & 1u) * n;
+    const int32_t* d_rd = a.dbuf + (size_t)((P + 2u) % 3u) * n;
+    int32_t* s_wr = a.sbuf + (size_t)((P + 1u) & 1u) * n;
+    int32_t* d_clr = a.dbuf + (size_t)((P + 1u) % 3u) * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        s_wr[i] = s_rd[i] + d_rd[i];
+        d_clr[i] = 0;
+    }
+}
 }  // namespace
 
 __global__ void __launch_bounds__(256) k_cpm_pass(CpmArgs a, int c, int sweep_off) {
@@ -30,14 +65,17 @@ __global__ void __launch_bounds__(256) k_cpm_pass(CpmArgs a, int c, int sweep_of
         ljs[i] = a.js[R.js_off + i];
     __syncthreads();
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
-    const uint32_t p = (uint32_t)(4 * t + (uint64_t)c);
+    const uint64_t P = 4 * t + (uint64_t)c;
+    const uint32_t p = (uint32_t)P;
+    pass_rotate(a, P);
+    const PassAreas pa = pass_areas(a, P, R.cell_off);
     const int cy = c >> 1, cx = c & 1;
     const int Lx = R.Lx, Ly = R.Ly, Wc = Lx >> 1, nt = R.n_types;
     int32_t* ids = a.lat + R.lat_off;
     const int8_t* ty = a.ctype + R.cell_off;
     const int32_t* A = a.target + R.cell_off;
-    const int32_t* snap = a.snap + R.cell_off;
-    int32_t* area = a.area + R.cell_off;
+    int32_t* area = pa.d_wr;
+    const auto snap_of = [&](int i) -> int64_t { return (int64_t)pa.s_rd[i] + pa.d_rd[i]; };
     const int total = (T.rows >> 1) * Wc;
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
         const int r = it / Wc;
@@ -71,8 +109,8 @@ __global__ void __launch_bounds__(256) k_cpm_pass(CpmArgs a, int c, int sweep_of
             kadh -= (s != m) ? ljs[ts + tm] : 0;
         }
         int64_t karea = 0;
-        if (tg != 0) karea += 2 * ((int64_t)snap[tg] - (int64_t)A[tg]) + 1;
-        if (s != 0) karea += -2 * ((int64_t)snap[s] - (int64_t)A[s]) + 1;
+        if (tg != 0) karea += 2 * (snap_of(tg) - (int64_t)A[tg]) + 1;
+        if (s != 0) karea += -2 * (snap_of(s) - (int64_t)A[s]) + 1;
         const int64_t kk = (int64_t)kadh + R.LS * karea;
         bool acc;
         if (kk <= 0) {
@@ -196,15 +234,21 @@ __global__ void __launch_bounds__(256) k_cpm_pass5(CpmArgs a, int c, int sweep_o
         ljs[i] = a.js[R.js_off + i];
     __syncthreads();
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
-    const uint32_t p = (uint32_t)(9 * t + (uint64_t)c);
+    const uint64_t P = 9 * t + (uint64_t)c;
+    const uint32_t p = (uint32_t)P;
+    pass_rotate(a, P);
+    const PassAreas pa = pass_areas(a, P, R.cell_off);
     const int cy = c / 3, cx = c - 3 * cy;
     const int Lx = R.Lx, Wc = Lx / 3;
     int32_t* ids = a.lat + R.lat_off;
     const int8_t* ty = a.ctype + R.cell_off;
     const int32_t* A = a.target + R.cell_off;
-    const int32_t* snap = a.snap + R.cell_off;
-    int32_t* area = a.area + R.cell_off;
-    const auto sa = [=](int i) -> int64_t { return (int64_t)snap[i] - (int64_t)A[i]; };
+    int32_t* area = pa.d_wr;
+    const int32_t* s_rd = pa.s_rd;
+    const int32_t* d_rd = pa.d_rd;
+    const auto sa = [=](int i) -> int64_t {
+        return (int64_t)s_rd[i] + (int64_t)d_rd[i] - (int64_t)A[i];
+    };
     const int total = (T.rows / 3) * Wc;
     for (int it = threadIdx.x; it < total; it += blockDim.x) {
         const int r = it / Wc;
@@ -277,22 +321,17 @@ __device__ __forceinline__ int cpm_decide(const CpmArgs& a, const RepDev& R, con
 
 // ids / area: the replica's cell ids and live areas (global memory for the
 // streamed pass, LDS for the resident kernel); rows y0 .. y0 + rows - 1.
-template <int CX>
-__device__ __forceinline__ void cpm_quads(const CpmArgs& a, const RepDev& R, int32_t* ids,
-                                          int32_t* area, int y0, int rows, int cy, uint32_t p,
-                                          const uint32_t* qthr, const int32_t* lsa,
-                                          const int8_t* lty, const int32_t* ljs);
 
 // Per-cell tables of replica R into LDS for one pass of a tile: thresholds,
 // adhesion, types and pass-start area minus target.  Each thread issues up
 // to 4 items' loads before storing any, so that the tables arrive in one
 // round of global loads.
-__device__ __forceinline__ void cpm_stage(const CpmArgs& a, const RepDev& R, uint32_t* qthr,
-                                          int32_t* lsa, int8_t* lty, int32_t* ljs) {
+__device__ __forceinline__ void cpm_stage(const CpmArgs& a, const RepDev& R, const PassAreas& pa,
+                                          uint32_t* qthr, int32_t* lsa, int8_t* lty,
+                                          int32_t* ljs) {
     const int ncell = R.q + 1;
     const int8_t* ty = a.ctype + R.cell_off;
     const int32_t* A = a.target + R.cell_off;
-    const int32_t* snap = a.snap + R.cell_off;
     const int nthr = blockDim.x;
     const int ntab = 2 * R.tab_n;
     for (int i0 = threadIdx.x; i0 < ntab; i0 += 4 * nthr) {
@@ -314,7 +353,7 @@ __device__ __forceinline__ void cpm_stage(const CpmArgs& a, const RepDev& R, uin
         for (int u = 0; u < 4; ++u) {
             const int i = i0 + u * nthr;
             const bool in = i < ncell;
-            sv[u] = in ? snap[i] : 0;
+            sv[u] = in ? pa.s_rd[i] + pa.d_rd[i] : 0;
             av[u] = in ? A[i] : 0;
             tv[u] = in ? ty[i] : (int8_t)0;
         }
@@ -329,27 +368,6 @@ __device__ __forceinline__ void cpm_stage(const CpmArgs& a, const RepDev& R, uin
     }
 }
 
-__global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int sweep_off,
-                                                       int tab_lds_bytes, int cell_cap) {
-    // dynamic LDS: [T hi | T lo] (tab_lds_bytes) | snap - A (int32) | type (int8)
-    extern __shared__ __align__(16) uint8_t dyn[];
-    uint32_t* qthr = reinterpret_cast<uint32_t*>(dyn);
-    int32_t* lsa = reinterpret_cast<int32_t*>(dyn + tab_lds_bytes);
-    int8_t* lty = reinterpret_cast<int8_t*>(lsa + cell_cap);
-    __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
-    const TileDev T = a.tiles[blockIdx.x];
-    const RepDev R = a.reps[T.rep];
-    cpm_stage(a, R, qthr, lsa, lty, ljs);
-    __syncthreads();
-    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
-    const uint32_t p = (uint32_t)(4 * t + (uint64_t)c);
-    int32_t* ids = a.lat + R.lat_off;
-    int32_t* area = a.area + R.cell_off;
-    if (c & 1)
-        cpm_quads<1>(a, R, ids, area, T.y0, T.rows, c >> 1, p, qthr, lsa, lty, ljs);
-    else
-        cpm_quads<0>(a, R, ids, area, T.y0, T.rows, c >> 1, p, qthr, lsa, lty, ljs);
-}
 
 // The copy attempt of site (y, x) of colour pass p, word u of Philox block kq
 // (the quad of four consecutive same-colour sites of the row): its Moore
@@ -397,57 +415,115 @@ __device__ __forceinline__ void cpm_sites(const CpmArgs& a, const RepDev& R, int
     }
 }
 
+// One quad's inputs: its 3 x 9 id window (rows y - 1, y, y + 1; the halo
+// column on the side of colour CX) and its Philox block.
+struct QuadIn {
+    int win[3][9];
+    uint32_t w[4];
+    int y, x0;
+    uint32_t kq;
+};
+
+// Loads of quad `it` of the colour-(2 cy + CX) sites of rows y0 ..: six
+// 16-byte loads, three halo loads and the Philox block (k >> 2 of the four
+// sites); nothing here reads the staged tables.
 template <int CX>
-__device__ __forceinline__ void cpm_quads(const CpmArgs& a, const RepDev& R, int32_t* ids,
-                                          int32_t* area, int y0, int rows, int cy, uint32_t p,
-                                          const uint32_t* qthr, const int32_t* lsa,
-                                          const int8_t* lty, const int32_t* ljs) {
-    const int Lx = R.Lx, Ly = R.Ly, Wc = Lx >> 1, Q = Wc >> 2;
-    const int total = (rows >> 1) * Q;
-    for (int it = threadIdx.x; it < total; it += blockDim.x) {
-        const int r = it / Q;
-        const int qi = it - r * Q;
-        const int y = y0 + 2 * r + cy;
-        const int x0 = 8 * qi;
-        const uint32_t kq = (uint32_t)((y >> 1) * Q + qi);  // k >> 2 of the four sites
-        const int yr[3] = {wrapc(y - 1, Ly), y, wrapc(y + 1, Ly)};
-        const int xh = CX == 0 ? wrapc(x0 - 1, Lx) : wrapc(x0 + 8, Lx);
-        int win[3][9];
+__device__ __forceinline__ void quad_load(const CpmArgs& a, const RepDev& R, const int32_t* ids,
+                                          int y0, int cy, uint32_t p, int it, QuadIn& q) {
+    const int Lx = R.Lx, Ly = R.Ly, Q = Lx >> 3;
+    const int r = it / Q;
+    const int qi = it - r * Q;
+    q.y = y0 + 2 * r + cy;
+    q.x0 = 8 * qi;
+    q.kq = (uint32_t)((q.y >> 1) * Q + qi);
+    const int yr[3] = {wrapc(q.y - 1, Ly), q.y, wrapc(q.y + 1, Ly)};
+    const int xh = CX == 0 ? wrapc(q.x0 - 1, Lx) : wrapc(q.x0 + 8, Lx);
 #pragma unroll
-        for (int rr = 0; rr < 3; ++rr) {
-            const int32_t* row = ids + (size_t)yr[rr] * Lx;
-            const int4 u = *reinterpret_cast<const int4*>(row + x0);
-            const int4 v = *reinterpret_cast<const int4*>(row + x0 + 4);
-            const int h = row[xh];
-            constexpr int o = CX == 0 ? 1 : 0;
-            win[rr][o + 0] = u.x;
-            win[rr][o + 1] = u.y;
-            win[rr][o + 2] = u.z;
-            win[rr][o + 3] = u.w;
-            win[rr][o + 4] = v.x;
-            win[rr][o + 5] = v.y;
-            win[rr][o + 6] = v.z;
-            win[rr][o + 7] = v.w;
-            win[rr][CX == 0 ? 0 : 8] = h;
-        }
-        uint32_t w[4];
-        philox4x32_10(kq, p, R.rid, kTagMain, a.key0, a.key1, w);
+    for (int rr = 0; rr < 3; ++rr) {
+        const int32_t* row = ids + (size_t)yr[rr] * Lx;
+        const int4 u = *reinterpret_cast<const int4*>(row + q.x0);
+        const int4 v = *reinterpret_cast<const int4*>(row + q.x0 + 4);
+        const int h = row[xh];
+        constexpr int o = CX == 0 ? 1 : 0;
+        q.win[rr][o + 0] = u.x;
+        q.win[rr][o + 1] = u.y;
+        q.win[rr][o + 2] = u.z;
+        q.win[rr][o + 3] = u.w;
+        q.win[rr][o + 4] = v.x;
+        q.win[rr][o + 5] = v.y;
+        q.win[rr][o + 6] = v.z;
+        q.win[rr][o + 7] = v.w;
+        q.win[rr][CX == 0 ? 0 : 8] = h;
+    }
+    philox4x32_10(q.kq, p, R.rid, kTagMain, a.key0, a.key1, q.w);
+}
+
+// The quad's four attempts (site 2u + CX of the quad is word u) and, on
+// acceptance, the id and area updates.
+template <int CX>
+__device__ __forceinline__ void quad_decide(const CpmArgs& a, const RepDev& R, int32_t* ids,
+                                            int32_t* area, uint32_t p, const QuadIn& q,
+                                            const uint32_t* qthr, const int32_t* lsa,
+                                            const int8_t* lty, const int32_t* ljs) {
+    const int Lx = R.Lx;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            // Moore order (dy, dx): (-1,-1) (-1,0) (-1,1) (0,-1) (0,1) (1,-1) (1,0) (1,1)
-            const int nb[8] = {win[0][2 * u], win[0][2 * u + 1], win[0][2 * u + 2],
-                               win[1][2 * u], win[1][2 * u + 2],
-                               win[2][2 * u], win[2][2 * u + 1], win[2][2 * u + 2]};
-            const int s = win[1][2 * u + 1];
-            const int tg = cpm_decide(a, R, nb, s, w[u], 4u * kq + (uint32_t)u, p, qthr, lsa, lty,
-                                      ljs);
-            if (tg >= 0) {
-                ids[(size_t)y * Lx + x0 + 2 * u + CX] = tg;
-                atomicAdd(&area[tg], 1);
-                atomicAdd(&area[s], -1);
-            }
+    for (int u = 0; u < 4; ++u) {
+        // Moore order (dy, dx): (-1,-1) (-1,0) (-1,1) (0,-1) (0,1) (1,-1) (1,0) (1,1)
+        const int nb[8] = {q.win[0][2 * u], q.win[0][2 * u + 1], q.win[0][2 * u + 2],
+                           q.win[1][2 * u], q.win[1][2 * u + 2],
+                           q.win[2][2 * u], q.win[2][2 * u + 1], q.win[2][2 * u + 2]};
+        const int s = q.win[1][2 * u + 1];
+        const int tg = cpm_decide(a, R, nb, s, q.w[u], 4u * q.kq + (uint32_t)u, p, qthr, lsa, lty,
+                                  ljs);
+        if (tg >= 0) {
+            ids[(size_t)q.y * Lx + q.x0 + 2 * u + CX] = tg;
+            atomicAdd(&area[tg], 1);
+            atomicAdd(&area[s], -1);
         }
     }
+}
+
+// A lane's first quad is loaded (window and Philox block) before the
+// per-cell tables are staged, so that the two rounds of global loads
+// overlap; the other quads of the lane follow the table barrier.
+template <int CX>
+__device__ __forceinline__ void quad_pass(const CpmArgs& a, int c, int sweep_off,
+                                          uint32_t* qthr, int32_t* lsa, int8_t* lty,
+                                          int32_t* ljs) {
+    const TileDev T = a.tiles[blockIdx.x];
+    const RepDev R = a.reps[T.rep];
+    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
+    const uint64_t P = 4 * t + (uint64_t)c;
+    const uint32_t p = (uint32_t)P;
+    const PassAreas pa = pass_areas(a, P, R.cell_off);
+    int32_t* ids = a.lat + R.lat_off;
+    const int cy = c >> 1;
+    const int total = (T.rows >> 1) * (R.Lx >> 3);
+    const int it0 = (int)threadIdx.x;
+    QuadIn q;
+    if (it0 < total) quad_load<CX>(a, R, ids, T.y0, cy, p, it0, q);
+    cpm_stage(a, R, pa, qthr, lsa, lty, ljs);
+    pass_rotate(a, P);
+    __syncthreads();
+    if (it0 < total) quad_decide<CX>(a, R, ids, pa.d_wr, p, q, qthr, lsa, lty, ljs);
+    for (int it = it0 + (int)blockDim.x; it < total; it += blockDim.x) {
+        quad_load<CX>(a, R, ids, T.y0, cy, p, it, q);
+        quad_decide<CX>(a, R, ids, pa.d_wr, p, q, qthr, lsa, lty, ljs);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int sweep_off,
+                                                       int tab_lds_bytes, int cell_cap) {
+    // dynamic LDS: [T hi | T lo] (tab_lds_bytes) | snap - A (int32) | type (int8)
+    extern __shared__ __align__(16) uint8_t dyn[];
+    uint32_t* qthr = reinterpret_cast<uint32_t*>(dyn);
+    int32_t* lsa = reinterpret_cast<int32_t*>(dyn + tab_lds_bytes);
+    int8_t* lty = reinterpret_cast<int8_t*>(lsa + cell_cap);
+    __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
+    if (c & 1)
+        quad_pass<1>(a, c, sweep_off, qthr, lsa, lty, ljs);
+    else
+        quad_pass<0>(a, c, sweep_off, qthr, lsa, lty, ljs);
 }
 
 // All n_steps unrecorded Monte Carlo steps of every replica in one launch:
@@ -544,6 +620,34 @@ hipError_t launch_cpm_resident(const CpmArgs& a, int n_steps, int tab_lds_bytes,
 __global__ void k_cpm_copy(const int32_t* src, int32_t* dst, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
         dst[i] = src[i];
+}
+
+__device__ __forceinline__ uint64_t first_pass(const CpmArgs& a, int sweep_off) {
+    return (uint64_t)(a.range == 2 ? 9 : 4) * (*a.t_base + (uint64_t)sweep_off);
+}
+
+__global__ void k_cpm_pass_init(CpmArgs a, int sweep_off) {
+    const uint64_t P = first_pass(a, sweep_off);
+    const size_t n = (size_t)a.total_cells;
+    int32_t* s_wr = a.sbuf + (size_t)(P & 1u) * n;
+    int32_t* d0 = a.dbuf + (size_t)((P + 2u) % 3u) * n;
+    int32_t* d1 = a.dbuf + (size_t)(P % 3u) * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        s_wr[i] = a.area[i];
+        d0[i] = 0;
+        d1[i] = 0;
+    }
+}
+
+__global__ void k_cpm_pass_final(CpmArgs a, int sweep_off) {
+    const uint64_t P = first_pass(a, sweep_off);
+    const size_t n = (size_t)a.total_cells;
+    const int32_t* s_rd = a.sbuf + (size_t)(P & 1u) * n;
+    const int32_t* d_rd = a.dbuf + (size_t)((P + 2u) % 3u) * n;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x)
+        a.area[i] = s_rd[i] + d_rd[i];
 }
 
 // Areas from the lattice (after set_state): per tile, atomics into area
@@ -671,6 +775,20 @@ hipError_t launch_cpm_snapshot(const CpmArgs& a, int total_cells, hipStream_t s)
     int blocks = (total_cells + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_cpm_copy, dim3(blocks), dim3(256), 0, s, a.area, a.snap, total_cells);
+    return hipGetLastError();
+}
+
+hipError_t launch_cpm_pass_init(const CpmArgs& a, int sweep_off, hipStream_t s) {
+    int blocks = (a.total_cells + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_cpm_pass_init, dim3(blocks), dim3(256), 0, s, a, sweep_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_cpm_pass_final(const CpmArgs& a, int sweep_off, hipStream_t s) {
+    int blocks = (a.total_cells + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_cpm_pass_final, dim3(blocks), dim3(256), 0, s, a, sweep_off);
     return hipGetLastError();
 }
 

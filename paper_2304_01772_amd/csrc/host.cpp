@@ -170,6 +170,8 @@ struct spinmc_ctx {
     int32_t* d_target = nullptr;
     int32_t* d_area = nullptr;
     int32_t* d_snap = nullptr;
+    int32_t* d_sbuf = nullptr;  // [2][total_cells] pass snapshots of the streamed passes
+    int32_t* d_dbuf = nullptr;  // [3][total_cells] pass area changes
     int32_t* d_js = nullptr;
     int total_cells = 0;
     // CPM passes with four sites per lane and LDS cell tables (every Lx a
@@ -247,6 +249,10 @@ void free_all(spinmc_ctx* c) {
     hipFree(c->d_target);
     hipFree(c->d_area);
     hipFree(c->d_snap);
+    hipFree(c->d_sbuf);
+    hipFree(c->d_dbuf);
+    c->d_sbuf = nullptr;
+    c->d_dbuf = nullptr;
     hipFree(c->d_js);
     hipFree(c->d_tab64);
     c->d_tab64 = nullptr;
@@ -1801,6 +1807,9 @@ CpmArgs cpm_args(spinmc_ctx* c, int32_t* stats) {
     a.target = c->d_target;
     a.area = c->d_area;
     a.snap = c->d_snap;
+    a.sbuf = c->d_sbuf;
+    a.dbuf = c->d_dbuf;
+    a.total_cells = c->total_cells;
     a.js = c->d_js;
     a.t_base = c->d_t;
     a.stats = stats;
@@ -1931,6 +1940,8 @@ int create_cpm(const spinmc_replica_desc* d, int n, uint64_t seed, void* stream,
         (e = A((void**)&c->d_target, sizeof(int32_t) * target.size())) ||
         (e = A((void**)&c->d_area, sizeof(int32_t) * cell_off)) ||
         (e = A((void**)&c->d_snap, sizeof(int32_t) * cell_off)) ||
+        (e = A((void**)&c->d_sbuf, sizeof(int32_t) * 2 * cell_off)) ||
+        (e = A((void**)&c->d_dbuf, sizeof(int32_t) * 3 * cell_off)) ||
         (e = A((void**)&c->d_js, sizeof(int32_t) * js.size()))) {
         free_all(c);
         delete c;
@@ -2009,8 +2020,6 @@ int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
 hipError_t cpm_enqueue_pass(spinmc_ctx* c, const CpmArgs& a, int i, int col, hipStream_t s) {
     const size_t tab_bytes = align_up((size_t)8 * std::max(c->max_tab_n, 1), 16);
     const int threads = c->sched.wg_threads > 0 ? std::min(c->sched.wg_threads, 256) : 256;
-    hipError_t e = launch_cpm_snapshot(a, c->total_cells, s);
-    if (e != hipSuccess) return e;
     return timed(c, SPINMC_K_CPM_PASS, [&] {
         if (c->cpm_range == 2)
             return launch_cpm_pass5(a, c->n_tiles, col, i, threads, tab_bytes, s);
@@ -2021,9 +2030,9 @@ hipError_t cpm_enqueue_pass(spinmc_ctx* c, const CpmArgs& a, int i, int col, hip
     }, s);
 }
 
-// One graph for a chunk of G unrecorded Monte Carlo steps (their snapshot
-// copies and colour passes; the device step counter advances by G at its
-// end), replayed instead of 2 n_col G direct launches.
+// One graph for a chunk of G unrecorded Monte Carlo steps (their n_col G
+// colour passes; the device step counter advances by G at its end), replayed
+// instead of the direct launches.
 int cpm_chunk_graph(spinmc_ctx* c, int G, hipGraphExec_t* out) {
     auto it = c->graphs.find(G);
     if (it != c->graphs.end()) {
@@ -2083,29 +2092,40 @@ int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
         }
         return check_dev(c, e, "sweep (resident)");
     }
+    if (n == 0) return SPINMC_OK;
+    // the streamed passes keep their snapshots in rotating buffers seeded
+    // from the areas here and folded back into them at the end of the call
+    // (and before recorded statistics)
     if (re == 0 && !c->prof && c->use_graphs) {
         const int G = std::min(n, kGraphChunk);
         const int full = n / G, rest = n - full * G;
         hipGraphExec_t ex = nullptr;
         int rc = cpm_chunk_graph(c, G, &ex);
         if (rc) return rc;
-        for (int k = 0; k < full && e == hipSuccess; ++k) e = hipGraphLaunch(ex, c->stream);
-        if (e == hipSuccess && rest > 0) {
-            rc = cpm_chunk_graph(c, rest, &ex);
+        hipGraphExec_t ex_rest = nullptr;
+        if (rest > 0) {
+            rc = cpm_chunk_graph(c, rest, &ex_rest);
             if (rc) return rc;
-            e = hipGraphLaunch(ex, c->stream);
         }
+        e = launch_cpm_pass_init(a, 0, c->stream);
+        for (int k = 0; k < full && e == hipSuccess; ++k) e = hipGraphLaunch(ex, c->stream);
+        if (e == hipSuccess && rest > 0) e = hipGraphLaunch(ex_rest, c->stream);
+        if (e == hipSuccess) e = launch_cpm_pass_final(a, 0, c->stream);
         return check_dev(c, e, "sweep (graph)");
     }
     const int n_rec = re > 0 ? n / re : 0;
     if (n_rec > 0) e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
     const int n_col = c->cpm_range == 2 ? 9 : 4;
+    if (e == hipSuccess) e = launch_cpm_pass_init(a, 0, c->stream);
     for (int i = 0; i < n && e == hipSuccess; ++i) {
         for (int col = 0; col < n_col && e == hipSuccess; ++col)
             e = cpm_enqueue_pass(c, a, i, col, c->stream);
-        if (e == hipSuccess && re > 0 && ((i + 1) % re) == 0)
-            e = launch_cpm_stats(a, c->n_tiles, (i + 1) / re - 1, c->stream);
+        if (e == hipSuccess && re > 0 && ((i + 1) % re) == 0) {
+            e = launch_cpm_pass_final(a, i + 1, c->stream);
+            if (e == hipSuccess) e = launch_cpm_stats(a, c->n_tiles, (i + 1) / re - 1, c->stream);
+        }
     }
+    if (e == hipSuccess) e = launch_cpm_pass_final(a, n, c->stream);
     if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)n, c->stream);
     return check_dev(c, e, "sweep");
 }

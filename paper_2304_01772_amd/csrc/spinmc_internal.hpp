@@ -158,8 +158,15 @@ struct CpmArgs {
     int32_t* lat;                 // cell ids (int32, natural layout)
     const int8_t* ctype;
     const int32_t* target;
-    int32_t* area;                // current areas
-    int32_t* snap;                // pass-start snapshot
+    int32_t* area;                // areas between calls (and at recorded steps)
+    int32_t* snap;                // copy of the areas written by the resident kernel
+    // Streamed passes: pass P (= n_col t + c) reads its snapshot as
+    // sbuf[P & 1] + dbuf[(P - 1) mod 3], adds its changes into dbuf[P mod 3]
+    // and writes sbuf[(P + 1) & 1] (its snapshot) and zeroes dbuf[(P + 1) mod
+    // 3] for the next pass; buffers of total_cells entries each.
+    int32_t* sbuf;                // [2][total_cells]
+    int32_t* dbuf;                // [3][total_cells]
+    int32_t total_cells;
     const int32_t* js;            // fixed-point adhesion
     const uint64_t* t_base;
     int32_t* stats;
@@ -180,7 +187,12 @@ hipError_t launch_cpm_pass_quad(const CpmArgs& a, int n_tiles, int c, int sweep_
                                 int threads, int tab_lds_bytes, int cell_cap, hipStream_t s);
 // Allow k_cpm_pass_quad up to lds_bytes of dynamic LDS (call outside capture).
 hipError_t cpm_reserve_lds(size_t lds_bytes);
-hipError_t launch_cpm_snapshot(const CpmArgs& a, int total_cells, hipStream_t s);
+// Before a call's streamed passes: sbuf[P0 & 1] = area, dbuf[(P0 - 1) mod 3]
+// = dbuf[P0 mod 3] = 0 for the pass P0 = n_col (t + sweep_off).
+hipError_t launch_cpm_pass_init(const CpmArgs& a, int sweep_off, hipStream_t s);
+// After the passes before pass P = n_col (t + sweep_off): area = the
+// snapshot pass P would read.
+hipError_t launch_cpm_pass_final(const CpmArgs& a, int sweep_off, hipStream_t s);
 hipError_t launch_cpm_stats(const CpmArgs& a, int n_tiles, int rec_row, hipStream_t s);
 hipError_t launch_cpm_area_recount(const CpmArgs& a, int n_tiles, int total_cells, hipStream_t s);
 
