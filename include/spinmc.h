@@ -266,8 +266,10 @@ int spinmc_thresholds(const spinmc_ctx *ctx, int32_t replica, uint64_t *host_T, 
  * mode 3 hybrid: resident where the lattice fits the LDS budget, streamed
  *   otherwise; both run concurrently.
  * mode 0 auto: resident if every lattice fits, else hybrid.
- * Calls without recording replay cached hipGraphs of 50-sweep chunks
- * (streamed passes and the concurrent resident branch captured together).
+ * Calls without recording replay cached hipGraphs of 50-sweep chunks of
+ * the streamed passes; resident groups run one launch per group for all
+ * sweeps of a call on side streams forked from and joined into the call's
+ * stream, concurrently with the streamed work.
  * tile_rows: rows of a plane per streamed unit (even; 0 = about 16 KiB);
  * wg_threads: 256 or 512 (0 = default);
  * flags: 0, SPINMC_SCHED_NT_ON or SPINMC_SCHED_NT_OFF: streamed passes load

@@ -622,7 +622,7 @@ int spinmc_create(const spinmc_replica_desc* d, int32_t n, uint64_t seed, int32_
     if ((e = A((void**)&c->d_lat, c->lat_bytes)) != hipSuccess ||
         (e = A((void**)&c->d_reps, sizeof(RepDev) * n)) != hipSuccess ||
         (e = A((void**)&c->d_tab, sizeof(uint32_t) * tab.size())) != hipSuccess ||
-        (e = A((void**)&c->d_t, sizeof(uint64_t))) != hipSuccess ||
+        (e = A((void**)&c->d_t, 2 * sizeof(uint64_t))) != hipSuccess ||
         (e = A((void**)&c->d_hist, sizeof(int32_t) * std::max<size_t>(hist_off, 1))) != hipSuccess ||
         (e = A((void**)&c->d_lists, sizeof(int32_t) * 5 * n)) != hipSuccess) {
         free_all(c);
@@ -1712,11 +1712,13 @@ int ensure_side_streams(spinmc_ctx* c) {
     return SPINMC_OK;
 }
 
-// One graph for a chunk of G unrecorded sweeps: the resident kernel on a
-// forked branch runs concurrently with the 2G streamed passes; the device
-// sweep counter advances by G at the join.
-int chunk_graph(spinmc_ctx* c, int G, hipGraphExec_t* out) {
-    auto it = c->graphs.find(G);
+// One graph for a chunk of G unrecorded sweeps: the streamed passes (2G
+// launches, or one persistent launch per model) and, unless stream_only,
+// the resident kernels on forked branches; the device sweep counter
+// advances by G at the end.
+int chunk_graph(spinmc_ctx* c, int G, bool stream_only, hipGraphExec_t* out) {
+    const int key = stream_only ? -G : G;
+    auto it = c->graphs.find(key);
     if (it != c->graphs.end()) {
         *out = it->second;
         return SPINMC_OK;
@@ -1728,10 +1730,10 @@ int chunk_graph(spinmc_ctx* c, int G, hipGraphExec_t* out) {
     hipError_t e = hipStreamBeginCapture(c->cap[0], hipStreamCaptureModeRelaxed);
     const bool prof = c->prof;
     c->prof = false;
-    if (e == hipSuccess) e = enqueue_resident(c, a, c->cap[0]);
+    if (e == hipSuccess && !stream_only) e = enqueue_resident(c, a, c->cap[0]);
     if (e == hipSuccess && c->n_tiles > 0)
         e = c->persist ? enqueue_persist(c, a, G, c->cap[0]) : enqueue_stream(c, a, 0, G, 0, c->cap[0]);
-    if (e == hipSuccess) e = join_resident(c, c->cap[0]);
+    if (e == hipSuccess && !stream_only) e = join_resident(c, c->cap[0]);
     c->prof = prof;
     if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)G, c->cap[0]);
     hipError_t e2 = hipStreamEndCapture(c->cap[0], &g);
@@ -1740,7 +1742,7 @@ int chunk_graph(spinmc_ctx* c, int G, hipGraphExec_t* out) {
     if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     if (g) hipGraphDestroy(g);
     if (e != hipSuccess) return check_dev(c, e, "graph capture");
-    c->graphs[G] = ex;
+    c->graphs[key] = ex;
     *out = ex;
     return SPINMC_OK;
 }
@@ -1750,19 +1752,33 @@ int enqueue_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
     int rc = prepare(c, mode);
     if (rc) return rc;
     hipError_t e = hipSuccess;
-    // Unrecorded, untimed calls replay cached graphs of whole chunks.
+    // Unrecorded, untimed calls replay cached graphs of whole chunks.  When
+    // both resident groups and streamed tiles exist, the resident kernels
+    // run outside the graphs, one launch per group for all n sweeps on side
+    // streams forked from the call's stream (their start counter copied to
+    // d_t[1] first, since the graphs advance d_t[0] meanwhile), so that they
+    // overlap the streamed graph replays for the whole call rather than
+    // meeting them at every chunk boundary.
     if (re == 0 && !c->prof && c->use_graphs) {
+        const bool split = c->n_tiles > 0 && !c->res_groups.empty();
         const int G = std::min(n, kGraphChunk);
         const int full = n / G, rest = n - full * G;
-        hipGraphExec_t ex = nullptr;
-        rc = chunk_graph(c, G, &ex);
+        hipGraphExec_t ex = nullptr, ex_rest = nullptr;
+        rc = chunk_graph(c, G, split, &ex);
         if (rc) return rc;
-        for (int k = 0; k < full && e == hipSuccess; ++k) e = hipGraphLaunch(ex, c->stream);
-        if (e == hipSuccess && rest > 0) {
-            rc = chunk_graph(c, rest, &ex);
+        if (rest > 0) {
+            rc = chunk_graph(c, rest, split, &ex_rest);
             if (rc) return rc;
-            e = hipGraphLaunch(ex, c->stream);
         }
+        if (split) {
+            e = launch_copy_counter(c->d_t, c->stream);
+            SweepArgs ar = sweep_args(c, n, 0, nullptr);
+            ar.t_base = c->d_t + 1;
+            if (e == hipSuccess) e = enqueue_resident(c, ar, c->stream);
+        }
+        for (int k = 0; k < full && e == hipSuccess; ++k) e = hipGraphLaunch(ex, c->stream);
+        if (e == hipSuccess && rest > 0) e = hipGraphLaunch(ex_rest, c->stream);
+        if (e == hipSuccess && split) e = join_resident(c, c->stream);
         return check_dev(c, e, "sweep (graph)");
     }
     SweepArgs a = sweep_args(c, n, re, stats);
@@ -1772,22 +1788,23 @@ int enqueue_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
         // first (resident replicas overwrite theirs)
         e = launch_fill_i32(stats, (size_t)n_rec * c->R * c->width, 0, c->stream);
     }
-    // resident groups on side streams, concurrent with the streamed passes;
-    // when both exist, in chunks of the graph's length so that direct
-    // launches overlap the way graph replays do
-    const bool mixed = c->n_tiles > 0 && !c->res_groups.empty();
-    const int G = mixed ? kGraphChunk : std::max(n, 1);
-    for (int j0 = 0; j0 < n && e == hipSuccess; j0 += G) {
-        const int m = std::min(G, n - j0);
-        SweepArgs aj = a;
-        aj.n_sweeps = m;
-        aj.sweep_off = j0;
-        e = enqueue_resident(c, aj, c->stream);
-        if (e == hipSuccess && c->n_tiles > 0)
-            e = (c->persist && re == 0) ? enqueue_persist(c, aj, m, c->stream)
-                                        : enqueue_stream(c, a, j0, m, re, c->stream);
-        if (e == hipSuccess) e = join_resident(c, c->stream);
+    // resident groups on side streams, one launch per group for all n
+    // sweeps, concurrent with the streamed passes (as in the graph replays;
+    // the device counter does not move before the end of the call);
+    // persistent streamed launches in chunks of the graph's length
+    if (e == hipSuccess) e = enqueue_resident(c, a, c->stream);
+    if (e == hipSuccess && c->n_tiles > 0) {
+        if (c->persist && re == 0) {
+            for (int j0 = 0; j0 < n && e == hipSuccess; j0 += kGraphChunk) {
+                SweepArgs aj = a;
+                aj.sweep_off = j0;
+                e = enqueue_persist(c, aj, std::min(kGraphChunk, n - j0), c->stream);
+            }
+        } else {
+            e = enqueue_stream(c, a, 0, n, re, c->stream);
+        }
     }
+    if (e == hipSuccess) e = join_resident(c, c->stream);
     if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)n, c->stream);
     return check_dev(c, e, "sweep");
 }

@@ -1035,6 +1035,10 @@ __global__ void k_advance(uint64_t* t, uint64_t n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *t += n;
 }
 
+__global__ void k_copy_counter(uint64_t* t) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) t[1] = t[0];
+}
+
 // FP64 observables from integer statistics (one thread per replica).
 __global__ void k_observables(const RepDev* reps, int R, const int32_t* stats, int width,
                               double* obs) {
@@ -1181,6 +1185,11 @@ hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s) {
     size_t blocks = (n + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_counter(uint64_t* t, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_counter, dim3(1), dim3(64), 0, s, t);
     return hipGetLastError();
 }
 

@@ -141,6 +141,9 @@ hipError_t persist_occupancy(int model, bool nt, size_t lds_bytes, int* per_cu);
 hipError_t persist_reserve_lds(size_t lds_bytes);
 hipError_t launch_fill_i32(int32_t* p, size_t n, int32_t v, hipStream_t s);
 hipError_t launch_advance(uint64_t* t, uint64_t n, hipStream_t s);
+// t[1] = t[0] (the start counter of resident launches that run beside
+// graph replays advancing t[0])
+hipError_t launch_copy_counter(uint64_t* t, hipStream_t s);
 hipError_t launch_measure(const RepDev* reps, const int32_t* list, int n, int max_sites,
                           const uint8_t* lat, int32_t* stats, int32_t* hist, int width,
                           hipStream_t s);
