@@ -669,8 +669,8 @@ def _read_run(d):
 def summarize_counters(dirs):
     """Per-attempt FETCH / WRITE bytes and VALU lane-instructions of each
     lattice kernel from counter runs (bench.py --steps 0 --warmup 0 ...
-    under rocprofv3 --pmc, one counter per run), calibrated by the plain
-    device copy each run ends with."""
+    under rocprofv3 --pmc, one or several counters per run), calibrated by
+    the plain device copy each run ends with."""
     modes, calib, cmds, hashes = {}, {}, [], set()
     for d in dirs:
         js, rows = _read_run(d)
@@ -679,60 +679,82 @@ def summarize_counters(dirs):
         mode = cfg["schedule_name"]
         sw = cfg["profiled_sweeps"]
         n_copy = cfg["copy_calibration_bytes"]
-        counter = rows[0]["Counter_Name"]
-        cmds.append(f"rocprofv3 --pmc {counter} --output-format csv -d <dir> -o pmc -- "
-                    f"python bench.py {' '.join(js['argv'])}")
-        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        scale = 1.0
-        if counter in ("FETCH_SIZE", "WRITE_SIZE"):
-            # counter reads KiB; the copy moves n_copy bytes each way
-            scale = n_copy / (max(copies) * 1024.0)
-            calib[counter] = round(scale, 4)
-        st, re_ = cfg["streamed_sites_by_model"], cfg["resident_sites_by_model"]
-        per_disp = {"k_stream_pass_ising": st["ising"] // 2, "k_stream_pass_potts": st["potts"] // 2}
-        res_total = (re_["ising"] + re_["potts"]) * sw
-        # persistent kernels: the profiled sweeps' launches come last
-        kern = js.get("kernels") or js.get("ising_probe", {}).get("kernels") or {}
-        n_pers = {"k_persist_ising": (kern.get("persist_ising") or {}).get("launches", 0),
-                  "k_persist_potts": (kern.get("persist_potts") or {}).get("launches", 0)}
-        pers_total = {"k_persist_ising": st["ising"] * sw, "k_persist_potts": st["potts"] * sw}
-        m = modes.setdefault(mode, {})
-        for kname in ("k_stream_pass_ising", "k_stream_pass_potts", "k_persist_ising",
-                      "k_persist_potts", "k_resident"):
-            vals = [float(r["Counter_Value"]) for r in rows if kname in r["Kernel_Name"]]
-            if not vals:
-                continue
-            if kname == "k_resident":
-                att, v = res_total, sum(vals)
-            elif kname in n_pers:
-                if not n_pers[kname]:
-                    continue
-                vals = vals[-n_pers[kname]:]
-                # per dispatch: the mean over the profiled launches
-                att, v = pers_total[kname] // len(vals), sum(vals) / len(vals)
-            else:
-                # the profiled sweeps come last: 2 launches per sweep
-                vals = vals[-2 * sw:]
-                att, v = per_disp[kname], statistics.median(vals)
-            if att <= 0:
-                continue
-            e = m.setdefault(kname, {"dispatches": len(vals)})
-            e["attempts_per_dispatch" if kname != "k_resident" else "attempts_total"] = att
-            if counter == "FETCH_SIZE":
-                e["fetch_bytes_per_attempt"] = round(v * 1024.0 * scale / att, 4)
-            elif counter == "WRITE_SIZE":
-                e["write_bytes_per_attempt"] = round(v * 1024.0 * scale / att, 4)
-            elif counter == "SQ_INSTS_VALU":
-                e["valu_lane_instr_per_attempt"] = round(v * 64.0 / att, 3)
-            elif counter == "VALUBusy":
-                e["valu_busy_pct"] = round(statistics.median(vals), 1)
+        counters = sorted({r["Counter_Name"] for r in rows})
+        cmds.append(f"rocprofv3 --pmc {' '.join(counters)} --output-format csv -d <dir> -o pmc "
+                    f"-- python3 bench.py {' '.join(js['argv'])}")
+        for counter in counters:
+            _summarize_counter(js, cfg, [r for r in rows if r["Counter_Name"] == counter],
+                               counter, mode, sw, n_copy, calib, modes)
     if len(hashes) != 1:
         raise SystemExit(f"counter runs were taken on different kernel sources: {hashes}")
+    # derived: VALU issue cycles per instruction and the 64-bit share
+    for m in modes.values():
+        for e in m.values():
+            if e.get("valu_active_cycles_per_attempt") and e.get("valu_lane_instr_per_attempt"):
+                e["valu_cycles_per_instr"] = round(
+                    e["valu_active_cycles_per_attempt"] / (e["valu_lane_instr_per_attempt"] / 64.0), 3)
+            if e.get("valu_int64_lane_instr_per_attempt") and e.get("valu_lane_instr_per_attempt"):
+                e["valu_int64_share"] = round(
+                    e["valu_int64_lane_instr_per_attempt"] / e["valu_lane_instr_per_attempt"], 4)
     out = {"kernel_source_hash": hashes.pop(), "copy_calibration": calib,
            "commands": cmds, "modes": modes}
     with open(COUNTERS, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out, indent=1))
+
+
+def _summarize_counter(js, cfg, rows, counter, mode, sw, n_copy, calib, modes):
+    """Per-attempt figures of one counter of one run (rows in dispatch
+    order) into modes[mode][kernel]."""
+    copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+    scale = 1.0
+    if counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        # counter reads KiB; the copy moves n_copy bytes each way
+        scale = n_copy / (max(copies) * 1024.0)
+        calib[counter] = round(scale, 4)
+    st, re_ = cfg["streamed_sites_by_model"], cfg["resident_sites_by_model"]
+    per_disp = {"k_stream_pass_ising": st["ising"] // 2, "k_stream_pass_potts": st["potts"] // 2}
+    res_total = (re_["ising"] + re_["potts"]) * sw
+    # persistent kernels: the profiled sweeps' launches come last
+    kern = js.get("kernels") or js.get("ising_probe", {}).get("kernels") or {}
+    n_pers = {"k_persist_ising": (kern.get("persist_ising") or {}).get("launches", 0),
+              "k_persist_potts": (kern.get("persist_potts") or {}).get("launches", 0)}
+    pers_total = {"k_persist_ising": st["ising"] * sw, "k_persist_potts": st["potts"] * sw}
+    m = modes.setdefault(mode, {})
+    for kname in ("k_stream_pass_ising", "k_stream_pass_potts", "k_persist_ising",
+                  "k_persist_potts", "k_resident"):
+        vals = [float(r["Counter_Value"]) for r in rows if kname in r["Kernel_Name"]]
+        if not vals:
+            continue
+        if kname == "k_resident":
+            att, v = res_total, sum(vals)
+        elif kname in n_pers:
+            if not n_pers[kname]:
+                continue
+            vals = vals[-n_pers[kname]:]
+            # per dispatch: the mean over the profiled launches
+            att, v = pers_total[kname] // len(vals), sum(vals) / len(vals)
+        else:
+            # the profiled sweeps come last: 2 launches per sweep
+            vals = vals[-2 * sw:]
+            att, v = per_disp[kname], statistics.median(vals)
+        if att <= 0:
+            continue
+        e = m.setdefault(kname, {"dispatches": len(vals)})
+        e["attempts_per_dispatch" if kname != "k_resident" else "attempts_total"] = att
+        if counter == "FETCH_SIZE":
+            e["fetch_bytes_per_attempt"] = round(v * 1024.0 * scale / att, 4)
+        elif counter == "WRITE_SIZE":
+            e["write_bytes_per_attempt"] = round(v * 1024.0 * scale / att, 4)
+        elif counter == "SQ_INSTS_VALU":
+            e["valu_lane_instr_per_attempt"] = round(v * 64.0 / att, 3)
+        elif counter == "SQ_INSTS_VALU_INT64":
+            e["valu_int64_lane_instr_per_attempt"] = round(v * 64.0 / att, 3)
+        elif counter == "SQ_ACTIVE_INST_VALU":
+            # cycles waves spend issuing VALU instructions, per attempt
+            e["valu_active_cycles_per_attempt"] = round(v / att, 4)
+        elif counter == "VALUBusy":
+            e["valu_busy_pct"] = round(statistics.median(vals), 1)
 
 
 def copy_calibration(torch, mib):
@@ -784,6 +806,9 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--nt", choices=["auto", "on", "off"], default="auto",
                     help="nontemporal own-plane access of the streamed passes")
+    ap.add_argument("--rpb", type=int, default=0, help="replicas per resident workgroup")
+    ap.add_argument("--persistent", action="store_true",
+                    help="persistent streamed passes (one launch per chunk)")
     ap.add_argument("--cpu-sweeps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probes", action="store_true",
@@ -828,9 +853,10 @@ def main():
     if args.ising_probe:
         # the streamed Ising probe alone (counter collection for its roofline)
         sched = None
-        if args.tile_rows or args.threads or args.nt != "auto":
+        if args.tile_rows or args.threads or args.nt != "auto" or args.persistent:
             sched = dict(tile_rows=args.tile_rows, wg_threads=args.threads,
-                         nt={"auto": None, "on": True, "off": False}[args.nt])
+                         nt={"auto": None, "on": True, "off": False}[args.nt],
+                         persistent=args.persistent)
         res, cfg = ising_stream_probe(Sampler, torch, args.ising_probe, args.prof_sweeps, sched)
         n_copy = copy_calibration(torch, args.copy_calibration_mib)
         cfg.update(schedule_name=f"ising_probe_{args.ising_probe}",
@@ -852,7 +878,8 @@ def main():
         print(f"# autotune: {tuning}", file=sys.stderr, flush=True)
     else:
         smp.set_schedule(mode=args.mode, tile_rows=args.tile_rows, wg_threads=args.threads,
-                         nt={"auto": None, "on": True, "off": False}[args.nt])
+                         nt={"auto": None, "on": True, "off": False}[args.nt], rpb=args.rpb,
+                         persistent=args.persistent)
     sched = smp.get_schedule()
     mode_name = {v: k for k, v in MODES.items()}[sched["mode"]]
     for w in range(args.warmup):
@@ -885,6 +912,26 @@ def main():
         dom = max(kern, key=lambda k: kern[k]["ms"])
         roof = roofline(dom, kern[dom], mode_name)
         roof["units"] = f"{mode_name} schedule of the workload, {args.prof_sweeps} sweeps"
+        if ms is not None:
+            # the whole timed sweep against the VALU issue peak: VALU lane-
+            # instructions per sweep from the counters of every kernel kind
+            per = {"k_stream_pass_ising": st_m["ising"], "k_stream_pass_potts": st_m["potts"],
+                   "k_persist_ising": st_m["ising"], "k_persist_potts": st_m["potts"],
+                   "k_resident": re_m["ising"] + re_m["potts"]}
+            ran = {KERNEL_NAMES[k] for k in kern}
+            lanes, ok = 0.0, True
+            for kname in ran:
+                ce = counter_entry(mode_name, kname)
+                if not ce or not ce.get("valu_lane_instr_per_attempt"):
+                    ok = False
+                    break
+                lanes += ce["valu_lane_instr_per_attempt"] * per[kname]
+            if ok and lanes > 0:
+                sweep_s = ms * 1e-3 / (args.steps * args.sweeps)
+                roof["sweep_alu"] = {
+                    "lane_instr_per_sweep": round(lanes),
+                    "achieved": round(lanes / sweep_s / 1e12, 2), "peak": round(VALU_PEAK / 1e12, 2),
+                    "unit": "T lane-instr/s", "frac": round(lanes / sweep_s / VALU_PEAK, 4)}
     smp.close()
 
     n_copy = copy_calibration(torch, args.copy_calibration_mib)

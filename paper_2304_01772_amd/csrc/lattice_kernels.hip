@@ -252,12 +252,12 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
     // byte 2 of the 16-bit Lemire product (< 2^24), and the smallest low half
     // of the products flags a rejection anywhere
     uint32_t pr[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) pr[j] = __umul24(w[j] & 0xFFFFu, mq);  // full-rate 24-bit multiply
+    // low halves compared in pairs (one word-select min per pair)
     uint32_t lmin = 0xFFFFFFFFu;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        pr[j] = __umul24(w[j] & 0xFFFFu, mq);  // full-rate 24-bit multiply
-        lmin = min(lmin, pr[j] & 0xFFFFu);
-    }
+    for (int j = 0; j < 16; j += 2) lmin = min(lmin, min(pr[j] & 0xFFFFu, pr[j + 1] & 0xFFFFu));
     // Bytewise: t = s + 1 + off <= 2q - 2 < 256; t + (128 - q) has bit 7 set
     // iff t >= q (and stays below 256); those bytes take t - q.
     const uint32_t Qb = (uint32_t)q * 0x01010101u;
