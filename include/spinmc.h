@@ -388,6 +388,19 @@ int spinmc_mlp_backward(const void *dev_params, const void *dev_x, const void *d
                         const void *dev_t, const void *dev_w, int32_t B, void *dev_grad,
                         void *dev_dx, void *dev_loss, void *dev_workspace, void *hip_stream);
 
+/* One training step in one call: spinmc_mlp_forward (pre-activations into
+ * dev_act, [B][256] FP32), spinmc_mlp_backward (no input gradient) and
+ * spinmc_mlp_adam, with the fixed-order reduction of the partial gradients
+ * and the Adam update fused into one kernel: the same arithmetic in the same
+ * order as the three calls, so the parameters, moments, dev_grad (may be
+ * NULL) and dev_loss (may be NULL) equal theirs bit for bit.  Arguments as
+ * in those calls.                                                           */
+int spinmc_mlp_train_step(void *dev_params, const void *dev_x, const void *dev_t,
+                          const void *dev_w, int32_t B, void *dev_grad, void *dev_m,
+                          void *dev_v, int32_t step, float lr, float beta1, float beta2,
+                          float eps, void *dev_loss, void *dev_act, void *dev_workspace,
+                          void *hip_stream);
+
 /* One Adam step on the FP32 parameters: m, v (FP32, same size) are the
  * moment buffers, step >= 1 the 1-based step number.                        */
 int spinmc_mlp_adam(void *dev_params, const void *dev_grad, void *dev_m, void *dev_v,

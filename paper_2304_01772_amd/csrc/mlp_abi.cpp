@@ -43,6 +43,20 @@ int spinmc_mlp_backward(const void* params, const void* x, const void* act, cons
                                       (hipStream_t)stream));
 }
 
+int spinmc_mlp_train_step(void* params, const void* x, const void* t, const void* w, int32_t B,
+                          void* grad, void* m, void* v, int32_t step, float lr, float beta1,
+                          float beta2, float eps, void* loss, void* act, void* workspace,
+                          void* stream) {
+    if (!params || !x || !t || !w || !m || !v || !act || !workspace || B < 1 || step < 1 ||
+        !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+        !(eps > 0.f))
+        return SPINMC_E_INVALID;
+    return status(launch_mlp_train_step((float*)params, (const float*)x, (const float*)t,
+                                        (const float*)w, B, (float*)grad, (float*)m, (float*)v,
+                                        step, lr, beta1, beta2, eps, (float*)loss, (float*)act,
+                                        (float*)workspace, (hipStream_t)stream));
+}
+
 int spinmc_mlp_adam(void* params, const void* grad, void* m, void* v, int32_t step, float lr,
                     float beta1, float beta2, float eps, void* stream) {
     if (!params || !grad || !m || !v || step < 1 || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||

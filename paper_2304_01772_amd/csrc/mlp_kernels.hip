@@ -5,7 +5,7 @@
 // of the paper's optimisation experiments (Results) while Monte Carlo checks
 // its answers.  Weights and activations enter the matrix cores as BF16
 // (round to nearest even from FP32), products accumulate in FP32
-// (v_mfma_f32_16x16x16_bf16).  Rounding points (the oracle mirrors them):
+// (gfx950's v_mfma_f32_16x16x32_bf16: a 16x16 tile per wave, K = 32).  Rounding points (the oracle mirrors them):
 //   forward : xb = bf16(x); z1 = W1b xb + b1; h1 = bf16(silu z1);
 //             z2 = W2b h1 + b2; h2 = bf16(silu z2); y = W3b h2 + b3
 //   backward: dY = 2 w (y - t) / B (FP32);  dW3 = sum dY h2, dH2 = W3b^T dY;
@@ -27,11 +27,12 @@ constexpr int oW1 = 0, ob1 = oW1 + kH * kIn, oW2 = ob1 + kH, ob2 = oW2 + kH * kH
               oW3 = ob2 + kH, ob3 = oW3 + kOut * kH, kNP = ob3 + kOut;
 constexpr int kSamplesPerWG = 64;
 constexpr int kPadK = 8;             // LDS row padding (bf16 elements) against bank conflicts
-constexpr int kS1 = 16 + kPadK;      // row stride of K=16 tiles
+constexpr int kK1 = 32;              // layer-1 K (4 inputs, zero-padded to one MFMA step)
+constexpr int kS1 = kK1 + kPadK;     // row stride of layer-1 tiles
 constexpr int kS2 = kH + kPadK;      // row stride of K=128 tiles
 constexpr int kST = kSamplesPerWG + kPadK;  // row stride of sample-major transposed tiles
 
-typedef short short4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
@@ -48,28 +49,24 @@ __device__ __forceinline__ float dsilu(float z) {
     return s * (1.0f + z * (1.0f - s));
 }
 
-// 16x16 A fragment (rows r, k in [k0, k0+16)) from a row-major bf16 tile.
-__device__ __forceinline__ short4v frag(const uint16_t* base, int stride, int k0) {
+// Operand fragment of a 16 x 32 tile (rows r, k in [k0, k0 + 32)) from a
+// row-major bf16 tile: lane l holds row l % 16, k0 + 8 (l / 16) .. + 7, one
+// 16-byte load (row strides and k0 keep it 16-byte aligned).
+__device__ __forceinline__ bf16x8 frag(const uint16_t* base, int stride, int k0) {
     const int l = threadIdx.x & 63;
-    const uint16_t* p = base + (l & 15) * stride + k0 + 4 * (l >> 4);
-    const uint2 v = *reinterpret_cast<const uint2*>(p);
-    short4v r;
-    r[0] = (short)(v.x & 0xFFFFu);
-    r[1] = (short)(v.x >> 16);
-    r[2] = (short)(v.y & 0xFFFFu);
-    r[3] = (short)(v.y >> 16);
-    return r;
+    const uint16_t* p = base + (l & 15) * stride + k0 + 8 * (l >> 4);
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
 }
 
-__device__ __forceinline__ float4v mfma(short4v a, short4v b, float4v c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+__device__ __forceinline__ float4v mfma(bf16x8 a, bf16x8 b, float4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 // Weights into LDS as BF16, [out][in] rows (B^T layout of the matrix cores).
 // 16-byte loads, all of a thread's loads issued before their conversions.
 __device__ void stage_weights(const float* P, uint16_t* w1, uint16_t* w2, uint16_t* w3,
                               bool need_w2) {
-    // W1: 128 x 4 -> rows of 16 (k >= 4 zero); one float4 per row
+    // W1: 128 x 4 -> rows of kK1 (k >= 4 zero); one float4 per row
     for (int n = threadIdx.x; n < kH; n += blockDim.x) {
         const float4 v = *reinterpret_cast<const float4*>(P + oW1 + n * kIn);
         uint16_t* r = w1 + n * kS1;
@@ -78,7 +75,7 @@ __device__ void stage_weights(const float* P, uint16_t* w1, uint16_t* w2, uint16
         r[2] = f2bf(v.z);
         r[3] = f2bf(v.w);
 #pragma unroll
-        for (int k = kIn; k < 16; ++k) r[k] = 0;
+        for (int k = kIn; k < kK1; ++k) r[k] = 0;
     }
     if (need_w2) {
         constexpr int kV = kH * kH / 4;  // float4 of W2
@@ -117,7 +114,7 @@ __device__ void stage_weights(const float* P, uint16_t* w1, uint16_t* w2, uint16
 __device__ __forceinline__ float4v out_layer(const uint16_t* h2, const uint16_t* w3) {
     float4v acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kt = 0; kt < kH / 16; ++kt) acc = mfma(frag(h2, kS2, 16 * kt), frag(w3, kS2, 16 * kt), acc);
+    for (int kt = 0; kt < kH / 32; ++kt) acc = mfma(frag(h2, kS2, 32 * kt), frag(w3, kS2, 32 * kt), acc);
     return acc;
 }
 
@@ -135,14 +132,14 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const float* P, const float* x,
     stage_weights(P, w1, w2, w3, true);
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int s0 = blockIdx.x * kSamplesPerWG + wave * 16;
-    for (int i = l; i < 16 * 16; i += 64) {
-        const int r = i >> 4, k = i & 15;
+    for (int i = l; i < 16 * kK1; i += 64) {
+        const int r = i / kK1, k = i % kK1;
         const int s = s0 + r;
         xa[wave][r * kS1 + k] = (k < kIn && s < B) ? f2bf(x[(size_t)s * kIn + k]) : (uint16_t)0;
     }
     __syncthreads();
     const int col = l & 15, rb = 4 * (l >> 4);
-    // layer 1 (K = 4, zero-padded to 16)
+    // layer 1 (K = 4, zero-padded to 32)
 #pragma unroll
     for (int nt = 0; nt < kH / 16; ++nt) {
         float4v acc = {0.f, 0.f, 0.f, 0.f};
@@ -162,8 +159,8 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const float* P, const float* x,
     for (int nt = 0; nt < kH / 16; ++nt) {
         float4v acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < kH / 16; ++kt)
-            acc = mfma(frag(h1[wave], kS2, 16 * kt), frag(w2 + nt * 16 * kS2, kS2, 16 * kt), acc);
+        for (int kt = 0; kt < kH / 32; ++kt)
+            acc = mfma(frag(h1[wave], kS2, 32 * kt), frag(w2 + nt * 16 * kS2, kS2, 32 * kt), acc);
         const int n = nt * 16 + col;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -174,6 +171,7 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const float* P, const float* x,
         }
     }
     __syncthreads();
+    if (!y) return;  // training steps keep only the pre-activations
     const float4v o = out_layer(h2[wave], w3);
     if (col < kOut) {
 #pragma unroll
@@ -320,9 +318,9 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(const float* P, const float* x,
         for (int nt = 0; nt < kH / 16; ++nt) {
             float4v acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kt = 0; kt < kSamplesPerWG / 16; ++kt)
-                acc = mfma(frag(dz2t + mt * 16 * kST, kST, 16 * kt),
-                           frag(h1t + nt * 16 * kST, kST, 16 * kt), acc);
+            for (int kt = 0; kt < kSamplesPerWG / 32; ++kt)
+                acc = mfma(frag(dz2t + mt * 16 * kST, kST, 32 * kt),
+                           frag(h1t + nt * 16 * kST, kST, 32 * kt), acc);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 pg[oW2 + (mt * 16 + rb + i) * kH + nt * 16 + col] = acc[i];
@@ -353,8 +351,8 @@ __global__ void __launch_bounds__(256) k_mlp_bwd(const float* P, const float* x,
     for (int nt = 0; nt < kH / 16; ++nt) {
         float4v acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < kH / 16; ++kt)
-            acc = mfma(frag(dz2 + s0 * kS2, kS2, 16 * kt), frag(w2t + nt * 16 * kS2, kS2, 16 * kt),
+        for (int kt = 0; kt < kH / 32; ++kt)
+            acc = mfma(frag(dz2 + s0 * kS2, kS2, 32 * kt), frag(w2t + nt * 16 * kS2, kS2, 32 * kt),
                        acc);
         const int n = nt * 16 + col;
 #pragma unroll
@@ -416,6 +414,47 @@ __global__ void k_mlp_adam(float* p, const float* g, float* m, float* v, int n, 
     v[i] = vi;
     const float mh = mi / c1, vh = vi / c2;
     p[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// The fixed-order sum of k_mlp_reduce and the Adam update of k_mlp_adam in
+// one pass over the parameters (the same arithmetic in the same order).
+__global__ void k_mlp_reduce_adam(const float* part, int n_wg, float* grad, float* loss,
+                                  float* p, float* m, float* v, float lr, float b1, float b2,
+                                  float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > kNP) return;
+    float gi = 0.f;
+    for (int g = 0; g < n_wg; ++g) gi += part[(size_t)g * (kNP + 1) + i];
+    if (i == kNP) {
+        if (loss) *loss = gi;
+        return;
+    }
+    if (grad) grad[i] = gi;
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1, vh = vi / c2;
+    p[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+hipError_t launch_mlp_train_step(float* params, const float* x, const float* t, const float* w,
+                                 int B, float* grad, float* m, float* v, int step, float lr,
+                                 float b1, float b2, float eps, float* loss, float* act,
+                                 float* scratch, hipStream_t s) {
+    const int g = (B + kSamplesPerWG - 1) / kSamplesPerWG;
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(g), dim3(256), 0, s, params, x, B, (float*)nullptr, act);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mlp_bwd, dim3(g), dim3(256), 0, s, params, x, act, t, w, B, scratch,
+                       (float*)nullptr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const float c1 = (float)(1.0 - std::pow((double)b1, (double)step));
+    const float c2 = (float)(1.0 - std::pow((double)b2, (double)step));
+    hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((kNP + 1 + 255) / 256), dim3(256), 0, s, scratch, g,
+                       grad, loss, params, m, v, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
 }
 
 hipError_t launch_mlp_forward(const float* params, const float* x, int B, float* y, float* act,

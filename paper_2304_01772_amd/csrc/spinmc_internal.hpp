@@ -207,5 +207,11 @@ hipError_t launch_mlp_backward(const float* params, const float* x, const float*
                                float* loss, float* scratch, hipStream_t s);
 hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v, int n, int step,
                            float lr, float b1, float b2, float eps, hipStream_t s);
+// forward (pre-activations into act), backward (partials into scratch), and
+// the fixed-order reduction fused with the Adam update: three launches
+hipError_t launch_mlp_train_step(float* params, const float* x, const float* t, const float* w,
+                                 int B, float* grad, float* m, float* v, int step, float lr,
+                                 float b1, float b2, float eps, float* loss, float* act,
+                                 float* scratch, hipStream_t s);
 
 }  // namespace spinmc

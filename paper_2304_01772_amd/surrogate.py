@@ -91,16 +91,14 @@ class SurrogateMLP:
         return y * self.y_sd + self.y_mu
 
     def train_step(self, xn, tn, w, lr=1e-3):
+        """Forward, backward and Adam in one library call (three launches)."""
         B = xn.shape[0]
         b = self._buffers(B)
-        L = lib()
-        s = self._stream()
-        check(L.spinmc_mlp_forward(_p(self.params), _p(xn), B, _p(b["y"]), _p(b["act"]), s))
-        check(L.spinmc_mlp_backward(_p(self.params), _p(xn), _p(b["act"]), _p(tn), _p(w), B,
-                                    _p(self.grad), None, _p(b["loss"]), _p(b["ws"]), s))
         self.step_no += 1
-        check(L.spinmc_mlp_adam(_p(self.params), _p(self.grad), _p(self.m), _p(self.v),
-                                self.step_no, lr, 0.9, 0.999, 1e-8, s))
+        check(lib().spinmc_mlp_train_step(_p(self.params), _p(xn), _p(tn), _p(w), B,
+                                          _p(self.grad), _p(self.m), _p(self.v), self.step_no, lr,
+                                          0.9, 0.999, 1e-8, _p(b["loss"]), _p(b["act"]),
+                                          _p(b["ws"]), self._stream()))
         return b["loss"]
 
     def input_grad(self, xn, tn, w):

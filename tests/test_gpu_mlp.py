@@ -106,3 +106,45 @@ def test_adam_matches_oracle(L):
         po, mo, vo = mlp.adam(po, g, mo, vo, step)
     torch.cuda.synchronize()
     np.testing.assert_allclose(pt.cpu().numpy(), po, rtol=1e-5, atol=1e-6)
+
+
+def test_train_step_equals_the_separate_calls(L):
+    """spinmc_mlp_train_step (forward, backward, reduction fused with Adam)
+    leaves parameters, moments, gradient and loss bit-identical to the
+    separate forward / backward / adam calls, over three steps, and each
+    gradient matches the oracle's."""
+    rng = np.random.default_rng(21)
+    dev = torch.device("cuda")
+    B = 200
+    P = mlp.init_params(rng)
+    x = torch.tensor(rng.normal(size=(B, 4)).astype(np.float32), device=dev)
+    t = torch.tensor(rng.normal(size=(B, 3)).astype(np.float32), device=dev)
+    w = torch.tensor([1.0, 0.5, 2.0], dtype=torch.float32, device=dev)
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    state = {}
+    for name in ("sep", "fused"):
+        state[name] = dict(p=torch.tensor(P, device=dev), m=torch.zeros(mlp.NP, device=dev),
+                           v=torch.zeros(mlp.NP, device=dev),
+                           g=torch.empty(mlp.NP, device=dev), loss=torch.empty(1, device=dev),
+                           act=torch.empty(L.spinmc_mlp_act_floats(B), device=dev),
+                           ws=torch.empty(L.spinmc_mlp_workspace_floats(B), device=dev))
+    y = torch.empty((B, 3), device=dev)
+    for step in range(1, 4):
+        a = state["sep"]
+        p_before = a["p"].cpu().numpy().copy()
+        assert L.spinmc_mlp_forward(_p(a["p"]), _p(x), B, _p(y), _p(a["act"]), s) == 0
+        assert L.spinmc_mlp_backward(_p(a["p"]), _p(x), _p(a["act"]), _p(t), _p(w), B, _p(a["g"]),
+                                     None, _p(a["loss"]), _p(a["ws"]), s) == 0
+        assert L.spinmc_mlp_adam(_p(a["p"]), _p(a["g"]), _p(a["m"]), _p(a["v"]), step, 1e-3, 0.9,
+                                 0.999, 1e-8, s) == 0
+        b = state["fused"]
+        assert L.spinmc_mlp_train_step(_p(b["p"]), _p(x), _p(t), _p(w), B, _p(b["g"]), _p(b["m"]),
+                                       _p(b["v"]), step, 1e-3, 0.9, 0.999, 1e-8, _p(b["loss"]),
+                                       _p(b["act"]), _p(b["ws"]), s) == 0
+        torch.cuda.synchronize()
+        for k in ("p", "m", "v", "g", "loss"):
+            assert torch.equal(a[k], b[k]), (step, k)
+        go, _, _ = mlp.backward(p_before, x.cpu().numpy(), t.cpu().numpy(), w.cpu().numpy())
+        _, bg, _ = mlp.magnitude_bounds(p_before, x.cpu().numpy(), t.cpu().numpy(),
+                                        w.cpu().numpy())
+        _close(b["g"].cpu().numpy(), go, bg)
