@@ -205,15 +205,18 @@ def cpm_probe(Sampler, torch, mcs):
     smp.sweep(mcs)
     torch.cuda.synchronize()
     kms, nl = smp.profile_read("cpm_pass")
+    kind, per_launch = "k_cpm_pass_quad (one launch per colour pass)", ids.size // 4
+    if nl == 0:  # the tiled persistent passes: one launch for all passes of the call
+        kms, nl = smp.profile_read("cpm_tiled")
+        kind, per_launch = "k_cpm_tiled (one launch per chunk)", ids.size * mcs // nl
     smp.profile(False)
     smp.close()
     sites = ids.shape[0] * ids.shape[1] * ids.shape[2]
     avg_s = kms / nl * 1e-3
-    per_launch = sites // 4
     return {"config": f"{ids.shape[0]} CPM replicas of {ids.shape[1]}x{ids.shape[2]}, "
                       f"1000 cells, {mcs} MCS (graph replays)", "schedule": chosen,
             "attempts_per_ns": round(sites * mcs / (ms * 1e6), 2),
-            "kernel": "k_cpm_pass", "bound": "alu", "launches": nl,
+            "kernel": kind, "bound": "alu", "launches": nl,
             "avg_launch_us": round(avg_s * 1e6, 2),
             "kernel_attempts_per_ns": round(per_launch / avg_s / 1e9, 2),
             "algorithmic_GBs": round(per_launch * 17 / avg_s / 1e9, 1)}

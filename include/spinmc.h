@@ -289,6 +289,14 @@ int spinmc_thresholds(const spinmc_ctx *ctx, int32_t replica, uint64_t *host_T, 
  *   bound (which only a slab workgroup that never became resident could
  *   cause) ends the launch early; the next spinmc_get_state then returns
  *   SPINMC_E_DEVICE and poisons the context.
+ * CPM contexts with the 3x3 neighbourhood: SPINMC_SCHED_PERSIST runs the
+ *   unrecorded steps of replicas of one shape (Lx a multiple of 8) as tiled
+ *   persistent passes: one launch per chunk of up to 500 steps, a workgroup
+ *   per tile (tile_rows rows, or 64, by up to 64 columns) holding its ids in
+ *   LDS, neighbouring tiles exchanging their border cells through the
+ *   lattice at a per-replica barrier after every pass; when the tiles do not
+ *   divide the lattice or cannot all be resident at once, the streamed passes
+ *   run instead.  A barrier wait past its bound poisons the context as above.
  * Invalid values return SPINMC_E_INVALID.  CPM contexts: mode 2 keeps every
  * step on streamed passes; any other mode lets the unrecorded steps of
  * lattices whose ids and tables fit 64 KiB of LDS run resident (one
@@ -353,7 +361,8 @@ enum spinmc_kernel_kind {
     SPINMC_K_HC_PASS = 6,       /* chain / cubic Ising colour pass            */
     SPINMC_K_MSC_PASS = 7,      /* multispin-coded Ising colour pass          */
     SPINMC_K_PERSIST_ISING = 8, /* persistent streamed Ising chunk            */
-    SPINMC_K_PERSIST_POTTS = 9  /* persistent streamed Potts chunk            */
+    SPINMC_K_PERSIST_POTTS = 9, /* persistent streamed Potts chunk            */
+    SPINMC_K_CPM_TILED = 10     /* tiled persistent CPM chunk                 */
 };
 int spinmc_profile(spinmc_ctx *ctx, int32_t enable);
 int spinmc_profile_read(spinmc_ctx *ctx, int32_t kind, double *ms_total, int64_t *launches);

@@ -597,6 +597,199 @@ __global__ void __launch_bounds__(1024) k_cpm_resident(CpmArgs a, int n_steps,
     }
 }
 
+// ------------------------------------------- tiled persistent streamed passes
+// All 4 G colour passes of G unrecorded Monte Carlo steps in one launch for
+// lattices too large for one workgroup's LDS (range 1, Lx % 8 == 0): every
+// replica is cut into TH x TW tiles, one workgroup per tile for the whole
+// launch, its ids (with a one-cell halo) in LDS.  A pass: the tile's sites
+// of the colour attempt their copies on the LDS ids (the decision of the
+// streamed passes, cpm_decide), the tile's border cells go to the global
+// lattice and its area changes to the pass's change buffer; then the
+// replica's workgroups meet at a barrier (a counter per replica, agent-scope
+// release / acquire), after which each reads its halo ring, which the
+// neighbouring tiles wrote, and stages the next pass's snapshot.  Snapshots
+// rotate as in the streamed passes (S[P & 1] + D[(P-1) % 3], the side work of
+// pass P spread over the replica's tiles).  Every tile workgroup of the
+// launch must be resident at once (the host sizes the grid within the chip's
+// occupancy); a barrier wait beyond its bound (about two seconds) raises
+// *abort and every waiting workgroup leaves, so a launch always ends.
+constexpr uint32_t kCpmSpinCap = 1u << 25;
+
+__device__ __forceinline__ void cpm_wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+__device__ int cpm_tile_barrier(uint32_t* bar, uint32_t need, uint32_t* abort_flag) {
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t spin = 0;; ++spin) {
+        if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) break;
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return 0;
+        if (spin >= kCpmSpinCap) {
+            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return 1;
+}
+
+__global__ void __launch_bounds__(256) k_cpm_tiled(CpmArgs a, int n_steps, int TH, int TW,
+                                                   int tab_lds_bytes, int cell_cap,
+                                                   uint32_t* bar, uint32_t* abort_flag) {
+    // dynamic LDS: [T hi | T lo] (tab_lds_bytes) | snap - A (int32 [cell_cap]) |
+    // type (int8 [cell_cap], padded to 16) | ids with halo (int32 [TH + 2][TW + 2])
+    extern __shared__ __align__(16) uint8_t dyn[];
+    uint32_t* qthr = reinterpret_cast<uint32_t*>(dyn);
+    int32_t* lsa = reinterpret_cast<int32_t*>(dyn + tab_lds_bytes);
+    int8_t* lty = reinterpret_cast<int8_t*>(lsa + cell_cap);
+    int32_t* tile = reinterpret_cast<int32_t*>(lty + ((cell_cap + 15) & ~15));
+    __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
+    __shared__ int go;
+    // block b: replica b % R, tile b / R (with R a multiple of 8 a replica's
+    // tiles share one XCD)
+    const int r = (int)blockIdx.x % a.R, tix = (int)blockIdx.x / a.R;
+    const RepDev R = a.reps[r];
+    const int Lx = R.Lx, Ly = R.Ly, ntx = Lx / TW, n_tiles = ntx * (Ly / TH);
+    const int y0 = (tix / ntx) * TH, x0 = (tix % ntx) * TW;
+    const int ts = TW + 2, nthr = (int)blockDim.x, tid = (int)threadIdx.x;
+    const int ncell = R.q + 1;
+    int32_t* gids = a.lat + R.lat_off;
+    const int32_t* A = a.target + R.cell_off;
+    for (int i = tid; i < 2 * R.tab_n; i += nthr) qthr[i] = a.tab[R.tab_off + i];
+    for (int i = tid; i < R.n_types * R.n_types; i += nthr) ljs[i] = a.js[R.js_off + i];
+    for (int i = tid; i < ncell; i += nthr) lty[i] = a.ctype[R.cell_off + i];
+    // the tile with its halo (periodic)
+    for (int i = tid; i < (TH + 2) * ts; i += nthr) {
+        const int ly = i / ts, lx = i - ly * ts;
+        const int gy = wrapc(y0 + ly - 1, Ly), gx = wrapc(x0 + lx - 1, Lx);
+        tile[i] = gids[gy * Lx + gx];
+    }
+    const uint64_t t0 = *a.t_base;
+    const int Q = Lx >> 3;                 // quads per global row
+    const int nq = (TH >> 1) * (TW >> 3);  // quads of one colour in the tile
+    // this tile's share of the replica's cells for the side work
+    const int per = (ncell + n_tiles - 1) / n_tiles;
+    const int c0 = tix * per, c1 = min(ncell, c0 + per);
+    for (int sw = 0; sw < n_steps; ++sw) {
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t j = (uint32_t)(4 * sw + c);
+            const uint64_t P = 4 * (t0 + (uint64_t)sw) + (uint64_t)c;
+            const uint32_t p = (uint32_t)P;
+            const PassAreas pa = pass_areas(a, P, R.cell_off);
+            if (j > 0) {
+                // the halo ring, written by the neighbouring tiles' last pass
+                const int ring = 2 * ts + 2 * TH;
+                for (int i = tid; i < ring; i += nthr) {
+                    int ly, lx;
+                    if (i < ts) {
+                        ly = 0;
+                        lx = i;
+                    } else if (i < 2 * ts) {
+                        ly = TH + 1;
+                        lx = i - ts;
+                    } else {
+                        const int k = i - 2 * ts;
+                        ly = 1 + (k >> 1);
+                        lx = (k & 1) ? TW + 1 : 0;
+                    }
+                    tile[ly * ts + lx] =
+                        gids[wrapc(y0 + ly - 1, Ly) * Lx + wrapc(x0 + lx - 1, Lx)];
+                }
+            }
+            for (int i = tid; i < ncell; i += nthr) lsa[i] = pa.s_rd[i] + pa.d_rd[i] - A[i];
+            // side work of pass P for this tile's cells
+            {
+                const size_t n = (size_t)a.total_cells;
+                int32_t* s_wr = a.sbuf + (size_t)((P + 1u) & 1u) * n + R.cell_off;
+                int32_t* d_clr = a.dbuf + (size_t)((P + 1u) % 3u) * n + R.cell_off;
+                for (int i = c0 + tid; i < c1; i += nthr) {
+                    s_wr[i] = pa.s_rd[i] + pa.d_rd[i];
+                    d_clr[i] = 0;
+                }
+            }
+            __syncthreads();
+            // the colour's quads of the tile: four consecutive same-colour
+            // sites of a row share Philox block k >> 2 (global counters)
+            const int cy = c >> 1, cx = c & 1;
+            for (int it = tid; it < nq; it += nthr) {
+                const int rr = it / (TW >> 3), qi = it - rr * (TW >> 3);
+                const int gy = y0 + 2 * rr + cy;
+                const int gx0 = x0 + 8 * qi;
+                const uint32_t kq = (uint32_t)((gy >> 1) * Q + (gx0 >> 3));
+                uint32_t w[4];
+                philox4x32_10(kq, p, R.rid, kTagMain, a.key0, a.key1, w);
+                const int ly = gy - y0 + 1;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int lx = gx0 - x0 + 2 * u + cx + 1;
+                    const int32_t* ru = tile + (ly - 1) * ts;
+                    const int32_t* ry = tile + ly * ts;
+                    const int32_t* rd = tile + (ly + 1) * ts;
+                    const int nb[8] = {ru[lx - 1], ru[lx], ru[lx + 1], ry[lx - 1], ry[lx + 1],
+                                       rd[lx - 1], rd[lx], rd[lx + 1]};
+                    const int s = ry[lx];
+                    const int tg = cpm_decide(a, R, nb, s, w[u], 4u * kq + (uint32_t)u, p, qthr,
+                                              lsa, lty, ljs);
+                    if (tg >= 0) {
+                        tile[ly * ts + lx] = tg;
+                        atomicAdd(&pa.d_wr[tg], 1);
+                        atomicAdd(&pa.d_wr[s], -1);
+                    }
+                }
+            }
+            __syncthreads();
+            // the tile's border cells for the neighbouring tiles
+            for (int i = tid; i < 2 * TW + 2 * (TH - 2); i += nthr) {
+                int ly, lx;
+                if (i < TW) {
+                    ly = 1;
+                    lx = 1 + i;
+                } else if (i < 2 * TW) {
+                    ly = TH;
+                    lx = 1 + i - TW;
+                } else {
+                    const int k = i - 2 * TW;
+                    ly = 2 + (k >> 1);
+                    lx = (k & 1) ? TW : 1;
+                }
+                gids[(y0 + ly - 1) * Lx + x0 + lx - 1] = tile[ly * ts + lx];
+            }
+            cpm_wait_stores();
+            __syncthreads();
+            if (tid == 0)
+                go = cpm_tile_barrier(bar + r, (uint32_t)n_tiles * (j + 1u), abort_flag);
+            __syncthreads();
+            if (!go) return;  // uniform: the whole workgroup leaves
+        }
+    }
+    // the tile's interior (its border is already in place)
+    for (int i = tid; i < TH * TW; i += nthr) {
+        const int ly = 1 + i / TW, lx = 1 + i % TW;
+        gids[(y0 + ly - 1) * Lx + x0 + lx - 1] = tile[ly * ts + lx];
+    }
+}
+
+size_t cpm_tiled_lds_bytes(int tab_lds_bytes, int cell_cap, int TH, int TW) {
+    return (size_t)tab_lds_bytes + (size_t)4 * cell_cap + (size_t)((cell_cap + 15) & ~15) +
+           (size_t)4 * (TH + 2) * (TW + 2);
+}
+
+hipError_t cpm_tiled_occupancy(int tab_lds_bytes, int cell_cap, int TH, int TW, int* per_cu) {
+    const size_t lds = cpm_tiled_lds_bytes(tab_lds_bytes, cell_cap, TH, TW);
+    hipError_t e = hipFuncSetAttribute((const void*)k_cpm_tiled,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, (const void*)k_cpm_tiled, 256, lds);
+}
+
+hipError_t launch_cpm_tiled(const CpmArgs& a, int n_steps, int TH, int TW, int tab_lds_bytes,
+                            int cell_cap, int n_blocks, uint32_t* bar, uint32_t* abort_flag,
+                            hipStream_t s) {
+    const size_t lds = cpm_tiled_lds_bytes(tab_lds_bytes, cell_cap, TH, TW);
+    hipLaunchKernelGGL(k_cpm_tiled, dim3(n_blocks), dim3(256), lds, s, a, n_steps, TH, TW,
+                       tab_lds_bytes, cell_cap, bar, abort_flag);
+    return hipGetLastError();
+}
+
 size_t cpm_resident_lds_bytes(int tab_lds_bytes, int cell_cap, int max_sites) {
     return (size_t)tab_lds_bytes + (size_t)12 * cell_cap + (size_t)((cell_cap + 15) & ~15) +
            (size_t)4 * max_sites;

@@ -188,6 +188,8 @@ struct spinmc_ctx {
     long long* d_cov_part = nullptr;  // chunk sums of the split covariance estimator
     size_t cov_part_n = 0;
     int cpm_cell_cap = 0;
+    uint32_t* d_cpm_bar = nullptr;  // tiled persistent CPM passes: [0] abort word, [1 .. R] barriers
+    bool cpm_tiled_used = false;
     // kernel timing
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
@@ -251,6 +253,8 @@ void free_all(spinmc_ctx* c) {
     hipFree(c->d_snap);
     hipFree(c->d_sbuf);
     hipFree(c->d_dbuf);
+    hipFree(c->d_cpm_bar);
+    c->d_cpm_bar = nullptr;
     c->d_sbuf = nullptr;
     c->d_dbuf = nullptr;
     hipFree(c->d_js);
@@ -476,6 +480,7 @@ int cpm_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes);
 int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes);
 int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats);
 int cpm_recount_if_dirty(spinmc_ctx* c);
+bool cpm_tiled_plan(spinmc_ctx* c, int* TH, int* TW, int* n_blocks);
 int create_tri(const spinmc_replica_desc* d, int n, uint64_t seed, int init, void* stream,
                spinmc_ctx** out);
 int tri_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes);
@@ -812,9 +817,10 @@ int spinmc_set_schedule(spinmc_ctx* c, const spinmc_schedule* s) {
             (SPINMC_SCHED_NT_ON | SPINMC_SCHED_NT_OFF))
         return fail(SPINMC_E_INVALID,
                     "set_schedule: flags must be 0, NT_ON or NT_OFF, optionally with PERSIST");
-    if ((s->flags & SPINMC_SCHED_PERSIST) && (c->cpm || c->tri || c->msc))
+    if ((s->flags & SPINMC_SCHED_PERSIST) && (c->tri || c->msc || (c->cpm && c->cpm_range != 1)))
         return fail(SPINMC_E_UNSUPPORTED,
-                    "set_schedule: persistent passes serve square-lattice Ising and Potts only");
+                    "set_schedule: persistent passes serve square-lattice Ising, Potts and the "
+                    "3x3 CPM only");
     if (s->mode == 1 && !c->cpm)
         for (const HostRep& h : c->reps)
             if (!h.resident)
@@ -1082,6 +1088,10 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
         // then streamed passes over several tile heights
         cand.push_back(spinmc_schedule{0, 0, 0, 0});
         for (int tr : {0, 2, 4, 8, 16}) cand.push_back(spinmc_schedule{2, tr, 256, 0});
+        // tiled persistent passes (where they apply), tiles of 64 and 32 rows
+        int TH = 0, TW = 0, nb = 0;
+        if (cpm_tiled_plan(c, &TH, &TW, &nb))
+            for (int tr : {0, 32}) cand.push_back(spinmc_schedule{2, tr, 256, SPINMC_SCHED_PERSIST});
     } else {
         bool all_res = true, any_res_chunk = false, any_stream = false;
         int min_def = 1 << 30;
@@ -2022,10 +2032,62 @@ int cpm_recount_if_dirty(spinmc_ctx* c) {
     return check_dev(c, e, "area count");
 }
 
+// A tiled persistent launch whose barrier wait ran past its bound leaves the
+// state undefined: report it (synchronising) and poison the context.
+int cpm_tiled_check(spinmc_ctx* c) {
+    if (!c->cpm_tiled_used || !c->d_cpm_bar) return SPINMC_OK;
+    uint32_t abort_word = 0;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(&abort_word, c->d_cpm_bar, sizeof abort_word, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return check_dev(c, e, "CPM tiled check");
+    if (abort_word != 0) {
+        c->poisoned = true;
+        return fail(SPINMC_E_DEVICE, "CPM tiled passes: a workgroup waited past its bound "
+                                     "(tile workgroups not resident together); state undefined");
+    }
+    return SPINMC_OK;
+}
+
+// Tiles of the tiled persistent passes for the context, or false when they
+// do not apply: range 1, four-site quads, every replica of one shape, tiles
+// dividing the lattice, and all tile workgroups resident at once.
+bool cpm_tiled_plan(spinmc_ctx* c, int* TH, int* TW, int* n_blocks) {
+    if (c->cpm_range != 1 || !c->cpm_quad) return false;
+    const int Lx = c->reps[0].dev.Lx, Ly = c->reps[0].dev.Ly;
+    for (const HostRep& h : c->reps)
+        if (h.dev.Lx != Lx || h.dev.Ly != Ly) return false;
+    int tw = 0;
+    for (int cand : {64, 32, 16, 8})
+        if (Lx % cand == 0) {
+            tw = cand;
+            break;
+        }
+    int th = c->sched.tile_rows > 0 ? c->sched.tile_rows : 64;
+    th = std::min(th, Ly) & ~1;
+    while (th >= 2 && Ly % th != 0) th -= 2;
+    if (tw == 0 || th < 2) return false;
+    const long blocks = (long)c->R * (Lx / tw) * (Ly / th);
+    const size_t tab_bytes = align_up((size_t)8 * std::max(c->max_tab_n, 1), 16);
+    int per_cu = 0, n_cu = 0;
+    if (cpm_tiled_occupancy((int)tab_bytes, c->cpm_cell_cap, th, tw, &per_cu) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, c->device) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (per_cu < 1 || blocks > (long)per_cu * n_cu) return false;
+    *TH = th;
+    *TW = tw;
+    *n_blocks = (int)blocks;
+    return true;
+}
+
 int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
     const HostRep& h = c->reps[r];
     if (bytes != (size_t)h.dev.Lx * h.dev.Ly * 4)
         return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
+    if (int rc = cpm_tiled_check(c)) return rc;
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess)
         e = hipMemcpy(host, reinterpret_cast<int32_t*>(c->d_lat) + h.dev.lat_off, bytes,
@@ -2033,7 +2095,7 @@ int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
     return check_dev(c, e, "get_state");
 }
 
-// The snapshot copy and the colour pass of pass `col` of sweep `i` of a call.
+// The colour pass `col` of sweep `i` of a call.
 hipError_t cpm_enqueue_pass(spinmc_ctx* c, const CpmArgs& a, int i, int col, hipStream_t s) {
     const size_t tab_bytes = align_up((size_t)8 * std::max(c->max_tab_n, 1), 16);
     const int threads = c->sched.wg_threads > 0 ? std::min(c->sched.wg_threads, 256) : 256;
@@ -2110,6 +2172,34 @@ int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
         return check_dev(c, e, "sweep (resident)");
     }
     if (n == 0) return SPINMC_OK;
+    // tiled persistent passes (schedule flag SPINMC_SCHED_PERSIST): one
+    // launch per chunk of up to 500 steps, barriers cleared before each
+    int TH = 0, TW = 0, n_blocks = 0;
+    if (re == 0 && (c->sched.flags & SPINMC_SCHED_PERSIST) && cpm_tiled_plan(c, &TH, &TW, &n_blocks)) {
+        if (!c->d_cpm_bar) {
+            if (hipMalloc((void**)&c->d_cpm_bar, sizeof(uint32_t) * (c->R + 1)) != hipSuccess ||
+                hipMemset(c->d_cpm_bar, 0, sizeof(uint32_t) * (c->R + 1)) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(SPINMC_E_NOMEM, "sweep: CPM barrier words");
+            }
+        }
+        e = launch_cpm_pass_init(a, 0, c->stream);
+        for (int done = 0; done < n && e == hipSuccess;) {
+            const int k = std::min(500, n - done);
+            e = launch_fill_i32(reinterpret_cast<int32_t*>(c->d_cpm_bar + 1), (size_t)c->R, 0,
+                                c->stream);
+            if (e == hipSuccess)
+                e = timed(c, SPINMC_K_CPM_TILED, [&] {
+                    return launch_cpm_tiled(a, k, TH, TW, (int)tab_bytes, c->cpm_cell_cap,
+                                            n_blocks, c->d_cpm_bar + 1, c->d_cpm_bar, c->stream);
+                }, c->stream);
+            if (e == hipSuccess) e = launch_advance(c->d_t, (uint64_t)k, c->stream);
+            done += k;
+        }
+        if (e == hipSuccess) e = launch_cpm_pass_final(a, 0, c->stream);
+        c->cpm_tiled_used = true;
+        return check_dev(c, e, "sweep (tiled)");
+    }
     // the streamed passes keep their snapshots in rotating buffers seeded
     // from the areas here and folded back into them at the end of the call
     // (and before recorded statistics)

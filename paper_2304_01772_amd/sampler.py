@@ -205,7 +205,8 @@ class Sampler:
 
     # ------------------------------------------------------------- timing
     KERNELS = {"stream_ising": 0, "resident": 1, "cpm_pass": 3, "stream_potts": 4, "tri_pass": 5,
-               "hc_pass": 6, "msc_pass": 7, "persist_ising": 8, "persist_potts": 9}
+               "hc_pass": 6, "msc_pass": 7, "persist_ising": 8, "persist_potts": 9,
+               "cpm_tiled": 10}
 
     def profile(self, enable=True):
         check(lib().spinmc_profile(self.ctx, 1 if enable else 0))

@@ -146,6 +146,69 @@ def test_cell_sorting_config_full_length(S):
     smp.close()
 
 
+@pytest.mark.parametrize("shape,tile_rows,n_rep", [((64, 64), 16, 3), ((128, 96), 0, 2),
+                                                   ((32, 64), 2, 2), ((48, 40), 0, 4)])
+def test_tiled_persistent_passes_match_oracle(S, shape, tile_rows, n_rep):
+    """Tiled persistent CPM passes (one workgroup per tile, ids in LDS,
+    border exchange at a per-replica barrier after every pass): states
+    bit-exact with the oracle across a 500-step chunk boundary, with
+    recorded steps (per-pass launches) in between; thin (2-row) tiles,
+    32- and 8-column tiles."""
+    J = JS["sorting"]
+    cases = [_random_case(900 + 17 * r + shape[0], shape, 9) for r in range(n_rep)]
+    reps = [_rep(ids, J, ct, A, 1.0, 10.0, 60 + r) for r, (ids, ct, A) in enumerate(cases)]
+    smp = S(reps, 23, init=False)
+    smp.set_schedule(mode="stream", tile_rows=tile_rows, persistent=True)
+    for r, (ids, _, _) in enumerate(cases):
+        smp.set_state(r, ids)
+    cur = [ids for ids, _, _ in cases]
+    t0 = 0
+    smp.profile(True)
+    for n, re in ((505, 0), (4, 2), (9, 0)):
+        st = smp.sweep(n, re)
+        torch.cuda.synchronize()
+        for r, (_, ct, A) in enumerate(cases):
+            cur[r], _, ost = orc.cpm_run(cur[r], J, ct, A, 1.0, 10.0, 23, 60 + r, t0, n, re)
+            assert np.array_equal(smp.get_state(r), cur[r]), (r, t0)
+            if re:
+                assert np.array_equal(st[:, r].cpu().numpy(), ost)
+        t0 += n
+    ms, n_l = smp.profile_read("cpm_tiled")
+    assert n_l == 3 and ms > 0  # 500 + 5 steps, then 9
+    smp.close()
+
+
+def test_cell_sorting_full_length_tiled_persistent(S):
+    """The cell-sorting workload at 2000 Monte Carlo steps on the tiled
+    persistent passes (64 x 64 tiles, 64 per replica): two replicas' states
+    bit-exact with the oracle, and the launches were the tiled kernel."""
+    from concurrent.futures import ThreadPoolExecutor
+    ids, ctype, A, J, prm = synth.cpm_sorting()
+    reps = [_rep(ids[r], J, ctype, A, prm["lambda_area"], prm["temperature"], r)
+            for r in range(ids.shape[0])]
+    smp = S(reps, prm["seed"], init=False)
+    smp.set_schedule(mode="stream", persistent=True)
+    for r in range(len(reps)):
+        smp.set_state(r, ids[r])
+    smp.profile(True)
+    smp.sweep(prm["n_mcs"])
+    torch.cuda.synchronize()
+    ms, n_l = smp.profile_read("cpm_tiled")
+    smp.profile(False)
+    assert n_l == 4 and ms > 0
+    sample = (1, 6)
+
+    def oracle(r):
+        return orc.cpm_run(ids[r], J, ctype, A, prm["lambda_area"], prm["temperature"],
+                           prm["seed"], r, 0, prm["n_mcs"])
+
+    with ThreadPoolExecutor(len(sample)) as ex:
+        outs = list(ex.map(oracle, sample))
+    for r, (want, _, _) in zip(sample, outs):
+        assert np.array_equal(smp.get_state(r), want), f"replica {r}"
+    smp.close()
+
+
 def test_paper_cell_sorting_setting(S):
     """The paper's own CPM setting (36 cells of area 25 in a touching 6 x 6
     aggregate, Table 2 adhesion, k_B T = 8, A = 25, lambda = 1) on 16
@@ -347,7 +410,8 @@ def test_autotune_keeps_the_chain(S):
         smp.set_state(r, ids)
     smp.sweep(4)
     chosen, rates = smp.autotune(trial_sweeps=5)
-    assert len(rates) == 6 and all(x > 0 for x in rates)
+    # resident, five streamed tile heights, two tiled persistent candidates
+    assert len(rates) == 8 and all(x > 0 for x in rates)
     smp.sweep(5)
     for r, (ids, ct, A) in enumerate(cases):
         want, _, _ = orc.cpm_run(ids, J, ct, A, 1.0, 10.0, 15, 80 + r, 0, 9)
