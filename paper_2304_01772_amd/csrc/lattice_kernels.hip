@@ -98,23 +98,37 @@ struct ChunkIn {
     uint32_t e;
 };
 
-template <int PAR, bool NT>
-__device__ __forceinline__ ChunkIn chunk_load(const uint8_t* own, const uint8_t* oth, int W,
-                                              uint32_t ro, uint32_t rom, uint32_t rop, int j0) {
+// Byte offsets within a plane: oo of the chunk (own row and the other
+// plane's same row), uo / dof of the rows above / below, eo of the halo dword.
+template <bool NT>
+__device__ __forceinline__ ChunkIn chunk_load(const uint8_t* own, const uint8_t* oth, uint32_t oo,
+                                              uint32_t uo, uint32_t dof, uint32_t eo) {
     ChunkIn in;
-    in.o = load_own<NT>(own + ro + j0);
-    in.m = *reinterpret_cast<const uint4*>(oth + ro + j0);
-    in.U = *reinterpret_cast<const uint4*>(oth + rom + j0);
-    in.D = *reinterpret_cast<const uint4*>(oth + rop + j0);
-    const int je = PAR == 0 ? ((j0 == 0) ? W - 4 : j0 - 4) : ((j0 + 16 == W) ? 0 : j0 + 16);
-    in.e = *reinterpret_cast<const uint32_t*>(oth + ro + je);
+    in.o = load_own<NT>(own + oo);
+    in.m = *reinterpret_cast<const uint4*>(oth + oo);
+    in.U = *reinterpret_cast<const uint4*>(oth + uo);
+    in.D = *reinterpret_cast<const uint4*>(oth + dof);
+    in.e = *reinterpret_cast<const uint32_t*>(oth + eo);
     return in;
 }
+
+// Plane offsets of one chunk: row offset ro (= y W), column j0; the rows
+// above and below wrap periodically, and so does the halo dword.
+template <int PAR>
+struct ChunkOff {
+    uint32_t oo, uo, dof, eo;
+    __device__ __forceinline__ ChunkOff(uint32_t ro, uint32_t j0, uint32_t W, uint32_t last) {
+        oo = ro + j0;
+        uo = (ro == 0u ? last : ro - W) + j0;
+        dof = (ro == last ? 0u : ro + W) + j0;
+        eo = ro + (PAR == 0 ? (j0 == 0u ? W - 4u : j0 - 4u) : (j0 + 16u == W ? 0u : j0 + 16u));
+    }
+};
 
 // PAR = (y + c) & 1 selects which horizontal neighbour the shifted byte
 // stream supplies.  thr: LDS [18 hi | 18 lo].
 template <int PAR, bool REC, bool NT>
-__device__ __forceinline__ void ising_compute(const ChunkIn& in, uint8_t* own, uint32_t ro, int j0,
+__device__ __forceinline__ void ising_compute(const ChunkIn& in, uint8_t* own, uint32_t oo,
                                               uint32_t p, uint32_t rid, uint32_t k0, uint32_t k1,
                                               const uint32_t* thr, IsingAcc& acc) {
     const uint32_t e = in.e;
@@ -143,7 +157,7 @@ __device__ __forceinline__ void ising_compute(const ChunkIn& in, uint8_t* own, u
         const uint32_t ny = Uv[k] + Dv[k];
         idx4[k] = ((ov[k] << 3) + ov[k] + (nx << 1) + nx + ny) << 2;
     }
-    const uint32_t kb = (uint32_t)(ro + j0);  // within-colour index of the first site
+    const uint32_t kb = oo;  // within-colour index of the first site
     uint32_t w[8];
     philox4x32_10(kb >> 3, p, rid, kTagMain, k0, k1, &w[0]);
     philox4x32_10((kb >> 3) + 1u, p, rid, kTagMain, k0, k1, &w[4]);
@@ -177,7 +191,7 @@ __device__ __forceinline__ void ising_compute(const ChunkIn& in, uint8_t* own, u
     uint32_t nv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) nv[k] = ov[k] ^ flip[k];
-    store_own<NT>(own + ro + j0, nv[0], nv[1], nv[2], nv[3]);
+    store_own<NT>(own + oo, nv[0], nv[1], nv[2], nv[3]);
     if (REC) {
         // Colour-1 pass of a recorded sweep: every bond has exactly one
         // colour-1 end, so summing over the updated sites counts each once.
@@ -207,25 +221,20 @@ __device__ __forceinline__ uint32_t ne_hi(uint32_t a, uint32_t b) {
 
 // 16-site Potts chunk.  thr: LDS [n hi | n lo], n = 9(2q-1); thr9: LDS
 // [9 hi | 9 lo] by dn + 4 (used when HZ, i.e. h = 0).
+// Byte offsets within a plane: oo of the chunk (own row and the other
+// plane's same row), uo / dof of the rows above / below, eo of the halo dword.
 template <int PAR, bool REC, bool HZ, bool NT>
-__device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, int W, uint32_t ro,
-                                            uint32_t rom, uint32_t rop, int j0, uint32_t p,
+__device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, uint32_t oo,
+                                            uint32_t uo, uint32_t dof, uint32_t eo, uint32_t p,
                                             uint32_t rid, uint32_t k0, uint32_t k1,
                                             const uint32_t* thr, const uint32_t* thr9, int q,
                                             int ntab, uint32_t lem_thr, PottsAcc& acc,
                                             int* lhist) {
-    const uint4 o = load_own<NT>(own + ro + j0);
-    const uint4 m = *reinterpret_cast<const uint4*>(oth + ro + j0);
-    const uint4 U = *reinterpret_cast<const uint4*>(oth + rom + j0);
-    const uint4 D = *reinterpret_cast<const uint4*>(oth + rop + j0);
-    uint32_t e;
-    if (PAR == 0) {
-        const int je = (j0 == 0) ? W - 4 : j0 - 4;
-        e = *reinterpret_cast<const uint32_t*>(oth + ro + je);
-    } else {
-        const int je = (j0 + 16 == W) ? 0 : j0 + 16;
-        e = *reinterpret_cast<const uint32_t*>(oth + ro + je);
-    }
+    const uint4 o = load_own<NT>(own + oo);
+    const uint4 m = *reinterpret_cast<const uint4*>(oth + oo);
+    const uint4 U = *reinterpret_cast<const uint4*>(oth + uo);
+    const uint4 D = *reinterpret_cast<const uint4*>(oth + dof);
+    const uint32_t e = *reinterpret_cast<const uint32_t*>(oth + eo);
     const uint32_t ov[4] = {o.x, o.y, o.z, o.w};
     const uint32_t mv[4] = {m.x, m.y, m.z, m.w};
     const uint32_t Uv[4] = {U.x, U.y, U.z, U.w};
@@ -242,7 +251,7 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
         sv[2] = __builtin_amdgcn_alignbyte(mv[3], mv[2], 1);
         sv[3] = __builtin_amdgcn_alignbyte(e, mv[3], 1);
     }
-    const uint32_t kb = (uint32_t)(ro + j0);
+    const uint32_t kb = oo;
     uint32_t w[16];
 #pragma unroll
     for (int b = 0; b < 4; ++b)
@@ -254,23 +263,43 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
     uint32_t pr[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) pr[j] = __umul24(w[j] & 0xFFFFu, mq);  // full-rate 24-bit multiply
-    // low halves compared in pairs (one word-select min per pair)
-    uint32_t lmin = 0xFFFFFFFFu;
-#pragma unroll
-    for (int j = 0; j < 16; j += 2) lmin = min(lmin, min(pr[j] & 0xFFFFu, pr[j + 1] & 0xFFFFu));
-    // Bytewise: t = s + 1 + off <= 2q - 2 < 256; t + (128 - q) has bit 7 set
-    // iff t >= q (and stays below 256); those bytes take t - q.
-    const uint32_t Qb = (uint32_t)q * 0x01010101u;
+    // Bytewise: t = s + 1 + off <= 2q - 2 < 256; u = t + (128 - q) has bit 7
+    // set iff t >= q (and stays below 256); those bytes take t - q.
     const uint32_t Cb = (uint32_t)(128 - q) * 0x01010101u;
+    const uint32_t Cb1 = Cb + 0x01010101u;
     uint32_t s2v[4];
+    if (q <= 64) {
+        // t < 128: the bytes with t >= q take the low seven bits of u
+        // (u - 128 = t - q), the others u - (128 - q) = t, in one select
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t offs = __builtin_amdgcn_perm(pr[4 * k + 1], pr[4 * k], 0x0C0C0602u) |
-                              __builtin_amdgcn_perm(pr[4 * k + 3], pr[4 * k + 2], 0x06020C0Cu);
-        const uint32_t t = ov[k] + offs + 0x01010101u;
-        const uint32_t ge = (t + Cb) & 0x80808080u;
-        const uint32_t wrap = ((ge << 1) - (ge >> 7)) & Qb;  // q in the bytes with t >= q
-        s2v[k] = t - wrap;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t offs = __builtin_amdgcn_perm(pr[4 * k + 1], pr[4 * k], 0x0C0C0602u) |
+                                  __builtin_amdgcn_perm(pr[4 * k + 3], pr[4 * k + 2], 0x06020C0Cu);
+            const uint32_t u = ov[k] + offs + Cb1;
+            const uint32_t G = u & 0x80808080u;
+            const uint32_t M = G - (G >> 7);  // 0x7F in the bytes with t >= q
+            s2v[k] = (u & M) | ((u - Cb) & ~M);
+        }
+    } else {
+        const uint32_t Qb = (uint32_t)q * 0x01010101u;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t offs = __builtin_amdgcn_perm(pr[4 * k + 1], pr[4 * k], 0x0C0C0602u) |
+                                  __builtin_amdgcn_perm(pr[4 * k + 3], pr[4 * k + 2], 0x06020C0Cu);
+            const uint32_t u = ov[k] + offs + Cb1;
+            const uint32_t ge = u & 0x80808080u;
+            const uint32_t wrap = ((ge << 1) - (ge >> 7)) & Qb;  // q in the bytes with t >= q
+            s2v[k] = u - Cb - wrap;
+        }
+    }
+    // a rejected 16-bit Lemire draw (low half of the product below
+    // 2^16 mod (q - 1)) is redrawn from the fallback stream; none are
+    // rejected when q - 1 divides 2^16
+    uint32_t lmin = 0xFFFFFFFFu;
+    if (lem_thr != 0u) {
+        // low halves compared in pairs (one word-select min per pair)
+#pragma unroll
+        for (int j = 0; j < 16; j += 2) lmin = min(lmin, min(pr[j] & 0xFFFFu, pr[j + 1] & 0xFFFFu));
     }
     if (lmin < lem_thr) {
         for (int j = 0; j < 16; ++j) {
@@ -285,9 +314,10 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
             s2v[j >> 2] = (s2v[j >> 2] & ~(0xFFu << sh)) | (min(s2, s2 - (uint32_t)q) << sh);
         }
     }
-    // dn + 4 = #ne(s) - #ne(s') + 4 per byte.  Labels below 2^b (b <= 4):
-    // ((a ^ c) + (2^b - 1)) has bit b set iff a != c, and four such flags sum
-    // and 4 + dn (times 2^b) stays below 256, so no per-flag shift is needed.
+    // dn + 4 = #ne(s) - #ne(s') + 4 = #ne(s) + #eq(s') per byte.  Labels
+    // below 2^b (b <= 4): ((a ^ c) + (2^b - 1)) has bit b set iff a != c;
+    // the eight flags (unequal to s, equal to s') sum to (4 + dn) 2^b < 256
+    // in each byte, so no per-flag shift is needed.
     uint32_t dn4[4];
     if (q <= 16) {
         const int b = q <= 2 ? 1 : 32 - __clz(q - 1);
@@ -296,9 +326,9 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
         for (int k = 0; k < 4; ++k) {
             const uint32_t neo = (((ov[k] ^ mv[k]) + A) & F) + (((ov[k] ^ sv[k]) + A) & F) +
                                  (((ov[k] ^ Uv[k]) + A) & F) + (((ov[k] ^ Dv[k]) + A) & F);
-            const uint32_t nen = (((s2v[k] ^ mv[k]) + A) & F) + (((s2v[k] ^ sv[k]) + A) & F) +
-                                 (((s2v[k] ^ Uv[k]) + A) & F) + (((s2v[k] ^ Dv[k]) + A) & F);
-            dn4[k] = (neo + (F << 2) - nen) >> b;
+            const uint32_t eqn = (~((s2v[k] ^ mv[k]) + A) & F) + (~((s2v[k] ^ sv[k]) + A) & F) +
+                                 (~((s2v[k] ^ Uv[k]) + A) & F) + (~((s2v[k] ^ Dv[k]) + A) & F);
+            dn4[k] = (neo + eqn) >> b;
         }
     } else {
 #pragma unroll
@@ -358,7 +388,7 @@ __device__ __forceinline__ void potts_chunk(uint8_t* own, const uint8_t* oth, in
     uint32_t nv[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) nv[k] = (s2v[k] & acc_sel[k]) | (ov[k] & ~acc_sel[k]);
-    store_own<NT>(own + ro + j0, nv[0], nv[1], nv[2], nv[3]);
+    store_own<NT>(own + oo, nv[0], nv[1], nv[2], nv[3]);
     if (REC) {
         uint32_t nex = 0u, ney = 0u, ssum = 0u;
 #pragma unroll
@@ -394,32 +424,36 @@ __device__ __forceinline__ void run_tile_potts(uint8_t* planes, int W, int Ly, i
     uint8_t* own = planes + (size_t)c * Ly * W;
     const uint8_t* oth = planes + (size_t)(1 - c) * Ly * W;
     const int cpr = W >> 4;
-    const int items = (rows >> 1) * cpr;
     // item it = r * cpr + jc (row pair r, chunk column jc), advanced by nthr
     // without a division per item
     const int dr = nthr / cpr, dj = nthr - dr * cpr;
     const int r0 = tid / cpr, jc0 = tid - r0 * cpr;
-    const uint32_t last = (uint32_t)(Ly - 1) * (uint32_t)W;
+    const uint32_t Wb = (uint32_t)W, W2 = 2u * Wb;
+    const uint32_t last = (uint32_t)(Ly - 1) * Wb;
+    // 32-bit plane offsets advanced per item: row offset ro by dr row pairs
+    // (one more when the chunk column wraps), column j0 by dj chunks; the
+    // row pairs of the tile end where ro reaches row y0 + rows
+    const uint32_t dro = (uint32_t)dr * W2, dj0 = (uint32_t)dj << 4;
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
         const int yf = y0 + ((par ^ c) & 1);
-        int r = r0, jc = jc0;
-        for (int it = tid; it < items; it += nthr) {
-            const uint32_t ro = (uint32_t)(yf + 2 * r) * (uint32_t)W;
-            const uint32_t rom = ro == 0u ? last : ro - (uint32_t)W;
-            const uint32_t rop = ro == last ? 0u : ro + (uint32_t)W;
-            const int j0 = jc << 4;
-            if (par == 0)
-                potts_chunk<0, REC, HZ, NT>(own, oth, W, ro, rom, rop, j0, p, rid, k0, k1, thr, thr9, q,
-                                        ntab, lem_thr, pa, lhist);
-            else
-                potts_chunk<1, REC, HZ, NT>(own, oth, W, ro, rom, rop, j0, p, rid, k0, k1, thr, thr9, q,
-                                        ntab, lem_thr, pa, lhist);
-            r += dr;
-            jc += dj;
-            if (jc >= cpr) {
-                jc -= cpr;
-                ++r;
+        const uint32_t ro_end = (uint32_t)(yf + rows) * Wb;
+        uint32_t ro = (uint32_t)(yf + 2 * r0) * Wb, j0 = (uint32_t)jc0 << 4;
+        for (; ro < ro_end;) {
+            if (par == 0) {
+                const ChunkOff<0> f(ro, j0, Wb, last);
+                potts_chunk<0, REC, HZ, NT>(own, oth, f.oo, f.uo, f.dof, f.eo, p, rid, k0, k1, thr,
+                                        thr9, q, ntab, lem_thr, pa, lhist);
+            } else {
+                const ChunkOff<1> f(ro, j0, Wb, last);
+                potts_chunk<1, REC, HZ, NT>(own, oth, f.oo, f.uo, f.dof, f.eo, p, rid, k0, k1, thr,
+                                        thr9, q, ntab, lem_thr, pa, lhist);
+            }
+            ro += dro;
+            j0 += dj0;
+            if (j0 >= Wb) {
+                j0 -= Wb;
+                ro += W2;
             }
         }
     }
@@ -437,54 +471,58 @@ __device__ __forceinline__ void run_tile_ising(uint8_t* planes, int W, int Ly, i
     uint8_t* own = planes + (size_t)c * Ly * W;
     const uint8_t* oth = planes + (size_t)(1 - c) * Ly * W;
     const int cpr = W >> 4;
-    const int items = (rows >> 1) * cpr;
     const int ya = y0 + (c & 1);        // rows with (y + c) & 1 == 0
     const int yb = y0 + ((c & 1) ^ 1);  // rows with (y + c) & 1 == 1
-    // item it = r * cpr + jc, advanced by nthr without a division per item
+    // item it = r * cpr + jc (row pair r, chunk column jc), advanced by nthr
+    // without a division per item: the 32-bit row offset by dr row pairs (one
+    // more when the column wraps), the column by dj chunks; the row pairs of
+    // the tile end where the row offset reaches row y0 + rows
     const int dr = nthr / cpr, dj = nthr - dr * cpr;
     const int r0 = tid / cpr, jc0 = tid - r0 * cpr;
-    const uint32_t last = (uint32_t)(Ly - 1) * (uint32_t)W;
+    const uint32_t Wb = (uint32_t)W, W2 = 2u * Wb;
+    const uint32_t last = (uint32_t)(Ly - 1) * Wb;
+    const uint32_t dro = (uint32_t)dr * W2, dj0 = (uint32_t)dj << 4;
     if (DUAL) {
-        int r = r0, jc = jc0;
-        for (int it = tid; it < items; it += nthr) {
-            const int j0 = jc << 4;
-            const uint32_t ra = (uint32_t)(ya + 2 * r) * (uint32_t)W;
-            const uint32_t rb = (uint32_t)(yb + 2 * r) * (uint32_t)W;
-            const ChunkIn A = chunk_load<0, NT>(own, oth, W, ra, ra == 0u ? last : ra - (uint32_t)W,
-                                            ra == last ? 0u : ra + (uint32_t)W, j0);
-            const ChunkIn B = chunk_load<1, NT>(own, oth, W, rb, rb == 0u ? last : rb - (uint32_t)W,
-                                            rb == last ? 0u : rb + (uint32_t)W, j0);
-            ising_compute<0, REC, NT>(A, own, ra, j0, p, rid, k0, k1, thr, ia);
-            ising_compute<1, REC, NT>(B, own, rb, j0, p, rid, k0, k1, thr, ia);
-            r += dr;
-            jc += dj;
-            if (jc >= cpr) {
-                jc -= cpr;
-                ++r;
+        // ra: row of parity 0, ra + db: the row of parity 1 in the same pair
+        const int db = yb - ya;  // +1 or -1
+        const uint32_t ra_end = (uint32_t)(ya + rows) * Wb;
+        uint32_t ra = (uint32_t)(ya + 2 * r0) * Wb, j0 = (uint32_t)jc0 << 4;
+        for (; ra < ra_end;) {
+            const uint32_t rb = ra + (uint32_t)db * Wb;
+            const ChunkOff<0> fa(ra, j0, Wb, last);
+            const ChunkOff<1> fb(rb, j0, Wb, last);
+            const ChunkIn A = chunk_load<NT>(own, oth, fa.oo, fa.uo, fa.dof, fa.eo);
+            const ChunkIn B = chunk_load<NT>(own, oth, fb.oo, fb.uo, fb.dof, fb.eo);
+            ising_compute<0, REC, NT>(A, own, fa.oo, p, rid, k0, k1, thr, ia);
+            ising_compute<1, REC, NT>(B, own, fb.oo, p, rid, k0, k1, thr, ia);
+            ra += dro;
+            j0 += dj0;
+            if (j0 >= Wb) {
+                j0 -= Wb;
+                ra += W2;
             }
         }
     } else {
 #pragma unroll
         for (int par = 0; par < 2; ++par) {
             const int yf = par == 0 ? ya : yb;
-            int r = r0, jc = jc0;
-            for (int it = tid; it < items; it += nthr) {
-                const int j0 = jc << 4;
-                const uint32_t ro = (uint32_t)(yf + 2 * r) * (uint32_t)W;
-                const uint32_t rom = ro == 0u ? last : ro - (uint32_t)W;
-                const uint32_t rop = ro == last ? 0u : ro + (uint32_t)W;
+            const uint32_t ro_end = (uint32_t)(yf + rows) * Wb;
+            uint32_t ro = (uint32_t)(yf + 2 * r0) * Wb, j0 = (uint32_t)jc0 << 4;
+            for (; ro < ro_end;) {
                 if (par == 0) {
-                    const ChunkIn A = chunk_load<0, NT>(own, oth, W, ro, rom, rop, j0);
-                    ising_compute<0, REC, NT>(A, own, ro, j0, p, rid, k0, k1, thr, ia);
+                    const ChunkOff<0> f(ro, j0, Wb, last);
+                    const ChunkIn A = chunk_load<NT>(own, oth, f.oo, f.uo, f.dof, f.eo);
+                    ising_compute<0, REC, NT>(A, own, f.oo, p, rid, k0, k1, thr, ia);
                 } else {
-                    const ChunkIn B = chunk_load<1, NT>(own, oth, W, ro, rom, rop, j0);
-                    ising_compute<1, REC, NT>(B, own, ro, j0, p, rid, k0, k1, thr, ia);
+                    const ChunkOff<1> f(ro, j0, Wb, last);
+                    const ChunkIn B = chunk_load<NT>(own, oth, f.oo, f.uo, f.dof, f.eo);
+                    ising_compute<1, REC, NT>(B, own, f.oo, p, rid, k0, k1, thr, ia);
                 }
-                r += dr;
-                jc += dj;
-                if (jc >= cpr) {
-                    jc -= cpr;
-                    ++r;
+                ro += dro;
+                j0 += dj0;
+                if (j0 >= Wb) {
+                    j0 -= Wb;
+                    ro += W2;
                 }
             }
         }
