@@ -392,7 +392,7 @@ def msc_probe(Sampler, torch, n_groups=256, L=256, sweeps=200):
     gbs = per_launch * 0.375 / avg_s / 1e9
     return {"config": f"{n_groups} groups x 32 replicas of {L}x{L} (shared random words), "
                       f"beta 0.4407, {sweeps} sweeps",
-            "attempts_per_ns": round(attempts * sweeps / (ms * 1e6), 1), "kernel": "k_msc_pass8",
+            "attempts_per_ns": round(attempts * sweeps / (ms * 1e6), 1), "kernel": "k_msc_pass4",
             "avg_launch_us": round(avg_s * 1e6, 2),
             "kernel_attempts_per_ns": round(per_launch / avg_s / 1e9, 1),
             "GBs_algorithmic": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}

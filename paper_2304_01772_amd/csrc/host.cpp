@@ -687,6 +687,22 @@ int spinmc_sweep_counter(const spinmc_ctx* c, uint64_t* t) {
     return SPINMC_OK;
 }
 
+// Multispin-coded words between the natural order y Lx + x (host buffers)
+// and the device's colour planes (site (y, x) at word (y, x >> 1) of plane
+// (x + y) & 1, planes of Ly rows by Lx / 2 words).
+static void msc_permute(int Lx, int Ly, const uint32_t* src, uint32_t* dst, bool to_planes) {
+    const size_t W = (size_t)Lx / 2;
+    for (int y = 0; y < Ly; ++y)
+        for (int x = 0; x < Lx; ++x) {
+            const size_t nat = (size_t)y * Lx + x;
+            const size_t pl = (size_t)((x + y) & 1) * Ly * W + (size_t)y * W + (x >> 1);
+            if (to_planes)
+                dst[pl] = src[nat];
+            else
+                dst[nat] = src[pl];
+        }
+}
+
 int spinmc_set_state(spinmc_ctx* c, int32_t r, const void* host, size_t bytes) {
     if (!c || !host) return fail(SPINMC_E_INVALID, "set_state: null argument");
     if (c->poisoned) return fail(SPINMC_E_DEVICE, "set_state: context poisoned");
@@ -696,9 +712,11 @@ int spinmc_set_state(spinmc_ctx* c, int32_t r, const void* host, size_t bytes) {
         if (r >= (int)c->reps.size()) return fail(SPINMC_E_INVALID, "set_state: group out of range");
         const HostRep& h = c->reps[r];
         if (bytes != h.lat_bytes) return fail(SPINMC_E_INVALID, "set_state: wrong byte count");
+        std::vector<uint32_t> planes((size_t)h.dev.Lx * h.dev.Ly);
+        msc_permute(h.dev.Lx, h.dev.Ly, (const uint32_t*)host, planes.data(), true);
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e == hipSuccess)
-            e = hipMemcpy(c->d_lat + h.dev.lat_off, host, bytes, hipMemcpyHostToDevice);
+            e = hipMemcpy(c->d_lat + h.dev.lat_off, planes.data(), bytes, hipMemcpyHostToDevice);
         return check_dev(c, e, "set_state");
     }
     if (c->tri) return tri_set_state(c, r, host, bytes);
@@ -737,9 +755,11 @@ int spinmc_get_state(spinmc_ctx* c, int32_t r, void* host, size_t bytes) {
         if (r >= (int)c->reps.size()) return fail(SPINMC_E_INVALID, "get_state: group out of range");
         const HostRep& h = c->reps[r];
         if (bytes != h.lat_bytes) return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
+        std::vector<uint32_t> planes((size_t)h.dev.Lx * h.dev.Ly);
         hipError_t e = hipStreamSynchronize(c->stream);
         if (e == hipSuccess)
-            e = hipMemcpy(host, c->d_lat + h.dev.lat_off, bytes, hipMemcpyDeviceToHost);
+            e = hipMemcpy(planes.data(), c->d_lat + h.dev.lat_off, bytes, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) msc_permute(h.dev.Lx, h.dev.Ly, planes.data(), (uint32_t*)host, false);
         return check_dev(c, e, "get_state");
     }
     if (c->tri) return tri_get_state(c, r, host, bytes);

@@ -10,7 +10,7 @@ constexpr int kMscClasses = 18;  // 9 [s > 0] + 3 (Sx/2 + 1) + (Sy/2 + 1)
 
 struct MscArgs {
     const RepDev* reps;       // per group: Lx, Ly, rid, lat_off (bytes)
-    uint32_t* lat;            // packed words, natural row-major per group
+    uint32_t* lat;            // packed words, two colour planes per group
     const uint64_t* tab;      // [G][18] thresholds (2^32 = always)
     const uint64_t* t_base;   // device sweep counter
     int32_t* stats;           // [rows][32 G][width]

@@ -1,9 +1,12 @@
 // Multispin-coded square-lattice Ising (1-bit spins): 32 replicas with the
 // same lattice shape, couplings, field and temperature packed bit by bit in
-// one uint32 per site (bit b = 1 is s = +1 in replica b), natural row-major
-// layout.  The replicas share the random numbers, so one Philox word decides
-// 32 attempts: in pass p = 2t + c (colour c = (x + y) & 1) the site n with
-// within-colour index k = n >> 1 takes W = word k & 3 of block
+// one uint32 per site (bit b = 1 is s = +1 in replica b).  On the device a
+// group's words sit in two colour planes, as the byte planes of the square
+// lattice: site (y, x) is word (y, x >> 1) of plane (x + y) & 1, each plane
+// Ly rows of W = Lx / 2 words.  The replicas share the random numbers, so
+// one Philox word decides 32 attempts: in pass p = 2t + c (colour
+// c = (x + y) & 1) the site with within-colour index k = (y Lx + x) >> 1 --
+// its plane word index y W + (x >> 1) -- takes W = word k & 3 of block
 // (k >> 2, p, rid, 0), and every bit whose class idx = 9 [s > 0] +
 // 3 (Sx/2 + 1) + (Sy/2 + 1) has W < T[idx] flips (Algorithm 1; the
 // thresholds are the FP64 host table of the square lattice).  The classes of
@@ -12,10 +15,10 @@
 // (vertical) neighbours are ~(a | b), a ^ b and a & b.
 //
 // Lx is a multiple of 8: a lane takes the four sites of one Philox block,
-// the own-colour words of the 8-word row span [x0, x0 + 8); the spans of
-// rows y - 1, y, y + 1 come in as 16-byte loads plus the two halo words of
-// row y, and the own span is written back whole (the other colour's words
-// unchanged; no other lane writes the span in the pass).
+// four consecutive words of a row of plane c, and reads the other plane's
+// same row (its horizontal neighbours, with one halo word on the side of the
+// row parity) and rows y - 1, y + 1 (vertical neighbours) as 16-byte loads;
+// only the own plane is written.
 #include "msc_internal.hpp"
 
 namespace spinmc {
@@ -23,20 +26,14 @@ namespace spinmc {
 namespace {
 constexpr uint32_t kMscTagMain = 0u, kMscTagInit = 2u;
 
-struct Span32 {
-    uint4 a, b;
-};
-
-__device__ __forceinline__ Span32 ld_span(const uint32_t* p) {
-    return Span32{*reinterpret_cast<const uint4*>(p), *reinterpret_cast<const uint4*>(p + 4)};
-}
-
 __device__ __forceinline__ uint32_t e4(const uint4& v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
 
-__device__ __forceinline__ uint32_t el(const Span32& s, int i) {
-    return i < 4 ? e4(s.a, i) : e4(s.b, i - 4);
+// Word index of site (y, x) of a group's lattice in its colour planes.
+__device__ __forceinline__ size_t plane_word(int y, int x, int Lx, int Ly) {
+    const int W = Lx >> 1;
+    return (size_t)((x + y) & 1) * Ly * W + (size_t)y * W + (x >> 1);
 }
 }  // namespace
 
@@ -55,11 +52,16 @@ __global__ void __launch_bounds__(256) k_msc_init(MscArgs a) {
     }
     uint32_t* lat = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(a.lat) + D.lat_off);
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-        if (4 * q + u < n) lat[4 * q + u] = v[u];
+    for (int u = 0; u < 4; ++u) {
+        const int i = 4 * q + u;
+        if (i < n) {
+            const int y = i / D.Lx;
+            lat[plane_word(y, i - y * D.Lx, D.Lx, D.Ly)] = v[u];
+        }
+    }
 }
 
-__global__ void __launch_bounds__(256) k_msc_pass8(MscArgs a, int c, int sweep_off) {
+__global__ void __launch_bounds__(256) k_msc_pass4(MscArgs a, int c, int sweep_off) {
     const int g = blockIdx.y;
     // W < T as a 32-bit compare: W <= T - 1 for 1 <= T <= 2^32, and never
     // for T = 0 (uniform per class: scalar registers and scalar logic)
@@ -73,37 +75,41 @@ __global__ void __launch_bounds__(256) k_msc_pass8(MscArgs a, int c, int sweep_o
         tm1[i] = T == 0 ? 0u : (uint32_t)(T - 1);
     }
     const RepDev D = a.reps[g];
-    const int Lx = D.Lx, Ly = D.Ly;
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= Lx * Ly / 8) return;
-    const int y = (8 * b) / Lx, x0 = 8 * b - y * Lx;
-    const int par = (c + y) & 1;
+    const int Lx = D.Lx, Ly = D.Ly, W = Lx >> 1, qpr = W >> 2;
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;  // Philox block = word (y W + j0) / 4
+    if (b >= Ly * qpr) return;
+    const int y = b / qpr, j0 = 4 * (b - y * qpr);
+    const int par = (c + y) & 1;  // own site of word j: x = 2 j + par
     const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
     uint32_t* lat = reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(a.lat) + D.lat_off);
-    const Span32 S = ld_span(lat + (size_t)y * Lx + x0);
-    const Span32 U = ld_span(lat + (size_t)yu * Lx + x0);
-    const Span32 Dn = ld_span(lat + (size_t)yd * Lx + x0);
-    const uint32_t hl = lat[(size_t)y * Lx + (x0 == 0 ? Lx - 1 : x0 - 1)];
-    const uint32_t hr = lat[(size_t)y * Lx + (x0 + 8 == Lx ? 0 : x0 + 8)];
+    uint32_t* own = lat + (size_t)c * Ly * W;
+    const uint32_t* oth = lat + (size_t)(1 - c) * Ly * W;
+    const uint4 S = *reinterpret_cast<const uint4*>(own + (size_t)y * W + j0);
+    const uint4 M = *reinterpret_cast<const uint4*>(oth + (size_t)y * W + j0);
+    const uint4 U = *reinterpret_cast<const uint4*>(oth + (size_t)yu * W + j0);
+    const uint4 Dn = *reinterpret_cast<const uint4*>(oth + (size_t)yd * W + j0);
+    // the horizontal neighbour outside the four words: word j0 - 1 (par 0)
+    // or j0 + 4 (par 1) of the other plane's row, periodic
+    const uint32_t halo =
+        oth[(size_t)y * W + (par ? (j0 + 4 == W ? 0 : j0 + 4) : (j0 == 0 ? W - 1 : j0 - 1))];
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
     const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
     uint32_t w[4];
     philox4x32_10((uint32_t)b, p, D.rid, kMscTagMain, a.key0, a.key1, w);
-    uint32_t flip[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+    uint32_t nv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const int o = 2 * u;  // the own site is at o + par
-        const uint32_t s = par ? el(S, o + 1) : el(S, o);
-        const uint32_t l = par ? el(S, o) : (o == 0 ? hl : el(S, o - 1));
-        const uint32_t r = par ? (o + 2 == 8 ? hr : el(S, o + 2)) : el(S, o + 1);
-        const uint32_t up = par ? el(U, o + 1) : el(U, o);
-        const uint32_t dn = par ? el(Dn, o + 1) : el(Dn, o);
+        const uint32_t s = e4(S, u);
+        // left (x - 1) and right (x + 1) neighbours: words j - 1 + par and j + par
+        const uint32_t l = par ? e4(M, u) : (u == 0 ? halo : e4(M, u - 1));
+        const uint32_t r = par ? (u == 3 ? halo : e4(M, u + 1)) : e4(M, u);
+        const uint32_t up = e4(U, u), dn = e4(Dn, u);
         // agreeing neighbours per bit
         const uint32_t al = ~(s ^ l), ar = ~(s ^ r), au = ~(s ^ up), ad = ~(s ^ dn);
         const uint32_t ax[3] = {~(al | ar), al ^ ar, al & ar};
         const uint32_t ay[3] = {~(au | ad), au ^ ad, au & ad};
         // for s = +1, Sx/2 + 1 is the agreeing count; for s = -1, 2 minus it
-        const uint32_t W = w[u];
+        const uint32_t Wd = w[u];
         uint32_t fp = 0u, fn = 0u;
 #pragma unroll
         for (int i = 0; i < 3; ++i)
@@ -111,25 +117,12 @@ __global__ void __launch_bounds__(256) k_msc_pass8(MscArgs a, int c, int sweep_o
             for (int j = 0; j < 3; ++j) {
                 const uint32_t m = ax[i] & ay[j];
                 const int cp = 9 + 3 * i + j, cn = 3 * (2 - i) + (2 - j);
-                fp |= (W <= tm1[cp] && !never[cp]) ? m : 0u;
-                fn |= (W <= tm1[cn] && !never[cn]) ? m : 0u;
+                fp |= (Wd <= tm1[cp] && !never[cp]) ? m : 0u;
+                fn |= (Wd <= tm1[cn] && !never[cn]) ? m : 0u;
             }
-        flip[o] = (s & fp) | (~s & fn);
+        nv[u] = s ^ ((s & fp) | (~s & fn));
     }
-    // the own words sit at odd offsets when par = 1
-    uint32_t f[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) f[i] = 0u;
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        f[2 * u] = par ? 0u : flip[2 * u];
-        f[2 * u + 1] = par ? flip[2 * u] : 0u;
-    }
-    uint32_t* out = lat + (size_t)y * Lx + x0;
-    *reinterpret_cast<uint4*>(out) =
-        make_uint4(S.a.x ^ f[0], S.a.y ^ f[1], S.a.z ^ f[2], S.a.w ^ f[3]);
-    *reinterpret_cast<uint4*>(out + 4) =
-        make_uint4(S.b.x ^ f[4], S.b.y ^ f[5], S.b.z ^ f[6], S.b.w ^ f[7]);
+    *reinterpret_cast<uint4*>(own + (size_t)y * W + j0) = make_uint4(nv[0], nv[1], nv[2], nv[3]);
 }
 
 // Per bit b: M = 2 ones - N, Bx = N - 2 (ones of s ^ right), By likewise;
@@ -149,9 +142,9 @@ __global__ void __launch_bounds__(256) k_msc_stats(MscArgs a, int rec_row) {
         const bool in = i < n;
         if (in) {
             const int y = i / Lx, x = i - y * Lx;
-            s = lat[i];
-            xr = s ^ lat[(size_t)y * Lx + (x + 1 == Lx ? 0 : x + 1)];
-            xd = s ^ lat[(size_t)(y + 1 == Ly ? 0 : y + 1) * Lx + x];
+            s = lat[plane_word(y, x, Lx, Ly)];
+            xr = s ^ lat[plane_word(y, x + 1 == Lx ? 0 : x + 1, Lx, Ly)];
+            xd = s ^ lat[plane_word(y + 1 == Ly ? 0 : y + 1, x, Lx, Ly)];
         }
         for (int bit = 0; bit < 32; ++bit) {
             const int c0 = __popcll(__ballot(in && ((s >> bit) & 1u)));
@@ -186,7 +179,7 @@ hipError_t launch_msc_init(const MscArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_msc_pass(const MscArgs& a, int c, int sweep_off, hipStream_t s) {
-    hipLaunchKernelGGL(k_msc_pass8, dim3((a.max_blocks + 255) / 256, a.G), dim3(256), 0, s, a, c,
+    hipLaunchKernelGGL(k_msc_pass4, dim3((a.max_blocks + 255) / 256, a.G), dim3(256), 0, s, a, c,
                        sweep_off);
     return hipGetLastError();
 }
