@@ -358,7 +358,7 @@ def hc_probe(Sampler, torch, n_rep=256, L=32, sweeps=200):
             "attempts_per_ns": round(sites * sweeps / (ms * 1e6), 1),
             "recorded_attempts_per_ns": round(sites * sweeps / (ms_rec * 1e6), 1),
             "kernel": "k_nat_resident (lattices in LDS)",
-            "stream_pass": {"kernel": "k_hc_pass8", "avg_launch_us": round(avg_s * 1e6, 2),
+            "stream_pass": {"kernel": "k_hc_pass4", "avg_launch_us": round(avg_s * 1e6, 2),
                             "attempts_per_ns": round(sites / 2 / avg_s / 1e9, 1),
                             "GBs_algorithmic": round(gbs, 1),
                             "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}}

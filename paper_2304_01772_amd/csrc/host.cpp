@@ -2384,14 +2384,38 @@ int create_tri(const spinmc_replica_desc* d, int n, uint64_t seed, int init, voi
     return SPINMC_OK;
 }
 
+// Chain / square / cubic spins between the natural order (z Ly + y) Lx + x
+// of host buffers and the device's colour planes (site (z, y, x) at byte
+// (z Ly + y, x >> 1) of plane (x + y + z) & 1, planes of Ly Lz rows by Lx / 2).
+static void hc_permute(const RepDev& d, const int8_t* src, int8_t* dst, bool to_planes) {
+    const size_t W = (size_t)d.Lx / 2, psz = (size_t)d.Ly * d.q * W;
+    for (int z = 0; z < d.q; ++z)
+        for (int y = 0; y < d.Ly; ++y)
+            for (int x = 0; x < d.Lx; ++x) {
+                const size_t row = (size_t)z * d.Ly + y;
+                const size_t nat = row * d.Lx + x;
+                const size_t pl = (size_t)((x + y + z) & 1) * psz + row * W + (x >> 1);
+                if (to_planes)
+                    dst[pl] = src[nat];
+                else
+                    dst[nat] = src[pl];
+            }
+}
+
 int tri_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes) {
     const HostRep& h = c->reps[r];
     if (bytes != h.lat_bytes) return fail(SPINMC_E_INVALID, "set_state: wrong byte count");
     const int8_t* v = (const int8_t*)host;
     for (size_t i = 0; i < bytes; ++i)
         if (v[i] != 1 && v[i] != -1) return fail(SPINMC_E_INVALID, "set_state: Ising spins must be +-1");
+    std::vector<int8_t> planes;
+    if (h.dev.model == kModelIsingHC) {
+        planes.resize(bytes);
+        hc_permute(h.dev, v, planes.data(), true);
+        v = planes.data();
+    }
     hipError_t e = hipStreamSynchronize(c->stream);
-    if (e == hipSuccess) e = hipMemcpy(c->d_lat + h.dev.lat_off, host, bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->d_lat + h.dev.lat_off, v, bytes, hipMemcpyHostToDevice);
     return check_dev(c, e, "set_state");
 }
 
@@ -2399,7 +2423,14 @@ int tri_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
     const HostRep& h = c->reps[r];
     if (bytes != h.lat_bytes) return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
     hipError_t e = hipStreamSynchronize(c->stream);
-    if (e == hipSuccess) e = hipMemcpy(host, c->d_lat + h.dev.lat_off, bytes, hipMemcpyDeviceToHost);
+    if (h.dev.model == kModelIsingHC) {
+        std::vector<int8_t> planes(bytes);
+        if (e == hipSuccess)
+            e = hipMemcpy(planes.data(), c->d_lat + h.dev.lat_off, bytes, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) hc_permute(h.dev, planes.data(), (int8_t*)host, false);
+    } else if (e == hipSuccess) {
+        e = hipMemcpy(host, c->d_lat + h.dev.lat_off, bytes, hipMemcpyDeviceToHost);
+    }
     return check_dev(c, e, "get_state");
 }
 

@@ -1,6 +1,6 @@
-// Internal declarations of the natural-layout Ising kernels: the triangular
-// lattice and the chain / square / simple-cubic lattices.  Not part of the
-// C ABI.
+// Internal declarations of the triangular-lattice (natural layout) and the
+// chain / square / simple-cubic (two colour planes) Ising kernels.  Not part
+// of the C ABI.
 #pragma once
 #include "spinmc_internal.hpp"
 
@@ -12,7 +12,8 @@ constexpr int kTriClasses = 14;  // 7 [s > 0] + (S6 + 6) / 2
 
 struct TriArgs {
     const RepDev* reps;       // Lx, Ly, rid, lat_off (bytes), Jx = J, h
-    int8_t* lat;              // natural row-major int8 spins, +-1
+    int8_t* lat;              // int8 spins +-1: triangular natural row-major, chain /
+                              // cubic in two colour planes of Ly Lz rows by Lx / 2
     const uint64_t* tab;      // [R][14] thresholds (2^32 = always)
     const uint64_t* t_base;   // device sweep counter
     int32_t* stats;           // [rows][R][width]

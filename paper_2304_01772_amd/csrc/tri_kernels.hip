@@ -20,6 +20,15 @@ namespace {
 constexpr uint32_t kTriTagMain = 0u, kTriTagInit = 2u;
 
 __device__ __forceinline__ int wrapt(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Chain / square / cubic lattices sit in two colour planes on the device:
+// site (z, y, x) of row z Ly + y is byte (row, x >> 1) of plane
+// (x + y + z) & 1, each plane Ly Lz rows of W = Lx / 2 bytes.  The byte's
+// offset in its plane is the site's within-colour index k = (row Lx + x) >> 1.
+__device__ __forceinline__ size_t hc_byte(int z, int y, int x, int Lx, int Ly, int Lz) {
+    const size_t W = (size_t)(Lx >> 1);
+    return (size_t)((x + y + z) & 1) * Ly * Lz * W + ((size_t)z * Ly + y) * W + (x >> 1);
+}
 }  // namespace
 
 // Initial spins from the init stream of the Ising model: site n = y Lx + x
@@ -33,8 +42,17 @@ __global__ void __launch_bounds__(256) k_tri_init(TriArgs a) {
     philox4x32_10((uint32_t)b, 0u, D.rid, kTriTagInit, a.key0, a.key1, w);
     int8_t* lat = a.lat + D.lat_off;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-        if (4 * b + u < n) lat[4 * b + u] = w[u] < 0x80000000u ? (int8_t)1 : (int8_t)-1;
+    for (int u = 0; u < 4; ++u) {
+        const int i = 4 * b + u;
+        if (i >= n) break;
+        const int8_t v = w[u] < 0x80000000u ? (int8_t)1 : (int8_t)-1;
+        if (D.model == kModelIsingHC) {
+            const int row = i / D.Lx, x = i - row * D.Lx, z = row / D.Ly;
+            lat[hc_byte(z, row - z * D.Ly, x, D.Lx, D.Ly, D.q)] = v;
+        } else {
+            lat[i] = v;
+        }
+    }
 }
 
 __global__ void __launch_bounds__(256) k_tri_pass(TriArgs a, int c, int sweep_off) {
@@ -142,9 +160,10 @@ __device__ __forceinline__ void tri_span(uint32_t (&S)[3], const uint32_t (&U)[3
     }
 }
 
-// Chain / square / cubic: S the 8-byte span [x0, x0 + 8) of the own row, the
-// own sites x0 + 2u + par; N0, N1 the added flags of the neighbouring rows
-// and planes over the span; hl, hr the flags of (x0 - 1) and (x0 + 8).
+// Chain / square / cubic in natural layout (the lattice the LDS-resident
+// kernel holds): S the 8-byte span [x0, x0 + 8) of the own row, the own
+// sites x0 + 2u + par; N0, N1 the added flags of the neighbouring rows and
+// planes over the span; hl, hr the flags of (x0 - 1) and (x0 + 8).
 __device__ __forceinline__ void hc_span(uint32_t (&S)[2], uint32_t N0, uint32_t N1, uint32_t hl,
                                         uint32_t hr, uint32_t par, const uint32_t (&w)[4],
                                         const uint64_t* lt) {
@@ -159,6 +178,25 @@ __device__ __forceinline__ void hc_span(uint32_t (&S)[2], uint32_t N0, uint32_t 
     const uint32_t e0 = 0xFEu << o0, e1 = 0xFEu << o1;
     S[0] ^= (f0 ? e0 : 0u) | (f1 ? e1 : 0u);
     S[1] ^= (f2 ? e0 : 0u) | (f3 ? e1 : 0u);
+}
+
+// Chain / square / cubic on the colour planes: S the four own bytes (plane
+// bytes j0 .. j0 + 3 of a row, own sites x = 2 j + par), N the added -1 flags
+// of the vertical partners (the other plane's rows y +- 1 and z +- 1, same
+// bytes), M the other plane's word of the same row and hf the -1 flag of its
+// halo byte (j0 - 1 for par = 0, j0 + 4 for par = 1): the horizontal partners
+// of own byte j are the other plane's bytes j - 1 + par and j + par.
+__device__ __forceinline__ uint32_t hc_word(uint32_t S, uint32_t N, uint32_t M, uint32_t hf,
+                                            uint32_t par, const uint32_t (&w)[4],
+                                            const uint64_t* lt) {
+    const uint32_t mf = M & kNegFlag;
+    const uint32_t H = mf + (par ? abyte(hf, mf, 1) : abyte(mf, hf << 24, 3));
+    const uint32_t K = (N + H) | ((S & kNegFlag) << 3);  // 2n + 16 [s < 0] per byte
+    uint32_t F = 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        F |= (uint64_t)w[u] < lt[(K >> (8 * u + 1)) & 15u] ? 0xFEu << (8 * u) : 0u;
+    return S ^ F;  // a flip negates the byte: s -> -s is s ^ 0xFE for s = +-1
 }
 
 // b / d for 0 <= b < 2^22, d >= 1: the FP32 estimate b (1/d) is within one
@@ -281,95 +319,92 @@ __global__ void __launch_bounds__(256) k_tri_stats(TriArgs a, int rec_row) {
     }
 }
 
-// Chain / square / simple cubic (Lz = D.q): the colour-c site of the pair
-// (2k, 2k + 1) -- both in one row since Lx is even -- for the four k of a
-// Philox block; neighbours x +- 1 and, where the extent exceeds 1, y +- 1 and
-// z +- 1.
+// Chain / square / simple cubic (Lz = D.q) on the colour planes: the
+// colour-c site with within-colour index k -- byte k of plane c -- for the
+// four k of a Philox block; neighbours x +- 1 and, where the extent exceeds
+// 1, y +- 1 and z +- 1, all in the other plane.
 __global__ void __launch_bounds__(256) k_hc_pass(TriArgs a, int c, int sweep_off) {
     __shared__ uint64_t lt[kTriClasses];
     const int r = blockIdx.y;
     if (threadIdx.x < kTriClasses) lt[threadIdx.x] = a.tab[(size_t)r * kTriClasses + threadIdx.x];
     __syncthreads();
     const RepDev D = a.reps[r];
-    const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, plane = Lx * Ly;
-    const int nk = plane * Lz / 2;
+    const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, W = Lx >> 1;
+    const int nk = Ly * Lz * W;
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (4 * b >= nk) return;
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
     const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
     uint32_t w[4];
     philox4x32_10((uint32_t)b, p, D.rid, kTriTagMain, a.key0, a.key1, w);
-    int8_t* lat = a.lat + D.lat_off;
+    int8_t* own = a.lat + D.lat_off + (size_t)c * nk;
+    const int8_t* oth = a.lat + D.lat_off + (size_t)(1 - c) * nk;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const int k = 4 * b + u;
         if (k >= nk) break;
-        const int row = (2 * k) / Lx;  // z Ly + y
+        const int row = k / W, j = k - row * W;  // row = z Ly + y
         const int z = row / Ly, y = row - z * Ly;
-        const int x = 2 * k - row * Lx + ((c + y + z) & 1);
-        const size_t rb = (size_t)row * Lx;
-        const int s = lat[rb + x];
-        int S = lat[rb + wrapt(x - 1, Lx)] + lat[rb + wrapt(x + 1, Lx)];
+        const int x = 2 * j + ((c + y + z) & 1);
+        const size_t rb = (size_t)row * W;
+        const int s = own[k];
+        int S = oth[rb + (wrapt(x - 1, Lx) >> 1)] + oth[rb + (wrapt(x + 1, Lx) >> 1)];
         if (Ly > 1)
-            S += lat[(size_t)(z * Ly + wrapt(y - 1, Ly)) * Lx + x] +
-                 lat[(size_t)(z * Ly + wrapt(y + 1, Ly)) * Lx + x];
+            S += oth[(size_t)(z * Ly + wrapt(y - 1, Ly)) * W + j] +
+                 oth[(size_t)(z * Ly + wrapt(y + 1, Ly)) * W + j];
         if (Lz > 1)
-            S += lat[(size_t)wrapt(z - 1, Lz) * plane + (size_t)y * Lx + x] +
-                 lat[(size_t)wrapt(z + 1, Lz) * plane + (size_t)y * Lx + x];
+            S += oth[(size_t)(wrapt(z - 1, Lz) * Ly + y) * W + j] +
+                 oth[(size_t)(wrapt(z + 1, Lz) * Ly + y) * W + j];
         const int idx = 7 * (s > 0) + (S + 6) / 2;
-        if ((uint64_t)w[u] < lt[idx]) lat[rb + x] = (int8_t)(-s);
+        if ((uint64_t)w[u] < lt[idx]) own[k] = (int8_t)(-s);
     }
 }
 
-// Lx a multiple of 8: the four sites of a Philox block are the colour-c
-// bytes of one 8-byte row span [x0, x0 + 8), offsets o = 2u + par with
-// par = (c + y + z) & 1; the spans of the neighbouring rows (y +- 1) and
-// planes (z +- 1) come in as dword pairs, plus the halo bytes x0 - 1 and
-// x0 + 8 of the own row.  The own span is written back whole (its other
-// colour's bytes unchanged; no other lane writes it during the pass).
+// Lx a multiple of 8: the four sites of a Philox block are four consecutive
+// bytes j0 .. j0 + 3 of a row of plane c (plane rows of W = Lx / 2 bytes, so
+// a row holds W / 4 blocks); the other plane's word of the same row plus one
+// halo byte, and its words of rows y +- 1 and z +- 1, come in as dwords, and
+// only the own word is stored.  A lane takes NB Philox blocks, 256 apart, as
+// k_tri_pass12.
 template <int NB>
-__global__ void __launch_bounds__(256) k_hc_pass8(TriArgs a, int c, int sweep_off, int gx) {
+__global__ void __launch_bounds__(256) k_hc_pass4(TriArgs a, int c, int sweep_off, int gx) {
     __shared__ uint64_t lt[16];
     const int wl = xcd_logical((int)blockIdx.x, (int)gridDim.x);  // see k_tri_pass12
     const int r = wl / gx, wx = wl - r * gx;
     const RepDev D = a.reps[r];
-    const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, plane = Lx * Ly;
-    const int nb = plane * Lz / 8;
+    const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, W = Lx >> 1, qpr = W >> 2;
+    const int nb = Ly * Lz * qpr;  // Philox blocks per pass: Lx Ly Lz / 8
     const int bt = NB * wx * 256 + (int)threadIdx.x;  // block k: bt + 256 k
     if (NB * wx * 256 >= nb) return;  // whole workgroup past the end
-    const bool small = 8 * (int64_t)nb < (1 << 22);
-    int8_t* lat = a.lat + D.lat_off;
-    uint32_t S[NB][2], N0[NB], N1[NB], hl[NB], hr[NB], own[NB], par[NB];
+    const bool small = nb < (1 << 22);
+    // 32-bit offsets from the replica's base (a lattice below 2^31 bytes)
+    const uint32_t psz = (uint32_t)(Ly * Lz) * (uint32_t)W;  // bytes per plane
+    int8_t* own = a.lat + D.lat_off + (c ? psz : 0u);
+    const int8_t* oth = a.lat + D.lat_off + (c ? 0u : psz);
+    uint32_t S[NB], N[NB], M[NB], hf[NB], off[NB], par[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
         const int b = bt + 256 * k < nb ? bt + 256 * k : nb - 1;  // see k_tri_pass12
-        const int row = qdiv(8 * b, Lx, small);        // z Ly + y
+        const int row = qdiv(b, qpr, small);  // z Ly + y
+        const int j0 = 4 * (b - (int)__umul24((uint32_t)row, (uint32_t)qpr));
         const int z = qdiv(row, Ly, small), y = row - (int)__umul24((uint32_t)z, (uint32_t)Ly);
-        // 32-bit offsets from the replica's base (a lattice below 2^31 bytes)
-        const uint32_t orow = (uint32_t)row * (uint32_t)Lx;
-        const int x0 = 8 * b - (int)orow;
-        own[k] = orow + x0;
-        const uint2 S2 = ld64(lat + own[k]);
-        S[k][0] = S2.x;
-        S[k][1] = S2.y;
-        hl[k] = negflag(lat + (orow + (x0 == 0 ? Lx - 1 : x0 - 1)));
-        hr[k] = negflag(lat + (orow + (x0 + 8 == Lx ? 0 : x0 + 8)));
-        N0[k] = N1[k] = 0u;
+        const uint32_t ro = (uint32_t)row * (uint32_t)W;
+        off[k] = ro + (uint32_t)j0;
+        par[k] = (uint32_t)((c + y + z) & 1);
+        S[k] = ld32(own + off[k]);
+        M[k] = ld32(oth + off[k]);
+        const int hb = par[k] ? (j0 + 4 == W ? 0 : j0 + 4) : (j0 == 0 ? W - 1 : j0 - 1);
+        hf[k] = negflag(oth + (ro + (uint32_t)hb));
+        N[k] = 0u;
         if (Ly > 1) {
             const uint32_t zr = (uint32_t)(z * Ly);
-            const uint2 vu = ld64(lat + ((zr + wrapt(y - 1, Ly)) * (uint32_t)Lx + x0));
-            const uint2 vd = ld64(lat + ((zr + wrapt(y + 1, Ly)) * (uint32_t)Lx + x0));
-            N0[k] += (vu.x & kNegFlag) + (vd.x & kNegFlag);
-            N1[k] += (vu.y & kNegFlag) + (vd.y & kNegFlag);
+            N[k] += (ld32(oth + ((zr + wrapt(y - 1, Ly)) * (uint32_t)W + j0)) & kNegFlag) +
+                    (ld32(oth + ((zr + wrapt(y + 1, Ly)) * (uint32_t)W + j0)) & kNegFlag);
         }
         if (Lz > 1) {
-            const uint32_t in_plane = own[k] - (uint32_t)(z * plane);
-            const uint2 vu = ld64(lat + ((uint32_t)(wrapt(z - 1, Lz) * plane) + in_plane));
-            const uint2 vd = ld64(lat + ((uint32_t)(wrapt(z + 1, Lz) * plane) + in_plane));
-            N0[k] += (vu.x & kNegFlag) + (vd.x & kNegFlag);
-            N1[k] += (vu.y & kNegFlag) + (vd.y & kNegFlag);
+            N[k] += (ld32(oth + ((uint32_t)(wrapt(z - 1, Lz) * Ly + y) * (uint32_t)W + j0)) & kNegFlag) +
+                    (ld32(oth + ((uint32_t)(wrapt(z + 1, Lz) * Ly + y) * (uint32_t)W + j0)) & kNegFlag);
         }
-        par[k] = (uint32_t)((c + y + z) & 1);
     }
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
     const uint32_t p = (uint32_t)(2 * t + (uint64_t)c);
@@ -383,8 +418,8 @@ __global__ void __launch_bounds__(256) k_hc_pass8(TriArgs a, int c, int sweep_of
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        hc_span(S[k], N0[k], N1[k], hl[k], hr[k], par[k], w[k], lt);
-        if (bt + 256 * k < nb) *reinterpret_cast<uint2*>(lat + own[k]) = make_uint2(S[k][0], S[k][1]);
+        const uint32_t v = hc_word(S[k], N[k], M[k], hf[k], par[k], w[k], lt);
+        if (bt + 256 * k < nb) *reinterpret_cast<uint32_t*>(own + off[k]) = v;
     }
 }
 
@@ -392,17 +427,17 @@ __global__ void __launch_bounds__(256) k_hc_pass8(TriArgs a, int c, int sweep_of
 __global__ void __launch_bounds__(256) k_hc_stats(TriArgs a, int rec_row) {
     const int r = blockIdx.y;
     const RepDev D = a.reps[r];
-    const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, plane = Lx * Ly, n = plane * Lz;
+    const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, n = Lx * Ly * Lz;
     const int8_t* lat = a.lat + D.lat_off;
     int M = 0, Bx = 0, By = 0, Bz = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int row = i / Lx, x = i - row * Lx;
         const int z = row / Ly, y = row - z * Ly;
-        const int s = lat[i];
+        const int s = lat[hc_byte(z, y, x, Lx, Ly, Lz)];
         M += s;
-        Bx += s * lat[(size_t)row * Lx + wrapt(x + 1, Lx)];
-        if (Ly > 1) By += s * lat[(size_t)(z * Ly + wrapt(y + 1, Ly)) * Lx + x];
-        if (Lz > 1) Bz += s * lat[(size_t)wrapt(z + 1, Lz) * plane + (size_t)y * Lx + x];
+        Bx += s * lat[hc_byte(z, y, wrapt(x + 1, Lx), Lx, Ly, Lz)];
+        if (Ly > 1) By += s * lat[hc_byte(z, wrapt(y + 1, Ly), x, Lx, Ly, Lz)];
+        if (Lz > 1) Bz += s * lat[hc_byte(wrapt(z + 1, Lz), y, x, Lx, Ly, Lz)];
     }
     for (int o = 32; o > 0; o >>= 1) {
         M += __shfl_xor(M, o);
@@ -448,6 +483,31 @@ __global__ void k_tri_observables(TriArgs a, double* obs) {
 // iff their xor is 0xFE (7 bits), so a bond sum is sites - 2 popc(v ^ w) / 7
 // with w the word of the bond partners (byte funnel shifts for the x + 1
 // and, on the triangular lattice, the down-left partners).
+// The four sites (z, y, x0 .. x0 + 3) of natural index i = row Lx + x0
+// (x0 % 4 == 0, Lx % 8 == 0) as one natural-order word, and back: sites x0
+// and x0 + 2 are bytes (row, x0 / 2) and (row, x0 / 2 + 1) of plane
+// (x0 + y + z) & 1, sites x0 + 1 and x0 + 3 the same bytes of the other plane.
+__device__ __forceinline__ uint32_t hc_natural_word(const int8_t* lat, int i, int Lx, int Ly,
+                                                    int Lz) {
+    const int row = i / Lx, x0 = i - row * Lx, z = row / Ly, y = row - z * Ly;
+    const size_t psz = (size_t)Ly * Lz * (Lx >> 1);
+    const size_t pa = hc_byte(z, y, x0, Lx, Ly, Lz);
+    const size_t pb = ((x0 + y + z) & 1) ? pa - psz : pa + psz;
+    const uint32_t A = *reinterpret_cast<const uint16_t*>(lat + pa);
+    const uint32_t B = *reinterpret_cast<const uint16_t*>(lat + pb);
+    return __builtin_amdgcn_perm(B, A, 0x05010400u);  // bytes A0 B0 A1 B1
+}
+
+__device__ __forceinline__ void hc_store_natural_word(int8_t* lat, int i, uint32_t v, int Lx,
+                                                      int Ly, int Lz) {
+    const int row = i / Lx, x0 = i - row * Lx, z = row / Ly, y = row - z * Ly;
+    const size_t psz = (size_t)Ly * Lz * (Lx >> 1);
+    const size_t pa = hc_byte(z, y, x0, Lx, Ly, Lz);
+    const size_t pb = ((x0 + y + z) & 1) ? pa - psz : pa + psz;
+    *reinterpret_cast<uint16_t*>(lat + pa) = (uint16_t)__builtin_amdgcn_perm(0u, v, 0x0C0C0200u);
+    *reinterpret_cast<uint16_t*>(lat + pb) = (uint16_t)__builtin_amdgcn_perm(0u, v, 0x0C0C0301u);
+}
+
 template <int MODEL>
 __device__ __forceinline__ int4 nat_stats(const int8_t* ls, int Lx, int Ly, int Lz) {
     const int plane = Lx * Ly, nq = (plane * Lz) >> 2;
@@ -497,7 +557,9 @@ __global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps, 
             a.tab + (size_t)r * kTriClasses, threadIdx.x,
             MODEL == kModelIsingHC ? 2 + 2 * (Ly > 1) + 2 * (Lz > 1) : 6);
     for (int i = threadIdx.x; i < n / 4; i += blockDim.x)
-        reinterpret_cast<uint32_t*>(ls)[i] = reinterpret_cast<const uint32_t*>(lat)[i];
+        reinterpret_cast<uint32_t*>(ls)[i] = MODEL == kModelIsingHC
+                                                 ? hc_natural_word(lat, 4 * i, Lx, Ly, Lz)
+                                                 : reinterpret_cast<const uint32_t*>(lat)[i];
     // recorded rows rec0 .. rec0 + n_rows - 1 (1-based) of this launch
     int* lrec = reinterpret_cast<int*>(ls + ((n + 15) & ~15));
     const int rec0 = REC ? sw0 / re + 1 : 0;
@@ -583,8 +645,13 @@ __global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps, 
     if (REC)
         for (int i = threadIdx.x; i < 4 * n_rows; i += blockDim.x)
             a.stats[((size_t)(rec0 - 1 + (i >> 2)) * a.R + r) * a.width + (i & 3)] = lrec[i];
-    for (int i = threadIdx.x; i < n / 4; i += blockDim.x)
-        reinterpret_cast<uint32_t*>(lat)[i] = reinterpret_cast<const uint32_t*>(ls)[i];
+    for (int i = threadIdx.x; i < n / 4; i += blockDim.x) {
+        const uint32_t v = reinterpret_cast<const uint32_t*>(ls)[i];
+        if (MODEL == kModelIsingHC)
+            hc_store_natural_word(lat, 4 * i, v, Lx, Ly, Lz);
+        else
+            reinterpret_cast<uint32_t*>(lat)[i] = v;
+    }
 }
 
 hipError_t launch_nat_resident(const TriArgs& a, int n_sweeps, int sw0, int re, int lds_bytes,
@@ -626,9 +693,9 @@ hipError_t launch_tri_pass(const TriArgs& a, int c, int sweep_off, hipStream_t s
     const dim3 g1((unsigned)gx1 * a.R), g2((unsigned)gx2 * a.R);
     if (a.model == kModelIsingHC && a.all_lx8) {
         if (two)
-            hipLaunchKernelGGL(k_hc_pass8<2>, g2, dim3(256), 0, s, a, c, sweep_off, gx2);
+            hipLaunchKernelGGL(k_hc_pass4<2>, g2, dim3(256), 0, s, a, c, sweep_off, gx2);
         else
-            hipLaunchKernelGGL(k_hc_pass8<1>, g1, dim3(256), 0, s, a, c, sweep_off, gx1);
+            hipLaunchKernelGGL(k_hc_pass4<1>, g1, dim3(256), 0, s, a, c, sweep_off, gx1);
     } else if (a.model == kModelIsingHC)
         hipLaunchKernelGGL(k_hc_pass, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s, a,
                            c, sweep_off);
