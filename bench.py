@@ -317,7 +317,7 @@ def tri_probe(Sampler, torch, n_rep=1024, L=96, sweeps=200):
             "attempts_per_ns": round(sites * sweeps / (ms * 1e6), 1),
             "recorded_attempts_per_ns": round(sites * sweeps / (ms_rec * 1e6), 1),
             "kernel": "k_nat_resident (lattices in LDS)",
-            "stream_pass": {"kernel": "k_tri_pass12", "avg_launch_us": round(avg_s * 1e6, 2),
+            "stream_pass": {"kernel": "k_tri_pass4", "avg_launch_us": round(avg_s * 1e6, 2),
                             "attempts_per_ns": round(per_launch / avg_s / 1e9, 1),
                             "GBs_algorithmic": round(gbs, 1),
                             "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}}

@@ -2402,18 +2402,34 @@ static void hc_permute(const RepDev& d, const int8_t* src, int8_t* dst, bool to_
             }
 }
 
+// Triangular spins between the natural order y Lx + x and the device's three
+// colour planes (site (y, x) at byte (y, x / 3) of plane (x + 2y) mod 3,
+// planes of Ly rows by Lx / 3).
+static void tri_permute(const RepDev& d, const int8_t* src, int8_t* dst, bool to_planes) {
+    const size_t W3 = (size_t)d.Lx / 3, psz = (size_t)d.Ly * W3;
+    for (int y = 0; y < d.Ly; ++y)
+        for (int x = 0; x < d.Lx; ++x) {
+            const size_t nat = (size_t)y * d.Lx + x;
+            const size_t pl = (size_t)((x + 2 * y) % 3) * psz + (size_t)y * W3 + (size_t)(x / 3);
+            if (to_planes)
+                dst[pl] = src[nat];
+            else
+                dst[nat] = src[pl];
+        }
+}
+
 int tri_set_state(spinmc_ctx* c, int r, const void* host, size_t bytes) {
     const HostRep& h = c->reps[r];
     if (bytes != h.lat_bytes) return fail(SPINMC_E_INVALID, "set_state: wrong byte count");
     const int8_t* v = (const int8_t*)host;
     for (size_t i = 0; i < bytes; ++i)
         if (v[i] != 1 && v[i] != -1) return fail(SPINMC_E_INVALID, "set_state: Ising spins must be +-1");
-    std::vector<int8_t> planes;
-    if (h.dev.model == kModelIsingHC) {
-        planes.resize(bytes);
+    std::vector<int8_t> planes(bytes);
+    if (h.dev.model == kModelIsingHC)
         hc_permute(h.dev, v, planes.data(), true);
-        v = planes.data();
-    }
+    else
+        tri_permute(h.dev, v, planes.data(), true);
+    v = planes.data();
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = hipMemcpy(c->d_lat + h.dev.lat_off, v, bytes, hipMemcpyHostToDevice);
     return check_dev(c, e, "set_state");
@@ -2423,13 +2439,14 @@ int tri_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
     const HostRep& h = c->reps[r];
     if (bytes != h.lat_bytes) return fail(SPINMC_E_INVALID, "get_state: wrong byte count");
     hipError_t e = hipStreamSynchronize(c->stream);
-    if (h.dev.model == kModelIsingHC) {
-        std::vector<int8_t> planes(bytes);
-        if (e == hipSuccess)
-            e = hipMemcpy(planes.data(), c->d_lat + h.dev.lat_off, bytes, hipMemcpyDeviceToHost);
-        if (e == hipSuccess) hc_permute(h.dev, planes.data(), (int8_t*)host, false);
-    } else if (e == hipSuccess) {
-        e = hipMemcpy(host, c->d_lat + h.dev.lat_off, bytes, hipMemcpyDeviceToHost);
+    std::vector<int8_t> planes(bytes);
+    if (e == hipSuccess)
+        e = hipMemcpy(planes.data(), c->d_lat + h.dev.lat_off, bytes, hipMemcpyDeviceToHost);
+    if (e == hipSuccess) {
+        if (h.dev.model == kModelIsingHC)
+            hc_permute(h.dev, planes.data(), (int8_t*)host, false);
+        else
+            tri_permute(h.dev, planes.data(), (int8_t*)host, false);
     }
     return check_dev(c, e, "get_state");
 }

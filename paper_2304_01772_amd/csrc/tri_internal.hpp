@@ -1,4 +1,4 @@
-// Internal declarations of the triangular-lattice (natural layout) and the
+// Internal declarations of the triangular (three colour planes) and the
 // chain / square / simple-cubic (two colour planes) Ising kernels.  Not part
 // of the C ABI.
 #pragma once
@@ -12,8 +12,8 @@ constexpr int kTriClasses = 14;  // 7 [s > 0] + (S6 + 6) / 2
 
 struct TriArgs {
     const RepDev* reps;       // Lx, Ly, rid, lat_off (bytes), Jx = J, h
-    int8_t* lat;              // int8 spins +-1: triangular natural row-major, chain /
-                              // cubic in two colour planes of Ly Lz rows by Lx / 2
+    int8_t* lat;              // int8 spins +-1 in colour planes: triangular three of Ly
+                              // rows by Lx / 3, chain / cubic two of Ly Lz rows by Lx / 2
     const uint64_t* tab;      // [R][14] thresholds (2^32 = always)
     const uint64_t* t_base;   // device sweep counter
     int32_t* stats;           // [rows][R][width]

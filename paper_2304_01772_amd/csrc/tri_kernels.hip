@@ -1,13 +1,15 @@
 // Triangular-lattice Ising (the triangular kernels of the Methods): the
 // checkerboard Metropolis chain of Algorithm 1 on the six-neighbour lattice.
 //
-// Sites sit on an Ly x Lx array (int8 spins, natural row-major); the
-// neighbours of (y, x) are (y, x+-1), (y+-1, x), (y-1, x+1) and (y+1, x-1)
-// (periodic), one coupling J for every bond, H = -J sum s s' - h sum s.
-// Three colours c = (x + 2y) mod 3 -- no bond joins two sites of one colour
-// when Lx and Ly are multiples of 3 -- make a sweep of three passes
-// p = 3t + c.  The sites of colour c in row y are x = 3i + (c + y) mod 3; the
-// within-colour index k = y Lx/3 + i selects word k & 3 of Philox4x32-10
+// Sites sit on an Ly x Lx lattice of int8 spins; the neighbours of (y, x)
+// are (y, x+-1), (y+-1, x), (y-1, x+1) and (y+1, x-1) (periodic), one
+// coupling J for every bond, H = -J sum s s' - h sum s.  Three colours
+// c = (x + 2y) mod 3 -- no bond joins two sites of one colour when Lx and Ly
+// are multiples of 3 -- make a sweep of three passes p = 3t + c.  The sites
+// of colour c in row y are x = 3i + (c + y) mod 3; on the device each colour
+// has a plane of Ly rows of Lx/3 bytes, site (y, x) at byte (y, x / 3) of
+// plane (x + 2y) mod 3, so that byte k of plane c is the site with
+// within-colour index k = y Lx/3 + i.  It selects word k & 3 of Philox4x32-10
 // block (k >> 2, p, rid, 0), used whole as W; the flip is accepted iff
 // W < T[7 [s > 0] + (S6 + 6) / 2] with the FP64 host thresholds
 // T = ceil(2^32 exp(-beta 2 s (J S6 + h))) (2^32 when that change is <= 0).
@@ -20,6 +22,12 @@ namespace {
 constexpr uint32_t kTriTagMain = 0u, kTriTagInit = 2u;
 
 __device__ __forceinline__ int wrapt(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Byte of site (y, x) of a triangular lattice in its colour planes.
+__device__ __forceinline__ size_t tri_byte(int y, int x, int Lx, int Ly) {
+    const size_t W3 = (size_t)(Lx / 3);
+    return (size_t)((x + 2 * y) % 3) * Ly * W3 + (size_t)y * W3 + (size_t)(x / 3);
+}
 
 // Chain / square / cubic lattices sit in two colour planes on the device:
 // site (z, y, x) of row z Ly + y is byte (row, x >> 1) of plane
@@ -50,7 +58,8 @@ __global__ void __launch_bounds__(256) k_tri_init(TriArgs a) {
             const int row = i / D.Lx, x = i - row * D.Lx, z = row / D.Ly;
             lat[hc_byte(z, row - z * D.Ly, x, D.Lx, D.Ly, D.q)] = v;
         } else {
-            lat[i] = v;
+            const int y = i / D.Lx;
+            lat[tri_byte(y, i - y * D.Lx, D.Lx, D.Ly)] = v;
         }
     }
 }
@@ -78,13 +87,12 @@ __global__ void __launch_bounds__(256) k_tri_pass(TriArgs a, int c, int sweep_of
         const int x = 3 * (k - y * W3) + (c + y) % 3;
         const int yu = wrapt(y - 1, Ly), yd = wrapt(y + 1, Ly);
         const int xl = wrapt(x - 1, Lx), xr = wrapt(x + 1, Lx);
-        const int8_t* row = lat + (size_t)y * Lx;
-        const int8_t* up = lat + (size_t)yu * Lx;
-        const int8_t* dn = lat + (size_t)yd * Lx;
-        const int s = row[x];
-        const int S6 = row[xl] + row[xr] + up[x] + dn[x] + up[xr] + dn[xl];
+        const int s = lat[(size_t)c * nk + k];
+        const int S6 = lat[tri_byte(y, xl, Lx, Ly)] + lat[tri_byte(y, xr, Lx, Ly)] +
+                       lat[tri_byte(yu, x, Lx, Ly)] + lat[tri_byte(yd, x, Lx, Ly)] +
+                       lat[tri_byte(yu, xr, Lx, Ly)] + lat[tri_byte(yd, xl, Lx, Ly)];
         const int idx = 7 * (s > 0) + (S6 + 6) / 2;
-        if ((uint64_t)w[u] < lt[idx]) lat[(size_t)y * Lx + x] = (int8_t)(-s);
+        if ((uint64_t)w[u] < lt[idx]) lat[(size_t)c * nk + k] = (int8_t)(-s);
     }
 }
 
@@ -218,56 +226,70 @@ __device__ __forceinline__ int xcd_logical(int w, int n) {
 }
 
 __device__ __forceinline__ uint32_t ld32(const int8_t* p) { return *reinterpret_cast<const uint32_t*>(p); }
-__device__ __forceinline__ uint3 ld96(const int8_t* p) { return *reinterpret_cast<const uint3*>(p); }
 __device__ __forceinline__ uint2 ld64(const int8_t* p) { return *reinterpret_cast<const uint2*>(p); }
 __device__ __forceinline__ uint32_t negflag(const int8_t* p) { return (uint32_t)(uint8_t)*p & 2u; }
 }  // namespace
 
-// Lx a multiple of 12: the four sites of a Philox block lie in one row,
-// x = 12 j + xc + 3u (xc = (c + y) mod 3), inside the 12-byte span
-// [12 j, 12 j + 12) of rows y - 1, y, y + 1, which come in as dwords (plus one
-// halo byte at either end of row y, the right one of row y - 1 and the left
-// one of row y + 1).  The row-y span is written back whole: no other lane
-// writes it during the pass, and the other colours' bytes are unchanged.
-// A lane takes NB Philox blocks, 256 apart (a wave's loads of one block
-// index stay contiguous), their loads all in flight together: NB = 2 for
-// large passes (see launch_tri_pass), 1 otherwise.
-// The grid is 1-D: gx workgroups per replica, replica-major in logical order.
+// Lx a multiple of 12: the four sites of a Philox block are four consecutive
+// bytes i0 .. i0 + 3 of row y of plane c (planes of W3 = Lx / 3 bytes per
+// row).  With r = (c + y) mod 3 the six neighbours of own byte i are, in
+// plane c + 1: row y at i + [r = 2] (x + 1), row y - 1 at i (y - 1, x) and
+// row y + 1 at i - [r = 0] (y + 1, x - 1); in plane c + 2: row y at
+// i - [r = 0] (x - 1), row y + 1 at i (y + 1, x) and row y - 1 at
+// i + [r = 2] (y - 1, x + 1) -- six dwords, two of them with a halo byte
+// on the side of the shift.  Only the own dword is stored.  A lane takes NB
+// Philox blocks, 256 apart (a wave's loads of one block index stay
+// contiguous), their loads all in flight together: NB = 2 for large passes
+// (see launch_tri_pass), 1 otherwise.  The grid is 1-D: gx workgroups per
+// replica, replica-major in logical order.
 template <int NB>
-__global__ void __launch_bounds__(256) k_tri_pass12(TriArgs a, int c, int sweep_off, int gx) {
+__global__ void __launch_bounds__(256) k_tri_pass4(TriArgs a, int c, int sweep_off, int gx) {
     __shared__ uint64_t lt[16];
     const int wl = xcd_logical((int)blockIdx.x, (int)gridDim.x);
     const int r = wl / gx, wx = wl - r * gx;
     const RepDev D = a.reps[r];
-    const int Lx = D.Lx, Ly = D.Ly, G = Lx / 12, nb = Ly * G;
+    const int Lx = D.Lx, Ly = D.Ly, W3 = Lx / 3, qpr = W3 >> 2, nb = Ly * qpr;
     const int bt = NB * wx * 256 + (int)threadIdx.x;  // block k: bt + 256 k
     if (NB * wx * 256 >= nb) return;  // whole workgroup past the end
-    int8_t* lat = a.lat + D.lat_off;
     const bool small = nb < (1 << 22);
+    // 32-bit offsets from the replica's base (a lattice below 2^31 bytes)
+    const uint32_t psz = (uint32_t)Ly * (uint32_t)W3;  // bytes per plane
+    const int cp = c == 2 ? 0 : c + 1, cm = c == 0 ? 2 : c - 1;
+    int8_t* own = a.lat + D.lat_off + (uint32_t)c * psz;
+    const int8_t* pp = a.lat + D.lat_off + (uint32_t)cp * psz;
+    const int8_t* pm = a.lat + D.lat_off + (uint32_t)cm * psz;
     // blocks past the end compute the last block and store nothing (every
     // lane reaches the barrier)
-    uint32_t S[NB][3], U[NB][3], Dn[NB][3], hl[NB], hr[NB], orow[NB], x0[NB], xc[NB];
+    uint32_t S[NB], N[NB], off[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
         const int b = bt + 256 * k < nb ? bt + 256 * k : nb - 1;
-        const int y = qdiv(b, G, small);
-        const int x = 12 * (b - (int)__umul24((uint32_t)y, (uint32_t)G));
+        const int y = qdiv(b, qpr, small);
+        const int i0 = 4 * (b - (int)__umul24((uint32_t)y, (uint32_t)qpr));
         const int yu = y == 0 ? Ly - 1 : y - 1, yd = y + 1 == Ly ? 0 : y + 1;
-        const int xl = x == 0 ? Lx - 1 : x - 1, xr = x + 12 == Lx ? 0 : x + 12;
-        // 32-bit offsets from the replica's base (rows and columns below
-        // 2^24, a lattice below 2^31 bytes)
-        const uint32_t o = __umul24((uint32_t)y, (uint32_t)Lx);
-        const uint32_t ou = __umul24((uint32_t)yu, (uint32_t)Lx);
-        const uint32_t od = __umul24((uint32_t)yd, (uint32_t)Lx);
-        const uint3 s3 = ld96(lat + (o + x)), u3 = ld96(lat + (ou + x)), d3 = ld96(lat + (od + x));
-        S[k][0] = s3.x; S[k][1] = s3.y; S[k][2] = s3.z;
-        U[k][0] = u3.x; U[k][1] = u3.y; U[k][2] = u3.z;
-        Dn[k][0] = d3.x; Dn[k][1] = d3.y; Dn[k][2] = d3.z;
-        hl[k] = negflag(lat + (o + xl)) + negflag(lat + (od + xl));
-        hr[k] = negflag(lat + (o + xr)) + negflag(lat + (ou + xr));
-        orow[k] = o;
-        x0[k] = (uint32_t)x;
-        xc[k] = (uint32_t)((c + y) % 3);
+        const uint32_t o = __umul24((uint32_t)y, (uint32_t)W3);
+        const uint32_t ou = __umul24((uint32_t)yu, (uint32_t)W3);
+        const uint32_t od = __umul24((uint32_t)yd, (uint32_t)W3);
+        const int rr = (c + y) % 3;
+        off[k] = o + (uint32_t)i0;
+        S[k] = ld32(own + off[k]);
+        const uint32_t fa = ld32(pp + off[k]) & kNegFlag;           // (y, x + 1)
+        const uint32_t fb = ld32(pp + (ou + i0)) & kNegFlag;        // (y - 1, x)
+        const uint32_t fc = ld32(pp + (od + i0)) & kNegFlag;        // (y + 1, x - 1)
+        const uint32_t fd = ld32(pm + off[k]) & kNegFlag;           // (y, x - 1)
+        const uint32_t fe = ld32(pm + (od + i0)) & kNegFlag;        // (y + 1, x)
+        const uint32_t ff = ld32(pm + (ou + i0)) & kNegFlag;        // (y - 1, x + 1)
+        // halo bytes: r = 2 shifts (y, x + 1) and (y - 1, x + 1) by one byte
+        // up (byte i0 + 4), r = 0 shifts (y + 1, x - 1) and (y, x - 1) down
+        // (byte i0 - 1); r = 1 needs neither
+        const int ir = i0 + 4 == W3 ? 0 : i0 + 4, il = i0 == 0 ? W3 - 1 : i0 - 1;
+        const uint32_t h1 = negflag(rr == 2 ? pp + (o + ir) : pp + (od + il));
+        const uint32_t h2 = negflag(rr == 2 ? pm + (ou + ir) : pm + (o + il));
+        const uint32_t sa = rr == 2 ? abyte(h1, fa, 1) : fa;
+        const uint32_t sf = rr == 2 ? abyte(h2, ff, 1) : ff;
+        const uint32_t sc = rr == 0 ? abyte(fc, h1 << 24, 3) : fc;
+        const uint32_t sd = rr == 0 ? abyte(fd, h2 << 24, 3) : fd;
+        N[k] = sa + fb + sc + sd + fe + sf;  // 2n per byte, n <= 6 -1 neighbours
     }
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
     const uint32_t p = (uint32_t)(3 * t + (uint64_t)c);
@@ -281,9 +303,12 @@ __global__ void __launch_bounds__(256) k_tri_pass12(TriArgs a, int c, int sweep_
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        tri_span(S[k], U[k], Dn[k], hl[k], hr[k], xc[k], w[k], lt);
-        if (bt + 256 * k < nb)
-            *reinterpret_cast<uint3*>(lat + (orow[k] + x0[k])) = make_uint3(S[k][0], S[k][1], S[k][2]);
+        const uint32_t K = N[k] | ((S[k] & kNegFlag) << 3);  // 2n + 16 [s < 0] per byte
+        uint32_t F = 0u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            F |= (uint64_t)w[k][u] < lt[(K >> (8 * u + 1)) & 15u] ? 0xFEu << (8 * u) : 0u;
+        if (bt + 256 * k < nb) *reinterpret_cast<uint32_t*>(own + off[k]) = S[k] ^ F;
     }
 }
 
@@ -298,11 +323,11 @@ __global__ void __launch_bounds__(256) k_tri_stats(TriArgs a, int rec_row) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int y = i / Lx, x = i - y * Lx;
         const int yd = wrapt(y + 1, Ly), xr = wrapt(x + 1, Lx), xl = wrapt(x - 1, Lx);
-        const int s = lat[i];
+        const int s = lat[tri_byte(y, x, Lx, Ly)];
         M += s;
-        Bh += s * lat[(size_t)y * Lx + xr];
-        Bv += s * lat[(size_t)yd * Lx + x];
-        Bd += s * lat[(size_t)yd * Lx + xl];
+        Bh += s * lat[tri_byte(y, xr, Lx, Ly)];
+        Bv += s * lat[tri_byte(yd, x, Lx, Ly)];
+        Bd += s * lat[tri_byte(yd, xl, Lx, Ly)];
     }
     for (int o = 32; o > 0; o >>= 1) {
         M += __shfl_xor(M, o);
@@ -365,11 +390,11 @@ __global__ void __launch_bounds__(256) k_hc_pass(TriArgs a, int c, int sweep_off
 // a row holds W / 4 blocks); the other plane's word of the same row plus one
 // halo byte, and its words of rows y +- 1 and z +- 1, come in as dwords, and
 // only the own word is stored.  A lane takes NB Philox blocks, 256 apart, as
-// k_tri_pass12.
+// k_tri_pass4.
 template <int NB>
 __global__ void __launch_bounds__(256) k_hc_pass4(TriArgs a, int c, int sweep_off, int gx) {
     __shared__ uint64_t lt[16];
-    const int wl = xcd_logical((int)blockIdx.x, (int)gridDim.x);  // see k_tri_pass12
+    const int wl = xcd_logical((int)blockIdx.x, (int)gridDim.x);  // see k_tri_pass4
     const int r = wl / gx, wx = wl - r * gx;
     const RepDev D = a.reps[r];
     const int Lx = D.Lx, Ly = D.Ly, Lz = D.q, W = Lx >> 1, qpr = W >> 2;
@@ -384,7 +409,7 @@ __global__ void __launch_bounds__(256) k_hc_pass4(TriArgs a, int c, int sweep_of
     uint32_t S[NB], N[NB], M[NB], hf[NB], off[NB], par[NB];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
-        const int b = bt + 256 * k < nb ? bt + 256 * k : nb - 1;  // see k_tri_pass12
+        const int b = bt + 256 * k < nb ? bt + 256 * k : nb - 1;  // see k_tri_pass4
         const int row = qdiv(b, qpr, small);  // z Ly + y
         const int j0 = 4 * (b - (int)__umul24((uint32_t)row, (uint32_t)qpr));
         const int z = qdiv(row, Ly, small), y = row - (int)__umul24((uint32_t)z, (uint32_t)Ly);
@@ -508,6 +533,22 @@ __device__ __forceinline__ void hc_store_natural_word(int8_t* lat, int i, uint32
     *reinterpret_cast<uint16_t*>(lat + pb) = (uint16_t)__builtin_amdgcn_perm(0u, v, 0x0C0C0301u);
 }
 
+// The same for the triangular planes: sites (y, x0 .. x0 + 3), byte by byte.
+__device__ __forceinline__ uint32_t tri_natural_word(const int8_t* lat, int i, int Lx, int Ly) {
+    const int y = i / Lx, x0 = i - y * Lx;
+    uint32_t v = 0u;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v |= (uint32_t)(uint8_t)lat[tri_byte(y, x0 + u, Lx, Ly)] << (8 * u);
+    return v;
+}
+
+__device__ __forceinline__ void tri_store_natural_word(int8_t* lat, int i, uint32_t v, int Lx,
+                                                       int Ly) {
+    const int y = i / Lx, x0 = i - y * Lx;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) lat[tri_byte(y, x0 + u, Lx, Ly)] = (int8_t)(v >> (8 * u));
+}
+
 template <int MODEL>
 __device__ __forceinline__ int4 nat_stats(const int8_t* ls, int Lx, int Ly, int Lz) {
     const int plane = Lx * Ly, nq = (plane * Lz) >> 2;
@@ -559,7 +600,7 @@ __global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps, 
     for (int i = threadIdx.x; i < n / 4; i += blockDim.x)
         reinterpret_cast<uint32_t*>(ls)[i] = MODEL == kModelIsingHC
                                                  ? hc_natural_word(lat, 4 * i, Lx, Ly, Lz)
-                                                 : reinterpret_cast<const uint32_t*>(lat)[i];
+                                                 : tri_natural_word(lat, 4 * i, Lx, Ly);
     // recorded rows rec0 .. rec0 + n_rows - 1 (1-based) of this launch
     int* lrec = reinterpret_cast<int*>(ls + ((n + 15) & ~15));
     const int rec0 = REC ? sw0 / re + 1 : 0;
@@ -650,7 +691,7 @@ __global__ void __launch_bounds__(1024) k_nat_resident(TriArgs a, int n_sweeps, 
         if (MODEL == kModelIsingHC)
             hc_store_natural_word(lat, 4 * i, v, Lx, Ly, Lz);
         else
-            reinterpret_cast<uint32_t*>(lat)[i] = v;
+            tri_store_natural_word(lat, 4 * i, v, Lx, Ly);
     }
 }
 
@@ -700,9 +741,9 @@ hipError_t launch_tri_pass(const TriArgs& a, int c, int sweep_off, hipStream_t s
         hipLaunchKernelGGL(k_hc_pass, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s, a,
                            c, sweep_off);
     else if (a.all_lx12 && two)
-        hipLaunchKernelGGL(k_tri_pass12<2>, g2, dim3(256), 0, s, a, c, sweep_off, gx2);
+        hipLaunchKernelGGL(k_tri_pass4<2>, g2, dim3(256), 0, s, a, c, sweep_off, gx2);
     else if (a.all_lx12)
-        hipLaunchKernelGGL(k_tri_pass12<1>, g1, dim3(256), 0, s, a, c, sweep_off, gx1);
+        hipLaunchKernelGGL(k_tri_pass4<1>, g1, dim3(256), 0, s, a, c, sweep_off, gx1);
     else
         hipLaunchKernelGGL(k_tri_pass, dim3((a.max_blocks + 255) / 256, a.R), dim3(256), 0, s, a,
                            c, sweep_off);
