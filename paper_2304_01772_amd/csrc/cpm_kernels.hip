@@ -618,7 +618,16 @@ constexpr uint32_t kCpmSpinCap = 1u << 25;
 __device__ __forceinline__ void cpm_wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 __device__ int cpm_tile_barrier(uint32_t* bar, uint32_t need, uint32_t* abort_flag) {
-    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // release: the fence writes the L2 back (border ids, snapshot and change
+    // buffers reach memory for the other XCDs), the explicit vmcnt(0) waits
+    // for that write-back to finish, and only then is the arrival counted.
+    // (A release add alone compiles to the write-back directly followed by
+    // the add, with no wait between them, when the workgroup's stores were
+    // already waited for, so a workgroup on another XCD could pass the
+    // barrier and read memory the write-back had not reached.)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    cpm_wait_stores();
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (uint32_t spin = 0;; ++spin) {
         if (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= need) break;
         if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return 0;

@@ -685,6 +685,18 @@ constexpr uint32_t kPersistSpinCap = 1u << 25;  // polls of ~128 cycles each
 // left at their maxima)
 __device__ __forceinline__ void wait_stores() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Agent-scope release of a pass flag: the fence writes the L2 back (the
+// workgroup's rows reach memory for the other XCDs), the explicit vmcnt(0)
+// waits for that write-back to finish, then the flag is stored.  (The
+// release store alone compiles to the write-back directly followed by the
+// flag store, with no wait between them, when the workgroup's stores were
+// already waited for, so the flag could be seen before the rows.)
+__device__ __forceinline__ void persist_publish(uint32_t* flag, uint32_t v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    wait_stores();
+    __hip_atomic_store(flag, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ int persist_wait(uint32_t* flags, int up, int down, uint32_t need, uint32_t* abort_flag) {
     for (uint32_t spin = 0;; ++spin) {
         const uint32_t u = __hip_atomic_load(&flags[up], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -745,9 +757,7 @@ __device__ __forceinline__ void persist_body(const SweepArgs& a, const PersistIt
                 if (it.slab >= 0) {
                     wait_stores();
                     __syncthreads();
-                    if (threadIdx.x == 0)
-                        __hip_atomic_store(&flags[it.slab], j + 1u, __ATOMIC_RELEASE,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+                    if (threadIdx.x == 0) persist_publish(&flags[it.slab], j + 1u);
                 }
             }
             __syncthreads();  // the workgroup's pass boundary
