@@ -459,7 +459,8 @@ __device__ __forceinline__ void quad_load(const CpmArgs& a, const RepDev& R, con
 }
 
 // The quad's four attempts (site 2u + CX of the quad is word u) and, on
-// acceptance, the id and area updates.
+// acceptance, the id update and the area changes (LDS atomics into the
+// workgroup's per-cell sums).
 template <int CX>
 __device__ __forceinline__ void quad_decide(const CpmArgs& a, const RepDev& R, int32_t* ids,
                                             int32_t* area, uint32_t p, const QuadIn& q,
@@ -485,11 +486,15 @@ __device__ __forceinline__ void quad_decide(const CpmArgs& a, const RepDev& R, i
 
 // A lane's first quad is loaded (window and Philox block) before the
 // per-cell tables are staged, so that the two rounds of global loads
-// overlap; the other quads of the lane follow the table barrier.
+// overlap; the other quads of the lane follow the table barrier.  Area
+// changes gather in LDS (one sum per cell of the replica) and go to the
+// pass's change buffer as one global atomic per touched cell at the end:
+// integer sums, so the buffer ends equal to one atomic per copy, with far
+// fewer atomics on the cells' words.
 template <int CX>
 __device__ __forceinline__ void quad_pass(const CpmArgs& a, int c, int sweep_off,
                                           uint32_t* qthr, int32_t* lsa, int8_t* lty,
-                                          int32_t* ljs) {
+                                          int32_t* ljs, int32_t* ldel) {
     const TileDev T = a.tiles[blockIdx.x];
     const RepDev R = a.reps[T.rep];
     const uint64_t t = *a.t_base + (uint64_t)sweep_off;
@@ -504,26 +509,35 @@ __device__ __forceinline__ void quad_pass(const CpmArgs& a, int c, int sweep_off
     if (it0 < total) quad_load<CX>(a, R, ids, T.y0, cy, p, it0, q);
     cpm_stage(a, R, pa, qthr, lsa, lty, ljs);
     pass_rotate(a, P);
+    const int ncell = R.q + 1;
+    for (int i = (int)threadIdx.x; i < ncell; i += (int)blockDim.x) ldel[i] = 0;
     __syncthreads();
-    if (it0 < total) quad_decide<CX>(a, R, ids, pa.d_wr, p, q, qthr, lsa, lty, ljs);
+    if (it0 < total) quad_decide<CX>(a, R, ids, ldel, p, q, qthr, lsa, lty, ljs);
     for (int it = it0 + (int)blockDim.x; it < total; it += blockDim.x) {
         quad_load<CX>(a, R, ids, T.y0, cy, p, it, q);
-        quad_decide<CX>(a, R, ids, pa.d_wr, p, q, qthr, lsa, lty, ljs);
+        quad_decide<CX>(a, R, ids, ldel, p, q, qthr, lsa, lty, ljs);
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < ncell; i += (int)blockDim.x) {
+        const int d = ldel[i];
+        if (d != 0) atomicAdd(&pa.d_wr[i], d);
     }
 }
 
 __global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int sweep_off,
                                                        int tab_lds_bytes, int cell_cap) {
-    // dynamic LDS: [T hi | T lo] (tab_lds_bytes) | snap - A (int32) | type (int8)
+    // dynamic LDS: [T hi | T lo] (tab_lds_bytes) | snap - A (int32) | type (int8) |
+    // area changes of the pass (int32); cell_cap is a multiple of 16
     extern __shared__ __align__(16) uint8_t dyn[];
     uint32_t* qthr = reinterpret_cast<uint32_t*>(dyn);
     int32_t* lsa = reinterpret_cast<int32_t*>(dyn + tab_lds_bytes);
     int8_t* lty = reinterpret_cast<int8_t*>(lsa + cell_cap);
+    int32_t* ldel = reinterpret_cast<int32_t*>(lty + cell_cap);
     __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
     if (c & 1)
-        quad_pass<1>(a, c, sweep_off, qthr, lsa, lty, ljs);
+        quad_pass<1>(a, c, sweep_off, qthr, lsa, lty, ljs, ldel);
     else
-        quad_pass<0>(a, c, sweep_off, qthr, lsa, lty, ljs);
+        quad_pass<0>(a, c, sweep_off, qthr, lsa, lty, ljs, ldel);
 }
 
 // All n_steps unrecorded Monte Carlo steps of every replica in one launch:
@@ -960,9 +974,13 @@ hipError_t launch_cpm_pass5(const CpmArgs& a, int n_tiles, int c, int sweep_off,
     return hipGetLastError();
 }
 
+size_t cpm_quad_lds_bytes(int tab_lds_bytes, int cell_cap) {
+    return (size_t)tab_lds_bytes + (size_t)cell_cap * 9;
+}
+
 hipError_t launch_cpm_pass_quad(const CpmArgs& a, int n_tiles, int c, int sweep_off,
                                 int threads, int tab_lds_bytes, int cell_cap, hipStream_t s) {
-    const size_t lds = (size_t)tab_lds_bytes + (size_t)cell_cap * 5;
+    const size_t lds = cpm_quad_lds_bytes(tab_lds_bytes, cell_cap);
     hipLaunchKernelGGL(k_cpm_pass_quad, dim3(n_tiles), dim3(threads), lds, s, a, c, sweep_off,
                        tab_lds_bytes, cell_cap);
     return hipGetLastError();

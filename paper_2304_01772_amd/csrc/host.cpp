@@ -51,6 +51,7 @@ constexpr size_t kResidentLdsBudget = 150 * 1024;
 // cache between passes: their own-plane traffic goes nontemporal by default.
 constexpr size_t kNtAutoBytes = 192ull << 20;
 constexpr int kCpmLdsCells = 16384;  // cells (medium included) per replica in LDS tables
+constexpr size_t kCpmQuadLdsMax = 160 * 1024;  // LDS of one workgroup of the quad pass
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -1973,7 +1974,9 @@ int create_cpm(const spinmc_replica_desc* d, int n, uint64_t seed, void* stream,
             quad = quad && (c->reps[i].dev.Lx % 8 == 0);
         }
         c->cpm_cell_cap = (int)align_up((size_t)cap, 16);
-        c->cpm_quad = quad && c->cpm_cell_cap <= kCpmLdsCells;
+        const size_t tab_lds = align_up((size_t)8 * std::max(c->max_tab_n, 1), 16);
+        c->cpm_quad = quad && c->cpm_cell_cap <= kCpmLdsCells &&
+                      cpm_quad_lds_bytes((int)tab_lds, c->cpm_cell_cap) <= kCpmQuadLdsMax;
     }
     std::vector<RepDev> rd(n);
     for (int i = 0; i < n; ++i) rd[i] = c->reps[i].dev;
@@ -2171,7 +2174,7 @@ int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
     CpmArgs a = cpm_args(c, stats);
     const size_t tab_bytes = align_up((size_t)8 * std::max(c->max_tab_n, 1), 16);
     if (c->cpm_quad && !c->cpm_lds_reserved) {
-        hipError_t er = cpm_reserve_lds(tab_bytes + (size_t)c->cpm_cell_cap * 5);
+        hipError_t er = cpm_reserve_lds(cpm_quad_lds_bytes((int)tab_bytes, c->cpm_cell_cap));
         if (er != hipSuccess) return check_dev(c, er, "CPM LDS reservation");
         c->cpm_lds_reserved = true;
     }

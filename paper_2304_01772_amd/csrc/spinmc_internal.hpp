@@ -183,9 +183,10 @@ hipError_t launch_cpm_pass(const CpmArgs& a, int n_tiles, int c, int sweep_off, 
 // per lane; tiles of whole multiples of 3 rows.
 hipError_t launch_cpm_pass5(const CpmArgs& a, int n_tiles, int c, int sweep_off, int threads,
                             size_t lds_tab_bytes, hipStream_t s);
-// Four same-colour sites per lane with the cell tables in LDS: needs every
-// Lx a multiple of 8 and cell_cap >= n_cells + 1 (a multiple of 16) for
-// every replica; dynamic LDS tab_lds_bytes + 5 cell_cap.
+// Four same-colour sites per lane with the cell tables and the pass's area
+// changes in LDS: needs every Lx a multiple of 8 and cell_cap >= n_cells + 1
+// (a multiple of 16) for every replica; dynamic LDS cpm_quad_lds_bytes.
+size_t cpm_quad_lds_bytes(int tab_lds_bytes, int cell_cap);
 hipError_t launch_cpm_pass_quad(const CpmArgs& a, int n_tiles, int c, int sweep_off,
                                 int threads, int tab_lds_bytes, int cell_cap, hipStream_t s);
 // Allow k_cpm_pass_quad up to lds_bytes of dynamic LDS (call outside capture).
