@@ -205,7 +205,10 @@ def cpm_probe(Sampler, torch, mcs):
     smp.sweep(mcs)
     torch.cuda.synchronize()
     kms, nl = smp.profile_read("cpm_pass")
-    kind, per_launch = "k_cpm_pass_quad (one launch per colour pass)", ids.size // 4
+    site_form = chosen.get("wg_threads", 0) in (0, 512)
+    kind = ("k_cpm_pass_site (one site per lane, one launch per colour pass)" if site_form
+            else "k_cpm_pass_quad (one quad per lane, one launch per colour pass)")
+    per_launch = ids.size // 4
     if nl == 0:  # the tiled persistent passes: one launch for all passes of the call
         kms, nl = smp.profile_read("cpm_tiled")
         kind, per_launch = "k_cpm_tiled (one launch per chunk)", ids.size * mcs // nl

@@ -524,6 +524,90 @@ __device__ __forceinline__ void quad_pass(const CpmArgs& a, int c, int sweep_off
     }
 }
 
+// One lane per site (the "site" form of the quad pass): lane u of each
+// group of four takes site 2u + CX of a quad, computes the quad's Philox
+// block itself and keeps word u, loads its own 3 x 3 window and decides one
+// attempt, so that a workgroup of 1024 lanes carries four times the
+// attempts in flight of the quad form at the same tile, each lane's
+// chain of table lookups a quarter as long.  Same decisions, same stores;
+// area changes gather in LDS as in the quad form.
+struct SiteIn {
+    int nb[8];
+    int s;
+    uint32_t w;
+    int y, x;
+    uint32_t kq;
+};
+
+template <int CX>
+__device__ __forceinline__ void site_load(const CpmArgs& a, const RepDev& R, const int32_t* ids,
+                                          int y0, int cy, uint32_t p, int it, int u, SiteIn& q) {
+    const int Lx = R.Lx, Ly = R.Ly, Q = Lx >> 3;
+    const int r = it / Q;
+    const int qi = it - r * Q;
+    q.y = y0 + 2 * r + cy;
+    q.x = 8 * qi + 2 * u + CX;
+    q.kq = (uint32_t)((q.y >> 1) * Q + qi);
+    const int yu = wrapc(q.y - 1, Ly), yd = wrapc(q.y + 1, Ly);
+    const int xl = wrapc(q.x - 1, Lx), xr = wrapc(q.x + 1, Lx);
+    const int32_t* ru = ids + (size_t)yu * Lx;
+    const int32_t* ry = ids + (size_t)q.y * Lx;
+    const int32_t* rd = ids + (size_t)yd * Lx;
+    // Moore order (dy, dx): (-1,-1) (-1,0) (-1,1) (0,-1) (0,1) (1,-1) (1,0) (1,1)
+    q.nb[0] = ru[xl];
+    q.nb[1] = ru[q.x];
+    q.nb[2] = ru[xr];
+    q.nb[3] = ry[xl];
+    q.nb[4] = ry[xr];
+    q.nb[5] = rd[xl];
+    q.nb[6] = rd[q.x];
+    q.nb[7] = rd[xr];
+    q.s = ry[q.x];
+    uint32_t w[4];
+    philox4x32_10(q.kq, p, R.rid, kTagMain, a.key0, a.key1, w);
+    q.w = u == 0 ? w[0] : (u == 1 ? w[1] : (u == 2 ? w[2] : w[3]));
+}
+
+template <int CX>
+__device__ __forceinline__ void site_pass(const CpmArgs& a, int c, int sweep_off,
+                                          uint32_t* qthr, int32_t* lsa, int8_t* lty,
+                                          int32_t* ljs, int32_t* ldel) {
+    const TileDev T = a.tiles[blockIdx.x];
+    const RepDev R = a.reps[T.rep];
+    const uint64_t t = *a.t_base + (uint64_t)sweep_off;
+    const uint64_t P = 4 * t + (uint64_t)c;
+    const uint32_t p = (uint32_t)P;
+    const PassAreas pa = pass_areas(a, P, R.cell_off);
+    int32_t* ids = a.lat + R.lat_off;
+    const int cy = c >> 1;
+    const int total = (T.rows >> 1) * (R.Lx >> 3);  // quads of the tile
+    const int u = (int)threadIdx.x & 3, qs = (int)blockDim.x >> 2;
+    int it = (int)threadIdx.x >> 2;
+    SiteIn q;
+    if (it < total) site_load<CX>(a, R, ids, T.y0, cy, p, it, u, q);
+    cpm_stage(a, R, pa, qthr, lsa, lty, ljs);
+    pass_rotate(a, P);
+    const int ncell = R.q + 1;
+    for (int i = (int)threadIdx.x; i < ncell; i += (int)blockDim.x) ldel[i] = 0;
+    __syncthreads();
+    while (it < total) {
+        const int tg = cpm_decide(a, R, q.nb, q.s, q.w, 4u * q.kq + (uint32_t)u, p, qthr, lsa,
+                                  lty, ljs);
+        if (tg >= 0) {
+            ids[(size_t)q.y * R.Lx + q.x] = tg;
+            atomicAdd(&ldel[tg], 1);
+            atomicAdd(&ldel[q.s], -1);
+        }
+        it += qs;
+        if (it < total) site_load<CX>(a, R, ids, T.y0, cy, p, it, u, q);
+    }
+    __syncthreads();
+    for (int i = (int)threadIdx.x; i < ncell; i += (int)blockDim.x) {
+        const int d = ldel[i];
+        if (d != 0) atomicAdd(&pa.d_wr[i], d);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int sweep_off,
                                                        int tab_lds_bytes, int cell_cap) {
     // dynamic LDS: [T hi | T lo] (tab_lds_bytes) | snap - A (int32) | type (int8) |
@@ -538,6 +622,21 @@ __global__ void __launch_bounds__(256) k_cpm_pass_quad(CpmArgs a, int c, int swe
         quad_pass<1>(a, c, sweep_off, qthr, lsa, lty, ljs, ldel);
     else
         quad_pass<0>(a, c, sweep_off, qthr, lsa, lty, ljs, ldel);
+}
+
+__global__ void __launch_bounds__(1024) k_cpm_pass_site(CpmArgs a, int c, int sweep_off,
+                                                        int tab_lds_bytes, int cell_cap) {
+    // dynamic LDS as k_cpm_pass_quad
+    extern __shared__ __align__(16) uint8_t dyn[];
+    uint32_t* qthr = reinterpret_cast<uint32_t*>(dyn);
+    int32_t* lsa = reinterpret_cast<int32_t*>(dyn + tab_lds_bytes);
+    int8_t* lty = reinterpret_cast<int8_t*>(lsa + cell_cap);
+    int32_t* ldel = reinterpret_cast<int32_t*>(lty + cell_cap);
+    __shared__ int32_t ljs[kMaxCpmTypes * kMaxCpmTypes];
+    if (c & 1)
+        site_pass<1>(a, c, sweep_off, qthr, lsa, lty, ljs, ldel);
+    else
+        site_pass<0>(a, c, sweep_off, qthr, lsa, lty, ljs, ldel);
 }
 
 // All n_steps unrecorded Monte Carlo steps of every replica in one launch:
@@ -981,14 +1080,22 @@ size_t cpm_quad_lds_bytes(int tab_lds_bytes, int cell_cap) {
 hipError_t launch_cpm_pass_quad(const CpmArgs& a, int n_tiles, int c, int sweep_off,
                                 int threads, int tab_lds_bytes, int cell_cap, hipStream_t s) {
     const size_t lds = cpm_quad_lds_bytes(tab_lds_bytes, cell_cap);
-    hipLaunchKernelGGL(k_cpm_pass_quad, dim3(n_tiles), dim3(threads), lds, s, a, c, sweep_off,
-                       tab_lds_bytes, cell_cap);
+    if (threads > 256)
+        hipLaunchKernelGGL(k_cpm_pass_site, dim3(n_tiles), dim3(threads), lds, s, a, c, sweep_off,
+                           tab_lds_bytes, cell_cap);
+    else
+        hipLaunchKernelGGL(k_cpm_pass_quad, dim3(n_tiles), dim3(threads), lds, s, a, c, sweep_off,
+                           tab_lds_bytes, cell_cap);
     return hipGetLastError();
 }
 
 hipError_t cpm_reserve_lds(size_t lds_bytes) {
-    return hipFuncSetAttribute((const void*)k_cpm_pass_quad,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    hipError_t e = hipFuncSetAttribute((const void*)k_cpm_pass_quad,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void*)k_cpm_pass_site,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    return e;
 }
 
 hipError_t launch_cpm_snapshot(const CpmArgs& a, int total_cells, hipStream_t s) {

@@ -133,6 +133,7 @@ struct spinmc_ctx {
     int n_tiles = 0;
     int n_tiles_ising = 0;  // streamed Ising tiles come first in d_tiles
     int tiles_rows = 0;
+    int tiles_threads = 0;  // CPM: pass threads the tiles were sized for
     spinmc_schedule sched{0, 0, 0, 0};
     bool prepared = false;
     long prepared_key = 0;
@@ -1109,6 +1110,10 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
         // then streamed passes over several tile heights
         cand.push_back(spinmc_schedule{0, 0, 0, 0});
         for (int tr : {0, 2, 4, 8, 16}) cand.push_back(spinmc_schedule{2, tr, 256, 0});
+        if (c->cpm_range == 1 && c->cpm_quad) {  // one site per lane
+            for (int tr : {0, 8, 32}) cand.push_back(spinmc_schedule{2, tr, 0, 0});
+            for (int tr : {0, 8}) cand.push_back(spinmc_schedule{2, tr, 512, 0});
+        }
         // tiled persistent passes (where they apply), tiles of 64 and 32 rows
         int TH = 0, TW = 0, nb = 0;
         if (cpm_tiled_plan(c, &TH, &TW, &nb))
@@ -1869,8 +1874,18 @@ CpmArgs cpm_args(spinmc_ctx* c, int32_t* stats) {
     return a;
 }
 
+// Threads of a streamed CPM pass: the quad pass one site per lane in
+// workgroups of 1024 (wg_threads 0) or 512, one quad per lane at 256; the
+// other passes at most 256.
+int cpm_pass_threads(const spinmc_ctx* c) {
+    const int w = c->sched.wg_threads;
+    if (c->cpm_range == 1 && c->cpm_quad) return w == 0 ? 1024 : w;
+    return w > 0 ? std::min(w, 256) : 256;
+}
+
 // Row tiles: whole periods of the colouring (2 rows for the 2x2 sublattice,
-// 6 for the 3x3 one, which also keeps them even).
+// 6 for the 3x3 one, which also keeps them even); by default about 4096
+// sites a tile, 8192 for the one-site-per-lane quad pass.
 int cpm_build_tiles(spinmc_ctx* c) {
     // captured graphs refer to the tile buffer and its count
     for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
@@ -1879,7 +1894,8 @@ int cpm_build_tiles(spinmc_ctx* c) {
     const int period = c->cpm_range == 2 ? 6 : 2;
     for (int i = 0; i < c->R; ++i) {
         const RepDev& r = c->reps[i].dev;
-        int rows = c->sched.tile_rows > 0 ? c->sched.tile_rows : 4096 / r.Lx;
+        const int per = cpm_pass_threads(c) > 256 ? 8192 : 4096;
+        int rows = c->sched.tile_rows > 0 ? c->sched.tile_rows : per / r.Lx;
         rows -= rows % period;
         rows = std::max(period, std::min(rows, r.Ly));
         for (int y0 = 0; y0 < r.Ly; y0 += rows)
@@ -1896,6 +1912,7 @@ int cpm_build_tiles(spinmc_ctx* c) {
                       hipMemcpyHostToDevice);
     c->n_tiles = (int)tiles.size();
     c->tiles_rows = c->sched.tile_rows;
+    c->tiles_threads = cpm_pass_threads(c);
     return check_dev(c, e, "CPM tiles");
 }
 
@@ -2121,7 +2138,7 @@ int cpm_get_state(spinmc_ctx* c, int r, void* host, size_t bytes) {
 // The colour pass `col` of sweep `i` of a call.
 hipError_t cpm_enqueue_pass(spinmc_ctx* c, const CpmArgs& a, int i, int col, hipStream_t s) {
     const size_t tab_bytes = align_up((size_t)8 * std::max(c->max_tab_n, 1), 16);
-    const int threads = c->sched.wg_threads > 0 ? std::min(c->sched.wg_threads, 256) : 256;
+    const int threads = cpm_pass_threads(c);
     return timed(c, SPINMC_K_CPM_PASS, [&] {
         if (c->cpm_range == 2)
             return launch_cpm_pass5(a, c->n_tiles, col, i, threads, tab_bytes, s);
@@ -2166,7 +2183,7 @@ int cpm_chunk_graph(spinmc_ctx* c, int G, hipGraphExec_t* out) {
 }
 
 int cpm_sweep(spinmc_ctx* c, int n, int re, int32_t* stats) {
-    if (c->tiles_rows != c->sched.tile_rows) {
+    if (c->tiles_rows != c->sched.tile_rows || c->tiles_threads != cpm_pass_threads(c)) {
         int rc = cpm_build_tiles(c);
         if (rc) return rc;
     }

@@ -183,13 +183,16 @@ hipError_t launch_cpm_pass(const CpmArgs& a, int n_tiles, int c, int sweep_off, 
 // per lane; tiles of whole multiples of 3 rows.
 hipError_t launch_cpm_pass5(const CpmArgs& a, int n_tiles, int c, int sweep_off, int threads,
                             size_t lds_tab_bytes, hipStream_t s);
-// Four same-colour sites per lane with the cell tables and the pass's area
-// changes in LDS: needs every Lx a multiple of 8 and cell_cap >= n_cells + 1
-// (a multiple of 16) for every replica; dynamic LDS cpm_quad_lds_bytes.
+// Four same-colour sites per lane (threads <= 256), or one site per lane
+// with four lanes per Philox quad (threads 512 or 1024), the cell tables and
+// the pass's area changes in LDS: needs every Lx a multiple of 8 and
+// cell_cap >= n_cells + 1 (a multiple of 16) for every replica; dynamic LDS
+// cpm_quad_lds_bytes.
 size_t cpm_quad_lds_bytes(int tab_lds_bytes, int cell_cap);
 hipError_t launch_cpm_pass_quad(const CpmArgs& a, int n_tiles, int c, int sweep_off,
                                 int threads, int tab_lds_bytes, int cell_cap, hipStream_t s);
-// Allow k_cpm_pass_quad up to lds_bytes of dynamic LDS (call outside capture).
+// Allow both forms of the quad pass up to lds_bytes of dynamic LDS (call
+// outside capture).
 hipError_t cpm_reserve_lds(size_t lds_bytes);
 // Before a call's streamed passes: sbuf[P0 & 1] = area, dbuf[(P0 - 1) mod 3]
 // = dbuf[P0 mod 3] = 0 for the pass P0 = n_col (t + sweep_off).

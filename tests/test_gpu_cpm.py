@@ -49,7 +49,8 @@ JS = {
     # more cells than the LDS cell tables hold: the per-site kernel
     ((128, 128), 17000, "sorting", 1.0, 10.0, 0),
 ])
-def test_cpm_matches_oracle(S, shape, n_cells, Jname, lam, T, tile_rows):
+@pytest.mark.parametrize("threads", [0, 256])  # one site per lane (1024), one quad per lane
+def test_cpm_matches_oracle(S, shape, n_cells, Jname, lam, T, tile_rows, threads):
     J = JS[Jname]
     reps, init = [], []
     for r in range(3):
@@ -57,7 +58,7 @@ def test_cpm_matches_oracle(S, shape, n_cells, Jname, lam, T, tile_rows):
         reps.append(_rep(ids, J, ctype, A, lam, T, 7 + r))
         init.append(ids)
     smp = S(reps, 17, init=False)
-    smp.set_schedule(mode="stream", tile_rows=tile_rows)
+    smp.set_schedule(mode="stream", tile_rows=tile_rows, wg_threads=threads)
     for i, ids in enumerate(init):
         smp.set_state(i, ids)
     n, re = 6, 2
@@ -380,14 +381,17 @@ def test_unrecorded_steps_resident(S, cpm_range):
     smp.close()
 
 
-def test_streamed_passes_over_ragged_tiles_match_oracle(S):
+@pytest.mark.parametrize("threads", [0, 512, 256])
+def test_streamed_passes_over_ragged_tiles_match_oracle(S, threads):
     """The 3x3 streamed pass, recorded, over several tiles of 8 rows with a
-    ragged last one (22 rows): states and statistics equal the oracle's."""
+    ragged last one (22 rows), in both forms (one site per lane in
+    workgroups of 1024 or 512, one quad per lane in 256): states and
+    statistics equal the oracle's."""
     J = JS["sorting"]
     cases = [_random_case(950 + r, (22, 40), 9) for r in range(2)]
     reps = [_rep(ids, J, ct, A, 1.0, 10.0, 60 + r) for r, (ids, ct, A) in enumerate(cases)]
     smp = S(reps, 13, init=False)
-    smp.set_schedule(mode="stream", tile_rows=8)
+    smp.set_schedule(mode="stream", tile_rows=8, wg_threads=threads)
     for r, (ids, _, _) in enumerate(cases):
         smp.set_state(r, ids)
     st = smp.sweep(6, 3).cpu().numpy()
@@ -410,8 +414,9 @@ def test_autotune_keeps_the_chain(S):
         smp.set_state(r, ids)
     smp.sweep(4)
     chosen, rates = smp.autotune(trial_sweeps=5)
-    # resident, five streamed tile heights, two tiled persistent candidates
-    assert len(rates) == 8 and all(x > 0 for x in rates)
+    # resident, five streamed tile heights of the quad form, five of the
+    # one-site-per-lane form (1024 and 512 lanes), two tiled persistent
+    assert len(rates) == 13 and all(x > 0 for x in rates)
     smp.sweep(5)
     for r, (ids, ct, A) in enumerate(cases):
         want, _, _ = orc.cpm_run(ids, J, ct, A, 1.0, 10.0, 15, 80 + r, 0, 9)
