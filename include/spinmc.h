@@ -301,8 +301,13 @@ int spinmc_thresholds(const spinmc_ctx *ctx, int32_t replica, uint64_t *host_T, 
  * step on streamed passes; any other mode lets the unrecorded steps of
  * lattices whose ids and tables fit 64 KiB of LDS run resident (one
  * workgroup per replica).  tile_rows is rounded down to whole periods of
- * the colouring (2 rows, or 6 with the 5x5 neighbourhood); wg_threads caps
- * the threads of a streamed pass at 256.  spinmc_autotune also tries the
+ * the colouring (2 rows, or 6 with the 5x5 neighbourhood).  wg_threads of
+ * a streamed 3x3 pass where every Lx is a multiple of 8: 0 = one site per
+ * lane in workgroups of 1024 (tiles of about 8192 sites by default), 512 =
+ * the same in workgroups of 512, 256 = four same-colour sites per lane in
+ * workgroups of 256 (tiles of about 4096 sites); the same decisions either
+ * way.  Other CPM passes use at most 256 threads.  spinmc_autotune tries
+ * both forms of the 3x3 pass, and for Ising and Potts contexts also the
  * best streaming schedule with NT forced on and off.                        */
 enum { SPINMC_SCHED_NT_ON = 1, SPINMC_SCHED_NT_OFF = 2, SPINMC_SCHED_PERSIST = 4 };
 typedef struct spinmc_schedule {
