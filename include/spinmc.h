@@ -338,7 +338,10 @@ int spinmc_schedule_sites(const spinmc_ctx *ctx, int64_t streamed[3], int64_t re
  * The candidates: modes, tile heights, workgroup sizes, persistent passes,
  * then nontemporal access forced on and off for the best streaming
  * candidate and replicas per resident workgroup 1, 2, 4 and 8 for the best
- * candidate with resident groups.  Choices are cached per process, keyed by
+ * candidate with resident groups.  The three fastest then run again, twice
+ * each for 4 trial_sweeps sweeps (not reported in host_rates), and the best
+ * of those runs is chosen: short trials of close candidates differ by
+ * timing noise.  Choices are cached per process, keyed by
  * the device's architecture and compute-unit count and the context's shape
  * signature (model, Lx, Ly, q and the multiplicity of every shape, CPM
  * neighbourhood range): a later call for an equal signature returns the

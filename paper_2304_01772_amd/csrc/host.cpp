@@ -1194,13 +1194,16 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
     int best = -1;
     double best_rate = 0;
     int tried = 0;
-    auto trial = [&](const spinmc_schedule& sc) -> double {
+    // one timed run of trial_sweeps * mult sweeps under schedule sc (after a
+    // warm-up that builds tiles and graphs), the state restored after it;
+    // recorded in rates for the first round of candidates
+    auto timed_run = [&](const spinmc_schedule& sc, int mult, bool record) -> double {
+        const int n = trial_sweeps * mult;
         c->sched = sc;
         c->prepared = false;
-        // one warm-up sweep builds tiles and graphs
         int rc = c->cpm ? cpm_sweep(c, 1, 0, nullptr) : enqueue_sweep(c, 1, 0, nullptr);
-        if (rc == SPINMC_OK) rc = c->cpm ? cpm_sweep(c, trial_sweeps, 0, nullptr)
-                                         : enqueue_sweep(c, trial_sweeps, 0, nullptr);
+        if (rc == SPINMC_OK) rc = c->cpm ? cpm_sweep(c, n, 0, nullptr)
+                                         : enqueue_sweep(c, n, 0, nullptr);
         if (rc != SPINMC_OK) {
             e = hipErrorUnknown;
             return 0.0;
@@ -1208,8 +1211,7 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
         e = restore();
         if (e != hipSuccess) return 0.0;
         e = hipEventRecord(e0, c->stream);
-        rc = c->cpm ? cpm_sweep(c, trial_sweeps, 0, nullptr)
-                    : enqueue_sweep(c, trial_sweeps, 0, nullptr);
+        rc = c->cpm ? cpm_sweep(c, n, 0, nullptr) : enqueue_sweep(c, n, 0, nullptr);
         if (rc != SPINMC_OK) {
             e = hipErrorUnknown;
             return 0.0;
@@ -1218,11 +1220,19 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
         if (e == hipSuccess) e = hipEventSynchronize(e1);
         float ms = 0.f;
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        const double rate = ms > 0 ? sites * trial_sweeps / (ms * 1e6) : 0.0;
-        if (rates && tried < cap) rates[tried] = rate;
-        ++tried;
+        const double rate = ms > 0 ? sites * n / (ms * 1e6) : 0.0;
+        if (record) {
+            if (rates && tried < cap) rates[tried] = rate;
+            ++tried;
+        }
         if (e == hipSuccess) e = restore();
         return rate;
+    };
+    std::vector<double> cand_rate;
+    auto trial = [&](const spinmc_schedule& sc) -> double {
+        const double r = timed_run(sc, 1, true);
+        cand_rate.push_back(r);
+        return r;
     };
     for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
         const double rate = trial(cand[k]);
@@ -1265,6 +1275,25 @@ int spinmc_autotune(spinmc_ctx* c, int32_t trial_sweeps, spinmc_schedule* chosen
                 if (e == hipSuccess && rate > best_rate) {
                     best_rate = rate;
                     best = (int)k;
+                }
+            }
+        }
+    }
+    // run-off: short trials of close candidates differ by noise, so the three
+    // fastest run again four times as long, twice each, and the best of
+    // those runs decides (not recorded in rates)
+    if (e == hipSuccess && cand.size() > 1 && cand_rate.size() == cand.size()) {
+        std::vector<int> order(cand.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+        std::sort(order.begin(), order.end(),
+                  [&](int x, int y) { return cand_rate[x] > cand_rate[y]; });
+        double run_best = 0;
+        for (int k = 0; k < 3 && k < (int)order.size() && e == hipSuccess; ++k) {
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                const double r = timed_run(cand[order[k]], 4, false);
+                if (e == hipSuccess && r > run_best) {
+                    run_best = r;
+                    best = order[k];
                 }
             }
         }
