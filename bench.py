@@ -805,7 +805,9 @@ def main():
     ap.add_argument("--mode", default="tuned",
                     choices=["tuned", "auto", "resident", "stream", "hybrid"],
                     help="schedule; 'tuned' runs the library's autotuner first")
-    ap.add_argument("--tune-sweeps", type=int, default=20)
+    ap.add_argument("--tune-sweeps", type=int, default=100,
+                    help="sweeps per autotuner trial (trials of 20 sweeps misjudged the hybrid "
+                         "schedule's long-run rate)")
     ap.add_argument("--prof-sweeps", type=int, default=200,
                     help="sweeps of the per-kernel timing run after the timed steps")
     ap.add_argument("--tile-rows", type=int, default=0)
