@@ -497,7 +497,8 @@ __global__ void k_tri_observables(TriArgs a, double* obs) {
 }
 
 // All n_sweeps unrecorded sweeps in one launch, one workgroup per replica
-// with its lattice in LDS (the layout of global memory) and a barrier after
+// with its lattice in LDS in natural order (converted from the colour planes
+// of global memory when loaded, and back when stored) and a barrier after
 // every colour pass: the same decisions as the streamed passes, without the
 // per-pass launches and lattice round trips.  Needs Lx % 12 == 0 for the
 // triangular lattice (the four sites of a Philox block in one row) and
